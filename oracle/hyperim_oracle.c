@@ -1,0 +1,746 @@
+/*
+ * hyperim_oracle.c -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, obviously-correct CPU implementation of HyperIM's hot path
+ * (influence maximization in hypergraphs by RR-set sampling plus greedy max
+ * coverage).  It exists to check the GPU library: only the test suite, the
+ * smoke entry point and the benchmark's CPU-baseline leg may load it.  It
+ * shares no code, header, table or constant generator with the GPU library.
+ *
+ * What it computes, and where in the paper each step comes from:
+ *   - the hypergraph G=(V,HE) and its implicit weighted clique graph G_w
+ *     (Section 2.1, problem definition); G_w is never built, only walked;
+ *   - independent-cascade channels (Section 2.1, "Cascade models", IC):
+ *     every hyperedge he and every ordered pair of distinct members u->v of he
+ *     is one channel, live with probability p_v;
+ *   - the sample-set layers of each vertex by co-membership weight w(v,u)
+ *     (Section 3.1.1, "Sample set division"), the layer count l_v, and the
+ *     statistics alpha, beta of Section 4.1 and theta(l*) of Theorem 2;
+ *   - RR sets: a root, then the reverse breadth-first closure over live
+ *     channels (Algorithm 3's skeleton: root, queue, activated marks);
+ *   - greedy max coverage (Algorithm 1, Equations (1)-(2));
+ *   - the sample-size loop of HyperIM_BRR (Algorithm 4): theta_max
+ *     (Lemma 6 / Equation (13)), theta_0, the lower bound of Equation (12)
+ *     and the upper bound of Lemma 5, doubling until the ratio test passes.
+ *
+ * Readings where the paper is silent or garbled (each restated in the design
+ * notes): one independent channel per (hyperedge, ordered pair); coins are
+ * Philox4x32-10 words keyed by (seed, instance) with counter
+ * (j_lo, he, v, pool<<31 | j_hi<<24 | pos>>2); thresholds floor(p * 2^32)
+ * from float32 p; layers by descending w; stratum = min(7, 1+floor(log2 l_v))
+ * (0 for l_v = 0); roots by systematic sampling over the stratum-sorted vertex
+ * list with one 64-bit random offset per ladder block; theta_max in the
+ * OPIM-C form; the stop test sigma_l/sigma_u >= 1-1/e-eps.
+ *
+ * Build: gcc -O2 -shared -fPIC -pthread -o liboracle.so hyperim_oracle.c -lm
+ */
+#include <math.h>
+#include <pthread.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_OK 0
+#define ORC_EINVAL (-1)
+#define ORC_ENOMEM (-2)
+#define ORC_NSTRATA 8u
+#define ORC_ALWAYS 0xFFFFFFFFu
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw: "Parallel random numbers: as   */
+/* easy as 1, 2, 3", SC'11).  Ten rounds of the 4x32 Philox S-P network; the */
+/* two-word key is bumped by the Weyl constants between rounds.              */
+/* ------------------------------------------------------------------------ */
+void orc_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t out[4])
+{
+    uint32_t c0 = ctr_in[0], c1 = ctr_in[1], c2 = ctr_in[2], c3 = ctr_in[3];
+    uint32_t k0 = key_in[0], k1 = key_in[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        uint64_t prod0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+        uint64_t prod1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+        uint32_t hi0 = (uint32_t)(prod0 >> 32), lo0 = (uint32_t)prod0;
+        uint32_t hi1 = (uint32_t)(prod1 >> 32), lo1 = (uint32_t)prod1;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n1 = lo1;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        uint32_t n3 = lo0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* Philox over a batch of (counter, key) records, for cross-checks. */
+void orc_philox_batch(uint64_t count, const uint32_t *ctr, const uint32_t *key, uint32_t *out)
+{
+    for (uint64_t i = 0; i < count; ++i) orc_philox4x32_10(ctr + 4 * i, key + 2 * i, out + 4 * i);
+}
+
+/* The coin of channel (he, u -> v) in RR set j of pool `pool`, where pos is
+ * u's index inside he's member list.  IC, Section 2.1: one independent
+ * Bernoulli trial per channel. */
+uint32_t orc_coin(uint64_t seed, uint32_t instance, uint32_t pool, uint64_t j,
+                  uint32_t he, uint32_t v, uint32_t pos)
+{
+    uint32_t ctr[4], key[2], out[4];
+    ctr[0] = (uint32_t)j;
+    ctr[1] = he;
+    ctr[2] = v;
+    ctr[3] = (pool << 31) | ((uint32_t)(j >> 32) << 24) | (pos >> 2);
+    key[0] = (uint32_t)seed;
+    key[1] = instance;
+    orc_philox4x32_10(ctr, key, out);
+    return out[pos & 3u];
+}
+
+static int orc_live(uint32_t coin, uint32_t thr)
+{
+    return thr == ORC_ALWAYS || coin < thr;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Graph                                                                     */
+/* ------------------------------------------------------------------------ */
+typedef struct orc_graph {
+    uint32_t n, m;
+    uint64_t nnz;
+    uint32_t *he_off, *he_mem;     /* hyperedge -> members (caller's order) */
+    uint32_t *v_off, *v_he;        /* vertex -> hyperedges (ascending ids)  */
+    uint32_t *thr;                 /* coin threshold of channels into v     */
+    uint64_t *c;                   /* sum over he containing v of |he|-1    */
+    int stratified;
+    uint32_t *l, *deg, *top, *P;   /* layers, G_w degree, |L_1|, ordering   */
+    uint8_t *stratum;
+    uint32_t B[ORC_NSTRATA + 1];
+    double alpha, beta, theta_l;
+} orc_graph;
+
+void orc_graph_free(orc_graph *g)
+{
+    if (!g) return;
+    free(g->he_off); free(g->he_mem); free(g->v_off); free(g->v_he);
+    free(g->thr); free(g->c); free(g->l); free(g->deg); free(g->top);
+    free(g->P); free(g->stratum);
+    free(g);
+}
+
+/* Probability threshold: a channel into v is live when its coin is below
+ * thr[v]; thr = ALWAYS when p_v >= 1.  p_v is float32; floor(p_v * 2^32) is
+ * exact in double because a float32 has a 24-bit significand. */
+static uint32_t orc_threshold(float pv)
+{
+    if (pv >= 1.0f) return ORC_ALWAYS;
+    if (!(pv > 0.0f)) return 0u;
+    return (uint32_t)floor(ldexp((double)pv, 32));
+}
+
+/* Section 2.1: G = (V, HE) with V(he) given as member lists.  Validates the
+ * input, builds the vertex -> hyperedge incidence lists and the per-target
+ * thresholds (model 0: constant p; model 1: weighted cascade, p_v = 1/c(v)
+ * with c(v) the weighted in-degree of v in G_w). */
+int orc_graph_new(uint32_t n, uint32_t m, const uint32_t *he_off, const uint32_t *he_mem,
+                  uint32_t model, float p, orc_graph **out)
+{
+    *out = NULL;
+    if (model > 1u) return ORC_EINVAL;
+    if (model == 0u && (isnan(p) || p < 0.0f)) return ORC_EINVAL;
+    if (he_off[0] != 0u) return ORC_EINVAL;
+    for (uint32_t e = 0; e < m; ++e)
+        if (he_off[e + 1] < he_off[e]) return ORC_EINVAL;
+    uint64_t nnz = he_off[m];
+    for (uint64_t i = 0; i < nnz; ++i)
+        if (he_mem[i] >= n) return ORC_EINVAL;
+    /* duplicate member inside one hyperedge */
+    uint32_t *stamp = (uint32_t *)malloc(sizeof(uint32_t) * (n ? n : 1));
+    if (!stamp) return ORC_ENOMEM;
+    for (uint32_t v = 0; v < n; ++v) stamp[v] = 0xFFFFFFFFu;
+    for (uint32_t e = 0; e < m; ++e)
+        for (uint32_t i = he_off[e]; i < he_off[e + 1]; ++i) {
+            if (stamp[he_mem[i]] == e) { free(stamp); return ORC_EINVAL; }
+            stamp[he_mem[i]] = e;
+        }
+    free(stamp);
+
+    orc_graph *g = (orc_graph *)calloc(1, sizeof(orc_graph));
+    if (!g) return ORC_ENOMEM;
+    g->n = n; g->m = m; g->nnz = nnz;
+    g->he_off = (uint32_t *)malloc(sizeof(uint32_t) * (m + 1));
+    g->he_mem = (uint32_t *)malloc(sizeof(uint32_t) * (nnz ? nnz : 1));
+    g->v_off = (uint32_t *)calloc(n + 1, sizeof(uint32_t));
+    g->v_he = (uint32_t *)malloc(sizeof(uint32_t) * (nnz ? nnz : 1));
+    g->thr = (uint32_t *)malloc(sizeof(uint32_t) * (n ? n : 1));
+    g->c = (uint64_t *)calloc(n ? n : 1, sizeof(uint64_t));
+    if (!g->he_off || !g->he_mem || !g->v_off || !g->v_he || !g->thr || !g->c) {
+        orc_graph_free(g);
+        return ORC_ENOMEM;
+    }
+    memcpy(g->he_off, he_off, sizeof(uint32_t) * (m + 1));
+    if (nnz) memcpy(g->he_mem, he_mem, sizeof(uint32_t) * nnz);
+
+    /* incidence lists: count, prefix sum, fill in ascending hyperedge order */
+    for (uint64_t i = 0; i < nnz; ++i) g->v_off[he_mem[i] + 1]++;
+    for (uint32_t v = 0; v < n; ++v) g->v_off[v + 1] += g->v_off[v];
+    uint32_t *fill = (uint32_t *)calloc(n ? n : 1, sizeof(uint32_t));
+    if (!fill) { orc_graph_free(g); return ORC_ENOMEM; }
+    for (uint32_t e = 0; e < m; ++e)
+        for (uint32_t i = he_off[e]; i < he_off[e + 1]; ++i) {
+            uint32_t v = he_mem[i];
+            g->v_he[g->v_off[v] + fill[v]++] = e;
+            g->c[v] += (uint64_t)(he_off[e + 1] - he_off[e] - 1u);
+        }
+    free(fill);
+
+    for (uint32_t v = 0; v < n; ++v) {
+        float pv;
+        if (model == 0u) pv = p;
+        else pv = g->c[v] ? (float)(1.0 / (double)g->c[v]) : 0.0f;
+        g->thr[v] = orc_threshold(pv);
+    }
+    *out = g;
+    return ORC_OK;
+}
+
+int orc_graph_export(const orc_graph *g, uint32_t *v_off, uint32_t *v_he, uint32_t *thr, uint64_t *c)
+{
+    memcpy(v_off, g->v_off, sizeof(uint32_t) * (g->n + 1));
+    if (g->nnz) memcpy(v_he, g->v_he, sizeof(uint32_t) * g->nnz);
+    memcpy(thr, g->thr, sizeof(uint32_t) * g->n);
+    memcpy(c, g->c, sizeof(uint64_t) * g->n);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Sample-set layers (Section 3.1.1) and strata                              */
+/* ------------------------------------------------------------------------ */
+static int cmp_u32(const void *a, const void *b)
+{
+    uint32_t x = *(const uint32_t *)a, y = *(const uint32_t *)b;
+    return (x > y) - (x < y);
+}
+
+static uint32_t orc_stratum_of(uint32_t l)
+{
+    if (l == 0u) return 0u;
+    uint32_t lg = 0;                 /* floor(log2 l) */
+    while ((l >> (lg + 1)) != 0u) ++lg;
+    uint32_t s = 1u + lg;
+    return s < ORC_NSTRATA - 1u ? s : ORC_NSTRATA - 1u;
+}
+
+/* For each vertex v: w(v,u) = number of hyperedges shared with co-member u;
+ * deg(v) = number of distinct u (degree in G_w); the sample set A(v) is
+ * divided into layers of equal w, layer 1 holding the largest w; l_v is the
+ * number of layers and top(v) = n(L_1).  Strata group vertices by l_v; P is
+ * the vertex list sorted by (stratum, id) and B[h] the first index of
+ * stratum h.  Section 4.1 statistics: alpha = F_cnt / T_cnt (first-layer
+ * vertices over all layered vertices), beta = L_cnt / |V|, and Theorem 2's
+ * theta(l*) = (1/|V|) sum_v l_v / ln(l_v + 1). */
+int orc_stratify(orc_graph *g)
+{
+    uint32_t n = g->n;
+    free(g->l); free(g->deg); free(g->top); free(g->P); free(g->stratum);
+    g->l = (uint32_t *)calloc(n ? n : 1, sizeof(uint32_t));
+    g->deg = (uint32_t *)calloc(n ? n : 1, sizeof(uint32_t));
+    g->top = (uint32_t *)calloc(n ? n : 1, sizeof(uint32_t));
+    g->P = (uint32_t *)malloc(sizeof(uint32_t) * (n ? n : 1));
+    g->stratum = (uint8_t *)calloc(n ? n : 1, 1);
+    if (!g->l || !g->deg || !g->top || !g->P || !g->stratum) return ORC_ENOMEM;
+
+    uint64_t cap = 16;
+    uint32_t *buf = (uint32_t *)malloc(sizeof(uint32_t) * cap);
+    uint32_t *wv = (uint32_t *)malloc(sizeof(uint32_t) * cap);
+    if (!buf || !wv) { free(buf); free(wv); return ORC_ENOMEM; }
+    uint64_t sum_top = 0, sum_deg = 0, sum_l = 0;
+    double theta_l = 0.0;
+    for (uint32_t v = 0; v < n; ++v) {
+        /* gather every co-member occurrence of v */
+        uint64_t cnt = 0;
+        for (uint32_t e = g->v_off[v]; e < g->v_off[v + 1]; ++e) {
+            uint32_t he = g->v_he[e];
+            for (uint32_t i = g->he_off[he]; i < g->he_off[he + 1]; ++i) {
+                uint32_t u = g->he_mem[i];
+                if (u == v) continue;
+                if (cnt == cap) {
+                    cap *= 2;
+                    uint32_t *nb = (uint32_t *)realloc(buf, sizeof(uint32_t) * cap);
+                    uint32_t *nw = (uint32_t *)realloc(wv, sizeof(uint32_t) * cap);
+                    if (!nb || !nw) { free(nb ? nb : buf); free(nw ? nw : wv); return ORC_ENOMEM; }
+                    buf = nb; wv = nw;
+                }
+                buf[cnt++] = u;
+            }
+        }
+        qsort(buf, cnt, sizeof(uint32_t), cmp_u32);
+        /* run lengths = w(v,u) */
+        uint64_t d = 0;
+        for (uint64_t i = 0; i < cnt;) {
+            uint64_t r = i;
+            while (r < cnt && buf[r] == buf[i]) ++r;
+            wv[d++] = (uint32_t)(r - i);
+            i = r;
+        }
+        qsort(wv, d, sizeof(uint32_t), cmp_u32);
+        uint32_t layers = 0, top = 0;
+        for (uint64_t i = 0; i < d; ++i)
+            if (i == 0 || wv[i] != wv[i - 1]) ++layers;
+        if (d) {
+            uint32_t wmax = wv[d - 1];
+            for (uint64_t i = 0; i < d; ++i)
+                if (wv[i] == wmax) ++top;
+        }
+        g->l[v] = layers;
+        g->deg[v] = (uint32_t)d;
+        g->top[v] = top;
+        g->stratum[v] = (uint8_t)orc_stratum_of(layers);
+        sum_top += top;
+        sum_deg += d;
+        sum_l += layers;
+        if (layers) theta_l += (double)layers / log((double)layers + 1.0);
+    }
+    free(buf);
+    free(wv);
+
+    uint32_t idx = 0;
+    for (uint32_t h = 0; h < ORC_NSTRATA; ++h) {
+        g->B[h] = idx;
+        for (uint32_t v = 0; v < n; ++v)
+            if (g->stratum[v] == h) g->P[idx++] = v;
+    }
+    g->B[ORC_NSTRATA] = idx;
+    g->alpha = sum_deg ? (double)sum_top / (double)sum_deg : 0.0;
+    g->beta = n ? (double)sum_l / (double)n : 0.0;
+    g->theta_l = n ? theta_l / (double)n : 0.0;
+    g->stratified = 1;
+    return ORC_OK;
+}
+
+int orc_strata_export(const orc_graph *g, uint32_t *l, uint32_t *deg, uint32_t *top,
+                      uint8_t *stratum, uint32_t *P, uint32_t *B, double *stats)
+{
+    if (!g->stratified) return ORC_EINVAL;
+    memcpy(l, g->l, sizeof(uint32_t) * g->n);
+    memcpy(deg, g->deg, sizeof(uint32_t) * g->n);
+    memcpy(top, g->top, sizeof(uint32_t) * g->n);
+    memcpy(stratum, g->stratum, g->n);
+    memcpy(P, g->P, sizeof(uint32_t) * g->n);
+    memcpy(B, g->B, sizeof(uint32_t) * (ORC_NSTRATA + 1));
+    stats[0] = g->alpha;
+    stats[1] = g->beta;
+    stats[2] = g->theta_l;
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Roots: stratified (systematic, proportional) root sampling                */
+/* ------------------------------------------------------------------------ */
+/* The pool's ids are cut into a ladder of blocks: block 0 = [0, Q), block
+ * b >= 1 = [Q 2^(b-1), Q 2^b), with Q = 2^qlog.  */
+void orc_block_of(uint64_t j, uint32_t qlog, uint32_t *b, uint64_t *J, uint64_t *T)
+{
+    uint64_t Q = (uint64_t)1 << qlog;
+    if (j < Q) { *b = 0; *J = 0; *T = Q; return; }
+    uint32_t bb = 1;
+    while (((Q << bb)) <= j) ++bb;
+    *b = bb;
+    *J = Q << (bb - 1);
+    *T = Q << (bb - 1);
+}
+
+/* The one random offset of block b in pool `pool`: o_b = floor(x * n / 2^64)
+ * with x the first two words of Philox at counter (b, ~0, ~0, pool). */
+uint64_t orc_block_offset(uint32_t n, uint64_t seed, uint32_t instance, uint32_t pool, uint32_t b)
+{
+    uint32_t ctr[4] = {b, 0xFFFFFFFFu, 0xFFFFFFFFu, pool};
+    uint32_t key[2] = {(uint32_t)seed, instance};
+    uint32_t out[4];
+    orc_philox4x32_10(ctr, key, out);
+    uint64_t x = (uint64_t)out[0] | ((uint64_t)out[1] << 32);
+    return (uint64_t)(((unsigned __int128)x * n) >> 64);
+}
+
+/* Algorithm 3 starts from "a randomly sampled node".  Here the sample is
+ * stratified: inside block b (size T) the t-th id takes the vertex at
+ * position floor((t n + o_b) / T) of the stratum-sorted list P, so every
+ * vertex is a root exactly T/n times in expectation and each stratum gets a
+ * quota within one of T N_h / n. */
+uint32_t orc_root(const orc_graph *g, uint64_t seed, uint32_t instance, uint32_t pool,
+                  uint64_t j, uint32_t qlog)
+{
+    uint32_t b;
+    uint64_t J, T;
+    orc_block_of(j, qlog, &b, &J, &T);
+    uint64_t o = orc_block_offset(g->n, seed, instance, pool, b);
+    unsigned __int128 pos = ((unsigned __int128)(j - J) * g->n + o) / T;
+    return g->P[(uint64_t)pos];
+}
+
+/* ------------------------------------------------------------------------ */
+/* One RR set (Algorithm 3's skeleton with per-channel coins)                */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    uint8_t *inR;
+    uint32_t *queue;
+} orc_scratch;
+
+/* R = {root}; pop v; for every hyperedge he containing v and every member u
+ * of he other than v, the channel u -> v is tested with its own coin; a live
+ * channel from a vertex outside R adds it to R and to the queue.  The result
+ * is the set of vertices with a live path to the root, written ascending. */
+static uint32_t orc_rr_into(const orc_graph *g, uint64_t seed, uint32_t instance, uint32_t pool,
+                            uint64_t j, uint32_t root, orc_scratch *s, uint32_t *out)
+{
+    uint32_t head = 0, tail = 0;
+    s->queue[tail++] = root;
+    s->inR[root] = 1;
+    while (head < tail) {
+        uint32_t v = s->queue[head++];
+        uint32_t thr = g->thr[v];
+        for (uint32_t e = g->v_off[v]; e < g->v_off[v + 1]; ++e) {
+            uint32_t he = g->v_he[e];
+            uint32_t base = g->he_off[he];
+            uint32_t size = g->he_off[he + 1] - base;
+            for (uint32_t pos = 0; pos < size; ++pos) {
+                uint32_t u = g->he_mem[base + pos];
+                if (u == v) continue;
+                if (!orc_live(orc_coin(seed, instance, pool, j, he, v, pos), thr)) continue;
+                if (s->inR[u]) continue;
+                s->inR[u] = 1;
+                s->queue[tail++] = u;
+            }
+        }
+    }
+    for (uint32_t i = 0; i < tail; ++i) {
+        out[i] = s->queue[i];
+        s->inR[s->queue[i]] = 0;
+    }
+    qsort(out, tail, sizeof(uint32_t), cmp_u32);
+    return tail;
+}
+
+/* RR set j of pool `pool` into out[] (room for n ids); returns its size. */
+uint32_t orc_rr_set(const orc_graph *g, uint64_t seed, uint32_t instance, uint32_t pool,
+                    uint64_t j, uint32_t qlog, uint32_t *out)
+{
+    orc_scratch s;
+    s.inR = (uint8_t *)calloc(g->n, 1);
+    s.queue = (uint32_t *)malloc(sizeof(uint32_t) * g->n);
+    uint32_t root = orc_root(g, seed, instance, pool, j, qlog);
+    uint32_t size = orc_rr_into(g, seed, instance, pool, j, root, &s, out);
+    free(s.inR);
+    free(s.queue);
+    return size;
+}
+
+/* Same, with a caller-chosen root (used by the statistical tests). */
+uint32_t orc_rr_set_rooted(const orc_graph *g, uint64_t seed, uint32_t instance, uint32_t pool,
+                           uint64_t j, uint32_t root, uint32_t *out)
+{
+    orc_scratch s;
+    s.inR = (uint8_t *)calloc(g->n, 1);
+    s.queue = (uint32_t *)malloc(sizeof(uint32_t) * g->n);
+    uint32_t size = orc_rr_into(g, seed, instance, pool, j, root, &s, out);
+    free(s.inR);
+    free(s.queue);
+    return size;
+}
+
+/* ---- many RR sets, one worker thread per host core ---------------------- */
+typedef struct {
+    const orc_graph *g;
+    uint64_t seed;
+    uint32_t instance, pool, qlog, tid, nthreads;
+    uint64_t id_begin, id_end;
+    const uint32_t *roots;    /* optional caller roots (iid baseline), else NULL */
+    uint32_t **buf;           /* per-id member arrays */
+    uint32_t *size;           /* per-id sizes */
+    uint32_t *root_out;
+    int err;
+} orc_gen_job;
+
+static void *orc_gen_worker(void *arg)
+{
+    orc_gen_job *job = (orc_gen_job *)arg;
+    const orc_graph *g = job->g;
+    orc_scratch s;
+    s.inR = (uint8_t *)calloc(g->n, 1);
+    s.queue = (uint32_t *)malloc(sizeof(uint32_t) * g->n);
+    uint32_t *tmp = (uint32_t *)malloc(sizeof(uint32_t) * g->n);
+    if (!s.inR || !s.queue || !tmp) { job->err = ORC_ENOMEM; goto done; }
+    for (uint64_t j = job->id_begin + job->tid; j < job->id_end; j += job->nthreads) {
+        uint64_t k = j - job->id_begin;
+        uint32_t root = job->roots ? job->roots[k]
+                                   : orc_root(g, job->seed, job->instance, job->pool, j, job->qlog);
+        uint32_t sz = orc_rr_into(g, job->seed, job->instance, job->pool, j, root, &s, tmp);
+        job->buf[k] = (uint32_t *)malloc(sizeof(uint32_t) * (sz ? sz : 1));
+        if (!job->buf[k]) { job->err = ORC_ENOMEM; goto done; }
+        memcpy(job->buf[k], tmp, sizeof(uint32_t) * sz);
+        job->size[k] = sz;
+        job->root_out[k] = root;
+    }
+done:
+    free(s.inR);
+    free(s.queue);
+    free(tmp);
+    return NULL;
+}
+
+/* RR sets [id_begin, id_end) of one pool as a CSR: *off_out (count+1, u64),
+ * *mem_out (members, ascending inside each set), *roots_out.  The arrays are
+ * malloc'ed here and released with orc_free. */
+int orc_generate(const orc_graph *g, uint64_t seed, uint32_t instance, uint32_t pool,
+                 uint64_t id_begin, uint64_t id_end, uint32_t qlog, uint32_t nthreads,
+                 const uint32_t *roots_in,
+                 uint64_t **off_out, uint32_t **mem_out, uint32_t **roots_out)
+{
+    if (!g->stratified && !roots_in) return ORC_EINVAL;
+    if (id_end < id_begin) return ORC_EINVAL;
+    uint64_t count = id_end - id_begin;
+    if (nthreads == 0) nthreads = 1;
+    uint32_t **buf = (uint32_t **)calloc(count ? count : 1, sizeof(uint32_t *));
+    uint32_t *size = (uint32_t *)calloc(count ? count : 1, sizeof(uint32_t));
+    uint32_t *roots = (uint32_t *)malloc(sizeof(uint32_t) * (count ? count : 1));
+    uint64_t *off = (uint64_t *)malloc(sizeof(uint64_t) * (count + 1));
+    if (!buf || !size || !roots || !off) {
+        free(buf); free(size); free(roots); free(off);
+        return ORC_ENOMEM;
+    }
+    orc_gen_job *jobs = (orc_gen_job *)calloc(nthreads, sizeof(orc_gen_job));
+    pthread_t *th = (pthread_t *)calloc(nthreads, sizeof(pthread_t));
+    int err = ORC_OK;
+    for (uint32_t t = 0; t < nthreads; ++t) {
+        orc_gen_job jb = {g, seed, instance, pool, qlog, t, nthreads, id_begin, id_end,
+                          roots_in, buf, size, roots, ORC_OK};
+        jobs[t] = jb;
+        if (nthreads == 1) orc_gen_worker(&jobs[t]);
+        else pthread_create(&th[t], NULL, orc_gen_worker, &jobs[t]);
+    }
+    if (nthreads > 1)
+        for (uint32_t t = 0; t < nthreads; ++t) pthread_join(th[t], NULL);
+    for (uint32_t t = 0; t < nthreads; ++t)
+        if (jobs[t].err) err = jobs[t].err;
+    free(jobs);
+    free(th);
+    uint32_t *mem = NULL;
+    if (err == ORC_OK) {
+        off[0] = 0;
+        for (uint64_t k = 0; k < count; ++k) off[k + 1] = off[k] + size[k];
+        mem = (uint32_t *)malloc(sizeof(uint32_t) * (off[count] ? off[count] : 1));
+        if (!mem) err = ORC_ENOMEM;
+        else
+            for (uint64_t k = 0; k < count; ++k)
+                memcpy(mem + off[k], buf[k], sizeof(uint32_t) * size[k]);
+    }
+    for (uint64_t k = 0; k < count; ++k) free(buf[k]);
+    free(buf);
+    free(size);
+    if (err != ORC_OK) { free(off); free(roots); free(mem); return err; }
+    *off_out = off;
+    *mem_out = mem;
+    *roots_out = roots;
+    return ORC_OK;
+}
+
+void orc_free(void *p) { free(p); }
+
+/* ------------------------------------------------------------------------ */
+/* Greedy max coverage (Algorithm 1, Equations (1)-(2))                      */
+/* ------------------------------------------------------------------------ */
+/* k rounds over the first theta sets of a pool: take the vertex of largest
+ * marginal coverage (ties -> smallest id; a chosen vertex is never chosen
+ * again, even when every count has dropped to zero), add it to S and remove
+ * every set it covers.  gains[i] is the marginal coverage of the i-th seed;
+ * their sum is the coverage Lambda_R(S_k). */
+int orc_greedy(uint32_t n, uint64_t theta, const uint64_t *off, const uint32_t *mem, uint32_t k,
+               uint32_t *seeds, uint64_t *gains)
+{
+    if (k == 0 || k > n) return ORC_EINVAL;
+    uint64_t total = off[theta];
+    uint64_t *cnt = (uint64_t *)calloc(n, sizeof(uint64_t));
+    uint64_t *inv_off = (uint64_t *)calloc((uint64_t)n + 1, sizeof(uint64_t));
+    uint64_t *fill = (uint64_t *)calloc(n, sizeof(uint64_t));
+    uint64_t *inv = (uint64_t *)malloc(sizeof(uint64_t) * (total ? total : 1));
+    uint8_t *covered = (uint8_t *)calloc(theta ? theta : 1, 1);
+    uint8_t *chosen = (uint8_t *)calloc(n, 1);
+    if (!cnt || !inv_off || !fill || !inv || !covered || !chosen) {
+        free(cnt); free(inv_off); free(fill); free(inv); free(covered); free(chosen);
+        return ORC_ENOMEM;
+    }
+    for (uint64_t e = 0; e < total; ++e) cnt[mem[e]]++;
+    for (uint32_t v = 0; v < n; ++v) inv_off[v + 1] = inv_off[v] + cnt[v];
+    for (uint64_t j = 0; j < theta; ++j)
+        for (uint64_t e = off[j]; e < off[j + 1]; ++e) {
+            uint32_t u = mem[e];
+            inv[inv_off[u] + fill[u]++] = j;
+        }
+    for (uint32_t i = 0; i < k; ++i) {
+        uint32_t best = 0xFFFFFFFFu;
+        for (uint32_t v = 0; v < n; ++v) {
+            if (chosen[v]) continue;
+            if (best == 0xFFFFFFFFu || cnt[v] > cnt[best]) best = v;
+        }
+        seeds[i] = best;
+        gains[i] = cnt[best];
+        chosen[best] = 1;
+        for (uint64_t x = inv_off[best]; x < inv_off[best + 1]; ++x) {
+            uint64_t j = inv[x];
+            if (covered[j]) continue;
+            covered[j] = 1;
+            for (uint64_t e = off[j]; e < off[j + 1]; ++e) cnt[mem[e]]--;
+        }
+    }
+    free(cnt); free(inv_off); free(fill); free(inv); free(covered); free(chosen);
+    return ORC_OK;
+}
+
+/* Lambda_R(S): the number of sets among the first theta that meet S. */
+uint64_t orc_coverage(uint32_t n, uint64_t theta, const uint64_t *off, const uint32_t *mem,
+                      uint32_t k, const uint32_t *seeds)
+{
+    uint8_t *inS = (uint8_t *)calloc(n ? n : 1, 1);
+    for (uint32_t i = 0; i < k; ++i) inS[seeds[i]] = 1;
+    uint64_t hit = 0;
+    for (uint64_t j = 0; j < theta; ++j) {
+        int h = 0;
+        for (uint64_t e = off[j]; e < off[j + 1] && !h; ++e) h = inS[mem[e]];
+        hit += (uint64_t)h;
+    }
+    free(inS);
+    return hit;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Sample-size control (Section 4, Algorithm 4)                              */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    double delta, lnC, theta_max, theta0, a;
+    uint64_t theta1;
+    uint32_t i_max;
+} orc_schedule;
+
+/* delta = |V|^-ell.  ln C(n,k) summed term by term in ascending i.
+ * theta_max follows Lemma 6 in the OPIM-C form the lemma cites:
+ *   2n (t sqrt(ln(6/delta)) + sqrt(t (ln C(n,k) + ln(6/delta))))^2 / (eps^2 k),
+ * t = 1 - 1/e.  theta_0 = theta_max eps^2 k / n, rounded up to a ladder
+ * boundary Q 2^b (and at least Q).  i_max is the first round whose size
+ * reaches theta_max; a = ln(3 i_max / delta) spreads delta over the rounds
+ * and the two bounds. */
+int orc_make_schedule(uint32_t n, uint32_t k, double eps, double ell, uint32_t qlog, orc_schedule *s)
+{
+    if (n == 0 || k == 0 || k > n || !(eps > 0.0 && eps < 1.0) || !(ell > 0.0)) return ORC_EINVAL;
+    double t = 1.0 - exp(-1.0);
+    double lndelta_inv = ell * log((double)n);          /* ln(1/delta) */
+    s->delta = exp(-lndelta_inv);
+    double lnC = 0.0;
+    for (uint32_t i = 0; i < k; ++i) lnC += log((double)(n - i) / (double)(i + 1));
+    s->lnC = lnC;
+    double l6 = log(6.0) + lndelta_inv;
+    double root = t * sqrt(l6) + sqrt(t * (lnC + l6));
+    s->theta_max = 2.0 * (double)n * root * root / (eps * eps * (double)k);
+    s->theta0 = s->theta_max * eps * eps * (double)k / (double)n;
+    uint64_t Q = (uint64_t)1 << qlog;
+    uint64_t th = Q;
+    while ((double)th < s->theta0) th <<= 1;
+    s->theta1 = th;
+    uint32_t i = 1;
+    while ((double)th < s->theta_max) { th <<= 1; ++i; }
+    s->i_max = i;
+    s->a = log(3.0 * (double)i) + lndelta_inv;
+    return ORC_OK;
+}
+
+/* Equation (12): lower bound on the spread of S* from its coverage Lambda2
+ * in the independent pool R2 of size theta (clamped at zero). */
+double orc_sigma_lower(double lambda2, double a, double n, double theta)
+{
+    double r = sqrt(lambda2 + 2.0 * a / 9.0) - sqrt(a / 2.0);
+    double v = r * r - a / 18.0;
+    if (v < 0.0) v = 0.0;
+    return v * n / theta;
+}
+
+/* Lemma 5 with p_max = 1: the optimum's coverage in R1 is at most
+ * Lambda1 / (1 - (1 - 1/k)^k); lifted to spread by the same concentration
+ * term as the lower bound. */
+double orc_sigma_upper(double lambda1, uint32_t k, double a, double n, double theta)
+{
+    double up = lambda1 / (1.0 - pow(1.0 - 1.0 / (double)k, (double)k));
+    double r = sqrt(up + a / 2.0) + sqrt(a / 2.0);
+    return r * r * n / theta;
+}
+
+typedef struct {
+    uint32_t rounds;
+    uint32_t i_max;
+    uint64_t theta;
+    uint64_t lambda1, lambda2;
+    double sigma_l, sigma_u, spread, theta_max;
+    uint64_t entries1, entries2;
+} orc_result;
+
+/* HyperIM_BRR (Algorithm 4): two independent pools R1 (tag 0) and R2 (tag 1)
+ * grow together over ladder prefixes theta_i = theta_1 2^(i-1); S* = greedy
+ * on R1; Lambda2 = coverage of S* in R2; stop once sigma_l / sigma_u >=
+ * 1 - 1/e - eps or at round i_max.  theta_fixed > 0 runs one round of that
+ * size with no bound test. */
+int orc_select_seeds(const orc_graph *g, uint32_t k, double eps, double ell, uint64_t seed,
+                     uint32_t instance, uint32_t qlog, uint64_t theta_fixed, uint32_t nthreads,
+                     uint32_t *seeds, uint64_t *gains, orc_result *res)
+{
+    if (!g->stratified) return ORC_EINVAL;
+    orc_schedule s;
+    int rc = orc_make_schedule(g->n, k, eps, ell, qlog, &s);
+    if (rc) return rc;
+    memset(res, 0, sizeof(*res));
+    res->i_max = s.i_max;
+    res->theta_max = s.theta_max;
+    double t = 1.0 - exp(-1.0);
+    uint64_t have = 0;
+    uint64_t *off1 = (uint64_t *)calloc(1, sizeof(uint64_t)), *off2 = (uint64_t *)calloc(1, sizeof(uint64_t));
+    uint32_t *mem1 = NULL, *mem2 = NULL;
+    uint32_t i_max = theta_fixed ? 1u : s.i_max;
+    for (uint32_t i = 1; i <= i_max; ++i) {
+        uint64_t theta = theta_fixed ? theta_fixed : (s.theta1 << (i - 1));
+        for (uint32_t pool = 0; pool < 2; ++pool) {
+            uint64_t *o, *noff; uint32_t *mm, *r;
+            rc = orc_generate(g, seed, instance, pool, have, theta, qlog, nthreads, NULL, &o, &mm, &r);
+            if (rc) goto out;
+            uint64_t **poff = pool ? &off2 : &off1;
+            uint32_t **pmem = pool ? &mem2 : &mem1;
+            uint64_t old_total = (*poff)[have];
+            uint64_t add = o[theta - have];
+            noff = (uint64_t *)realloc(*poff, sizeof(uint64_t) * (theta + 1));
+            uint32_t *nmem = (uint32_t *)realloc(*pmem, sizeof(uint32_t) * (old_total + add + 1));
+            if (!noff || !nmem) { rc = ORC_ENOMEM; free(o); free(mm); free(r); goto out; }
+            for (uint64_t x = 1; x <= theta - have; ++x) noff[have + x] = old_total + o[x];
+            memcpy(nmem + old_total, mm, sizeof(uint32_t) * add);
+            *poff = noff;
+            *pmem = nmem;
+            free(o); free(mm); free(r);
+        }
+        have = theta;
+        rc = orc_greedy(g->n, theta, off1, mem1, k, seeds, gains);
+        if (rc) goto out;
+        uint64_t lambda1 = 0;
+        for (uint32_t x = 0; x < k; ++x) lambda1 += gains[x];
+        uint64_t lambda2 = orc_coverage(g->n, theta, off2, mem2, k, seeds);
+        double sl = orc_sigma_lower((double)lambda2, s.a, (double)g->n, (double)theta);
+        double su = orc_sigma_upper((double)lambda1, k, s.a, (double)g->n, (double)theta);
+        res->rounds = i;
+        res->theta = theta;
+        res->lambda1 = lambda1;
+        res->lambda2 = lambda2;
+        res->sigma_l = sl;
+        res->sigma_u = su;
+        res->spread = (double)g->n * (double)lambda2 / (double)theta;
+        res->entries1 = off1[theta];
+        res->entries2 = off2[theta];
+        if (theta_fixed) break;
+        if (su > 0.0 && sl / su >= t - eps) break;
+    }
+out:
+    free(off1); free(off2); free(mem1); free(mem2);
+    return rc;
+}
