@@ -1,0 +1,162 @@
+"""Benchmark of HyperIM's hot path on one MI355X.
+
+One step = one whole query on a device-resident synthetic hypergraph:
+build the incidence CSR and thresholds, stratify, then the HyperIM_BRR loop
+(RR-set generation for both pools, greedy max coverage, R2 check, doubling)
+until the seed set is returned.  Inputs (he_off, he_mem) are already in HBM
+when the timed region starts.
+
+Prints one JSON line: RR sets/s (value), incidences/s, time-to-seed-set, the
+roofline of the RR-generation kernel (algorithmic bytes per launch over its
+HIP-event-timed average duration, against 8 TB/s) and the CPU oracle timed on
+a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+WORKLOAD_TEXT = {
+    "tiny": "|V|=1e3 |HE|=2e3 sizes U[2,6] uniform members, IC p=0.05, k=10 eps=0.5 ell=1",
+    "mid": "|V|=1e5 |HE|=2e5 sizes power-law(2.5) on [2,50], Zipf(1.0) members, weighted cascade, "
+           "k=50 eps=0.1 ell=1",
+    "large": "|V|=1e6 |HE|=2e6 sizes power-law(2.2) on [2,200], Zipf(1.1) members, IC p=0.01, "
+             "k=100 eps=0.1 ell=1",
+}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="mid", choices=sorted(WORKLOAD_TEXT))
+    ap.add_argument("--form", type=int, default=0, help="0 persistent launch per pool block, 1 plain per stratum")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU-baseline sample time")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+def cpu_baseline(hg, w, seconds: float):
+    """The oracle as it stands, on the host cores: RR sets of pool R1 from id 0
+    in chunks until about `seconds` of CPU work (build + stratify untimed)."""
+    import oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
+    threads = max(1, min(threads, os.cpu_count() or 1))
+    o = oracle.Graph(hg, w.model, w.p)
+    o.stratify()
+    done, chunk, t0 = 0, 512, time.perf_counter()
+    while True:
+        o.generate(w.philox_seed, 0, 0, done, done + chunk, nthreads=threads)
+        done += chunk
+        el = time.perf_counter() - t0
+        if el >= seconds or done >= (1 << 22):
+            break
+        if el < seconds / 4:
+            chunk *= 2
+    return {"value": done / el, "unit": "RR sets/s", "cores": threads, "kind": "oracle",
+            "sample": f"RR ids [0, {done}) of pool R1 of the same workload, {el:.1f} s wall, "
+                      f"{threads} threads over ids"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
+              "sharding of RR ids is a design note, not a measured path.", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import hypergen
+    import paper_2406_01911_amd as hy
+
+    hy.load_library()
+    torch.cuda.set_device(0)
+    w = hypergen.workload(args.workload)
+    hg = w.build()
+    dev_off = torch.from_numpy(hg.he_off.view(np.int32)).cuda()
+    dev_mem = torch.from_numpy(hg.he_mem.view(np.int32)).cuda()
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+
+    def step(flags=0):
+        g = hy.build_graph(hg.n, dev_off, dev_mem, w.model, w.p, stream=stream)
+        g.stratify(stream=stream)
+        r = hy.select_seeds(g, w.k, w.eps, w.ell, seed=w.philox_seed, form=args.form, flags=flags, stream=stream)
+        del g
+        return r
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    results = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        results.append(step())
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    # identical query with the incidence / byte counters switched on (untimed)
+    meas = step(flags=hy.FLAG_INCIDENCES)
+    last = results[-1]
+    assert np.array_equal(meas["seeds"], last["seeds"]) and meas["theta"] == last["theta"]
+
+    ms_per_step = 1000.0 * elapsed / args.steps
+    rr_sets_per_step = 2 * last["theta"]
+    value = rr_sets_per_step * args.steps / elapsed
+    inc_per_s = meas["incidences"] * args.steps / elapsed
+    bfs_ms = float(np.mean([r["ms_bfs"] for r in results]))
+    launches = last["bfs_launches"]
+    alg_bytes = meas["alg_bytes"]
+    achieved = alg_bytes / (bfs_ms * 1e-3) / 1e9 if bfs_ms > 0 else 0.0
+    line = {
+        "metric": "RR sets/s",
+        "value": value,
+        "unit": "RR sets/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {WORKLOAD_TEXT[args.workload]}",
+                   "form": "persistent" if args.form == 0 else "plain-per-stratum",
+                   "parallelism": "single-gpu"},
+        "incidences_per_s": inc_per_s,
+        "time_to_seed_set_ms": ms_per_step,
+        "theta": last["theta"],
+        "rounds": last["rounds"],
+        "spread": last["spread"],
+        "ms_rr": float(np.mean([r["ms_rr"] for r in results])),
+        "ms_greedy": float(np.mean([r["ms_greedy"] for r in results])),
+        "roofline": {
+            "kernel": "k_rr_bfs",
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+            "alg_bytes_per_launch": alg_bytes / max(launches, 1),
+            "avg_launch_ms": bfs_ms / max(launches, 1),
+            "launches_per_step": launches,
+        },
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(hg, w, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

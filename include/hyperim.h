@@ -1,0 +1,214 @@
+/*
+ * hyperim.h -- C ABI of libhyperim.so, an MI355X (gfx950) implementation of
+ * the hot path of HyperIM: influence maximization in hypergraphs by
+ * stratified reverse-reachable (RR) set sampling and greedy max coverage.
+ *
+ * Problem (Section 2.1, Definition 1): given a hypergraph G = (V, HE), an
+ * integer k and a cascade model, find k vertices of largest expected
+ * influence in the weighted clique graph G_w.  Influence is estimated from
+ * RR sets (Equation (1)): I(S) = |V| Pr[S meets R], estimated as
+ * |V| Lambda_R(S) / |R|.
+ *
+ * Conventions for every call:
+ *   - return value: HYPERIM_OK (0) or a negative status below; on error no
+ *     output is partially valid and hyperim_strerror() names the cause;
+ *   - `stream` is a hipStream_t (NULL = the default stream); device work is
+ *     ordered on it; calls that return host values synchronise it first;
+ *   - input arrays are borrowed for the duration of the call and never
+ *     retained; handles own their device memory until *_free;
+ *   - vertex ids are uint32 in [0, n); hyperedge ids uint32 in [0, m);
+ *     n, m < 2^32 - 1 and the number of incidences nnz = he_off[m] < 2^32;
+ *   - distinct handles may be used from different threads; one handle must
+ *     not be used by two threads at once.
+ */
+#ifndef HYPERIM_H
+#define HYPERIM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HYPERIM_OK 0
+#define HYPERIM_EINVAL (-1)     /* bad argument or malformed hypergraph        */
+#define HYPERIM_ENOMEM (-2)     /* device or host allocation failed             */
+#define HYPERIM_ECAPACITY (-3)  /* caller-provided pool buffer too small        */
+#define HYPERIM_ESTATE (-4)     /* call out of order (e.g. before stratify)     */
+#define HYPERIM_EHIP (-5)       /* HIP runtime error (see hyperim_strerror)     */
+
+#define HYPERIM_MODEL_CONST 0u  /* every channel into v live with probability p */
+#define HYPERIM_MODEL_WC 1u     /* weighted cascade: p_v = 1 / c(v)             */
+#define HYPERIM_NSTRATA 8u
+
+typedef struct hyperim_graph_s *hyperim_graph;
+typedef struct hyperim_pool_s *hyperim_pool;
+
+/* Independent-cascade channel probabilities (Section 2.1, "Cascade models",
+ * IC).  Every hyperedge he and every ordered pair u != v of its members is
+ * one channel u -> v, live with probability p_v of the target:
+ *   HYPERIM_MODEL_CONST: p_v = p (p >= 1 means always live; p must not be
+ *                        NaN or negative);
+ *   HYPERIM_MODEL_WC:    p_v = (float)(1.0 / c(v)), c(v) = sum over
+ *                        hyperedges he containing v of (|he| - 1), the
+ *                        weighted in-degree of v in G_w; p is ignored.
+ * A channel is live when its coin is below floor(p_v * 2^32). */
+typedef struct {
+    uint32_t model;
+    float p;
+} hyperim_prob;
+
+/* Statistics of the sample-set layers (Section 3.1.1; Section 4.1's F_cnt,
+ * T_cnt, L_cnt; Theorem 2's theta(l*)) and the strata boundaries. */
+typedef struct {
+    uint32_t B[HYPERIM_NSTRATA + 1]; /* stratum h holds P[B[h] .. B[h+1])      */
+    uint64_t sum_top;                /* F_cnt = sum_v n(L_1(v))                 */
+    uint64_t sum_deg;                /* T_cnt = sum_v deg(v) in G_w             */
+    uint64_t sum_l;                  /* L_cnt = sum_v l_v                       */
+    double alpha;                    /* F_cnt / T_cnt                           */
+    double beta;                     /* L_cnt / |V|                             */
+    double theta_l;                  /* (1/|V|) sum_v l_v / ln(l_v + 1)         */
+} hyperim_strata_info;
+
+/* Options of hyperim_select_seeds (zero-initialised = defaults). */
+typedef struct {
+    uint32_t qlog;          /* pool ladder base Q = 2^qlog; 0 -> 8; max 24    */
+    uint32_t form;          /* 0: one persistent launch per pool block;
+                               1: plain form, one launch per stratum          */
+    uint64_t theta_fixed;   /* > 0: one round of exactly this many RR sets per
+                               pool and no bound test                         */
+    uint64_t max_entries;   /* > 0: fail with HYPERIM_ECAPACITY rather than let
+                               a pool exceed this many members                */
+    uint32_t flags;         /* HYPERIM_FLAG_* bits                            */
+    uint32_t reserved;
+} hyperim_options;
+
+#define HYPERIM_FLAG_INCIDENCES 1u  /* fill hyperim_result.incidences (one extra
+                                       pass over the final pools)            */
+
+/* Outcome of hyperim_select_seeds. */
+typedef struct {
+    uint32_t rounds;        /* doubling rounds executed                       */
+    uint32_t i_max;         /* last admissible round                          */
+    uint64_t theta;         /* RR sets per pool in the final round            */
+    uint64_t lambda1;       /* coverage of S* in R1 (sum of the gains)        */
+    uint64_t lambda2;       /* coverage of S* in R2                           */
+    double sigma_l;         /* Equation (12) lower bound on I(S*)             */
+    double sigma_u;         /* Lemma 5 upper bound on the optimum             */
+    double spread;          /* |V| lambda2 / theta, unbiased estimate of I(S*)*/
+    double theta_max;       /* Lemma 6 / Equation (13) cap                    */
+    uint64_t entries1;      /* members stored in R1[0, theta)                 */
+    uint64_t entries2;      /* members stored in R2[0, theta)                 */
+    uint64_t incidences;    /* incidences read by RR generation (both pools)  */
+    double ms_rr;           /* device time in RR generation + compaction      */
+    double ms_greedy;       /* device time in coverage, greedy and R2 check   */
+    double ms_total;        /* wall time of the call                          */
+    uint64_t alg_bytes;     /* algorithmic bytes of RR generation (both pools):
+                               sum over members v of 20 + 12 d(v) + 4 S(v),
+                               d(v) = hyperedges of v, S(v) = their total size;
+                               filled with HYPERIM_FLAG_INCIDENCES            */
+    double ms_bfs;          /* device time of the RR-generation kernels alone  */
+    uint64_t bfs_launches;  /* number of RR-generation kernel launches         */
+} hyperim_result;
+
+/* Build the device-resident hypergraph (Section 2.1: G = (V, HE), V(he)).
+ * he_off[m+1] (nondecreasing, he_off[0] = 0) and he_mem[he_off[m]] give the
+ * members of every hyperedge in the caller's order; ptrs_on_device != 0 means
+ * both are device pointers, else host pointers.  Hyperedges of size 0 or 1
+ * are legal (no channels); a vertex repeated inside one hyperedge, an id >= n
+ * or decreasing offsets give HYPERIM_EINVAL.  Builds the vertex -> hyperedge
+ * incidence lists (ascending hyperedge ids) and per-target coin thresholds;
+ * the clique graph G_w is never materialised.  *out receives a new handle. */
+int hyperim_build_graph(uint32_t n, uint32_t m, const uint32_t *he_off, const uint32_t *he_mem,
+                        int ptrs_on_device, hyperim_prob prob, void *stream, hyperim_graph *out);
+
+/* Sample-set division (Section 3.1.1): for each vertex v, the co-membership
+ * weight w(v,u) = number of hyperedges shared with u; the layers of A(v) are
+ * its groups of equal w (layer 1 = largest w); l_v = number of layers,
+ * deg(v) = |A(v)|, top(v) = n(L_1).  Stratum s(v) = 0 if l_v = 0, else
+ * min(7, 1 + floor(log2 l_v)); P = vertices sorted by (s(v), v).  Required
+ * before hyperim_generate_rr / hyperim_select_seeds.  `out` may be NULL. */
+int hyperim_stratify(hyperim_graph g, void *stream, hyperim_strata_info *out);
+
+/* Copy the graph's derived arrays to caller buffers (host pointers unless
+ * dst_on_device != 0); any pointer may be NULL.  Sizes: v_off n+1, v_he nnz,
+ * thr n, c n (uint64), l/deg/top/P n, stratum n (uint8).  The strata arrays
+ * need a prior hyperim_stratify (else HYPERIM_ESTATE). */
+int hyperim_graph_read(hyperim_graph g, uint32_t *v_off, uint32_t *v_he, uint32_t *thr, uint64_t *c,
+                       uint32_t *l, uint32_t *deg, uint32_t *top, uint8_t *stratum, uint32_t *P,
+                       int dst_on_device, void *stream);
+
+/* A pool of RR sets stored as a CSR over consecutive ids.  dev_buf == NULL:
+ * the library allocates and grows the storage.  Otherwise the caller's
+ * device buffer of `bytes` bytes holds everything (it is never freed by the
+ * library) and `id_capacity` bounds the number of ids; a generate call that
+ * does not fit returns HYPERIM_ECAPACITY and hyperim_pool_required() then
+ * reports the bytes needed. */
+int hyperim_pool_create(hyperim_graph g, void *dev_buf, size_t bytes, uint64_t id_capacity,
+                        hyperim_pool *out);
+
+/* RR sets [id_begin, id_end) of pool `pool_tag` (0 = R1, 1 = R2) for key
+ * (seed, instance), appended to `pool`.  An empty pool accepts any id_begin;
+ * a non-empty pool only its current end and the same (seed, instance,
+ * pool_tag) (else HYPERIM_EINVAL).  seed must be < 2^32.
+ * RR set j (Algorithm 3's skeleton): root r(j) from the stratified ladder
+ * (block b of the pool's ladder, t-th id of the block: P[floor((t n + o_b) /
+ * T_b)]), then every vertex with a live path of channels to the root.
+ * Channel (he, u -> v) of RR set j is live when word (pos & 3) of
+ * Philox4x32-10 with key (seed, instance) and counter
+ * (j mod 2^32, he, v, pool_tag << 31 | (j >> 32) << 24 | pos >> 2), pos being
+ * u's index in he, is below v's threshold.  Members are stored ascending. */
+int hyperim_generate_rr(hyperim_graph g, uint64_t seed, uint32_t instance, uint32_t pool_tag,
+                        uint64_t id_begin, uint64_t id_end, hyperim_pool pool, void *stream);
+
+/* Device pointers of the pool's CSR (rr_off[count+1] uint64 relative to the
+ * pool, rr_mem, rr_root[count]) and its id range; valid until the next call
+ * on the pool. */
+int hyperim_pool_view(hyperim_pool pool, const uint64_t **off, const uint32_t **mem,
+                      const uint32_t **roots, uint64_t *id_begin, uint64_t *count);
+
+/* Copy the pool's CSR to caller buffers (host unless dst_on_device != 0). */
+int hyperim_pool_read(hyperim_pool pool, uint64_t *off, uint32_t *mem, uint32_t *roots,
+                      int dst_on_device, void *stream);
+
+/* Bytes a caller buffer needs for the last failed generate call. */
+int hyperim_pool_required(hyperim_pool pool, size_t *bytes);
+
+/* Empty the pool (keeps its storage). */
+int hyperim_pool_reset(hyperim_pool pool);
+
+/* Greedy max coverage over the first theta sets of a pool (Algorithm 1 with
+ * Equation (2)): k rounds, each taking the unchosen vertex of largest
+ * marginal coverage (ties to the smallest id) and removing the sets it
+ * covers.  seeds[k] and gains[k] are host arrays. */
+int hyperim_greedy(hyperim_graph g, hyperim_pool pool, uint64_t theta, uint32_t k, void *stream,
+                   uint32_t *seeds, uint64_t *gains);
+
+/* Lambda_R(S): how many of the first theta sets of the pool meet the k seeds
+ * (host array). */
+int hyperim_coverage(hyperim_graph g, hyperim_pool pool, uint64_t theta, const uint32_t *seeds,
+                     uint32_t k, void *stream, uint64_t *covered);
+
+/* HyperIM_BRR (Algorithm 4) with delta = n^-ell: pools R1 and R2 grow over
+ * the ladder theta_i = theta_1 2^(i-1) (theta_1 = theta_0 of Section 4.3
+ * rounded up to the ladder); S* = greedy on R1[0, theta_i); Lambda2 =
+ * coverage of S* in R2[0, theta_i); stop when sigma_l / sigma_u >=
+ * 1 - 1/e - eps (Equation (12), Lemma 5 with p_max = 1) or at round i_max,
+ * where theta_i reaches theta_max (Lemma 6 in its OPIM-C form).
+ * seeds[k] and gains[k] are host arrays; `opt` may be NULL. */
+int hyperim_select_seeds(hyperim_graph g, uint32_t k, double eps, double ell, uint64_t seed,
+                         uint32_t instance, const hyperim_options *opt, void *stream,
+                         uint32_t *seeds, uint64_t *gains, hyperim_result *out);
+
+void hyperim_pool_free(hyperim_pool pool);
+void hyperim_graph_free(hyperim_graph g);
+
+/* Text for a status code (thread-local detail of the last HIP error). */
+const char *hyperim_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HYPERIM_H */

@@ -1,0 +1,328 @@
+// Greedy max coverage over an RR-set pool (Algorithm 1 with the marginal
+// coverage of Equation (2)) and the coverage count Lambda_R(S) of a seed set
+// (Equation (1)'s estimator numerator).
+//
+// Coverage counts cnt[v] start as the number of sets containing v; an
+// inverted index (counting sort by vertex) lists the sets of each vertex.
+// Each round takes the argmax of the key (cnt+1, -v) over unchosen vertices
+// -- largest marginal coverage, ties to the smallest id -- with a device-wide
+// 64-bit max, then invalidates: every not-yet-covered set of the seed is
+// marked covered and each of its members loses one count.  Every set is
+// invalidated at most once, so all rounds together touch each pool entry at
+// most once.  Small sets are processed by wavefronts flattened over 64 sets,
+// sets above kBigSet members by whole workgroups.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "dev_common.h"
+#include "internal.h"
+
+namespace hyperim {
+namespace {
+
+constexpr int kWG = 256;
+constexpr int kWavesPerWG = kWG / kWave;
+constexpr uint32_t kBigSet = 4096;
+
+__global__ void k_hist(const uint32_t *__restrict__ mem, uint64_t entries, uint32_t *__restrict__ cnt) {
+    for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < entries;
+         e += (uint64_t)gridDim.x * blockDim.x)
+        atomicAdd(&cnt[mem[e]], 1u);
+}
+
+__global__ void k_big_list(const uint64_t *__restrict__ off, uint64_t theta, uint64_t *__restrict__ list,
+                           unsigned long long *__restrict__ count) {
+    for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < theta;
+         j += (uint64_t)gridDim.x * blockDim.x)
+        if (off[j + 1] - off[j] > kBigSet) list[atomicAdd(count, 1ull)] = j;
+}
+
+// Per wave: 64 lane-owned segments mem[beg_k, beg_k + len_k), flattened.
+struct FlatLds {
+    uint32_t scan[kWave];
+    uint64_t beg[kWave];
+    uint64_t tag[kWave];
+};
+
+template <typename F>
+__device__ __forceinline__ void wave_flat(FlatLds &L, uint32_t len, uint64_t beg, uint64_t tag, F &&body) {
+    const uint32_t lane = lane_id();
+    const uint32_t incl = wave_incl_scan(len);
+    const uint32_t total = wave_bcast(incl, kWave - 1);
+    wave_sync();
+    L.scan[lane] = incl;
+    L.beg[lane] = beg;
+    L.tag[lane] = tag;
+    wave_sync();
+    for (uint32_t base = 0; base < total; base += kWave) {
+        const uint32_t g = base + lane;
+        if (g < total) {
+            const uint32_t k = search64(L.scan, g);
+            const uint32_t e = g - (k ? L.scan[k - 1] : 0u);
+            body(k, L.beg[k] + e, L.tag[k]);
+        }
+    }
+    wave_sync();
+}
+
+__global__ __launch_bounds__(kWG) void k_inv_small(const uint64_t *__restrict__ off, const uint32_t *__restrict__ mem,
+                                                    uint64_t theta, const uint64_t *__restrict__ inv_off,
+                                                    uint32_t *__restrict__ cursor, uint32_t *__restrict__ inv) {
+    __shared__ FlatLds lds[kWavesPerWG];
+    const uint32_t wv = threadIdx.x / kWave;
+    const uint64_t waves = (uint64_t)gridDim.x * kWavesPerWG;
+    for (uint64_t grp = (uint64_t)blockIdx.x * kWavesPerWG + wv; grp * kWave < theta; grp += waves) {
+        const uint64_t j = grp * kWave + lane_id();
+        uint32_t len = 0;
+        uint64_t beg = 0;
+        if (j < theta) {
+            beg = off[j];
+            const uint64_t sz = off[j + 1] - beg;
+            len = sz > kBigSet ? 0u : (uint32_t)sz;
+        }
+        wave_flat(lds[wv], len, beg, j, [&](uint32_t, uint64_t e, uint64_t set) {
+            const uint32_t u = mem[e];
+            const uint32_t pos = atomicAdd(&cursor[u], 1u);
+            inv[inv_off[u] + pos] = (uint32_t)set;
+        });
+    }
+}
+
+__global__ __launch_bounds__(kWG) void k_inv_big(const uint64_t *__restrict__ off, const uint32_t *__restrict__ mem,
+                                                  const uint64_t *__restrict__ list,
+                                                  const unsigned long long *__restrict__ count,
+                                                  const uint64_t *__restrict__ inv_off, uint32_t *__restrict__ cursor,
+                                                  uint32_t *__restrict__ inv) {
+    const uint64_t nb = *count;
+    for (uint64_t b = blockIdx.x; b < nb; b += gridDim.x) {
+        const uint64_t j = list[b];
+        for (uint64_t e = off[j] + threadIdx.x; e < off[j + 1]; e += blockDim.x) {
+            const uint32_t u = mem[e];
+            const uint32_t pos = atomicAdd(&cursor[u], 1u);
+            inv[inv_off[u] + pos] = (uint32_t)j;
+        }
+    }
+}
+
+// key = 0 for chosen vertices, else (cnt + 1) << 32 | (~v): the max is the
+// largest count, then the smallest id.
+__global__ __launch_bounds__(kWG) void k_argmax(const uint32_t *__restrict__ cnt, const uint8_t *__restrict__ chosen,
+                                                 uint32_t n, unsigned long long *__restrict__ best) {
+    __shared__ unsigned long long part[kWavesPerWG];
+    unsigned long long m = 0;
+    for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+        const unsigned long long key =
+            chosen[v] ? 0ull : (((unsigned long long)cnt[v] + 1ull) << 32) | (unsigned long long)(0xFFFFFFFFu - v);
+        m = key > m ? key : m;
+    }
+    m = wave_max(m);
+    if (lane_id() == 0) part[threadIdx.x / kWave] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kWavesPerWG; ++w) m = part[w] > m ? part[w] : m;
+        m = part[0] > m ? part[0] : m;
+        atomicMax(best, m);
+    }
+}
+
+__global__ __launch_bounds__(kWG) void k_invalidate(const unsigned long long *__restrict__ best_i, uint32_t round,
+                                                     const uint64_t *__restrict__ inv_off,
+                                                     const uint32_t *__restrict__ inv, const uint64_t *__restrict__ off,
+                                                     const uint32_t *__restrict__ mem, uint8_t *__restrict__ covered,
+                                                     uint32_t *__restrict__ cnt, uint8_t *__restrict__ chosen,
+                                                     uint32_t *__restrict__ seeds, unsigned long long *__restrict__ gains,
+                                                     uint64_t *__restrict__ big, unsigned long long *__restrict__ nbig) {
+    __shared__ FlatLds lds[kWavesPerWG];
+    const unsigned long long key = *best_i;
+    const uint32_t s = 0xFFFFFFFFu - (uint32_t)key;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        seeds[round] = s;
+        gains[round] = (key >> 32) - 1ull;
+        chosen[s] = 1;
+    }
+    const uint64_t x0 = inv_off[s], x1 = inv_off[s + 1];
+    const uint32_t wv = threadIdx.x / kWave;
+    const uint64_t waves = (uint64_t)gridDim.x * kWavesPerWG;
+    for (uint64_t grp = (uint64_t)blockIdx.x * kWavesPerWG + wv; x0 + grp * kWave < x1; grp += waves) {
+        const uint64_t x = x0 + grp * kWave + lane_id();
+        uint32_t len = 0;
+        uint64_t beg = 0;
+        if (x < x1) {
+            const uint32_t j = inv[x];
+            if (!covered[j]) {
+                covered[j] = 1;
+                beg = off[j];
+                const uint64_t sz = off[j + 1] - beg;
+                if (sz > kBigSet) big[atomicAdd(nbig, 1ull)] = j;
+                else len = (uint32_t)sz;
+            }
+        }
+        wave_flat(lds[wv], len, beg, 0, [&](uint32_t, uint64_t e, uint64_t) { atomicSub(&cnt[mem[e]], 1u); });
+    }
+}
+
+__global__ __launch_bounds__(kWG) void k_invalidate_big(const uint64_t *__restrict__ big,
+                                                         const unsigned long long *__restrict__ nbig,
+                                                         const uint64_t *__restrict__ off,
+                                                         const uint32_t *__restrict__ mem, uint32_t *__restrict__ cnt) {
+    const uint64_t nb = *nbig;
+    for (uint64_t b = blockIdx.x; b < nb; b += gridDim.x) {
+        const uint64_t j = big[b];
+        for (uint64_t e = off[j] + threadIdx.x; e < off[j + 1]; e += blockDim.x) atomicSub(&cnt[mem[e]], 1u);
+    }
+}
+
+__global__ void k_mark(const uint32_t *__restrict__ seeds, uint32_t k, uint8_t *__restrict__ flags) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < k) flags[seeds[i]] = 1;
+}
+
+__global__ __launch_bounds__(kWG) void k_hits_small(const uint64_t *__restrict__ off, const uint32_t *__restrict__ mem,
+                                                     uint64_t theta, const uint8_t *__restrict__ flags,
+                                                     unsigned long long *__restrict__ hits) {
+    __shared__ FlatLds lds[kWavesPerWG];
+    __shared__ uint32_t hit[kWavesPerWG][kWave];
+    const uint32_t wv = threadIdx.x / kWave, lane = lane_id();
+    const uint64_t waves = (uint64_t)gridDim.x * kWavesPerWG;
+    for (uint64_t grp = (uint64_t)blockIdx.x * kWavesPerWG + wv; grp * kWave < theta; grp += waves) {
+        const uint64_t j = grp * kWave + lane;
+        uint32_t len = 0;
+        uint64_t beg = 0;
+        if (j < theta) {
+            beg = off[j];
+            const uint64_t sz = off[j + 1] - beg;
+            len = sz > kBigSet ? 0u : (uint32_t)sz;
+        }
+        hit[wv][lane] = 0;
+        wave_flat(lds[wv], len, beg, 0, [&](uint32_t k, uint64_t e, uint64_t) {
+            if (flags[mem[e]]) hit[wv][k] = 1;
+        });
+        const uint64_t bal = __ballot(hit[wv][lane] != 0);
+        if (lane == 0 && bal) atomicAdd(hits, (unsigned long long)__popcll(bal));
+        wave_sync();
+    }
+}
+
+__global__ __launch_bounds__(kWG) void k_hits_big(const uint64_t *__restrict__ list,
+                                                   const unsigned long long *__restrict__ count,
+                                                   const uint64_t *__restrict__ off, const uint32_t *__restrict__ mem,
+                                                   const uint8_t *__restrict__ flags,
+                                                   unsigned long long *__restrict__ hits) {
+    __shared__ int any;
+    const uint64_t nb = *count;
+    for (uint64_t b = blockIdx.x; b < nb; b += gridDim.x) {
+        const uint64_t j = list[b];
+        if (threadIdx.x == 0) any = 0;
+        __syncthreads();
+        for (uint64_t e = off[j] + threadIdx.x; e < off[j + 1]; e += blockDim.x)
+            if (flags[mem[e]]) any = 1;
+        __syncthreads();
+        if (threadIdx.x == 0 && any) atomicAdd(hits, 1ull);
+        __syncthreads();
+    }
+}
+
+uint32_t grid_for(uint64_t items, uint64_t per_block, uint32_t cap) {
+    uint64_t g = div_up(items, per_block);
+    return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(g, cap));
+}
+
+int read_entries(hyperim_pool p, uint64_t theta, hipStream_t s, uint64_t *entries) {
+    HIM_HIP(hipMemcpyAsync(entries, p->off + theta, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    HIM_HIP(hipStreamSynchronize(s));
+    return HYPERIM_OK;
+}
+
+// big-set list of the pool prefix; counter at ctr
+int big_list(hyperim_pool p, uint64_t theta, uint64_t *list, unsigned long long *ctr, hipStream_t s) {
+    HIM_HIP(hipMemsetAsync(ctr, 0, sizeof(unsigned long long), s));
+    hipLaunchKernelGGL(k_big_list, dim3(grid_for(theta, kWG, 4096)), dim3(kWG), 0, s, p->off, theta, list, ctr);
+    return HYPERIM_OK;
+}
+
+}  // namespace
+
+int greedy_device(hyperim_graph g, hyperim_pool p, uint64_t theta, uint32_t k, hipStream_t s, uint32_t *seeds_host,
+                  uint64_t *gains_host) {
+    GreedyWorkspace &w = g->gr;
+    const uint32_t n = g->n;
+    uint64_t entries = 0;
+    HIM_CHECK(read_entries(p, theta, s, &entries));
+    HIM_CHECK(w.cnt.reserve(sizeof(uint32_t) * n, s));
+    HIM_CHECK(w.inv_off.reserve(sizeof(uint64_t) * ((size_t)n + 1), s));
+    HIM_CHECK(w.cursor.reserve(sizeof(uint32_t) * n, s));
+    HIM_CHECK(w.inv.reserve(sizeof(uint32_t) * std::max<uint64_t>(entries, 1), s));
+    HIM_CHECK(w.covered.reserve(std::max<uint64_t>(theta, 1), s));
+    HIM_CHECK(w.chosen.reserve(n, s));
+    HIM_CHECK(w.best.reserve(sizeof(unsigned long long) * k + 2 * sizeof(unsigned long long) * (k + 1), s));
+    HIM_CHECK(w.out.reserve(sizeof(uint32_t) * k + sizeof(uint64_t) * k, s));
+    HIM_CHECK(w.big.reserve(sizeof(uint64_t) * std::max<uint64_t>(theta, 1), s));
+    HIM_CHECK(w.round_big.reserve(sizeof(uint64_t) * std::max<uint64_t>(theta, 1), s));
+    unsigned long long *best = w.best.as<unsigned long long>();
+    unsigned long long *nbig_round = best + k;          // k counters
+    unsigned long long *nbig_all = best + 2 * k + 1;    // one counter
+    uint32_t *seeds = w.out.as<uint32_t>();
+    unsigned long long *gains = reinterpret_cast<unsigned long long *>(w.out.as<char>() + sizeof(uint32_t) * k);
+    HIM_HIP(hipMemsetAsync(w.cnt.ptr, 0, sizeof(uint32_t) * n, s));
+    HIM_HIP(hipMemsetAsync(w.cursor.ptr, 0, sizeof(uint32_t) * n, s));
+    HIM_HIP(hipMemsetAsync(w.covered.ptr, 0, std::max<uint64_t>(theta, 1), s));
+    HIM_HIP(hipMemsetAsync(w.chosen.ptr, 0, n, s));
+    HIM_HIP(hipMemsetAsync(best, 0, sizeof(unsigned long long) * (3 * (size_t)k + 2), s));
+
+    if (entries)
+        hipLaunchKernelGGL(k_hist, dim3(grid_for(entries, kWG, 8192)), dim3(kWG), 0, s, p->mem, entries,
+                           w.cnt.as<uint32_t>());
+    HIM_CHECK(scan_u32_to_u64(w.cnt.as<uint32_t>(), w.inv_off.as<uint64_t>(), n, 0, w.scan_tmp, s));
+    HIM_CHECK(big_list(p, theta, w.big.as<uint64_t>(), nbig_all, s));
+    if (theta) {
+        hipLaunchKernelGGL(k_inv_small, dim3(grid_for(theta, kWG, 8192)), dim3(kWG), 0, s, p->off, p->mem, theta,
+                           w.inv_off.as<uint64_t>(), w.cursor.as<uint32_t>(), w.inv.as<uint32_t>());
+        hipLaunchKernelGGL(k_inv_big, dim3(1024), dim3(kWG), 0, s, p->off, p->mem, w.big.as<uint64_t>(), nbig_all,
+                           w.inv_off.as<uint64_t>(), w.cursor.as<uint32_t>(), w.inv.as<uint32_t>());
+    }
+    const uint32_t argmax_grid = grid_for(n, kWG, 1024);
+    const uint32_t inval_grid = grid_for(theta, kWG, 1024);
+    for (uint32_t i = 0; i < k; ++i) {
+        hipLaunchKernelGGL(k_argmax, dim3(argmax_grid), dim3(kWG), 0, s, w.cnt.as<uint32_t>(), w.chosen.as<uint8_t>(),
+                           n, best + i);
+        hipLaunchKernelGGL(k_invalidate, dim3(inval_grid), dim3(kWG), 0, s, best + i, i, w.inv_off.as<uint64_t>(),
+                           w.inv.as<uint32_t>(), p->off, p->mem, w.covered.as<uint8_t>(), w.cnt.as<uint32_t>(),
+                           w.chosen.as<uint8_t>(), seeds, gains, w.round_big.as<uint64_t>(), nbig_round + i);
+        hipLaunchKernelGGL(k_invalidate_big, dim3(256), dim3(kWG), 0, s, w.round_big.as<uint64_t>(), nbig_round + i,
+                           p->off, p->mem, w.cnt.as<uint32_t>());
+    }
+    HIM_HIP(hipGetLastError());
+    if (seeds_host) HIM_HIP(hipMemcpyAsync(seeds_host, seeds, sizeof(uint32_t) * k, hipMemcpyDeviceToHost, s));
+    if (gains_host) HIM_HIP(hipMemcpyAsync(gains_host, gains, sizeof(uint64_t) * k, hipMemcpyDeviceToHost, s));
+    HIM_HIP(hipStreamSynchronize(s));
+    return HYPERIM_OK;
+}
+
+int coverage_device(hyperim_graph g, hyperim_pool p, uint64_t theta, const uint32_t *seeds_dev, uint32_t k,
+                    hipStream_t s, uint64_t *covered_host) {
+    GreedyWorkspace &w = g->gr;
+    const uint32_t n = g->n;
+    HIM_CHECK(w.flags.reserve(n, s));
+    HIM_CHECK(w.big.reserve(sizeof(uint64_t) * std::max<uint64_t>(theta, 1), s));
+    HIM_CHECK(w.counters.reserve(4 * sizeof(unsigned long long), s));
+    unsigned long long *ctr = w.counters.as<unsigned long long>();
+    HIM_HIP(hipMemsetAsync(w.flags.ptr, 0, n, s));
+    HIM_HIP(hipMemsetAsync(ctr, 0, 4 * sizeof(unsigned long long), s));
+    hipLaunchKernelGGL(k_mark, dim3(grid_for(k, kWG, 65535)), dim3(kWG), 0, s, seeds_dev, k, w.flags.as<uint8_t>());
+    HIM_CHECK(big_list(p, theta, w.big.as<uint64_t>(), ctr + 1, s));
+    if (theta) {
+        hipLaunchKernelGGL(k_hits_small, dim3(grid_for(theta, kWG, 8192)), dim3(kWG), 0, s, p->off, p->mem, theta,
+                           w.flags.as<uint8_t>(), ctr);
+        hipLaunchKernelGGL(k_hits_big, dim3(1024), dim3(kWG), 0, s, w.big.as<uint64_t>(), ctr + 1, p->off, p->mem,
+                           w.flags.as<uint8_t>(), ctr);
+    }
+    HIM_HIP(hipGetLastError());
+    unsigned long long h = 0;
+    HIM_HIP(hipMemcpyAsync(&h, ctr, sizeof(h), hipMemcpyDeviceToHost, s));
+    HIM_HIP(hipStreamSynchronize(s));
+    *covered_host = h;
+    return HYPERIM_OK;
+}
+
+}  // namespace hyperim

@@ -1,0 +1,312 @@
+// Sample-set division (Section 3.1.1) on the device.  For every vertex v the
+// co-membership weight w(v,u) (hyperedges shared with u) is counted in a
+// global open-addressing table keyed by (v,u); the layers of A(v) are the
+// distinct w values, layer 1 the largest.  Per vertex this yields l_v (number
+// of layers), deg(v) = |A(v)| and top(v) = n(L_1).  Strata are log2 buckets
+// of l_v, and P lists the vertices by (stratum, id) for stratified roots.
+// Vertices are processed in batches whose pair count fits the table budget,
+// so memory stays bounded for graphs with billions of co-member pairs.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "dev_common.h"
+#include "internal.h"
+
+namespace hyperim {
+namespace {
+
+constexpr int kBlock = 256;
+constexpr uint64_t kEmpty = ~0ull;
+constexpr uint64_t kPairBudget = 1ull << 27;   // co-member pairs per batch
+
+__device__ __forceinline__ uint64_t mix64(uint64_t x) {
+    x ^= x >> 30;
+    x *= 0xBF58476D1CE4E5B9ull;
+    x ^= x >> 27;
+    x *= 0x94D049BB133111EBull;
+    x ^= x >> 31;
+    return x;
+}
+
+// Count one occurrence of `key`.
+__device__ __forceinline__ void table_count(unsigned long long *keys, uint32_t *vals, uint64_t mask,
+                                            uint64_t key) {
+    uint64_t h = mix64(key) & mask;
+    for (;;) {
+        unsigned long long k = keys[h];
+        if (k == key) {
+            atomicAdd(&vals[h], 1u);
+            return;
+        }
+        if (k == kEmpty) {
+            unsigned long long prev = atomicCAS(&keys[h], kEmpty, (unsigned long long)key);
+            if (prev == kEmpty || prev == key) {
+                atomicAdd(&vals[h], 1u);
+                return;
+            }
+        }
+        h = (h + 1) & mask;
+    }
+}
+
+// Insert `key` into a set; true when it was not there before.
+__device__ __forceinline__ bool table_insert(unsigned long long *keys, uint64_t mask, uint64_t key) {
+    uint64_t h = mix64(key) & mask;
+    for (;;) {
+        unsigned long long k = keys[h];
+        if (k == key) return false;
+        if (k == kEmpty) {
+            unsigned long long prev = atomicCAS(&keys[h], kEmpty, (unsigned long long)key);
+            if (prev == kEmpty) return true;
+            if (prev == key) return false;
+        }
+        h = (h + 1) & mask;
+    }
+}
+
+// Every co-member occurrence (v, he, u != v) of the batch's vertices.
+__global__ void k_pairs(const uint32_t *__restrict__ he_off, const uint32_t *__restrict__ he_mem,
+                        const uint32_t *__restrict__ v_off, const uint32_t *__restrict__ v_he, uint32_t v0,
+                        uint32_t v1, unsigned long long *keys, uint32_t *vals, uint64_t mask) {
+    const uint32_t e_begin = v_off[v0], e_end = v_off[v1];
+    for (uint64_t e = (uint64_t)e_begin + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < e_end;
+         e += (uint64_t)gridDim.x * blockDim.x) {
+        uint32_t lo = v0, hi = v1;  // v_off[lo] <= e < v_off[hi]
+        while (hi - lo > 1) {
+            uint32_t mid = lo + (hi - lo) / 2;
+            if (v_off[mid] <= (uint32_t)e) lo = mid; else hi = mid;
+        }
+        const uint32_t v = lo, he = v_he[e];
+        for (uint32_t i = he_off[he]; i < he_off[he + 1]; ++i) {
+            uint32_t u = he_mem[i];
+            if (u != v) table_count(keys, vals, mask, ((uint64_t)v << 32) | u);
+        }
+    }
+}
+
+__global__ void k_layers(const unsigned long long *__restrict__ keys, const uint32_t *__restrict__ vals,
+                         uint64_t cap, unsigned long long *keys2, uint64_t mask2, uint32_t *__restrict__ deg,
+                         uint32_t *__restrict__ wmax, uint32_t *__restrict__ l) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cap; i += (uint64_t)gridDim.x * blockDim.x) {
+        unsigned long long k = keys[i];
+        if (k == kEmpty) continue;
+        const uint32_t v = (uint32_t)(k >> 32), w = vals[i];
+        atomicAdd(&deg[v], 1u);
+        atomicMax(&wmax[v], w);
+        if (table_insert(keys2, mask2, ((uint64_t)v << 32) | w)) atomicAdd(&l[v], 1u);
+    }
+}
+
+__global__ void k_top(const unsigned long long *__restrict__ keys, const uint32_t *__restrict__ vals, uint64_t cap,
+                      const uint32_t *__restrict__ wmax, uint32_t *__restrict__ top) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cap; i += (uint64_t)gridDim.x * blockDim.x) {
+        unsigned long long k = keys[i];
+        if (k == kEmpty) continue;
+        const uint32_t v = (uint32_t)(k >> 32);
+        if (vals[i] == wmax[v]) atomicAdd(&top[v], 1u);
+    }
+}
+
+// Stratum of each vertex, per-tile stratum counts (stratum-major layout),
+// per-tile integer sums and the largest l_v.
+__global__ __launch_bounds__(kBlock) void k_strata(uint32_t n, const uint32_t *__restrict__ l,
+                                                    const uint32_t *__restrict__ deg, const uint32_t *__restrict__ top,
+                                                    uint8_t *__restrict__ stratum, uint32_t *__restrict__ counts,
+                                                    uint32_t tiles, unsigned long long *__restrict__ isums,
+                                                    uint32_t *__restrict__ lmax) {
+    __shared__ uint32_t cnt[kNStrata];
+    __shared__ unsigned long long ps[3][kBlock / kWave];
+    if (threadIdx.x < kNStrata) cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const uint32_t v = blockIdx.x * kBlock + threadIdx.x;
+    uint64_t a = 0, b = 0, c = 0;
+    if (v < n) {
+        const uint32_t lv = l[v];
+        uint32_t s = lv ? 32u - __clz(lv) : 0u;   // 1 + floor(log2 l_v)
+        s = s < kNStrata - 1 ? s : kNStrata - 1;
+        stratum[v] = (uint8_t)s;
+        atomicAdd(&cnt[s], 1u);
+        atomicMax(lmax, lv);
+        a = top[v];
+        b = deg[v];
+        c = lv;
+    }
+    a = wave_sum(a);
+    b = wave_sum(b);
+    c = wave_sum(c);
+    const uint32_t lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+    if (lane == 0) {
+        ps[0][wv] = a;
+        ps[1][wv] = b;
+        ps[2][wv] = c;
+    }
+    __syncthreads();
+    if (threadIdx.x < kNStrata) counts[(uint64_t)threadIdx.x * tiles + blockIdx.x] = cnt[threadIdx.x];
+    if (threadIdx.x == 0) {
+        unsigned long long s0 = 0, s1 = 0, s2 = 0;
+        for (int w = 0; w < kBlock / kWave; ++w) {
+            s0 += ps[0][w];
+            s1 += ps[1][w];
+            s2 += ps[2][w];
+        }
+        isums[3 * (uint64_t)blockIdx.x + 0] = s0;
+        isums[3 * (uint64_t)blockIdx.x + 1] = s1;
+        isums[3 * (uint64_t)blockIdx.x + 2] = s2;
+    }
+}
+
+// Histogram of the layer counts (Theorem 2's theta(l*) is a sum over it).
+__global__ void k_lhist(uint32_t n, const uint32_t *__restrict__ l, unsigned long long *__restrict__ hist) {
+    const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < n) atomicAdd(&hist[l[v]], 1ull);
+}
+
+// Stable placement of each vertex at its (stratum, id) rank.
+__global__ __launch_bounds__(kBlock) void k_place(uint32_t n, const uint8_t *__restrict__ stratum,
+                                                   const uint64_t *__restrict__ base, uint32_t tiles,
+                                                   uint32_t *__restrict__ P) {
+    __shared__ uint32_t wcount[kBlock / kWave][kNStrata];
+    const uint32_t v = blockIdx.x * kBlock + threadIdx.x;
+    const uint32_t lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+    const uint32_t s = v < n ? stratum[v] : kNStrata;   // out-of-range lanes match nothing
+    uint32_t rank = 0;
+    for (uint32_t h = 0; h < kNStrata; ++h) {
+        uint64_t mask = __ballot(s == h);
+        if (lane == 0) wcount[wv][h] = (uint32_t)__popcll(mask);
+        if (s == h) rank = lane_rank(mask);
+    }
+    __syncthreads();
+    if (v < n) {
+        uint64_t pos = base[(uint64_t)s * tiles + blockIdx.x] + rank;
+        for (uint32_t w = 0; w < wv; ++w) pos += wcount[w][s];
+        P[pos] = v;
+    }
+}
+
+uint64_t next_pow2(uint64_t x) {
+    uint64_t p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+uint32_t grid_for(uint64_t items) {
+    uint64_t g = div_up(items, kBlock);
+    return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(g, 65535ull * 16));
+}
+
+}  // namespace
+
+int stratify_device(hyperim_graph g, hipStream_t s) {
+    const uint32_t n = g->n;
+    const size_t nn = std::max<uint32_t>(n, 1);
+    HIM_CHECK(g->l.reserve(sizeof(uint32_t) * nn, s));
+    HIM_CHECK(g->deg.reserve(sizeof(uint32_t) * nn, s));
+    HIM_CHECK(g->top.reserve(sizeof(uint32_t) * nn, s));
+    HIM_CHECK(g->stratum.reserve(nn, s));
+    HIM_CHECK(g->P.reserve(sizeof(uint32_t) * nn, s));
+    DevBuf wmax_b, pc_b, tmp_b;
+    HIM_CHECK(wmax_b.reserve(sizeof(uint32_t) * nn, s));
+    for (DevBuf *b : {&g->l, &g->deg, &g->top, &wmax_b}) HIM_HIP(hipMemsetAsync(b->ptr, 0, sizeof(uint32_t) * nn, s));
+
+    // pairs of vertex v = c(v); prefix sums pick the batches
+    HIM_CHECK(pc_b.reserve(sizeof(uint64_t) * ((size_t)n + 1), s));
+    HIM_CHECK(scan_u64(g->c.as<uint64_t>(), pc_b.as<uint64_t>(), n, 0, tmp_b, s));
+    std::vector<uint64_t> pc((size_t)n + 1);
+    HIM_HIP(hipMemcpyAsync(pc.data(), pc_b.ptr, sizeof(uint64_t) * ((size_t)n + 1), hipMemcpyDeviceToHost, s));
+    HIM_HIP(hipStreamSynchronize(s));
+
+    std::vector<std::pair<uint32_t, uint32_t>> batches;
+    uint64_t max_pairs = 0;
+    for (uint32_t v0 = 0; v0 < n;) {
+        // largest v1 with pc[v1] - pc[v0] <= budget (at least one vertex)
+        uint64_t limit = pc[v0] + kPairBudget;
+        uint32_t v1 = (uint32_t)(std::upper_bound(pc.begin() + v0 + 1, pc.end(), limit) - pc.begin()) - 1;
+        if (v1 <= v0) v1 = v0 + 1;
+        batches.push_back({v0, v1});
+        max_pairs = std::max(max_pairs, pc[v1] - pc[v0]);
+        v0 = v1;
+    }
+    if (max_pairs) {
+        const uint64_t cap = next_pow2(std::max<uint64_t>(2 * max_pairs, 1024));
+        DevBuf k1, vals, k2;
+        HIM_CHECK(k1.reserve(sizeof(uint64_t) * cap, s));
+        HIM_CHECK(vals.reserve(sizeof(uint32_t) * cap, s));
+        HIM_CHECK(k2.reserve(sizeof(uint64_t) * cap, s));
+        for (auto [v0, v1] : batches) {
+            const uint64_t pairs = pc[v1] - pc[v0];
+            if (!pairs) continue;
+            const uint64_t c = next_pow2(std::max<uint64_t>(2 * pairs, 1024));
+            HIM_HIP(hipMemsetAsync(k1.ptr, 0xFF, sizeof(uint64_t) * c, s));
+            HIM_HIP(hipMemsetAsync(vals.ptr, 0, sizeof(uint32_t) * c, s));
+            HIM_HIP(hipMemsetAsync(k2.ptr, 0xFF, sizeof(uint64_t) * c, s));
+            hipLaunchKernelGGL(k_pairs, dim3(grid_for(std::max<uint64_t>(pairs / 4, 1))), dim3(kBlock), 0, s,
+                               g->he_off.as<uint32_t>(), g->he_mem.as<uint32_t>(), g->v_off.as<uint32_t>(),
+                               g->v_he.as<uint32_t>(), v0, v1, k1.as<unsigned long long>(), vals.as<uint32_t>(),
+                               c - 1);
+            hipLaunchKernelGGL(k_layers, dim3(grid_for(c)), dim3(kBlock), 0, s, k1.as<unsigned long long>(),
+                               vals.as<uint32_t>(), c, k2.as<unsigned long long>(), c - 1, g->deg.as<uint32_t>(),
+                               wmax_b.as<uint32_t>(), g->l.as<uint32_t>());
+            hipLaunchKernelGGL(k_top, dim3(grid_for(c)), dim3(kBlock), 0, s, k1.as<unsigned long long>(),
+                               vals.as<uint32_t>(), c, wmax_b.as<uint32_t>(), g->top.as<uint32_t>());
+        }
+    }
+
+    // strata, counts, statistics
+    const uint32_t tiles = (uint32_t)std::max<uint64_t>(div_up(n, kBlock), 1);
+    DevBuf counts_b, base_b, isum_b, lmax_b, hist_b;
+    HIM_CHECK(counts_b.reserve(sizeof(uint32_t) * kNStrata * tiles, s));
+    HIM_CHECK(base_b.reserve(sizeof(uint64_t) * (kNStrata * (size_t)tiles + 1), s));
+    HIM_CHECK(isum_b.reserve(sizeof(uint64_t) * 3 * tiles, s));
+    HIM_CHECK(lmax_b.reserve(sizeof(uint32_t), s));
+    HIM_HIP(hipMemsetAsync(counts_b.ptr, 0, sizeof(uint32_t) * kNStrata * tiles, s));
+    HIM_HIP(hipMemsetAsync(isum_b.ptr, 0, sizeof(uint64_t) * 3 * tiles, s));
+    HIM_HIP(hipMemsetAsync(lmax_b.ptr, 0, sizeof(uint32_t), s));
+    if (n)
+        hipLaunchKernelGGL(k_strata, dim3(tiles), dim3(kBlock), 0, s, n, g->l.as<uint32_t>(), g->deg.as<uint32_t>(),
+                           g->top.as<uint32_t>(), g->stratum.as<uint8_t>(), counts_b.as<uint32_t>(), tiles,
+                           isum_b.as<unsigned long long>(), lmax_b.as<uint32_t>());
+    uint32_t lmax = 0;
+    HIM_HIP(hipMemcpyAsync(&lmax, lmax_b.ptr, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    HIM_HIP(hipStreamSynchronize(s));
+    HIM_CHECK(hist_b.reserve(sizeof(unsigned long long) * ((size_t)lmax + 1), s));
+    HIM_HIP(hipMemsetAsync(hist_b.ptr, 0, sizeof(unsigned long long) * ((size_t)lmax + 1), s));
+    if (n)
+        hipLaunchKernelGGL(k_lhist, dim3(tiles), dim3(kBlock), 0, s, n, g->l.as<uint32_t>(),
+                           hist_b.as<unsigned long long>());
+    HIM_CHECK(scan_u32_to_u64(counts_b.as<uint32_t>(), base_b.as<uint64_t>(), (uint64_t)kNStrata * tiles, 0, tmp_b,
+                              s));
+    if (n)
+        hipLaunchKernelGGL(k_place, dim3(tiles), dim3(kBlock), 0, s, n, g->stratum.as<uint8_t>(),
+                           base_b.as<uint64_t>(), tiles, g->P.as<uint32_t>());
+    HIM_HIP(hipGetLastError());
+
+    std::vector<uint64_t> base((size_t)kNStrata * tiles + 1);
+    std::vector<uint64_t> isums((size_t)3 * tiles);
+    std::vector<uint64_t> hist((size_t)lmax + 1);
+    HIM_HIP(hipMemcpyAsync(base.data(), base_b.ptr, sizeof(uint64_t) * base.size(), hipMemcpyDeviceToHost, s));
+    HIM_HIP(hipMemcpyAsync(isums.data(), isum_b.ptr, sizeof(uint64_t) * isums.size(), hipMemcpyDeviceToHost, s));
+    HIM_HIP(hipMemcpyAsync(hist.data(), hist_b.ptr, sizeof(uint64_t) * hist.size(), hipMemcpyDeviceToHost, s));
+    HIM_HIP(hipStreamSynchronize(s));
+    hyperim_strata_info &info = g->info;
+    for (uint32_t h = 0; h < kNStrata; ++h) info.B[h] = (uint32_t)base[(size_t)h * tiles];
+    info.B[kNStrata] = n;
+    info.sum_top = info.sum_deg = info.sum_l = 0;
+    for (uint32_t t = 0; t < tiles; ++t) {
+        info.sum_top += isums[3 * (size_t)t + 0];
+        info.sum_deg += isums[3 * (size_t)t + 1];
+        info.sum_l += isums[3 * (size_t)t + 2];
+    }
+    double tl = 0.0;   // sum over v with l_v > 0 of l_v / ln(l_v + 1), grouped by value
+    for (uint32_t lv = 1; lv <= lmax; ++lv)
+        if (hist[lv]) tl += (double)hist[lv] * ((double)lv / std::log((double)lv + 1.0));
+    info.alpha = info.sum_deg ? (double)info.sum_top / (double)info.sum_deg : 0.0;
+    info.beta = n ? (double)info.sum_l / (double)n : 0.0;
+    info.theta_l = n ? tl / (double)n : 0.0;
+    g->stratified = true;
+    return HYPERIM_OK;
+}
+
+}  // namespace hyperim
