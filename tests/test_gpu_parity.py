@@ -43,6 +43,10 @@ def _check_graph(g, o):
         assert np.array_equal(a[k], b[k]), k
 
 
+def hy_n(info):
+    return int(info["B"][-1])
+
+
 def _check_strata(g, o):
     info = g.stratify()
     st = o.stratify()
@@ -52,7 +56,11 @@ def _check_strata(g, o):
     assert np.array_equal(info["B"], st["B"])
     assert info["alpha"] == pytest.approx(st["alpha"], rel=1e-12)
     assert info["beta"] == pytest.approx(st["beta"], rel=1e-12)
-    assert info["theta_l"] == pytest.approx(st["theta_l"], rel=1e-12)
+    # theta(l*) is a sum of n doubles: the oracle adds them in vertex order, the
+    # library groups them by value; recursive summation differs by at most
+    # about n * 2^-52 relative
+    tol = max(1e-14, hy_n(info) * 2.0 ** -52)
+    assert info["theta_l"] == pytest.approx(st["theta_l"], rel=tol)
 
 
 CASES = {
