@@ -114,9 +114,22 @@ def main():
     value = rr_sets_per_step * args.steps / elapsed
     inc_per_s = meas["incidences"] * args.steps / elapsed
     bfs_ms = float(np.mean([r["ms_bfs"] for r in results]))
+    ms_light = float(np.mean([r["ms_light"] for r in results]))
+    ms_heavy = float(np.mean([r["ms_heavy"] for r in results]))
     launches = last["bfs_launches"]
     alg_bytes = meas["alg_bytes"]
+    # the kernels count the bytes of every expansion they perform; together
+    # they must equal the total recomputed from the output sets
+    assert meas["bytes_light"] + meas["bytes_heavy"] == alg_bytes, (meas["bytes_light"], meas["bytes_heavy"], alg_bytes)
     achieved = alg_bytes / (bfs_ms * 1e-3) / 1e9 if bfs_ms > 0 else 0.0
+    phases = {
+        "per_set_phase": {"kernel": "k_rr_light", "ms": ms_light, "alg_bytes": meas["bytes_light"],
+                          "GBps": meas["bytes_light"] / (ms_light * 1e-3) / 1e9 if ms_light > 0 else 0.0},
+        "grid_wide_phase": {"kernels": "k_plan + k_expand + k_finish", "ms": ms_heavy,
+                            "alg_bytes": meas["bytes_heavy"], "deferred_sets": meas["deferred"],
+                            "supersteps": meas["supersteps"],
+                            "GBps": meas["bytes_heavy"] / (ms_heavy * 1e-3) / 1e9 if ms_heavy > 0 else 0.0},
+    }
     line = {
         "metric": "RR sets/s",
         "value": value,
@@ -140,8 +153,9 @@ def main():
         "spread": last["spread"],
         "ms_rr": float(np.mean([r["ms_rr"] for r in results])),
         "ms_greedy": float(np.mean([r["ms_greedy"] for r in results])),
+        "rr_phases": phases,
         "roofline": {
-            "kernel": "k_rr_bfs",
+            "kernel": "RR generation (k_rr_light, k_plan, k_expand, k_finish)",
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,

@@ -110,6 +110,12 @@ typedef struct {
                                filled with HYPERIM_FLAG_INCIDENCES            */
     double ms_bfs;          /* device time of the RR-generation kernels alone  */
     uint64_t bfs_launches;  /* number of RR-generation kernel launches         */
+    double ms_light;        /* part of ms_bfs spent in the per-set phase       */
+    double ms_heavy;        /* part of ms_bfs spent in the grid-wide phase     */
+    uint64_t deferred;      /* RR sets handed to the grid-wide phase           */
+    uint64_t supersteps;    /* grid-wide supersteps launched                   */
+    uint64_t bytes_light;   /* algorithmic bytes expanded by the per-set phase */
+    uint64_t bytes_heavy;   /* algorithmic bytes expanded by the grid-wide one */
 } hyperim_result;
 
 /* Build the device-resident hypergraph (Section 2.1: G = (V, HE), V(he)).

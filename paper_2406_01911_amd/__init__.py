@@ -49,7 +49,9 @@ class _Result(C.Structure):
                 ("theta_max", C.c_double), ("entries1", C.c_uint64), ("entries2", C.c_uint64),
                 ("incidences", C.c_uint64), ("ms_rr", C.c_double), ("ms_greedy", C.c_double),
                 ("ms_total", C.c_double), ("alg_bytes", C.c_uint64), ("ms_bfs", C.c_double),
-                ("bfs_launches", C.c_uint64)]
+                ("bfs_launches", C.c_uint64), ("ms_light", C.c_double), ("ms_heavy", C.c_double),
+                ("deferred", C.c_uint64), ("supersteps", C.c_uint64), ("bytes_light", C.c_uint64),
+                ("bytes_heavy", C.c_uint64)]
 
 
 EXPORTS = ["hyperim_build_graph", "hyperim_stratify", "hyperim_graph_read", "hyperim_pool_create",

@@ -53,40 +53,16 @@ void DevBuf::release() {
     bytes = 0;
 }
 
-namespace {
-
-constexpr uint64_t kMaxIds = 1ull << 39;   // RR ids use 39 bits of the coin counter
-
-hipStream_t as_stream(void *s) { return static_cast<hipStream_t>(s); }
-
-void release_graph(hyperim_graph g) {
-    for (DevBuf *b : {&g->he_off, &g->he_mem, &g->v_off, &g->v_he, &g->thr, &g->c, &g->weight, &g->l, &g->deg,
-                      &g->top, &g->stratum, &g->P})
-        b->release();
-    RRWorkspace &r = g->rr;
-    for (DevBuf *b : {&r.lists, &r.bitmaps, &r.counters, &r.stage, &r.stage_off, &r.sizes, &r.roots, &r.scan_tmp,
-                      &r.big_ids})
-        b->release();
-    for (hipEvent_t e : r.events) (void)hipEventDestroy(e);
-    r.events.clear();
-    g->bytesw.release();
-    GreedyWorkspace &w = g->gr;
-    for (DevBuf *b : {&w.cnt, &w.inv_off, &w.cursor, &w.inv, &w.covered, &w.chosen, &w.best, &w.out, &w.big,
-                      &w.round_big, &w.flags, &w.counters, &w.scan_tmp})
-        b->release();
-}
-
-// Pool storage --------------------------------------------------------------------
-size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
-
-// Make room for `ids` more ids and `entries` more members.
-int pool_ensure(hyperim_pool p, uint64_t ids, uint64_t entries, hipStream_t s) {
+// Pool storage: make room for `ids` more ids and `entries` more members
+// (owned storage grows and keeps its contents; a caller buffer cannot grow).
+int pool_reserve(hyperim_pool p, uint64_t ids, uint64_t entries, hipStream_t s) {
     const uint64_t need_ids = p->count + ids;
     const uint64_t need_mem = p->total + entries;
     if (need_ids <= p->id_cap && need_mem <= p->mem_cap) return HYPERIM_OK;
     if (!p->owned) {
         const uint64_t ic = std::max(need_ids, p->id_cap);
-        p->required = align256(8 * (ic + 1)) + align256(4 * ic) + 4 * std::max(need_mem, (uint64_t)1);
+        auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+        p->required = al(8 * (ic + 1)) + al(4 * ic) + 4 * std::max(need_mem, (uint64_t)1);
         set_error_detail("pool buffer too small: " + std::to_string(p->required) + " bytes needed");
         return HYPERIM_ECAPACITY;
     }
@@ -106,6 +82,33 @@ int pool_ensure(hyperim_pool p, uint64_t ids, uint64_t entries, hipStream_t s) {
     p->mem = p->mem_b.as<uint32_t>();
     return HYPERIM_OK;
 }
+
+
+namespace {
+
+constexpr uint64_t kMaxIds = 1ull << 39;   // RR ids use 39 bits of the coin counter
+
+hipStream_t as_stream(void *s) { return static_cast<hipStream_t>(s); }
+
+void release_graph(hyperim_graph g) {
+    for (DevBuf *b : {&g->he_off, &g->he_mem, &g->v_off, &g->v_he, &g->thr, &g->c, &g->weight, &g->l, &g->deg,
+                      &g->top, &g->stratum, &g->P})
+        b->release();
+    RRWorkspace &r = g->rr;
+    for (DevBuf *b : {&r.lists, &r.bitmaps, &r.counters, &r.stage, &r.stage_off, &r.sizes, &r.roots, &r.scan_tmp,
+                      &r.big_ids, &r.def_idx, &r.def_u32, &r.items})
+        b->release();
+    for (hipEvent_t e : r.events) (void)hipEventDestroy(e);
+    r.events.clear();
+    g->bytesw.release();
+    GreedyWorkspace &w = g->gr;
+    for (DevBuf *b : {&w.cnt, &w.inv_off, &w.cursor, &w.inv, &w.covered, &w.chosen, &w.best, &w.out, &w.big,
+                      &w.round_big, &w.flags, &w.counters, &w.scan_tmp})
+        b->release();
+}
+
+// Pool storage --------------------------------------------------------------------
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 int pool_init_owned(hyperim_graph g, hyperim_pool p, hipStream_t s) {
     p->g = g;
@@ -129,21 +132,27 @@ void pool_clear(hyperim_pool p) {
     p->has_key = false;
 }
 
-int generate_into(hyperim_graph g, const RRKey &key, uint64_t id_begin, uint64_t id_end, int form, hyperim_pool p,
-                  uint64_t max_entries, hipStream_t s) {
-    const uint64_t count = id_end - id_begin;
-    if (count == 0) return HYPERIM_OK;
+// Generate the tasks in one go and append each task's sets to its pool.
+int generate_into(hyperim_graph g, const RRKey &key, const std::vector<RRTask> &tasks,
+                  const std::vector<hyperim_pool> &pools, int form, uint64_t max_entries, hipStream_t s) {
+    std::vector<RRTask> live;
+    std::vector<hyperim_pool> dst;
+    for (size_t i = 0; i < tasks.size(); ++i)
+        if (tasks[i].id_end > tasks[i].id_begin) {
+            live.push_back(tasks[i]);
+            dst.push_back(pools[i]);
+        }
+    if (live.empty()) return HYPERIM_OK;
     uint64_t total = 0;
-    HIM_CHECK(rr_generate_stage(g, key, id_begin, id_end, form, s, &total));
-    if (max_entries && p->total + total > max_entries) {
-        set_error_detail("pool would exceed max_entries");
-        return HYPERIM_ECAPACITY;
+    HIM_CHECK(rr_generate_stage(g, key, live, form, s, &total));
+    uint64_t first = 0;
+    for (size_t i = 0; i < live.size(); ++i) {
+        const uint64_t count = live[i].id_end - live[i].id_begin;
+        const bool was_empty = dst[i]->count == 0;
+        HIM_CHECK(rr_compact_into(g, dst[i], first, count, max_entries, s));
+        if (was_empty) dst[i]->id_begin = live[i].id_begin;
+        first += count;
     }
-    HIM_CHECK(pool_ensure(p, count, total, s));   // off[] always holds id_cap + 1 entries
-    HIM_CHECK(rr_compact_into(g, p, count, s));
-    if (p->count == 0) p->id_begin = id_begin;
-    p->count += count;
-    p->total += total;
     return HYPERIM_OK;
 }
 
@@ -363,8 +372,8 @@ int hyperim_generate_rr(hyperim_graph g, uint64_t seed, uint32_t instance, uint3
             return HYPERIM_EINVAL;
         }
     }
-    RRKey key{seed, instance, pool_tag, 8};
-    HIM_CHECK(generate_into(g, key, id_begin, id_end, 0, pool, 0, as_stream(stream)));
+    RRKey key{seed, instance, 8};
+    HIM_CHECK(generate_into(g, key, {RRTask{pool_tag, id_begin, id_end}}, {pool}, 0, 0, as_stream(stream)));
     pool->has_key = true;
     pool->seed = seed;
     pool->instance = instance;
@@ -463,8 +472,9 @@ int hyperim_select_seeds(hyperim_graph g, uint32_t k, double eps, double ell, ui
     HIM_HIP(hipEventCreate(&ev.a));
     HIM_HIP(hipEventCreate(&ev.b));
     hyperim_result res{};
-    g->rr.ms_bfs = 0.0;
-    g->rr.launches = 0;
+    g->rr.ms_bfs = g->rr.ms_light = g->rr.ms_heavy = 0.0;
+    g->rr.launches = g->rr.supersteps = g->rr.deferred = 0;
+    g->rr.bytes_light = g->rr.bytes_heavy = 0;
     res.i_max = o.theta_fixed ? 1 : sc.i_max;
     res.theta_max = sc.theta_max;
     uint64_t have = 0;
@@ -478,10 +488,10 @@ int hyperim_select_seeds(hyperim_graph g, uint32_t k, double eps, double ell, ui
             }
             float ms = 0.f;
             HIM_HIP(hipEventRecord(ev.a, s));
-            for (uint32_t pool = 0; pool < 2; ++pool) {
-                RRKey key{seed, instance, pool, o.qlog};
-                HIM_CHECK(generate_into(g, key, have, theta, (int)o.form, pool ? &r2 : &r1, o.max_entries, s));
-            }
+            // both pools of the round share one launch group
+            RRKey key{seed, instance, o.qlog};
+            HIM_CHECK(generate_into(g, key, {RRTask{0, have, theta}, RRTask{1, have, theta}}, {&r1, &r2},
+                                    (int)o.form, o.max_entries, s));
             HIM_HIP(hipEventRecord(ev.b, s));
             HIM_HIP(hipEventSynchronize(ev.b));
             HIM_HIP(hipEventElapsedTime(&ms, ev.a, ev.b));
@@ -531,6 +541,12 @@ int hyperim_select_seeds(hyperim_graph g, uint32_t k, double eps, double ell, ui
     res.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     res.ms_bfs = g->rr.ms_bfs;
     res.bfs_launches = g->rr.launches;
+    res.ms_light = g->rr.ms_light;
+    res.ms_heavy = g->rr.ms_heavy;
+    res.deferred = g->rr.deferred;
+    res.supersteps = g->rr.supersteps;
+    res.bytes_light = g->rr.bytes_light;
+    res.bytes_heavy = g->rr.bytes_heavy;
     if (out) *out = res;
     return HYPERIM_OK;
 }

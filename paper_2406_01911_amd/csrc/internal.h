@@ -42,10 +42,18 @@ struct DevBuf {
 
 // Workspace of RR generation, owned by a graph.
 struct RRWorkspace {
-    uint32_t waves = 0;          // persistent wave slots
-    uint32_t grid = 0;           // workgroups of the persistent launch
-    DevBuf lists;                // waves * n     : per-wave member list / queue
-    DevBuf bitmaps;              // waves * words : per-wave visited bitmap
+    uint32_t waves = 0;          // phase A wavefronts (each starts with its own slot)
+    uint32_t grid = 0;           // workgroups of the phase A launch
+    uint32_t slots = 0;          // slots: phase A waves + spare slots for deferred sets
+    uint32_t grid_b = 0;         // workgroups of a phase B expansion launch
+    DevBuf lists;                // slots * n     : member list / BFS queue per slot
+    DevBuf bitmaps;              // slots * words : visited bitmap per slot
+    DevBuf def_idx;              // deferred sets: per-id index (uint64)
+    DevBuf def_u32;              // deferred sets: root, slot, head, size (4 uint32 arrays)
+    DevBuf items;                // phase B work items (uint4)
+    double ms_light = 0.0, ms_heavy = 0.0;   // device time of phase A / phase B kernels
+    uint64_t supersteps = 0, deferred = 0;
+    uint64_t bytes_light = 0, bytes_heavy = 0;  // algorithmic bytes expanded in each phase
     DevBuf counters;             // work counter, stage bump, misc
     DevBuf stage;                // unsorted->sorted members before compaction
     DevBuf stage_off;            // per id (uint64)
@@ -126,15 +134,24 @@ int scan_u64(const uint64_t *in, uint64_t *out, uint64_t count, uint64_t init, D
 // ---- launchers (rr.hip) -------------------------------------------------------
 struct RRKey {
     uint64_t seed;
-    uint32_t instance, pool, qlog;
+    uint32_t instance, qlog;
 };
-// Generate RR ids [id_begin, id_end) into the workspace stage; returns the
-// number of stored members in *total.  form 0 = one persistent launch,
-// form 1 = one launch per (ladder block, stratum).
-int rr_generate_stage(hyperim_graph g, const RRKey &key, uint64_t id_begin, uint64_t id_end, int form,
-                      hipStream_t s, uint64_t *total);
-// Compact the stage into pool storage (pool capacity already ensured).
-int rr_compact_into(hyperim_graph g, hyperim_pool p, uint64_t count, hipStream_t s);
+// RR ids [id_begin, id_end) of pool tag `pool`.
+struct RRTask {
+    uint32_t pool;
+    uint64_t id_begin, id_end;
+};
+// Generate every task's RR sets into the workspace stage (per-id outputs laid
+// out task after task); *total = members staged.  form 0 = all tasks in one
+// launch group, form 1 = one launch group per (task, ladder block, stratum).
+int rr_generate_stage(hyperim_graph g, const RRKey &key, const std::vector<RRTask> &tasks, int form, hipStream_t s,
+                      uint64_t *total);
+// Append the staged sets with per-id indices [first, first + count) to pool p
+// (growing its storage; HYPERIM_ECAPACITY beyond max_entries or a caller buffer).
+int rr_compact_into(hyperim_graph g, hyperim_pool p, uint64_t first, uint64_t count, uint64_t max_entries,
+                    hipStream_t s);
+// Make room in pool p for `ids` more ids and `entries` more members.
+int pool_reserve(hyperim_pool p, uint64_t ids, uint64_t entries, hipStream_t s);
 // Sums of weight[] (incidences) and bytesw[] (algorithmic bytes) over the
 // members of the pool's first theta sets.
 int rr_incidences(hyperim_graph g, hyperim_pool p, uint64_t theta, hipStream_t s, uint64_t *incidences,

@@ -1,24 +1,41 @@
 // RR-set generation on gfx950 (Algorithm 3's skeleton with one keyed coin per
 // channel), stratified roots, and compaction into the RR-set CSR.
 //
-// Execution: a persistent launch whose wavefronts steal RR ids from a global
-// counter.  One wavefront owns one RR set at a time:
-//   - the set's member list doubles as the BFS queue (global, per wave slot);
-//   - visited marks are a bitmap, in LDS when |V| is small, else global;
-//   - each frontier batch (up to 64 queued vertices) is expanded cooperatively
-//     in three load-balanced levels -- vertices -> incidences (v, he) ->
-//     quads of 4 member positions -- so lanes stay busy whatever the degree
-//     and hyperedge-size skew, and member ids are read contiguously;
-//   - one Philox4x32-10 call yields the 4 coins of a quad; a live channel
-//     from an unvisited member sets its bit (atomic OR) and the winner
-//     appends it to the queue with a ballot-ranked store;
-//   - the finished set is written ascending to a staging area, sorted in LDS
-//     (small sets) or read back from the bitmap in id order (large sets).
+// RR sets are very uneven: most cost a few hundred incidences, while a set
+// that reaches a hub vertex (a member of ~1e5 hyperedges) or grows into a
+// giant component costs millions.  Generation therefore runs in two phases.
+//
+// Phase A (k_rr_light, persistent): wavefronts steal RR ids from a global
+// counter; one wavefront owns one set at a time in a "slot" (member list that
+// doubles as the BFS queue, plus a visited bitmap -- in LDS when |V| is
+// small).  Each frontier batch (up to 64 queued vertices) is expanded in
+// three load-balanced levels -- vertices -> incidences (v, he) -> quads of 4
+// member positions -- so lanes stay busy under degree and size skew and
+// member ids are read contiguously; one Philox4x32-10 call gives the 4 coins
+// of a quad; a live channel from an unvisited member sets its bit (atomic OR)
+// and the winner appends it with a ballot-ranked store.  A set whose next
+// batch holds a heavy vertex, or that has used up its incidence budget, is
+// handed over intact (slot, queue head, size) to phase B and the wave takes a
+// fresh slot.  Finished sets are written ascending to a staging area.
+//
+// Phase B (bulk-synchronous over the deferred sets): k_plan cuts every
+// deferred set's current frontier into work items of bounded cost --
+// segments of consecutive queue entries holding at most a few hundred
+// incidences, or one heavy vertex's incidences in chunks -- and k_expand
+// spreads the items over every wavefront of the GPU, so a single giant set
+// or hub expansion uses the whole chip.  Supersteps repeat until no frontier
+// is left; k_finish sorts and stages each set.  No wave ever waits for
+// another: items only refer to finished supersteps.  Several (pool, id
+// range) tasks -- e.g. both pools of a doubling round -- share one launch
+// group, so they share supersteps.
+//
 // Compaction turns the per-id sizes into CSR offsets (device scan) and moves
 // the staged members into the pool.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
 #include <vector>
 
 #include "dev_common.h"
@@ -29,10 +46,24 @@ namespace {
 
 constexpr int kWG = 256;
 constexpr int kWavesPerWG = kWG / kWave;
-constexpr uint32_t kSortMax = 1024;          // sets up to this size are sorted in LDS
+constexpr uint32_t kSortMax = 1024;          // phase A: sets up to this size are sorted in LDS
+constexpr uint32_t kSortMaxWG = 4096;        // phase B: one workgroup sorts up to this size in LDS
 constexpr uint32_t kLdsBitmapWords = 1024;   // visited bitmap in LDS when |V| <= 32768
 constexpr uint32_t kBigSet = 4096;           // compaction: one workgroup per larger set
-constexpr uint64_t kSlotBudget = 16ull << 30; // bytes of per-wave lists + bitmaps
+constexpr uint32_t kHeavy = 1024;            // phase A defers a set on a vertex with more incidences
+constexpr uint64_t kBudget = 16384;          // phase A defers a set after this many incidences
+constexpr uint32_t kChunk = 256;             // phase B: incidences per heavy-vertex item
+constexpr uint32_t kSeg = 512;               // phase B: light incidences per queue segment item
+constexpr uint32_t kMaxTasks = 4;            // (pool, id range) tasks per launch
+constexpr uint32_t kItemCap = (1u << 22) + 64;   // phase B: work items per superstep (one vertex always fits)
+constexpr uint32_t kPrefilterMin = 4096;     // phase B: test visited marks before coins from this size
+constexpr int kStepsPerSync = 8;             // phase B supersteps launched between host checks
+constexpr uint64_t kSlotBudget = 24ull << 30; // bytes of slot lists + bitmaps
+
+// Counters (uint64 each) in the workspace counter block.
+// kItems and kItems + 1 alternate between supersteps: superstep s plans into
+// counter s & 1 while its k_expand clears the other one for superstep s + 1.
+enum Ctr { kWork = 0, kBump, kBigCount, kFreeNext, kDefCount, kItems, kItemsOther, kBytesA, kBytesB, kNumCtr };
 
 struct RRArgs {
     const uint32_t *__restrict__ he_off;
@@ -41,33 +72,50 @@ struct RRArgs {
     const uint32_t *__restrict__ v_he;
     const uint32_t *__restrict__ thr;
     const uint32_t *__restrict__ P;
-    uint32_t n, key0, key1, pool, qlog, bm_words, prefilter;
-    uint64_t id_begin, count;        // ids [id_begin, id_begin + count)
-    uint64_t out_base;               // index of id_begin in the per-id arrays
-    unsigned long long *work;        // next relative id to take
-    unsigned long long *stage_bump;  // staged members so far
-    unsigned long long *big_count;   // sets larger than kBigSet
-    uint32_t *lists;                 // per wave slot: n entries
-    uint32_t *bitmaps;               // per wave slot: bm_words (global mode)
+    uint32_t n, key0, key1, qlog, bm_words;
+    // a launch covers up to kMaxTasks (pool, id range) tasks back to back:
+    // launch index idx belongs to task t when t_end[t-1] <= idx < t_end[t]
+    uint32_t ntasks;
+    uint64_t count;                  // launch indices [0, count)
+    uint64_t t_end[kMaxTasks];
+    uint64_t t_id[kMaxTasks];        // RR id of each task's first index
+    uint32_t t_pool[kMaxTasks];      // pool tag of each task
+    uint64_t out_base;               // per-id array index of launch index 0
+    unsigned long long *ctr;         // Ctr block
+    uint32_t *lists;                 // per slot: n entries
+    uint32_t *bitmaps;               // per slot: bm_words (global mode)
+    uint32_t slot_total;             // slots available (waves own the first ones)
     uint32_t *stage;
     uint64_t stage_cap;
     uint64_t *stage_off;             // per id
     uint32_t *sizes;                 // per id
     uint32_t *roots;                 // per id
-    uint64_t *big_ids;               // per big set: relative id
+    uint64_t *big_ids;               // per big set: per-id index
+    // deferred sets (phase B)
+    uint64_t *def_idx;
+    uint32_t *def_root, *def_slot, *def_head, *def_size;
+    uint4 *items;
 };
 
 struct WaveLds {
     uint32_t fr_scan[kWave], fr_v[kWave], fr_e0[kWave];
     uint32_t in_scan[kWave], in_he[kWave], in_hb[kWave], in_hs[kWave], in_v[kWave], in_thr[kWave];
-    uint32_t sort[kSortMax];
 };
+
+// RR id and pool tag of launch index idx.
+__device__ __forceinline__ void resolve(const RRArgs &a, uint64_t idx, uint64_t *j, uint32_t *pool) {
+    uint32_t t = 0;
+    while (t + 1 < a.ntasks && idx >= a.t_end[t]) ++t;
+    const uint64_t start = t ? a.t_end[t - 1] : 0ull;
+    *j = a.t_id[t] + (idx - start);
+    *pool = a.t_pool[t];
+}
 
 // Stratified root of RR id j: block b of the ladder (Q = 2^qlog ids in block
 // 0, Q 2^(b-1) in block b >= 1, so block sizes are powers of two), offset
 // o_b = floor(x n / 2^64) from the block's Philox draw, root =
 // P[floor((t n + o_b) / T_b)] computed in 128-bit arithmetic.
-__device__ __forceinline__ uint32_t rr_root(const RRArgs &a, uint64_t j, uint2 key) {
+__device__ __forceinline__ uint32_t rr_root(const RRArgs &a, uint64_t j, uint32_t pool, uint2 key) {
     const uint64_t Q = 1ull << a.qlog;
     uint32_t b, s;
     uint64_t J;
@@ -81,7 +129,7 @@ __device__ __forceinline__ uint32_t rr_root(const RRArgs &a, uint64_t j, uint2 k
         J = 1ull << hb;
         s = hb;
     }
-    const uint4 r = philox4x32_10(root_counter(b, a.pool), key);
+    const uint4 r = philox4x32_10(root_counter(b, pool), key);
     const uint64_t x = (uint64_t)r.x | ((uint64_t)r.y << 32);
     const uint64_t o = __umul64hi(x, (uint64_t)a.n);
     const uint64_t t = j - J;
@@ -99,154 +147,241 @@ __device__ __forceinline__ uint32_t bm_load(uint32_t *bm, uint32_t w) {
     else return __hip_atomic_load(bm + w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Appends a wave's newly reached members to a list whose size lives in a
+// register (phase A: one wave owns the set).
+struct LocalAppend {
+    uint32_t *list;
+    uint32_t size, n;
+    __device__ __forceinline__ void push(bool fresh, uint32_t u) {
+        const uint64_t bal = __ballot(fresh);
+        const uint32_t at = size + lane_rank(bal);
+        if (fresh && at < n) list[at] = u;   // at < n always holds: one bit per vertex
+        size = min(size + (uint32_t)__popcll(bal), n);
+    }
+};
+
+// Same with the size in global memory (phase B: many waves grow one set).
+struct SharedAppend {
+    uint32_t *list;
+    uint32_t *size;
+    uint32_t n;
+    __device__ __forceinline__ void push(bool fresh, uint32_t u) {
+        const uint64_t bal = __ballot(fresh);
+        if (bal == 0) return;
+        const uint32_t first = (uint32_t)__ffsll((unsigned long long)bal) - 1u;
+        uint32_t base = 0;
+        if (lane_id() == first) base = atomicAdd(size, (uint32_t)__popcll(bal));
+        base = wave_bcast(base, (int)first);
+        const uint32_t at = base + lane_rank(bal);
+        if (fresh && at < n) list[at] = u;
+    }
+};
+
+// Levels 2 and 3 of a frontier expansion.  Each lane brings one vertex v with
+// the incidence range [e0, e0 + d) of v_he to expand (d = 0 for none); every
+// channel (he, u -> v) of those incidences is tested with its coin and newly
+// reached members go to `app`.  Returns the algorithmic bytes of the
+// incidences read (12 per incidence plus 4 per member position), wave-uniform.
+template <bool kLds, class App>
+__device__ __forceinline__ uint64_t expand(const RRArgs &a, WaveLds &L, uint64_t j, uint32_t pool, uint2 key,
+                                           uint32_t *bm, bool prefilter, uint32_t v, uint32_t e0, uint32_t d,
+                                           App &app) {
+    const uint32_t lane = lane_id();
+    const uint32_t dscan = wave_incl_scan(d);
+    const uint32_t D = wave_bcast(dscan, kWave - 1);
+    wave_sync();
+    L.fr_scan[lane] = dscan;
+    L.fr_v[lane] = v;
+    L.fr_e0[lane] = e0;
+    wave_sync();
+    uint64_t bytes = 0;
+    for (uint32_t base = 0; base < D; base += kWave) {
+        // level 2: one incidence (v, he) per lane
+        const uint32_t g = base + lane;
+        uint32_t he = 0, hb = 0, hs = 0, vv = 0, th = 0, nq = 0;
+        if (g < D) {
+            const uint32_t k = search64(L.fr_scan, g);
+            const uint32_t start = k ? L.fr_scan[k - 1] : 0u;
+            vv = L.fr_v[k];
+            he = a.v_he[L.fr_e0[k] + (g - start)];
+            hb = a.he_off[he];
+            hs = a.he_off[he + 1] - hb;
+            th = a.thr[vv];
+            nq = th ? (hs + 3u) >> 2 : 0u;   // threshold 0: no channel into vv is live
+            bytes += 12u + 4u * hs;
+        }
+        const uint32_t qscan = wave_incl_scan(nq);
+        const uint32_t Qn = wave_bcast(qscan, kWave - 1);
+        wave_sync();
+        L.in_scan[lane] = qscan;
+        L.in_he[lane] = he;
+        L.in_hb[lane] = hb;
+        L.in_hs[lane] = hs;
+        L.in_v[lane] = vv;
+        L.in_thr[lane] = th;
+        wave_sync();
+        for (uint32_t qb = 0; qb < Qn; qb += kWave) {
+            // level 3: one quad of member positions per lane
+            const uint32_t qg = qb + lane;
+            uint32_t u[4] = {0u, 0u, 0u, 0u};
+            uint32_t ve = 0, hee = 0, q = 0, the = 0;
+            bool need = false;
+            if (qg < Qn) {
+                const uint32_t k = search64(L.in_scan, qg);
+                const uint32_t start = k ? L.in_scan[k - 1] : 0u;
+                q = qg - start;
+                hee = L.in_he[k];
+                ve = L.in_v[k];
+                the = L.in_thr[k];
+                const uint32_t hbk = L.in_hb[k], hsk = L.in_hs[k];
+                const uint32_t p0 = q * 4u;
+                const uint32_t cm = min(4u, hsk - p0);
+#pragma unroll
+                for (uint32_t t = 0; t < 4; ++t) u[t] = t < cm ? a.he_mem[hbk + p0 + t] : ve;
+#pragma unroll
+                for (uint32_t t = 0; t < 4; ++t) {
+                    bool cand = u[t] != ve;
+                    if (cand && prefilter) cand = !(bm_load<kLds>(bm, u[t] >> 5) & (1u << (u[t] & 31)));
+                    need |= cand;
+                }
+            }
+            if (__ballot(need) == 0) continue;
+            uint4 c = make_uint4(0u, 0u, 0u, 0u);
+            if (need) c = philox4x32_10(coin_counter(j, hee, ve, pool, q), key);
+            const uint32_t w[4] = {c.x, c.y, c.z, c.w};
+#pragma unroll
+            for (uint32_t t = 0; t < 4; ++t) {
+                bool fresh = false;
+                if (need && u[t] != ve && channel_live(w[t], the)) {
+                    const uint32_t bit = 1u << (u[t] & 31);
+                    fresh = (atomicOr(&bm[u[t] >> 5], bit) & bit) == 0u;
+                }
+                app.push(fresh, u[t]);
+            }
+        }
+    }
+    wave_sync();
+    return wave_sum(bytes);
+}
+
+// Record a finished set's per-id outputs.
+__device__ __forceinline__ void record_set(const RRArgs &a, uint64_t idx, uint64_t off, uint32_t size, uint32_t root) {
+    const uint64_t o = a.out_base + idx;
+    a.stage_off[o] = off;
+    a.sizes[o] = size;
+    a.roots[o] = root;
+    if (size > kBigSet) a.big_ids[atomicAdd(&a.ctr[kBigCount], 1ull)] = o;
+}
+
+// ---- phase A ---------------------------------------------------------------
 template <bool kLdsBitmap>
-__global__ __launch_bounds__(kWG) void k_rr_bfs(RRArgs a) {
+__global__ __launch_bounds__(kWG) void k_rr_light(RRArgs a) {
     __shared__ WaveLds lds[kWavesPerWG];
+    __shared__ uint32_t sort_s[kWavesPerWG][kSortMax];
     __shared__ uint32_t lbm[kLdsBitmap ? kWavesPerWG : 1][kLdsBitmap ? kLdsBitmapWords : 1];
     const uint32_t lane = lane_id(), wv = threadIdx.x / kWave;
-    const uint64_t slot = (uint64_t)blockIdx.x * kWavesPerWG + wv;
+    uint32_t slot = blockIdx.x * kWavesPerWG + wv;
     WaveLds &L = lds[wv];
-    uint32_t *list = a.lists + slot * a.n;
+    uint32_t *sortb = sort_s[wv];
+    uint32_t *list = a.lists + (uint64_t)slot * a.n;
     uint32_t *bm;
     if constexpr (kLdsBitmap) {
         bm = lbm[wv];
         for (uint32_t i = lane; i < a.bm_words; i += kWave) bm[i] = 0u;
     } else {
-        bm = a.bitmaps + slot * a.bm_words;
+        bm = a.bitmaps + (uint64_t)slot * a.bm_words;
     }
     wave_sync();
     const uint2 key = make_uint2(a.key0, a.key1);
+    bool can_defer = !kLdsBitmap;
+    uint64_t bytes_done = 0;
 
     for (;;) {
         unsigned long long idx = 0;
-        if (lane == 0) idx = atomicAdd(a.work, 1ull);
+        if (lane == 0) idx = atomicAdd(&a.ctr[kWork], 1ull);
         idx = wave_bcast64(idx, 0);
         if (idx >= a.count) break;
-        const uint64_t j = a.id_begin + idx;
-        const uint32_t root = rr_root(a, j, key);
+        uint64_t j;
+        uint32_t pool;
+        resolve(a, idx, &j, &pool);
+        const uint32_t root = rr_root(a, j, pool, key);
         if (lane == 0) {
             list[0] = root;
             atomicOr(&bm[root >> 5], 1u << (root & 31));
         }
-        uint32_t size = 1, head = 0;
+        LocalAppend app{list, 1u, a.n};
+        uint32_t head = 0;
+        uint64_t spent = 0;
+        bool deferred = false;
 
-        while (head < size) {
+        while (head < app.size) {
             // queue entries were stored by other lanes of this wave: wait for
             // the stores and drop stale L1 lines before reading them
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            const uint32_t nb = min((uint32_t)kWave, size - head);
+            const uint32_t nb = min((uint32_t)kWave, app.size - head);
             uint32_t v = 0, e0 = 0, d = 0;
             if (lane < nb) {
                 v = list[head + lane];
                 e0 = a.v_off[v];
                 d = a.v_off[v + 1] - e0;
             }
-            head += nb;
-            const uint32_t dscan = wave_incl_scan(d);
-            const uint32_t D = wave_bcast(dscan, kWave - 1);
-            L.fr_scan[lane] = dscan;
-            L.fr_v[lane] = v;
-            L.fr_e0[lane] = e0;
-            wave_sync();
-            for (uint32_t base = 0; base < D; base += kWave) {
-                // level 2: one incidence (v, he) per lane
-                const uint32_t g = base + lane;
-                uint32_t he = 0, hb = 0, hs = 0, vv = 0, th = 0, nq = 0;
-                if (g < D) {
-                    const uint32_t k = search64(L.fr_scan, g);
-                    const uint32_t start = k ? L.fr_scan[k - 1] : 0u;
-                    vv = L.fr_v[k];
-                    he = a.v_he[L.fr_e0[k] + (g - start)];
-                    hb = a.he_off[he];
-                    hs = a.he_off[he + 1] - hb;
-                    th = a.thr[vv];
-                    nq = th ? (hs + 3u) >> 2 : 0u;   // threshold 0: no channel into vv is live
-                }
-                const uint32_t qscan = wave_incl_scan(nq);
-                const uint32_t Qn = wave_bcast(qscan, kWave - 1);
-                wave_sync();
-                L.in_scan[lane] = qscan;
-                L.in_he[lane] = he;
-                L.in_hb[lane] = hb;
-                L.in_hs[lane] = hs;
-                L.in_v[lane] = vv;
-                L.in_thr[lane] = th;
-                wave_sync();
-                for (uint32_t qb = 0; qb < Qn; qb += kWave) {
-                    // level 3: one quad of member positions per lane
-                    const uint32_t qg = qb + lane;
-                    uint32_t u[4];
-                    uint32_t ve = 0, hee = 0, q = 0, the = 0;
-                    bool need = false;
-                    if (qg < Qn) {
-                        const uint32_t k = search64(L.in_scan, qg);
-                        const uint32_t start = k ? L.in_scan[k - 1] : 0u;
-                        q = qg - start;
-                        hee = L.in_he[k];
-                        ve = L.in_v[k];
-                        the = L.in_thr[k];
-                        const uint32_t hbk = L.in_hb[k], hsk = L.in_hs[k];
-                        const uint32_t p0 = q * 4u;
-                        const uint32_t cm = min(4u, hsk - p0);
-#pragma unroll
-                        for (uint32_t t = 0; t < 4; ++t) u[t] = t < cm ? a.he_mem[hbk + p0 + t] : ve;
-#pragma unroll
-                        for (uint32_t t = 0; t < 4; ++t) {
-                            bool cand = u[t] != ve;
-                            if (cand && a.prefilter) cand = !(bm_load<kLdsBitmap>(bm, u[t] >> 5) & (1u << (u[t] & 31)));
-                            need |= cand;
-                        }
-                    } else {
-#pragma unroll
-                        for (uint32_t t = 0; t < 4; ++t) u[t] = 0;
+            if (can_defer && (spent > kBudget || __ballot(d > kHeavy) != 0)) {
+                // hand the set over to phase B and continue with a fresh slot
+                uint32_t fresh_slot = 0;
+                if (lane == 0) fresh_slot = (uint32_t)atomicAdd(&a.ctr[kFreeNext], 1ull);
+                fresh_slot = wave_bcast(fresh_slot, 0);
+                if (fresh_slot < a.slot_total) {
+                    if (lane == 0) {
+                        const uint32_t dd = (uint32_t)atomicAdd(&a.ctr[kDefCount], 1ull);
+                        a.def_idx[dd] = idx;
+                        a.def_root[dd] = root;
+                        a.def_slot[dd] = slot;
+                        a.def_head[dd] = head;
+                        a.def_size[dd] = app.size;
                     }
-                    if (__ballot(need) == 0) continue;
-                    uint4 c = make_uint4(0u, 0u, 0u, 0u);
-                    if (need) c = philox4x32_10(coin_counter(j, hee, ve, a.pool, q), key);
-                    const uint32_t w[4] = {c.x, c.y, c.z, c.w};
-#pragma unroll
-                    for (uint32_t t = 0; t < 4; ++t) {
-                        bool fresh = false;
-                        if (need && u[t] != ve && channel_live(w[t], the)) {
-                            const uint32_t bit = 1u << (u[t] & 31);
-                            fresh = (atomicOr(&bm[u[t] >> 5], bit) & bit) == 0u;
-                        }
-                        const uint64_t bal = __ballot(fresh);
-                        const uint32_t at = size + lane_rank(bal);
-                        if (fresh && at < a.n) list[at] = u[t];   // at < n always holds: one bit per vertex
-                        size = min(size + (uint32_t)__popcll(bal), a.n);
-                    }
+                    slot = fresh_slot;
+                    list = a.lists + (uint64_t)slot * a.n;
+                    bm = a.bitmaps + (uint64_t)slot * a.bm_words;
+                    deferred = true;
+                    break;
                 }
+                can_defer = false;   // no spare slot left: this wave finishes its sets itself
             }
+            head += nb;
+            spent += wave_bcast(wave_incl_scan(d), kWave - 1);
+            bytes_done += 20ull * nb;
+            bytes_done += expand<kLdsBitmap>(a, L, j, pool, key, bm, false, v, e0, d, app);
         }
+        if (deferred) continue;
+        const uint32_t size = app.size;
 
         // ---- output: ascending members into the stage --------------------
         unsigned long long off = 0;
-        if (lane == 0) off = atomicAdd(a.stage_bump, (unsigned long long)size);
+        if (lane == 0) off = atomicAdd(&a.ctr[kBump], (unsigned long long)size);
         off = wave_bcast64(off, 0);
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         if (off + size <= a.stage_cap) {
             if (size <= kSortMax) {
                 uint32_t P2 = kWave;
                 while (P2 < size) P2 <<= 1;
-                for (uint32_t i = lane; i < P2; i += kWave) L.sort[i] = i < size ? list[i] : 0xFFFFFFFFu;
+                for (uint32_t i = lane; i < P2; i += kWave) sortb[i] = i < size ? list[i] : 0xFFFFFFFFu;
                 wave_sync();
                 for (uint32_t k = 2; k <= P2; k <<= 1) {
                     for (uint32_t jj = k >> 1; jj > 0; jj >>= 1) {
                         for (uint32_t i = lane; i < P2; i += kWave) {
                             const uint32_t x = i ^ jj;
                             if (x > i) {
-                                const uint32_t p = L.sort[i], qv = L.sort[x];
+                                const uint32_t p = sortb[i], qv = sortb[x];
                                 if ((p > qv) == ((i & k) == 0)) {
-                                    L.sort[i] = qv;
-                                    L.sort[x] = p;
+                                    sortb[i] = qv;
+                                    sortb[x] = p;
                                 }
                             }
                         }
                         wave_sync();
                     }
                 }
-                for (uint32_t i = lane; i < size; i += kWave) a.stage[off + i] = L.sort[i];
+                for (uint32_t i = lane; i < size; i += kWave) a.stage[off + i] = sortb[i];
                 wave_sync();
             } else {
                 uint32_t written = 0;
@@ -266,13 +401,7 @@ __global__ __launch_bounds__(kWG) void k_rr_bfs(RRArgs a) {
                 }
             }
         }
-        if (lane == 0) {
-            const uint64_t o = a.out_base + idx;
-            a.stage_off[o] = off;
-            a.sizes[o] = size;
-            a.roots[o] = root;
-            if (size > kBigSet) a.big_ids[atomicAdd(a.big_count, 1ull)] = o;
-        }
+        if (lane == 0) record_set(a, idx, off, size, root);
         // clear this set's marks (the bitmap is all-zero again afterwards)
         if (kLdsBitmap && size * 4u > a.bm_words) {
             for (uint32_t i = lane; i < a.bm_words; i += kWave) bm[i] = 0u;
@@ -282,10 +411,197 @@ __global__ __launch_bounds__(kWG) void k_rr_bfs(RRArgs a) {
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         wave_sync();
     }
+    if (lane == 0 && bytes_done) atomicAdd(&a.ctr[kBytesA], bytes_done);
 }
 
-// Compaction of sets up to kBigSet members: each wave moves 64 consecutive
-// ids, flattened over their members.
+// ---- phase B ---------------------------------------------------------------
+// Item: x = deferred set d | heavy << 31; light: y = first queue index,
+// z = count (<= 64); heavy: y = vertex, z = first incidence, w = end.
+// One atomicAdd per planning batch.  A reservation that crosses the cap is
+// abandoned: its slots below the cap are filled with skip markers (x = ~0)
+// by the reserving wave, so k_expand never reads an unwritten item.
+constexpr uint32_t kSkipItem = 0xFFFFFFFFu;
+
+__global__ __launch_bounds__(kWG) void k_plan(RRArgs a, uint32_t ndef, uint32_t parity) {
+    const uint32_t lane = lane_id(), wv = threadIdx.x / kWave;
+    const uint32_t waves = gridDim.x * kWavesPerWG;
+    for (uint32_t d = blockIdx.x * kWavesPerWG + wv; d < ndef; d += waves) {
+        uint32_t head = a.def_head[d];
+        const uint32_t size = a.def_size[d];
+        const uint32_t *list = a.lists + (uint64_t)a.def_slot[d] * a.n;
+        while (head < size) {
+            uint32_t nb = min((uint32_t)kWave, size - head);
+            uint32_t v = 0, e0 = 0, deg = 0, hv = 0, light = 0;
+            if (lane < nb) {
+                v = list[head + lane];
+                e0 = a.v_off[v];
+                deg = a.v_off[v + 1] - e0;
+                hv = deg > kChunk ? (deg + kChunk - 1u) / kChunk : 0u;
+                light = hv ? 0u : deg;
+            }
+            // light vertices form segments of consecutive queue entries: a lane
+            // belongs to segment floor(prefix of light incidences before it /
+            // kSeg); each light degree is <= kChunk <= kSeg, so segments have no
+            // gaps and hold fewer than kSeg + kChunk incidences
+            const uint32_t lscan = wave_incl_scan(light);
+            const uint32_t seg = (lscan - light) / kSeg;
+            const uint32_t prev_seg = __shfl_up(seg, 1, kWave);
+            const bool first = lane < nb && (lane == 0 || seg != prev_seg);
+            uint64_t firsts = __ballot(first);
+            uint32_t nseg = (uint32_t)__popcll(firsts);
+            uint32_t hscan = wave_incl_scan(hv);
+            uint32_t need = nseg + wave_bcast(hscan, kWave - 1);
+            if (need > kItemCap) {   // too many heavy chunks at once: plan one vertex
+                nb = 1;
+                if (lane > 0) hv = 0;
+                firsts = 1ull;
+                nseg = 1;
+                hscan = wave_incl_scan(hv);
+                need = 1u + wave_bcast(hscan, kWave - 1);
+            }
+            unsigned long long base = 0;
+            if (lane == 0) base = atomicAdd(&a.ctr[kItems + parity], (unsigned long long)need);
+            base = wave_bcast64(base, 0);
+            if (base + need > kItemCap) {
+                for (uint64_t x = base + lane; x < kItemCap; x += kWave) a.items[x].x = kSkipItem;
+                break;
+            }
+            if (lane < nb && ((firsts >> lane) & 1ull)) {
+                // segment = this lane up to the next first lane (or nb)
+                const uint64_t above = lane + 1 < 64 ? (firsts >> (lane + 1)) << (lane + 1) : 0ull;
+                const uint32_t next = above ? (uint32_t)__ffsll((unsigned long long)above) - 1u : nb;
+                a.items[base + lane_rank(firsts)] = make_uint4(d, head + lane, min(next, nb) - lane, 0u);
+            }
+            for (uint32_t k = 0; k < hv; ++k) {
+                const uint32_t b0 = e0 + k * kChunk;
+                a.items[base + nseg + hscan - hv + k] = make_uint4(d | 0x80000000u, v, b0, min(b0 + kChunk, e0 + deg));
+            }
+            head += nb;
+        }
+        if (lane == 0) a.def_head[d] = head;
+    }
+}
+
+__global__ __launch_bounds__(kWG) void k_expand(RRArgs a, uint32_t parity) {
+    __shared__ WaveLds lds[kWavesPerWG];
+    const uint32_t lane = lane_id(), wv = threadIdx.x / kWave;
+    WaveLds &L = lds[wv];
+    const uint2 key = make_uint2(a.key0, a.key1);
+    const uint64_t nitems = min(a.ctr[kItems + parity], (unsigned long long)kItemCap);
+    if (blockIdx.x == 0 && threadIdx.x == 0) a.ctr[kItems + (parity ^ 1u)] = 0ull;   // next superstep's counter
+    uint64_t bytes_done = 0;
+    // items have bounded cost (< kSeg + kChunk incidences), so a static strided
+    // assignment balances well and needs no shared counter
+    const uint64_t waves = (uint64_t)gridDim.x * kWavesPerWG;
+    for (uint64_t it = (uint64_t)blockIdx.x * kWavesPerWG + wv; it < nitems; it += waves) {
+        const uint4 item = a.items[it];
+        if (item.x == kSkipItem) continue;
+        const uint32_t d = item.x & 0x7FFFFFFFu;
+        const bool heavy = (item.x >> 31) != 0u;
+        const uint32_t slot = a.def_slot[d];
+        uint32_t *list = a.lists + (uint64_t)slot * a.n;
+        uint32_t *bm = a.bitmaps + (uint64_t)slot * a.bm_words;
+        uint64_t j;
+        uint32_t pool;
+        resolve(a, a.def_idx[d], &j, &pool);
+        uint32_t *size_p = &a.def_size[d];
+        const bool prefilter = __hip_atomic_load(size_p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= kPrefilterMin;
+        uint32_t v = 0, e0 = 0, deg = 0;
+        if (!heavy) {
+            if (lane < item.z) {
+                v = list[item.y + lane];
+                e0 = a.v_off[v];
+                deg = a.v_off[v + 1] - e0;
+                if (deg > kChunk) deg = 0;   // expanded by its heavy items
+            }
+            bytes_done += 20ull * item.z;
+        } else if (lane == 0) {
+            v = item.y;
+            e0 = item.z;
+            deg = item.w - item.z;
+        }
+        SharedAppend app{list, size_p, a.n};
+        bytes_done += expand<false>(a, L, j, pool, key, bm, prefilter, v, e0, deg, app);
+    }
+    if (lane == 0 && bytes_done) atomicAdd(&a.ctr[kBytesB], bytes_done);
+}
+
+// One workgroup per deferred set: ascending members into the stage, per-id
+// outputs, then the set's marks are cleared.
+__global__ __launch_bounds__(kWG) void k_finish(RRArgs a, uint32_t ndef) {
+    __shared__ uint32_t buf[kSortMaxWG];
+    __shared__ uint32_t wave_tot[kWavesPerWG];
+    __shared__ unsigned long long off_s;
+    __shared__ uint32_t running;
+    const uint32_t lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+    for (uint32_t d = blockIdx.x; d < ndef; d += gridDim.x) {
+        const uint32_t size = a.def_size[d];
+        uint32_t *list = a.lists + (uint64_t)a.def_slot[d] * a.n;
+        uint32_t *bm = a.bitmaps + (uint64_t)a.def_slot[d] * a.bm_words;
+        if (threadIdx.x == 0) off_s = atomicAdd(&a.ctr[kBump], (unsigned long long)size);
+        __syncthreads();
+        const uint64_t off = off_s;
+        if (off + size <= a.stage_cap) {
+            if (size <= kSortMaxWG) {
+                uint32_t P2 = kWG;
+                while (P2 < size) P2 <<= 1;
+                for (uint32_t i = threadIdx.x; i < P2; i += kWG) buf[i] = i < size ? list[i] : 0xFFFFFFFFu;
+                __syncthreads();
+                for (uint32_t k = 2; k <= P2; k <<= 1) {
+                    for (uint32_t jj = k >> 1; jj > 0; jj >>= 1) {
+                        for (uint32_t i = threadIdx.x; i < P2; i += kWG) {
+                            const uint32_t x = i ^ jj;
+                            if (x > i) {
+                                const uint32_t p = buf[i], qv = buf[x];
+                                if ((p > qv) == ((i & k) == 0)) {
+                                    buf[i] = qv;
+                                    buf[x] = p;
+                                }
+                            }
+                        }
+                        __syncthreads();
+                    }
+                }
+                for (uint32_t i = threadIdx.x; i < size; i += kWG) a.stage[off + i] = buf[i];
+            } else {
+                if (threadIdx.x == 0) running = 0;
+                __syncthreads();
+                for (uint32_t w0 = 0; w0 < a.bm_words; w0 += kWG) {
+                    const uint32_t wi = w0 + threadIdx.x;
+                    uint32_t word = wi < a.bm_words ? bm[wi] : 0u;
+                    const uint32_t cnt = (uint32_t)__popc(word);
+                    const uint32_t incl = wave_incl_scan(cnt);
+                    if (lane == kWave - 1) wave_tot[wv] = incl;
+                    __syncthreads();
+                    uint32_t before = running;
+                    for (uint32_t q = 0; q < wv; ++q) before += wave_tot[q];
+                    uint64_t pos = off + before + incl - cnt;
+                    while (word) {
+                        const uint32_t bit = (uint32_t)__ffs(word) - 1u;
+                        word &= word - 1u;
+                        if (pos < off + size) a.stage[pos] = wi * 32u + bit;
+                        ++pos;
+                    }
+                    __syncthreads();
+                    if (threadIdx.x == kWG - 1) running = before + incl;
+                    __syncthreads();
+                }
+            }
+        }
+        if (threadIdx.x == 0) record_set(a, a.def_idx[d], off, size, a.def_root[d]);
+        __syncthreads();
+        if (size > a.bm_words) {
+            for (uint32_t i = threadIdx.x; i < a.bm_words; i += kWG) bm[i] = 0u;
+        } else {
+            for (uint32_t i = threadIdx.x; i < size; i += kWG) bm[list[i] >> 5] = 0u;
+        }
+        __syncthreads();
+    }
+}
+
+// ---- compaction ------------------------------------------------------------
+// Sets up to kBigSet members: each wave moves 64 consecutive ids, flattened
+// over their members.
 __global__ __launch_bounds__(kWG) void k_move_small(const uint64_t *__restrict__ stage_off,
                                                      const uint32_t *__restrict__ sizes,
                                                      const uint64_t *__restrict__ dst_off, uint64_t count,
@@ -322,16 +638,19 @@ __global__ __launch_bounds__(kWG) void k_move_small(const uint64_t *__restrict__
     }
 }
 
+// Sets above kBigSet members whose per-id index lies in [first, first + count):
+// one workgroup each.
 __global__ __launch_bounds__(kWG) void k_move_big(const uint64_t *__restrict__ big_ids,
-                                                   const unsigned long long *__restrict__ big_count,
-                                                   const uint64_t *__restrict__ stage_off,
+                                                   const unsigned long long *__restrict__ big_count, uint64_t first,
+                                                   uint64_t count, const uint64_t *__restrict__ stage_off,
                                                    const uint32_t *__restrict__ sizes,
                                                    const uint64_t *__restrict__ dst_off,
                                                    const uint32_t *__restrict__ stage, uint32_t *__restrict__ mem) {
     const uint64_t nbig = *big_count;
     for (uint64_t b = blockIdx.x; b < nbig; b += gridDim.x) {
         const uint64_t id = big_ids[b];
-        const uint64_t src = stage_off[id], dst = dst_off[id];
+        if (id < first || id >= first + count) continue;
+        const uint64_t src = stage_off[id], dst = dst_off[id - first];
         const uint32_t sz = sizes[id];
         for (uint32_t i = threadIdx.x; i < sz; i += blockDim.x) mem[dst + i] = stage[src + i];
     }
@@ -356,8 +675,11 @@ __global__ __launch_bounds__(kWG) void k_weight_sum(const uint32_t *__restrict__
     }
 }
 
+// ---- host side -------------------------------------------------------------
 struct LaunchShape {
-    uint32_t grid, waves;
+    uint32_t grid;        // phase A workgroups (one slot per wave)
+    uint32_t slots;       // total slots (phase A waves + spare slots for deferred sets)
+    uint32_t grid_b;      // phase B workgroups
     bool lds;
 };
 
@@ -371,34 +693,46 @@ int ensure_workspace(hyperim_graph g, hipStream_t s, LaunchShape *shape) {
         HIM_HIP(hipGetDevice(&dev));
         int cus = 0;
         HIM_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-        int per_cu = 0;
+        int per_cu = 0, per_cu_b = 0;
         if (lds)
-            HIM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rr_bfs<true>, kWG, 0));
+            HIM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rr_light<true>, kWG, 0));
         else
-            HIM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rr_bfs<false>, kWG, 0));
+            HIM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rr_light<false>, kWG, 0));
+        HIM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_b, k_expand, kWG, 0));
         per_cu = std::max(per_cu, 1);
+        per_cu_b = std::max(per_cu_b, 1);
+        const uint64_t per_slot = (uint64_t)n * 4u + (lds ? 0u : (uint64_t)words * 4u);
+        const uint64_t max_slots = std::max<uint64_t>(kSlotBudget / std::max<uint64_t>(per_slot, 1), 2 * kWavesPerWG);
         uint64_t grid = (uint64_t)cus * (uint64_t)per_cu;
-        const uint64_t per_wave = (uint64_t)n * 4u + (lds ? 0u : (uint64_t)words * 4u);
-        const uint64_t max_waves = std::max<uint64_t>(kSlotBudget / std::max<uint64_t>(per_wave, 1), kWavesPerWG);
-        grid = std::min<uint64_t>(grid, max_waves / kWavesPerWG);
+        // phase A keeps at least half of the slots spare for deferred sets
+        grid = std::min<uint64_t>(grid, max_slots / (2 * kWavesPerWG));
         grid = std::max<uint64_t>(grid, 1);
+        const uint64_t waves = grid * kWavesPerWG;
+        const uint64_t slots = lds ? waves : std::min<uint64_t>(max_slots, 4 * waves);
         ws.grid = (uint32_t)grid;
-        ws.waves = ws.grid * kWavesPerWG;
-        HIM_CHECK(ws.lists.reserve(sizeof(uint32_t) * (size_t)ws.waves * std::max<uint32_t>(n, 1), s));
+        ws.waves = (uint32_t)waves;
+        ws.slots = (uint32_t)slots;
+        ws.grid_b = (uint32_t)(cus * per_cu_b);
+        HIM_CHECK(ws.lists.reserve(sizeof(uint32_t) * (size_t)slots * std::max<uint32_t>(n, 1), s));
         if (!lds) {
-            HIM_CHECK(ws.bitmaps.reserve(sizeof(uint32_t) * (size_t)ws.waves * words, s));
-            HIM_HIP(hipMemsetAsync(ws.bitmaps.ptr, 0, sizeof(uint32_t) * (size_t)ws.waves * words, s));
+            HIM_CHECK(ws.bitmaps.reserve(sizeof(uint32_t) * (size_t)slots * words, s));
+            HIM_HIP(hipMemsetAsync(ws.bitmaps.ptr, 0, sizeof(uint32_t) * (size_t)slots * words, s));
         }
-        HIM_CHECK(ws.counters.reserve(sizeof(unsigned long long) * 8, s));
+        HIM_CHECK(ws.counters.reserve(sizeof(unsigned long long) * kNumCtr, s));
+        const size_t ndef = std::max<uint64_t>(slots - waves, 1);
+        HIM_CHECK(ws.def_idx.reserve(sizeof(uint64_t) * ndef, s));
+        HIM_CHECK(ws.def_u32.reserve(sizeof(uint32_t) * 4 * ndef, s));
+        HIM_CHECK(ws.items.reserve(sizeof(uint4) * (size_t)kItemCap, s));
     }
     shape->grid = ws.grid;
-    shape->waves = ws.waves;
+    shape->slots = ws.slots;
+    shape->grid_b = ws.grid_b;
     shape->lds = lds;
     return HYPERIM_OK;
 }
 
 // Id ranges of every (ladder block, stratum) pair inside [id_begin, id_end).
-void stratum_ranges(hyperim_graph g, const RRKey &key, uint64_t id_begin, uint64_t id_end,
+void stratum_ranges(hyperim_graph g, const RRKey &key, uint32_t pool, uint64_t id_begin, uint64_t id_end,
                     std::vector<std::pair<uint64_t, uint64_t>> *out) {
     const uint64_t Q = 1ull << key.qlog;
     const uint32_t n = g->n;
@@ -416,7 +750,7 @@ void stratum_ranges(hyperim_graph g, const RRKey &key, uint64_t id_begin, uint64
             J = 1ull << hb;
             T = J;
         }
-        const uint4 r = philox4x32_10(root_counter(b, key.pool), make_uint2((uint32_t)key.seed, key.instance));
+        const uint4 r = philox4x32_10(root_counter(b, pool), make_uint2((uint32_t)key.seed, key.instance));
         const uint64_t x = (uint64_t)r.x | ((uint64_t)r.y << 32);
         const uint64_t o = (uint64_t)(((unsigned __int128)x * n) >> 64);
         uint64_t prev = 0;
@@ -438,33 +772,127 @@ void stratum_ranges(hyperim_graph g, const RRKey &key, uint64_t id_begin, uint64
     }
 }
 
+int read_ctr(hipStream_t s, const unsigned long long *dev, int idx, uint64_t *out) {
+    unsigned long long v = 0;
+    HIM_HIP(hipMemcpyAsync(&v, dev + idx, sizeof(v), hipMemcpyDeviceToHost, s));
+    HIM_HIP(hipStreamSynchronize(s));
+    *out = v;
+    return HYPERIM_OK;
+}
+
+int event_pair(RRWorkspace &ws, size_t i) {
+    while (ws.events.size() < 2 * (i + 1)) {
+        hipEvent_t e;
+        HIM_HIP(hipEventCreate(&e));
+        ws.events.push_back(e);
+    }
+    return HYPERIM_OK;
+}
+
+// One launch group: phase A over `a`'s tasks, then phase B over the sets it
+// deferred.  Per-id outputs land at a.out_base + launch index.
+int run_launch(hyperim_graph g, RRArgs &a, const LaunchShape &shape, uint32_t grid, bool trace, hipStream_t s) {
+    RRWorkspace &ws = g->rr;
+    unsigned long long *ctr = a.ctr;
+    // fresh work counter, deferred list and spare-slot cursor
+    const unsigned long long first_free = (unsigned long long)shape.grid * kWavesPerWG;
+    HIM_HIP(hipMemsetAsync(ctr + kWork, 0, sizeof(unsigned long long), s));
+    HIM_HIP(hipMemsetAsync(ctr + kDefCount, 0, sizeof(unsigned long long), s));
+    HIM_HIP(hipMemcpyAsync(ctr + kFreeNext, &first_free, sizeof(unsigned long long), hipMemcpyHostToDevice, s));
+    HIM_CHECK(event_pair(ws, 0));
+    HIM_HIP(hipEventRecord(ws.events[0], s));
+    if (shape.lds)
+        hipLaunchKernelGGL(k_rr_light<true>, dim3(grid), dim3(kWG), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_rr_light<false>, dim3(grid), dim3(kWG), 0, s, a);
+    HIM_HIP(hipGetLastError());
+    HIM_HIP(hipEventRecord(ws.events[1], s));
+    uint64_t ndef = 0;
+    HIM_CHECK(read_ctr(s, ctr, kDefCount, &ndef));
+    float ms = 0.f;
+    HIM_HIP(hipEventElapsedTime(&ms, ws.events[0], ws.events[1]));
+    ws.ms_bfs += ms;
+    ws.ms_light += ms;
+    ws.launches += 1;
+    if (ndef == 0) return HYPERIM_OK;
+    // phase B: supersteps over the deferred sets
+    const uint32_t plan_grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(div_up(ndef, kWavesPerWG), 4096));
+    // every superstep with items advances some queue head, and a set holds at
+    // most n members, so n supersteps per set bound the loop
+    const uint64_t max_steps = (uint64_t)g->n * ndef + 2 * kStepsPerSync;
+    uint64_t steps = 0;
+    HIM_HIP(hipMemsetAsync(ctr + kItems, 0, 2 * sizeof(unsigned long long), s));
+    for (;;) {
+        if (steps > max_steps) {
+            set_error_detail("phase B did not converge");
+            return HYPERIM_EHIP;
+        }
+        HIM_HIP(hipEventRecord(ws.events[0], s));
+        const int batch = trace ? 1 : kStepsPerSync;
+        uint32_t parity = 0;
+        for (int step = 0; step < batch; ++step) {
+            parity = (uint32_t)((steps + step) & 1u);
+            hipLaunchKernelGGL(k_plan, dim3(plan_grid), dim3(kWG), 0, s, a, (uint32_t)ndef, parity);
+            hipLaunchKernelGGL(k_expand, dim3(shape.grid_b), dim3(kWG), 0, s, a, parity);
+        }
+        steps += batch;
+        HIM_HIP(hipGetLastError());
+        HIM_HIP(hipEventRecord(ws.events[1], s));
+        uint64_t items = 0;
+        HIM_CHECK(read_ctr(s, ctr, kItems + (int)parity, &items));
+        HIM_HIP(hipEventElapsedTime(&ms, ws.events[0], ws.events[1]));
+        if (trace)
+            fprintf(stderr, "[hyperim] superstep %llu: %llu items, %.3f ms\n", (unsigned long long)steps,
+                    (unsigned long long)items, ms);
+        ws.ms_bfs += ms;
+        ws.ms_heavy += ms;
+        ws.launches += 2 * batch;
+        ws.supersteps += batch;
+        if (items == 0) break;   // the last superstep found no frontier left
+    }
+    HIM_HIP(hipEventRecord(ws.events[0], s));
+    hipLaunchKernelGGL(k_finish, dim3((uint32_t)std::min<uint64_t>(ndef, 4096)), dim3(kWG), 0, s, a, (uint32_t)ndef);
+    HIM_HIP(hipGetLastError());
+    HIM_HIP(hipEventRecord(ws.events[1], s));
+    HIM_HIP(hipEventSynchronize(ws.events[1]));
+    HIM_HIP(hipEventElapsedTime(&ms, ws.events[0], ws.events[1]));
+    ws.ms_bfs += ms;
+    ws.ms_heavy += ms;
+    ws.launches += 1;
+    ws.deferred += ndef;
+    return HYPERIM_OK;
+}
+
 }  // namespace
 
-int rr_generate_stage(hyperim_graph g, const RRKey &key, uint64_t id_begin, uint64_t id_end, int form,
-                      hipStream_t s, uint64_t *total) {
+int rr_generate_stage(hyperim_graph g, const RRKey &key, const std::vector<RRTask> &tasks, int form, hipStream_t s,
+                      uint64_t *total) {
     RRWorkspace &ws = g->rr;
-    const uint64_t count = id_end - id_begin;
+    // HYPERIM_TRACE=1: synchronise after every grid-wide superstep and report
+    // its item count and time on stderr (diagnostics; same results)
+    static const bool trace = [] {
+        const char *e = getenv("HYPERIM_TRACE");
+        return e && e[0] == '1';
+    }();
+    if (tasks.empty() || tasks.size() > kMaxTasks) {
+        set_error_detail("1 to 4 generation tasks per call");
+        return HYPERIM_EINVAL;
+    }
+    uint64_t count = 0;
+    for (const RRTask &t : tasks) count += t.id_end - t.id_begin;
     LaunchShape shape;
     HIM_CHECK(ensure_workspace(g, s, &shape));
     HIM_CHECK(ws.stage_off.reserve(sizeof(uint64_t) * std::max<uint64_t>(count, 1), s, false));
     HIM_CHECK(ws.sizes.reserve(sizeof(uint32_t) * std::max<uint64_t>(count, 1), s, false));
     HIM_CHECK(ws.roots.reserve(sizeof(uint32_t) * std::max<uint64_t>(count, 1), s, false));
-    HIM_CHECK(ws.big_ids.reserve(sizeof(uint64_t) * std::max<uint64_t>(count, 1), s, false));  // big ids
+    HIM_CHECK(ws.big_ids.reserve(sizeof(uint64_t) * std::max<uint64_t>(count, 1), s, false));
     if (ws.stage.bytes < sizeof(uint32_t) * 4 * count)
         HIM_CHECK(ws.stage.reserve(sizeof(uint32_t) * std::max<uint64_t>(4 * count, 1 << 20), s, false));
 
-    std::vector<std::pair<uint64_t, uint64_t>> ranges;
-    if (form == 1) stratum_ranges(g, key, id_begin, id_end, &ranges);
-    else ranges.push_back({id_begin, id_end});
-
     unsigned long long *ctr = ws.counters.as<unsigned long long>();
-    while (ws.events.size() < 2 * ranges.size()) {
-        hipEvent_t e;
-        HIM_HIP(hipEventCreate(&e));
-        ws.events.push_back(e);
-    }
+    const size_t ndef_cap = std::max<uint64_t>(shape.slots - (uint64_t)shape.grid * kWavesPerWG, 1);
     for (int attempt = 0; attempt < 2; ++attempt) {
-        HIM_HIP(hipMemsetAsync(ctr, 0, sizeof(unsigned long long) * 8, s));
+        HIM_HIP(hipMemsetAsync(ctr, 0, sizeof(unsigned long long) * kNumCtr, s));
         RRArgs a{};
         a.he_off = g->he_off.as<uint32_t>();
         a.he_mem = g->he_mem.as<uint32_t>();
@@ -475,45 +903,62 @@ int rr_generate_stage(hyperim_graph g, const RRKey &key, uint64_t id_begin, uint
         a.n = g->n;
         a.key0 = (uint32_t)key.seed;
         a.key1 = key.instance;
-        a.pool = key.pool;
         a.qlog = key.qlog;
         a.bm_words = (g->n + 31u) / 32u;
-        a.prefilter = 1;
-        a.stage_bump = ctr + 1;
-        a.big_count = ctr + 2;
+        a.ctr = ctr;
         a.lists = ws.lists.as<uint32_t>();
         a.bitmaps = ws.bitmaps.as<uint32_t>();
+        a.slot_total = shape.slots;
         a.stage = ws.stage.as<uint32_t>();
         a.stage_cap = ws.stage.bytes / sizeof(uint32_t);
         a.stage_off = ws.stage_off.as<uint64_t>();
         a.sizes = ws.sizes.as<uint32_t>();
         a.roots = ws.roots.as<uint32_t>();
         a.big_ids = ws.big_ids.as<uint64_t>();
-        for (size_t r = 0; r < ranges.size(); ++r) {
-            a.id_begin = ranges[r].first;
-            a.count = ranges[r].second - ranges[r].first;
-            a.out_base = ranges[r].first - id_begin;
-            a.work = ctr + 3 + (r & 1);
-            if (r >= 1) HIM_HIP(hipMemsetAsync(a.work, 0, sizeof(unsigned long long), s));
-            uint32_t grid = shape.grid;
-            if (form == 1) grid = (uint32_t)std::min<uint64_t>(grid, div_up(a.count, kWavesPerWG));
-            HIM_HIP(hipEventRecord(ws.events[2 * r], s));
-            if (shape.lds)
-                hipLaunchKernelGGL(k_rr_bfs<true>, dim3(grid), dim3(kWG), 0, s, a);
-            else
-                hipLaunchKernelGGL(k_rr_bfs<false>, dim3(grid), dim3(kWG), 0, s, a);
-            HIM_HIP(hipGetLastError());
-            HIM_HIP(hipEventRecord(ws.events[2 * r + 1], s));
+        a.def_idx = ws.def_idx.as<uint64_t>();
+        a.def_root = ws.def_u32.as<uint32_t>();
+        a.def_slot = a.def_root + ndef_cap;
+        a.def_head = a.def_slot + ndef_cap;
+        a.def_size = a.def_head + ndef_cap;
+        a.items = ws.items.as<uint4>();
+        if (form == 0) {
+            // every task in one launch group
+            a.ntasks = (uint32_t)tasks.size();
+            uint64_t acc = 0;
+            for (size_t t = 0; t < tasks.size(); ++t) {
+                acc += tasks[t].id_end - tasks[t].id_begin;
+                a.t_end[t] = acc;
+                a.t_id[t] = tasks[t].id_begin;
+                a.t_pool[t] = tasks[t].pool;
+            }
+            a.count = acc;
+            a.out_base = 0;
+            HIM_CHECK(run_launch(g, a, shape, shape.grid, trace, s));
+        } else {
+            // plain form: one launch group per (task, ladder block, stratum)
+            uint64_t task_base = 0;
+            for (const RRTask &t : tasks) {
+                std::vector<std::pair<uint64_t, uint64_t>> ranges;
+                stratum_ranges(g, key, t.pool, t.id_begin, t.id_end, &ranges);
+                for (const auto &rg : ranges) {
+                    a.ntasks = 1;
+                    a.count = rg.second - rg.first;
+                    a.t_end[0] = a.count;
+                    a.t_id[0] = rg.first;
+                    a.t_pool[0] = t.pool;
+                    a.out_base = task_base + (rg.first - t.id_begin);
+                    const uint32_t grid = (uint32_t)std::min<uint64_t>(shape.grid, div_up(a.count, kWavesPerWG));
+                    HIM_CHECK(run_launch(g, a, shape, grid, trace, s));
+                }
+                task_base += t.id_end - t.id_begin;
+            }
         }
-        unsigned long long bump = 0;
-        HIM_HIP(hipMemcpyAsync(&bump, ctr + 1, sizeof(bump), hipMemcpyDeviceToHost, s));
-        HIM_HIP(hipStreamSynchronize(s));
-        for (size_t r = 0; r < ranges.size(); ++r) {
-            float ms = 0.f;
-            HIM_HIP(hipEventElapsedTime(&ms, ws.events[2 * r], ws.events[2 * r + 1]));
-            ws.ms_bfs += ms;
-            ws.launches += 1;
-        }
+        uint64_t bump = 0, ba = 0, bb = 0;
+        HIM_CHECK(read_ctr(s, ctr, kBump, &bump));
+        HIM_CHECK(read_ctr(s, ctr, kBytesA, &ba));
+        HIM_CHECK(read_ctr(s, ctr, kBytesB, &bb));
+        ws.bytes_light += ba;
+        ws.bytes_heavy += bb;
         if (bump <= ws.stage.bytes / sizeof(uint32_t)) {
             *total = bump;
             return HYPERIM_OK;
@@ -524,22 +969,34 @@ int rr_generate_stage(hyperim_graph g, const RRKey &key, uint64_t id_begin, uint
     return HYPERIM_ENOMEM;
 }
 
-int rr_compact_into(hyperim_graph g, hyperim_pool p, uint64_t count, hipStream_t s) {
+int rr_compact_into(hyperim_graph g, hyperim_pool p, uint64_t first, uint64_t count, uint64_t max_entries,
+                    hipStream_t s) {
     RRWorkspace &ws = g->rr;
+    if (count == 0) return HYPERIM_OK;
+    HIM_CHECK(pool_reserve(p, count, 0, s));
     uint64_t *dst_off = p->off + p->count;
-    HIM_CHECK(scan_u32_to_u64(ws.sizes.as<uint32_t>(), dst_off, count, p->total, ws.scan_tmp, s));
-    if (count) {
-        HIM_HIP(hipMemcpyAsync(p->roots + p->count, ws.roots.ptr, sizeof(uint32_t) * count,
-                               hipMemcpyDeviceToDevice, s));
-        const uint32_t grid = (uint32_t)std::min<uint64_t>(div_up(count, kWave * kWavesPerWG), 65535u);
-        hipLaunchKernelGGL(k_move_small, dim3(std::max<uint32_t>(grid, 1)), dim3(kWG), 0, s,
-                           ws.stage_off.as<uint64_t>(), ws.sizes.as<uint32_t>(), dst_off, count,
-                           ws.stage.as<uint32_t>(), p->mem);
-        hipLaunchKernelGGL(k_move_big, dim3(1024), dim3(kWG), 0, s, ws.big_ids.as<uint64_t>(),
-                           ws.counters.as<unsigned long long>() + 2, ws.stage_off.as<uint64_t>(),
-                           ws.sizes.as<uint32_t>(), dst_off, ws.stage.as<uint32_t>(), p->mem);
-        HIM_HIP(hipGetLastError());
+    HIM_CHECK(scan_u32_to_u64(ws.sizes.as<uint32_t>() + first, dst_off, count, p->total, ws.scan_tmp, s));
+    uint64_t new_total = 0;
+    HIM_HIP(hipMemcpyAsync(&new_total, dst_off + count, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    HIM_HIP(hipStreamSynchronize(s));
+    if (max_entries && new_total > max_entries) {
+        set_error_detail("pool would exceed max_entries");
+        return HYPERIM_ECAPACITY;
     }
+    HIM_CHECK(pool_reserve(p, count, new_total - p->total, s));
+    dst_off = p->off + p->count;   // storage may have moved
+    HIM_HIP(hipMemcpyAsync(p->roots + p->count, ws.roots.as<uint32_t>() + first, sizeof(uint32_t) * count,
+                           hipMemcpyDeviceToDevice, s));
+    const uint32_t grid = (uint32_t)std::min<uint64_t>(div_up(count, kWave * kWavesPerWG), 65535u);
+    hipLaunchKernelGGL(k_move_small, dim3(std::max<uint32_t>(grid, 1)), dim3(kWG), 0, s,
+                       ws.stage_off.as<uint64_t>() + first, ws.sizes.as<uint32_t>() + first, dst_off, count,
+                       ws.stage.as<uint32_t>(), p->mem);
+    hipLaunchKernelGGL(k_move_big, dim3(1024), dim3(kWG), 0, s, ws.big_ids.as<uint64_t>(),
+                       ws.counters.as<unsigned long long>() + kBigCount, first, count, ws.stage_off.as<uint64_t>(),
+                       ws.sizes.as<uint32_t>(), dst_off, ws.stage.as<uint32_t>(), p->mem);
+    HIM_HIP(hipGetLastError());
+    p->count += count;
+    p->total = new_total;
     return HYPERIM_OK;
 }
 
