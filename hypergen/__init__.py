@@ -147,15 +147,21 @@ def draw_members(rng: np.random.Generator, n: int, sizes: np.ndarray, members: t
     nnz = int(off[-1])
     seg = np.repeat(np.arange(len(sizes), dtype=np.int64), sizes)
     mem = draw(nnz)
-    while True:
-        order = np.lexsort((mem, seg))
-        sm, ss = mem[order], seg[order]
-        dup = np.zeros(nnz, dtype=bool)
+    pos_all = np.arange(nnz, dtype=np.int64)
+    active = pos_all                       # positions of hyperedges still to check
+    while active.size:
+        order = np.lexsort((mem[active], seg[active]))
+        idx = active[order]
+        sm, ss = mem[idx], seg[idx]
+        dup = np.zeros(idx.size, dtype=bool)
         dup[1:] = (sm[1:] == sm[:-1]) & (ss[1:] == ss[:-1])
         if not dup.any():
             break
-        pos = order[dup]
+        pos = idx[dup]
         mem[pos] = draw(len(pos))
+        bad = np.zeros(len(sizes), dtype=bool)
+        bad[seg[pos]] = True
+        active = pos_all[bad[seg]]
     return mem
 
 

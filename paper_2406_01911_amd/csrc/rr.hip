@@ -58,7 +58,7 @@ constexpr uint32_t kMaxTasks = 4;            // (pool, id range) tasks per launc
 constexpr uint32_t kItemCap = (1u << 22) + 64;   // phase B: work items per superstep (one vertex always fits)
 constexpr uint32_t kPrefilterMin = 4096;     // phase B: test visited marks before coins from this size
 constexpr int kStepsPerSync = 8;             // phase B supersteps launched between host checks
-constexpr uint64_t kSlotBudget = 24ull << 30; // bytes of slot lists + bitmaps
+constexpr uint64_t kSlotBudget = 48ull << 30; // bytes of slot lists + bitmaps
 
 // Counters (uint64 each) in the workspace counter block.
 // kItems and kItems + 1 alternate between supersteps: superstep s plans into
@@ -238,12 +238,14 @@ __device__ __forceinline__ uint64_t expand(const RRArgs &a, WaveLds &L, uint64_t
                 const uint32_t cm = min(4u, hsk - p0);
 #pragma unroll
                 for (uint32_t t = 0; t < 4; ++t) u[t] = t < cm ? a.he_mem[hbk + p0 + t] : ve;
+                uint32_t seen[4] = {0u, 0u, 0u, 0u};
+                if (prefilter) {
+                    // all four mark words in flight together (u[t] is always a vertex id)
 #pragma unroll
-                for (uint32_t t = 0; t < 4; ++t) {
-                    bool cand = u[t] != ve;
-                    if (cand && prefilter) cand = !(bm_load<kLds>(bm, u[t] >> 5) & (1u << (u[t] & 31)));
-                    need |= cand;
+                    for (uint32_t t = 0; t < 4; ++t) seen[t] = bm_load<kLds>(bm, u[t] >> 5);
                 }
+#pragma unroll
+                for (uint32_t t = 0; t < 4; ++t) need |= u[t] != ve && !(seen[t] & (1u << (u[t] & 31)));
             }
             if (__ballot(need) == 0) continue;
             uint4 c = make_uint4(0u, 0u, 0u, 0u);
@@ -886,11 +888,17 @@ int rr_generate_stage(hyperim_graph g, const RRKey &key, const std::vector<RRTas
     HIM_CHECK(ws.sizes.reserve(sizeof(uint32_t) * std::max<uint64_t>(count, 1), s, false));
     HIM_CHECK(ws.roots.reserve(sizeof(uint32_t) * std::max<uint64_t>(count, 1), s, false));
     HIM_CHECK(ws.big_ids.reserve(sizeof(uint64_t) * std::max<uint64_t>(count, 1), s, false));
-    if (ws.stage.bytes < sizeof(uint32_t) * 4 * count)
-        HIM_CHECK(ws.stage.reserve(sizeof(uint32_t) * std::max<uint64_t>(4 * count, 1 << 20), s, false));
+    // stage sized from the members per id seen so far (a miss costs a re-run)
+    const uint64_t predicted = (uint64_t)(ws.members_per_id * 1.3 * (double)count) + 4 * count + (1u << 20);
+    if (ws.stage.bytes < sizeof(uint32_t) * predicted)
+        HIM_CHECK(ws.stage.reserve(sizeof(uint32_t) * predicted, s, false));
 
     unsigned long long *ctr = ws.counters.as<unsigned long long>();
     const size_t ndef_cap = std::max<uint64_t>(shape.slots - (uint64_t)shape.grid * kWavesPerWG, 1);
+    // launch groups no larger than the spare slots can absorb at the deferral
+    // rate seen so far (a set that finds no spare slot stays with its wave)
+    const double rate = std::max(ws.defer_rate * 1.25, 1.0 / 64.0);
+    const uint64_t chunk = std::max<uint64_t>((uint64_t)((double)ndef_cap / rate), 4096);
     for (int attempt = 0; attempt < 2; ++attempt) {
         HIM_HIP(hipMemsetAsync(ctr, 0, sizeof(unsigned long long) * kNumCtr, s));
         RRArgs a{};
@@ -921,19 +929,28 @@ int rr_generate_stage(hyperim_graph g, const RRKey &key, const std::vector<RRTas
         a.def_head = a.def_slot + ndef_cap;
         a.def_size = a.def_head + ndef_cap;
         a.items = ws.items.as<uint4>();
+        const uint64_t deferred_before = ws.deferred;
         if (form == 0) {
-            // every task in one launch group
-            a.ntasks = (uint32_t)tasks.size();
-            uint64_t acc = 0;
-            for (size_t t = 0; t < tasks.size(); ++t) {
-                acc += tasks[t].id_end - tasks[t].id_begin;
-                a.t_end[t] = acc;
-                a.t_id[t] = tasks[t].id_begin;
-                a.t_pool[t] = tasks[t].pool;
+            // the tasks back to back, cut into launch groups of at most `chunk` indices
+            for (uint64_t lo = 0; lo < count; lo += chunk) {
+                const uint64_t hi = std::min(count, lo + chunk);
+                a.ntasks = 0;
+                uint64_t tstart = 0;
+                for (const RRTask &t : tasks) {
+                    const uint64_t tn = t.id_end - t.id_begin;
+                    const uint64_t a0 = std::max(lo, tstart), a1 = std::min(hi, tstart + tn);
+                    if (a0 < a1) {
+                        a.t_id[a.ntasks] = t.id_begin + (a0 - tstart);
+                        a.t_pool[a.ntasks] = t.pool;
+                        a.t_end[a.ntasks] = a1 - lo;
+                        ++a.ntasks;
+                    }
+                    tstart += tn;
+                }
+                a.count = hi - lo;
+                a.out_base = lo;
+                HIM_CHECK(run_launch(g, a, shape, shape.grid, trace, s));
             }
-            a.count = acc;
-            a.out_base = 0;
-            HIM_CHECK(run_launch(g, a, shape, shape.grid, trace, s));
         } else {
             // plain form: one launch group per (task, ladder block, stratum)
             uint64_t task_base = 0;
@@ -957,9 +974,14 @@ int rr_generate_stage(hyperim_graph g, const RRKey &key, const std::vector<RRTas
         HIM_CHECK(read_ctr(s, ctr, kBump, &bump));
         HIM_CHECK(read_ctr(s, ctr, kBytesA, &ba));
         HIM_CHECK(read_ctr(s, ctr, kBytesB, &bb));
-        ws.bytes_light += ba;
-        ws.bytes_heavy += bb;
+        if (count) {
+            ws.members_per_id = (double)bump / (double)count;
+            ws.defer_rate = (double)(ws.deferred - deferred_before) / (double)count;
+        }
         if (bump <= ws.stage.bytes / sizeof(uint32_t)) {
+            // bytes of the run that produced the output (time counts every run)
+            ws.bytes_light += ba;
+            ws.bytes_heavy += bb;
             *total = bump;
             return HYPERIM_OK;
         }
