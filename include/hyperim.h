@@ -207,6 +207,26 @@ int hyperim_select_seeds(hyperim_graph g, uint32_t k, double eps, double ell, ui
                          uint32_t instance, const hyperim_options *opt, void *stream,
                          uint32_t *seeds, uint64_t *gains, hyperim_result *out);
 
+/* Execution parameters of RR generation (a schedule, not the method: every
+ * setting produces the same bytes).  Zero fields keep their defaults.
+ *   heavy:         a set whose next frontier batch holds a vertex with more
+ *                  hyperedges than this moves to the grid-wide phase (1024);
+ *   budget:        ... or once it has read this many incidences (16384);
+ *   chunk:         incidences per heavy-vertex work item (256);
+ *   seg:           light incidences per frontier-segment work item (512,
+ *                  raised to chunk if smaller);
+ *   prefilter_min: the grid-wide phase tests visited marks before coins in
+ *                  sets of at least this many members (4096);
+ *   steps_per_sync: grid-wide supersteps launched between host checks (8). */
+typedef struct {
+    uint32_t heavy, budget, chunk, seg, prefilter_min, steps_per_sync;
+    uint32_t reserved[2];
+} hyperim_tuning;
+
+/* Set / read the execution parameters of graph g (host-side values). */
+int hyperim_set_tuning(hyperim_graph g, const hyperim_tuning *t);
+int hyperim_get_tuning(hyperim_graph g, hyperim_tuning *t);
+
 void hyperim_pool_free(hyperim_pool pool);
 void hyperim_graph_free(hyperim_graph g);
 

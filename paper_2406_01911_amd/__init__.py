@@ -54,9 +54,17 @@ class _Result(C.Structure):
                 ("bytes_heavy", C.c_uint64)]
 
 
+class _Tuning(C.Structure):
+    _fields_ = [("heavy", C.c_uint32), ("budget", C.c_uint32), ("chunk", C.c_uint32), ("seg", C.c_uint32),
+                ("prefilter_min", C.c_uint32), ("steps_per_sync", C.c_uint32), ("reserved", C.c_uint32 * 2)]
+
+
+TUNING_FIELDS = ["heavy", "budget", "chunk", "seg", "prefilter_min", "steps_per_sync"]
+
 EXPORTS = ["hyperim_build_graph", "hyperim_stratify", "hyperim_graph_read", "hyperim_pool_create",
            "hyperim_generate_rr", "hyperim_pool_view", "hyperim_pool_read", "hyperim_pool_required",
            "hyperim_pool_reset", "hyperim_greedy", "hyperim_coverage", "hyperim_select_seeds",
+           "hyperim_set_tuning", "hyperim_get_tuning",
            "hyperim_pool_free", "hyperim_graph_free", "hyperim_strerror"]
 
 _lib = None
@@ -85,6 +93,8 @@ def load_library(path: str = LIB_PATH):
     L.hyperim_coverage.argtypes = [vp, vp, u64, vp, u32, vp, C.POINTER(u64)]
     L.hyperim_select_seeds.argtypes = [vp, u32, C.c_double, C.c_double, u64, u32, C.POINTER(_Options), vp, vp, vp,
                                        C.POINTER(_Result)]
+    L.hyperim_set_tuning.argtypes = [vp, C.POINTER(_Tuning)]
+    L.hyperim_get_tuning.argtypes = [vp, C.POINTER(_Tuning)]
     L.hyperim_pool_free.argtypes = [vp]
     L.hyperim_pool_free.restype = None
     L.hyperim_graph_free.argtypes = [vp]
@@ -136,6 +146,21 @@ class Graph:
         self.info = {"B": np.array(list(info.B), np.uint32), "sum_top": info.sum_top, "sum_deg": info.sum_deg,
                      "sum_l": info.sum_l, "alpha": info.alpha, "beta": info.beta, "theta_l": info.theta_l}
         return self.info
+
+    # hyperim_set_tuning / hyperim_get_tuning
+    def set_tuning(self, **kw):
+        t = _Tuning()
+        for k, v in kw.items():
+            if k not in TUNING_FIELDS:
+                raise KeyError(k)
+            setattr(t, k, int(v))
+        _check(_lib.hyperim_set_tuning(self._h, C.byref(t)))
+        return self.tuning()
+
+    def tuning(self) -> dict:
+        t = _Tuning()
+        _check(_lib.hyperim_get_tuning(self._h, C.byref(t)))
+        return {k: getattr(t, k) for k in TUNING_FIELDS}
 
     # hyperim_graph_read
     def read(self, strata: bool = True) -> dict:

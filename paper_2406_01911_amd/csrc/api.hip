@@ -551,6 +551,25 @@ int hyperim_select_seeds(hyperim_graph g, uint32_t k, double eps, double ell, ui
     return HYPERIM_OK;
 }
 
+int hyperim_set_tuning(hyperim_graph g, const hyperim_tuning *t) {
+    if (!g || !t) return HYPERIM_EINVAL;
+    hyperim_tuning &cur = g->rr.tune;
+    if (t->heavy) cur.heavy = t->heavy;
+    if (t->budget) cur.budget = t->budget;
+    if (t->chunk) cur.chunk = std::max<uint32_t>(t->chunk, 16);
+    if (t->seg) cur.seg = t->seg;
+    cur.seg = std::max(cur.seg, cur.chunk);
+    if (t->prefilter_min) cur.prefilter_min = t->prefilter_min;
+    if (t->steps_per_sync) cur.steps_per_sync = std::min<uint32_t>(t->steps_per_sync, 64);
+    return HYPERIM_OK;
+}
+
+int hyperim_get_tuning(hyperim_graph g, hyperim_tuning *t) {
+    if (!g || !t) return HYPERIM_EINVAL;
+    *t = g->rr.tune;
+    return HYPERIM_OK;
+}
+
 void hyperim_pool_free(hyperim_pool pool) {
     if (!pool) return;
     pool->off_b.release();

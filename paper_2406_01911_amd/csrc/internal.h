@@ -52,6 +52,7 @@ struct RRWorkspace {
     DevBuf def_u32;              // deferred sets: root, slot, head, size (4 uint32 arrays)
     DevBuf items;                // phase B work items (uint4)
     double ms_light = 0.0, ms_heavy = 0.0;   // device time of phase A / phase B kernels
+    hyperim_tuning tune{1024, 16384, 256, 512, 4096, 8, {0, 0}};  // execution parameters
     double members_per_id = 0.0;  // staged members per RR id in the last call (stage sizing)
     double defer_rate = 0.5;      // deferred sets per RR id in the last call (launch-group sizing)
     uint64_t supersteps = 0, deferred = 0;

@@ -50,15 +50,13 @@ constexpr uint32_t kSortMax = 1024;          // phase A: sets up to this size ar
 constexpr uint32_t kSortMaxWG = 4096;        // phase B: one workgroup sorts up to this size in LDS
 constexpr uint32_t kLdsBitmapWords = 1024;   // visited bitmap in LDS when |V| <= 32768
 constexpr uint32_t kBigSet = 4096;           // compaction: one workgroup per larger set
-constexpr uint32_t kHeavy = 1024;            // phase A defers a set on a vertex with more incidences
-constexpr uint64_t kBudget = 16384;          // phase A defers a set after this many incidences
-constexpr uint32_t kChunk = 256;             // phase B: incidences per heavy-vertex item
-constexpr uint32_t kSeg = 512;               // phase B: light incidences per queue segment item
 constexpr uint32_t kMaxTasks = 4;            // (pool, id range) tasks per launch
-constexpr uint32_t kItemCap = (1u << 22) + 64;   // phase B: work items per superstep (one vertex always fits)
-constexpr uint32_t kPrefilterMin = 4096;     // phase B: test visited marks before coins from this size
-constexpr int kStepsPerSync = 8;             // phase B supersteps launched between host checks
+constexpr uint32_t kItemCap = 1u << 22;      // phase B: work items per superstep
+constexpr uint32_t kMaxItemsPerVertex = 1u << 20;  // heavy chunks grow so one vertex fits a superstep
 constexpr uint64_t kSlotBudget = 48ull << 30; // bytes of slot lists + bitmaps
+// The remaining execution parameters (heavy-vertex threshold, per-set budget,
+// chunk and segment sizes, prefilter threshold, supersteps per sync) are
+// runtime values, see hyperim_tuning.
 
 // Counters (uint64 each) in the workspace counter block.
 // kItems and kItems + 1 alternate between supersteps: superstep s plans into
@@ -73,6 +71,7 @@ struct RRArgs {
     const uint32_t *__restrict__ thr;
     const uint32_t *__restrict__ P;
     uint32_t n, key0, key1, qlog, bm_words;
+    uint32_t heavy, budget, chunk, seg, prefilter_min;   // execution parameters
     // a launch covers up to kMaxTasks (pool, id range) tasks back to back:
     // launch index idx belongs to task t when t_end[t-1] <= idx < t_end[t]
     uint32_t ntasks;
@@ -251,10 +250,19 @@ __device__ __forceinline__ uint64_t expand(const RRArgs &a, WaveLds &L, uint64_t
             uint4 c = make_uint4(0u, 0u, 0u, 0u);
             if (need) c = philox4x32_10(coin_counter(j, hee, ve, pool, q), key);
             const uint32_t w[4] = {c.x, c.y, c.z, c.w};
+            bool live[4];
+            bool any_live = false;
+#pragma unroll
+            for (uint32_t t = 0; t < 4; ++t) {
+                live[t] = need && u[t] != ve && channel_live(w[t], the);
+                any_live |= live[t];
+            }
+            // with small probabilities most quads have no live channel at all
+            if (__ballot(any_live) == 0) continue;
 #pragma unroll
             for (uint32_t t = 0; t < 4; ++t) {
                 bool fresh = false;
-                if (need && u[t] != ve && channel_live(w[t], the)) {
+                if (live[t]) {
                     const uint32_t bit = 1u << (u[t] & 31);
                     fresh = (atomicOr(&bm[u[t] >> 5], bit) & bit) == 0u;
                 }
@@ -327,7 +335,7 @@ __global__ __launch_bounds__(kWG) void k_rr_light(RRArgs a) {
                 e0 = a.v_off[v];
                 d = a.v_off[v + 1] - e0;
             }
-            if (can_defer && (spent > kBudget || __ballot(d > kHeavy) != 0)) {
+            if (can_defer && (spent > a.budget || __ballot(d > a.heavy) != 0)) {
                 // hand the set over to phase B and continue with a fresh slot
                 uint32_t fresh_slot = 0;
                 if (lane == 0) fresh_slot = (uint32_t)atomicAdd(&a.ctr[kFreeNext], 1ull);
@@ -433,20 +441,23 @@ __global__ __launch_bounds__(kWG) void k_plan(RRArgs a, uint32_t ndef, uint32_t 
         const uint32_t *list = a.lists + (uint64_t)a.def_slot[d] * a.n;
         while (head < size) {
             uint32_t nb = min((uint32_t)kWave, size - head);
-            uint32_t v = 0, e0 = 0, deg = 0, hv = 0, light = 0;
+            uint32_t v = 0, e0 = 0, deg = 0, hv = 0, light = 0, cv = a.chunk;
             if (lane < nb) {
                 v = list[head + lane];
                 e0 = a.v_off[v];
                 deg = a.v_off[v + 1] - e0;
-                hv = deg > kChunk ? (deg + kChunk - 1u) / kChunk : 0u;
+                // a heavy vertex is cut into chunks of cv incidences, cv grown
+                // so that one vertex never needs more than kMaxItemsPerVertex
+                cv = max(a.chunk, (uint32_t)div_up(deg, kMaxItemsPerVertex));
+                hv = deg > a.chunk ? (uint32_t)div_up(deg, cv) : 0u;
                 light = hv ? 0u : deg;
             }
             // light vertices form segments of consecutive queue entries: a lane
             // belongs to segment floor(prefix of light incidences before it /
-            // kSeg); each light degree is <= kChunk <= kSeg, so segments have no
-            // gaps and hold fewer than kSeg + kChunk incidences
+            // seg); each light degree is <= chunk <= seg, so segments have no
+            // gaps and hold fewer than seg + chunk incidences
             const uint32_t lscan = wave_incl_scan(light);
-            const uint32_t seg = (lscan - light) / kSeg;
+            const uint32_t seg = (lscan - light) / a.seg;
             const uint32_t prev_seg = __shfl_up(seg, 1, kWave);
             const bool first = lane < nb && (lane == 0 || seg != prev_seg);
             uint64_t firsts = __ballot(first);
@@ -475,8 +486,8 @@ __global__ __launch_bounds__(kWG) void k_plan(RRArgs a, uint32_t ndef, uint32_t 
                 a.items[base + lane_rank(firsts)] = make_uint4(d, head + lane, min(next, nb) - lane, 0u);
             }
             for (uint32_t k = 0; k < hv; ++k) {
-                const uint32_t b0 = e0 + k * kChunk;
-                a.items[base + nseg + hscan - hv + k] = make_uint4(d | 0x80000000u, v, b0, min(b0 + kChunk, e0 + deg));
+                const uint32_t b0 = e0 + k * cv;
+                a.items[base + nseg + hscan - hv + k] = make_uint4(d | 0x80000000u, v, b0, min(b0 + cv, e0 + deg));
             }
             head += nb;
         }
@@ -492,7 +503,7 @@ __global__ __launch_bounds__(kWG) void k_expand(RRArgs a, uint32_t parity) {
     const uint64_t nitems = min(a.ctr[kItems + parity], (unsigned long long)kItemCap);
     if (blockIdx.x == 0 && threadIdx.x == 0) a.ctr[kItems + (parity ^ 1u)] = 0ull;   // next superstep's counter
     uint64_t bytes_done = 0;
-    // items have bounded cost (< kSeg + kChunk incidences), so a static strided
+    // items have bounded cost (< seg + chunk incidences), so a static strided
     // assignment balances well and needs no shared counter
     const uint64_t waves = (uint64_t)gridDim.x * kWavesPerWG;
     for (uint64_t it = (uint64_t)blockIdx.x * kWavesPerWG + wv; it < nitems; it += waves) {
@@ -507,14 +518,14 @@ __global__ __launch_bounds__(kWG) void k_expand(RRArgs a, uint32_t parity) {
         uint32_t pool;
         resolve(a, a.def_idx[d], &j, &pool);
         uint32_t *size_p = &a.def_size[d];
-        const bool prefilter = __hip_atomic_load(size_p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= kPrefilterMin;
+        const bool prefilter = __hip_atomic_load(size_p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= a.prefilter_min;
         uint32_t v = 0, e0 = 0, deg = 0;
         if (!heavy) {
             if (lane < item.z) {
                 v = list[item.y + lane];
                 e0 = a.v_off[v];
                 deg = a.v_off[v + 1] - e0;
-                if (deg > kChunk) deg = 0;   // expanded by its heavy items
+                if (deg > a.chunk) deg = 0;   // expanded by its heavy items
             }
             bytes_done += 20ull * item.z;
         } else if (lane == 0) {
@@ -821,7 +832,8 @@ int run_launch(hyperim_graph g, RRArgs &a, const LaunchShape &shape, uint32_t gr
     const uint32_t plan_grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(div_up(ndef, kWavesPerWG), 4096));
     // every superstep with items advances some queue head, and a set holds at
     // most n members, so n supersteps per set bound the loop
-    const uint64_t max_steps = (uint64_t)g->n * ndef + 2 * kStepsPerSync;
+    const int per_sync = (int)std::max<uint32_t>(ws.tune.steps_per_sync, 1);
+    const uint64_t max_steps = (uint64_t)g->n * ndef + 2 * (uint64_t)per_sync;
     uint64_t steps = 0;
     HIM_HIP(hipMemsetAsync(ctr + kItems, 0, 2 * sizeof(unsigned long long), s));
     for (;;) {
@@ -830,7 +842,7 @@ int run_launch(hyperim_graph g, RRArgs &a, const LaunchShape &shape, uint32_t gr
             return HYPERIM_EHIP;
         }
         HIM_HIP(hipEventRecord(ws.events[0], s));
-        const int batch = trace ? 1 : kStepsPerSync;
+        const int batch = trace ? 1 : per_sync;
         uint32_t parity = 0;
         for (int step = 0; step < batch; ++step) {
             parity = (uint32_t)((steps + step) & 1u);
@@ -913,6 +925,11 @@ int rr_generate_stage(hyperim_graph g, const RRKey &key, const std::vector<RRTas
         a.key1 = key.instance;
         a.qlog = key.qlog;
         a.bm_words = (g->n + 31u) / 32u;
+        a.heavy = ws.tune.heavy;
+        a.budget = ws.tune.budget;
+        a.chunk = ws.tune.chunk;
+        a.seg = std::max(ws.tune.seg, ws.tune.chunk);
+        a.prefilter_min = ws.tune.prefilter_min;
         a.ctr = ctr;
         a.lists = ws.lists.as<uint32_t>();
         a.bitmaps = ws.bitmaps.as<uint32_t>();
