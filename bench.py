@@ -42,6 +42,9 @@ def parse():
     ap.add_argument("--form", type=int, default=0, help="0 persistent launch per pool block, 1 plain per stratum")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU-baseline sample time")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="also run one device-to-device copy of this many MiB (reference kernel for "
+                         "scaling hardware byte counters)")
     return ap.parse_args()
 
 
@@ -94,6 +97,15 @@ def main():
         r = hy.select_seeds(g, w.k, w.eps, w.ell, seed=w.philox_seed, form=args.form, flags=flags, stream=stream)
         del g
         return r
+
+    if args.copy_calibration:
+        nbytes = args.copy_calibration << 20
+        src = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": nbytes}), file=sys.stderr, flush=True)
+        del src, dst
 
     for _ in range(args.warmup):
         step()

@@ -176,98 +176,139 @@ struct SharedAppend {
     }
 };
 
-// Levels 2 and 3 of a frontier expansion.  Each lane brings one vertex v with
-// the incidence range [e0, e0 + d) of v_he to expand (d = 0 for none); every
-// channel (he, u -> v) of those incidences is tested with its coin and newly
-// reached members go to `app`.  Returns the algorithmic bytes of the
-// incidences read (12 per incidence plus 4 per member position), wave-uniform.
+// Test the channels (he, u -> ve) at member positions [p0, p0 + cm) of one
+// hyperedge (cm <= 8, p0 a multiple of 8) in this lane: the coins are the words
+// of the two Philox blocks of quads p0/4 and p0/4 + 1.  Newly reached members
+// go to `app`.  Every lane of the wave must call it (inactive lanes with
+// active = false).
 template <bool kLds, class App>
+__device__ __forceinline__ void test_octet(const RRArgs &a, uint64_t j, uint32_t pool, uint2 key, uint32_t *bm,
+                                           bool prefilter, bool active, uint32_t he, uint32_t hb, uint32_t p0,
+                                           uint32_t cm, uint32_t ve, uint32_t the, App &app) {
+    uint32_t u[8];
+#pragma unroll
+    for (uint32_t t = 0; t < 8; ++t) u[t] = (active && t < cm) ? a.he_mem[hb + p0 + t] : ve;
+    uint32_t seen[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
+    if (prefilter) {
+        // all mark words in flight together (u[t] is always a vertex id)
+#pragma unroll
+        for (uint32_t t = 0; t < 8; ++t) seen[t] = bm_load<kLds>(bm, u[t] >> 5);
+    }
+    bool cand[8];
+    bool lo = false, hi = false;
+#pragma unroll
+    for (uint32_t t = 0; t < 8; ++t) {
+        cand[t] = u[t] != ve && !(seen[t] & (1u << (u[t] & 31)));
+        if (t < 4) lo |= cand[t];
+        else hi |= cand[t];
+    }
+    const uint64_t blo = __ballot(lo), bhi = __ballot(hi);
+    if ((blo | bhi) == 0) return;
+    uint4 c0 = make_uint4(0u, 0u, 0u, 0u), c1 = c0;
+    if (blo && lo) c0 = philox4x32_10(coin_counter(j, he, ve, pool, p0 >> 2), key);
+    if (bhi && hi) c1 = philox4x32_10(coin_counter(j, he, ve, pool, (p0 >> 2) + 1u), key);
+    const uint32_t w[8] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
+    bool live[8];
+    bool any_live = false;
+#pragma unroll
+    for (uint32_t t = 0; t < 8; ++t) {
+        live[t] = cand[t] && channel_live(w[t], the);
+        any_live |= live[t];
+    }
+    // with small probabilities most octets have no live channel at all
+    if (__ballot(any_live) == 0) return;
+#pragma unroll
+    for (uint32_t t = 0; t < 8; ++t) {
+        bool fresh = false;
+        if (live[t]) {
+            const uint32_t bit = 1u << (u[t] & 31);
+            fresh = (atomicOr(&bm[u[t] >> 5], bit) & bit) == 0u;
+        }
+        app.push(fresh, u[t]);
+    }
+}
+
+// Levels 2 and 3 of a frontier expansion.  Each lane brings one vertex v with
+// the incidence range [e0, e0 + d) of v_he to expand (d = 0 for none); with
+// kUniform all lanes pass the same v and e0 and d is the wave's incidence
+// count (one heavy vertex), which needs no owner search.  Every channel
+// (he, u -> v) of those incidences is tested with its coin and newly reached
+// members go to `app`.  Level 3 first tests the first 8 member positions of
+// each lane's own incidence, then spreads the remaining octets of the longer
+// hyperedges over the wave.  Returns the algorithmic bytes of the incidences
+// read (12 per incidence plus 4 per member position), wave-uniform.
+template <bool kLds, bool kUniform, class App>
 __device__ __forceinline__ uint64_t expand(const RRArgs &a, WaveLds &L, uint64_t j, uint32_t pool, uint2 key,
                                            uint32_t *bm, bool prefilter, uint32_t v, uint32_t e0, uint32_t d,
                                            App &app) {
     const uint32_t lane = lane_id();
-    const uint32_t dscan = wave_incl_scan(d);
-    const uint32_t D = wave_bcast(dscan, kWave - 1);
-    wave_sync();
-    L.fr_scan[lane] = dscan;
-    L.fr_v[lane] = v;
-    L.fr_e0[lane] = e0;
-    wave_sync();
+    uint32_t D = d;
+    uint32_t th_uniform = 0;
+    if constexpr (kUniform) {
+        th_uniform = a.thr[v];
+    } else {
+        const uint32_t dscan = wave_incl_scan(d);
+        D = wave_bcast(dscan, kWave - 1);
+        wave_sync();
+        L.fr_scan[lane] = dscan;
+        L.fr_v[lane] = v;
+        L.fr_e0[lane] = e0;
+        wave_sync();
+    }
     uint64_t bytes = 0;
     for (uint32_t base = 0; base < D; base += kWave) {
         // level 2: one incidence (v, he) per lane
         const uint32_t g = base + lane;
-        uint32_t he = 0, hb = 0, hs = 0, vv = 0, th = 0, nq = 0;
+        uint32_t he = 0, hb = 0, hs = 0, vv = v, th = th_uniform, no = 0;
         if (g < D) {
-            const uint32_t k = search64(L.fr_scan, g);
-            const uint32_t start = k ? L.fr_scan[k - 1] : 0u;
-            vv = L.fr_v[k];
-            he = a.v_he[L.fr_e0[k] + (g - start)];
+            if constexpr (kUniform) {
+                he = a.v_he[e0 + g];
+            } else {
+                const uint32_t k = search64(L.fr_scan, g);
+                const uint32_t start = k ? L.fr_scan[k - 1] : 0u;
+                vv = L.fr_v[k];
+                he = a.v_he[L.fr_e0[k] + (g - start)];
+                th = a.thr[vv];
+            }
             hb = a.he_off[he];
             hs = a.he_off[he + 1] - hb;
-            th = a.thr[vv];
-            nq = th ? (hs + 3u) >> 2 : 0u;   // threshold 0: no channel into vv is live
+            no = th ? (hs + 7u) >> 3 : 0u;   // threshold 0: no channel into vv is live
             bytes += 12u + 4u * hs;
         }
-        const uint32_t qscan = wave_incl_scan(nq);
-        const uint32_t Qn = wave_bcast(qscan, kWave - 1);
+        // level 3, first pass: octet 0 of the lane's own incidence
+        test_octet<kLds>(a, j, pool, key, bm, prefilter, no > 0, he, hb, 0u, min(8u, hs), vv, th, app);
+        // second pass: octets 1.. of the longer hyperedges, flattened over the wave
+        const uint32_t rem = no > 1 ? no - 1u : 0u;
+        if (__ballot(rem > 0) == 0) continue;
+        const uint32_t rscan = wave_incl_scan(rem);
+        const uint32_t R = wave_bcast(rscan, kWave - 1);
         wave_sync();
-        L.in_scan[lane] = qscan;
+        L.in_scan[lane] = rscan;
         L.in_he[lane] = he;
         L.in_hb[lane] = hb;
         L.in_hs[lane] = hs;
-        L.in_v[lane] = vv;
-        L.in_thr[lane] = th;
+        if constexpr (!kUniform) {
+            L.in_v[lane] = vv;
+            L.in_thr[lane] = th;
+        }
         wave_sync();
-        for (uint32_t qb = 0; qb < Qn; qb += kWave) {
-            // level 3: one quad of member positions per lane
+        for (uint32_t qb = 0; qb < R; qb += kWave) {
             const uint32_t qg = qb + lane;
-            uint32_t u[4] = {0u, 0u, 0u, 0u};
-            uint32_t ve = 0, hee = 0, q = 0, the = 0;
-            bool need = false;
-            if (qg < Qn) {
+            const bool active = qg < R;
+            uint32_t hee = 0, hbk = 0, p0 = 0, cm = 0, ve = v, the = th_uniform;
+            if (active) {
                 const uint32_t k = search64(L.in_scan, qg);
                 const uint32_t start = k ? L.in_scan[k - 1] : 0u;
-                q = qg - start;
+                p0 = (qg - start + 1u) * 8u;
                 hee = L.in_he[k];
-                ve = L.in_v[k];
-                the = L.in_thr[k];
-                const uint32_t hbk = L.in_hb[k], hsk = L.in_hs[k];
-                const uint32_t p0 = q * 4u;
-                const uint32_t cm = min(4u, hsk - p0);
-#pragma unroll
-                for (uint32_t t = 0; t < 4; ++t) u[t] = t < cm ? a.he_mem[hbk + p0 + t] : ve;
-                uint32_t seen[4] = {0u, 0u, 0u, 0u};
-                if (prefilter) {
-                    // all four mark words in flight together (u[t] is always a vertex id)
-#pragma unroll
-                    for (uint32_t t = 0; t < 4; ++t) seen[t] = bm_load<kLds>(bm, u[t] >> 5);
+                hbk = L.in_hb[k];
+                cm = min(8u, L.in_hs[k] - p0);
+                if constexpr (!kUniform) {
+                    ve = L.in_v[k];
+                    the = L.in_thr[k];
                 }
-#pragma unroll
-                for (uint32_t t = 0; t < 4; ++t) need |= u[t] != ve && !(seen[t] & (1u << (u[t] & 31)));
             }
-            if (__ballot(need) == 0) continue;
-            uint4 c = make_uint4(0u, 0u, 0u, 0u);
-            if (need) c = philox4x32_10(coin_counter(j, hee, ve, pool, q), key);
-            const uint32_t w[4] = {c.x, c.y, c.z, c.w};
-            bool live[4];
-            bool any_live = false;
-#pragma unroll
-            for (uint32_t t = 0; t < 4; ++t) {
-                live[t] = need && u[t] != ve && channel_live(w[t], the);
-                any_live |= live[t];
-            }
-            // with small probabilities most quads have no live channel at all
-            if (__ballot(any_live) == 0) continue;
-#pragma unroll
-            for (uint32_t t = 0; t < 4; ++t) {
-                bool fresh = false;
-                if (live[t]) {
-                    const uint32_t bit = 1u << (u[t] & 31);
-                    fresh = (atomicOr(&bm[u[t] >> 5], bit) & bit) == 0u;
-                }
-                app.push(fresh, u[t]);
-            }
+            test_octet<kLds>(a, j, pool, key, bm, prefilter, active, hee, hbk, p0, cm, ve, the, app);
         }
     }
     wave_sync();
@@ -360,7 +401,7 @@ __global__ __launch_bounds__(kWG) void k_rr_light(RRArgs a) {
             head += nb;
             spent += wave_bcast(wave_incl_scan(d), kWave - 1);
             bytes_done += 20ull * nb;
-            bytes_done += expand<kLdsBitmap>(a, L, j, pool, key, bm, false, v, e0, d, app);
+            bytes_done += expand<kLdsBitmap, false>(a, L, j, pool, key, bm, false, v, e0, d, app);
         }
         if (deferred) continue;
         const uint32_t size = app.size;
@@ -519,8 +560,9 @@ __global__ __launch_bounds__(kWG) void k_expand(RRArgs a, uint32_t parity) {
         resolve(a, a.def_idx[d], &j, &pool);
         uint32_t *size_p = &a.def_size[d];
         const bool prefilter = __hip_atomic_load(size_p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= a.prefilter_min;
-        uint32_t v = 0, e0 = 0, deg = 0;
+        SharedAppend app{list, size_p, a.n};
         if (!heavy) {
+            uint32_t v = 0, e0 = 0, deg = 0;
             if (lane < item.z) {
                 v = list[item.y + lane];
                 e0 = a.v_off[v];
@@ -528,13 +570,11 @@ __global__ __launch_bounds__(kWG) void k_expand(RRArgs a, uint32_t parity) {
                 if (deg > a.chunk) deg = 0;   // expanded by its heavy items
             }
             bytes_done += 20ull * item.z;
-        } else if (lane == 0) {
-            v = item.y;
-            e0 = item.z;
-            deg = item.w - item.z;
+            bytes_done += expand<false, false>(a, L, j, pool, key, bm, prefilter, v, e0, deg, app);
+        } else {
+            // one heavy vertex: incidences [item.z, item.w) of vertex item.y
+            bytes_done += expand<false, true>(a, L, j, pool, key, bm, prefilter, item.y, item.z, item.w - item.z, app);
         }
-        SharedAppend app{list, size_p, a.n};
-        bytes_done += expand<false>(a, L, j, pool, key, bm, prefilter, v, e0, deg, app);
     }
     if (lane == 0 && bytes_done) atomicAdd(&a.ctr[kBytesB], bytes_done);
 }
