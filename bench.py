@@ -30,6 +30,8 @@ WORKLOAD_TEXT = {
            "k=50 eps=0.1 ell=1",
     "large": "|V|=1e6 |HE|=2e6 sizes power-law(2.2) on [2,200], Zipf(1.1) members, IC p=0.01, "
              "k=100 eps=0.1 ell=1",
+    "multi": "64 instances: |V| log-uniform in [1e4,5e5], |HE|=2|V|, sizes power-law(2.5) on [2,100], "
+             "uniform members, IC p~U[0.005,0.05], k~U{10..200}, eps in {0.1,0.2}, ell=1, instance id i",
 }
 
 
@@ -40,6 +42,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="mid", choices=sorted(WORKLOAD_TEXT))
     ap.add_argument("--form", type=int, default=0, help="0 persistent launch per pool block, 1 plain per stratum")
+    ap.add_argument("--plain-steps", type=int, default=-1,
+                    help="steps of the plain per-stratum form timed for comparison (-1: same as --steps on "
+                         "tiny/mid/multi, 0 on large)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU-baseline sample time")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -84,19 +89,42 @@ def main():
 
     hy.load_library()
     torch.cuda.set_device(0)
-    w = hypergen.workload(args.workload)
-    hg = w.build()
-    dev_off = torch.from_numpy(hg.he_off.view(np.int32)).cuda()
-    dev_mem = torch.from_numpy(hg.he_mem.view(np.int32)).cuda()
     stream = torch.cuda.current_stream()
+    if args.workload != "multi":
+        w = hypergen.workload(args.workload)
+        hg = w.build()
+        dev_off = torch.from_numpy(hg.he_off.view(np.int32)).cuda()
+        dev_mem = torch.from_numpy(hg.he_mem.view(np.int32)).cuda()
+
+    if args.workload == "multi":
+        ws = hypergen.multi_instance_workloads(64)
+        hgs = [w.build() for w in ws]
+        dev = [(torch.from_numpy(h.he_off.view(np.int32)).cuda(), torch.from_numpy(h.he_mem.view(np.int32)).cuda())
+               for h in hgs]
+    else:
+        ws = [w]
+        hgs = [hg]
+        dev = [(dev_off, dev_mem)]
     torch.cuda.synchronize()
 
-    def step(flags=0):
-        g = hy.build_graph(hg.n, dev_off, dev_mem, w.model, w.p, stream=stream)
-        g.stratify(stream=stream)
-        r = hy.select_seeds(g, w.k, w.eps, w.ell, seed=w.philox_seed, form=args.form, flags=flags, stream=stream)
-        del g
-        return r
+    def step(flags=0, form=args.form):
+        """One query step: build + stratify every graph, then seed selection
+        (one query, or all instances batched; form 1 runs them one by one in
+        the plain per-stratum form)."""
+        gs = []
+        for h, (o, m), wl in zip(hgs, dev, ws):
+            g = hy.build_graph(h.n, o, m, wl.model, wl.p, stream=stream)
+            g.stratify(stream=stream)
+            gs.append(g)
+        if args.workload != "multi":
+            return [hy.select_seeds(gs[0], w.k, w.eps, w.ell, seed=w.philox_seed, form=form, flags=flags,
+                                    stream=stream)]
+        if form == 0:
+            return hy.select_seeds_batch([dict(graph=g, k=wl.k, eps=wl.eps, ell=wl.ell, seed=wl.philox_seed,
+                                               instance=i) for i, (g, wl) in enumerate(zip(gs, ws))],
+                                         flags=flags, stream=stream)
+        return [hy.select_seeds(g, wl.k, wl.eps, wl.ell, seed=wl.philox_seed, instance=i, form=1, flags=flags,
+                                stream=stream) for i, (g, wl) in enumerate(zip(gs, ws))]
 
     if args.copy_calibration:
         nbytes = args.copy_calibration << 20
@@ -107,40 +135,61 @@ def main():
         print(json.dumps({"copy_calibration_bytes": nbytes}), file=sys.stderr, flush=True)
         del src, dst
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    results = []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        results.append(step())
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    # identical query with the incidence / byte counters switched on (untimed)
+    def timed(steps, warmup, form):
+        for _ in range(warmup):
+            step(form=form)
+        torch.cuda.synchronize()
+        out = []
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            out.append(step(form=form))
+        torch.cuda.synchronize()
+        return out, time.perf_counter() - t0
+
+    results, elapsed = timed(args.steps, args.warmup, args.form)
+    print(f"[bench] {args.steps} steps of form {args.form}: {elapsed:.3f} s", file=sys.stderr, flush=True)
+    plain_steps = args.plain_steps if args.plain_steps >= 0 else (0 if args.workload == "large" else args.steps)
+    plain = None
+    if plain_steps and args.form == 0:
+        pres, pel = timed(plain_steps, 1, 1)
+        for a, b in zip(pres[-1], results[-1]):
+            assert np.array_equal(a["seeds"], b["seeds"]) and a["theta"] == b["theta"]
+        plain = {"form": "plain per-stratum launches, one query at a time", "steps": plain_steps,
+                 "ms_per_step": 1000.0 * pel / plain_steps}
+        print(f"[bench] {plain_steps} steps of the plain form: {pel:.3f} s", file=sys.stderr, flush=True)
+    # identical step with the incidence / byte counters switched on (untimed)
     meas = step(flags=hy.FLAG_INCIDENCES)
     last = results[-1]
-    assert np.array_equal(meas["seeds"], last["seeds"]) and meas["theta"] == last["theta"]
+    for a, b in zip(meas, last):
+        assert np.array_equal(a["seeds"], b["seeds"]) and a["theta"] == b["theta"]
+    # the query that ran every round took part in every shared launch
+    lead = max(range(len(last)), key=lambda i: last[i]["rounds"])
+
+    def shared(rs, key):
+        return float(np.mean([r[lead][key] for r in rs]))
 
     ms_per_step = 1000.0 * elapsed / args.steps
-    rr_sets_per_step = 2 * last["theta"]
+    rr_sets_per_step = sum(2 * r["theta"] for r in last)
     value = rr_sets_per_step * args.steps / elapsed
-    inc_per_s = meas["incidences"] * args.steps / elapsed
-    bfs_ms = float(np.mean([r["ms_bfs"] for r in results]))
-    ms_light = float(np.mean([r["ms_light"] for r in results]))
-    ms_heavy = float(np.mean([r["ms_heavy"] for r in results]))
-    launches = last["bfs_launches"]
-    alg_bytes = meas["alg_bytes"]
+    incidences = sum(r["incidences"] for r in meas)
+    inc_per_s = incidences * args.steps / elapsed
+    bfs_ms = shared(results, "ms_bfs")
+    ms_light = shared(results, "ms_light")
+    ms_heavy = shared(results, "ms_heavy")
+    launches = last[lead]["bfs_launches"]
+    alg_bytes = sum(r["alg_bytes"] for r in meas)
+    bytes_light, bytes_heavy = meas[lead]["bytes_light"], meas[lead]["bytes_heavy"]
     # the kernels count the bytes of every expansion they perform; together
     # they must equal the total recomputed from the output sets
-    assert meas["bytes_light"] + meas["bytes_heavy"] == alg_bytes, (meas["bytes_light"], meas["bytes_heavy"], alg_bytes)
+    assert bytes_light + bytes_heavy == alg_bytes, (bytes_light, bytes_heavy, alg_bytes)
     achieved = alg_bytes / (bfs_ms * 1e-3) / 1e9 if bfs_ms > 0 else 0.0
     phases = {
-        "per_set_phase": {"kernel": "k_rr_light", "ms": ms_light, "alg_bytes": meas["bytes_light"],
-                          "GBps": meas["bytes_light"] / (ms_light * 1e-3) / 1e9 if ms_light > 0 else 0.0},
+        "per_set_phase": {"kernel": "k_rr_light", "ms": ms_light, "alg_bytes": bytes_light,
+                          "GBps": bytes_light / (ms_light * 1e-3) / 1e9 if ms_light > 0 else 0.0},
         "grid_wide_phase": {"kernels": "k_plan + k_expand + k_finish", "ms": ms_heavy,
-                            "alg_bytes": meas["bytes_heavy"], "deferred_sets": meas["deferred"],
-                            "supersteps": meas["supersteps"],
-                            "GBps": meas["bytes_heavy"] / (ms_heavy * 1e-3) / 1e9 if ms_heavy > 0 else 0.0},
+                            "alg_bytes": bytes_heavy, "deferred_sets": meas[lead]["deferred"],
+                            "supersteps": meas[lead]["supersteps"],
+                            "GBps": bytes_heavy / (ms_heavy * 1e-3) / 1e9 if ms_heavy > 0 else 0.0},
     }
     line = {
         "metric": "RR sets/s",
@@ -160,11 +209,11 @@ def main():
                    "parallelism": "single-gpu"},
         "incidences_per_s": inc_per_s,
         "time_to_seed_set_ms": ms_per_step,
-        "theta": last["theta"],
-        "rounds": last["rounds"],
-        "spread": last["spread"],
-        "ms_rr": float(np.mean([r["ms_rr"] for r in results])),
-        "ms_greedy": float(np.mean([r["ms_greedy"] for r in results])),
+        "theta": [r["theta"] for r in last] if len(last) > 1 else last[0]["theta"],
+        "rounds": max(r["rounds"] for r in last),
+        "spread": [r["spread"] for r in last] if len(last) > 1 else last[0]["spread"],
+        "ms_rr": shared(results, "ms_rr"),
+        "ms_greedy": float(np.mean([sum(q["ms_greedy"] for q in r) for r in results])),
         "rr_phases": phases,
         "roofline": {
             "kernel": "RR generation (k_rr_light, k_plan, k_expand, k_finish)",
@@ -179,8 +228,11 @@ def main():
             "launches_per_step": launches,
         },
     }
+    if plain is not None:
+        plain["batched_speedup"] = plain["ms_per_step"] / ms_per_step
+        line["plain_form"] = plain
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(hg, w, args.cpu_seconds)
+        line["cpu_baseline"] = cpu_baseline(hgs[0], ws[0], args.cpu_seconds)
     print(json.dumps(line), flush=True)
 
 

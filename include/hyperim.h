@@ -19,7 +19,8 @@
  *   - vertex ids are uint32 in [0, n); hyperedge ids uint32 in [0, m);
  *     n, m < 2^32 - 1 and the number of incidences nnz = he_off[m] < 2^32;
  *   - distinct handles may be used from different threads; one handle must
- *     not be used by two threads at once.
+ *     not be used by two threads at once (RR generation on one device is
+ *     serialised internally: it shares that device's workspace).
  */
 #ifndef HYPERIM_H
 #define HYPERIM_H
@@ -37,6 +38,7 @@ extern "C" {
 #define HYPERIM_ECAPACITY (-3)  /* caller-provided pool buffer too small        */
 #define HYPERIM_ESTATE (-4)     /* call out of order (e.g. before stratify)     */
 #define HYPERIM_EHIP (-5)       /* HIP runtime error (see hyperim_strerror)     */
+#define HYPERIM_PENDING 1       /* hyperim_session_poll: query not finished yet */
 
 #define HYPERIM_MODEL_CONST 0u  /* every channel into v live with probability p */
 #define HYPERIM_MODEL_WC 1u     /* weighted cascade: p_v = 1 / c(v)             */
@@ -44,6 +46,7 @@ extern "C" {
 
 typedef struct hyperim_graph_s *hyperim_graph;
 typedef struct hyperim_pool_s *hyperim_pool;
+typedef struct hyperim_session_s *hyperim_session;
 
 /* Independent-cascade channel probabilities (Section 2.1, "Cascade models",
  * IC).  Every hyperedge he and every ordered pair u != v of its members is
@@ -207,6 +210,81 @@ int hyperim_select_seeds(hyperim_graph g, uint32_t k, double eps, double ell, ui
                          uint32_t instance, const hyperim_options *opt, void *stream,
                          uint32_t *seeds, uint64_t *gains, hyperim_result *out);
 
+/* One influence-maximization query (Definition 1's input plus the sampling
+ * key): a stratified graph on the current device, k, eps, ell, and the
+ * Philox key (seed < 2^32, instance). */
+typedef struct {
+    hyperim_graph graph;
+    uint32_t k;
+    uint32_t instance;
+    double eps, ell;
+    uint64_t seed;
+} hyperim_query;
+
+/* hyperim_select_seeds for `count` queries at once, on one or several graphs.
+ * Round i of every unfinished query runs together: the RR sets that all of
+ * them need for the round are generated in shared launches (all strata, both
+ * pools, all instances), then each query takes its greedy step and bound test.
+ * Queries with the same graph and key share their pools.  Every query's
+ * seeds, gains and result fields other than the timings equal those of
+ * hyperim_select_seeds on that query alone; timings cover the shared launches
+ * the query took part in.  seeds and gains (may be NULL) are host arrays
+ * holding query 0's k_0 entries, then query 1's, and so on; results[count]
+ * and status[count] may be NULL.  Returns HYPERIM_OK when every query
+ * succeeded, else the first failing query's status (status[] tells which);
+ * a malformed query (as for hyperim_select_seeds) fails the whole call with
+ * HYPERIM_EINVAL before any work. */
+int hyperim_select_seeds_batch(const hyperim_query *queries, uint32_t count, const hyperim_options *opt,
+                               void *stream, uint32_t *seeds, uint64_t *gains, hyperim_result *results,
+                               int *status);
+
+/* Serving session: queries are submitted at any time and advanced together,
+ * one doubling round of every admitted query per hyperim_session_step
+ * (continuous batching: a query submitted while others run joins at the next
+ * step).  RR pools stay resident, keyed by (graph, seed, instance), so a
+ * later query with the same key reuses the prefix already generated.
+ * Admission (at each step, in submission order) keeps the device bytes of
+ * the graphs in use, the resident pools, the greedy workspaces and the RR
+ * workspace within hbm_budget (0 = the device's memory less 8 GiB), using a
+ * learned members-per-RR-set estimate; idle pools are evicted least recently
+ * used first; a running query whose next round does not fit waits; a query
+ * that cannot fit even alone fails with HYPERIM_ECAPACITY.  Results are those
+ * of hyperim_select_seeds on the query alone.  `opt` applies to every query
+ * (theta_fixed, form, qlog, max_entries, flags).  A session handle must not
+ * be used by two threads at once; graphs must outlive their use by the
+ * session (hyperim_session_drop releases a graph's pools). */
+typedef struct {
+    uint64_t submitted, admitted, finished, failed;  /* totals since creation       */
+    uint32_t active, waiting;   /* queries admitted and running / not yet admitted */
+    uint64_t steps;             /* hyperim_session_step calls                      */
+    uint64_t ran_last;          /* queries advanced by the last step               */
+    size_t bytes_resident;      /* graphs in use + pools + greedy + RR workspace  */
+    size_t hbm_budget;
+} hyperim_session_stats;
+
+int hyperim_session_create(size_t hbm_budget, const hyperim_options *opt, void *stream, hyperim_session *out);
+/* Queue a query (validated as for hyperim_select_seeds); *ticket names it. */
+int hyperim_session_submit(hyperim_session s, const hyperim_query *q, uint64_t *ticket);
+/* Admit what fits and advance every admitted query by one round; `out` may
+ * be NULL.  Returns a HIP error if the device work failed (then the session's
+ * queries of that step fail). */
+int hyperim_session_step(hyperim_session s, hyperim_session_stats *out);
+/* HYPERIM_PENDING while the query runs or waits; else its status, with
+ * seeds[k], gains[k] (may be NULL) and *out (may be NULL) filled on
+ * HYPERIM_OK.  A finished ticket is forgotten once polled. */
+int hyperim_session_poll(hyperim_session s, uint64_t ticket, uint32_t *seeds, uint64_t *gains,
+                         hyperim_result *out);
+/* Release the resident pools of graph g (HYPERIM_ESTATE while a query on g
+ * is running or waiting). */
+int hyperim_session_drop(hyperim_session s, hyperim_graph g);
+int hyperim_session_stats_get(hyperim_session s, hyperim_session_stats *out);
+void hyperim_session_free(hyperim_session s);
+
+/* The RR-generation workspace is shared by every graph of a device and kept
+ * between calls: its current size on the current device, and its release. */
+int hyperim_workspace_info(size_t *bytes);
+int hyperim_workspace_release(void);
+
 /* Execution parameters of RR generation (a schedule, not the method: every
  * setting produces the same bytes).  Zero fields keep their defaults.
  *   heavy:         a set whose next frontier batch holds a vertex with more
@@ -223,7 +301,8 @@ typedef struct {
     uint32_t reserved[2];
 } hyperim_tuning;
 
-/* Set / read the execution parameters of graph g (host-side values). */
+/* Set / read the execution parameters of graph g (host-side values).  A
+ * launch that covers several graphs uses those of its first task's graph. */
 int hyperim_set_tuning(hyperim_graph g, const hyperim_tuning *t);
 int hyperim_get_tuning(hyperim_graph g, hyperim_tuning *t);
 

@@ -18,6 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhyperim.so")
 
 OK, EINVAL, ENOMEM, ECAPACITY, ESTATE, EHIP = 0, -1, -2, -3, -4, -5
+PENDING = 1
 MODEL_CONST, MODEL_WC = 0, 1
 NSTRATA = 8
 FLAG_INCIDENCES = 1
@@ -59,11 +60,25 @@ class _Tuning(C.Structure):
                 ("prefilter_min", C.c_uint32), ("steps_per_sync", C.c_uint32), ("reserved", C.c_uint32 * 2)]
 
 
+class _Query(C.Structure):
+    _fields_ = [("graph", C.c_void_p), ("k", C.c_uint32), ("instance", C.c_uint32), ("eps", C.c_double),
+                ("ell", C.c_double), ("seed", C.c_uint64)]
+
+
+class _SessionStats(C.Structure):
+    _fields_ = [("submitted", C.c_uint64), ("admitted", C.c_uint64), ("finished", C.c_uint64),
+                ("failed", C.c_uint64), ("active", C.c_uint32), ("waiting", C.c_uint32), ("steps", C.c_uint64),
+                ("ran_last", C.c_uint64), ("bytes_resident", C.c_size_t), ("hbm_budget", C.c_size_t)]
+
+
 TUNING_FIELDS = ["heavy", "budget", "chunk", "seg", "prefilter_min", "steps_per_sync"]
 
 EXPORTS = ["hyperim_build_graph", "hyperim_stratify", "hyperim_graph_read", "hyperim_pool_create",
            "hyperim_generate_rr", "hyperim_pool_view", "hyperim_pool_read", "hyperim_pool_required",
            "hyperim_pool_reset", "hyperim_greedy", "hyperim_coverage", "hyperim_select_seeds",
+           "hyperim_select_seeds_batch", "hyperim_session_create", "hyperim_session_submit",
+           "hyperim_session_step", "hyperim_session_poll", "hyperim_session_drop", "hyperim_session_stats_get",
+           "hyperim_session_free", "hyperim_workspace_info", "hyperim_workspace_release",
            "hyperim_set_tuning", "hyperim_get_tuning",
            "hyperim_pool_free", "hyperim_graph_free", "hyperim_strerror"]
 
@@ -93,6 +108,18 @@ def load_library(path: str = LIB_PATH):
     L.hyperim_coverage.argtypes = [vp, vp, u64, vp, u32, vp, C.POINTER(u64)]
     L.hyperim_select_seeds.argtypes = [vp, u32, C.c_double, C.c_double, u64, u32, C.POINTER(_Options), vp, vp, vp,
                                        C.POINTER(_Result)]
+    L.hyperim_select_seeds_batch.argtypes = [C.POINTER(_Query), u32, C.POINTER(_Options), vp, vp, vp,
+                                             C.POINTER(_Result), C.POINTER(i32)]
+    L.hyperim_session_create.argtypes = [C.c_size_t, C.POINTER(_Options), vp, C.POINTER(vp)]
+    L.hyperim_session_submit.argtypes = [vp, C.POINTER(_Query), C.POINTER(u64)]
+    L.hyperim_session_step.argtypes = [vp, C.POINTER(_SessionStats)]
+    L.hyperim_session_poll.argtypes = [vp, u64, vp, vp, C.POINTER(_Result)]
+    L.hyperim_session_drop.argtypes = [vp, vp]
+    L.hyperim_session_stats_get.argtypes = [vp, C.POINTER(_SessionStats)]
+    L.hyperim_session_free.argtypes = [vp]
+    L.hyperim_session_free.restype = None
+    L.hyperim_workspace_info.argtypes = [C.POINTER(C.c_size_t)]
+    L.hyperim_workspace_release.argtypes = []
     L.hyperim_set_tuning.argtypes = [vp, C.POINTER(_Tuning)]
     L.hyperim_get_tuning.argtypes = [vp, C.POINTER(_Tuning)]
     L.hyperim_pool_free.argtypes = [vp]
@@ -280,3 +307,122 @@ def select_seeds(g: Graph, k: int, eps: float, ell: float, seed: int = 0, instan
     out["seeds"] = seeds
     out["gains"] = gains
     return out
+
+
+def _result_dict(res: _Result) -> dict:
+    return {f: getattr(res, f) for f, _ in _Result._fields_}
+
+
+def _query(q) -> _Query:
+    """q: dict or tuple (graph, k, eps, ell, seed, instance)."""
+    if isinstance(q, dict):
+        g, k, eps, ell = q["graph"], q["k"], q["eps"], q.get("ell", 1.0)
+        seed, inst = q.get("seed", 0), q.get("instance", 0)
+    else:
+        g, k, eps, ell, seed, inst = q
+    return _Query(g._h, int(k), int(inst), float(eps), float(ell), int(seed))
+
+
+def select_seeds_batch(queries, qlog: int = 0, form: int = 0, theta_fixed: int = 0, max_entries: int = 0,
+                       flags: int = 0, stream=None, raise_on_error: bool = True) -> list:
+    """hyperim_select_seeds_batch: queries answered together (shared RR launches).
+
+    Each query is a dict {graph, k, eps, ell, seed, instance}; returns one dict
+    per query (seeds, gains, result fields, status)."""
+    qs = [_query(q) for q in queries]
+    arr = (_Query * max(len(qs), 1))(*qs)
+    ks = [q.k for q in qs]
+    seeds = np.zeros(max(sum(ks), 1), np.uint32)
+    gains = np.zeros(max(sum(ks), 1), np.uint64)
+    res = (_Result * max(len(qs), 1))()
+    status = (C.c_int * max(len(qs), 1))()
+    opt = _Options(qlog, form, theta_fixed, max_entries, flags, 0)
+    rc = _lib.hyperim_select_seeds_batch(arr, len(qs), C.byref(opt), _stream(stream), _ptr(seeds), _ptr(gains),
+                                         res, status)
+    if raise_on_error:
+        _check(rc)
+    out, at = [], 0
+    for i, k in enumerate(ks):
+        d = _result_dict(res[i])
+        d["seeds"] = seeds[at:at + k].copy()
+        d["gains"] = gains[at:at + k].copy()
+        d["status"] = status[i]
+        out.append(d)
+        at += k
+    return out
+
+
+class Session:
+    """Serving session (hyperim_session_*): submit queries at any time, step
+    to advance every admitted query by one round, poll for results."""
+
+    def __init__(self, hbm_budget: int = 0, qlog: int = 0, form: int = 0, theta_fixed: int = 0,
+                 max_entries: int = 0, flags: int = 0, stream=None):
+        load_library()
+        opt = _Options(qlog, form, theta_fixed, max_entries, flags, 0)
+        h = C.c_void_p()
+        _check(_lib.hyperim_session_create(int(hbm_budget), C.byref(opt), _stream(stream), C.byref(h)))
+        self._h = h
+        self._k = {}
+        self._graphs = {}   # keep graphs alive while the session may hold their pools
+
+    def __del__(self):
+        self.close()
+
+    def close(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.hyperim_session_free(self._h)
+            self._h = None
+            self._graphs = {}
+
+    def submit(self, graph: Graph, k: int, eps: float, ell: float = 1.0, seed: int = 0, instance: int = 0) -> int:
+        q = _Query(graph._h, int(k), int(instance), float(eps), float(ell), int(seed))
+        t = C.c_uint64()
+        _check(_lib.hyperim_session_submit(self._h, C.byref(q), C.byref(t)))
+        self._k[t.value] = int(k)
+        self._graphs[id(graph)] = graph
+        return t.value
+
+    def step(self) -> dict:
+        st = _SessionStats()
+        _check(_lib.hyperim_session_step(self._h, C.byref(st)))
+        return {f: getattr(st, f) for f, _ in _SessionStats._fields_}
+
+    def stats(self) -> dict:
+        st = _SessionStats()
+        _check(_lib.hyperim_session_stats_get(self._h, C.byref(st)))
+        return {f: getattr(st, f) for f, _ in _SessionStats._fields_}
+
+    def poll(self, ticket: int):
+        """None while pending; else the result dict (raises on a failed query)."""
+        k = self._k[ticket]
+        seeds = np.zeros(k, np.uint32)
+        gains = np.zeros(k, np.uint64)
+        res = _Result()
+        rc = _lib.hyperim_session_poll(self._h, ticket, _ptr(seeds), _ptr(gains), C.byref(res))
+        if rc == PENDING:
+            return None
+        del self._k[ticket]
+        _check(rc)
+        d = _result_dict(res)
+        d["seeds"] = seeds
+        d["gains"] = gains
+        return d
+
+    def drop(self, graph: Graph):
+        _check(_lib.hyperim_session_drop(self._h, graph._h))
+        self._graphs.pop(id(graph), None)
+
+
+def workspace_bytes() -> int:
+    """hyperim_workspace_info: bytes of the current device's RR workspace."""
+    load_library()
+    b = C.c_size_t()
+    _check(_lib.hyperim_workspace_info(C.byref(b)))
+    return b.value
+
+
+def workspace_release():
+    """hyperim_workspace_release: free the current device's RR workspace."""
+    load_library()
+    _check(_lib.hyperim_workspace_release())

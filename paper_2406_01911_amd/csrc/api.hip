@@ -1,11 +1,11 @@
 // C ABI of libhyperim (declared in include/hyperim.h): handles, argument
-// validation, pool storage, the sample-size schedule and the HyperIM_BRR loop
-// (Algorithm 4) that drives the device kernels.
+// validation, pool storage, the per-device RR workspace and the single-call
+// entry points.  The HyperIM_BRR loop (Algorithm 4) lives in query.hip.
 #include <hip/hip_runtime.h>
 
-#include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -17,6 +17,7 @@ namespace hyperim {
 static thread_local std::string g_detail;
 
 void set_error_detail(const std::string &msg) { g_detail = msg; }
+void clear_error_detail() { g_detail.clear(); }
 
 int DevBuf::reserve(size_t need, hipStream_t s, bool keep) {
     if (need <= bytes && ptr) return HYPERIM_OK;
@@ -84,23 +85,71 @@ int pool_reserve(hyperim_pool p, uint64_t ids, uint64_t entries, hipStream_t s) 
 }
 
 
+// Per-device RR workspace (created on first use, kept until the process ends
+// or hyperim_workspace_release).
 namespace {
+struct DevCtx {
+    std::mutex mu;
+    RRWorkspace ws;
+};
+constexpr int kMaxDevices = 256;
+std::mutex g_ctx_mu;
+DevCtx *g_ctx[kMaxDevices];
 
-constexpr uint64_t kMaxIds = 1ull << 39;   // RR ids use 39 bits of the coin counter
+DevCtx *device_ctx(int device) {
+    std::lock_guard<std::mutex> l(g_ctx_mu);
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    if (!g_ctx[device]) g_ctx[device] = new DevCtx();
+    return g_ctx[device];
+}
+}  // namespace
 
-hipStream_t as_stream(void *s) { return static_cast<hipStream_t>(s); }
+RRWorkspaceLock::RRWorkspaceLock(int device) {
+    DevCtx *c = device_ctx(device);
+    c->mu.lock();
+    ws = &c->ws;
+    lock = c;
+}
+
+RRWorkspaceLock::~RRWorkspaceLock() { static_cast<DevCtx *>(lock)->mu.unlock(); }
+
+size_t RRWorkspace::bytes() const {
+    size_t b = 0;
+    for (const DevBuf *x : {&lists, &bitmaps, &def_idx, &def_u32, &graph_desc, &task_desc, &items, &counters, &stage,
+                            &stage_off, &sizes, &roots, &scan_tmp, &big_ids})
+        b += x->bytes;
+    return b;
+}
+
+void RRWorkspace::release() {
+    for (DevBuf *x : {&lists, &bitmaps, &def_idx, &def_u32, &graph_desc, &task_desc, &items, &counters, &stage,
+                      &stage_off, &sizes, &roots, &scan_tmp, &big_ids})
+        x->release();
+    for (hipEvent_t e : events) (void)hipEventDestroy(e);
+    events.clear();
+    grid = waves = slots = grid_b = slot_n = slot_words = 0;
+}
+
+size_t GreedyWorkspace::bytes() const {
+    size_t b = 0;
+    for (const DevBuf *x : {&cnt, &inv_off, &cursor, &inv, &covered, &chosen, &best, &out, &big, &round_big, &flags,
+                            &counters, &scan_tmp})
+        b += x->bytes;
+    return b;
+}
+
+size_t graph_bytes(hyperim_graph g) {
+    size_t b = g->gr.bytes();
+    for (const DevBuf *x : {&g->he_off, &g->he_mem, &g->v_off, &g->v_he, &g->thr, &g->c, &g->weight, &g->bytesw, &g->l,
+                            &g->deg, &g->top, &g->stratum, &g->P})
+        b += x->bytes;
+    return b;
+}
 
 void release_graph(hyperim_graph g) {
-    for (DevBuf *b : {&g->he_off, &g->he_mem, &g->v_off, &g->v_he, &g->thr, &g->c, &g->weight, &g->l, &g->deg,
-                      &g->top, &g->stratum, &g->P})
+    for (DevBuf *b : {&g->he_off, &g->he_mem, &g->v_off, &g->v_he, &g->thr, &g->c, &g->weight, &g->bytesw, &g->l,
+                      &g->deg, &g->top, &g->stratum, &g->P})
         b->release();
-    RRWorkspace &r = g->rr;
-    for (DevBuf *b : {&r.lists, &r.bitmaps, &r.counters, &r.stage, &r.stage_off, &r.sizes, &r.roots, &r.scan_tmp,
-                      &r.big_ids, &r.def_idx, &r.def_u32, &r.items})
-        b->release();
-    for (hipEvent_t e : r.events) (void)hipEventDestroy(e);
-    r.events.clear();
-    g->bytesw.release();
     GreedyWorkspace &w = g->gr;
     for (DevBuf *b : {&w.cnt, &w.inv_off, &w.cursor, &w.inv, &w.covered, &w.chosen, &w.best, &w.out, &w.big,
                       &w.round_big, &w.flags, &w.counters, &w.scan_tmp})
@@ -132,88 +181,57 @@ void pool_clear(hyperim_pool p) {
     p->has_key = false;
 }
 
-// Generate the tasks in one go and append each task's sets to its pool.
-int generate_into(hyperim_graph g, const RRKey &key, const std::vector<RRTask> &tasks,
-                  const std::vector<hyperim_pool> &pools, int form, uint64_t max_entries, hipStream_t s) {
+void pool_release(hyperim_pool p) {
+    p->off_b.release();
+    p->roots_b.release();
+    p->mem_b.release();
+    p->off = nullptr;
+    p->roots = nullptr;
+    p->mem = nullptr;
+    p->id_cap = p->mem_cap = 0;
+    pool_clear(p);
+}
+
+size_t pool_bytes(const hyperim_pool_s &p) { return p.off_b.bytes + p.roots_b.bytes + p.mem_b.bytes; }
+
+// Generate the tasks in one go and append each task's sets to its pool
+// (tasks with an empty id range are skipped).
+int generate_into(const std::vector<RRTask> &tasks, const std::vector<hyperim_pool> &pools, uint32_t qlog, int form,
+                  uint64_t max_entries, hipStream_t s, RRStats &st, std::vector<int> *pool_status) {
     std::vector<RRTask> live;
-    std::vector<hyperim_pool> dst;
+    std::vector<size_t> which;
     for (size_t i = 0; i < tasks.size(); ++i)
         if (tasks[i].id_end > tasks[i].id_begin) {
             live.push_back(tasks[i]);
-            dst.push_back(pools[i]);
+            which.push_back(i);
         }
+    if (pool_status) pool_status->assign(tasks.size(), HYPERIM_OK);
     if (live.empty()) return HYPERIM_OK;
+    int device = 0;
+    HIM_HIP(hipGetDevice(&device));
+    RRWorkspaceLock lk(device);
     uint64_t total = 0;
-    HIM_CHECK(rr_generate_stage(g, key, live, form, s, &total));
+    HIM_CHECK(rr_generate_stage(*lk.ws, st, live, qlog, form, s, &total));
     uint64_t first = 0;
+    int first_fail = HYPERIM_OK;
     for (size_t i = 0; i < live.size(); ++i) {
         const uint64_t count = live[i].id_end - live[i].id_begin;
-        const bool was_empty = dst[i]->count == 0;
-        HIM_CHECK(rr_compact_into(g, dst[i], first, count, max_entries, s));
-        if (was_empty) dst[i]->id_begin = live[i].id_begin;
+        hyperim_pool p = pools[which[i]];
+        const bool was_empty = p->count == 0;
+        const int rc = rr_compact_into(*lk.ws, p, first, count, max_entries, s);
+        if (rc == HYPERIM_OK) {
+            if (was_empty) p->id_begin = live[i].id_begin;
+        } else if (rc == HYPERIM_ECAPACITY && pool_status) {
+            (*pool_status)[which[i]] = rc;   // this pool is full; the others go on
+            if (first_fail == HYPERIM_OK) first_fail = rc;
+        } else {
+            return rc;
+        }
         first += count;
     }
-    return HYPERIM_OK;
+    return pool_status ? HYPERIM_OK : first_fail;
 }
 
-// Sample-size schedule (Section 4): delta = n^-ell; theta_max from Lemma 6 in
-// the OPIM-C form it cites, 2n (t sqrt(ln 6/delta) + sqrt(t (ln C(n,k) +
-// ln 6/delta)))^2 / (eps^2 k) with t = 1 - 1/e; theta_0 = theta_max eps^2 k / n
-// rounded up to a power-of-two ladder size >= Q; i_max = first round whose
-// size reaches theta_max; a = ln(3 i_max / delta).
-struct Schedule {
-    double theta_max, theta0, a, ln_inv_delta;
-    uint64_t theta1;
-    uint32_t i_max;
-};
-
-Schedule make_schedule(uint32_t n, uint32_t k, double eps, double ell, uint32_t qlog) {
-    Schedule sc{};
-    const double t = 1.0 - std::exp(-1.0);
-    sc.ln_inv_delta = ell * std::log((double)n);
-    double ln_binom = 0.0;
-    for (uint32_t i = 0; i < k; ++i) ln_binom += std::log((double)(n - i) / (double)(i + 1));
-    const double l6 = std::log(6.0) + sc.ln_inv_delta;
-    const double r = t * std::sqrt(l6) + std::sqrt(t * (ln_binom + l6));
-    sc.theta_max = 2.0 * (double)n * r * r / (eps * eps * (double)k);
-    sc.theta0 = sc.theta_max * eps * eps * (double)k / (double)n;
-    uint64_t th = 1ull << qlog;
-    while ((double)th < sc.theta0) th <<= 1;
-    sc.theta1 = th;
-    uint32_t i = 1;
-    while ((double)th < sc.theta_max) {
-        th <<= 1;
-        ++i;
-    }
-    sc.i_max = i;
-    sc.a = std::log(3.0 * (double)i) + sc.ln_inv_delta;
-    return sc;
-}
-
-// Equation (12), clamped at zero.
-double lower_bound(double lambda2, double a, double n, double theta) {
-    const double r = std::sqrt(lambda2 + 2.0 * a / 9.0) - std::sqrt(a / 2.0);
-    double v = r * r - a / 18.0;
-    if (v < 0.0) v = 0.0;
-    return v * n / theta;
-}
-
-// Lemma 5 with p_max = 1, lifted by the OPIM-C concentration term.
-double upper_bound(double lambda1, uint32_t k, double a, double n, double theta) {
-    const double cov = lambda1 / (1.0 - std::pow(1.0 - 1.0 / (double)k, (double)k));
-    const double r = std::sqrt(cov + a / 2.0) + std::sqrt(a / 2.0);
-    return r * r * n / theta;
-}
-
-struct EventPair {
-    hipEvent_t a = nullptr, b = nullptr;
-    ~EventPair() {
-        if (a) (void)hipEventDestroy(a);
-        if (b) (void)hipEventDestroy(b);
-    }
-};
-
-}  // namespace
 }  // namespace hyperim
 
 using namespace hyperim;
@@ -359,6 +377,7 @@ int hyperim_pool_create(hyperim_graph g, void *dev_buf, size_t bytes, uint64_t i
 int hyperim_generate_rr(hyperim_graph g, uint64_t seed, uint32_t instance, uint32_t pool_tag, uint64_t id_begin,
                         uint64_t id_end, hyperim_pool pool, void *stream) {
     if (!g || !pool || pool->g != g) return HYPERIM_EINVAL;
+    HIM_CHECK(check_device(g));
     g_detail.clear();
     if (!g->stratified) return HYPERIM_ESTATE;
     if (pool_tag > 1 || seed >> 32 || id_end < id_begin || id_end > kMaxIds) {
@@ -372,8 +391,9 @@ int hyperim_generate_rr(hyperim_graph g, uint64_t seed, uint32_t instance, uint3
             return HYPERIM_EINVAL;
         }
     }
-    RRKey key{seed, instance, 8};
-    HIM_CHECK(generate_into(g, key, {RRTask{pool_tag, id_begin, id_end}}, {pool}, 0, 0, as_stream(stream)));
+    RRStats st;
+    HIM_CHECK(generate_into({RRTask{g, seed, instance, pool_tag, id_begin, id_end}}, {pool}, kDefaultQlog, 0, 0,
+                            as_stream(stream), st, nullptr));
     pool->has_key = true;
     pool->seed = seed;
     pool->instance = instance;
@@ -447,113 +467,9 @@ int hyperim_coverage(hyperim_graph g, hyperim_pool pool, uint64_t theta, const u
     return rc;
 }
 
-int hyperim_select_seeds(hyperim_graph g, uint32_t k, double eps, double ell, uint64_t seed, uint32_t instance,
-                         const hyperim_options *opt, void *stream, uint32_t *seeds, uint64_t *gains,
-                         hyperim_result *out) {
-    if (!g || !seeds) return HYPERIM_EINVAL;
-    g_detail.clear();
-    if (!g->stratified) return HYPERIM_ESTATE;
-    hyperim_options o{};
-    if (opt) o = *opt;
-    if (o.qlog == 0) o.qlog = 8;
-    if (k == 0 || k > g->n || !(eps > 0.0 && eps < 1.0) || !(ell > 0.0) || seed >> 32 || o.qlog > 24 ||
-        o.form > 1) {
-        set_error_detail("need 1 <= k <= n, 0 < eps < 1, ell > 0, seed < 2^32, qlog <= 24, form 0/1");
-        return HYPERIM_EINVAL;
-    }
-    const auto t0 = std::chrono::steady_clock::now();
-    hipStream_t s = as_stream(stream);
-    const Schedule sc = make_schedule(g->n, k, eps, ell, o.qlog);
-    const double t = 1.0 - std::exp(-1.0);
-    hyperim_pool_s r1, r2;
-    HIM_CHECK(pool_init_owned(g, &r1, s));
-    HIM_CHECK(pool_init_owned(g, &r2, s));
-    EventPair ev;
-    HIM_HIP(hipEventCreate(&ev.a));
-    HIM_HIP(hipEventCreate(&ev.b));
-    hyperim_result res{};
-    g->rr.ms_bfs = g->rr.ms_light = g->rr.ms_heavy = 0.0;
-    g->rr.launches = g->rr.supersteps = g->rr.deferred = 0;
-    g->rr.bytes_light = g->rr.bytes_heavy = 0;
-    res.i_max = o.theta_fixed ? 1 : sc.i_max;
-    res.theta_max = sc.theta_max;
-    uint64_t have = 0;
-    std::vector<uint64_t> gains_h(k);
-    int rc = [&]() -> int {
-        for (uint32_t i = 1; i <= res.i_max; ++i) {
-            const uint64_t theta = o.theta_fixed ? o.theta_fixed : (sc.theta1 << (i - 1));
-            if (theta > kMaxIds || theta >= (1ull << 32)) {
-                set_error_detail("theta exceeds the id space");
-                return HYPERIM_ECAPACITY;
-            }
-            float ms = 0.f;
-            HIM_HIP(hipEventRecord(ev.a, s));
-            // both pools of the round share one launch group
-            RRKey key{seed, instance, o.qlog};
-            HIM_CHECK(generate_into(g, key, {RRTask{0, have, theta}, RRTask{1, have, theta}}, {&r1, &r2},
-                                    (int)o.form, o.max_entries, s));
-            HIM_HIP(hipEventRecord(ev.b, s));
-            HIM_HIP(hipEventSynchronize(ev.b));
-            HIM_HIP(hipEventElapsedTime(&ms, ev.a, ev.b));
-            res.ms_rr += ms;
-            have = theta;
-            HIM_HIP(hipEventRecord(ev.a, s));
-            HIM_CHECK(greedy_device(g, &r1, theta, k, s, seeds, gains_h.data()));
-            uint64_t lambda2 = 0;
-            HIM_CHECK(coverage_device(g, &r2, theta, g->gr.out.as<uint32_t>(), k, s, &lambda2));
-            HIM_HIP(hipEventRecord(ev.b, s));
-            HIM_HIP(hipEventSynchronize(ev.b));
-            HIM_HIP(hipEventElapsedTime(&ms, ev.a, ev.b));
-            res.ms_greedy += ms;
-            uint64_t lambda1 = 0;
-            for (uint32_t x = 0; x < k; ++x) lambda1 += gains_h[x];
-            const double sl = lower_bound((double)lambda2, sc.a, (double)g->n, (double)theta);
-            const double su = upper_bound((double)lambda1, k, sc.a, (double)g->n, (double)theta);
-            res.rounds = i;
-            res.theta = theta;
-            res.lambda1 = lambda1;
-            res.lambda2 = lambda2;
-            res.sigma_l = sl;
-            res.sigma_u = su;
-            res.spread = (double)g->n * (double)lambda2 / (double)theta;
-            res.entries1 = r1.total;   // pools hold exactly [0, theta)
-            res.entries2 = r2.total;
-            if (o.theta_fixed) break;
-            if (su > 0.0 && sl / su >= t - eps) break;
-        }
-        if (o.flags & HYPERIM_FLAG_INCIDENCES) {
-            uint64_t i1 = 0, i2 = 0, b1 = 0, b2 = 0;
-            HIM_CHECK(rr_incidences(g, &r1, res.theta, s, &i1, &b1));
-            HIM_CHECK(rr_incidences(g, &r2, res.theta, s, &i2, &b2));
-            res.incidences = i1 + i2;
-            res.alg_bytes = b1 + b2;
-        }
-        return HYPERIM_OK;
-    }();
-    for (hyperim_pool_s *p : {&r1, &r2}) {
-        p->off_b.release();
-        p->roots_b.release();
-        p->mem_b.release();
-    }
-    if (rc != HYPERIM_OK) return rc;
-    if (gains)
-        for (uint32_t x = 0; x < k; ++x) gains[x] = gains_h[x];
-    res.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-    res.ms_bfs = g->rr.ms_bfs;
-    res.bfs_launches = g->rr.launches;
-    res.ms_light = g->rr.ms_light;
-    res.ms_heavy = g->rr.ms_heavy;
-    res.deferred = g->rr.deferred;
-    res.supersteps = g->rr.supersteps;
-    res.bytes_light = g->rr.bytes_light;
-    res.bytes_heavy = g->rr.bytes_heavy;
-    if (out) *out = res;
-    return HYPERIM_OK;
-}
-
 int hyperim_set_tuning(hyperim_graph g, const hyperim_tuning *t) {
     if (!g || !t) return HYPERIM_EINVAL;
-    hyperim_tuning &cur = g->rr.tune;
+    hyperim_tuning &cur = g->tune;
     if (t->heavy) cur.heavy = t->heavy;
     if (t->budget) cur.budget = t->budget;
     if (t->chunk) cur.chunk = std::max<uint32_t>(t->chunk, 16);
@@ -566,16 +482,32 @@ int hyperim_set_tuning(hyperim_graph g, const hyperim_tuning *t) {
 
 int hyperim_get_tuning(hyperim_graph g, hyperim_tuning *t) {
     if (!g || !t) return HYPERIM_EINVAL;
-    *t = g->rr.tune;
+    *t = g->tune;
     return HYPERIM_OK;
 }
 
 void hyperim_pool_free(hyperim_pool pool) {
     if (!pool) return;
-    pool->off_b.release();
-    pool->roots_b.release();
-    pool->mem_b.release();
+    pool_release(pool);
     delete pool;
+}
+
+int hyperim_workspace_info(size_t *bytes) {
+    if (!bytes) return HYPERIM_EINVAL;
+    int device = 0;
+    HIM_HIP(hipGetDevice(&device));
+    RRWorkspaceLock lk(device);
+    *bytes = lk.ws->bytes();
+    return HYPERIM_OK;
+}
+
+int hyperim_workspace_release(void) {
+    int device = 0;
+    HIM_HIP(hipGetDevice(&device));
+    RRWorkspaceLock lk(device);
+    HIM_HIP(hipDeviceSynchronize());
+    lk.ws->release();
+    return HYPERIM_OK;
 }
 
 void hyperim_graph_free(hyperim_graph g) {

@@ -14,6 +14,7 @@ namespace hyperim {
 
 // Status plumbing -------------------------------------------------------------
 void set_error_detail(const std::string &msg);
+void clear_error_detail();
 
 #define HIM_HIP(expr)                                                              \
     do {                                                                           \
@@ -40,23 +41,23 @@ struct DevBuf {
     T *as() const { return static_cast<T *>(ptr); }
 };
 
-// Workspace of RR generation, owned by a graph.
+// Workspace of RR generation: one per device, shared by every graph on it
+// (calls that use it hold its lock).
 struct RRWorkspace {
     uint32_t waves = 0;          // phase A wavefronts (each starts with its own slot)
     uint32_t grid = 0;           // workgroups of the phase A launch
     uint32_t slots = 0;          // slots: phase A waves + spare slots for deferred sets
     uint32_t grid_b = 0;         // workgroups of a phase B expansion launch
-    DevBuf lists;                // slots * n     : member list / BFS queue per slot
-    DevBuf bitmaps;              // slots * words : visited bitmap per slot
-    DevBuf def_idx;              // deferred sets: per-id index (uint64)
-    DevBuf def_u32;              // deferred sets: root, slot, head, size (4 uint32 arrays)
+    uint32_t slot_n = 0, slot_words = 0;  // slot list length / bitmap words (largest graph so far)
+    bool lds = false;            // phase A bitmaps in LDS (every graph small)
+    DevBuf lists;                // slots * slot_n     : member list / BFS queue per slot
+    DevBuf bitmaps;              // slots * slot_words : visited bitmap per slot
+    DevBuf def_idx;              // deferred sets: launch index (uint64)
+    DevBuf def_u32;              // deferred sets: root, slot, head, size, task (5 uint32 arrays)
+    DevBuf graph_desc, task_desc;  // launch-group descriptors in device memory
     DevBuf items;                // phase B work items (uint4)
-    double ms_light = 0.0, ms_heavy = 0.0;   // device time of phase A / phase B kernels
-    hyperim_tuning tune{1024, 16384, 256, 512, 4096, 8, {0, 0}};  // execution parameters
     double members_per_id = 0.0;  // staged members per RR id in the last call (stage sizing)
     double defer_rate = 0.5;      // deferred sets per RR id in the last call (launch-group sizing)
-    uint64_t supersteps = 0, deferred = 0;
-    uint64_t bytes_light = 0, bytes_heavy = 0;  // algorithmic bytes expanded in each phase
     DevBuf counters;             // work counter, stage bump, misc
     DevBuf stage;                // unsorted->sorted members before compaction
     DevBuf stage_off;            // per id (uint64)
@@ -65,8 +66,25 @@ struct RRWorkspace {
     DevBuf scan_tmp;             // scan block sums
     DevBuf big_ids;              // per-id indices of sets compacted by whole workgroups
     std::vector<hipEvent_t> events;  // start/stop pairs around RR-generation launches
-    double ms_bfs = 0.0;         // accumulated device time of those launches
-    uint64_t launches = 0;
+    size_t bytes() const;        // device memory held
+    void release();
+};
+
+// What one generation call did (device times from HIP events).
+struct RRStats {
+    double ms_bfs = 0.0, ms_light = 0.0, ms_heavy = 0.0;  // all / phase A / phase B kernels
+    uint64_t launches = 0, supersteps = 0, deferred = 0;
+    uint64_t bytes_light = 0, bytes_heavy = 0;   // algorithmic bytes expanded in each phase
+};
+
+// The device's shared RR workspace, locked for the caller's lifetime.
+struct RRWorkspaceLock {
+    RRWorkspace *ws;
+    void *lock;
+    explicit RRWorkspaceLock(int device);
+    ~RRWorkspaceLock();
+    RRWorkspaceLock(const RRWorkspaceLock &) = delete;
+    RRWorkspaceLock &operator=(const RRWorkspaceLock &) = delete;
 };
 
 // Workspace of greedy / coverage, owned by a graph.
@@ -84,6 +102,7 @@ struct GreedyWorkspace {
     DevBuf flags;     // n uint8 seed marks (coverage)
     DevBuf counters;  // coverage counters
     DevBuf scan_tmp;
+    size_t bytes() const;
 };
 
 }  // namespace hyperim
@@ -99,7 +118,7 @@ struct hyperim_graph_s {
     bool stratified = false;
     hyperim::DevBuf l, deg, top, stratum, P;
     hyperim_strata_info info{};
-    hyperim::RRWorkspace rr;
+    hyperim_tuning tune{1024, 16384, 256, 512, 4096, 8, {0, 0}};  // RR execution parameters
     hyperim::GreedyWorkspace gr;
 };
 
@@ -122,6 +141,37 @@ struct hyperim_pool_s {
 
 namespace hyperim {
 
+constexpr uint64_t kMaxIds = 1ull << 39;   // RR ids use 39 bits of the coin counter
+constexpr uint32_t kDefaultQlog = 8;       // pool ladder base Q = 2^8
+
+inline hipStream_t as_stream(void *s) { return static_cast<hipStream_t>(s); }
+
+// The graph must live on the current device.
+inline int check_device(hyperim_graph g) {
+    int d = 0;
+    HIM_HIP(hipGetDevice(&d));
+    if (d != g->device) {
+        set_error_detail("the graph lives on another device than the current one");
+        return HYPERIM_EINVAL;
+    }
+    return HYPERIM_OK;
+}
+
+// ---- handles and storage (api.hip) --------------------------------------------
+size_t graph_bytes(hyperim_graph g);                       // device bytes of the graph incl. greedy workspace
+int pool_init_owned(hyperim_graph g, hyperim_pool p, hipStream_t s);
+void pool_clear(hyperim_pool p);                           // empty, keeps storage
+void pool_release(hyperim_pool p);                         // empty, frees owned storage
+size_t pool_bytes(const hyperim_pool_s &p);
+struct RRStats;
+struct RRTask;
+// Generate tasks[i] into pools[i] (one generation pass; tasks with empty
+// ranges skipped).  With pool_status, a pool that would exceed max_entries
+// gets HYPERIM_ECAPACITY there and the others are still filled; without it
+// that status is returned.
+int generate_into(const std::vector<RRTask> &tasks, const std::vector<hyperim_pool> &pools, uint32_t qlog, int form,
+                  uint64_t max_entries, hipStream_t s, RRStats &st, std::vector<int> *pool_status);
+
 // ---- launchers (graph.hip) --------------------------------------------------
 int graph_build_device(hyperim_graph g, hipStream_t s);
 
@@ -135,23 +185,24 @@ int scan_u32_to_u64(const uint32_t *in, uint64_t *out, uint64_t count, uint64_t 
 int scan_u64(const uint64_t *in, uint64_t *out, uint64_t count, uint64_t init, DevBuf &tmp, hipStream_t s);
 
 // ---- launchers (rr.hip) -------------------------------------------------------
-struct RRKey {
-    uint64_t seed;
-    uint32_t instance, qlog;
-};
-// RR ids [id_begin, id_end) of pool tag `pool`.
+// RR ids [id_begin, id_end) of pool tag `pool` on graph g, Philox key
+// (seed mod 2^32, instance).
 struct RRTask {
-    uint32_t pool;
+    hyperim_graph g;
+    uint64_t seed;
+    uint32_t instance, pool;
     uint64_t id_begin, id_end;
 };
-// Generate every task's RR sets into the workspace stage (per-id outputs laid
-// out task after task); *total = members staged.  form 0 = all tasks in one
-// launch group, form 1 = one launch group per (task, ladder block, stratum).
-int rr_generate_stage(hyperim_graph g, const RRKey &key, const std::vector<RRTask> &tasks, int form, hipStream_t s,
-                      uint64_t *total);
-// Append the staged sets with per-id indices [first, first + count) to pool p
-// (growing its storage; HYPERIM_ECAPACITY beyond max_entries or a caller buffer).
-int rr_compact_into(hyperim_graph g, hyperim_pool p, uint64_t first, uint64_t count, uint64_t max_entries,
+// Generate every task's RR sets into workspace ws's stage (per-id outputs laid
+// out task after task); *total = members staged.  Tasks may name different
+// (stratified) graphs on the current device.  form 0 = the tasks share launch
+// groups, form 1 = one launch group per (task, ladder block, stratum).
+int rr_generate_stage(RRWorkspace &ws, RRStats &st, const std::vector<RRTask> &tasks, uint32_t qlog, int form,
+                      hipStream_t s, uint64_t *total);
+// Append the staged sets with per-id indices [first, first + count) of ws to
+// pool p (growing its storage; HYPERIM_ECAPACITY beyond max_entries or a
+// caller buffer).
+int rr_compact_into(RRWorkspace &ws, hyperim_pool p, uint64_t first, uint64_t count, uint64_t max_entries,
                     hipStream_t s);
 // Make room in pool p for `ids` more ids and `entries` more members.
 int pool_reserve(hyperim_pool p, uint64_t ids, uint64_t entries, hipStream_t s);

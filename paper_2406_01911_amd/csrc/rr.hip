@@ -7,16 +7,17 @@
 //
 // Phase A (k_rr_light, persistent): wavefronts steal RR ids from a global
 // counter; one wavefront owns one set at a time in a "slot" (member list that
-// doubles as the BFS queue, plus a visited bitmap -- in LDS when |V| is
-// small).  Each frontier batch (up to 64 queued vertices) is expanded in
-// three load-balanced levels -- vertices -> incidences (v, he) -> quads of 4
-// member positions -- so lanes stay busy under degree and size skew and
-// member ids are read contiguously; one Philox4x32-10 call gives the 4 coins
-// of a quad; a live channel from an unvisited member sets its bit (atomic OR)
-// and the winner appends it with a ballot-ranked store.  A set whose next
-// batch holds a heavy vertex, or that has used up its incidence budget, is
-// handed over intact (slot, queue head, size) to phase B and the wave takes a
-// fresh slot.  Finished sets are written ascending to a staging area.
+// doubles as the BFS queue, plus a visited bitmap -- in LDS when every graph
+// of the launch is small).  Each frontier batch (up to 64 queued vertices) is
+// expanded in three load-balanced levels -- vertices -> incidences (v, he) ->
+// octets of 8 member positions -- so lanes stay busy under degree and size
+// skew and member ids are read contiguously; two Philox4x32-10 blocks give the
+// 8 coins of an octet; a live channel from an unvisited member sets its bit
+// (atomic OR) and the winner appends it with a ballot-ranked store.  A set
+// whose next batch holds a heavy vertex, or that has used up its incidence
+// budget, is handed over intact (slot, queue head, size) to phase B and the
+// wave takes a fresh slot.  Finished sets are written ascending to a staging
+// area.
 //
 // Phase B (bulk-synchronous over the deferred sets): k_plan cuts every
 // deferred set's current frontier into work items of bounded cost --
@@ -25,17 +26,20 @@
 // spreads the items over every wavefront of the GPU, so a single giant set
 // or hub expansion uses the whole chip.  Supersteps repeat until no frontier
 // is left; k_finish sorts and stages each set.  No wave ever waits for
-// another: items only refer to finished supersteps.  Several (pool, id
-// range) tasks -- e.g. both pools of a doubling round -- share one launch
-// group, so they share supersteps.
+// another: items only refer to finished supersteps.
+//
+// A launch group covers several tasks -- (graph, key, pool, id range) -- back
+// to back, described in device memory: both pools of a doubling round, or
+// many IM instances on different graphs, share phase A and the supersteps.
 //
 // Compaction turns the per-id sizes into CSR offsets (device scan) and moves
-// the staged members into the pool.
+// the staged members into the pools.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cstdio>
 #include <cstdlib>
+#include <map>
 #include <vector>
 
 #include "dev_common.h"
@@ -48,9 +52,8 @@ constexpr int kWG = 256;
 constexpr int kWavesPerWG = kWG / kWave;
 constexpr uint32_t kSortMax = 1024;          // phase A: sets up to this size are sorted in LDS
 constexpr uint32_t kSortMaxWG = 4096;        // phase B: one workgroup sorts up to this size in LDS
-constexpr uint32_t kLdsBitmapWords = 1024;   // visited bitmap in LDS when |V| <= 32768
+constexpr uint32_t kLdsBitmapWords = 1024;   // visited bitmap in LDS when every |V| <= 32768
 constexpr uint32_t kBigSet = 4096;           // compaction: one workgroup per larger set
-constexpr uint32_t kMaxTasks = 4;            // (pool, id range) tasks per launch
 constexpr uint32_t kItemCap = 1u << 22;      // phase B: work items per superstep
 constexpr uint32_t kMaxItemsPerVertex = 1u << 20;  // heavy chunks grow so one vertex fits a superstep
 constexpr uint64_t kSlotBudget = 48ull << 30; // bytes of slot lists + bitmaps
@@ -63,26 +66,31 @@ constexpr uint64_t kSlotBudget = 48ull << 30; // bytes of slot lists + bitmaps
 // counter s & 1 while its k_expand clears the other one for superstep s + 1.
 enum Ctr { kWork = 0, kBump, kBigCount, kFreeNext, kDefCount, kItems, kItemsOther, kBytesA, kBytesB, kNumCtr };
 
+// One graph of a launch group.
+struct GraphDesc {
+    const uint32_t *he_off, *he_mem, *v_off, *v_he, *thr, *P;
+    uint32_t n, bm_words;
+};
+
+// One task of a launch group: launch indices [previous end, end) are RR ids
+// first_id, first_id + 1, ... of pool `pool` on graph `graph` with Philox key
+// (key0, key1).
+struct TaskDesc {
+    uint64_t end, first_id;
+    uint32_t pool, graph, key0, key1;
+};
+
 struct RRArgs {
-    const uint32_t *__restrict__ he_off;
-    const uint32_t *__restrict__ he_mem;
-    const uint32_t *__restrict__ v_off;
-    const uint32_t *__restrict__ v_he;
-    const uint32_t *__restrict__ thr;
-    const uint32_t *__restrict__ P;
-    uint32_t n, key0, key1, qlog, bm_words;
+    const GraphDesc *graphs;
+    const TaskDesc *tasks;
+    uint32_t ntasks, qlog;
     uint32_t heavy, budget, chunk, seg, prefilter_min;   // execution parameters
-    // a launch covers up to kMaxTasks (pool, id range) tasks back to back:
-    // launch index idx belongs to task t when t_end[t-1] <= idx < t_end[t]
-    uint32_t ntasks;
+    uint32_t slot_n, slot_words;     // slot list length and bitmap words (largest graph)
     uint64_t count;                  // launch indices [0, count)
-    uint64_t t_end[kMaxTasks];
-    uint64_t t_id[kMaxTasks];        // RR id of each task's first index
-    uint32_t t_pool[kMaxTasks];      // pool tag of each task
     uint64_t out_base;               // per-id array index of launch index 0
     unsigned long long *ctr;         // Ctr block
-    uint32_t *lists;                 // per slot: n entries
-    uint32_t *bitmaps;               // per slot: bm_words (global mode)
+    uint32_t *lists;                 // per slot: slot_n entries
+    uint32_t *bitmaps;               // per slot: slot_words (global mode)
     uint32_t slot_total;             // slots available (waves own the first ones)
     uint32_t *stage;
     uint64_t stage_cap;
@@ -92,7 +100,7 @@ struct RRArgs {
     uint64_t *big_ids;               // per big set: per-id index
     // deferred sets (phase B)
     uint64_t *def_idx;
-    uint32_t *def_root, *def_slot, *def_head, *def_size;
+    uint32_t *def_root, *def_slot, *def_head, *def_size, *def_task;
     uint4 *items;
 };
 
@@ -101,43 +109,63 @@ struct WaveLds {
     uint32_t in_scan[kWave], in_he[kWave], in_hb[kWave], in_hs[kWave], in_v[kWave], in_thr[kWave];
 };
 
-// RR id and pool tag of launch index idx.
-__device__ __forceinline__ void resolve(const RRArgs &a, uint64_t idx, uint64_t *j, uint32_t *pool) {
-    uint32_t t = 0;
-    while (t + 1 < a.ntasks && idx >= a.t_end[t]) ++t;
-    const uint64_t start = t ? a.t_end[t - 1] : 0ull;
-    *j = a.t_id[t] + (idx - start);
-    *pool = a.t_pool[t];
+// The task of launch index idx (first task whose end exceeds idx).
+__device__ __forceinline__ uint32_t task_of(const RRArgs &a, uint64_t idx) {
+    uint32_t lo = 0, hi = a.ntasks - 1;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (a.tasks[mid].end > idx) hi = mid; else lo = mid + 1;
+    }
+    return lo;
+}
+
+// What a set needs to know about where it comes from.
+struct SetRef {
+    GraphDesc G;
+    uint64_t j;
+    uint32_t pool;
+    uint2 key;
+};
+
+__device__ __forceinline__ SetRef set_ref(const RRArgs &a, uint32_t t, uint64_t idx) {
+    const TaskDesc T = a.tasks[t];
+    const uint64_t start = t ? a.tasks[t - 1].end : 0ull;
+    SetRef r;
+    r.G = a.graphs[T.graph];
+    r.j = T.first_id + (idx - start);
+    r.pool = T.pool;
+    r.key = make_uint2(T.key0, T.key1);
+    return r;
 }
 
 // Stratified root of RR id j: block b of the ladder (Q = 2^qlog ids in block
 // 0, Q 2^(b-1) in block b >= 1, so block sizes are powers of two), offset
 // o_b = floor(x n / 2^64) from the block's Philox draw, root =
 // P[floor((t n + o_b) / T_b)] computed in 128-bit arithmetic.
-__device__ __forceinline__ uint32_t rr_root(const RRArgs &a, uint64_t j, uint32_t pool, uint2 key) {
-    const uint64_t Q = 1ull << a.qlog;
+__device__ __forceinline__ uint32_t rr_root(const GraphDesc &G, uint32_t qlog, uint64_t j, uint32_t pool, uint2 key) {
+    const uint64_t Q = 1ull << qlog;
     uint32_t b, s;
     uint64_t J;
     if (j < Q) {
         b = 0;
         J = 0;
-        s = a.qlog;
+        s = qlog;
     } else {
         const uint32_t hb = 63u - (uint32_t)__clzll((long long)j);
-        b = hb - a.qlog + 1u;
+        b = hb - qlog + 1u;
         J = 1ull << hb;
         s = hb;
     }
     const uint4 r = philox4x32_10(root_counter(b, pool), key);
     const uint64_t x = (uint64_t)r.x | ((uint64_t)r.y << 32);
-    const uint64_t o = __umul64hi(x, (uint64_t)a.n);
+    const uint64_t o = __umul64hi(x, (uint64_t)G.n);
     const uint64_t t = j - J;
-    const uint64_t lo = t * (uint64_t)a.n;
-    uint64_t hi = __umul64hi(t, (uint64_t)a.n);
+    const uint64_t lo = t * (uint64_t)G.n;
+    uint64_t hi = __umul64hi(t, (uint64_t)G.n);
     const uint64_t lo2 = lo + o;
     hi += lo2 < lo ? 1ull : 0ull;
     const uint64_t pos = s == 0 ? lo2 : ((lo2 >> s) | (hi << (64u - s)));
-    return a.P[pos];
+    return G.P[pos];
 }
 
 template <bool kLds>
@@ -182,12 +210,12 @@ struct SharedAppend {
 // go to `app`.  Every lane of the wave must call it (inactive lanes with
 // active = false).
 template <bool kLds, class App>
-__device__ __forceinline__ void test_octet(const RRArgs &a, uint64_t j, uint32_t pool, uint2 key, uint32_t *bm,
+__device__ __forceinline__ void test_octet(const GraphDesc &G, uint64_t j, uint32_t pool, uint2 key, uint32_t *bm,
                                            bool prefilter, bool active, uint32_t he, uint32_t hb, uint32_t p0,
                                            uint32_t cm, uint32_t ve, uint32_t the, App &app) {
     uint32_t u[8];
 #pragma unroll
-    for (uint32_t t = 0; t < 8; ++t) u[t] = (active && t < cm) ? a.he_mem[hb + p0 + t] : ve;
+    for (uint32_t t = 0; t < 8; ++t) u[t] = (active && t < cm) ? G.he_mem[hb + p0 + t] : ve;
     uint32_t seen[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
     if (prefilter) {
         // all mark words in flight together (u[t] is always a vertex id)
@@ -238,14 +266,14 @@ __device__ __forceinline__ void test_octet(const RRArgs &a, uint64_t j, uint32_t
 // hyperedges over the wave.  Returns the algorithmic bytes of the incidences
 // read (12 per incidence plus 4 per member position), wave-uniform.
 template <bool kLds, bool kUniform, class App>
-__device__ __forceinline__ uint64_t expand(const RRArgs &a, WaveLds &L, uint64_t j, uint32_t pool, uint2 key,
+__device__ __forceinline__ uint64_t expand(const GraphDesc &G, WaveLds &L, uint64_t j, uint32_t pool, uint2 key,
                                            uint32_t *bm, bool prefilter, uint32_t v, uint32_t e0, uint32_t d,
                                            App &app) {
     const uint32_t lane = lane_id();
     uint32_t D = d;
     uint32_t th_uniform = 0;
     if constexpr (kUniform) {
-        th_uniform = a.thr[v];
+        th_uniform = G.thr[v];
     } else {
         const uint32_t dscan = wave_incl_scan(d);
         D = wave_bcast(dscan, kWave - 1);
@@ -262,21 +290,21 @@ __device__ __forceinline__ uint64_t expand(const RRArgs &a, WaveLds &L, uint64_t
         uint32_t he = 0, hb = 0, hs = 0, vv = v, th = th_uniform, no = 0;
         if (g < D) {
             if constexpr (kUniform) {
-                he = a.v_he[e0 + g];
+                he = G.v_he[e0 + g];
             } else {
                 const uint32_t k = search64(L.fr_scan, g);
                 const uint32_t start = k ? L.fr_scan[k - 1] : 0u;
                 vv = L.fr_v[k];
-                he = a.v_he[L.fr_e0[k] + (g - start)];
-                th = a.thr[vv];
+                he = G.v_he[L.fr_e0[k] + (g - start)];
+                th = G.thr[vv];
             }
-            hb = a.he_off[he];
-            hs = a.he_off[he + 1] - hb;
+            hb = G.he_off[he];
+            hs = G.he_off[he + 1] - hb;
             no = th ? (hs + 7u) >> 3 : 0u;   // threshold 0: no channel into vv is live
             bytes += 12u + 4u * hs;
         }
         // level 3, first pass: octet 0 of the lane's own incidence
-        test_octet<kLds>(a, j, pool, key, bm, prefilter, no > 0, he, hb, 0u, min(8u, hs), vv, th, app);
+        test_octet<kLds>(G, j, pool, key, bm, prefilter, no > 0, he, hb, 0u, min(8u, hs), vv, th, app);
         // second pass: octets 1.. of the longer hyperedges, flattened over the wave
         const uint32_t rem = no > 1 ? no - 1u : 0u;
         if (__ballot(rem > 0) == 0) continue;
@@ -308,7 +336,7 @@ __device__ __forceinline__ uint64_t expand(const RRArgs &a, WaveLds &L, uint64_t
                     the = L.in_thr[k];
                 }
             }
-            test_octet<kLds>(a, j, pool, key, bm, prefilter, active, hee, hbk, p0, cm, ve, the, app);
+            test_octet<kLds>(G, j, pool, key, bm, prefilter, active, hee, hbk, p0, cm, ve, the, app);
         }
     }
     wave_sync();
@@ -334,16 +362,15 @@ __global__ __launch_bounds__(kWG) void k_rr_light(RRArgs a) {
     uint32_t slot = blockIdx.x * kWavesPerWG + wv;
     WaveLds &L = lds[wv];
     uint32_t *sortb = sort_s[wv];
-    uint32_t *list = a.lists + (uint64_t)slot * a.n;
+    uint32_t *list = a.lists + (uint64_t)slot * a.slot_n;
     uint32_t *bm;
     if constexpr (kLdsBitmap) {
         bm = lbm[wv];
-        for (uint32_t i = lane; i < a.bm_words; i += kWave) bm[i] = 0u;
+        for (uint32_t i = lane; i < kLdsBitmapWords; i += kWave) bm[i] = 0u;
     } else {
-        bm = a.bitmaps + (uint64_t)slot * a.bm_words;
+        bm = a.bitmaps + (uint64_t)slot * a.slot_words;
     }
     wave_sync();
-    const uint2 key = make_uint2(a.key0, a.key1);
     bool can_defer = !kLdsBitmap;
     uint64_t bytes_done = 0;
 
@@ -352,15 +379,15 @@ __global__ __launch_bounds__(kWG) void k_rr_light(RRArgs a) {
         if (lane == 0) idx = atomicAdd(&a.ctr[kWork], 1ull);
         idx = wave_bcast64(idx, 0);
         if (idx >= a.count) break;
-        uint64_t j;
-        uint32_t pool;
-        resolve(a, idx, &j, &pool);
-        const uint32_t root = rr_root(a, j, pool, key);
+        const uint32_t task = task_of(a, idx);
+        const SetRef S = set_ref(a, task, idx);
+        const GraphDesc &G = S.G;
+        const uint32_t root = rr_root(G, a.qlog, S.j, S.pool, S.key);
         if (lane == 0) {
             list[0] = root;
             atomicOr(&bm[root >> 5], 1u << (root & 31));
         }
-        LocalAppend app{list, 1u, a.n};
+        LocalAppend app{list, 1u, G.n};
         uint32_t head = 0;
         uint64_t spent = 0;
         bool deferred = false;
@@ -373,8 +400,8 @@ __global__ __launch_bounds__(kWG) void k_rr_light(RRArgs a) {
             uint32_t v = 0, e0 = 0, d = 0;
             if (lane < nb) {
                 v = list[head + lane];
-                e0 = a.v_off[v];
-                d = a.v_off[v + 1] - e0;
+                e0 = G.v_off[v];
+                d = G.v_off[v + 1] - e0;
             }
             if (can_defer && (spent > a.budget || __ballot(d > a.heavy) != 0)) {
                 // hand the set over to phase B and continue with a fresh slot
@@ -389,10 +416,11 @@ __global__ __launch_bounds__(kWG) void k_rr_light(RRArgs a) {
                         a.def_slot[dd] = slot;
                         a.def_head[dd] = head;
                         a.def_size[dd] = app.size;
+                        a.def_task[dd] = task;
                     }
                     slot = fresh_slot;
-                    list = a.lists + (uint64_t)slot * a.n;
-                    bm = a.bitmaps + (uint64_t)slot * a.bm_words;
+                    list = a.lists + (uint64_t)slot * a.slot_n;
+                    bm = a.bitmaps + (uint64_t)slot * a.slot_words;
                     deferred = true;
                     break;
                 }
@@ -401,7 +429,7 @@ __global__ __launch_bounds__(kWG) void k_rr_light(RRArgs a) {
             head += nb;
             spent += wave_bcast(wave_incl_scan(d), kWave - 1);
             bytes_done += 20ull * nb;
-            bytes_done += expand<kLdsBitmap, false>(a, L, j, pool, key, bm, false, v, e0, d, app);
+            bytes_done += expand<kLdsBitmap, false>(G, L, S.j, S.pool, S.key, bm, false, v, e0, d, app);
         }
         if (deferred) continue;
         const uint32_t size = app.size;
@@ -436,9 +464,9 @@ __global__ __launch_bounds__(kWG) void k_rr_light(RRArgs a) {
                 wave_sync();
             } else {
                 uint32_t written = 0;
-                for (uint32_t w0 = 0; w0 < a.bm_words; w0 += kWave) {
+                for (uint32_t w0 = 0; w0 < G.bm_words; w0 += kWave) {
                     const uint32_t wi = w0 + lane;
-                    uint32_t word = wi < a.bm_words ? bm_load<kLdsBitmap>(bm, wi) : 0u;
+                    uint32_t word = wi < G.bm_words ? bm_load<kLdsBitmap>(bm, wi) : 0u;
                     const uint32_t cnt = (uint32_t)__popc(word);
                     const uint32_t incl = wave_incl_scan(cnt);
                     uint64_t pos = off + written + incl - cnt;
@@ -454,8 +482,8 @@ __global__ __launch_bounds__(kWG) void k_rr_light(RRArgs a) {
         }
         if (lane == 0) record_set(a, idx, off, size, root);
         // clear this set's marks (the bitmap is all-zero again afterwards)
-        if (kLdsBitmap && size * 4u > a.bm_words) {
-            for (uint32_t i = lane; i < a.bm_words; i += kWave) bm[i] = 0u;
+        if (kLdsBitmap && size * 4u > G.bm_words) {
+            for (uint32_t i = lane; i < G.bm_words; i += kWave) bm[i] = 0u;
         } else {
             for (uint32_t i = lane; i < size; i += kWave) bm[list[i] >> 5] = 0u;
         }
@@ -479,14 +507,15 @@ __global__ __launch_bounds__(kWG) void k_plan(RRArgs a, uint32_t ndef, uint32_t 
     for (uint32_t d = blockIdx.x * kWavesPerWG + wv; d < ndef; d += waves) {
         uint32_t head = a.def_head[d];
         const uint32_t size = a.def_size[d];
-        const uint32_t *list = a.lists + (uint64_t)a.def_slot[d] * a.n;
+        const uint32_t *list = a.lists + (uint64_t)a.def_slot[d] * a.slot_n;
+        const GraphDesc G = a.graphs[a.tasks[a.def_task[d]].graph];
         while (head < size) {
             uint32_t nb = min((uint32_t)kWave, size - head);
             uint32_t v = 0, e0 = 0, deg = 0, hv = 0, light = 0, cv = a.chunk;
             if (lane < nb) {
                 v = list[head + lane];
-                e0 = a.v_off[v];
-                deg = a.v_off[v + 1] - e0;
+                e0 = G.v_off[v];
+                deg = G.v_off[v + 1] - e0;
                 // a heavy vertex is cut into chunks of cv incidences, cv grown
                 // so that one vertex never needs more than kMaxItemsPerVertex
                 cv = max(a.chunk, (uint32_t)div_up(deg, kMaxItemsPerVertex));
@@ -538,42 +567,42 @@ __global__ __launch_bounds__(kWG) void k_plan(RRArgs a, uint32_t ndef, uint32_t 
 
 __global__ __launch_bounds__(kWG) void k_expand(RRArgs a, uint32_t parity) {
     __shared__ WaveLds lds[kWavesPerWG];
-    const uint32_t lane = lane_id(), wv = threadIdx.x / kWave;
+    const uint32_t wv = threadIdx.x / kWave;
     WaveLds &L = lds[wv];
-    const uint2 key = make_uint2(a.key0, a.key1);
     const uint64_t nitems = min(a.ctr[kItems + parity], (unsigned long long)kItemCap);
     if (blockIdx.x == 0 && threadIdx.x == 0) a.ctr[kItems + (parity ^ 1u)] = 0ull;   // next superstep's counter
     uint64_t bytes_done = 0;
     // items have bounded cost (< seg + chunk incidences), so a static strided
     // assignment balances well and needs no shared counter
     const uint64_t waves = (uint64_t)gridDim.x * kWavesPerWG;
+    const uint32_t lane = lane_id();
     for (uint64_t it = (uint64_t)blockIdx.x * kWavesPerWG + wv; it < nitems; it += waves) {
         const uint4 item = a.items[it];
         if (item.x == kSkipItem) continue;
         const uint32_t d = item.x & 0x7FFFFFFFu;
         const bool heavy = (item.x >> 31) != 0u;
         const uint32_t slot = a.def_slot[d];
-        uint32_t *list = a.lists + (uint64_t)slot * a.n;
-        uint32_t *bm = a.bitmaps + (uint64_t)slot * a.bm_words;
-        uint64_t j;
-        uint32_t pool;
-        resolve(a, a.def_idx[d], &j, &pool);
+        const SetRef S = set_ref(a, a.def_task[d], a.def_idx[d]);
+        const GraphDesc &G = S.G;
+        uint32_t *list = a.lists + (uint64_t)slot * a.slot_n;
+        uint32_t *bm = a.bitmaps + (uint64_t)slot * a.slot_words;
         uint32_t *size_p = &a.def_size[d];
         const bool prefilter = __hip_atomic_load(size_p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= a.prefilter_min;
-        SharedAppend app{list, size_p, a.n};
+        SharedAppend app{list, size_p, G.n};
         if (!heavy) {
             uint32_t v = 0, e0 = 0, deg = 0;
             if (lane < item.z) {
                 v = list[item.y + lane];
-                e0 = a.v_off[v];
-                deg = a.v_off[v + 1] - e0;
+                e0 = G.v_off[v];
+                deg = G.v_off[v + 1] - e0;
                 if (deg > a.chunk) deg = 0;   // expanded by its heavy items
             }
             bytes_done += 20ull * item.z;
-            bytes_done += expand<false, false>(a, L, j, pool, key, bm, prefilter, v, e0, deg, app);
+            bytes_done += expand<false, false>(G, L, S.j, S.pool, S.key, bm, prefilter, v, e0, deg, app);
         } else {
             // one heavy vertex: incidences [item.z, item.w) of vertex item.y
-            bytes_done += expand<false, true>(a, L, j, pool, key, bm, prefilter, item.y, item.z, item.w - item.z, app);
+            bytes_done += expand<false, true>(G, L, S.j, S.pool, S.key, bm, prefilter, item.y, item.z,
+                                              item.w - item.z, app);
         }
     }
     if (lane == 0 && bytes_done) atomicAdd(&a.ctr[kBytesB], bytes_done);
@@ -589,8 +618,9 @@ __global__ __launch_bounds__(kWG) void k_finish(RRArgs a, uint32_t ndef) {
     const uint32_t lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
     for (uint32_t d = blockIdx.x; d < ndef; d += gridDim.x) {
         const uint32_t size = a.def_size[d];
-        uint32_t *list = a.lists + (uint64_t)a.def_slot[d] * a.n;
-        uint32_t *bm = a.bitmaps + (uint64_t)a.def_slot[d] * a.bm_words;
+        uint32_t *list = a.lists + (uint64_t)a.def_slot[d] * a.slot_n;
+        uint32_t *bm = a.bitmaps + (uint64_t)a.def_slot[d] * a.slot_words;
+        const uint32_t words = a.graphs[a.tasks[a.def_task[d]].graph].bm_words;
         if (threadIdx.x == 0) off_s = atomicAdd(&a.ctr[kBump], (unsigned long long)size);
         __syncthreads();
         const uint64_t off = off_s;
@@ -619,9 +649,9 @@ __global__ __launch_bounds__(kWG) void k_finish(RRArgs a, uint32_t ndef) {
             } else {
                 if (threadIdx.x == 0) running = 0;
                 __syncthreads();
-                for (uint32_t w0 = 0; w0 < a.bm_words; w0 += kWG) {
+                for (uint32_t w0 = 0; w0 < words; w0 += kWG) {
                     const uint32_t wi = w0 + threadIdx.x;
-                    uint32_t word = wi < a.bm_words ? bm[wi] : 0u;
+                    uint32_t word = wi < words ? bm[wi] : 0u;
                     const uint32_t cnt = (uint32_t)__popc(word);
                     const uint32_t incl = wave_incl_scan(cnt);
                     if (lane == kWave - 1) wave_tot[wv] = incl;
@@ -643,8 +673,8 @@ __global__ __launch_bounds__(kWG) void k_finish(RRArgs a, uint32_t ndef) {
         }
         if (threadIdx.x == 0) record_set(a, a.def_idx[d], off, size, a.def_root[d]);
         __syncthreads();
-        if (size > a.bm_words) {
-            for (uint32_t i = threadIdx.x; i < a.bm_words; i += kWG) bm[i] = 0u;
+        if (size > words) {
+            for (uint32_t i = threadIdx.x; i < words; i += kWG) bm[i] = 0u;
         } else {
             for (uint32_t i = threadIdx.x; i < size; i += kWG) bm[list[i] >> 5] = 0u;
         }
@@ -733,14 +763,21 @@ struct LaunchShape {
     uint32_t grid;        // phase A workgroups (one slot per wave)
     uint32_t slots;       // total slots (phase A waves + spare slots for deferred sets)
     uint32_t grid_b;      // phase B workgroups
+    uint32_t slot_n, slot_words;
     bool lds;
 };
 
-int ensure_workspace(hyperim_graph g, hipStream_t s, LaunchShape *shape) {
-    RRWorkspace &ws = g->rr;
-    const uint32_t n = g->n;
-    const bool lds = n <= kLdsBitmapWords * 32u;
-    const uint32_t words = (n + 31u) / 32u;
+// Slots sized for graphs of up to n_max vertices (re-created when a larger
+// graph arrives).
+int ensure_workspace(RRWorkspace &ws, uint32_t n_max, hipStream_t s, LaunchShape *shape) {
+    const bool lds = n_max <= kLdsBitmapWords * 32u;
+    const uint32_t words = (n_max + 31u) / 32u;
+    if (ws.grid != 0 && (ws.slot_n < n_max || ws.lds != lds)) {
+        HIM_HIP(hipStreamSynchronize(s));
+        ws.lists.release();
+        ws.bitmaps.release();
+        ws.grid = 0;
+    }
     if (ws.grid == 0) {
         int dev = 0;
         HIM_HIP(hipGetDevice(&dev));
@@ -754,7 +791,7 @@ int ensure_workspace(hyperim_graph g, hipStream_t s, LaunchShape *shape) {
         HIM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_b, k_expand, kWG, 0));
         per_cu = std::max(per_cu, 1);
         per_cu_b = std::max(per_cu_b, 1);
-        const uint64_t per_slot = (uint64_t)n * 4u + (lds ? 0u : (uint64_t)words * 4u);
+        const uint64_t per_slot = (uint64_t)n_max * 4u + (lds ? 0u : (uint64_t)words * 4u);
         const uint64_t max_slots = std::max<uint64_t>(kSlotBudget / std::max<uint64_t>(per_slot, 1), 2 * kWavesPerWG);
         uint64_t grid = (uint64_t)cus * (uint64_t)per_cu;
         // phase A keeps at least half of the slots spare for deferred sets
@@ -766,7 +803,10 @@ int ensure_workspace(hyperim_graph g, hipStream_t s, LaunchShape *shape) {
         ws.waves = (uint32_t)waves;
         ws.slots = (uint32_t)slots;
         ws.grid_b = (uint32_t)(cus * per_cu_b);
-        HIM_CHECK(ws.lists.reserve(sizeof(uint32_t) * (size_t)slots * std::max<uint32_t>(n, 1), s));
+        ws.slot_n = std::max<uint32_t>(n_max, 1);
+        ws.slot_words = words;
+        ws.lds = lds;
+        HIM_CHECK(ws.lists.reserve(sizeof(uint32_t) * (size_t)slots * ws.slot_n, s));
         if (!lds) {
             HIM_CHECK(ws.bitmaps.reserve(sizeof(uint32_t) * (size_t)slots * words, s));
             HIM_HIP(hipMemsetAsync(ws.bitmaps.ptr, 0, sizeof(uint32_t) * (size_t)slots * words, s));
@@ -774,20 +814,22 @@ int ensure_workspace(hyperim_graph g, hipStream_t s, LaunchShape *shape) {
         HIM_CHECK(ws.counters.reserve(sizeof(unsigned long long) * kNumCtr, s));
         const size_t ndef = std::max<uint64_t>(slots - waves, 1);
         HIM_CHECK(ws.def_idx.reserve(sizeof(uint64_t) * ndef, s));
-        HIM_CHECK(ws.def_u32.reserve(sizeof(uint32_t) * 4 * ndef, s));
+        HIM_CHECK(ws.def_u32.reserve(sizeof(uint32_t) * 5 * ndef, s));
         HIM_CHECK(ws.items.reserve(sizeof(uint4) * (size_t)kItemCap, s));
     }
     shape->grid = ws.grid;
     shape->slots = ws.slots;
     shape->grid_b = ws.grid_b;
+    shape->slot_n = ws.slot_n;
+    shape->slot_words = ws.slot_words;
     shape->lds = lds;
     return HYPERIM_OK;
 }
 
 // Id ranges of every (ladder block, stratum) pair inside [id_begin, id_end).
-void stratum_ranges(hyperim_graph g, const RRKey &key, uint32_t pool, uint64_t id_begin, uint64_t id_end,
-                    std::vector<std::pair<uint64_t, uint64_t>> *out) {
-    const uint64_t Q = 1ull << key.qlog;
+void stratum_ranges(hyperim_graph g, uint64_t seed, uint32_t instance, uint32_t qlog, uint32_t pool,
+                    uint64_t id_begin, uint64_t id_end, std::vector<std::pair<uint64_t, uint64_t>> *out) {
+    const uint64_t Q = 1ull << qlog;
     const uint32_t n = g->n;
     uint64_t j = id_begin;
     while (j < id_end) {
@@ -799,11 +841,11 @@ void stratum_ranges(hyperim_graph g, const RRKey &key, uint32_t pool, uint64_t i
             T = Q;
         } else {
             uint32_t hb = 63u - (uint32_t)__builtin_clzll(j);
-            b = hb - key.qlog + 1u;
+            b = hb - qlog + 1u;
             J = 1ull << hb;
             T = J;
         }
-        const uint4 r = philox4x32_10(root_counter(b, pool), make_uint2((uint32_t)key.seed, key.instance));
+        const uint4 r = philox4x32_10(root_counter(b, pool), make_uint2((uint32_t)seed, instance));
         const uint64_t x = (uint64_t)r.x | ((uint64_t)r.y << 32);
         const uint64_t o = (uint64_t)(((unsigned __int128)x * n) >> 64);
         uint64_t prev = 0;
@@ -833,8 +875,8 @@ int read_ctr(hipStream_t s, const unsigned long long *dev, int idx, uint64_t *ou
     return HYPERIM_OK;
 }
 
-int event_pair(RRWorkspace &ws, size_t i) {
-    while (ws.events.size() < 2 * (i + 1)) {
+int event_pair(RRWorkspace &ws) {
+    while (ws.events.size() < 2) {
         hipEvent_t e;
         HIM_HIP(hipEventCreate(&e));
         ws.events.push_back(e);
@@ -844,15 +886,15 @@ int event_pair(RRWorkspace &ws, size_t i) {
 
 // One launch group: phase A over `a`'s tasks, then phase B over the sets it
 // deferred.  Per-id outputs land at a.out_base + launch index.
-int run_launch(hyperim_graph g, RRArgs &a, const LaunchShape &shape, uint32_t grid, bool trace, hipStream_t s) {
-    RRWorkspace &ws = g->rr;
+int run_launch(RRWorkspace &ws, RRStats &st, const hyperim_tuning &tune, RRArgs &a, const LaunchShape &shape,
+               uint32_t grid, bool trace, hipStream_t s) {
     unsigned long long *ctr = a.ctr;
     // fresh work counter, deferred list and spare-slot cursor
     const unsigned long long first_free = (unsigned long long)shape.grid * kWavesPerWG;
     HIM_HIP(hipMemsetAsync(ctr + kWork, 0, sizeof(unsigned long long), s));
     HIM_HIP(hipMemsetAsync(ctr + kDefCount, 0, sizeof(unsigned long long), s));
     HIM_HIP(hipMemcpyAsync(ctr + kFreeNext, &first_free, sizeof(unsigned long long), hipMemcpyHostToDevice, s));
-    HIM_CHECK(event_pair(ws, 0));
+    HIM_CHECK(event_pair(ws));
     HIM_HIP(hipEventRecord(ws.events[0], s));
     if (shape.lds)
         hipLaunchKernelGGL(k_rr_light<true>, dim3(grid), dim3(kWG), 0, s, a);
@@ -864,16 +906,16 @@ int run_launch(hyperim_graph g, RRArgs &a, const LaunchShape &shape, uint32_t gr
     HIM_CHECK(read_ctr(s, ctr, kDefCount, &ndef));
     float ms = 0.f;
     HIM_HIP(hipEventElapsedTime(&ms, ws.events[0], ws.events[1]));
-    ws.ms_bfs += ms;
-    ws.ms_light += ms;
-    ws.launches += 1;
+    st.ms_bfs += ms;
+    st.ms_light += ms;
+    st.launches += 1;
     if (ndef == 0) return HYPERIM_OK;
     // phase B: supersteps over the deferred sets
     const uint32_t plan_grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(div_up(ndef, kWavesPerWG), 4096));
     // every superstep with items advances some queue head, and a set holds at
     // most n members, so n supersteps per set bound the loop
-    const int per_sync = (int)std::max<uint32_t>(ws.tune.steps_per_sync, 1);
-    const uint64_t max_steps = (uint64_t)g->n * ndef + 2 * (uint64_t)per_sync;
+    const int per_sync = (int)std::max<uint32_t>(tune.steps_per_sync, 1);
+    const uint64_t max_steps = (uint64_t)a.slot_n * ndef + 2 * (uint64_t)per_sync;
     uint64_t steps = 0;
     HIM_HIP(hipMemsetAsync(ctr + kItems, 0, 2 * sizeof(unsigned long long), s));
     for (;;) {
@@ -898,10 +940,10 @@ int run_launch(hyperim_graph g, RRArgs &a, const LaunchShape &shape, uint32_t gr
         if (trace)
             fprintf(stderr, "[hyperim] superstep %llu: %llu items, %.3f ms\n", (unsigned long long)steps,
                     (unsigned long long)items, ms);
-        ws.ms_bfs += ms;
-        ws.ms_heavy += ms;
-        ws.launches += 2 * batch;
-        ws.supersteps += batch;
+        st.ms_bfs += ms;
+        st.ms_heavy += ms;
+        st.launches += 2 * batch;
+        st.supersteps += batch;
         if (items == 0) break;   // the last superstep found no frontier left
     }
     HIM_HIP(hipEventRecord(ws.events[0], s));
@@ -910,32 +952,46 @@ int run_launch(hyperim_graph g, RRArgs &a, const LaunchShape &shape, uint32_t gr
     HIM_HIP(hipEventRecord(ws.events[1], s));
     HIM_HIP(hipEventSynchronize(ws.events[1]));
     HIM_HIP(hipEventElapsedTime(&ms, ws.events[0], ws.events[1]));
-    ws.ms_bfs += ms;
-    ws.ms_heavy += ms;
-    ws.launches += 1;
-    ws.deferred += ndef;
+    st.ms_bfs += ms;
+    st.ms_heavy += ms;
+    st.launches += 1;
+    st.deferred += ndef;
     return HYPERIM_OK;
 }
 
 }  // namespace
 
-int rr_generate_stage(hyperim_graph g, const RRKey &key, const std::vector<RRTask> &tasks, int form, hipStream_t s,
-                      uint64_t *total) {
-    RRWorkspace &ws = g->rr;
+int rr_generate_stage(RRWorkspace &ws, RRStats &st, const std::vector<RRTask> &tasks, uint32_t qlog, int form,
+                      hipStream_t s, uint64_t *total) {
     // HYPERIM_TRACE=1: synchronise after every grid-wide superstep and report
     // its item count and time on stderr (diagnostics; same results)
     static const bool trace = [] {
         const char *e = getenv("HYPERIM_TRACE");
         return e && e[0] == '1';
     }();
-    if (tasks.empty() || tasks.size() > kMaxTasks) {
-        set_error_detail("1 to 4 generation tasks per call");
+    if (tasks.empty()) {
+        set_error_detail("no generation task");
         return HYPERIM_EINVAL;
+    }
+    // execution parameters of the first task's graph
+    const hyperim_tuning &tune = tasks[0].g->tune;
+    // graph descriptors (one per distinct graph)
+    std::map<hyperim_graph, uint32_t> gid;
+    std::vector<GraphDesc> gdesc;
+    uint32_t n_max = 1;
+    for (const RRTask &t : tasks) {
+        if (gid.count(t.g)) continue;
+        gid[t.g] = (uint32_t)gdesc.size();
+        hyperim_graph g = t.g;
+        gdesc.push_back(GraphDesc{g->he_off.as<uint32_t>(), g->he_mem.as<uint32_t>(), g->v_off.as<uint32_t>(),
+                                  g->v_he.as<uint32_t>(), g->thr.as<uint32_t>(), g->P.as<uint32_t>(), g->n,
+                                  (g->n + 31u) / 32u});
+        n_max = std::max(n_max, g->n);
     }
     uint64_t count = 0;
     for (const RRTask &t : tasks) count += t.id_end - t.id_begin;
     LaunchShape shape;
-    HIM_CHECK(ensure_workspace(g, s, &shape));
+    HIM_CHECK(ensure_workspace(ws, n_max, s, &shape));
     HIM_CHECK(ws.stage_off.reserve(sizeof(uint64_t) * std::max<uint64_t>(count, 1), s, false));
     HIM_CHECK(ws.sizes.reserve(sizeof(uint32_t) * std::max<uint64_t>(count, 1), s, false));
     HIM_CHECK(ws.roots.reserve(sizeof(uint32_t) * std::max<uint64_t>(count, 1), s, false));
@@ -945,31 +1001,70 @@ int rr_generate_stage(hyperim_graph g, const RRKey &key, const std::vector<RRTas
     if (ws.stage.bytes < sizeof(uint32_t) * predicted)
         HIM_CHECK(ws.stage.reserve(sizeof(uint32_t) * predicted, s, false));
 
-    unsigned long long *ctr = ws.counters.as<unsigned long long>();
+    // launch groups: [index lo, index hi) of the tasks laid back to back, each
+    // with its task descriptors
+    struct Group {
+        uint64_t lo, hi;
+        size_t first_desc, ndesc;
+    };
+    std::vector<Group> groups;
+    std::vector<TaskDesc> tdesc;
     const size_t ndef_cap = std::max<uint64_t>(shape.slots - (uint64_t)shape.grid * kWavesPerWG, 1);
-    // launch groups no larger than the spare slots can absorb at the deferral
-    // rate seen so far (a set that finds no spare slot stays with its wave)
-    const double rate = std::max(ws.defer_rate * 1.25, 1.0 / 64.0);
-    const uint64_t chunk = std::max<uint64_t>((uint64_t)((double)ndef_cap / rate), 4096);
+    if (form == 0) {
+        // cut so that the sets a group defers fit the spare slots at the
+        // deferral rate seen so far (a set that finds no spare slot stays with
+        // its wave)
+        const double rate = std::max(ws.defer_rate * 1.25, 1.0 / 64.0);
+        const uint64_t chunk = std::max<uint64_t>((uint64_t)((double)ndef_cap / rate), 4096);
+        for (uint64_t lo = 0; lo < count; lo += chunk) {
+            const uint64_t hi = std::min(count, lo + chunk);
+            Group gr{lo, hi, tdesc.size(), 0};
+            uint64_t tstart = 0;
+            for (const RRTask &t : tasks) {
+                const uint64_t tn = t.id_end - t.id_begin;
+                const uint64_t a0 = std::max(lo, tstart), a1 = std::min(hi, tstart + tn);
+                if (a0 < a1)
+                    tdesc.push_back(TaskDesc{a1 - lo, t.id_begin + (a0 - tstart), t.pool, gid[t.g], (uint32_t)t.seed,
+                                             t.instance});
+                tstart += tn;
+            }
+            gr.ndesc = tdesc.size() - gr.first_desc;
+            groups.push_back(gr);
+        }
+    } else {
+        // plain form: one launch group per (task, ladder block, stratum)
+        uint64_t tstart = 0;
+        for (const RRTask &t : tasks) {
+            std::vector<std::pair<uint64_t, uint64_t>> ranges;
+            stratum_ranges(t.g, t.seed, t.instance, qlog, t.pool, t.id_begin, t.id_end, &ranges);
+            for (const auto &rg : ranges) {
+                const uint64_t lo = tstart + (rg.first - t.id_begin);
+                groups.push_back(Group{lo, lo + (rg.second - rg.first), tdesc.size(), 1});
+                tdesc.push_back(TaskDesc{rg.second - rg.first, rg.first, t.pool, gid[t.g], (uint32_t)t.seed,
+                                         t.instance});
+            }
+            tstart += t.id_end - t.id_begin;
+        }
+    }
+    HIM_CHECK(ws.graph_desc.reserve(sizeof(GraphDesc) * gdesc.size(), s));
+    HIM_CHECK(ws.task_desc.reserve(sizeof(TaskDesc) * std::max<size_t>(tdesc.size(), 1), s));
+    HIM_HIP(hipMemcpyAsync(ws.graph_desc.ptr, gdesc.data(), sizeof(GraphDesc) * gdesc.size(), hipMemcpyHostToDevice, s));
+    HIM_HIP(hipMemcpyAsync(ws.task_desc.ptr, tdesc.data(), sizeof(TaskDesc) * tdesc.size(), hipMemcpyHostToDevice, s));
+    HIM_HIP(hipStreamSynchronize(s));   // host vectors are pageable and local
+
+    unsigned long long *ctr = ws.counters.as<unsigned long long>();
     for (int attempt = 0; attempt < 2; ++attempt) {
         HIM_HIP(hipMemsetAsync(ctr, 0, sizeof(unsigned long long) * kNumCtr, s));
         RRArgs a{};
-        a.he_off = g->he_off.as<uint32_t>();
-        a.he_mem = g->he_mem.as<uint32_t>();
-        a.v_off = g->v_off.as<uint32_t>();
-        a.v_he = g->v_he.as<uint32_t>();
-        a.thr = g->thr.as<uint32_t>();
-        a.P = g->P.as<uint32_t>();
-        a.n = g->n;
-        a.key0 = (uint32_t)key.seed;
-        a.key1 = key.instance;
-        a.qlog = key.qlog;
-        a.bm_words = (g->n + 31u) / 32u;
-        a.heavy = ws.tune.heavy;
-        a.budget = ws.tune.budget;
-        a.chunk = ws.tune.chunk;
-        a.seg = std::max(ws.tune.seg, ws.tune.chunk);
-        a.prefilter_min = ws.tune.prefilter_min;
+        a.graphs = ws.graph_desc.as<GraphDesc>();
+        a.qlog = qlog;
+        a.heavy = tune.heavy;
+        a.budget = tune.budget;
+        a.chunk = tune.chunk;
+        a.seg = std::max(tune.seg, tune.chunk);
+        a.prefilter_min = tune.prefilter_min;
+        a.slot_n = shape.slot_n;
+        a.slot_words = shape.slot_words;
         a.ctr = ctr;
         a.lists = ws.lists.as<uint32_t>();
         a.bitmaps = ws.bitmaps.as<uint32_t>();
@@ -985,60 +1080,36 @@ int rr_generate_stage(hyperim_graph g, const RRKey &key, const std::vector<RRTas
         a.def_slot = a.def_root + ndef_cap;
         a.def_head = a.def_slot + ndef_cap;
         a.def_size = a.def_head + ndef_cap;
+        a.def_task = a.def_size + ndef_cap;
         a.items = ws.items.as<uint4>();
-        const uint64_t deferred_before = ws.deferred;
-        if (form == 0) {
-            // the tasks back to back, cut into launch groups of at most `chunk` indices
-            for (uint64_t lo = 0; lo < count; lo += chunk) {
-                const uint64_t hi = std::min(count, lo + chunk);
-                a.ntasks = 0;
-                uint64_t tstart = 0;
-                for (const RRTask &t : tasks) {
-                    const uint64_t tn = t.id_end - t.id_begin;
-                    const uint64_t a0 = std::max(lo, tstart), a1 = std::min(hi, tstart + tn);
-                    if (a0 < a1) {
-                        a.t_id[a.ntasks] = t.id_begin + (a0 - tstart);
-                        a.t_pool[a.ntasks] = t.pool;
-                        a.t_end[a.ntasks] = a1 - lo;
-                        ++a.ntasks;
-                    }
-                    tstart += tn;
-                }
-                a.count = hi - lo;
-                a.out_base = lo;
-                HIM_CHECK(run_launch(g, a, shape, shape.grid, trace, s));
-            }
-        } else {
-            // plain form: one launch group per (task, ladder block, stratum)
-            uint64_t task_base = 0;
-            for (const RRTask &t : tasks) {
-                std::vector<std::pair<uint64_t, uint64_t>> ranges;
-                stratum_ranges(g, key, t.pool, t.id_begin, t.id_end, &ranges);
-                for (const auto &rg : ranges) {
-                    a.ntasks = 1;
-                    a.count = rg.second - rg.first;
-                    a.t_end[0] = a.count;
-                    a.t_id[0] = rg.first;
-                    a.t_pool[0] = t.pool;
-                    a.out_base = task_base + (rg.first - t.id_begin);
-                    const uint32_t grid = (uint32_t)std::min<uint64_t>(shape.grid, div_up(a.count, kWavesPerWG));
-                    HIM_CHECK(run_launch(g, a, shape, grid, trace, s));
-                }
-                task_base += t.id_end - t.id_begin;
-            }
+        RRStats run{};
+        for (const Group &gr : groups) {
+            a.tasks = ws.task_desc.as<TaskDesc>() + gr.first_desc;
+            a.ntasks = (uint32_t)gr.ndesc;
+            a.count = gr.hi - gr.lo;
+            a.out_base = gr.lo;
+            const uint32_t grid =
+                form == 0 ? shape.grid : (uint32_t)std::min<uint64_t>(shape.grid, div_up(a.count, kWavesPerWG));
+            HIM_CHECK(run_launch(ws, run, tune, a, shape, grid, trace, s));
         }
+        // time counts every attempt, work only the one that produced the output
+        st.ms_bfs += run.ms_bfs;
+        st.ms_light += run.ms_light;
+        st.ms_heavy += run.ms_heavy;
+        st.launches += run.launches;
+        st.supersteps += run.supersteps;
         uint64_t bump = 0, ba = 0, bb = 0;
         HIM_CHECK(read_ctr(s, ctr, kBump, &bump));
         HIM_CHECK(read_ctr(s, ctr, kBytesA, &ba));
         HIM_CHECK(read_ctr(s, ctr, kBytesB, &bb));
         if (count) {
             ws.members_per_id = (double)bump / (double)count;
-            ws.defer_rate = (double)(ws.deferred - deferred_before) / (double)count;
+            ws.defer_rate = (double)run.deferred / (double)count;
         }
         if (bump <= ws.stage.bytes / sizeof(uint32_t)) {
-            // bytes of the run that produced the output (time counts every run)
-            ws.bytes_light += ba;
-            ws.bytes_heavy += bb;
+            st.deferred += run.deferred;
+            st.bytes_light += ba;
+            st.bytes_heavy += bb;
             *total = bump;
             return HYPERIM_OK;
         }
@@ -1048,9 +1119,8 @@ int rr_generate_stage(hyperim_graph g, const RRKey &key, const std::vector<RRTas
     return HYPERIM_ENOMEM;
 }
 
-int rr_compact_into(hyperim_graph g, hyperim_pool p, uint64_t first, uint64_t count, uint64_t max_entries,
+int rr_compact_into(RRWorkspace &ws, hyperim_pool p, uint64_t first, uint64_t count, uint64_t max_entries,
                     hipStream_t s) {
-    RRWorkspace &ws = g->rr;
     if (count == 0) return HYPERIM_OK;
     HIM_CHECK(pool_reserve(p, count, 0, s));
     uint64_t *dst_off = p->off + p->count;
