@@ -119,6 +119,9 @@ typedef struct {
     uint64_t supersteps;    /* grid-wide supersteps launched                   */
     uint64_t bytes_light;   /* algorithmic bytes expanded by the per-set phase */
     uint64_t bytes_heavy;   /* algorithmic bytes expanded by the grid-wide one */
+    double ms_expand;       /* part of ms_heavy spent in the expansion kernel
+                               itself (HIP events around each launch)          */
+    uint64_t expand_launches; /* its launches (one per superstep)              */
 } hyperim_result;
 
 /* Build the device-resident hypergraph (Section 2.1: G = (V, HE), V(he)).

@@ -75,6 +75,8 @@ struct RRStats {
     double ms_bfs = 0.0, ms_light = 0.0, ms_heavy = 0.0;  // all / phase A / phase B kernels
     uint64_t launches = 0, supersteps = 0, deferred = 0;
     uint64_t bytes_light = 0, bytes_heavy = 0;   // algorithmic bytes expanded in each phase
+    double ms_expand = 0.0;                      // k_expand launches alone
+    uint64_t expand_launches = 0;
 };
 
 // The device's shared RR workspace, locked for the caller's lifetime.

@@ -258,6 +258,8 @@ int run_round(const std::vector<QueryRun *> &qs, const hyperim_options &o, hipSt
         res.supersteps += st.supersteps;
         res.bytes_light += st.bytes_light;
         res.bytes_heavy += st.bytes_heavy;
+        res.ms_expand += st.ms_expand;
+        res.expand_launches += st.expand_launches;
         hyperim_graph g = q->q.graph;
         const uint64_t theta = q->next_theta(o);
         const uint32_t k = q->q.k;

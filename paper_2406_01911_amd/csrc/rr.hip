@@ -875,8 +875,10 @@ int read_ctr(hipStream_t s, const unsigned long long *dev, int idx, uint64_t *ou
     return HYPERIM_OK;
 }
 
+// events[0..1] bracket a phase; events[2 + 2i], events[3 + 2i] bracket the
+// i-th k_expand launch of a superstep batch
 int event_pair(RRWorkspace &ws) {
-    while (ws.events.size() < 2) {
+    while (ws.events.size() < 2 + 2 * 64) {
         hipEvent_t e;
         HIM_HIP(hipEventCreate(&e));
         ws.events.push_back(e);
@@ -929,7 +931,9 @@ int run_launch(RRWorkspace &ws, RRStats &st, const hyperim_tuning &tune, RRArgs 
         for (int step = 0; step < batch; ++step) {
             parity = (uint32_t)((steps + step) & 1u);
             hipLaunchKernelGGL(k_plan, dim3(plan_grid), dim3(kWG), 0, s, a, (uint32_t)ndef, parity);
+            HIM_HIP(hipEventRecord(ws.events[2 + 2 * step], s));
             hipLaunchKernelGGL(k_expand, dim3(shape.grid_b), dim3(kWG), 0, s, a, parity);
+            HIM_HIP(hipEventRecord(ws.events[3 + 2 * step], s));
         }
         steps += batch;
         HIM_HIP(hipGetLastError());
@@ -937,6 +941,12 @@ int run_launch(RRWorkspace &ws, RRStats &st, const hyperim_tuning &tune, RRArgs 
         uint64_t items = 0;
         HIM_CHECK(read_ctr(s, ctr, kItems + (int)parity, &items));
         HIM_HIP(hipEventElapsedTime(&ms, ws.events[0], ws.events[1]));
+        for (int step = 0; step < batch; ++step) {
+            float me = 0.f;
+            HIM_HIP(hipEventElapsedTime(&me, ws.events[2 + 2 * step], ws.events[3 + 2 * step]));
+            st.ms_expand += me;
+        }
+        st.expand_launches += batch;
         if (trace)
             fprintf(stderr, "[hyperim] superstep %llu: %llu items, %.3f ms\n", (unsigned long long)steps,
                     (unsigned long long)items, ms);
@@ -1098,6 +1108,8 @@ int rr_generate_stage(RRWorkspace &ws, RRStats &st, const std::vector<RRTask> &t
         st.ms_heavy += run.ms_heavy;
         st.launches += run.launches;
         st.supersteps += run.supersteps;
+        st.ms_expand += run.ms_expand;
+        st.expand_launches += run.expand_launches;
         uint64_t bump = 0, ba = 0, bb = 0;
         HIM_CHECK(read_ctr(s, ctr, kBump, &bump));
         HIM_CHECK(read_ctr(s, ctr, kBytesA, &ba));
