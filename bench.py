@@ -142,14 +142,19 @@ def main():
             g.stratify(stream=stream)
             gs.append(g)
         if args.workload != "multi":
-            return [hy.select_seeds(gs[0], w.k, w.eps, w.ell, seed=w.philox_seed, form=form, flags=flags,
-                                    stream=stream)]
+            r = hy.select_seeds(gs[0], w.k, w.eps, w.ell, seed=w.philox_seed, form=form, flags=flags,
+                                stream=stream)
+            return [r], r
         if form == 0:
-            return hy.select_seeds_batch([dict(graph=g, k=wl.k, eps=wl.eps, ell=wl.ell, seed=wl.philox_seed,
-                                               instance=i) for i, (g, wl) in enumerate(zip(gs, ws))],
-                                         flags=flags, stream=stream)
-        return [hy.select_seeds(g, wl.k, wl.eps, wl.ell, seed=wl.philox_seed, instance=i, form=1, flags=flags,
-                                stream=stream) for i, (g, wl) in enumerate(zip(gs, ws))]
+            tot = {}
+            rs = hy.select_seeds_batch([dict(graph=g, k=wl.k, eps=wl.eps, ell=wl.ell, seed=wl.philox_seed,
+                                             instance=i) for i, (g, wl) in enumerate(zip(gs, ws))],
+                                       flags=flags, stream=stream, totals=tot)
+            return rs, tot
+        rs = [hy.select_seeds(g, wl.k, wl.eps, wl.ell, seed=wl.philox_seed, instance=i, form=1, flags=flags,
+                              stream=stream) for i, (g, wl) in enumerate(zip(gs, ws))]
+        tot = {k: sum(r[k] for r in rs) for k in rs[0] if k not in ("seeds", "gains")}
+        return rs, tot
 
     if args.copy_calibration:
         nbytes = args.copy_calibration << 20
@@ -171,55 +176,55 @@ def main():
         torch.cuda.synchronize()
         return out, time.perf_counter() - t0
 
-    results, elapsed = timed(args.steps, args.warmup, args.form)
+    steps_out, elapsed = timed(args.steps, args.warmup, args.form)
+    results = [r for r, _ in steps_out]
+    totals = [t for _, t in steps_out]
     print(f"[bench] {args.steps} steps of form {args.form}: {elapsed:.3f} s", file=sys.stderr, flush=True)
     plain_steps = args.plain_steps if args.plain_steps >= 0 else (0 if args.workload == "large" else args.steps)
     plain = None
     if plain_steps and args.form == 0:
         pres, pel = timed(plain_steps, 1, 1)
-        for a, b in zip(pres[-1], results[-1]):
+        for a, b in zip(pres[-1][0], results[-1]):
             assert np.array_equal(a["seeds"], b["seeds"]) and a["theta"] == b["theta"]
         plain = {"form": "plain per-stratum launches, one query at a time", "steps": plain_steps,
                  "ms_per_step": 1000.0 * pel / plain_steps}
         print(f"[bench] {plain_steps} steps of the plain form: {pel:.3f} s", file=sys.stderr, flush=True)
     # identical step with the incidence / byte counters switched on (untimed)
-    meas = step(flags=hy.FLAG_INCIDENCES)
+    meas, mtot = step(flags=hy.FLAG_INCIDENCES)
     last = results[-1]
     for a, b in zip(meas, last):
         assert np.array_equal(a["seeds"], b["seeds"]) and a["theta"] == b["theta"]
-    # the query that ran every round took part in every shared launch
-    lead = max(range(len(last)), key=lambda i: last[i]["rounds"])
 
-    def shared(rs, key):
-        return float(np.mean([r[lead][key] for r in rs]))
+    def mean_total(key):
+        return float(np.mean([t[key] for t in totals]))
 
     ms_per_step = 1000.0 * elapsed / args.steps
     rr_sets_per_step = sum(2 * r["theta"] for r in last)
     value = rr_sets_per_step * args.steps / elapsed
-    incidences = sum(r["incidences"] for r in meas)
+    incidences = mtot["incidences"]
     inc_per_s = incidences * args.steps / elapsed
-    bfs_ms = shared(results, "ms_bfs")
-    ms_light = shared(results, "ms_light")
-    ms_heavy = shared(results, "ms_heavy")
-    launches = last[lead]["bfs_launches"]
-    alg_bytes = sum(r["alg_bytes"] for r in meas)
-    bytes_light, bytes_heavy = meas[lead]["bytes_light"], meas[lead]["bytes_heavy"]
+    bfs_ms = mean_total("ms_bfs")
+    ms_light = mean_total("ms_light")
+    ms_heavy = mean_total("ms_heavy")
+    launches = totals[-1]["bfs_launches"]
+    alg_bytes = mtot["alg_bytes"]
+    bytes_light, bytes_heavy = mtot["bytes_light"], mtot["bytes_heavy"]
     # the kernels count the bytes of every expansion they perform; together
     # they must equal the total recomputed from the output sets
     assert bytes_light + bytes_heavy == alg_bytes, (bytes_light, bytes_heavy, alg_bytes)
     achieved_all = alg_bytes / (bfs_ms * 1e-3) / 1e9 if bfs_ms > 0 else 0.0
     # dominant kernel: k_expand (the grid-wide expansion); its own HIP-event
     # time over the timed steps and the algorithmic bytes it expanded
-    ms_expand = shared(results, "ms_expand")
-    expand_launches = last[lead]["expand_launches"]
+    ms_expand = mean_total("ms_expand")
+    expand_launches = totals[-1]["expand_launches"]
     achieved = bytes_heavy / (ms_expand * 1e-3) / 1e9 if ms_expand > 0 else 0.0
     traffic = expand_traffic(args.workload)
     phases = {
         "per_set_phase": {"kernel": "k_rr_light", "ms": ms_light, "alg_bytes": bytes_light,
                           "GBps": bytes_light / (ms_light * 1e-3) / 1e9 if ms_light > 0 else 0.0},
         "grid_wide_phase": {"kernels": "k_plan + k_expand + k_finish", "ms": ms_heavy,
-                            "alg_bytes": bytes_heavy, "deferred_sets": meas[lead]["deferred"],
-                            "supersteps": meas[lead]["supersteps"],
+                            "alg_bytes": bytes_heavy, "deferred_sets": mtot["deferred"],
+                            "supersteps": mtot["supersteps"],
                             "GBps": bytes_heavy / (ms_heavy * 1e-3) / 1e9 if ms_heavy > 0 else 0.0},
     }
     line = {
@@ -243,8 +248,8 @@ def main():
         "theta": [r["theta"] for r in last] if len(last) > 1 else last[0]["theta"],
         "rounds": max(r["rounds"] for r in last),
         "spread": [r["spread"] for r in last] if len(last) > 1 else last[0]["spread"],
-        "ms_rr": shared(results, "ms_rr"),
-        "ms_greedy": float(np.mean([sum(q["ms_greedy"] for q in r) for r in results])),
+        "ms_rr": mean_total("ms_rr"),
+        "ms_greedy": mean_total("ms_greedy"),
         "rr_phases": phases,
         "roofline": {
             "kernel": "k_expand",

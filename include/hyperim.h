@@ -233,13 +233,19 @@ typedef struct {
  * hyperim_select_seeds on that query alone; timings cover the shared launches
  * the query took part in.  seeds and gains (may be NULL) are host arrays
  * holding query 0's k_0 entries, then query 1's, and so on; results[count]
- * and status[count] may be NULL.  Returns HYPERIM_OK when every query
+ * and status[count] may be NULL.  *total (may be NULL) receives the whole
+ * batch: rounds = rounds run, theta / entries / incidences / alg_bytes summed
+ * over the queries, device times and kernel counters of every launch once,
+ * ms_total the wall time.  Queries are admitted as the device memory allows
+ * (as in a session whose budget is the memory free at the call plus what the
+ * batch already holds, less 4 GiB); the first sample of R1 on a graph not
+ * seen before also sizes its admission.  Returns HYPERIM_OK when every query
  * succeeded, else the first failing query's status (status[] tells which);
  * a malformed query (as for hyperim_select_seeds) fails the whole call with
  * HYPERIM_EINVAL before any work. */
 int hyperim_select_seeds_batch(const hyperim_query *queries, uint32_t count, const hyperim_options *opt,
                                void *stream, uint32_t *seeds, uint64_t *gains, hyperim_result *results,
-                               int *status);
+                               int *status, hyperim_result *total);
 
 /* Serving session: queries are submitted at any time and advanced together,
  * one doubling round of every admitted query per hyperim_session_step
@@ -298,10 +304,13 @@ int hyperim_workspace_release(void);
  *                  raised to chunk if smaller);
  *   prefilter_min: the grid-wide phase tests visited marks before coins in
  *                  sets of at least this many members (4096);
- *   steps_per_sync: grid-wide supersteps launched between host checks (8). */
+ *   steps_per_sync: grid-wide supersteps launched between host checks (8);
+ *   stage_mib:     staging memory a generation pass aims at: launch groups
+ *                  are cut so that their members fit (16384 MiB, min 64). */
 typedef struct {
     uint32_t heavy, budget, chunk, seg, prefilter_min, steps_per_sync;
-    uint32_t reserved[2];
+    uint32_t stage_mib;
+    uint32_t reserved;
 } hyperim_tuning;
 
 /* Set / read the execution parameters of graph g (host-side values).  A

@@ -57,7 +57,8 @@ class _Result(C.Structure):
 
 class _Tuning(C.Structure):
     _fields_ = [("heavy", C.c_uint32), ("budget", C.c_uint32), ("chunk", C.c_uint32), ("seg", C.c_uint32),
-                ("prefilter_min", C.c_uint32), ("steps_per_sync", C.c_uint32), ("reserved", C.c_uint32 * 2)]
+                ("prefilter_min", C.c_uint32), ("steps_per_sync", C.c_uint32), ("stage_mib", C.c_uint32),
+                ("reserved", C.c_uint32)]
 
 
 class _Query(C.Structure):
@@ -71,7 +72,7 @@ class _SessionStats(C.Structure):
                 ("ran_last", C.c_uint64), ("bytes_resident", C.c_size_t), ("hbm_budget", C.c_size_t)]
 
 
-TUNING_FIELDS = ["heavy", "budget", "chunk", "seg", "prefilter_min", "steps_per_sync"]
+TUNING_FIELDS = ["heavy", "budget", "chunk", "seg", "prefilter_min", "steps_per_sync", "stage_mib"]
 
 EXPORTS = ["hyperim_build_graph", "hyperim_stratify", "hyperim_graph_read", "hyperim_pool_create",
            "hyperim_generate_rr", "hyperim_pool_view", "hyperim_pool_read", "hyperim_pool_required",
@@ -109,7 +110,7 @@ def load_library(path: str = LIB_PATH):
     L.hyperim_select_seeds.argtypes = [vp, u32, C.c_double, C.c_double, u64, u32, C.POINTER(_Options), vp, vp, vp,
                                        C.POINTER(_Result)]
     L.hyperim_select_seeds_batch.argtypes = [C.POINTER(_Query), u32, C.POINTER(_Options), vp, vp, vp,
-                                             C.POINTER(_Result), C.POINTER(i32)]
+                                             C.POINTER(_Result), C.POINTER(i32), C.POINTER(_Result)]
     L.hyperim_session_create.argtypes = [C.c_size_t, C.POINTER(_Options), vp, C.POINTER(vp)]
     L.hyperim_session_submit.argtypes = [vp, C.POINTER(_Query), C.POINTER(u64)]
     L.hyperim_session_step.argtypes = [vp, C.POINTER(_SessionStats)]
@@ -324,11 +325,12 @@ def _query(q) -> _Query:
 
 
 def select_seeds_batch(queries, qlog: int = 0, form: int = 0, theta_fixed: int = 0, max_entries: int = 0,
-                       flags: int = 0, stream=None, raise_on_error: bool = True) -> list:
+                       flags: int = 0, stream=None, raise_on_error: bool = True, totals: dict | None = None) -> list:
     """hyperim_select_seeds_batch: queries answered together (shared RR launches).
 
     Each query is a dict {graph, k, eps, ell, seed, instance}; returns one dict
-    per query (seeds, gains, result fields, status)."""
+    per query (seeds, gains, result fields, status).  If `totals` is a dict it
+    receives the whole-batch result fields."""
     qs = [_query(q) for q in queries]
     arr = (_Query * max(len(qs), 1))(*qs)
     ks = [q.k for q in qs]
@@ -337,8 +339,11 @@ def select_seeds_batch(queries, qlog: int = 0, form: int = 0, theta_fixed: int =
     res = (_Result * max(len(qs), 1))()
     status = (C.c_int * max(len(qs), 1))()
     opt = _Options(qlog, form, theta_fixed, max_entries, flags, 0)
+    tot = _Result()
     rc = _lib.hyperim_select_seeds_batch(arr, len(qs), C.byref(opt), _stream(stream), _ptr(seeds), _ptr(gains),
-                                         res, status)
+                                         res, status, C.byref(tot))
+    if totals is not None:
+        totals.update(_result_dict(tot))
     if raise_on_error:
         _check(rc)
     out, at = [], 0

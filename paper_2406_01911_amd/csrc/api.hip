@@ -90,7 +90,8 @@ int pool_reserve(hyperim_pool p, uint64_t ids, uint64_t entries, hipStream_t s) 
 namespace {
 struct DevCtx {
     std::mutex mu;
-    RRWorkspace ws;
+    RRWorkspace rr;
+    GreedyWorkspace gr;
 };
 constexpr int kMaxDevices = 256;
 std::mutex g_ctx_mu;
@@ -104,14 +105,21 @@ DevCtx *device_ctx(int device) {
 }
 }  // namespace
 
-RRWorkspaceLock::RRWorkspaceLock(int device) {
+DeviceLock::DeviceLock(int device) {
     DevCtx *c = device_ctx(device);
     c->mu.lock();
-    ws = &c->ws;
+    rr = &c->rr;
+    gr = &c->gr;
     lock = c;
 }
 
-RRWorkspaceLock::~RRWorkspaceLock() { static_cast<DevCtx *>(lock)->mu.unlock(); }
+DeviceLock::~DeviceLock() { static_cast<DevCtx *>(lock)->mu.unlock(); }
+
+void GreedyWorkspace::release() {
+    for (DevBuf *x : {&cnt, &inv_off, &cursor, &inv, &covered, &chosen, &best, &out, &big, &round_big, &flags,
+                      &counters, &scan_tmp})
+        x->release();
+}
 
 size_t RRWorkspace::bytes() const {
     size_t b = 0;
@@ -138,8 +146,20 @@ size_t GreedyWorkspace::bytes() const {
     return b;
 }
 
+SharedBytes shared_bytes() {
+    SharedBytes b{0, 0, 0, 0};
+    int device = 0;
+    if (hipGetDevice(&device) != hipSuccess) return b;
+    DeviceLock lk(device);
+    b.slots = lk.rr->lists.bytes + lk.rr->bitmaps.bytes;
+    b.stage = lk.rr->bytes() - b.slots;
+    b.greedy = lk.gr->bytes();
+    b.total = b.slots + b.stage + b.greedy;
+    return b;
+}
+
 size_t graph_bytes(hyperim_graph g) {
-    size_t b = g->gr.bytes();
+    size_t b = 0;
     for (const DevBuf *x : {&g->he_off, &g->he_mem, &g->v_off, &g->v_he, &g->thr, &g->c, &g->weight, &g->bytesw, &g->l,
                             &g->deg, &g->top, &g->stratum, &g->P})
         b += x->bytes;
@@ -149,10 +169,6 @@ size_t graph_bytes(hyperim_graph g) {
 void release_graph(hyperim_graph g) {
     for (DevBuf *b : {&g->he_off, &g->he_mem, &g->v_off, &g->v_he, &g->thr, &g->c, &g->weight, &g->bytesw, &g->l,
                       &g->deg, &g->top, &g->stratum, &g->P})
-        b->release();
-    GreedyWorkspace &w = g->gr;
-    for (DevBuf *b : {&w.cnt, &w.inv_off, &w.cursor, &w.inv, &w.covered, &w.chosen, &w.best, &w.out, &w.big,
-                      &w.round_big, &w.flags, &w.counters, &w.scan_tmp})
         b->release();
 }
 
@@ -199,35 +215,31 @@ size_t pool_bytes(const hyperim_pool_s &p) { return p.off_b.bytes + p.roots_b.by
 int generate_into(const std::vector<RRTask> &tasks, const std::vector<hyperim_pool> &pools, uint32_t qlog, int form,
                   uint64_t max_entries, hipStream_t s, RRStats &st, std::vector<int> *pool_status) {
     std::vector<RRTask> live;
+    std::vector<hyperim_pool> dst;
     std::vector<size_t> which;
+    std::vector<bool> was_empty;
     for (size_t i = 0; i < tasks.size(); ++i)
         if (tasks[i].id_end > tasks[i].id_begin) {
             live.push_back(tasks[i]);
+            dst.push_back(pools[i]);
             which.push_back(i);
+            was_empty.push_back(pools[i]->count == 0);
         }
     if (pool_status) pool_status->assign(tasks.size(), HYPERIM_OK);
     if (live.empty()) return HYPERIM_OK;
     int device = 0;
     HIM_HIP(hipGetDevice(&device));
-    RRWorkspaceLock lk(device);
-    uint64_t total = 0;
-    HIM_CHECK(rr_generate_stage(*lk.ws, st, live, qlog, form, s, &total));
-    uint64_t first = 0;
+    DeviceLock lk(device);
+    std::vector<int> status;
+    const uint64_t stage_budget = (uint64_t)std::max<uint32_t>(live[0].g->tune.stage_mib, 64) << 20;
+    HIM_CHECK(rr_generate_into(*lk.rr, st, live, dst, qlog, form, max_entries, stage_budget, s, status));
     int first_fail = HYPERIM_OK;
     for (size_t i = 0; i < live.size(); ++i) {
-        const uint64_t count = live[i].id_end - live[i].id_begin;
-        hyperim_pool p = pools[which[i]];
-        const bool was_empty = p->count == 0;
-        const int rc = rr_compact_into(*lk.ws, p, first, count, max_entries, s);
-        if (rc == HYPERIM_OK) {
-            if (was_empty) p->id_begin = live[i].id_begin;
-        } else if (rc == HYPERIM_ECAPACITY && pool_status) {
-            (*pool_status)[which[i]] = rc;   // this pool is full; the others go on
-            if (first_fail == HYPERIM_OK) first_fail = rc;
-        } else {
-            return rc;
+        if (was_empty[i] && dst[i]->count) dst[i]->id_begin = live[i].id_begin;
+        if (status[i] != HYPERIM_OK) {
+            if (pool_status) (*pool_status)[which[i]] = status[i];
+            if (first_fail == HYPERIM_OK) first_fail = status[i];
         }
-        first += count;
     }
     return pool_status ? HYPERIM_OK : first_fail;
 }
@@ -445,7 +457,9 @@ int hyperim_greedy(hyperim_graph g, hyperim_pool pool, uint64_t theta, uint32_t 
         set_error_detail("need 1 <= k <= n and theta <= pool size < 2^32");
         return HYPERIM_EINVAL;
     }
-    return greedy_device(g, pool, theta, k, as_stream(stream), seeds, gains);
+    HIM_CHECK(check_device(g));
+    DeviceLock lk(g->device);
+    return greedy_device(*lk.gr, g, pool, theta, k, as_stream(stream), seeds, gains);
 }
 
 int hyperim_coverage(hyperim_graph g, hyperim_pool pool, uint64_t theta, const uint32_t *seeds, uint32_t k,
@@ -462,7 +476,11 @@ int hyperim_coverage(hyperim_graph g, hyperim_pool pool, uint64_t theta, const u
     DevBuf d;
     HIM_CHECK(d.reserve(sizeof(uint32_t) * std::max<uint32_t>(k, 1), s));
     if (k) HIM_HIP(hipMemcpyAsync(d.ptr, seeds, sizeof(uint32_t) * k, hipMemcpyHostToDevice, s));
-    int rc = coverage_device(g, pool, theta, d.as<uint32_t>(), k, s, covered);
+    int rc;
+    {
+        DeviceLock lk(g->device);
+        rc = coverage_device(*lk.gr, g, pool, theta, d.as<uint32_t>(), k, s, covered);
+    }
     d.release();
     return rc;
 }
@@ -477,6 +495,7 @@ int hyperim_set_tuning(hyperim_graph g, const hyperim_tuning *t) {
     cur.seg = std::max(cur.seg, cur.chunk);
     if (t->prefilter_min) cur.prefilter_min = t->prefilter_min;
     if (t->steps_per_sync) cur.steps_per_sync = std::min<uint32_t>(t->steps_per_sync, 64);
+    if (t->stage_mib) cur.stage_mib = std::max<uint32_t>(t->stage_mib, 64);
     return HYPERIM_OK;
 }
 
@@ -496,17 +515,18 @@ int hyperim_workspace_info(size_t *bytes) {
     if (!bytes) return HYPERIM_EINVAL;
     int device = 0;
     HIM_HIP(hipGetDevice(&device));
-    RRWorkspaceLock lk(device);
-    *bytes = lk.ws->bytes();
+    DeviceLock lk(device);
+    *bytes = lk.rr->bytes() + lk.gr->bytes();
     return HYPERIM_OK;
 }
 
 int hyperim_workspace_release(void) {
     int device = 0;
     HIM_HIP(hipGetDevice(&device));
-    RRWorkspaceLock lk(device);
+    DeviceLock lk(device);
     HIM_HIP(hipDeviceSynchronize());
-    lk.ws->release();
+    lk.rr->release();
+    lk.gr->release();
     return HYPERIM_OK;
 }
 

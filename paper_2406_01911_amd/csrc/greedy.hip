@@ -243,9 +243,8 @@ int big_list(hyperim_pool p, uint64_t theta, uint64_t *list, unsigned long long 
 
 }  // namespace
 
-int greedy_device(hyperim_graph g, hyperim_pool p, uint64_t theta, uint32_t k, hipStream_t s, uint32_t *seeds_host,
-                  uint64_t *gains_host) {
-    GreedyWorkspace &w = g->gr;
+int greedy_device(GreedyWorkspace &w, hyperim_graph g, hyperim_pool p, uint64_t theta, uint32_t k, hipStream_t s,
+                  uint32_t *seeds_host, uint64_t *gains_host) {
     const uint32_t n = g->n;
     uint64_t entries = 0;
     HIM_CHECK(read_entries(p, theta, s, &entries));
@@ -299,9 +298,8 @@ int greedy_device(hyperim_graph g, hyperim_pool p, uint64_t theta, uint32_t k, h
     return HYPERIM_OK;
 }
 
-int coverage_device(hyperim_graph g, hyperim_pool p, uint64_t theta, const uint32_t *seeds_dev, uint32_t k,
-                    hipStream_t s, uint64_t *covered_host) {
-    GreedyWorkspace &w = g->gr;
+int coverage_device(GreedyWorkspace &w, hyperim_graph g, hyperim_pool p, uint64_t theta, const uint32_t *seeds_dev,
+                    uint32_t k, hipStream_t s, uint64_t *covered_host) {
     const uint32_t n = g->n;
     HIM_CHECK(w.flags.reserve(n, s));
     HIM_CHECK(w.big.reserve(sizeof(uint64_t) * std::max<uint64_t>(theta, 1), s));

@@ -8,7 +8,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/hyperim.h"
+#include "hyperim.h"
 
 namespace hyperim {
 
@@ -31,10 +31,14 @@ void clear_error_detail();
         if (_rc != HYPERIM_OK) return _rc; \
     } while (0)
 
-// Growable device buffer (never shrinks). ---------------------------------------
+// Growable device buffer (never shrinks); frees its memory when destroyed.
 struct DevBuf {
     void *ptr = nullptr;
     size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf() { release(); }
     int reserve(size_t need, hipStream_t s, bool keep = false);
     void release();
     template <typename T>
@@ -56,8 +60,6 @@ struct RRWorkspace {
     DevBuf def_u32;              // deferred sets: root, slot, head, size, task (5 uint32 arrays)
     DevBuf graph_desc, task_desc;  // launch-group descriptors in device memory
     DevBuf items;                // phase B work items (uint4)
-    double members_per_id = 0.0;  // staged members per RR id in the last call (stage sizing)
-    double defer_rate = 0.5;      // deferred sets per RR id in the last call (launch-group sizing)
     DevBuf counters;             // work counter, stage bump, misc
     DevBuf stage;                // unsorted->sorted members before compaction
     DevBuf stage_off;            // per id (uint64)
@@ -79,17 +81,7 @@ struct RRStats {
     uint64_t expand_launches = 0;
 };
 
-// The device's shared RR workspace, locked for the caller's lifetime.
-struct RRWorkspaceLock {
-    RRWorkspace *ws;
-    void *lock;
-    explicit RRWorkspaceLock(int device);
-    ~RRWorkspaceLock();
-    RRWorkspaceLock(const RRWorkspaceLock &) = delete;
-    RRWorkspaceLock &operator=(const RRWorkspaceLock &) = delete;
-};
-
-// Workspace of greedy / coverage, owned by a graph.
+// Workspace of greedy / coverage: one per device, shared by every graph on it.
 struct GreedyWorkspace {
     DevBuf cnt;       // n uint32  marginal coverage
     DevBuf inv_off;   // (n+1) uint64
@@ -105,6 +97,19 @@ struct GreedyWorkspace {
     DevBuf counters;  // coverage counters
     DevBuf scan_tmp;
     size_t bytes() const;
+    void release();
+};
+
+// The device's shared workspaces (RR generation, greedy / coverage), locked
+// for the holder's lifetime.
+struct DeviceLock {
+    RRWorkspace *rr;
+    GreedyWorkspace *gr;
+    void *lock;
+    explicit DeviceLock(int device);
+    ~DeviceLock();
+    DeviceLock(const DeviceLock &) = delete;
+    DeviceLock &operator=(const DeviceLock &) = delete;
 };
 
 }  // namespace hyperim
@@ -120,8 +125,11 @@ struct hyperim_graph_s {
     bool stratified = false;
     hyperim::DevBuf l, deg, top, stratum, P;
     hyperim_strata_info info{};
-    hyperim_tuning tune{1024, 16384, 256, 512, 4096, 8, {0, 0}};  // RR execution parameters
-    hyperim::GreedyWorkspace gr;
+    hyperim_tuning tune{1024, 16384, 256, 512, 4096, 8, 16384, 0};  // RR execution parameters
+    // learned from generated sets (launch-group and stage sizing, admission);
+    // -1 = nothing generated yet
+    double rr_members = -1.0, rr_defer = -1.0;
+    uint64_t rr_seen_sets = 0, rr_seen_members = 0;
 };
 
 struct hyperim_pool_s {
@@ -160,8 +168,14 @@ inline int check_device(hyperim_graph g) {
 }
 
 // ---- handles and storage (api.hip) --------------------------------------------
-size_t graph_bytes(hyperim_graph g);                       // device bytes of the graph incl. greedy workspace
+size_t graph_bytes(hyperim_graph g);                       // device bytes of the graph
 int pool_init_owned(hyperim_graph g, hyperim_pool p, hipStream_t s);
+// Current bytes of the device's shared workspaces: RR slots (lists and
+// bitmaps), RR stage and per-set arrays, greedy / coverage.
+struct SharedBytes {
+    size_t slots, stage, greedy, total;
+};
+SharedBytes shared_bytes();
 void pool_clear(hyperim_pool p);                           // empty, keeps storage
 void pool_release(hyperim_pool p);                         // empty, frees owned storage
 size_t pool_bytes(const hyperim_pool_s &p);
@@ -195,17 +209,19 @@ struct RRTask {
     uint32_t instance, pool;
     uint64_t id_begin, id_end;
 };
-// Generate every task's RR sets into workspace ws's stage (per-id outputs laid
-// out task after task); *total = members staged.  Tasks may name different
-// (stratified) graphs on the current device.  form 0 = the tasks share launch
-// groups, form 1 = one launch group per (task, ladder block, stratum).
-int rr_generate_stage(RRWorkspace &ws, RRStats &st, const std::vector<RRTask> &tasks, uint32_t qlog, int form,
-                      hipStream_t s, uint64_t *total);
-// Append the staged sets with per-id indices [first, first + count) of ws to
-// pool p (growing its storage; HYPERIM_ECAPACITY beyond max_entries or a
-// caller buffer).
-int rr_compact_into(RRWorkspace &ws, hyperim_pool p, uint64_t first, uint64_t count, uint64_t max_entries,
-                    hipStream_t s);
+// Generate tasks[i]'s RR sets and append them to pools[i].  Tasks may name
+// different (stratified) graphs on the current device.  form 0 = the tasks
+// share launch groups, form 1 = launch groups per (task, ladder block,
+// stratum).  Each launch group is compacted into its pools before the next
+// one runs; groups are cut so their staged members stay near stage_budget
+// bytes.  pool_status[i] = HYPERIM_ECAPACITY when pools[i] would exceed
+// max_entries (its remaining sets are dropped; the other pools go on).
+// Bytes of slot lists and bitmaps the workspace holds for graphs of up to
+// n_max vertices.
+size_t rr_slot_bytes(uint32_t n_max);
+int rr_generate_into(RRWorkspace &ws, RRStats &st, const std::vector<RRTask> &tasks,
+                     const std::vector<hyperim_pool> &pools, uint32_t qlog, int form, uint64_t max_entries,
+                     uint64_t stage_budget, hipStream_t s, std::vector<int> &pool_status);
 // Make room in pool p for `ids` more ids and `entries` more members.
 int pool_reserve(hyperim_pool p, uint64_t ids, uint64_t entries, hipStream_t s);
 // Sums of weight[] (incidences) and bytesw[] (algorithmic bytes) over the
@@ -214,10 +230,12 @@ int rr_incidences(hyperim_graph g, hyperim_pool p, uint64_t theta, hipStream_t s
                   uint64_t *alg_bytes);
 
 // ---- launchers (greedy.hip) ---------------------------------------------------
-int greedy_device(hyperim_graph g, hyperim_pool p, uint64_t theta, uint32_t k, hipStream_t s,
+// Greedy max coverage of the pool's first theta sets; the seeds also stay in
+// w.out (device) for coverage_device.
+int greedy_device(GreedyWorkspace &w, hyperim_graph g, hyperim_pool p, uint64_t theta, uint32_t k, hipStream_t s,
                   uint32_t *seeds_host, uint64_t *gains_host);
-int coverage_device(hyperim_graph g, hyperim_pool p, uint64_t theta, const uint32_t *seeds_dev, uint32_t k,
-                    hipStream_t s, uint64_t *covered_host);
+int coverage_device(GreedyWorkspace &w, hyperim_graph g, hyperim_pool p, uint64_t theta, const uint32_t *seeds_dev,
+                    uint32_t k, hipStream_t s, uint64_t *covered_host);
 
 // ---- host schedule (theta.cpp logic lives in api.hip) ---------------------------
 uint32_t query_cu_count();

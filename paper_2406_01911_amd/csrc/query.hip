@@ -79,13 +79,14 @@ struct EventPair {
     }
 };
 
-// The two pools of one (graph, seed, instance) key; both hold ids [0, have).
+// The two pools of one (graph, seed, instance) key; pool x holds ids
+// [0, have[x]).
 struct PoolPair {
     hyperim_graph g = nullptr;
     uint64_t seed = 0;
     uint32_t instance = 0;
     hyperim_pool_s r[2];
-    uint64_t have = 0;
+    uint64_t have[2] = {0, 0};
     uint32_t users = 0;        // queries admitted on these pools
     uint64_t last_step = 0;    // for least-recently-used eviction
     bool allocated = false;
@@ -102,9 +103,17 @@ struct PoolPair {
         allocated = true;
         return HYPERIM_OK;
     }
+    void clear() {
+        for (int x = 0; x < 2; ++x) {
+            pool_clear(&r[x]);
+            have[x] = 0;
+        }
+    }
     void release() {
-        for (int x = 0; x < 2; ++x) pool_release(&r[x]);
-        have = 0;
+        for (int x = 0; x < 2; ++x) {
+            pool_release(&r[x]);
+            have[x] = 0;
+        }
         allocated = false;
     }
     size_t bytes() const { return pool_bytes(r[0]) + pool_bytes(r[1]); }
@@ -172,200 +181,43 @@ void start(QueryRun &r, const hyperim_options &o) {
     r.t0 = std::chrono::steady_clock::now();
 }
 
-// One round of every query in qs (none done): RR generation for all their
-// pools in one generation pass, then each query's greedy on R1[0, theta),
-// coverage of R2[0, theta) and bound test.  Per-query failures (a pool over
-// max_entries, theta beyond the id space) end that query only; a HIP error is
-// returned and ends them all.
-int run_round(const std::vector<QueryRun *> &qs, const hyperim_options &o, hipStream_t s, EventPair &ev,
-              uint64_t step) {
-    const double tconst = 1.0 - std::exp(-1.0);
-    HIM_CHECK(ev.create());
-    // targets per pool pair
-    std::vector<PoolPair *> pps;
-    std::vector<uint64_t> target;
-    std::vector<QueryRun *> live;
-    for (QueryRun *q : qs) {
-        const uint64_t theta = q->next_theta(o);
-        if (theta > kMaxIds || theta >= (1ull << 32)) {
-            set_error_detail("theta exceeds the id space");
-            q->fail(HYPERIM_ECAPACITY);
-            continue;
-        }
-        live.push_back(q);
-        size_t i = 0;
-        while (i < pps.size() && pps[i] != q->pp) ++i;
-        if (i == pps.size()) {
-            pps.push_back(q->pp);
-            target.push_back(theta);
-        } else {
-            target[i] = std::max(target[i], theta);
-        }
-    }
-    std::vector<RRTask> tasks;
-    std::vector<hyperim_pool> dst;
-    std::vector<size_t> task_pp;
-    for (size_t i = 0; i < pps.size(); ++i) {
-        PoolPair *pp = pps[i];
-        pp->last_step = step;
-        HIM_CHECK(pp->ensure(s));
-        if (target[i] <= pp->have) continue;
-        for (uint32_t x = 0; x < 2; ++x) {
-            tasks.push_back(RRTask{pp->g, pp->seed, pp->instance, x, pp->have, target[i]});
-            dst.push_back(&pp->r[x]);
-            task_pp.push_back(i);
-        }
-    }
-    RRStats st;
-    float ms_rr = 0.f;
-    std::vector<int> pp_status(pps.size(), HYPERIM_OK);
-    if (!tasks.empty()) {
-        HIM_HIP(hipEventRecord(ev.a, s));
-        std::vector<int> pool_status;
-        HIM_CHECK(generate_into(tasks, dst, o.qlog, (int)o.form, o.max_entries, s, st, &pool_status));
-        HIM_HIP(hipEventRecord(ev.b, s));
-        HIM_HIP(hipEventSynchronize(ev.b));
-        HIM_HIP(hipEventElapsedTime(&ms_rr, ev.a, ev.b));
-        for (size_t t = 0; t < tasks.size(); ++t)
-            if (pool_status[t] != HYPERIM_OK) pp_status[task_pp[t]] = pool_status[t];
-        for (size_t i = 0; i < pps.size(); ++i) {
-            PoolPair *pp = pps[i];
-            if (pp_status[i] == HYPERIM_OK) {
-                pp->have = std::max(pp->have, target[i]);
-            } else {
-                // a pool that did not take its new sets: both start over
-                pool_clear(&pp->r[0]);
-                pool_clear(&pp->r[1]);
-                pp->have = 0;
-            }
-        }
-    }
-    for (QueryRun *q : live) {
-        size_t i = 0;
-        while (pps[i] != q->pp) ++i;
-        if (pp_status[i] != HYPERIM_OK) {
-            set_error_detail("pool would exceed max_entries");
-            q->fail(pp_status[i]);
-            continue;
-        }
-        hyperim_result &res = q->res;
-        res.ms_rr += ms_rr;
-        res.ms_bfs += st.ms_bfs;
-        res.ms_light += st.ms_light;
-        res.ms_heavy += st.ms_heavy;
-        res.bfs_launches += st.launches;
-        res.deferred += st.deferred;
-        res.supersteps += st.supersteps;
-        res.bytes_light += st.bytes_light;
-        res.bytes_heavy += st.bytes_heavy;
-        res.ms_expand += st.ms_expand;
-        res.expand_launches += st.expand_launches;
-        hyperim_graph g = q->q.graph;
-        const uint64_t theta = q->next_theta(o);
-        const uint32_t k = q->q.k;
-        float ms = 0.f;
-        HIM_HIP(hipEventRecord(ev.a, s));
-        HIM_CHECK(greedy_device(g, &q->pp->r[0], theta, k, s, q->seeds.data(), q->gains.data()));
-        uint64_t lambda2 = 0;
-        HIM_CHECK(coverage_device(g, &q->pp->r[1], theta, g->gr.out.as<uint32_t>(), k, s, &lambda2));
-        HIM_HIP(hipEventRecord(ev.b, s));
-        HIM_HIP(hipEventSynchronize(ev.b));
-        HIM_HIP(hipEventElapsedTime(&ms, ev.a, ev.b));
-        res.ms_greedy += ms;
-        uint64_t lambda1 = 0;
-        for (uint32_t x = 0; x < k; ++x) lambda1 += q->gains[x];
-        const double n = (double)g->n;
-        const double sl = lower_bound((double)lambda2, q->sc.a, n, (double)theta);
-        const double su = upper_bound((double)lambda1, k, q->sc.a, n, (double)theta);
-        q->round += 1;
-        res.rounds = q->round;
-        res.theta = theta;
-        res.lambda1 = lambda1;
-        res.lambda2 = lambda2;
-        res.sigma_l = sl;
-        res.sigma_u = su;
-        res.spread = n * (double)lambda2 / (double)theta;
-        const bool stop = o.theta_fixed || (su > 0.0 && sl / su >= tconst - q->q.eps) || q->round >= q->sc.i_max;
-        if (!stop) continue;
-        // members of the two pool prefixes [0, theta)
-        uint64_t e[2] = {0, 0};
-        for (int x = 0; x < 2; ++x)
-            HIM_HIP(hipMemcpyAsync(&e[x], q->pp->r[x].off + theta, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
-        HIM_HIP(hipStreamSynchronize(s));
-        res.entries1 = e[0];
-        res.entries2 = e[1];
-        if (o.flags & HYPERIM_FLAG_INCIDENCES) {
-            uint64_t i1 = 0, i2 = 0, b1 = 0, b2 = 0;
-            HIM_CHECK(rr_incidences(g, &q->pp->r[0], theta, s, &i1, &b1));
-            HIM_CHECK(rr_incidences(g, &q->pp->r[1], theta, s, &i2, &b2));
-            res.incidences = i1 + i2;
-            res.alg_bytes = b1 + b2;
-        }
-        res.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - q->t0).count();
-        q->done = true;
-    }
-    return HYPERIM_OK;
+// Add one generation pass's device times and counters to a result.
+void add_stats(hyperim_result &res, const RRStats &st, float ms_rr) {
+    res.ms_rr += ms_rr;
+    res.ms_bfs += st.ms_bfs;
+    res.ms_light += st.ms_light;
+    res.ms_heavy += st.ms_heavy;
+    res.bfs_launches += st.launches;
+    res.deferred += st.deferred;
+    res.supersteps += st.supersteps;
+    res.bytes_light += st.bytes_light;
+    res.bytes_heavy += st.bytes_heavy;
+    res.ms_expand += st.ms_expand;
+    res.expand_launches += st.expand_launches;
 }
 
-// Run queries to completion in lockstep rounds; pools shared by queries with
-// the same graph and key live in `pools`.
-int run_batch(std::vector<QueryRun> &runs, const hyperim_options &o, hipStream_t s) {
-    std::vector<std::unique_ptr<PoolPair>> pools;
-    for (QueryRun &r : runs) {
-        for (auto &pp : pools)
-            if (pp->g == r.q.graph && pp->seed == r.q.seed && pp->instance == r.q.instance) r.pp = pp.get();
-        if (!r.pp) {
-            pools.emplace_back(new PoolPair());
-            PoolPair *pp = pools.back().get();
-            pp->g = r.q.graph;
-            pp->seed = r.q.seed;
-            pp->instance = r.q.instance;
-            r.pp = pp;
-        }
-        start(r, o);
-    }
-    EventPair ev;
-    for (uint64_t step = 0;; ++step) {
-        std::vector<QueryRun *> active;
-        for (QueryRun &r : runs)
-            if (!r.done) active.push_back(&r);
-        if (active.empty()) break;
-        const int rc = run_round(active, o, s, ev, step);
-        if (rc != HYPERIM_OK) {
-            for (QueryRun *r : active)
-                if (!r->done) r->fail(rc);
-            return rc;
-        }
-    }
-    return HYPERIM_OK;
+size_t device_shared_bytes() {
+    size_t b = 0;
+    return hyperim_workspace_info(&b) == HYPERIM_OK ? b : 0;
 }
 
-}  // namespace
-}  // namespace hyperim
-
-using namespace hyperim;
-
-// ---- serving session -------------------------------------------------------
-struct hyperim_session_s {
-    int device = 0;
+// Queries in flight over resident pools, advanced one doubling round at a
+// time.  With a finite budget, queries are admitted in submission order while
+// the estimated device bytes fit (see hyperim_session_create).
+struct Engine {
     hipStream_t stream = nullptr;
     hyperim_options opt{};
-    size_t budget = 0;
-    uint64_t next_ticket = 1;
+    size_t budget = ~(size_t)0;
+    uint64_t steps = 0;
     std::deque<QueryRun *> waiting;
-    std::vector<QueryRun *> active;           // admission order
-    std::map<uint64_t, QueryRun *> finished;
-    std::map<QueryRun *, uint64_t> ticket_of;
+    std::vector<QueryRun *> active;   // admission order
     std::vector<std::unique_ptr<PoolPair>> pools;
-    std::map<hyperim_graph, double> mpi;      // learned members per RR set, per graph
     EventPair ev;
-    hyperim_session_stats stats{};
+    // whole-engine totals: device times and counters of every shared launch
+    // (pilot samples included), steps in `rounds`
+    hyperim_result total{};
 
-    ~hyperim_session_s() {
-        for (QueryRun *q : waiting) delete q;
-        for (QueryRun *q : active) delete q;
-        for (auto &kv : finished) delete kv.second;
-    }
+    bool bounded() const { return budget != ~(size_t)0; }
 
     PoolPair *pool_for(const hyperim_query &q) {
         for (auto &pp : pools)
@@ -380,13 +232,11 @@ struct hyperim_session_s {
 
     double members_per_id(const PoolPair *pp) const {
         const double own = pp->members_per_id();
-        if (own >= 0.0) return own;
-        auto it = mpi.find(pp->g);
-        return it != mpi.end() ? it->second : 16.0;
+        return own >= 0.0 ? own : pp->g->rr_members;
     }
 
-    // Bytes in use now: graphs with queries or pools, pools, RR workspace.
-    size_t resident() {
+    // Device bytes in use: graphs with queries or pools here, pools, shared workspaces.
+    size_t resident() const {
         std::vector<hyperim_graph> gs;
         auto add = [&](hyperim_graph g) {
             if (std::find(gs.begin(), gs.end(), g) == gs.end()) gs.push_back(g);
@@ -398,28 +248,48 @@ struct hyperim_session_s {
         }
         for (QueryRun *q : active) add(q->q.graph);
         for (hyperim_graph g : gs) b += graph_bytes(g);
-        size_t ws = 0;
-        if (hyperim_workspace_info(&ws) == HYPERIM_OK) b += ws;
-        return b;
+        return b + device_shared_bytes();
     }
 
-    // Estimated extra device bytes for query q's next round: growth of its
-    // pools (geometric growth slack 1.5), of its graph's greedy workspace
-    // and of the shared stage.
-    size_t growth(const QueryRun *q) const {
+    // Estimated extra device bytes for query q's next round that q alone
+    // needs: its pools (plus the old storage while a pool grows and keeps its
+    // contents) and its graph if nothing here uses it yet.  Its share of the
+    // shared workspaces goes to `need`.  A graph without a members-per-set
+    // estimate is priced at the worst case, n members per set.
+    struct Shared {
+        uint32_t n_max = 0;      // largest graph of the step (RR slots)
+        double stage = 0.0;      // staged bytes of the step
+        double greedy = 0.0;     // largest greedy index of the step
+    };
+    size_t own_growth(const QueryRun *q, Shared &need) const {
         const uint64_t theta = q->next_theta(opt);
         const PoolPair *pp = q->pp;
-        const double mpi_est = members_per_id(pp);
-        double g_b = 0.0;
-        if (theta > pp->have) {
-            const double pools = 2.0 * 1.5 * (double)theta * (12.0 + 4.0 * mpi_est) + 2.0 * 1.5 * 4.0 * 4096;
-            g_b += std::max(0.0, pools - (double)pp->bytes());
-            g_b += 2.0 * (double)(theta - pp->have) * (1.3 * 4.0 * mpi_est + 24.0);   // stage and per-id arrays
+        const double n = (double)q->q.graph->n;
+        double m = members_per_id(pp);
+        if (m < 0.0) m = n;
+        double b = 0.0;
+        for (int x = 0; x < 2; ++x) {
+            if (theta <= pp->have[x]) continue;
+            const double add = (double)(theta - pp->have[x]) * m;
+            const double bytes = ((double)theta + 1.0) * 12.0 + 4.0 * ((double)pp->r[x].total + add);
+            const double cur = (double)pool_bytes(pp->r[x]);
+            if (bytes > cur) b += bytes - cur + 4.0 * (double)pp->r[x].total;
+            need.stage += 4.0 * 1.3 * add + 24.0 * (double)(theta - pp->have[x]);
         }
-        const double greedy = 1.5 * (double)theta * (4.0 * mpi_est + 17.0) + 21.0 * (double)q->q.graph->n;
-        g_b += std::max(0.0, greedy - (double)q->q.graph->gr.bytes());
-        if (!pp->allocated && !pp->users) g_b += (double)graph_bytes(q->q.graph);
-        return (size_t)g_b;
+        need.greedy = std::max(need.greedy, 4.0 * 1.1 * (double)theta * m + 17.0 * (double)theta + 21.0 * n);
+        need.n_max = std::max(need.n_max, q->q.graph->n);
+        if (!pp->allocated && !pp->users) b += (double)graph_bytes(q->q.graph);
+        return (size_t)b;
+    }
+
+    // Growth of the shared workspaces beyond what they hold now.
+    size_t shared_growth(const Shared &need, const SharedBytes &have, hyperim_graph g) const {
+        const double stage_cap = (double)((uint64_t)std::max<uint32_t>(g->tune.stage_mib, 64) << 20);
+        const double slots = (double)rr_slot_bytes(need.n_max);
+        double b = std::max(0.0, slots - (double)have.slots);
+        b += std::max(0.0, std::min(need.stage, stage_cap) - (double)have.stage);
+        b += std::max(0.0, need.greedy - (double)have.greedy);
+        return (size_t)b;
     }
 
     // Free idle pools, least recently used first, until `need` more bytes fit.
@@ -437,18 +307,321 @@ struct hyperim_session_s {
         return true;
     }
 
-    void finish(QueryRun *q) {
-        q->pp->users -= 1;
-        const double m = q->pp->members_per_id();
-        if (m >= 0.0) mpi[q->q.graph] = m;
-        if (q->status == HYPERIM_OK)
-            stats.finished += 1;
-        else
-            stats.failed += 1;
-        finished[ticket_of[q]] = q;
-        ticket_of.erase(q);
+    // A first sample of R1 (ids [0, Q)) for waiting queries on graphs without
+    // a members-per-set estimate; those sets are the start of R1 anyway.
+    int pilot(size_t used) {
+        const uint64_t Q = 1ull << opt.qlog;
+        std::vector<PoolPair *> pps;
+        for (QueryRun *q : waiting) {
+            PoolPair *pp = pool_for(q->q);
+            if (members_per_id(pp) >= 0.0 || std::find(pps.begin(), pps.end(), pp) != pps.end()) continue;
+            const uint64_t ids = std::min<uint64_t>(Q, q->next_theta(opt));
+            const size_t worst = (size_t)(2.0 * 4.0 * 1.3 * (double)ids * (double)pp->g->n) + graph_bytes(pp->g);
+            if (used + worst > budget) break;
+            used += worst;
+            pps.push_back(pp);
+        }
+        if (pps.empty()) return HYPERIM_OK;
+        std::vector<RRTask> tasks;
+        std::vector<hyperim_pool> dst;
+        for (PoolPair *pp : pps) {
+            HIM_CHECK(pp->ensure(stream));
+            tasks.push_back(RRTask{pp->g, pp->seed, pp->instance, 0, 0, Q});
+            dst.push_back(&pp->r[0]);
+        }
+        RRStats st;
+        std::vector<int> status;
+        HIM_CHECK(ev.create());
+        float ms = 0.f;
+        HIM_HIP(hipEventRecord(ev.a, stream));
+        HIM_CHECK(generate_into(tasks, dst, opt.qlog, (int)opt.form, opt.max_entries, stream, st, &status));
+        HIM_HIP(hipEventRecord(ev.b, stream));
+        HIM_HIP(hipEventSynchronize(ev.b));
+        HIM_HIP(hipEventElapsedTime(&ms, ev.a, ev.b));
+        for (size_t i = 0; i < pps.size(); ++i) {
+            if (status[i] == HYPERIM_OK)
+                pps[i]->have[0] = Q;
+            else
+                pps[i]->clear();
+        }
+        add_stats(total, st, ms);
+        // the sample is part of the piloted queries' generation
+        for (QueryRun *q : waiting)
+            if (std::find(pps.begin(), pps.end(), pool_for(q->q)) != pps.end()) add_stats(q->res, st, ms);
+        return HYPERIM_OK;
+    }
+
+    // One round of every query in qs (none done): RR generation for all their
+    // pools in one generation pass, then each query's greedy on R1[0, theta),
+    // coverage of R2[0, theta) and bound test.  Per-query failures (a pool
+    // over max_entries, theta beyond the id space) end that query only; a HIP
+    // error is returned and ends them all.
+    int run_round(const std::vector<QueryRun *> &qs) {
+        const double tconst = 1.0 - std::exp(-1.0);
+        const hipStream_t s = stream;
+        const hyperim_options &o = opt;
+        HIM_CHECK(ev.create());
+        std::vector<PoolPair *> pps;
+        std::vector<uint64_t> target;
+        std::vector<QueryRun *> live;
+        for (QueryRun *q : qs) {
+            const uint64_t theta = q->next_theta(o);
+            if (theta > kMaxIds || theta >= (1ull << 32)) {
+                set_error_detail("theta exceeds the id space");
+                q->fail(HYPERIM_ECAPACITY);
+                continue;
+            }
+            live.push_back(q);
+            size_t i = 0;
+            while (i < pps.size() && pps[i] != q->pp) ++i;
+            if (i == pps.size()) {
+                pps.push_back(q->pp);
+                target.push_back(theta);
+            } else {
+                target[i] = std::max(target[i], theta);
+            }
+        }
+        std::vector<RRTask> tasks;
+        std::vector<hyperim_pool> dst;
+        std::vector<size_t> task_pp;
+        for (size_t i = 0; i < pps.size(); ++i) {
+            PoolPair *pp = pps[i];
+            pp->last_step = steps;
+            HIM_CHECK(pp->ensure(s));
+            for (uint32_t x = 0; x < 2; ++x) {
+                if (target[i] <= pp->have[x]) continue;
+                tasks.push_back(RRTask{pp->g, pp->seed, pp->instance, x, pp->have[x], target[i]});
+                dst.push_back(&pp->r[x]);
+                task_pp.push_back(i);
+            }
+        }
+        RRStats st;
+        float ms_rr = 0.f;
+        std::vector<int> pp_status(pps.size(), HYPERIM_OK);
+        if (!tasks.empty()) {
+            HIM_HIP(hipEventRecord(ev.a, s));
+            std::vector<int> pool_status;
+            HIM_CHECK(generate_into(tasks, dst, o.qlog, (int)o.form, o.max_entries, s, st, &pool_status));
+            HIM_HIP(hipEventRecord(ev.b, s));
+            HIM_HIP(hipEventSynchronize(ev.b));
+            HIM_HIP(hipEventElapsedTime(&ms_rr, ev.a, ev.b));
+            add_stats(total, st, ms_rr);
+            for (size_t t = 0; t < tasks.size(); ++t)
+                if (pool_status[t] != HYPERIM_OK) pp_status[task_pp[t]] = pool_status[t];
+            for (size_t i = 0; i < pps.size(); ++i) {
+                PoolPair *pp = pps[i];
+                if (pp_status[i] == HYPERIM_OK) {
+                    for (int x = 0; x < 2; ++x) pp->have[x] = std::max(pp->have[x], target[i]);
+                } else {
+                    pp->clear();   // a pool that did not take its new sets: both start over
+                }
+            }
+        }
+        int device = 0;
+        HIM_HIP(hipGetDevice(&device));
+        for (QueryRun *q : live) {
+            size_t i = 0;
+            while (pps[i] != q->pp) ++i;
+            if (pp_status[i] != HYPERIM_OK) {
+                set_error_detail("pool would exceed max_entries");
+                q->fail(pp_status[i]);
+                continue;
+            }
+            hyperim_result &res = q->res;
+            add_stats(res, st, ms_rr);
+            hyperim_graph g = q->q.graph;
+            const uint64_t theta = q->next_theta(o);
+            const uint32_t k = q->q.k;
+            float ms = 0.f;
+            uint64_t lambda2 = 0;
+            {
+                DeviceLock lk(device);
+                HIM_HIP(hipEventRecord(ev.a, s));
+                HIM_CHECK(greedy_device(*lk.gr, g, &q->pp->r[0], theta, k, s, q->seeds.data(), q->gains.data()));
+                HIM_CHECK(coverage_device(*lk.gr, g, &q->pp->r[1], theta, lk.gr->out.as<uint32_t>(), k, s,
+                                          &lambda2));
+                HIM_HIP(hipEventRecord(ev.b, s));
+                HIM_HIP(hipEventSynchronize(ev.b));
+            }
+            HIM_HIP(hipEventElapsedTime(&ms, ev.a, ev.b));
+            res.ms_greedy += ms;
+            total.ms_greedy += ms;
+            uint64_t lambda1 = 0;
+            for (uint32_t x = 0; x < k; ++x) lambda1 += q->gains[x];
+            const double n = (double)g->n;
+            const double sl = lower_bound((double)lambda2, q->sc.a, n, (double)theta);
+            const double su = upper_bound((double)lambda1, k, q->sc.a, n, (double)theta);
+            q->round += 1;
+            res.rounds = q->round;
+            res.theta = theta;
+            res.lambda1 = lambda1;
+            res.lambda2 = lambda2;
+            res.sigma_l = sl;
+            res.sigma_u = su;
+            res.spread = n * (double)lambda2 / (double)theta;
+            const bool stop =
+                o.theta_fixed || (su > 0.0 && sl / su >= tconst - q->q.eps) || q->round >= q->sc.i_max;
+            if (!stop) continue;
+            // members of the two pool prefixes [0, theta)
+            uint64_t e[2] = {0, 0};
+            for (int x = 0; x < 2; ++x)
+                HIM_HIP(hipMemcpyAsync(&e[x], q->pp->r[x].off + theta, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+            HIM_HIP(hipStreamSynchronize(s));
+            res.entries1 = e[0];
+            res.entries2 = e[1];
+            if (o.flags & HYPERIM_FLAG_INCIDENCES) {
+                uint64_t i1 = 0, i2 = 0, b1 = 0, b2 = 0;
+                HIM_CHECK(rr_incidences(g, &q->pp->r[0], theta, s, &i1, &b1));
+                HIM_CHECK(rr_incidences(g, &q->pp->r[1], theta, s, &i2, &b2));
+                res.incidences = i1 + i2;
+                res.alg_bytes = b1 + b2;
+            }
+            total.entries1 += res.entries1;
+            total.entries2 += res.entries2;
+            total.theta += theta;
+            total.incidences += res.incidences;
+            total.alg_bytes += res.alg_bytes;
+            res.ms_total =
+                std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - q->t0).count();
+            q->done = true;
+        }
+        return HYPERIM_OK;
+    }
+
+    // Admit what fits and run one round; `finished` receives the queries that
+    // ended in this step (done or failed).
+    int step(std::vector<QueryRun *> &finished, size_t *ran) {
+        steps += 1;
+        total.rounds = (uint32_t)steps;
+        size_t used = bounded() ? resident() : 0;
+        if (bounded()) HIM_CHECK(pilot(used));
+        if (bounded()) used = resident();
+        std::vector<QueryRun *> run;
+        Shared need;
+        const SharedBytes have = bounded() ? shared_bytes() : SharedBytes{0, 0, 0, 0};
+        size_t shared_so_far = 0;
+        auto fits = [&](QueryRun *q) {
+            if (!bounded()) return true;
+            Shared trial = need;
+            const size_t own = own_growth(q, trial);
+            const size_t shared = shared_growth(trial, have, q->q.graph);
+            const size_t delta = own + (shared > shared_so_far ? shared - shared_so_far : 0);
+            if (used + delta > budget && !make_room(used, delta)) return false;
+            need = trial;
+            used += delta;
+            shared_so_far = std::max(shared, shared_so_far);
+            return true;
+        };
+        // running queries first, in admission order
+        for (QueryRun *q : active)
+            if (fits(q)) run.push_back(q);
+        // then new queries, in submission order (no overtaking)
+        while (!waiting.empty()) {
+            QueryRun *q = waiting.front();
+            q->pp = pool_for(q->q);
+            if (!fits(q)) break;
+            waiting.pop_front();
+            q->pp->users += 1;
+            active.push_back(q);
+            run.push_back(q);
+        }
+        if (run.empty() && (!active.empty() || !waiting.empty())) {
+            // nothing fits: the oldest query cannot run even alone
+            QueryRun *q = nullptr;
+            if (!active.empty()) {
+                q = active.front();
+                active.erase(active.begin());
+            } else {
+                q = waiting.front();
+                waiting.pop_front();
+                q->pp = pool_for(q->q);
+                q->pp->users += 1;
+            }
+            set_error_detail("query does not fit the HBM budget");
+            q->fail(HYPERIM_ECAPACITY);
+            q->pp->users -= 1;
+            finished.push_back(q);
+        }
+        int rc = HYPERIM_OK;
+        if (!run.empty()) {
+            rc = run_round(run);
+            if (rc != HYPERIM_OK)
+                for (QueryRun *q : run)
+                    if (!q->done) q->fail(rc);
+        }
+        if (ran) *ran = run.size();
+        for (size_t i = 0; i < active.size();) {
+            QueryRun *q = active[i];
+            if (q->done) {
+                active.erase(active.begin() + (long)i);
+                q->pp->users -= 1;
+                finished.push_back(q);
+            } else {
+                ++i;
+            }
+        }
+        return rc;
     }
 };
+
+}  // namespace
+}  // namespace hyperim
+
+using namespace hyperim;
+
+// ---- serving session -------------------------------------------------------
+struct hyperim_session_s {
+    int device = 0;
+    Engine eng;
+    uint64_t next_ticket = 1;
+    std::map<uint64_t, QueryRun *> finished;
+    std::map<QueryRun *, uint64_t> ticket_of;
+    hyperim_session_stats stats{};
+
+    ~hyperim_session_s() {
+        for (QueryRun *q : eng.waiting) delete q;
+        for (QueryRun *q : eng.active) delete q;
+        for (auto &kv : finished) delete kv.second;
+    }
+};
+
+namespace {
+
+// Lockstep rounds for queries[0, count) (none waits once admitted); with a
+// finite budget, admission as in a session.
+int run_queries(const hyperim_query *queries, uint32_t count, const hyperim_options &o, hipStream_t s, size_t budget,
+                std::vector<std::unique_ptr<QueryRun>> &runs, hyperim_result *total) {
+    const auto t0 = std::chrono::steady_clock::now();
+    Engine eng;
+    eng.stream = s;
+    eng.opt = o;
+    eng.budget = budget;
+    for (uint32_t i = 0; i < count; ++i) {
+        runs.emplace_back(new QueryRun());
+        QueryRun *r = runs.back().get();
+        r->q = queries[i];
+        start(*r, o);
+        eng.waiting.push_back(r);
+    }
+    std::vector<QueryRun *> finished;
+    int rc = HYPERIM_OK;
+    while (!eng.waiting.empty() || !eng.active.empty()) {
+        rc = eng.step(finished, nullptr);
+        if (rc != HYPERIM_OK) {
+            for (QueryRun *q : eng.active)
+                if (!q->done) q->fail(rc);
+            for (QueryRun *q : eng.waiting) q->fail(rc);
+            break;
+        }
+    }
+    if (total) {
+        *total = eng.total;
+        total->ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return rc;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -460,19 +633,19 @@ int hyperim_select_seeds(hyperim_graph g, uint32_t k, double eps, double ell, ui
     const hyperim_options o = normalize(opt);
     hyperim_query q{g, k, instance, eps, ell, seed};
     HIM_CHECK(validate(q, o));
-    std::vector<QueryRun> runs(1);
-    runs[0].q = q;
-    HIM_CHECK(run_batch(runs, o, as_stream(stream)));
-    if (runs[0].status != HYPERIM_OK) return runs[0].status;
-    std::copy(runs[0].seeds.begin(), runs[0].seeds.end(), seeds);
-    if (gains) std::copy(runs[0].gains.begin(), runs[0].gains.end(), gains);
-    if (out) *out = runs[0].res;
+    std::vector<std::unique_ptr<QueryRun>> runs;
+    HIM_CHECK(run_queries(&q, 1, o, as_stream(stream), ~(size_t)0, runs, nullptr));
+    const QueryRun &r = *runs[0];
+    if (r.status != HYPERIM_OK) return r.status;
+    std::copy(r.seeds.begin(), r.seeds.end(), seeds);
+    if (gains) std::copy(r.gains.begin(), r.gains.end(), gains);
+    if (out) *out = r.res;
     return HYPERIM_OK;
 }
 
 int hyperim_select_seeds_batch(const hyperim_query *queries, uint32_t count, const hyperim_options *opt,
                                void *stream, uint32_t *seeds, uint64_t *gains, hyperim_result *results,
-                               int *status) {
+                               int *status, hyperim_result *total) {
     if ((count && !queries) || !seeds) return HYPERIM_EINVAL;
     clear_error_detail();
     const hyperim_options o = normalize(opt);
@@ -483,13 +656,25 @@ int hyperim_select_seeds_batch(const hyperim_query *queries, uint32_t count, con
             return rc;
         }
     }
-    std::vector<QueryRun> runs(count);
-    for (uint32_t i = 0; i < count; ++i) runs[i].q = queries[i];
-    const int rc = run_batch(runs, o, as_stream(stream));
+    // budget: the device memory free now plus what the batch already holds
+    // (its graphs, the shared workspaces), less a reserve
+    size_t free_b = 0, total_b = 0;
+    HIM_HIP(hipMemGetInfo(&free_b, &total_b));
+    std::vector<hyperim_graph> gs;
+    size_t held = device_shared_bytes();
+    for (uint32_t i = 0; i < count; ++i)
+        if (std::find(gs.begin(), gs.end(), queries[i].graph) == gs.end()) {
+            gs.push_back(queries[i].graph);
+            held += graph_bytes(queries[i].graph);
+        }
+    const size_t reserve = 4ull << 30;
+    const size_t budget = free_b + held > reserve ? free_b + held - reserve : 0;
+    std::vector<std::unique_ptr<QueryRun>> runs;
+    const int rc = run_queries(queries, count, o, as_stream(stream), budget, runs, total);
     int first_fail = rc;
     uint64_t at = 0;
     for (uint32_t i = 0; i < count; ++i) {
-        const QueryRun &r = runs[i];
+        const QueryRun &r = *runs[i];
         if (status) status[i] = r.status;
         if (first_fail == HYPERIM_OK && r.status != HYPERIM_OK) first_fail = r.status;
         if (r.status == HYPERIM_OK) {
@@ -513,8 +698,8 @@ int hyperim_session_create(size_t hbm_budget, const hyperim_options *opt, void *
     }
     hyperim_session s = new (std::nothrow) hyperim_session_s();
     if (!s) return HYPERIM_ENOMEM;
-    s->opt = o;
-    s->stream = as_stream(stream);
+    s->eng.opt = o;
+    s->eng.stream = as_stream(stream);
     if (hipGetDevice(&s->device) != hipSuccess) {
         delete s;
         return HYPERIM_EHIP;
@@ -528,7 +713,7 @@ int hyperim_session_create(size_t hbm_budget, const hyperim_options *opt, void *
         const size_t reserve = 8ull << 30;
         hbm_budget = total_b > reserve ? total_b - reserve : total_b / 2;
     }
-    s->budget = hbm_budget;
+    s->eng.budget = hbm_budget;
     s->stats.hbm_budget = hbm_budget;
     *out = s;
     return HYPERIM_OK;
@@ -537,7 +722,7 @@ int hyperim_session_create(size_t hbm_budget, const hyperim_options *opt, void *
 int hyperim_session_submit(hyperim_session s, const hyperim_query *q, uint64_t *ticket) {
     if (!s || !q || !ticket) return HYPERIM_EINVAL;
     clear_error_detail();
-    HIM_CHECK(validate(*q, s->opt));
+    HIM_CHECK(validate(*q, s->eng.opt));
     if (q->graph->device != s->device) {
         set_error_detail("the graph lives on another device than the session");
         return HYPERIM_EINVAL;
@@ -545,10 +730,10 @@ int hyperim_session_submit(hyperim_session s, const hyperim_query *q, uint64_t *
     QueryRun *r = new (std::nothrow) QueryRun();
     if (!r) return HYPERIM_ENOMEM;
     r->q = *q;
-    start(*r, s->opt);   // latency of the call counts from submission
+    start(*r, s->eng.opt);   // latency of the query counts from submission
     const uint64_t t = s->next_ticket++;
     s->ticket_of[r] = t;
-    s->waiting.push_back(r);
+    s->eng.waiting.push_back(r);
     s->stats.submitted += 1;
     *ticket = t;
     return HYPERIM_OK;
@@ -557,71 +742,24 @@ int hyperim_session_submit(hyperim_session s, const hyperim_query *q, uint64_t *
 int hyperim_session_step(hyperim_session s, hyperim_session_stats *out) {
     if (!s) return HYPERIM_EINVAL;
     clear_error_detail();
-    s->stats.steps += 1;
-    const uint64_t step = s->stats.steps;
-    size_t used = s->resident();
-    std::vector<QueryRun *> run;
-    // running queries first, in admission order
-    for (QueryRun *q : s->active) {
-        const size_t need = q->pp ? s->growth(q) : 0;
-        if (used + need <= s->budget || s->make_room(used, need)) {
-            run.push_back(q);
-            used += need;
-        }
+    const size_t waiting_before = s->eng.waiting.size();
+    std::vector<QueryRun *> done;
+    size_t ran = 0;
+    const int rc = s->eng.step(done, &ran);
+    s->stats.steps = s->eng.steps;
+    s->stats.admitted += waiting_before - s->eng.waiting.size();
+    s->stats.ran_last = ran;
+    for (QueryRun *q : done) {
+        if (q->status == HYPERIM_OK)
+            s->stats.finished += 1;
+        else
+            s->stats.failed += 1;
+        s->finished[s->ticket_of[q]] = q;
+        s->ticket_of.erase(q);
     }
-    // then new queries, in submission order (no overtaking)
-    while (!s->waiting.empty()) {
-        QueryRun *q = s->waiting.front();
-        PoolPair *pp = s->pool_for(q->q);
-        q->pp = pp;
-        const size_t need = s->growth(q);
-        if (used + need > s->budget && !s->make_room(used, need)) {
-            q->pp = nullptr;
-            break;
-        }
-        s->waiting.pop_front();
-        pp->users += 1;
-        s->active.push_back(q);
-        s->stats.admitted += 1;
-        run.push_back(q);
-        used += need;
-    }
-    if (run.empty() && (!s->active.empty() || !s->waiting.empty())) {
-        // nothing fits: the oldest query cannot run even alone
-        QueryRun *q = nullptr;
-        if (!s->active.empty()) {
-            q = s->active.front();
-            s->active.erase(s->active.begin());
-        } else {
-            q = s->waiting.front();
-            s->waiting.pop_front();
-            q->pp = s->pool_for(q->q);
-            q->pp->users += 1;
-        }
-        set_error_detail("query does not fit the session's HBM budget");
-        q->fail(HYPERIM_ECAPACITY);
-        s->finish(q);
-    }
-    int rc = HYPERIM_OK;
-    if (!run.empty()) {
-        rc = run_round(run, s->opt, s->stream, s->ev, step);
-        if (rc != HYPERIM_OK)
-            for (QueryRun *q : run)
-                if (!q->done) q->fail(rc);
-    }
-    s->stats.ran_last = run.size();
-    for (size_t i = 0; i < s->active.size();) {
-        QueryRun *q = s->active[i];
-        if (q->done) {
-            s->active.erase(s->active.begin() + (long)i);
-            s->finish(q);
-        } else {
-            ++i;
-        }
-    }
-    s->stats.active = (uint32_t)s->active.size();
-    s->stats.waiting = (uint32_t)s->waiting.size();
-    s->stats.bytes_resident = s->resident();
+    s->stats.active = (uint32_t)s->eng.active.size();
+    s->stats.waiting = (uint32_t)s->eng.waiting.size();
+    s->stats.bytes_resident = s->eng.resident();
     if (out) *out = s->stats;
     return rc;
 }
@@ -650,32 +788,31 @@ int hyperim_session_poll(hyperim_session s, uint64_t ticket, uint32_t *seeds, ui
 
 int hyperim_session_drop(hyperim_session s, hyperim_graph g) {
     if (!s || !g) return HYPERIM_EINVAL;
-    for (QueryRun *q : s->active)
+    for (QueryRun *q : s->eng.active)
         if (q->q.graph == g) return HYPERIM_ESTATE;
-    for (QueryRun *q : s->waiting)
+    for (QueryRun *q : s->eng.waiting)
         if (q->q.graph == g) return HYPERIM_ESTATE;
-    HIM_HIP(hipStreamSynchronize(s->stream));
-    for (size_t i = 0; i < s->pools.size();) {
-        if (s->pools[i]->g == g) {
-            s->pools.erase(s->pools.begin() + (long)i);
-        } else {
+    HIM_HIP(hipStreamSynchronize(s->eng.stream));
+    auto &pools = s->eng.pools;
+    for (size_t i = 0; i < pools.size();) {
+        if (pools[i]->g == g)
+            pools.erase(pools.begin() + (long)i);
+        else
             ++i;
-        }
     }
-    s->mpi.erase(g);
     return HYPERIM_OK;
 }
 
 int hyperim_session_stats_get(hyperim_session s, hyperim_session_stats *out) {
     if (!s || !out) return HYPERIM_EINVAL;
-    s->stats.bytes_resident = s->resident();
+    s->stats.bytes_resident = s->eng.resident();
     *out = s->stats;
     return HYPERIM_OK;
 }
 
 void hyperim_session_free(hyperim_session s) {
     if (!s) return;
-    (void)hipStreamSynchronize(s->stream);
+    (void)hipStreamSynchronize(s->eng.stream);
     delete s;
 }
 

@@ -767,6 +767,40 @@ struct LaunchShape {
     bool lds;
 };
 
+// Slot layout for graphs of up to n_max vertices: phase A grid (from
+// occupancy), slots (phase A waves plus spare slots for deferred sets, within
+// kSlotBudget bytes) and the phase B grid.
+struct SlotLayout {
+    uint64_t grid, waves, slots, grid_b, bytes;
+    bool lds;
+};
+
+int slot_layout(uint32_t n_max, SlotLayout *out) {
+    int per_cu_lds = 0, per_cu_glb = 0, per_cu_b = 0, cus = 0, dev = 0;
+    HIM_HIP(hipGetDevice(&dev));
+    HIM_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    HIM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_lds, k_rr_light<true>, kWG, 0));
+    HIM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_glb, k_rr_light<false>, kWG, 0));
+    HIM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_b, k_expand, kWG, 0));
+    const bool lds = n_max <= kLdsBitmapWords * 32u;
+    const uint64_t words = (n_max + 31u) / 32u;
+    const uint64_t per_slot = (uint64_t)n_max * 4u + (lds ? 0u : words * 4u);
+    const uint64_t max_slots = std::max<uint64_t>(kSlotBudget / std::max<uint64_t>(per_slot, 1), 2 * kWavesPerWG);
+    uint64_t grid = (uint64_t)cus * (uint64_t)std::max(lds ? per_cu_lds : per_cu_glb, 1);
+    // phase A keeps at least half of the slots spare for deferred sets
+    grid = std::min<uint64_t>(grid, max_slots / (2 * kWavesPerWG));
+    grid = std::max<uint64_t>(grid, 1);
+    const uint64_t waves = grid * kWavesPerWG;
+    const uint64_t slots = lds ? waves : std::min<uint64_t>(max_slots, 4 * waves);
+    out->grid = grid;
+    out->waves = waves;
+    out->slots = slots;
+    out->grid_b = (uint64_t)cus * (uint64_t)std::max(per_cu_b, 1);
+    out->bytes = slots * per_slot;
+    out->lds = lds;
+    return HYPERIM_OK;
+}
+
 // Slots sized for graphs of up to n_max vertices (re-created when a larger
 // graph arrives).
 int ensure_workspace(RRWorkspace &ws, uint32_t n_max, hipStream_t s, LaunchShape *shape) {
@@ -779,30 +813,13 @@ int ensure_workspace(RRWorkspace &ws, uint32_t n_max, hipStream_t s, LaunchShape
         ws.grid = 0;
     }
     if (ws.grid == 0) {
-        int dev = 0;
-        HIM_HIP(hipGetDevice(&dev));
-        int cus = 0;
-        HIM_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-        int per_cu = 0, per_cu_b = 0;
-        if (lds)
-            HIM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rr_light<true>, kWG, 0));
-        else
-            HIM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rr_light<false>, kWG, 0));
-        HIM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_b, k_expand, kWG, 0));
-        per_cu = std::max(per_cu, 1);
-        per_cu_b = std::max(per_cu_b, 1);
-        const uint64_t per_slot = (uint64_t)n_max * 4u + (lds ? 0u : (uint64_t)words * 4u);
-        const uint64_t max_slots = std::max<uint64_t>(kSlotBudget / std::max<uint64_t>(per_slot, 1), 2 * kWavesPerWG);
-        uint64_t grid = (uint64_t)cus * (uint64_t)per_cu;
-        // phase A keeps at least half of the slots spare for deferred sets
-        grid = std::min<uint64_t>(grid, max_slots / (2 * kWavesPerWG));
-        grid = std::max<uint64_t>(grid, 1);
-        const uint64_t waves = grid * kWavesPerWG;
-        const uint64_t slots = lds ? waves : std::min<uint64_t>(max_slots, 4 * waves);
+        SlotLayout L;
+        HIM_CHECK(slot_layout(n_max, &L));
+        const uint64_t grid = L.grid, waves = L.waves, slots = L.slots;
         ws.grid = (uint32_t)grid;
         ws.waves = (uint32_t)waves;
         ws.slots = (uint32_t)slots;
-        ws.grid_b = (uint32_t)(cus * per_cu_b);
+        ws.grid_b = (uint32_t)L.grid_b;
         ws.slot_n = std::max<uint32_t>(n_max, 1);
         ws.slot_words = words;
         ws.lds = lds;
@@ -971,168 +988,13 @@ int run_launch(RRWorkspace &ws, RRStats &st, const hyperim_tuning &tune, RRArgs 
 
 }  // namespace
 
-int rr_generate_stage(RRWorkspace &ws, RRStats &st, const std::vector<RRTask> &tasks, uint32_t qlog, int form,
-                      hipStream_t s, uint64_t *total) {
-    // HYPERIM_TRACE=1: synchronise after every grid-wide superstep and report
-    // its item count and time on stderr (diagnostics; same results)
-    static const bool trace = [] {
-        const char *e = getenv("HYPERIM_TRACE");
-        return e && e[0] == '1';
-    }();
-    if (tasks.empty()) {
-        set_error_detail("no generation task");
-        return HYPERIM_EINVAL;
-    }
-    // execution parameters of the first task's graph
-    const hyperim_tuning &tune = tasks[0].g->tune;
-    // graph descriptors (one per distinct graph)
-    std::map<hyperim_graph, uint32_t> gid;
-    std::vector<GraphDesc> gdesc;
-    uint32_t n_max = 1;
-    for (const RRTask &t : tasks) {
-        if (gid.count(t.g)) continue;
-        gid[t.g] = (uint32_t)gdesc.size();
-        hyperim_graph g = t.g;
-        gdesc.push_back(GraphDesc{g->he_off.as<uint32_t>(), g->he_mem.as<uint32_t>(), g->v_off.as<uint32_t>(),
-                                  g->v_he.as<uint32_t>(), g->thr.as<uint32_t>(), g->P.as<uint32_t>(), g->n,
-                                  (g->n + 31u) / 32u});
-        n_max = std::max(n_max, g->n);
-    }
-    uint64_t count = 0;
-    for (const RRTask &t : tasks) count += t.id_end - t.id_begin;
-    LaunchShape shape;
-    HIM_CHECK(ensure_workspace(ws, n_max, s, &shape));
-    HIM_CHECK(ws.stage_off.reserve(sizeof(uint64_t) * std::max<uint64_t>(count, 1), s, false));
-    HIM_CHECK(ws.sizes.reserve(sizeof(uint32_t) * std::max<uint64_t>(count, 1), s, false));
-    HIM_CHECK(ws.roots.reserve(sizeof(uint32_t) * std::max<uint64_t>(count, 1), s, false));
-    HIM_CHECK(ws.big_ids.reserve(sizeof(uint64_t) * std::max<uint64_t>(count, 1), s, false));
-    // stage sized from the members per id seen so far (a miss costs a re-run)
-    const uint64_t predicted = (uint64_t)(ws.members_per_id * 1.3 * (double)count) + 4 * count + (1u << 20);
-    if (ws.stage.bytes < sizeof(uint32_t) * predicted)
-        HIM_CHECK(ws.stage.reserve(sizeof(uint32_t) * predicted, s, false));
+namespace {
 
-    // launch groups: [index lo, index hi) of the tasks laid back to back, each
-    // with its task descriptors
-    struct Group {
-        uint64_t lo, hi;
-        size_t first_desc, ndesc;
-    };
-    std::vector<Group> groups;
-    std::vector<TaskDesc> tdesc;
-    const size_t ndef_cap = std::max<uint64_t>(shape.slots - (uint64_t)shape.grid * kWavesPerWG, 1);
-    if (form == 0) {
-        // cut so that the sets a group defers fit the spare slots at the
-        // deferral rate seen so far (a set that finds no spare slot stays with
-        // its wave)
-        const double rate = std::max(ws.defer_rate * 1.25, 1.0 / 64.0);
-        const uint64_t chunk = std::max<uint64_t>((uint64_t)((double)ndef_cap / rate), 4096);
-        for (uint64_t lo = 0; lo < count; lo += chunk) {
-            const uint64_t hi = std::min(count, lo + chunk);
-            Group gr{lo, hi, tdesc.size(), 0};
-            uint64_t tstart = 0;
-            for (const RRTask &t : tasks) {
-                const uint64_t tn = t.id_end - t.id_begin;
-                const uint64_t a0 = std::max(lo, tstart), a1 = std::min(hi, tstart + tn);
-                if (a0 < a1)
-                    tdesc.push_back(TaskDesc{a1 - lo, t.id_begin + (a0 - tstart), t.pool, gid[t.g], (uint32_t)t.seed,
-                                             t.instance});
-                tstart += tn;
-            }
-            gr.ndesc = tdesc.size() - gr.first_desc;
-            groups.push_back(gr);
-        }
-    } else {
-        // plain form: one launch group per (task, ladder block, stratum)
-        uint64_t tstart = 0;
-        for (const RRTask &t : tasks) {
-            std::vector<std::pair<uint64_t, uint64_t>> ranges;
-            stratum_ranges(t.g, t.seed, t.instance, qlog, t.pool, t.id_begin, t.id_end, &ranges);
-            for (const auto &rg : ranges) {
-                const uint64_t lo = tstart + (rg.first - t.id_begin);
-                groups.push_back(Group{lo, lo + (rg.second - rg.first), tdesc.size(), 1});
-                tdesc.push_back(TaskDesc{rg.second - rg.first, rg.first, t.pool, gid[t.g], (uint32_t)t.seed,
-                                         t.instance});
-            }
-            tstart += t.id_end - t.id_begin;
-        }
-    }
-    HIM_CHECK(ws.graph_desc.reserve(sizeof(GraphDesc) * gdesc.size(), s));
-    HIM_CHECK(ws.task_desc.reserve(sizeof(TaskDesc) * std::max<size_t>(tdesc.size(), 1), s));
-    HIM_HIP(hipMemcpyAsync(ws.graph_desc.ptr, gdesc.data(), sizeof(GraphDesc) * gdesc.size(), hipMemcpyHostToDevice, s));
-    HIM_HIP(hipMemcpyAsync(ws.task_desc.ptr, tdesc.data(), sizeof(TaskDesc) * tdesc.size(), hipMemcpyHostToDevice, s));
-    HIM_HIP(hipStreamSynchronize(s));   // host vectors are pageable and local
-
-    unsigned long long *ctr = ws.counters.as<unsigned long long>();
-    for (int attempt = 0; attempt < 2; ++attempt) {
-        HIM_HIP(hipMemsetAsync(ctr, 0, sizeof(unsigned long long) * kNumCtr, s));
-        RRArgs a{};
-        a.graphs = ws.graph_desc.as<GraphDesc>();
-        a.qlog = qlog;
-        a.heavy = tune.heavy;
-        a.budget = tune.budget;
-        a.chunk = tune.chunk;
-        a.seg = std::max(tune.seg, tune.chunk);
-        a.prefilter_min = tune.prefilter_min;
-        a.slot_n = shape.slot_n;
-        a.slot_words = shape.slot_words;
-        a.ctr = ctr;
-        a.lists = ws.lists.as<uint32_t>();
-        a.bitmaps = ws.bitmaps.as<uint32_t>();
-        a.slot_total = shape.slots;
-        a.stage = ws.stage.as<uint32_t>();
-        a.stage_cap = ws.stage.bytes / sizeof(uint32_t);
-        a.stage_off = ws.stage_off.as<uint64_t>();
-        a.sizes = ws.sizes.as<uint32_t>();
-        a.roots = ws.roots.as<uint32_t>();
-        a.big_ids = ws.big_ids.as<uint64_t>();
-        a.def_idx = ws.def_idx.as<uint64_t>();
-        a.def_root = ws.def_u32.as<uint32_t>();
-        a.def_slot = a.def_root + ndef_cap;
-        a.def_head = a.def_slot + ndef_cap;
-        a.def_size = a.def_head + ndef_cap;
-        a.def_task = a.def_size + ndef_cap;
-        a.items = ws.items.as<uint4>();
-        RRStats run{};
-        for (const Group &gr : groups) {
-            a.tasks = ws.task_desc.as<TaskDesc>() + gr.first_desc;
-            a.ntasks = (uint32_t)gr.ndesc;
-            a.count = gr.hi - gr.lo;
-            a.out_base = gr.lo;
-            const uint32_t grid =
-                form == 0 ? shape.grid : (uint32_t)std::min<uint64_t>(shape.grid, div_up(a.count, kWavesPerWG));
-            HIM_CHECK(run_launch(ws, run, tune, a, shape, grid, trace, s));
-        }
-        // time counts every attempt, work only the one that produced the output
-        st.ms_bfs += run.ms_bfs;
-        st.ms_light += run.ms_light;
-        st.ms_heavy += run.ms_heavy;
-        st.launches += run.launches;
-        st.supersteps += run.supersteps;
-        st.ms_expand += run.ms_expand;
-        st.expand_launches += run.expand_launches;
-        uint64_t bump = 0, ba = 0, bb = 0;
-        HIM_CHECK(read_ctr(s, ctr, kBump, &bump));
-        HIM_CHECK(read_ctr(s, ctr, kBytesA, &ba));
-        HIM_CHECK(read_ctr(s, ctr, kBytesB, &bb));
-        if (count) {
-            ws.members_per_id = (double)bump / (double)count;
-            ws.defer_rate = (double)run.deferred / (double)count;
-        }
-        if (bump <= ws.stage.bytes / sizeof(uint32_t)) {
-            st.deferred += run.deferred;
-            st.bytes_light += ba;
-            st.bytes_heavy += bb;
-            *total = bump;
-            return HYPERIM_OK;
-        }
-        HIM_CHECK(ws.stage.reserve(sizeof(uint32_t) * (size_t)(bump + bump / 4 + 1024), s, false));
-    }
-    set_error_detail("RR stage overflow after resize");
-    return HYPERIM_ENOMEM;
-}
-
-int rr_compact_into(RRWorkspace &ws, hyperim_pool p, uint64_t first, uint64_t count, uint64_t max_entries,
-                    hipStream_t s) {
+// Append the staged sets with group-local indices [first, first + count) to
+// pool p (growing its storage; HYPERIM_ECAPACITY beyond max_entries or a
+// caller buffer).
+int compact_into(RRWorkspace &ws, hyperim_pool p, uint64_t first, uint64_t count, uint64_t max_entries,
+                 hipStream_t s) {
     if (count == 0) return HYPERIM_OK;
     HIM_CHECK(pool_reserve(p, count, 0, s));
     uint64_t *dst_off = p->off + p->count;
@@ -1158,6 +1020,251 @@ int rr_compact_into(RRWorkspace &ws, hyperim_pool p, uint64_t first, uint64_t co
     HIM_HIP(hipGetLastError());
     p->count += count;
     p->total = new_total;
+    return HYPERIM_OK;
+}
+
+}  // namespace
+
+size_t rr_slot_bytes(uint32_t n_max) {
+    SlotLayout L;
+    return slot_layout(n_max, &L) == HYPERIM_OK ? (size_t)L.bytes : 0;
+}
+
+int rr_generate_into(RRWorkspace &ws, RRStats &st, const std::vector<RRTask> &tasks,
+                     const std::vector<hyperim_pool> &pools, uint32_t qlog, int form, uint64_t max_entries,
+                     uint64_t stage_budget, hipStream_t s, std::vector<int> &pool_status) {
+    // HYPERIM_TRACE=1: synchronise after every grid-wide superstep and report
+    // its item count and time on stderr (diagnostics; same results)
+    static const bool trace = [] {
+        const char *e = getenv("HYPERIM_TRACE");
+        return e && e[0] == '1';
+    }();
+    pool_status.assign(tasks.size(), HYPERIM_OK);
+    if (tasks.empty()) return HYPERIM_OK;
+    // execution parameters of the first task's graph
+    const hyperim_tuning &tune = tasks[0].g->tune;
+    // graph descriptors (one per distinct graph)
+    std::map<hyperim_graph, uint32_t> gid;
+    std::vector<GraphDesc> gdesc;
+    uint32_t n_max = 1;
+    for (const RRTask &t : tasks) {
+        if (gid.count(t.g)) continue;
+        gid[t.g] = (uint32_t)gdesc.size();
+        hyperim_graph g = t.g;
+        gdesc.push_back(GraphDesc{g->he_off.as<uint32_t>(), g->he_mem.as<uint32_t>(), g->v_off.as<uint32_t>(),
+                                  g->v_he.as<uint32_t>(), g->thr.as<uint32_t>(), g->P.as<uint32_t>(), g->n,
+                                  (g->n + 31u) / 32u});
+        n_max = std::max(n_max, g->n);
+    }
+    uint64_t count = 0;
+    for (const RRTask &t : tasks) count += t.id_end - t.id_begin;
+    if (count == 0) return HYPERIM_OK;
+    LaunchShape shape;
+    HIM_CHECK(ensure_workspace(ws, n_max, s, &shape));
+
+    // Launch groups: [index lo, index hi) of the tasks laid back to back, each
+    // with its task descriptors.  A group's sets are staged, then compacted
+    // into their pools before the next group runs, so the stage holds one
+    // group.  Groups are cut so that their predicted members fit the stage
+    // budget -- 1.3 x the graph's members per set seen so far, or n (an upper
+    // bound) for a graph not seen yet -- and (form 0) so that the sets a group
+    // defers fit the spare slots at the deferral rate seen so far (a set that
+    // finds no spare slot stays with its wave).
+    const size_t ndef_cap = std::max<uint64_t>(shape.slots - (uint64_t)shape.grid * kWavesPerWG, 1);
+    const double stage_words = (double)stage_budget / 4.0;
+    auto per_set = [](hyperim_graph g) { return g->rr_members >= 0.0 ? 1.3 * g->rr_members + 1.0 : (double)g->n; };
+    double rate = 0.0;
+    for (const RRTask &t : tasks) rate = std::max(rate, t.g->rr_defer >= 0.0 ? t.g->rr_defer : 0.5);
+    const uint64_t def_chunk =
+        form == 0 ? std::max<uint64_t>((uint64_t)((double)ndef_cap / std::max(rate * 1.25, 1.0 / 64.0)), 4096)
+                  : ~0ull;
+    struct Group {
+        uint64_t lo, hi;
+        size_t first_desc, ndesc;
+        double predicted;   // staged words
+    };
+    struct Slice {
+        size_t task;
+        uint64_t lo, hi;   // launch indices
+    };
+    std::vector<Group> groups;
+    std::vector<TaskDesc> tdesc;
+    std::vector<Slice> slices;   // per descriptor
+    auto add_group = [&](uint64_t lo, uint64_t hi) {
+        Group gr{lo, hi, tdesc.size(), 0, 0.0};
+        uint64_t tstart = 0;
+        for (size_t ti = 0; ti < tasks.size(); ++ti) {
+            const RRTask &t = tasks[ti];
+            const uint64_t tn = t.id_end - t.id_begin;
+            const uint64_t a0 = std::max(lo, tstart), a1 = std::min(hi, tstart + tn);
+            if (a0 < a1) {
+                tdesc.push_back(TaskDesc{a1 - lo, t.id_begin + (a0 - tstart), t.pool, gid[t.g], (uint32_t)t.seed,
+                                         t.instance});
+                slices.push_back(Slice{ti, a0, a1});
+                gr.predicted += (double)(a1 - a0) * per_set(t.g);
+            }
+            tstart += tn;
+        }
+        gr.ndesc = tdesc.size() - gr.first_desc;
+        groups.push_back(gr);
+    };
+    // cut the index range [lo, hi) of one task (per-set prediction m) into
+    // the running group, closing groups as they fill
+    uint64_t g_lo = 0, g_cnt = 0;
+    double g_acc = 0.0;
+    auto feed = [&](uint64_t lo, uint64_t hi, double m, uint64_t cap) {
+        uint64_t x = lo;
+        while (x < hi) {
+            const double room = stage_words - g_acc;
+            uint64_t take = std::min<uint64_t>(hi - x, room > 0.0 ? (uint64_t)(room / m) : 0);
+            take = std::min<uint64_t>(take, cap - g_cnt);
+            if (take == 0) {
+                if (g_cnt == 0) {
+                    take = 1;   // one set always fits
+                } else {
+                    add_group(g_lo, g_lo + g_cnt);
+                    g_lo += g_cnt;
+                    g_cnt = 0;
+                    g_acc = 0.0;
+                    continue;
+                }
+            }
+            g_acc += (double)take * m;
+            g_cnt += take;
+            x += take;
+        }
+    };
+    auto close = [&]() {
+        if (g_cnt) add_group(g_lo, g_lo + g_cnt);
+        g_lo += g_cnt;
+        g_cnt = 0;
+        g_acc = 0.0;
+    };
+    if (form == 0) {
+        uint64_t tstart = 0;
+        for (const RRTask &t : tasks) {
+            const uint64_t tn = t.id_end - t.id_begin;
+            feed(tstart, tstart + tn, per_set(t.g), def_chunk);
+            tstart += tn;
+        }
+        close();
+    } else {
+        // plain form: launches per (task, ladder block, stratum), a stratum
+        // range split further only by the stage budget
+        uint64_t tstart = 0;
+        for (const RRTask &t : tasks) {
+            std::vector<std::pair<uint64_t, uint64_t>> ranges;
+            stratum_ranges(t.g, t.seed, t.instance, qlog, t.pool, t.id_begin, t.id_end, &ranges);
+            for (const auto &rg : ranges) {
+                g_lo = tstart + (rg.first - t.id_begin);
+                feed(g_lo, g_lo + (rg.second - rg.first), per_set(t.g), ~0ull);
+                close();
+            }
+            tstart += t.id_end - t.id_begin;
+        }
+    }
+    uint64_t max_group = 0;
+    for (const Group &gr : groups) max_group = std::max(max_group, gr.hi - gr.lo);
+    HIM_CHECK(ws.stage_off.reserve(sizeof(uint64_t) * max_group, s, false));
+    HIM_CHECK(ws.sizes.reserve(sizeof(uint32_t) * max_group, s, false));
+    HIM_CHECK(ws.roots.reserve(sizeof(uint32_t) * max_group, s, false));
+    HIM_CHECK(ws.big_ids.reserve(sizeof(uint64_t) * max_group, s, false));
+    HIM_CHECK(ws.graph_desc.reserve(sizeof(GraphDesc) * gdesc.size(), s));
+    HIM_CHECK(ws.task_desc.reserve(sizeof(TaskDesc) * std::max<size_t>(tdesc.size(), 1), s));
+    HIM_HIP(hipMemcpyAsync(ws.graph_desc.ptr, gdesc.data(), sizeof(GraphDesc) * gdesc.size(), hipMemcpyHostToDevice, s));
+    HIM_HIP(hipMemcpyAsync(ws.task_desc.ptr, tdesc.data(), sizeof(TaskDesc) * tdesc.size(), hipMemcpyHostToDevice, s));
+    HIM_HIP(hipStreamSynchronize(s));   // host vectors are pageable and local
+
+    unsigned long long *ctr = ws.counters.as<unsigned long long>();
+    RRArgs a{};
+    a.graphs = ws.graph_desc.as<GraphDesc>();
+    a.qlog = qlog;
+    a.heavy = tune.heavy;
+    a.budget = tune.budget;
+    a.chunk = tune.chunk;
+    a.seg = std::max(tune.seg, tune.chunk);
+    a.prefilter_min = tune.prefilter_min;
+    a.slot_n = shape.slot_n;
+    a.slot_words = shape.slot_words;
+    a.ctr = ctr;
+    a.lists = ws.lists.as<uint32_t>();
+    a.bitmaps = ws.bitmaps.as<uint32_t>();
+    a.slot_total = shape.slots;
+    a.out_base = 0;
+    a.stage_off = ws.stage_off.as<uint64_t>();
+    a.sizes = ws.sizes.as<uint32_t>();
+    a.roots = ws.roots.as<uint32_t>();
+    a.big_ids = ws.big_ids.as<uint64_t>();
+    a.def_idx = ws.def_idx.as<uint64_t>();
+    a.def_root = ws.def_u32.as<uint32_t>();
+    a.def_slot = a.def_root + ndef_cap;
+    a.def_head = a.def_slot + ndef_cap;
+    a.def_size = a.def_head + ndef_cap;
+    a.def_task = a.def_size + ndef_cap;
+    a.items = ws.items.as<uint4>();
+    for (const Group &gr : groups) {
+        a.tasks = ws.task_desc.as<TaskDesc>() + gr.first_desc;
+        a.ntasks = (uint32_t)gr.ndesc;
+        a.count = gr.hi - gr.lo;
+        const uint32_t grid =
+            form == 0 ? shape.grid : (uint32_t)std::min<uint64_t>(shape.grid, div_up(a.count, kWavesPerWG));
+        // stage sized from the prediction (a miss re-runs the group)
+        const uint64_t predicted = (uint64_t)gr.predicted + 4 * a.count + (1u << 20);
+        if (ws.stage.bytes < sizeof(uint32_t) * predicted)
+            HIM_CHECK(ws.stage.reserve(sizeof(uint32_t) * predicted, s, false));
+        bool staged = false;
+        for (int attempt = 0; attempt < 2 && !staged; ++attempt) {
+            a.stage = ws.stage.as<uint32_t>();
+            a.stage_cap = ws.stage.bytes / sizeof(uint32_t);
+            HIM_HIP(hipMemsetAsync(ctr, 0, sizeof(unsigned long long) * kNumCtr, s));
+            RRStats run{};
+            HIM_CHECK(run_launch(ws, run, tune, a, shape, grid, trace, s));
+            // time counts every attempt, work only the one that produced the output
+            st.ms_bfs += run.ms_bfs;
+            st.ms_light += run.ms_light;
+            st.ms_heavy += run.ms_heavy;
+            st.launches += run.launches;
+            st.supersteps += run.supersteps;
+            st.ms_expand += run.ms_expand;
+            st.expand_launches += run.expand_launches;
+            uint64_t bump = 0, ba = 0, bb = 0;
+            HIM_CHECK(read_ctr(s, ctr, kBump, &bump));
+            HIM_CHECK(read_ctr(s, ctr, kBytesA, &ba));
+            HIM_CHECK(read_ctr(s, ctr, kBytesB, &bb));
+            for (size_t d = gr.first_desc; d < gr.first_desc + gr.ndesc; ++d)
+                tasks[slices[d].task].g->rr_defer = (double)run.deferred / (double)a.count;
+            if (bump <= a.stage_cap) {
+                st.deferred += run.deferred;
+                st.bytes_light += ba;
+                st.bytes_heavy += bb;
+                staged = true;
+            } else {
+                HIM_CHECK(ws.stage.reserve(sizeof(uint32_t) * (size_t)(bump + bump / 4 + 1024), s, false));
+            }
+        }
+        if (!staged) {
+            set_error_detail("RR stage overflow after resize");
+            return HYPERIM_ENOMEM;
+        }
+        for (size_t d = gr.first_desc; d < gr.first_desc + gr.ndesc; ++d) {
+            const Slice &sl = slices[d];
+            if (pool_status[sl.task] != HYPERIM_OK) continue;
+            hyperim_pool p = pools[sl.task];
+            const uint64_t before = p->total;
+            const int rc = compact_into(ws, p, sl.lo - gr.lo, sl.hi - sl.lo, max_entries, s);
+            if (rc == HYPERIM_ECAPACITY) {
+                pool_status[sl.task] = rc;   // this pool is full; the others go on
+            } else if (rc != HYPERIM_OK) {
+                return rc;
+            } else {
+                // members per set of this graph, learned for later predictions
+                hyperim_graph g = tasks[sl.task].g;
+                g->rr_seen_sets += sl.hi - sl.lo;
+                g->rr_seen_members += p->total - before;
+                g->rr_members = (double)g->rr_seen_members / (double)g->rr_seen_sets;
+            }
+        }
+    }
     return HYPERIM_OK;
 }
 
