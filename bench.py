@@ -48,6 +48,8 @@ def parse():
                          "tiny/mid/multi, 0 on large)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU-baseline sample time")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tuning", default="stored", choices=["stored", "default"],
+                    help="execution parameters: the autotuner's stored result for the workload, or the defaults")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="also run one device-to-device copy of this many MiB (reference kernel for "
                          "scaling hardware byte counters)")
@@ -131,6 +133,8 @@ def main():
         hgs = [hg]
         dev = [(dev_off, dev_mem)]
     torch.cuda.synchronize()
+    from paper_2406_01911_amd import autotune
+    tuning = autotune.load(args.workload) if args.tuning == "stored" else None
 
     def step(flags=0, form=args.form):
         """One query step: build + stratify every graph, then seed selection
@@ -140,6 +144,8 @@ def main():
         for h, (o, m), wl in zip(hgs, dev, ws):
             g = hy.build_graph(h.n, o, m, wl.model, wl.p, stream=stream)
             g.stratify(stream=stream)
+            if tuning:
+                g.set_tuning(**tuning)
             gs.append(g)
         if args.workload != "multi":
             r = hy.select_seeds(gs[0], w.k, w.eps, w.ell, seed=w.philox_seed, form=form, flags=flags,
@@ -242,6 +248,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {WORKLOAD_TEXT[args.workload]}",
                    "form": "persistent" if args.form == 0 else "plain-per-stratum",
+                   "tuning": tuning if tuning else "default",
                    "parallelism": "single-gpu"},
         "incidences_per_s": inc_per_s,
         "time_to_seed_set_ms": ms_per_step,

@@ -103,6 +103,19 @@ def multi_instance_workloads(count: int = 64, base_seed: int = 1000):
     return out
 
 
+def serving_workloads(count: int = 16, n_max: int = 5_000_000, n_min: int = 50_000, base_seed: int = 2000):
+    """Graphs of the serving pool: |V| log-spaced from n_max down to n_min,
+    |HE| = 2|V|, sizes power law (2.1) on [2, 1000], uniform members, weighted
+    cascade.  Query parameters (k in {10, 50, 200}, eps = 0.1) are drawn by
+    the serving driver."""
+    out = []
+    for i in range(count):
+        n = int(round(n_max * (n_min / n_max) ** (i / max(count - 1, 1))))
+        out.append(Workload(f"serve{i}", n, 2 * n, ("powerlaw", 2.1, 2, 1000), ("uniform",),
+                            MODEL_WC, 0.0, 50, 0.1, 1.0, gen_seed=base_seed + i))
+    return out
+
+
 def power_law_sizes(rng: np.random.Generator, m: int, gamma: float, lo: int, hi: int) -> np.ndarray:
     """m sizes from P(s) proportional to s**-gamma on [lo, hi], by inverse CDF
     over the exact probability table."""

@@ -303,13 +303,19 @@ int hyperim_workspace_release(void);
  *   seg:           light incidences per frontier-segment work item (512,
  *                  raised to chunk if smaller);
  *   prefilter_min: the grid-wide phase tests visited marks before coins in
- *                  sets of at least this many members (4096);
+ *                  sets of at least this many members (0xFFFFFFFF: never;
+ *                  the scattered mark loads cost more than the coins they
+ *                  save on the workloads measured);
  *   steps_per_sync: grid-wide supersteps launched between host checks (8);
  *   stage_mib:     staging memory a generation pass aims at: launch groups
- *                  are cut so that their members fit (16384 MiB, min 64). */
+ *                  are cut so that their members fit (16384 MiB, min 64);
+ *   blocks_a:      per-set phase workgroups per compute unit, at most the
+ *                  occupancy limit (4; 0 = the occupancy limit);
+ *   blocks_b:      grid-wide expansion workgroups per compute unit (6; 0 =
+ *                  the occupancy limit). */
 typedef struct {
     uint32_t heavy, budget, chunk, seg, prefilter_min, steps_per_sync;
-    uint32_t stage_mib;
+    uint32_t stage_mib, blocks_a, blocks_b;
     uint32_t reserved;
 } hyperim_tuning;
 

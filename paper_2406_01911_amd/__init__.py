@@ -58,7 +58,7 @@ class _Result(C.Structure):
 class _Tuning(C.Structure):
     _fields_ = [("heavy", C.c_uint32), ("budget", C.c_uint32), ("chunk", C.c_uint32), ("seg", C.c_uint32),
                 ("prefilter_min", C.c_uint32), ("steps_per_sync", C.c_uint32), ("stage_mib", C.c_uint32),
-                ("reserved", C.c_uint32)]
+                ("blocks_a", C.c_uint32), ("blocks_b", C.c_uint32), ("reserved", C.c_uint32)]
 
 
 class _Query(C.Structure):
@@ -72,7 +72,8 @@ class _SessionStats(C.Structure):
                 ("ran_last", C.c_uint64), ("bytes_resident", C.c_size_t), ("hbm_budget", C.c_size_t)]
 
 
-TUNING_FIELDS = ["heavy", "budget", "chunk", "seg", "prefilter_min", "steps_per_sync", "stage_mib"]
+TUNING_FIELDS = ["heavy", "budget", "chunk", "seg", "prefilter_min", "steps_per_sync", "stage_mib", "blocks_a",
+                 "blocks_b"]
 
 EXPORTS = ["hyperim_build_graph", "hyperim_stratify", "hyperim_graph_read", "hyperim_pool_create",
            "hyperim_generate_rr", "hyperim_pool_view", "hyperim_pool_read", "hyperim_pool_required",

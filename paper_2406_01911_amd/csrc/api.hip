@@ -117,8 +117,12 @@ DeviceLock::~DeviceLock() { static_cast<DevCtx *>(lock)->mu.unlock(); }
 
 void GreedyWorkspace::release() {
     for (DevBuf *x : {&cnt, &inv_off, &cursor, &inv, &covered, &chosen, &best, &out, &big, &round_big, &flags,
-                      &counters, &scan_tmp})
+                      &counters, &scan_tmp, &params})
         x->release();
+    if (rounds_exec) (void)hipGraphExecDestroy(rounds_exec);
+    rounds_exec = nullptr;
+    graph_k = 0;
+    graph_params = nullptr;
 }
 
 size_t RRWorkspace::bytes() const {
@@ -496,6 +500,8 @@ int hyperim_set_tuning(hyperim_graph g, const hyperim_tuning *t) {
     if (t->prefilter_min) cur.prefilter_min = t->prefilter_min;
     if (t->steps_per_sync) cur.steps_per_sync = std::min<uint32_t>(t->steps_per_sync, 64);
     if (t->stage_mib) cur.stage_mib = std::max<uint32_t>(t->stage_mib, 64);
+    if (t->blocks_a) cur.blocks_a = t->blocks_a;
+    if (t->blocks_b) cur.blocks_b = t->blocks_b;
     return HYPERIM_OK;
 }
 

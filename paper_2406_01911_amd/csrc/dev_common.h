@@ -95,6 +95,17 @@ __device__ __forceinline__ uint64_t wave_bcast64(uint64_t x, int src) {
     return (uint64_t)__shfl((unsigned long long)x, src, kWave);
 }
 
+// Wave-uniform values kept in scalar registers: the value of the first active
+// lane (callers pass values that are equal on every active lane).
+__device__ __forceinline__ uint32_t uni(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ uint64_t uni64(uint64_t x) {
+    return ((uint64_t)uni((uint32_t)(x >> 32)) << 32) | (uint64_t)uni((uint32_t)x);
+}
+template <typename P>
+__device__ __forceinline__ P uni_ptr(P p) {
+    return (P)uni64((uint64_t)p);
+}
+
 // Make this wave's earlier LDS and global writes visible to its own later
 // reads by other lanes, and keep the compiler from moving memory accesses
 // across the point.

@@ -14,6 +14,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstring>
 
 #include "dev_common.h"
 #include "internal.h"
@@ -105,11 +106,31 @@ __global__ __launch_bounds__(kWG) void k_inv_big(const uint64_t *__restrict__ of
     }
 }
 
+// Arguments of the per-round kernels, in device memory so that one captured
+// graph of all k rounds serves every pool and theta.
+struct GreedyParams {
+    const uint64_t *off;
+    const uint32_t *mem;
+    const uint64_t *inv_off;
+    const uint32_t *inv;
+    uint8_t *covered;
+    uint32_t *cnt;
+    uint8_t *chosen;
+    uint32_t *seeds;
+    unsigned long long *gains;
+    uint64_t *round_big;
+    unsigned long long *best;        // k argmax keys
+    unsigned long long *nbig_round;  // k counters
+    uint32_t n;
+};
+
 // key = 0 for chosen vertices, else (cnt + 1) << 32 | (~v): the max is the
 // largest count, then the smallest id.
-__global__ __launch_bounds__(kWG) void k_argmax(const uint32_t *__restrict__ cnt, const uint8_t *__restrict__ chosen,
-                                                 uint32_t n, unsigned long long *__restrict__ best) {
+__global__ __launch_bounds__(kWG) void k_argmax(const GreedyParams *__restrict__ P, uint32_t round) {
     __shared__ unsigned long long part[kWavesPerWG];
+    const uint32_t n = P->n;
+    const uint32_t *__restrict__ cnt = P->cnt;
+    const uint8_t *__restrict__ chosen = P->chosen;
     unsigned long long m = 0;
     for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
         const unsigned long long key =
@@ -122,26 +143,25 @@ __global__ __launch_bounds__(kWG) void k_argmax(const uint32_t *__restrict__ cnt
     if (threadIdx.x == 0) {
         for (int w = 1; w < kWavesPerWG; ++w) m = part[w] > m ? part[w] : m;
         m = part[0] > m ? part[0] : m;
-        atomicMax(best, m);
+        atomicMax(P->best + round, m);
     }
 }
 
-__global__ __launch_bounds__(kWG) void k_invalidate(const unsigned long long *__restrict__ best_i, uint32_t round,
-                                                     const uint64_t *__restrict__ inv_off,
-                                                     const uint32_t *__restrict__ inv, const uint64_t *__restrict__ off,
-                                                     const uint32_t *__restrict__ mem, uint8_t *__restrict__ covered,
-                                                     uint32_t *__restrict__ cnt, uint8_t *__restrict__ chosen,
-                                                     uint32_t *__restrict__ seeds, unsigned long long *__restrict__ gains,
-                                                     uint64_t *__restrict__ big, unsigned long long *__restrict__ nbig) {
+__global__ __launch_bounds__(kWG) void k_invalidate(const GreedyParams *__restrict__ P, uint32_t round) {
     __shared__ FlatLds lds[kWavesPerWG];
-    const unsigned long long key = *best_i;
+    const unsigned long long key = P->best[round];
     const uint32_t s = 0xFFFFFFFFu - (uint32_t)key;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        seeds[round] = s;
-        gains[round] = (key >> 32) - 1ull;
-        chosen[s] = 1;
+        P->seeds[round] = s;
+        P->gains[round] = (key >> 32) - 1ull;
+        P->chosen[s] = 1;
     }
-    const uint64_t x0 = inv_off[s], x1 = inv_off[s + 1];
+    const uint64_t *__restrict__ off = P->off;
+    const uint32_t *__restrict__ mem = P->mem;
+    const uint32_t *__restrict__ inv = P->inv;
+    uint8_t *__restrict__ covered = P->covered;
+    uint32_t *__restrict__ cnt = P->cnt;
+    const uint64_t x0 = P->inv_off[s], x1 = P->inv_off[s + 1];
     const uint32_t wv = threadIdx.x / kWave;
     const uint64_t waves = (uint64_t)gridDim.x * kWavesPerWG;
     for (uint64_t grp = (uint64_t)blockIdx.x * kWavesPerWG + wv; x0 + grp * kWave < x1; grp += waves) {
@@ -154,7 +174,7 @@ __global__ __launch_bounds__(kWG) void k_invalidate(const unsigned long long *__
                 covered[j] = 1;
                 beg = off[j];
                 const uint64_t sz = off[j + 1] - beg;
-                if (sz > kBigSet) big[atomicAdd(nbig, 1ull)] = j;
+                if (sz > kBigSet) P->round_big[atomicAdd(P->nbig_round + round, 1ull)] = j;
                 else len = (uint32_t)sz;
             }
         }
@@ -162,13 +182,13 @@ __global__ __launch_bounds__(kWG) void k_invalidate(const unsigned long long *__
     }
 }
 
-__global__ __launch_bounds__(kWG) void k_invalidate_big(const uint64_t *__restrict__ big,
-                                                         const unsigned long long *__restrict__ nbig,
-                                                         const uint64_t *__restrict__ off,
-                                                         const uint32_t *__restrict__ mem, uint32_t *__restrict__ cnt) {
-    const uint64_t nb = *nbig;
+__global__ __launch_bounds__(kWG) void k_invalidate_big(const GreedyParams *__restrict__ P, uint32_t round) {
+    const uint64_t nb = P->nbig_round[round];
+    const uint64_t *__restrict__ off = P->off;
+    const uint32_t *__restrict__ mem = P->mem;
+    uint32_t *__restrict__ cnt = P->cnt;
     for (uint64_t b = blockIdx.x; b < nb; b += gridDim.x) {
-        const uint64_t j = big[b];
+        const uint64_t j = P->round_big[b];
         for (uint64_t e = off[j] + threadIdx.x; e < off[j + 1]; e += blockDim.x) atomicSub(&cnt[mem[e]], 1u);
     }
 }
@@ -280,17 +300,42 @@ int greedy_device(GreedyWorkspace &w, hyperim_graph g, hyperim_pool p, uint64_t 
         hipLaunchKernelGGL(k_inv_big, dim3(1024), dim3(kWG), 0, s, p->off, p->mem, w.big.as<uint64_t>(), nbig_all,
                            w.inv_off.as<uint64_t>(), w.cursor.as<uint32_t>(), w.inv.as<uint32_t>());
     }
+    // the k rounds: one captured graph per (k, argmax grid), replayed with
+    // this call's arguments in the device parameter block; the invalidation
+    // grid is fixed (grid-stride over a seed's sets) so theta does not change
+    // the graph
     const uint32_t argmax_grid = grid_for(n, kWG, 1024);
-    const uint32_t inval_grid = grid_for(theta, kWG, 1024);
-    for (uint32_t i = 0; i < k; ++i) {
-        hipLaunchKernelGGL(k_argmax, dim3(argmax_grid), dim3(kWG), 0, s, w.cnt.as<uint32_t>(), w.chosen.as<uint8_t>(),
-                           n, best + i);
-        hipLaunchKernelGGL(k_invalidate, dim3(inval_grid), dim3(kWG), 0, s, best + i, i, w.inv_off.as<uint64_t>(),
-                           w.inv.as<uint32_t>(), p->off, p->mem, w.covered.as<uint8_t>(), w.cnt.as<uint32_t>(),
-                           w.chosen.as<uint8_t>(), seeds, gains, w.round_big.as<uint64_t>(), nbig_round + i);
-        hipLaunchKernelGGL(k_invalidate_big, dim3(256), dim3(kWG), 0, s, w.round_big.as<uint64_t>(), nbig_round + i,
-                           p->off, p->mem, w.cnt.as<uint32_t>());
+    const uint32_t inval_grid = 128;
+    GreedyParams hp{p->off, p->mem, w.inv_off.as<uint64_t>(), w.inv.as<uint32_t>(), w.covered.as<uint8_t>(),
+                    w.cnt.as<uint32_t>(), w.chosen.as<uint8_t>(), seeds, gains, w.round_big.as<uint64_t>(), best,
+                    nbig_round, n};
+    HIM_CHECK(w.params.reserve(sizeof(GreedyParams), s));
+    static_assert(sizeof(GreedyParams) <= sizeof(w.params_host), "parameter block");
+    memcpy(w.params_host, &hp, sizeof(hp));
+    HIM_HIP(hipMemcpyAsync(w.params.ptr, w.params_host, sizeof(GreedyParams), hipMemcpyHostToDevice, s));
+    const GreedyParams *P = w.params.as<GreedyParams>();
+    if (!w.rounds_exec || w.graph_k != k || w.graph_grid[0] != argmax_grid || w.graph_grid[1] != inval_grid ||
+        w.graph_params != w.params.ptr) {
+        if (w.rounds_exec) HIM_HIP(hipGraphExecDestroy(w.rounds_exec));
+        w.rounds_exec = nullptr;
+        if (!w.capture) HIM_HIP(hipStreamCreateWithFlags(&w.capture, hipStreamNonBlocking));
+        hipGraph_t graph = nullptr;
+        HIM_HIP(hipStreamBeginCapture(w.capture, hipStreamCaptureModeThreadLocal));
+        for (uint32_t i = 0; i < k; ++i) {
+            hipLaunchKernelGGL(k_argmax, dim3(argmax_grid), dim3(kWG), 0, w.capture, P, i);
+            hipLaunchKernelGGL(k_invalidate, dim3(inval_grid), dim3(kWG), 0, w.capture, P, i);
+            hipLaunchKernelGGL(k_invalidate_big, dim3(256), dim3(kWG), 0, w.capture, P, i);
+        }
+        HIM_HIP(hipStreamEndCapture(w.capture, &graph));
+        const hipError_t e = hipGraphInstantiate(&w.rounds_exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        HIM_HIP(e);
+        w.graph_k = k;
+        w.graph_grid[0] = argmax_grid;
+        w.graph_grid[1] = inval_grid;
+        w.graph_params = w.params.ptr;
     }
+    HIM_HIP(hipGraphLaunch(w.rounds_exec, s));
     HIM_HIP(hipGetLastError());
     if (seeds_host) HIM_HIP(hipMemcpyAsync(seeds_host, seeds, sizeof(uint32_t) * k, hipMemcpyDeviceToHost, s));
     if (gains_host) HIM_HIP(hipMemcpyAsync(gains_host, gains, sizeof(uint64_t) * k, hipMemcpyDeviceToHost, s));

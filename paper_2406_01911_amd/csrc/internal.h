@@ -52,6 +52,7 @@ struct RRWorkspace {
     uint32_t grid = 0;           // workgroups of the phase A launch
     uint32_t slots = 0;          // slots: phase A waves + spare slots for deferred sets
     uint32_t grid_b = 0;         // workgroups of a phase B expansion launch
+    uint32_t cus = 0;            // compute units of the device
     uint32_t slot_n = 0, slot_words = 0;  // slot list length / bitmap words (largest graph so far)
     bool lds = false;            // phase A bitmaps in LDS (every graph small)
     DevBuf lists;                // slots * slot_n     : member list / BFS queue per slot
@@ -96,6 +97,13 @@ struct GreedyWorkspace {
     DevBuf flags;     // n uint8 seed marks (coverage)
     DevBuf counters;  // coverage counters
     DevBuf scan_tmp;
+    DevBuf params;    // argument block of the per-round kernels
+    alignas(16) unsigned char params_host[256];
+    // captured graph of the k greedy rounds and what it was captured for
+    hipStream_t capture = nullptr;
+    hipGraphExec_t rounds_exec = nullptr;
+    uint32_t graph_k = 0, graph_grid[2] = {0, 0};
+    void *graph_params = nullptr;
     size_t bytes() const;
     void release();
 };
@@ -125,7 +133,7 @@ struct hyperim_graph_s {
     bool stratified = false;
     hyperim::DevBuf l, deg, top, stratum, P;
     hyperim_strata_info info{};
-    hyperim_tuning tune{1024, 16384, 256, 512, 4096, 8, 16384, 0};  // RR execution parameters
+    hyperim_tuning tune{1024, 16384, 256, 512, 0xFFFFFFFFu, 8, 16384, 4, 6, 0};  // RR execution parameters
     // learned from generated sets (launch-group and stage sizing, admission);
     // -1 = nothing generated yet
     double rr_members = -1.0, rr_defer = -1.0;

@@ -72,6 +72,30 @@ struct GraphDesc {
     uint32_t n, bm_words;
 };
 
+// The same arrays as global-memory pointers: descriptors are read from device
+// memory, where the compiler cannot tell their address space and would emit
+// flat loads.
+#define HIM_GLOBAL __attribute__((address_space(1)))
+struct GraphView {
+    const HIM_GLOBAL uint32_t *he_off, *he_mem, *v_off, *v_he, *thr, *P;
+    uint32_t n, bm_words;
+};
+
+// Descriptors are read at wave-uniform indices; their fields go to scalar
+// registers.
+__device__ __forceinline__ GraphView graph_view(const GraphDesc &d) {
+    GraphView v;
+    v.he_off = uni_ptr((const HIM_GLOBAL uint32_t *)d.he_off);
+    v.he_mem = uni_ptr((const HIM_GLOBAL uint32_t *)d.he_mem);
+    v.v_off = uni_ptr((const HIM_GLOBAL uint32_t *)d.v_off);
+    v.v_he = uni_ptr((const HIM_GLOBAL uint32_t *)d.v_he);
+    v.thr = uni_ptr((const HIM_GLOBAL uint32_t *)d.thr);
+    v.P = uni_ptr((const HIM_GLOBAL uint32_t *)d.P);
+    v.n = uni(d.n);
+    v.bm_words = uni(d.bm_words);
+    return v;
+}
+
 // One task of a launch group: launch indices [previous end, end) are RR ids
 // first_id, first_id + 1, ... of pool `pool` on graph `graph` with Philox key
 // (key0, key1).
@@ -109,32 +133,34 @@ struct WaveLds {
     uint32_t in_scan[kWave], in_he[kWave], in_hb[kWave], in_hs[kWave], in_v[kWave], in_thr[kWave];
 };
 
-// The task of launch index idx (first task whose end exceeds idx).
+// The task of launch index idx (first task whose end exceeds idx); idx is
+// wave-uniform.
 __device__ __forceinline__ uint32_t task_of(const RRArgs &a, uint64_t idx) {
     uint32_t lo = 0, hi = a.ntasks - 1;
     while (lo < hi) {
         const uint32_t mid = (lo + hi) >> 1;
-        if (a.tasks[mid].end > idx) hi = mid; else lo = mid + 1;
+        if (uni64(a.tasks[mid].end) > idx) hi = mid; else lo = mid + 1;
     }
     return lo;
 }
 
 // What a set needs to know about where it comes from.
 struct SetRef {
-    GraphDesc G;
+    GraphView G;
     uint64_t j;
     uint32_t pool;
     uint2 key;
 };
 
+// t and idx are wave-uniform.
 __device__ __forceinline__ SetRef set_ref(const RRArgs &a, uint32_t t, uint64_t idx) {
-    const TaskDesc T = a.tasks[t];
-    const uint64_t start = t ? a.tasks[t - 1].end : 0ull;
+    const TaskDesc &T = a.tasks[t];
+    const uint64_t start = t ? uni64(a.tasks[t - 1].end) : 0ull;
     SetRef r;
-    r.G = a.graphs[T.graph];
-    r.j = T.first_id + (idx - start);
-    r.pool = T.pool;
-    r.key = make_uint2(T.key0, T.key1);
+    r.G = graph_view(a.graphs[uni(T.graph)]);
+    r.j = uni64(T.first_id) + (idx - start);
+    r.pool = uni(T.pool);
+    r.key = make_uint2(uni(T.key0), uni(T.key1));
     return r;
 }
 
@@ -142,7 +168,7 @@ __device__ __forceinline__ SetRef set_ref(const RRArgs &a, uint32_t t, uint64_t 
 // 0, Q 2^(b-1) in block b >= 1, so block sizes are powers of two), offset
 // o_b = floor(x n / 2^64) from the block's Philox draw, root =
 // P[floor((t n + o_b) / T_b)] computed in 128-bit arithmetic.
-__device__ __forceinline__ uint32_t rr_root(const GraphDesc &G, uint32_t qlog, uint64_t j, uint32_t pool, uint2 key) {
+__device__ __forceinline__ uint32_t rr_root(const GraphView &G, uint32_t qlog, uint64_t j, uint32_t pool, uint2 key) {
     const uint64_t Q = 1ull << qlog;
     uint32_t b, s;
     uint64_t J;
@@ -210,7 +236,7 @@ struct SharedAppend {
 // go to `app`.  Every lane of the wave must call it (inactive lanes with
 // active = false).
 template <bool kLds, class App>
-__device__ __forceinline__ void test_octet(const GraphDesc &G, uint64_t j, uint32_t pool, uint2 key, uint32_t *bm,
+__device__ __forceinline__ void test_octet(const GraphView &G, uint64_t j, uint32_t pool, uint2 key, uint32_t *bm,
                                            bool prefilter, bool active, uint32_t he, uint32_t hb, uint32_t p0,
                                            uint32_t cm, uint32_t ve, uint32_t the, App &app) {
     uint32_t u[8];
@@ -266,7 +292,7 @@ __device__ __forceinline__ void test_octet(const GraphDesc &G, uint64_t j, uint3
 // hyperedges over the wave.  Returns the algorithmic bytes of the incidences
 // read (12 per incidence plus 4 per member position), wave-uniform.
 template <bool kLds, bool kUniform, class App>
-__device__ __forceinline__ uint64_t expand(const GraphDesc &G, WaveLds &L, uint64_t j, uint32_t pool, uint2 key,
+__device__ __forceinline__ uint64_t expand(const GraphView &G, WaveLds &L, uint64_t j, uint32_t pool, uint2 key,
                                            uint32_t *bm, bool prefilter, uint32_t v, uint32_t e0, uint32_t d,
                                            App &app) {
     const uint32_t lane = lane_id();
@@ -358,7 +384,7 @@ __global__ __launch_bounds__(kWG) void k_rr_light(RRArgs a) {
     __shared__ WaveLds lds[kWavesPerWG];
     __shared__ uint32_t sort_s[kWavesPerWG][kSortMax];
     __shared__ uint32_t lbm[kLdsBitmap ? kWavesPerWG : 1][kLdsBitmap ? kLdsBitmapWords : 1];
-    const uint32_t lane = lane_id(), wv = threadIdx.x / kWave;
+    const uint32_t lane = lane_id(), wv = uni(threadIdx.x / kWave);
     uint32_t slot = blockIdx.x * kWavesPerWG + wv;
     WaveLds &L = lds[wv];
     uint32_t *sortb = sort_s[wv];
@@ -377,11 +403,11 @@ __global__ __launch_bounds__(kWG) void k_rr_light(RRArgs a) {
     for (;;) {
         unsigned long long idx = 0;
         if (lane == 0) idx = atomicAdd(&a.ctr[kWork], 1ull);
-        idx = wave_bcast64(idx, 0);
+        idx = uni64(wave_bcast64(idx, 0));
         if (idx >= a.count) break;
         const uint32_t task = task_of(a, idx);
         const SetRef S = set_ref(a, task, idx);
-        const GraphDesc &G = S.G;
+        const GraphView &G = S.G;
         const uint32_t root = rr_root(G, a.qlog, S.j, S.pool, S.key);
         if (lane == 0) {
             list[0] = root;
@@ -502,13 +528,13 @@ __global__ __launch_bounds__(kWG) void k_rr_light(RRArgs a) {
 constexpr uint32_t kSkipItem = 0xFFFFFFFFu;
 
 __global__ __launch_bounds__(kWG) void k_plan(RRArgs a, uint32_t ndef, uint32_t parity) {
-    const uint32_t lane = lane_id(), wv = threadIdx.x / kWave;
+    const uint32_t lane = lane_id(), wv = uni(threadIdx.x / kWave);
     const uint32_t waves = gridDim.x * kWavesPerWG;
     for (uint32_t d = blockIdx.x * kWavesPerWG + wv; d < ndef; d += waves) {
-        uint32_t head = a.def_head[d];
-        const uint32_t size = a.def_size[d];
-        const uint32_t *list = a.lists + (uint64_t)a.def_slot[d] * a.slot_n;
-        const GraphDesc G = a.graphs[a.tasks[a.def_task[d]].graph];
+        uint32_t head = uni(a.def_head[d]);
+        const uint32_t size = uni(a.def_size[d]);
+        const uint32_t *list = a.lists + (uint64_t)uni(a.def_slot[d]) * a.slot_n;
+        const GraphView G = graph_view(a.graphs[uni(a.tasks[uni(a.def_task[d])].graph)]);
         while (head < size) {
             uint32_t nb = min((uint32_t)kWave, size - head);
             uint32_t v = 0, e0 = 0, deg = 0, hv = 0, light = 0, cv = a.chunk;
@@ -567,7 +593,7 @@ __global__ __launch_bounds__(kWG) void k_plan(RRArgs a, uint32_t ndef, uint32_t 
 
 __global__ __launch_bounds__(kWG) void k_expand(RRArgs a, uint32_t parity) {
     __shared__ WaveLds lds[kWavesPerWG];
-    const uint32_t wv = threadIdx.x / kWave;
+    const uint32_t wv = uni(threadIdx.x / kWave);
     WaveLds &L = lds[wv];
     const uint64_t nitems = min(a.ctr[kItems + parity], (unsigned long long)kItemCap);
     if (blockIdx.x == 0 && threadIdx.x == 0) a.ctr[kItems + (parity ^ 1u)] = 0ull;   // next superstep's counter
@@ -577,17 +603,19 @@ __global__ __launch_bounds__(kWG) void k_expand(RRArgs a, uint32_t parity) {
     const uint64_t waves = (uint64_t)gridDim.x * kWavesPerWG;
     const uint32_t lane = lane_id();
     for (uint64_t it = (uint64_t)blockIdx.x * kWavesPerWG + wv; it < nitems; it += waves) {
-        const uint4 item = a.items[it];
+        const uint4 ld = a.items[it];
+        const uint4 item = make_uint4(uni(ld.x), uni(ld.y), uni(ld.z), uni(ld.w));
         if (item.x == kSkipItem) continue;
         const uint32_t d = item.x & 0x7FFFFFFFu;
         const bool heavy = (item.x >> 31) != 0u;
-        const uint32_t slot = a.def_slot[d];
-        const SetRef S = set_ref(a, a.def_task[d], a.def_idx[d]);
-        const GraphDesc &G = S.G;
+        const uint32_t slot = uni(a.def_slot[d]);
+        const SetRef S = set_ref(a, uni(a.def_task[d]), uni64(a.def_idx[d]));
+        const GraphView &G = S.G;
         uint32_t *list = a.lists + (uint64_t)slot * a.slot_n;
         uint32_t *bm = a.bitmaps + (uint64_t)slot * a.slot_words;
         uint32_t *size_p = &a.def_size[d];
-        const bool prefilter = __hip_atomic_load(size_p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= a.prefilter_min;
+        const bool prefilter =
+            uni(__hip_atomic_load(size_p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) >= a.prefilter_min;
         SharedAppend app{list, size_p, G.n};
         if (!heavy) {
             uint32_t v = 0, e0 = 0, deg = 0;
@@ -760,9 +788,10 @@ __global__ __launch_bounds__(kWG) void k_weight_sum(const uint32_t *__restrict__
 
 // ---- host side -------------------------------------------------------------
 struct LaunchShape {
-    uint32_t grid;        // phase A workgroups (one slot per wave)
+    uint32_t grid;        // phase A workgroups at full occupancy (one slot per wave)
     uint32_t slots;       // total slots (phase A waves + spare slots for deferred sets)
-    uint32_t grid_b;      // phase B workgroups
+    uint32_t grid_b;      // phase B workgroups at full occupancy
+    uint32_t cus;         // compute units
     uint32_t slot_n, slot_words;
     bool lds;
 };
@@ -772,6 +801,7 @@ struct LaunchShape {
 // kSlotBudget bytes) and the phase B grid.
 struct SlotLayout {
     uint64_t grid, waves, slots, grid_b, bytes;
+    uint32_t cus;
     bool lds;
 };
 
@@ -797,6 +827,7 @@ int slot_layout(uint32_t n_max, SlotLayout *out) {
     out->slots = slots;
     out->grid_b = (uint64_t)cus * (uint64_t)std::max(per_cu_b, 1);
     out->bytes = slots * per_slot;
+    out->cus = (uint32_t)cus;
     out->lds = lds;
     return HYPERIM_OK;
 }
@@ -820,6 +851,7 @@ int ensure_workspace(RRWorkspace &ws, uint32_t n_max, hipStream_t s, LaunchShape
         ws.waves = (uint32_t)waves;
         ws.slots = (uint32_t)slots;
         ws.grid_b = (uint32_t)L.grid_b;
+        ws.cus = L.cus;
         ws.slot_n = std::max<uint32_t>(n_max, 1);
         ws.slot_words = words;
         ws.lds = lds;
@@ -829,7 +861,9 @@ int ensure_workspace(RRWorkspace &ws, uint32_t n_max, hipStream_t s, LaunchShape
             HIM_HIP(hipMemsetAsync(ws.bitmaps.ptr, 0, sizeof(uint32_t) * (size_t)slots * words, s));
         }
         HIM_CHECK(ws.counters.reserve(sizeof(unsigned long long) * kNumCtr, s));
-        const size_t ndef = std::max<uint64_t>(slots - waves, 1);
+        // deferred-set arrays for as many sets as there are slots (phase A may
+        // run fewer waves than the occupancy allows, leaving more spare slots)
+        const size_t ndef = slots;
         HIM_CHECK(ws.def_idx.reserve(sizeof(uint64_t) * ndef, s));
         HIM_CHECK(ws.def_u32.reserve(sizeof(uint32_t) * 5 * ndef, s));
         HIM_CHECK(ws.items.reserve(sizeof(uint4) * (size_t)kItemCap, s));
@@ -837,6 +871,7 @@ int ensure_workspace(RRWorkspace &ws, uint32_t n_max, hipStream_t s, LaunchShape
     shape->grid = ws.grid;
     shape->slots = ws.slots;
     shape->grid_b = ws.grid_b;
+    shape->cus = ws.cus;
     shape->slot_n = ws.slot_n;
     shape->slot_words = ws.slot_words;
     shape->lds = lds;
@@ -906,10 +941,11 @@ int event_pair(RRWorkspace &ws) {
 // One launch group: phase A over `a`'s tasks, then phase B over the sets it
 // deferred.  Per-id outputs land at a.out_base + launch index.
 int run_launch(RRWorkspace &ws, RRStats &st, const hyperim_tuning &tune, RRArgs &a, const LaunchShape &shape,
-               uint32_t grid, bool trace, hipStream_t s) {
+               uint32_t grid, uint32_t grid_b, bool trace, hipStream_t s) {
     unsigned long long *ctr = a.ctr;
-    // fresh work counter, deferred list and spare-slot cursor
-    const unsigned long long first_free = (unsigned long long)shape.grid * kWavesPerWG;
+    // fresh work counter, deferred list and spare-slot cursor (spare slots
+    // follow the launched waves' own slots)
+    const unsigned long long first_free = (unsigned long long)grid * kWavesPerWG;
     HIM_HIP(hipMemsetAsync(ctr + kWork, 0, sizeof(unsigned long long), s));
     HIM_HIP(hipMemsetAsync(ctr + kDefCount, 0, sizeof(unsigned long long), s));
     HIM_HIP(hipMemcpyAsync(ctr + kFreeNext, &first_free, sizeof(unsigned long long), hipMemcpyHostToDevice, s));
@@ -949,7 +985,7 @@ int run_launch(RRWorkspace &ws, RRStats &st, const hyperim_tuning &tune, RRArgs 
             parity = (uint32_t)((steps + step) & 1u);
             hipLaunchKernelGGL(k_plan, dim3(plan_grid), dim3(kWG), 0, s, a, (uint32_t)ndef, parity);
             HIM_HIP(hipEventRecord(ws.events[2 + 2 * step], s));
-            hipLaunchKernelGGL(k_expand, dim3(shape.grid_b), dim3(kWG), 0, s, a, parity);
+            hipLaunchKernelGGL(k_expand, dim3(grid_b), dim3(kWG), 0, s, a, parity);
             HIM_HIP(hipEventRecord(ws.events[3 + 2 * step], s));
         }
         steps += batch;
@@ -1070,13 +1106,20 @@ int rr_generate_into(RRWorkspace &ws, RRStats &st, const std::vector<RRTask> &ta
     // bound) for a graph not seen yet -- and (form 0) so that the sets a group
     // defers fit the spare slots at the deferral rate seen so far (a set that
     // finds no spare slot stays with its wave).
-    const size_t ndef_cap = std::max<uint64_t>(shape.slots - (uint64_t)shape.grid * kWavesPerWG, 1);
+    // launch shapes: the occupancy limits, capped per compute unit by the tuning
+    auto capped = [&](uint32_t full, uint32_t per_cu) {
+        return per_cu ? std::max<uint32_t>(1, std::min<uint32_t>(full, shape.cus * per_cu)) : full;
+    };
+    const uint32_t grid_a = capped(shape.grid, tune.blocks_a);
+    const uint32_t grid_b = capped(shape.grid_b, tune.blocks_b);
+    const size_t ndef_cap = shape.slots;   // stride of the deferred-set arrays
+    const size_t spare = std::max<uint64_t>(shape.slots - (uint64_t)grid_a * kWavesPerWG, 1);
     const double stage_words = (double)stage_budget / 4.0;
     auto per_set = [](hyperim_graph g) { return g->rr_members >= 0.0 ? 1.3 * g->rr_members + 1.0 : (double)g->n; };
     double rate = 0.0;
     for (const RRTask &t : tasks) rate = std::max(rate, t.g->rr_defer >= 0.0 ? t.g->rr_defer : 0.5);
     const uint64_t def_chunk =
-        form == 0 ? std::max<uint64_t>((uint64_t)((double)ndef_cap / std::max(rate * 1.25, 1.0 / 64.0)), 4096)
+        form == 0 ? std::max<uint64_t>((uint64_t)((double)spare / std::max(rate * 1.25, 1.0 / 64.0)), 4096)
                   : ~0ull;
     struct Group {
         uint64_t lo, hi;
@@ -1207,7 +1250,7 @@ int rr_generate_into(RRWorkspace &ws, RRStats &st, const std::vector<RRTask> &ta
         a.ntasks = (uint32_t)gr.ndesc;
         a.count = gr.hi - gr.lo;
         const uint32_t grid =
-            form == 0 ? shape.grid : (uint32_t)std::min<uint64_t>(shape.grid, div_up(a.count, kWavesPerWG));
+            form == 0 ? grid_a : (uint32_t)std::min<uint64_t>(grid_a, div_up(a.count, kWavesPerWG));
         // stage sized from the prediction (a miss re-runs the group)
         const uint64_t predicted = (uint64_t)gr.predicted + 4 * a.count + (1u << 20);
         if (ws.stage.bytes < sizeof(uint32_t) * predicted)
@@ -1218,7 +1261,7 @@ int rr_generate_into(RRWorkspace &ws, RRStats &st, const std::vector<RRTask> &ta
             a.stage_cap = ws.stage.bytes / sizeof(uint32_t);
             HIM_HIP(hipMemsetAsync(ctr, 0, sizeof(unsigned long long) * kNumCtr, s));
             RRStats run{};
-            HIM_CHECK(run_launch(ws, run, tune, a, shape, grid, trace, s));
+            HIM_CHECK(run_launch(ws, run, tune, a, shape, grid, grid_b, trace, s));
             // time counts every attempt, work only the one that produced the output
             st.ms_bfs += run.ms_bfs;
             st.ms_light += run.ms_light;

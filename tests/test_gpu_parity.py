@@ -158,6 +158,28 @@ def test_greedy_and_coverage_bit_exact(hy, case):
             assert hy.coverage(g, pool, theta, s) == oracle.coverage(hg.n, off, mem, s, theta=theta)
 
 
+def test_greedy_graph_replays(hy):
+    """The k greedy rounds run as one captured graph, replayed with new
+    arguments: thetas of one grid shape reuse it, with eager work (coverage,
+    generation into another pool) between the replays; every replay must
+    equal the oracle."""
+    _flush("[gpu] greedy graph replays")
+    hg, model, p = CASES["small_p03"]()
+    g, o = _pair(hy, hg, model, p)
+    g.stratify()
+    pool = hy.Pool(g)
+    other = hy.Pool(g)
+    hy.generate_rr(g, 3, 1, 0, 0, 2048, pool)
+    off, mem, _ = pool.read()
+    k = min(12, hg.n)
+    for i, theta in enumerate((2048, 1900, 2048, 1800, 2048)):
+        s, gn = hy.greedy(g, pool, theta, k)
+        rs, rg = oracle.greedy(hg.n, off, mem, k, theta=theta)
+        assert np.array_equal(s, rs) and np.array_equal(gn, rg), (i, theta)
+        assert hy.coverage(g, pool, theta, s) == oracle.coverage(hg.n, off, mem, s, theta=theta)
+        hy.generate_rr(g, 5, 0, 1, 256 * i, 256 * (i + 1), other)
+
+
 def test_select_seeds_tiny_matches_oracle(hy):
     _flush("[gpu] select tiny")
     w = hypergen.workload("tiny")
