@@ -298,7 +298,7 @@ int hyperim_workspace_release(void);
  * setting produces the same bytes).  Zero fields keep their defaults.
  *   heavy:         a set whose next frontier batch holds a vertex with more
  *                  hyperedges than this moves to the grid-wide phase (1024);
- *   budget:        ... or once it has read this many incidences (16384);
+ *   budget:        ... or once it has read this many incidences (262144);
  *   chunk:         incidences per heavy-vertex work item (256);
  *   seg:           light incidences per frontier-segment work item (512,
  *                  raised to chunk if smaller);

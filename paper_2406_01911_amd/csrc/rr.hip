@@ -1098,14 +1098,6 @@ int rr_generate_into(RRWorkspace &ws, RRStats &st, const std::vector<RRTask> &ta
     LaunchShape shape;
     HIM_CHECK(ensure_workspace(ws, n_max, s, &shape));
 
-    // Launch groups: [index lo, index hi) of the tasks laid back to back, each
-    // with its task descriptors.  A group's sets are staged, then compacted
-    // into their pools before the next group runs, so the stage holds one
-    // group.  Groups are cut so that their predicted members fit the stage
-    // budget -- 1.3 x the graph's members per set seen so far, or n (an upper
-    // bound) for a graph not seen yet -- and (form 0) so that the sets a group
-    // defers fit the spare slots at the deferral rate seen so far (a set that
-    // finds no spare slot stays with its wave).
     // launch shapes: the occupancy limits, capped per compute unit by the tuning
     auto capped = [&](uint32_t full, uint32_t per_cu) {
         return per_cu ? std::max<uint32_t>(1, std::min<uint32_t>(full, shape.cus * per_cu)) : full;
@@ -1114,113 +1106,38 @@ int rr_generate_into(RRWorkspace &ws, RRStats &st, const std::vector<RRTask> &ta
     const uint32_t grid_b = capped(shape.grid_b, tune.blocks_b);
     const size_t ndef_cap = shape.slots;   // stride of the deferred-set arrays
     const size_t spare = std::max<uint64_t>(shape.slots - (uint64_t)grid_a * kWavesPerWG, 1);
+
+    // Launch groups are contiguous ranges of launch indices (the tasks laid
+    // back to back), planned one at a time with what earlier groups taught.
+    // A group's sets are staged, then compacted into their pools before the
+    // next group runs, so the stage holds one group.  A group takes indices
+    // while its predicted members fit the stage budget -- 1.3 x the graph's
+    // members per set seen so far, or n (an upper bound) for a graph not
+    // seen yet, whose first group then stops after kLearnIds of its sets --
+    // and (form 0) while the sets it defers fit the spare slots at the
+    // deferral rate seen so far (a set that finds no spare slot stays with
+    // its wave).  The plain form (1) also ends a group at every (task, ladder
+    // block, stratum) boundary.
+    constexpr uint64_t kLearnIds = 2048;
     const double stage_words = (double)stage_budget / 4.0;
     auto per_set = [](hyperim_graph g) { return g->rr_members >= 0.0 ? 1.3 * g->rr_members + 1.0 : (double)g->n; };
-    double rate = 0.0;
-    for (const RRTask &t : tasks) rate = std::max(rate, t.g->rr_defer >= 0.0 ? t.g->rr_defer : 0.5);
-    const uint64_t def_chunk =
-        form == 0 ? std::max<uint64_t>((uint64_t)((double)spare / std::max(rate * 1.25, 1.0 / 64.0)), 4096)
-                  : ~0ull;
-    struct Group {
-        uint64_t lo, hi;
-        size_t first_desc, ndesc;
-        double predicted;   // staged words
-    };
-    struct Slice {
-        size_t task;
-        uint64_t lo, hi;   // launch indices
-    };
-    std::vector<Group> groups;
-    std::vector<TaskDesc> tdesc;
-    std::vector<Slice> slices;   // per descriptor
-    auto add_group = [&](uint64_t lo, uint64_t hi) {
-        Group gr{lo, hi, tdesc.size(), 0, 0.0};
-        uint64_t tstart = 0;
-        for (size_t ti = 0; ti < tasks.size(); ++ti) {
-            const RRTask &t = tasks[ti];
-            const uint64_t tn = t.id_end - t.id_begin;
-            const uint64_t a0 = std::max(lo, tstart), a1 = std::min(hi, tstart + tn);
-            if (a0 < a1) {
-                tdesc.push_back(TaskDesc{a1 - lo, t.id_begin + (a0 - tstart), t.pool, gid[t.g], (uint32_t)t.seed,
-                                         t.instance});
-                slices.push_back(Slice{ti, a0, a1});
-                gr.predicted += (double)(a1 - a0) * per_set(t.g);
-            }
-            tstart += tn;
-        }
-        gr.ndesc = tdesc.size() - gr.first_desc;
-        groups.push_back(gr);
-    };
-    // cut the index range [lo, hi) of one task (per-set prediction m) into
-    // the running group, closing groups as they fill
-    uint64_t g_lo = 0, g_cnt = 0;
-    double g_acc = 0.0;
-    auto feed = [&](uint64_t lo, uint64_t hi, double m, uint64_t cap) {
-        uint64_t x = lo;
-        while (x < hi) {
-            const double room = stage_words - g_acc;
-            uint64_t take = std::min<uint64_t>(hi - x, room > 0.0 ? (uint64_t)(room / m) : 0);
-            take = std::min<uint64_t>(take, cap - g_cnt);
-            if (take == 0) {
-                if (g_cnt == 0) {
-                    take = 1;   // one set always fits
-                } else {
-                    add_group(g_lo, g_lo + g_cnt);
-                    g_lo += g_cnt;
-                    g_cnt = 0;
-                    g_acc = 0.0;
-                    continue;
-                }
-            }
-            g_acc += (double)take * m;
-            g_cnt += take;
-            x += take;
-        }
-    };
-    auto close = [&]() {
-        if (g_cnt) add_group(g_lo, g_lo + g_cnt);
-        g_lo += g_cnt;
-        g_cnt = 0;
-        g_acc = 0.0;
-    };
-    if (form == 0) {
-        uint64_t tstart = 0;
-        for (const RRTask &t : tasks) {
-            const uint64_t tn = t.id_end - t.id_begin;
-            feed(tstart, tstart + tn, per_set(t.g), def_chunk);
-            tstart += tn;
-        }
-        close();
-    } else {
-        // plain form: launches per (task, ladder block, stratum), a stratum
-        // range split further only by the stage budget
-        uint64_t tstart = 0;
-        for (const RRTask &t : tasks) {
+    std::vector<uint64_t> tstart(tasks.size() + 1, 0);
+    for (size_t i = 0; i < tasks.size(); ++i) tstart[i + 1] = tstart[i] + (tasks[i].id_end - tasks[i].id_begin);
+    // unit boundaries: task ends (form 0), (task, block, stratum) ends (form 1)
+    std::vector<uint64_t> unit_end;
+    for (size_t i = 0; i < tasks.size(); ++i) {
+        const RRTask &t = tasks[i];
+        if (form == 1) {
             std::vector<std::pair<uint64_t, uint64_t>> ranges;
             stratum_ranges(t.g, t.seed, t.instance, qlog, t.pool, t.id_begin, t.id_end, &ranges);
-            for (const auto &rg : ranges) {
-                g_lo = tstart + (rg.first - t.id_begin);
-                feed(g_lo, g_lo + (rg.second - rg.first), per_set(t.g), ~0ull);
-                close();
-            }
-            tstart += t.id_end - t.id_begin;
+            for (const auto &rg : ranges) unit_end.push_back(tstart[i] + (rg.second - t.id_begin));
+        } else {
+            unit_end.push_back(tstart[i + 1]);
         }
     }
-    uint64_t max_group = 0;
-    for (const Group &gr : groups) max_group = std::max(max_group, gr.hi - gr.lo);
-    HIM_CHECK(ws.stage_off.reserve(sizeof(uint64_t) * max_group, s, false));
-    HIM_CHECK(ws.sizes.reserve(sizeof(uint32_t) * max_group, s, false));
-    HIM_CHECK(ws.roots.reserve(sizeof(uint32_t) * max_group, s, false));
-    HIM_CHECK(ws.big_ids.reserve(sizeof(uint64_t) * max_group, s, false));
-    HIM_CHECK(ws.graph_desc.reserve(sizeof(GraphDesc) * gdesc.size(), s));
-    HIM_CHECK(ws.task_desc.reserve(sizeof(TaskDesc) * std::max<size_t>(tdesc.size(), 1), s));
-    HIM_HIP(hipMemcpyAsync(ws.graph_desc.ptr, gdesc.data(), sizeof(GraphDesc) * gdesc.size(), hipMemcpyHostToDevice, s));
-    HIM_HIP(hipMemcpyAsync(ws.task_desc.ptr, tdesc.data(), sizeof(TaskDesc) * tdesc.size(), hipMemcpyHostToDevice, s));
-    HIM_HIP(hipStreamSynchronize(s));   // host vectors are pageable and local
 
     unsigned long long *ctr = ws.counters.as<unsigned long long>();
     RRArgs a{};
-    a.graphs = ws.graph_desc.as<GraphDesc>();
     a.qlog = qlog;
     a.heavy = tune.heavy;
     a.budget = tune.budget;
@@ -1234,10 +1151,6 @@ int rr_generate_into(RRWorkspace &ws, RRStats &st, const std::vector<RRTask> &ta
     a.bitmaps = ws.bitmaps.as<uint32_t>();
     a.slot_total = shape.slots;
     a.out_base = 0;
-    a.stage_off = ws.stage_off.as<uint64_t>();
-    a.sizes = ws.sizes.as<uint32_t>();
-    a.roots = ws.roots.as<uint32_t>();
-    a.big_ids = ws.big_ids.as<uint64_t>();
     a.def_idx = ws.def_idx.as<uint64_t>();
     a.def_root = ws.def_u32.as<uint32_t>();
     a.def_slot = a.def_root + ndef_cap;
@@ -1245,16 +1158,77 @@ int rr_generate_into(RRWorkspace &ws, RRStats &st, const std::vector<RRTask> &ta
     a.def_size = a.def_head + ndef_cap;
     a.def_task = a.def_size + ndef_cap;
     a.items = ws.items.as<uint4>();
-    for (const Group &gr : groups) {
-        a.tasks = ws.task_desc.as<TaskDesc>() + gr.first_desc;
-        a.ntasks = (uint32_t)gr.ndesc;
-        a.count = gr.hi - gr.lo;
-        const uint32_t grid =
-            form == 0 ? grid_a : (uint32_t)std::min<uint64_t>(grid_a, div_up(a.count, kWavesPerWG));
+    HIM_CHECK(ws.graph_desc.reserve(sizeof(GraphDesc) * gdesc.size(), s));
+    HIM_CHECK(ws.task_desc.reserve(sizeof(TaskDesc) * tasks.size(), s));
+    HIM_HIP(hipMemcpyAsync(ws.graph_desc.ptr, gdesc.data(), sizeof(GraphDesc) * gdesc.size(), hipMemcpyHostToDevice, s));
+    a.graphs = ws.graph_desc.as<GraphDesc>();
+
+    struct Slice {
+        size_t task;
+        uint64_t lo, hi;   // launch indices
+    };
+    size_t unit = 0;
+    for (uint64_t pos = 0; pos < count;) {
+        // ---- plan the next group ---------------------------------------
+        double rate = 0.0;
+        for (const RRTask &t : tasks) rate = std::max(rate, t.g->rr_defer >= 0.0 ? t.g->rr_defer : 0.5);
+        const uint64_t def_chunk =
+            form == 0 ? std::max<uint64_t>((uint64_t)((double)spare / std::max(rate * 1.25, 1.0 / 64.0)), 4096)
+                      : ~0ull;
+        const uint64_t lo = pos;
+        double acc = 0.0;
+        size_t ti = std::upper_bound(tstart.begin(), tstart.end(), pos) - tstart.begin() - 1;
+        while (unit_end[unit] <= pos) ++unit;
+        for (;;) {
+            const RRTask &t = tasks[ti];
+            const double m = per_set(t.g);
+            const bool learn = t.g->rr_members < 0.0;
+            uint64_t limit = (form == 1 ? unit_end[unit] : tstart[ti + 1]) - pos;
+            if (learn) limit = std::min(limit, kLearnIds);
+            const double room = stage_words - acc;
+            uint64_t take = std::min<uint64_t>(limit, room > 0.0 ? (uint64_t)(room / m) : 0);
+            take = std::min<uint64_t>(take, def_chunk - (pos - lo));
+            if (take == 0 && pos == lo) take = 1;   // one set always fits
+            acc += (double)take * m;
+            pos += take;
+            if (take < limit || learn || pos == count || form == 1 || pos - lo >= def_chunk) break;
+            ++ti;   // form 0: the group continues with the next task
+        }
+        const uint64_t hi = pos;
+        // descriptors of the group's task slices
+        std::vector<TaskDesc> tdesc;
+        std::vector<Slice> slices;
+        for (size_t i = 0; i < tasks.size(); ++i) {
+            const uint64_t a0 = std::max(lo, tstart[i]), a1 = std::min(hi, tstart[i + 1]);
+            if (a0 >= a1) continue;
+            const RRTask &t = tasks[i];
+            tdesc.push_back(TaskDesc{a1 - lo, t.id_begin + (a0 - tstart[i]), t.pool, gid[t.g], (uint32_t)t.seed,
+                                     t.instance});
+            slices.push_back(Slice{i, a0, a1});
+        }
+        const uint64_t n_ids = hi - lo;
+        HIM_CHECK(ws.stage_off.reserve(sizeof(uint64_t) * n_ids, s, false));
+        HIM_CHECK(ws.sizes.reserve(sizeof(uint32_t) * n_ids, s, false));
+        HIM_CHECK(ws.roots.reserve(sizeof(uint32_t) * n_ids, s, false));
+        HIM_CHECK(ws.big_ids.reserve(sizeof(uint64_t) * n_ids, s, false));
         // stage sized from the prediction (a miss re-runs the group)
-        const uint64_t predicted = (uint64_t)gr.predicted + 4 * a.count + (1u << 20);
+        const uint64_t predicted = (uint64_t)acc + 4 * n_ids + (1u << 20);
         if (ws.stage.bytes < sizeof(uint32_t) * predicted)
             HIM_CHECK(ws.stage.reserve(sizeof(uint32_t) * predicted, s, false));
+        HIM_HIP(hipMemcpyAsync(ws.task_desc.ptr, tdesc.data(), sizeof(TaskDesc) * tdesc.size(), hipMemcpyHostToDevice,
+                               s));
+        HIM_HIP(hipStreamSynchronize(s));   // host vectors are pageable and local
+        a.tasks = ws.task_desc.as<TaskDesc>();
+        a.ntasks = (uint32_t)tdesc.size();
+        a.count = n_ids;
+        a.stage_off = ws.stage_off.as<uint64_t>();
+        a.sizes = ws.sizes.as<uint32_t>();
+        a.roots = ws.roots.as<uint32_t>();
+        a.big_ids = ws.big_ids.as<uint64_t>();
+        const uint32_t grid =
+            form == 0 ? grid_a : (uint32_t)std::min<uint64_t>(grid_a, div_up(a.count, kWavesPerWG));
+
+        // ---- run it ----------------------------------------------------
         bool staged = false;
         for (int attempt = 0; attempt < 2 && !staged; ++attempt) {
             a.stage = ws.stage.as<uint32_t>();
@@ -1274,8 +1248,7 @@ int rr_generate_into(RRWorkspace &ws, RRStats &st, const std::vector<RRTask> &ta
             HIM_CHECK(read_ctr(s, ctr, kBump, &bump));
             HIM_CHECK(read_ctr(s, ctr, kBytesA, &ba));
             HIM_CHECK(read_ctr(s, ctr, kBytesB, &bb));
-            for (size_t d = gr.first_desc; d < gr.first_desc + gr.ndesc; ++d)
-                tasks[slices[d].task].g->rr_defer = (double)run.deferred / (double)a.count;
+            for (const Slice &sl : slices) tasks[sl.task].g->rr_defer = (double)run.deferred / (double)a.count;
             if (bump <= a.stage_cap) {
                 st.deferred += run.deferred;
                 st.bytes_light += ba;
@@ -1289,12 +1262,13 @@ int rr_generate_into(RRWorkspace &ws, RRStats &st, const std::vector<RRTask> &ta
             set_error_detail("RR stage overflow after resize");
             return HYPERIM_ENOMEM;
         }
-        for (size_t d = gr.first_desc; d < gr.first_desc + gr.ndesc; ++d) {
-            const Slice &sl = slices[d];
+
+        // ---- compact it ------------------------------------------------
+        for (const Slice &sl : slices) {
             if (pool_status[sl.task] != HYPERIM_OK) continue;
             hyperim_pool p = pools[sl.task];
             const uint64_t before = p->total;
-            const int rc = compact_into(ws, p, sl.lo - gr.lo, sl.hi - sl.lo, max_entries, s);
+            const int rc = compact_into(ws, p, sl.lo - lo, sl.hi - sl.lo, max_entries, s);
             if (rc == HYPERIM_ECAPACITY) {
                 pool_status[sl.task] = rc;   // this pool is full; the others go on
             } else if (rc != HYPERIM_OK) {
