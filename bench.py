@@ -56,19 +56,26 @@ def parse():
     return ap.parse_args()
 
 
+def rr_device_sha256() -> str:
+    """sha256 of rr.hip's device code: the text before its host-side marker."""
+    src = os.path.join(ROOT, "paper_2406_01911_amd", "csrc", "rr.hip")
+    with open(src) as f:
+        text = f.read()
+    return hashlib.sha256(text.split("// ---- host side", 1)[0].encode()).hexdigest()
+
+
 def expand_traffic(workload: str):
     """HBM bytes per k_expand launch from the committed hardware-counter
     summary of this workload (FETCH_SIZE + WRITE_SIZE per dispatch, scaled by
     the same counters on a copy of known size); None when there is none or
-    when the RR-generation source has changed since the counters were taken."""
+    when the device code of RR generation (rr.hip up to its host-side part)
+    has changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", f"k_expand_{workload}_counters.json")
-    src = os.path.join(ROOT, "paper_2406_01911_amd", "csrc", "rr.hip")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
-    with open(src, "rb") as f:
-        sha = hashlib.sha256(f.read()).hexdigest()
+    sha = rr_device_sha256()
     if rec.get("rr_hip_sha256") != sha:
         return None
     return rec["traffic_bytes_per_launch"]

@@ -1183,15 +1183,15 @@ int rr_generate_into(RRWorkspace &ws, RRStats &st, const std::vector<RRTask> &ta
             const RRTask &t = tasks[ti];
             const double m = per_set(t.g);
             const bool learn = t.g->rr_members < 0.0;
-            uint64_t limit = (form == 1 ? unit_end[unit] : tstart[ti + 1]) - pos;
-            if (learn) limit = std::min(limit, kLearnIds);
+            const uint64_t rest = (form == 1 ? unit_end[unit] : tstart[ti + 1]) - pos;
+            const uint64_t limit = learn ? std::min(rest, kLearnIds) : rest;
             const double room = stage_words - acc;
             uint64_t take = std::min<uint64_t>(limit, room > 0.0 ? (uint64_t)(room / m) : 0);
             take = std::min<uint64_t>(take, def_chunk - (pos - lo));
             if (take == 0 && pos == lo) take = 1;   // one set always fits
             acc += (double)take * m;
             pos += take;
-            if (take < limit || learn || pos == count || form == 1 || pos - lo >= def_chunk) break;
+            if (take < rest || pos == count || form == 1 || pos - lo >= def_chunk) break;
             ++ti;   // form 0: the group continues with the next task
         }
         const uint64_t hi = pos;
