@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <vector>
 
+#include "block_table.h"
 #include "dev_common.h"
 #include "internal.h"
 
@@ -25,16 +26,42 @@ __global__ void k_check_offsets(const uint32_t *__restrict__ he_off, uint32_t m,
     if (e < m && he_off[e + 1] < he_off[e]) atomicOr(flag, (uint32_t)kBadOffsets);
 }
 
-__global__ void k_count(const uint32_t *__restrict__ he_mem, uint64_t nnz, uint32_t n,
-                        uint32_t *__restrict__ cnt, uint32_t *flag) {
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nnz;
-         i += (uint64_t)gridDim.x * blockDim.x) {
-        uint32_t v = he_mem[i];
-        if (v >= n) {
-            atomicOr(flag, (uint32_t)kBadId);
-            continue;
+// Incidences per vertex.  Each workgroup takes chunks of kChunk consecutive
+// incidences and adds per-vertex totals to global memory once per chunk.
+constexpr uint32_t kChunkPer = 8;                 // incidences per thread per chunk
+constexpr uint32_t kChunk = kBlock * kChunkPer;
+constexpr uint32_t kTableSlots = 4096;
+
+__global__ __launch_bounds__(kBlock) void k_count(const uint32_t *__restrict__ he_mem, uint64_t nnz, uint32_t n,
+                                                   uint32_t *__restrict__ cnt, uint32_t *flag) {
+    __shared__ BlockTable<kTableSlots> tab;
+    __shared__ uint32_t tval[kTableSlots];
+    tab.clear_keys();
+    for (uint32_t s = threadIdx.x; s < kTableSlots; s += kBlock) tval[s] = 0;
+    __syncthreads();
+    for (uint64_t base = (uint64_t)blockIdx.x * kChunk; base < nnz; base += (uint64_t)gridDim.x * kChunk) {
+        for (uint32_t r = 0; r < kChunkPer; ++r) {
+            const uint64_t i = base + r * kBlock + threadIdx.x;
+            if (i >= nnz) break;
+            const uint32_t v = he_mem[i];
+            if (v >= n) {
+                atomicOr(flag, (uint32_t)kBadId);
+                continue;
+            }
+            const uint32_t sl = tab.slot(v);
+            if (sl != kTableEmpty) atomicAdd(&tval[sl], 1u);
+            else atomicAdd(&cnt[v], 1u);
         }
-        atomicAdd(&cnt[v], 1u);
+        __syncthreads();
+        for (uint32_t sl = threadIdx.x; sl < kTableSlots; sl += kBlock) {
+            const uint32_t v = tab.key[sl];
+            if (v != kTableEmpty) {
+                atomicAdd(&cnt[v], tval[sl]);
+                tab.key[sl] = kTableEmpty;
+                tval[sl] = 0;
+            }
+        }
+        __syncthreads();
     }
 }
 
@@ -45,23 +72,73 @@ __global__ void k_u64_to_u32(const uint64_t *__restrict__ in, uint32_t *__restri
 }
 
 // Scatter every incidence (he, position) into its vertex's segment (order
-// inside a segment fixed afterwards by sorting) and accumulate c(v).
-__global__ void k_fill(const uint32_t *__restrict__ he_off, const uint32_t *__restrict__ he_mem, uint32_t m,
-                       uint64_t nnz, const uint32_t *__restrict__ v_off, uint32_t *__restrict__ cursor,
-                       uint32_t *__restrict__ v_he, unsigned long long *__restrict__ c) {
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nnz;
-         i += (uint64_t)gridDim.x * blockDim.x) {
-        // owner hyperedge: largest e with he_off[e] <= i (skipping empty ones)
-        uint32_t lo = 0, hi = m;  // he_off[lo] <= i < he_off[hi]
-        while (hi - lo > 1) {
-            uint32_t mid = lo + (hi - lo) / 2;
-            if (he_off[mid] <= (uint32_t)i) lo = mid; else hi = mid;
+// inside a segment fixed afterwards by sorting) and accumulate c(v).  Per
+// chunk, each workgroup ranks its incidences of one vertex in LDS, reserves
+// the vertex's places with one global atomic and adds its c(v) share once.
+constexpr uint32_t kFillPer = 4;
+constexpr uint32_t kFillChunk = kBlock * kFillPer;
+constexpr uint32_t kFillSlots = 2048;
+
+__global__ __launch_bounds__(kBlock) void k_fill(const uint32_t *__restrict__ he_off,
+                                                  const uint32_t *__restrict__ he_mem, uint32_t m, uint64_t nnz,
+                                                  const uint32_t *__restrict__ v_off, uint32_t *__restrict__ cursor,
+                                                  uint32_t *__restrict__ v_he, unsigned long long *__restrict__ c) {
+    __shared__ BlockTable<kFillSlots> tab;
+    __shared__ uint32_t tcnt[kFillSlots], tbase[kFillSlots];
+    __shared__ unsigned long long tsum[kFillSlots];
+    tab.clear_keys();
+    for (uint32_t s = threadIdx.x; s < kFillSlots; s += kBlock) {
+        tcnt[s] = 0;
+        tsum[s] = 0;
+    }
+    __syncthreads();
+    for (uint64_t base = (uint64_t)blockIdx.x * kFillChunk; base < nnz; base += (uint64_t)gridDim.x * kFillChunk) {
+        uint32_t ev[kFillPer], vv[kFillPer], sl[kFillPer], rk[kFillPer];
+#pragma unroll
+        for (uint32_t r = 0; r < kFillPer; ++r) {
+            sl[r] = kTableEmpty;
+            vv[r] = kTableEmpty;
+            const uint64_t i = base + r * kBlock + threadIdx.x;
+            if (i >= nnz) continue;
+            // owner hyperedge: largest e with he_off[e] <= i (skipping empty ones)
+            uint32_t lo = 0, hi = m;  // he_off[lo] <= i < he_off[hi]
+            while (hi - lo > 1) {
+                const uint32_t mid = lo + (hi - lo) / 2;
+                if (he_off[mid] <= (uint32_t)i) lo = mid; else hi = mid;
+            }
+            const uint32_t e = lo, v = he_mem[i];
+            const unsigned long long cs = he_off[e + 1] - he_off[e] - 1u;
+            ev[r] = e;
+            vv[r] = v;
+            sl[r] = tab.slot(v);
+            if (sl[r] != kTableEmpty) {
+                rk[r] = atomicAdd(&tcnt[sl[r]], 1u);
+                atomicAdd(&tsum[sl[r]], cs);
+            } else {
+                const uint32_t pos = atomicAdd(&cursor[v], 1u);
+                v_he[v_off[v] + pos] = e;
+                atomicAdd(&c[v], cs);
+            }
         }
-        uint32_t e = lo;
-        uint32_t v = he_mem[i];
-        uint32_t slot = atomicAdd(&cursor[v], 1u);
-        v_he[v_off[v] + slot] = e;
-        atomicAdd(&c[v], (unsigned long long)(he_off[e + 1] - he_off[e] - 1u));
+        __syncthreads();
+        for (uint32_t s = threadIdx.x; s < kFillSlots; s += kBlock) {
+            const uint32_t v = tab.key[s];
+            if (v != kTableEmpty) {
+                tbase[s] = atomicAdd(&cursor[v], tcnt[s]);
+                atomicAdd(&c[v], tsum[s]);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (uint32_t r = 0; r < kFillPer; ++r)
+            if (sl[r] != kTableEmpty) v_he[v_off[vv[r]] + tbase[sl[r]] + rk[r]] = ev[r];
+        __syncthreads();
+        for (uint32_t s = threadIdx.x; s < kFillSlots; s += kBlock) {
+            tab.key[s] = kTableEmpty;
+            tcnt[s] = 0;
+            tsum[s] = 0;
+        }
+        __syncthreads();
     }
 }
 
@@ -232,7 +309,7 @@ int graph_build_device(hyperim_graph g, hipStream_t s) {
                        g->he_off.as<uint32_t>(), m, flag);
     HIM_CHECK(cnt_b.reserve(sizeof(uint32_t) * ((size_t)n + 1), s));
     HIM_HIP(hipMemsetAsync(cnt_b.ptr, 0, sizeof(uint32_t) * ((size_t)n + 1), s));
-    hipLaunchKernelGGL(k_count, dim3(grid_for(nnz)), dim3(kBlock), 0, s, g->he_mem.as<uint32_t>(), nnz, n,
+    hipLaunchKernelGGL(k_count, dim3(grid_for(nnz, kChunk, 4096)), dim3(kBlock), 0, s, g->he_mem.as<uint32_t>(), nnz, n,
                        cnt_b.as<uint32_t>(), flag);
     uint32_t hflag = 0;
     HIM_HIP(hipMemcpyAsync(&hflag, flag, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
@@ -254,7 +331,7 @@ int graph_build_device(hyperim_graph g, hipStream_t s) {
     HIM_HIP(hipMemsetAsync(g->c.ptr, 0, sizeof(uint64_t) * std::max<uint32_t>(n, 1), s));
     HIM_HIP(hipMemsetAsync(cnt_b.ptr, 0, sizeof(uint32_t) * ((size_t)n + 1), s));
     if (nnz)
-        hipLaunchKernelGGL(k_fill, dim3(grid_for(nnz)), dim3(kBlock), 0, s, g->he_off.as<uint32_t>(),
+        hipLaunchKernelGGL(k_fill, dim3(grid_for(nnz, kFillChunk, 4096)), dim3(kBlock), 0, s, g->he_off.as<uint32_t>(),
                            g->he_mem.as<uint32_t>(), m, nnz, g->v_off.as<uint32_t>(), cnt_b.as<uint32_t>(),
                            g->v_he.as<uint32_t>(), g->c.as<unsigned long long>());
 

@@ -205,11 +205,22 @@ __device__ __forceinline__ uint32_t bm_load(uint32_t *bm, uint32_t w) {
 struct LocalAppend {
     uint32_t *list;
     uint32_t size, n;
-    __device__ __forceinline__ void push(bool fresh, uint32_t u) {
-        const uint64_t bal = __ballot(fresh);
-        const uint32_t at = size + lane_rank(bal);
-        if (fresh && at < n) list[at] = u;   // at < n always holds: one bit per vertex
-        size = min(size + (uint32_t)__popcll(bal), n);
+    // Append the members u[t] of the set bits t of `mask` (this lane's newly
+    // reached members), all lanes at once: one wave scan gives each lane its
+    // place.  Every lane of the wave calls it.
+    __device__ __forceinline__ void push8(uint32_t mask, const uint32_t (&u)[8]) {
+        const uint32_t cnt = (uint32_t)__popc(mask);
+        const uint32_t incl = wave_incl_scan(cnt);
+        const uint32_t total = uni(wave_bcast(incl, kWave - 1));
+        if (total == 0) return;
+        uint32_t at = size + incl - cnt;
+#pragma unroll
+        for (uint32_t t = 0; t < 8; ++t)
+            if ((mask >> t) & 1u) {
+                if (at < n) list[at] = u[t];   // at < n always holds: one bit per vertex
+                ++at;
+            }
+        size = min(size + total, n);
     }
 };
 
@@ -218,15 +229,20 @@ struct SharedAppend {
     uint32_t *list;
     uint32_t *size;
     uint32_t n;
-    __device__ __forceinline__ void push(bool fresh, uint32_t u) {
-        const uint64_t bal = __ballot(fresh);
-        if (bal == 0) return;
-        const uint32_t first = (uint32_t)__ffsll((unsigned long long)bal) - 1u;
+    __device__ __forceinline__ void push8(uint32_t mask, const uint32_t (&u)[8]) {
+        const uint32_t cnt = (uint32_t)__popc(mask);
+        const uint32_t incl = wave_incl_scan(cnt);
+        const uint32_t total = uni(wave_bcast(incl, kWave - 1));
+        if (total == 0) return;
         uint32_t base = 0;
-        if (lane_id() == first) base = atomicAdd(size, (uint32_t)__popcll(bal));
-        base = wave_bcast(base, (int)first);
-        const uint32_t at = base + lane_rank(bal);
-        if (fresh && at < n) list[at] = u;
+        if (lane_id() == kWave - 1) base = atomicAdd(size, total);
+        uint32_t at = uni(wave_bcast(base, kWave - 1)) + incl - cnt;
+#pragma unroll
+        for (uint32_t t = 0; t < 8; ++t)
+            if ((mask >> t) & 1u) {
+                if (at < n) list[at] = u[t];
+                ++at;
+            }
     }
 };
 
@@ -271,15 +287,15 @@ __device__ __forceinline__ void test_octet(const GraphView &G, uint64_t j, uint3
     }
     // with small probabilities most octets have no live channel at all
     if (__ballot(any_live) == 0) return;
+    uint32_t fresh = 0;
 #pragma unroll
     for (uint32_t t = 0; t < 8; ++t) {
-        bool fresh = false;
         if (live[t]) {
             const uint32_t bit = 1u << (u[t] & 31);
-            fresh = (atomicOr(&bm[u[t] >> 5], bit) & bit) == 0u;
+            if ((atomicOr(&bm[u[t] >> 5], bit) & bit) == 0u) fresh |= 1u << t;
         }
-        app.push(fresh, u[t]);
     }
+    app.push8(fresh, u);
 }
 
 // Levels 2 and 3 of a frontier expansion.  Each lane brings one vertex v with

@@ -12,6 +12,7 @@
 #include <cmath>
 #include <vector>
 
+#include "block_table.h"
 #include "dev_common.h"
 #include "internal.h"
 
@@ -87,26 +88,89 @@ __global__ void k_pairs(const uint32_t *__restrict__ he_off, const uint32_t *__r
     }
 }
 
-__global__ void k_layers(const unsigned long long *__restrict__ keys, const uint32_t *__restrict__ vals,
-                         uint64_t cap, unsigned long long *keys2, uint64_t mask2, uint32_t *__restrict__ deg,
-                         uint32_t *__restrict__ wmax, uint32_t *__restrict__ l) {
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cap; i += (uint64_t)gridDim.x * blockDim.x) {
-        unsigned long long k = keys[i];
-        if (k == kEmpty) continue;
-        const uint32_t v = (uint32_t)(k >> 32), w = vals[i];
-        atomicAdd(&deg[v], 1u);
-        atomicMax(&wmax[v], w);
-        if (table_insert(keys2, mask2, ((uint64_t)v << 32) | w)) atomicAdd(&l[v], 1u);
+// Per table entry (v, u) with weight w: deg(v) += 1, wmax(v) = max, and l(v)
+// += 1 when (v, w) is a new layer weight.  Entries of one vertex are spread
+// over the table, so each workgroup aggregates per-vertex updates of a chunk
+// in LDS and applies them once (hubs have ~1e5 entries).
+constexpr uint32_t kAggPer = 4;
+constexpr uint32_t kAggChunk = kBlock * kAggPer;
+constexpr uint32_t kAggSlots = 2048;
+
+__global__ __launch_bounds__(kBlock) void k_layers(const unsigned long long *__restrict__ keys,
+                                                    const uint32_t *__restrict__ vals, uint64_t cap,
+                                                    unsigned long long *keys2, uint64_t mask2,
+                                                    uint32_t *__restrict__ deg, uint32_t *__restrict__ wmax,
+                                                    uint32_t *__restrict__ l) {
+    __shared__ BlockTable<kAggSlots> tab;
+    __shared__ uint32_t tdeg[kAggSlots], tmax[kAggSlots], tl[kAggSlots];
+    tab.clear_keys();
+    for (uint32_t s = threadIdx.x; s < kAggSlots; s += kBlock) tdeg[s] = tmax[s] = tl[s] = 0;
+    __syncthreads();
+    for (uint64_t base = (uint64_t)blockIdx.x * kAggChunk; base < cap; base += (uint64_t)gridDim.x * kAggChunk) {
+        for (uint32_t r = 0; r < kAggPer; ++r) {
+            const uint64_t i = base + r * kBlock + threadIdx.x;
+            if (i >= cap) break;
+            const unsigned long long k = keys[i];
+            if (k == kEmpty) continue;
+            const uint32_t v = (uint32_t)(k >> 32), w = vals[i];
+            const bool fresh = table_insert(keys2, mask2, ((uint64_t)v << 32) | w);
+            const uint32_t sl = tab.slot(v);
+            if (sl != kTableEmpty) {
+                atomicAdd(&tdeg[sl], 1u);
+                atomicMax(&tmax[sl], w);
+                if (fresh) atomicAdd(&tl[sl], 1u);
+            } else {
+                atomicAdd(&deg[v], 1u);
+                atomicMax(&wmax[v], w);
+                if (fresh) atomicAdd(&l[v], 1u);
+            }
+        }
+        __syncthreads();
+        for (uint32_t s = threadIdx.x; s < kAggSlots; s += kBlock) {
+            const uint32_t v = tab.key[s];
+            if (v != kTableEmpty) {
+                atomicAdd(&deg[v], tdeg[s]);
+                atomicMax(&wmax[v], tmax[s]);
+                if (tl[s]) atomicAdd(&l[v], tl[s]);
+                tab.key[s] = kTableEmpty;
+                tdeg[s] = tmax[s] = tl[s] = 0;
+            }
+        }
+        __syncthreads();
     }
 }
 
-__global__ void k_top(const unsigned long long *__restrict__ keys, const uint32_t *__restrict__ vals, uint64_t cap,
-                      const uint32_t *__restrict__ wmax, uint32_t *__restrict__ top) {
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cap; i += (uint64_t)gridDim.x * blockDim.x) {
-        unsigned long long k = keys[i];
-        if (k == kEmpty) continue;
-        const uint32_t v = (uint32_t)(k >> 32);
-        if (vals[i] == wmax[v]) atomicAdd(&top[v], 1u);
+// top(v) = entries of v with the largest weight, aggregated the same way.
+__global__ __launch_bounds__(kBlock) void k_top(const unsigned long long *__restrict__ keys,
+                                                 const uint32_t *__restrict__ vals, uint64_t cap,
+                                                 const uint32_t *__restrict__ wmax, uint32_t *__restrict__ top) {
+    __shared__ BlockTable<kAggSlots> tab;
+    __shared__ uint32_t tcnt[kAggSlots];
+    tab.clear_keys();
+    for (uint32_t s = threadIdx.x; s < kAggSlots; s += kBlock) tcnt[s] = 0;
+    __syncthreads();
+    for (uint64_t base = (uint64_t)blockIdx.x * kAggChunk; base < cap; base += (uint64_t)gridDim.x * kAggChunk) {
+        for (uint32_t r = 0; r < kAggPer; ++r) {
+            const uint64_t i = base + r * kBlock + threadIdx.x;
+            if (i >= cap) break;
+            const unsigned long long k = keys[i];
+            if (k == kEmpty) continue;
+            const uint32_t v = (uint32_t)(k >> 32);
+            if (vals[i] != wmax[v]) continue;
+            const uint32_t sl = tab.slot(v);
+            if (sl != kTableEmpty) atomicAdd(&tcnt[sl], 1u);
+            else atomicAdd(&top[v], 1u);
+        }
+        __syncthreads();
+        for (uint32_t s = threadIdx.x; s < kAggSlots; s += kBlock) {
+            const uint32_t v = tab.key[s];
+            if (v != kTableEmpty) {
+                atomicAdd(&top[v], tcnt[s]);
+                tab.key[s] = kTableEmpty;
+                tcnt[s] = 0;
+            }
+        }
+        __syncthreads();
     }
 }
 
@@ -158,10 +222,23 @@ __global__ __launch_bounds__(kBlock) void k_strata(uint32_t n, const uint32_t *_
     }
 }
 
-// Histogram of the layer counts (Theorem 2's theta(l*) is a sum over it).
-__global__ void k_lhist(uint32_t n, const uint32_t *__restrict__ l, unsigned long long *__restrict__ hist) {
-    const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
-    if (v < n) atomicAdd(&hist[l[v]], 1ull);
+// Histogram of the layer counts (Theorem 2's theta(l*) is a sum over it):
+// counts below kLhistBins in LDS per workgroup, flushed once.
+constexpr uint32_t kLhistBins = 1024;
+
+__global__ __launch_bounds__(kBlock) void k_lhist(uint32_t n, const uint32_t *__restrict__ l,
+                                                   unsigned long long *__restrict__ hist) {
+    __shared__ uint32_t bins[kLhistBins];
+    for (uint32_t b = threadIdx.x; b < kLhistBins; b += kBlock) bins[b] = 0;
+    __syncthreads();
+    for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+        const uint32_t x = l[v];
+        if (x < kLhistBins) atomicAdd(&bins[x], 1u);
+        else atomicAdd(&hist[x], 1ull);
+    }
+    __syncthreads();
+    for (uint32_t b = threadIdx.x; b < kLhistBins; b += kBlock)
+        if (bins[b]) atomicAdd(&hist[b], (unsigned long long)bins[b]);
 }
 
 // Stable placement of each vertex at its (stratum, id) rank.
@@ -246,10 +323,10 @@ int stratify_device(hyperim_graph g, hipStream_t s) {
                                g->he_off.as<uint32_t>(), g->he_mem.as<uint32_t>(), g->v_off.as<uint32_t>(),
                                g->v_he.as<uint32_t>(), v0, v1, k1.as<unsigned long long>(), vals.as<uint32_t>(),
                                c - 1);
-            hipLaunchKernelGGL(k_layers, dim3(grid_for(c)), dim3(kBlock), 0, s, k1.as<unsigned long long>(),
+            hipLaunchKernelGGL(k_layers, dim3(std::min<uint32_t>(grid_for(div_up(c, kAggPer)), 4096)), dim3(kBlock), 0, s, k1.as<unsigned long long>(),
                                vals.as<uint32_t>(), c, k2.as<unsigned long long>(), c - 1, g->deg.as<uint32_t>(),
                                wmax_b.as<uint32_t>(), g->l.as<uint32_t>());
-            hipLaunchKernelGGL(k_top, dim3(grid_for(c)), dim3(kBlock), 0, s, k1.as<unsigned long long>(),
+            hipLaunchKernelGGL(k_top, dim3(std::min<uint32_t>(grid_for(div_up(c, kAggPer)), 4096)), dim3(kBlock), 0, s, k1.as<unsigned long long>(),
                                vals.as<uint32_t>(), c, wmax_b.as<uint32_t>(), g->top.as<uint32_t>());
         }
     }
@@ -274,7 +351,7 @@ int stratify_device(hyperim_graph g, hipStream_t s) {
     HIM_CHECK(hist_b.reserve(sizeof(unsigned long long) * ((size_t)lmax + 1), s));
     HIM_HIP(hipMemsetAsync(hist_b.ptr, 0, sizeof(unsigned long long) * ((size_t)lmax + 1), s));
     if (n)
-        hipLaunchKernelGGL(k_lhist, dim3(tiles), dim3(kBlock), 0, s, n, g->l.as<uint32_t>(),
+        hipLaunchKernelGGL(k_lhist, dim3(std::min<uint32_t>(tiles, 64)), dim3(kBlock), 0, s, n, g->l.as<uint32_t>(),
                            hist_b.as<unsigned long long>());
     HIM_CHECK(scan_u32_to_u64(counts_b.as<uint32_t>(), base_b.as<uint64_t>(), (uint64_t)kNStrata * tiles, 0, tmp_b,
                               s));
