@@ -312,11 +312,15 @@ int hyperim_workspace_release(void);
  *   blocks_a:      per-set phase workgroups per compute unit, at most the
  *                  occupancy limit (4; 0 = the occupancy limit);
  *   blocks_b:      grid-wide expansion workgroups per compute unit (6; 0 =
- *                  the occupancy limit). */
+ *                  the occupancy limit);
+ *   ms_min:        graphs whose RR sets hold at least this many members on
+ *                  average (learned from earlier launches) grow their sets
+ *                  in bundles of 64, bit-parallel over the sets: each vertex
+ *                  expansion serves every set that reached it in the same
+ *                  level (4096; 0xFFFFFFFF = never). */
 typedef struct {
     uint32_t heavy, budget, chunk, seg, prefilter_min, steps_per_sync;
-    uint32_t stage_mib, blocks_a, blocks_b;
-    uint32_t reserved;
+    uint32_t stage_mib, blocks_a, blocks_b, ms_min;
 } hyperim_tuning;
 
 /* Set / read the execution parameters of graph g (host-side values).  A

@@ -58,7 +58,7 @@ class _Result(C.Structure):
 class _Tuning(C.Structure):
     _fields_ = [("heavy", C.c_uint32), ("budget", C.c_uint32), ("chunk", C.c_uint32), ("seg", C.c_uint32),
                 ("prefilter_min", C.c_uint32), ("steps_per_sync", C.c_uint32), ("stage_mib", C.c_uint32),
-                ("blocks_a", C.c_uint32), ("blocks_b", C.c_uint32), ("reserved", C.c_uint32)]
+                ("blocks_a", C.c_uint32), ("blocks_b", C.c_uint32), ("ms_min", C.c_uint32)]
 
 
 class _Query(C.Structure):
@@ -73,7 +73,7 @@ class _SessionStats(C.Structure):
 
 
 TUNING_FIELDS = ["heavy", "budget", "chunk", "seg", "prefilter_min", "steps_per_sync", "stage_mib", "blocks_a",
-                 "blocks_b"]
+                 "blocks_b", "ms_min"]
 
 EXPORTS = ["hyperim_build_graph", "hyperim_stratify", "hyperim_graph_read", "hyperim_pool_create",
            "hyperim_generate_rr", "hyperim_pool_view", "hyperim_pool_read", "hyperim_pool_required",

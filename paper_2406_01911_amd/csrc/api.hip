@@ -128,14 +128,16 @@ void GreedyWorkspace::release() {
 size_t RRWorkspace::bytes() const {
     size_t b = 0;
     for (const DevBuf *x : {&lists, &bitmaps, &def_idx, &def_u32, &graph_desc, &task_desc, &items, &counters, &stage,
-                            &stage_off, &sizes, &roots, &scan_tmp, &big_ids})
+                            &stage_off, &sizes, &roots, &scan_tmp, &big_ids, &ms_seen, &ms_nxt, &ms_cur, &ms_next,
+                            &ms_batch, &ms_vcnt, &ms_ctr})
         b += x->bytes;
     return b;
 }
 
 void RRWorkspace::release() {
     for (DevBuf *x : {&lists, &bitmaps, &def_idx, &def_u32, &graph_desc, &task_desc, &items, &counters, &stage,
-                      &stage_off, &sizes, &roots, &scan_tmp, &big_ids})
+                      &stage_off, &sizes, &roots, &scan_tmp, &big_ids, &ms_seen, &ms_nxt, &ms_cur, &ms_next,
+                      &ms_batch, &ms_vcnt, &ms_ctr})
         x->release();
     for (hipEvent_t e : events) (void)hipEventDestroy(e);
     events.clear();
@@ -502,6 +504,7 @@ int hyperim_set_tuning(hyperim_graph g, const hyperim_tuning *t) {
     if (t->stage_mib) cur.stage_mib = std::max<uint32_t>(t->stage_mib, 64);
     if (t->blocks_a) cur.blocks_a = t->blocks_a;
     if (t->blocks_b) cur.blocks_b = t->blocks_b;
+    if (t->ms_min) cur.ms_min = t->ms_min;
     return HYPERIM_OK;
 }
 

@@ -61,6 +61,9 @@ struct RRWorkspace {
     DevBuf def_u32;              // deferred sets: root, slot, head, size, task (5 uint32 arrays)
     DevBuf graph_desc, task_desc;  // launch-group descriptors in device memory
     DevBuf items;                // phase B work items (uint4)
+    // bundled mode: per-bundle seen / found masks, frontier and next-level
+    // lists, batch marks, output counts, counters
+    DevBuf ms_seen, ms_nxt, ms_cur, ms_next, ms_batch, ms_vcnt, ms_ctr;
     DevBuf counters;             // work counter, stage bump, misc
     DevBuf stage;                // unsorted->sorted members before compaction
     DevBuf stage_off;            // per id (uint64)
@@ -133,7 +136,7 @@ struct hyperim_graph_s {
     bool stratified = false;
     hyperim::DevBuf l, deg, top, stratum, P;
     hyperim_strata_info info{};
-    hyperim_tuning tune{1024, 262144, 256, 512, 0xFFFFFFFFu, 8, 16384, 4, 6, 0};  // RR execution parameters
+    hyperim_tuning tune{1024, 262144, 256, 512, 0xFFFFFFFFu, 8, 16384, 4, 6, 4096};  // RR execution parameters
     // learned from generated sets (launch-group and stage sizing, admission);
     // -1 = nothing generated yet
     double rr_members = -1.0, rr_defer = -1.0;

@@ -726,6 +726,453 @@ __global__ __launch_bounds__(kWG) void k_finish(RRArgs a, uint32_t ndef) {
     }
 }
 
+// ---- bundled mode: 64 sets per bundle, bit-parallel over the sets ----------
+// For graphs whose RR sets are large (supercritical cascades), the sets of a
+// launch group -- one task, launch indices in bundles of 64 -- grow together,
+// level by level.  Per bundle and vertex u, seen[u] has bit s when u is in
+// set s of the bundle and nxt[u] the bits found in the current level.  A
+// frontier entry (bundle, v, mask) expands v once for every set in mask: v's
+// incidences and their members are read once, seen[u] removes the sets that
+// already hold u, and only the remaining (set, quad) pairs draw their Philox
+// block.  RR sets are reachability closures, so the sets equal those of the
+// per-set traversal.
+constexpr uint32_t kMsSets = 64;
+constexpr uint32_t kMsOutVerts = 4096;   // vertices per output block (16 per thread)
+
+enum MsCtr { kMsCur = 0, kMsNext, kMsItems, kMsPending, kMsLevelDone, kMsDone, kMsEpoch, kMsOverflow, kMsNumCtr };
+
+struct MsArgs {
+    GraphDesc graph;
+    const unsigned long long *bytesw;   // algorithmic bytes of each vertex as a member
+    uint64_t first_id;                  // RR id of launch index 0
+    uint32_t pool, key0, key1, qlog;
+    uint32_t nbundles, chunk, seg;
+    uint64_t count;                     // sets: launch indices [0, count)
+    uint64_t stride;                    // words per bundle in seen / nxt (>= n)
+    unsigned long long *seen, *nxt;
+    uint32_t *cur_b, *cur_v;            // frontier entries (bundle, vertex) ...
+    unsigned long long *cur_m;          // ... and their set masks
+    uint32_t *nx_b, *nx_v;              // vertices reached in the current level
+    uint32_t *batch_epoch;              // per 64 frontier entries: level in which they were planned
+    uint64_t list_cap;                  // entries of each list
+    unsigned long long *ctr;            // MsCtr
+    unsigned long long *bytes;          // algorithmic bytes (RR counter block)
+    uint4 *items;
+    uint32_t *vcnt;                     // output: per (bundle, vertex block, set) counts
+    uint32_t nvb;                       // vertex blocks per bundle
+};
+
+struct MsLds {
+    // level 2: frontier entries of the wave
+    uint32_t fr_scan[kWave], fr_v[kWave], fr_e0[kWave], fr_b[kWave];
+    unsigned long long fr_m[kWave];
+    // level 3: one incidence per lane
+    uint32_t in_scan[kWave], in_he[kWave], in_hb[kWave], in_hs[kWave], in_v[kWave], in_thr[kWave], in_b[kWave];
+    unsigned long long in_m[kWave];
+    // level 4: one quad per lane
+    uint32_t q_scan[kWave], q_he[kWave], q_q[kWave], q_v[kWave], q_thr[kWave], q_b[kWave];
+    uint32_t q_u[kWave][4];
+    unsigned long long q_union[kWave], q_cand[kWave][4];
+};
+
+// Position of the r-th set bit (r < popcount(m)) of m.
+__device__ __forceinline__ uint32_t nth_bit(unsigned long long m, uint32_t r) {
+    uint32_t pos = 0;
+#pragma unroll
+    for (uint32_t w = 32; w > 0; w >>= 1) {
+        const unsigned long long low = m & ((1ull << w) - 1ull);
+        const uint32_t c = (uint32_t)__popcll(low);
+        if (r >= c) {
+            r -= c;
+            m >>= w;
+            pos += w;
+        } else {
+            m = low;
+        }
+    }
+    return pos;
+}
+
+__device__ __forceinline__ void ms_append_next(const MsArgs &m, uint32_t b, uint32_t u) {
+    const unsigned long long pos = atomicAdd(&m.ctr[kMsNext], 1ull);
+    if (pos < m.list_cap) {
+        m.nx_b[pos] = b;
+        m.nx_v[pos] = u;
+    } else {
+        atomicOr(&m.ctr[kMsOverflow], 1ull);
+    }
+}
+
+// Roots: set s of bundle b is launch index 64 b + s.
+__global__ __launch_bounds__(kWG) void k_ms_roots(MsArgs m, RRArgs a) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m.count) return;
+    const GraphView G = graph_view(m.graph);
+    const uint32_t root = rr_root(G, m.qlog, m.first_id + i, m.pool, make_uint2(m.key0, m.key1));
+    a.roots[a.out_base + i] = root;
+    const uint32_t b = (uint32_t)(i / kMsSets), s = (uint32_t)(i % kMsSets);
+    const unsigned long long old = atomicOr(&m.nxt[(uint64_t)b * m.stride + root], 1ull << s);
+    if (old == 0ull) ms_append_next(m, b, root);
+}
+
+// New level: the vertices reached in the last one, with the sets that did not
+// hold them yet, become the frontier.  Runs only once the level's frontier
+// is fully planned and expanded.
+__global__ __launch_bounds__(kWG) void k_ms_advance(MsArgs m) {
+    if (m.ctr[kMsLevelDone] == 0ull) return;
+    const uint64_t cnt = min(m.ctr[kMsNext], (unsigned long long)m.list_cap);
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t b = m.nx_b[i], u = m.nx_v[i];
+        const uint64_t w = (uint64_t)b * m.stride + u;
+        const unsigned long long found = m.nxt[w];
+        m.nxt[w] = 0ull;
+        const unsigned long long fresh = found & ~m.seen[w];
+        if (fresh) {
+            m.seen[w] |= fresh;   // each (bundle, vertex) appears once in the list
+            const unsigned long long pos = atomicAdd(&m.ctr[kMsCur], 1ull);
+            if (pos < m.list_cap) {
+                m.cur_b[pos] = b;
+                m.cur_v[pos] = u;
+                m.cur_m[pos] = fresh;
+            } else {
+                atomicOr(&m.ctr[kMsOverflow], 1ull);
+            }
+        }
+    }
+}
+
+// Level bookkeeping between the kernels of one step (a single thread).
+// After expansion: the level is done once every frontier batch was planned.
+__global__ void k_ms_ctl_expanded(unsigned long long *ctr) {
+    if (ctr[kMsPending] == 0ull) {
+        ctr[kMsLevelDone] = 1ull;
+        ctr[kMsCur] = 0ull;
+        ctr[kMsEpoch] += 1ull;
+    } else {
+        ctr[kMsLevelDone] = 0ull;
+    }
+    ctr[kMsItems] = 0ull;
+}
+
+// After advancing: the new level's batches are pending; no frontier, done.
+__global__ void k_ms_ctl_advanced(unsigned long long *ctr, uint64_t list_cap) {
+    if (ctr[kMsLevelDone] != 0ull) {
+        ctr[kMsNext] = 0ull;
+        const unsigned long long cur = min(ctr[kMsCur], (unsigned long long)list_cap);
+        ctr[kMsCur] = cur;
+        ctr[kMsPending] = (cur + kWave - 1) / kWave;
+        if (cur == 0ull) ctr[kMsDone] = 1ull;
+    }
+}
+
+// Cut the frontier into work items, 64 entries per wave at a time: light
+// vertices in segments of consecutive entries (< seg + chunk incidences),
+// heavy ones in chunks of their incidences.  A batch whose items do not fit
+// the item buffer stays pending for the next step of the same level.
+__global__ __launch_bounds__(kWG) void k_ms_plan(MsArgs m) {
+    const uint32_t lane = lane_id(), wv = uni(threadIdx.x / kWave);
+    const uint64_t ncur = m.ctr[kMsCur];
+    const uint32_t epoch = (uint32_t)m.ctr[kMsEpoch] + 1u;   // never 0: fresh entries read 0
+    const uint64_t nbatch = (ncur + kWave - 1) / kWave;
+    const GraphView G = graph_view(m.graph);
+    unsigned long long bytes = 0;
+    for (uint64_t bt = (uint64_t)blockIdx.x * kWavesPerWG + wv; bt < nbatch; bt += (uint64_t)gridDim.x * kWavesPerWG) {
+        if (uni(m.batch_epoch[bt]) == epoch) continue;
+        const uint64_t f = bt * kWave + lane;
+        const uint32_t nb = (uint32_t)min((uint64_t)kWave, ncur - bt * kWave);
+        uint32_t v = 0, e0 = 0, deg = 0, hv = 0, light = 0, cv = m.chunk;
+        if (lane < nb) {
+            v = m.cur_v[f];
+            e0 = G.v_off[v];
+            deg = G.v_off[v + 1] - e0;
+            // at most kItemCap / 128 items per vertex, so that any batch of 64
+            // entries fits an empty item buffer
+            cv = max(m.chunk, (uint32_t)div_up(deg, kItemCap / 128));
+            hv = deg > m.chunk ? (uint32_t)div_up(deg, cv) : 0u;
+            light = hv ? 0u : deg;
+        }
+        const uint32_t lscan = wave_incl_scan(light);
+        const uint32_t seg = (lscan - light) / m.seg;
+        const uint32_t prev_seg = __shfl_up(seg, 1, kWave);
+        const bool first = lane < nb && (lane == 0 || seg != prev_seg);
+        const uint64_t firsts = __ballot(first);
+        const uint32_t nseg = (uint32_t)__popcll(firsts);
+        const uint32_t hscan = wave_incl_scan(hv);
+        const uint32_t need = nseg + uni(wave_bcast(hscan, kWave - 1));
+        unsigned long long base = 0;
+        if (lane == 0) base = atomicAdd(&m.ctr[kMsItems], (unsigned long long)need);
+        base = uni64(wave_bcast64(base, 0));
+        if (base + need > kItemCap) {
+            for (uint64_t x = base + lane; x < kItemCap; x += kWave) m.items[x].x = kSkipItem;
+            continue;
+        }
+        if (lane < nb && ((firsts >> lane) & 1ull)) {
+            const uint64_t above = lane + 1 < 64 ? (firsts >> (lane + 1)) << (lane + 1) : 0ull;
+            const uint32_t next = above ? (uint32_t)__ffsll((unsigned long long)above) - 1u : nb;
+            m.items[base + lane_rank(firsts)] = make_uint4((uint32_t)f, min(next, nb) - lane, 0u, 0u);
+        }
+        for (uint32_t k = 0; k < hv; ++k) {
+            const uint32_t b0 = e0 + k * cv;
+            m.items[base + nseg + hscan - hv + k] = make_uint4((uint32_t)f | 0x80000000u, b0, min(b0 + cv, e0 + deg), 0u);
+        }
+        if (lane < nb) bytes += (unsigned long long)__popcll(m.cur_m[f]) * m.bytesw[v];
+        if (lane == 0) {
+            m.batch_epoch[bt] = epoch;
+            atomicSub(&m.ctr[kMsPending], 1ull);
+        }
+    }
+    bytes = wave_sum(bytes);
+    if (lane_id() == 0 && bytes) atomicAdd(m.bytes, bytes);
+}
+
+// Levels 2-4 of a bundled expansion.  Each lane brings a frontier entry
+// (bundle b, vertex v, set mask) and the incidence range [e0, e0 + d) of v to
+// expand (d = 0 for none).  Level 2 spreads the incidences over the wave,
+// level 3 the quads of member positions of those hyperedges, level 4 the
+// (quad, set) pairs whose coins are needed: the sets of the entry's mask
+// that do not hold the member yet.
+__device__ __forceinline__ void ms_expand(const MsArgs &m, const GraphView &G, MsLds &L, uint32_t b, uint32_t v,
+                                          unsigned long long mask, uint32_t e0, uint32_t d) {
+    const uint32_t lane = lane_id();
+    const uint32_t dscan = wave_incl_scan(d);
+    const uint32_t D = uni(wave_bcast(dscan, kWave - 1));
+    wave_sync();
+    L.fr_scan[lane] = dscan;
+    L.fr_v[lane] = v;
+    L.fr_e0[lane] = e0;
+    L.fr_b[lane] = b;
+    L.fr_m[lane] = mask;
+    wave_sync();
+    for (uint32_t base = 0; base < D; base += kWave) {
+        // level 2: one incidence (v, he) per lane
+        const uint32_t g = base + lane;
+        uint32_t he = 0, hb = 0, hs = 0, vv = 0, th = 0, bb = 0, nq = 0;
+        unsigned long long mm = 0;
+        if (g < D) {
+            const uint32_t k = search64(L.fr_scan, g);
+            const uint32_t start = k ? L.fr_scan[k - 1] : 0u;
+            vv = L.fr_v[k];
+            bb = L.fr_b[k];
+            mm = L.fr_m[k];
+            he = G.v_he[L.fr_e0[k] + (g - start)];
+            hb = G.he_off[he];
+            hs = G.he_off[he + 1] - hb;
+            th = G.thr[vv];
+            nq = th ? (hs + 3u) >> 2 : 0u;   // threshold 0: no channel into vv is live
+        }
+        const uint32_t qscan = wave_incl_scan(nq);
+        const uint32_t Q = uni(wave_bcast(qscan, kWave - 1));
+        if (Q == 0) continue;
+        wave_sync();
+        L.in_scan[lane] = qscan;
+        L.in_he[lane] = he;
+        L.in_hb[lane] = hb;
+        L.in_hs[lane] = hs;
+        L.in_v[lane] = vv;
+        L.in_thr[lane] = th;
+        L.in_b[lane] = bb;
+        L.in_m[lane] = mm;
+        wave_sync();
+        for (uint32_t qb = 0; qb < Q; qb += kWave) {
+            // level 3: one quad of member positions per lane
+            const uint32_t qg = qb + lane;
+            uint32_t pc = 0;
+            uint32_t u[4] = {0u, 0u, 0u, 0u};
+            unsigned long long cand[4] = {0ull, 0ull, 0ull, 0ull}, un = 0ull;
+            uint32_t qhe = 0, qq = 0, qv = 0, qth = 0, qbnd = 0;
+            if (qg < Q) {
+                const uint32_t k = search64(L.in_scan, qg);
+                const uint32_t start = k ? L.in_scan[k - 1] : 0u;
+                qq = qg - start;
+                qhe = L.in_he[k];
+                qv = L.in_v[k];
+                qth = L.in_thr[k];
+                qbnd = L.in_b[k];
+                const unsigned long long qm = L.in_m[k];
+                const uint32_t p0 = 4u * qq, cnt = min(4u, L.in_hs[k] - p0);
+                const uint64_t row = (uint64_t)qbnd * m.stride;
+#pragma unroll
+                for (uint32_t t = 0; t < 4; ++t) u[t] = t < cnt ? G.he_mem[L.in_hb[k] + p0 + t] : qv;
+                unsigned long long sm[4];
+#pragma unroll
+                for (uint32_t t = 0; t < 4; ++t) sm[t] = t < cnt && u[t] != qv ? m.seen[row + u[t]] : ~0ull;
+#pragma unroll
+                for (uint32_t t = 0; t < 4; ++t) {
+                    cand[t] = qm & ~sm[t];
+                    un |= cand[t];
+                }
+                pc = (uint32_t)__popcll(un);
+            }
+            const uint32_t pscan = wave_incl_scan(pc);
+            const uint32_t PT = uni(wave_bcast(pscan, kWave - 1));
+            if (PT == 0) continue;
+            wave_sync();
+            L.q_scan[lane] = pscan;
+            L.q_he[lane] = qhe;
+            L.q_q[lane] = qq;
+            L.q_v[lane] = qv;
+            L.q_thr[lane] = qth;
+            L.q_b[lane] = qbnd;
+            L.q_union[lane] = un;
+#pragma unroll
+            for (uint32_t t = 0; t < 4; ++t) {
+                L.q_u[lane][t] = u[t];
+                L.q_cand[lane][t] = cand[t];
+            }
+            wave_sync();
+            for (uint32_t pb = 0; pb < PT; pb += kWave) {
+                // level 4: one (quad, set) pair per lane
+                const uint32_t pg = pb + lane;
+                if (pg < PT) {
+                    const uint32_t k = search64(L.q_scan, pg);
+                    const uint32_t r = pg - (k ? L.q_scan[k - 1] : 0u);
+                    const uint32_t s = nth_bit(L.q_union[k], r);
+                    const uint32_t bk = L.q_b[k], vk = L.q_v[k], thk = L.q_thr[k];
+                    const uint64_t j = m.first_id + (uint64_t)bk * kMsSets + s;
+                    const uint4 c = philox4x32_10(coin_counter(j, L.q_he[k], vk, m.pool, L.q_q[k]),
+                                                  make_uint2(m.key0, m.key1));
+                    const uint32_t w[4] = {c.x, c.y, c.z, c.w};
+                    const unsigned long long bit = 1ull << s;
+                    const uint64_t row = (uint64_t)bk * m.stride;
+#pragma unroll
+                    for (uint32_t t = 0; t < 4; ++t) {
+                        if ((L.q_cand[k][t] & bit) && channel_live(w[t], thk)) {
+                            const uint32_t ut = L.q_u[k][t];
+                            const unsigned long long old = atomicOr(&m.nxt[row + ut], bit);
+                            if (old == 0ull) ms_append_next(m, bk, ut);
+                        }
+                    }
+                }
+            }
+            wave_sync();
+        }
+    }
+    wave_sync();
+}
+
+__global__ __launch_bounds__(kWG) void k_ms_expand(MsArgs m) {
+    __shared__ MsLds lds[kWavesPerWG];
+    const uint32_t wv = uni(threadIdx.x / kWave);
+    MsLds &L = lds[wv];
+    const GraphView G = graph_view(m.graph);
+    const uint64_t nitems = min(m.ctr[kMsItems], (unsigned long long)kItemCap);
+    const uint64_t waves = (uint64_t)gridDim.x * kWavesPerWG;
+    const uint32_t lane = lane_id();
+    for (uint64_t it = (uint64_t)blockIdx.x * kWavesPerWG + wv; it < nitems; it += waves) {
+        const uint4 ld = m.items[it];
+        const uint4 item = make_uint4(uni(ld.x), uni(ld.y), uni(ld.z), uni(ld.w));
+        if (item.x == kSkipItem) continue;
+        if ((item.x >> 31) == 0u) {
+            // light segment: entries [item.x, item.x + item.y)
+            uint32_t b = 0, v = 0, e0 = 0, d = 0;
+            unsigned long long mask = 0;
+            if (lane < item.y) {
+                const uint32_t f = item.x + lane;
+                b = m.cur_b[f];
+                v = m.cur_v[f];
+                mask = m.cur_m[f];
+                e0 = G.v_off[v];
+                d = G.v_off[v + 1] - e0;
+                if (d > m.chunk) d = 0;   // expanded by its heavy items
+            }
+            ms_expand(m, G, L, b, v, mask, e0, d);
+        } else {
+            // one heavy vertex: incidences [item.y, item.z) of entry item.x
+            const uint32_t f = item.x & 0x7FFFFFFFu;
+            const uint32_t b = uni(m.cur_b[f]), v = uni(m.cur_v[f]);
+            const unsigned long long mask = uni64(m.cur_m[f]);
+            // the chunk's incidences go to lanes in runs of up to 64 entries
+            for (uint32_t e = item.y; e < item.z; e += kWave) {
+                const uint32_t mine = e + lane < item.z ? 1u : 0u;
+                ms_expand(m, G, L, b, v, mask, e + lane, mine);
+            }
+        }
+    }
+}
+
+// Output, pass 1: per (bundle, block of kMsOutVerts vertices) member counts
+// of every set.
+__global__ __launch_bounds__(kWG) void k_ms_count(MsArgs m) {
+    __shared__ uint32_t cnt[kMsSets];
+    const uint32_t b = blockIdx.x / m.nvb, blk = blockIdx.x % m.nvb;
+    const uint32_t n = m.graph.n;
+    if (threadIdx.x < kMsSets) cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const uint64_t row = (uint64_t)b * m.stride;
+    for (uint32_t i = 0; i < kMsOutVerts / kWG; ++i) {
+        const uint32_t v = blk * kMsOutVerts + i * kWG + threadIdx.x;
+        if (v >= n) break;
+        unsigned long long w = m.seen[row + v];
+        while (w) {
+            const uint32_t s = (uint32_t)__ffsll(w) - 1u;
+            w &= w - 1ull;
+            atomicAdd(&cnt[s], 1u);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < kMsSets) m.vcnt[((uint64_t)b * m.nvb + blk) * kMsSets + threadIdx.x] = cnt[threadIdx.x];
+}
+
+// Pass 2, one thread per set: block counts become block offsets, the set
+// gets its stage range and its per-id outputs.
+__global__ __launch_bounds__(kWG) void k_ms_record(MsArgs m, RRArgs a) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m.count) return;
+    const uint32_t b = (uint32_t)(i / kMsSets), s = (uint32_t)(i % kMsSets);
+    uint32_t total = 0;
+    for (uint32_t blk = 0; blk < m.nvb; ++blk) {
+        uint32_t *c = &m.vcnt[((uint64_t)b * m.nvb + blk) * kMsSets + s];
+        const uint32_t x = *c;
+        *c = total;
+        total += x;
+    }
+    const unsigned long long off = atomicAdd(&a.ctr[kBump], (unsigned long long)total);
+    record_set(a, i, off, total, a.roots[a.out_base + i]);
+}
+
+// Pass 3: members in ascending order.  Each thread owns 16 consecutive
+// vertices of the block; per set, a workgroup scan of the threads' counts
+// places them.
+__global__ __launch_bounds__(kWG) void k_ms_write(MsArgs m, RRArgs a) {
+    __shared__ uint32_t wsum[kWavesPerWG];
+    constexpr uint32_t kPer = kMsOutVerts / kWG;
+    const uint32_t b = blockIdx.x / m.nvb, blk = blockIdx.x % m.nvb;
+    const uint32_t n = m.graph.n, lane = lane_id(), wv = threadIdx.x / kWave;
+    const uint64_t row = (uint64_t)b * m.stride;
+    const uint32_t v0 = blk * kMsOutVerts + threadIdx.x * kPer;
+    unsigned long long w[kPer];
+    unsigned long long any = 0;
+#pragma unroll
+    for (uint32_t t = 0; t < kPer; ++t) {
+        w[t] = v0 + t < n ? m.seen[row + v0 + t] : 0ull;
+        any |= w[t];
+    }
+    const uint64_t sets = min((uint64_t)kMsSets, m.count - (uint64_t)b * kMsSets);
+    for (uint32_t s = 0; s < sets; ++s) {
+        const unsigned long long bit = 1ull << s;
+        uint32_t c = 0;
+        if (any & bit) {
+#pragma unroll
+            for (uint32_t t = 0; t < kPer; ++t) c += (w[t] & bit) ? 1u : 0u;
+        }
+        const uint32_t incl = wave_incl_scan(c);
+        if (lane == kWave - 1) wsum[wv] = incl;
+        __syncthreads();
+        uint32_t before = incl - c;
+        for (uint32_t q = 0; q < wv; ++q) before += wsum[q];
+        const uint64_t id = a.out_base + (uint64_t)b * kMsSets + s;
+        const uint64_t off = a.stage_off[id];
+        const uint32_t size = a.sizes[id];
+        if (c && off + size <= a.stage_cap) {
+            uint64_t pos = off + m.vcnt[((uint64_t)b * m.nvb + blk) * kMsSets + s] + before;
+#pragma unroll
+            for (uint32_t t = 0; t < kPer; ++t)
+                if (w[t] & bit) a.stage[pos++] = v0 + t;
+        }
+        __syncthreads();
+    }
+}
+
 // ---- compaction ------------------------------------------------------------
 // Sets up to kBigSet members: each wave moves 64 consecutive ids, flattened
 // over their members.
@@ -1038,6 +1485,139 @@ int run_launch(RRWorkspace &ws, RRStats &st, const hyperim_tuning &tune, RRArgs 
     return HYPERIM_OK;
 }
 
+
+// Bytes of the bundled-mode state per bundle for a graph of n vertices:
+// seen and nxt masks, frontier and next-level lists, output counts, batch marks.
+uint64_t ms_bytes_per_bundle(uint32_t n) {
+    const uint64_t nvb = div_up(std::max<uint32_t>(n, 1), kMsOutVerts);
+    return (uint64_t)n * (8 + 8 + 16 + 8) + nvb * kMsSets * 4 + div_up(n, kWave) * 4 + 4096;
+}
+
+// One bundled launch group: ids [0, a.count) of one task (all on graph g),
+// bundles of 64 sets grown level by level, then written out in ascending
+// order per set.
+int run_ms_launch(RRWorkspace &ws, RRStats &st, const hyperim_tuning &tune, RRArgs &a, const LaunchShape &shape,
+                  hyperim_graph g, const TaskDesc &t, bool trace, hipStream_t s) {
+    const uint32_t n = g->n;
+    const uint32_t nbundles = (uint32_t)div_up(a.count, kMsSets);
+    const uint64_t stride = std::max<uint32_t>(n, 1);
+    const uint64_t list_cap = (uint64_t)nbundles * stride;
+    const uint32_t nvb = (uint32_t)div_up(stride, kMsOutVerts);
+    if (list_cap >= (1ull << 31)) {
+        set_error_detail("bundled launch group too large");
+        return HYPERIM_EINVAL;
+    }
+    HIM_CHECK(ws.ms_seen.reserve(sizeof(unsigned long long) * nbundles * stride, s));
+    HIM_CHECK(ws.ms_nxt.reserve(sizeof(unsigned long long) * nbundles * stride, s));
+    HIM_CHECK(ws.ms_cur.reserve((sizeof(uint32_t) * 2 + sizeof(unsigned long long)) * list_cap, s));
+    HIM_CHECK(ws.ms_next.reserve(sizeof(uint32_t) * 2 * list_cap, s));
+    HIM_CHECK(ws.ms_batch.reserve(sizeof(uint32_t) * div_up(list_cap, kWave), s));
+    HIM_CHECK(ws.ms_vcnt.reserve(sizeof(uint32_t) * (uint64_t)nbundles * nvb * kMsSets, s));
+    HIM_CHECK(ws.ms_ctr.reserve(sizeof(unsigned long long) * kMsNumCtr, s));
+    MsArgs m{};
+    m.graph = GraphDesc{g->he_off.as<uint32_t>(), g->he_mem.as<uint32_t>(), g->v_off.as<uint32_t>(),
+                        g->v_he.as<uint32_t>(), g->thr.as<uint32_t>(), g->P.as<uint32_t>(), n, (n + 31u) / 32u};
+    m.bytesw = g->bytesw.as<unsigned long long>();
+    m.first_id = t.first_id;
+    m.pool = t.pool;
+    m.key0 = t.key0;
+    m.key1 = t.key1;
+    m.qlog = a.qlog;
+    m.nbundles = nbundles;
+    m.chunk = a.chunk;
+    m.seg = a.seg;
+    m.count = a.count;
+    m.stride = stride;
+    m.seen = ws.ms_seen.as<unsigned long long>();
+    m.nxt = ws.ms_nxt.as<unsigned long long>();
+    m.cur_b = ws.ms_cur.as<uint32_t>();
+    m.cur_v = m.cur_b + list_cap;
+    m.cur_m = reinterpret_cast<unsigned long long *>(m.cur_v + list_cap);
+    m.nx_b = ws.ms_next.as<uint32_t>();
+    m.nx_v = m.nx_b + list_cap;
+    m.batch_epoch = ws.ms_batch.as<uint32_t>();
+    m.list_cap = list_cap;
+    m.ctr = ws.ms_ctr.as<unsigned long long>();
+    m.bytes = a.ctr + kBytesB;
+    m.items = a.items;
+    m.vcnt = ws.ms_vcnt.as<uint32_t>();
+    m.nvb = nvb;
+    // clean state: no set holds anything, no vertex found, no batch planned
+    HIM_HIP(hipMemsetAsync(m.seen, 0, sizeof(unsigned long long) * nbundles * stride, s));
+    HIM_HIP(hipMemsetAsync(m.nxt, 0, sizeof(unsigned long long) * nbundles * stride, s));
+    HIM_HIP(hipMemsetAsync(m.batch_epoch, 0, sizeof(uint32_t) * div_up(list_cap, kWave), s));
+    HIM_HIP(hipMemsetAsync(m.ctr, 0, sizeof(unsigned long long) * kMsNumCtr, s));
+    const unsigned long long one = 1;
+    HIM_HIP(hipMemcpyAsync(m.ctr + kMsLevelDone, &one, sizeof(one), hipMemcpyHostToDevice, s));
+    HIM_CHECK(event_pair(ws));
+    HIM_HIP(hipEventRecord(ws.events[0], s));
+    const uint32_t grid_b = shape.grid_b;
+    hipLaunchKernelGGL(k_ms_roots, dim3((uint32_t)div_up(a.count, kWG)), dim3(kWG), 0, s, m, a);
+    hipLaunchKernelGGL(k_ms_advance, dim3(grid_b), dim3(kWG), 0, s, m);
+    hipLaunchKernelGGL(k_ms_ctl_advanced, dim3(1), dim3(1), 0, s, m.ctr, list_cap);
+    HIM_HIP(hipGetLastError());
+    // levels: plan, expand, bookkeeping, advance, bookkeeping; a level whose
+    // items overflow the buffer takes several steps
+    const int per_sync = (int)std::max<uint32_t>(tune.steps_per_sync, 1);
+    const uint64_t max_steps = 4ull * stride + 64ull + 2ull * (uint64_t)per_sync;
+    uint64_t steps = 0;
+    float ms = 0.f;
+    for (;;) {
+        if (steps > max_steps) {
+            set_error_detail("bundled generation did not converge");
+            return HYPERIM_EHIP;
+        }
+        const int batch = trace ? 1 : per_sync;
+        for (int k = 0; k < batch; ++k) {
+            hipLaunchKernelGGL(k_ms_plan, dim3(grid_b), dim3(kWG), 0, s, m);
+            HIM_HIP(hipEventRecord(ws.events[2 + 2 * k], s));
+            hipLaunchKernelGGL(k_ms_expand, dim3(grid_b), dim3(kWG), 0, s, m);
+            HIM_HIP(hipEventRecord(ws.events[3 + 2 * k], s));
+            hipLaunchKernelGGL(k_ms_ctl_expanded, dim3(1), dim3(1), 0, s, m.ctr);
+            hipLaunchKernelGGL(k_ms_advance, dim3(grid_b), dim3(kWG), 0, s, m);
+            hipLaunchKernelGGL(k_ms_ctl_advanced, dim3(1), dim3(1), 0, s, m.ctr, list_cap);
+        }
+        HIM_HIP(hipGetLastError());
+        steps += batch;
+        uint64_t done = 0;
+        HIM_CHECK(read_ctr(s, m.ctr, kMsDone, &done));
+        for (int k = 0; k < batch; ++k) {
+            float me = 0.f;
+            HIM_HIP(hipEventElapsedTime(&me, ws.events[2 + 2 * k], ws.events[3 + 2 * k]));
+            st.ms_expand += me;
+        }
+        st.expand_launches += batch;
+        st.supersteps += batch;
+        st.launches += 5 * batch;
+        if (trace) {
+            uint64_t cur = 0;
+            HIM_CHECK(read_ctr(s, m.ctr, kMsCur, &cur));
+            fprintf(stderr, "[hyperim] bundled step %llu: frontier %llu\n", (unsigned long long)steps,
+                    (unsigned long long)cur);
+        }
+        if (done) break;
+    }
+    uint64_t overflow = 0;
+    HIM_CHECK(read_ctr(s, m.ctr, kMsOverflow, &overflow));
+    if (overflow) {
+        set_error_detail("bundled frontier list overflow");
+        return HYPERIM_EHIP;
+    }
+    // output: counts per vertex block, set ranges, members in ascending order
+    const uint32_t out_grid = nbundles * nvb;
+    hipLaunchKernelGGL(k_ms_count, dim3(out_grid), dim3(kWG), 0, s, m);
+    hipLaunchKernelGGL(k_ms_record, dim3((uint32_t)div_up(a.count, kWG)), dim3(kWG), 0, s, m, a);
+    hipLaunchKernelGGL(k_ms_write, dim3(out_grid), dim3(kWG), 0, s, m, a);
+    HIM_HIP(hipGetLastError());
+    HIM_HIP(hipEventRecord(ws.events[1], s));
+    HIM_HIP(hipEventSynchronize(ws.events[1]));
+    HIM_HIP(hipEventElapsedTime(&ms, ws.events[0], ws.events[1]));
+    st.ms_bfs += ms;
+    st.ms_heavy += ms;
+    st.launches += 6;
+    return HYPERIM_OK;
+}
+
 }  // namespace
 
 namespace {
@@ -1135,6 +1715,12 @@ int rr_generate_into(RRWorkspace &ws, RRStats &st, const std::vector<RRTask> &ta
     // its wave).  The plain form (1) also ends a group at every (task, ladder
     // block, stratum) boundary.
     constexpr uint64_t kLearnIds = 2048;
+    constexpr uint64_t kMsBudget = 8ull << 30;   // bytes of bundled-mode state per launch group
+    // bundled mode for graphs whose sets are large on average (form 0 only;
+    // the plain form keeps one traversal per set)
+    auto bundled = [&](const RRTask &t) {
+        return form == 0 && t.g->rr_members >= 0.0 && t.g->rr_members >= (double)tune.ms_min;
+    };
     const double stage_words = (double)stage_budget / 4.0;
     auto per_set = [](hyperim_graph g) { return g->rr_members >= 0.0 ? 1.3 * g->rr_members + 1.0 : (double)g->n; };
     std::vector<uint64_t> tstart(tasks.size() + 1, 0);
@@ -1195,7 +1781,21 @@ int rr_generate_into(RRWorkspace &ws, RRStats &st, const std::vector<RRTask> &ta
         double acc = 0.0;
         size_t ti = std::upper_bound(tstart.begin(), tstart.end(), pos) - tstart.begin() - 1;
         while (unit_end[unit] <= pos) ++unit;
-        for (;;) {
+        const bool ms = bundled(tasks[ti]);
+        if (ms) {
+            // bundled mode: one task, as many sets as the stage and the
+            // bundle memory allow
+            const RRTask &t = tasks[ti];
+            const uint64_t rest = tstart[ti + 1] - pos;
+            const uint64_t max_sets =
+                kMsSets * std::max<uint64_t>(1, kMsBudget / ms_bytes_per_bundle(t.g->n));
+            const double m = per_set(t.g);
+            uint64_t take = std::min<uint64_t>(rest, max_sets);
+            take = std::min<uint64_t>(take, std::max<uint64_t>(1, (uint64_t)(stage_words / m)));
+            acc = (double)take * m;
+            pos += take;
+        }
+        for (; !ms;) {
             const RRTask &t = tasks[ti];
             const double m = per_set(t.g);
             const bool learn = t.g->rr_members < 0.0;
@@ -1208,7 +1808,8 @@ int rr_generate_into(RRWorkspace &ws, RRStats &st, const std::vector<RRTask> &ta
             acc += (double)take * m;
             pos += take;
             if (take < rest || pos == count || form == 1 || pos - lo >= def_chunk) break;
-            ++ti;   // form 0: the group continues with the next task
+            ++ti;   // form 0: the group continues with the next task ...
+            if (bundled(tasks[ti])) break;   // ... unless that one runs bundled
         }
         const uint64_t hi = pos;
         // descriptors of the group's task slices
@@ -1251,7 +1852,10 @@ int rr_generate_into(RRWorkspace &ws, RRStats &st, const std::vector<RRTask> &ta
             a.stage_cap = ws.stage.bytes / sizeof(uint32_t);
             HIM_HIP(hipMemsetAsync(ctr, 0, sizeof(unsigned long long) * kNumCtr, s));
             RRStats run{};
-            HIM_CHECK(run_launch(ws, run, tune, a, shape, grid, grid_b, trace, s));
+            if (ms)
+                HIM_CHECK(run_ms_launch(ws, run, tune, a, shape, tasks[slices[0].task].g, tdesc[0], trace, s));
+            else
+                HIM_CHECK(run_launch(ws, run, tune, a, shape, grid, grid_b, trace, s));
             // time counts every attempt, work only the one that produced the output
             st.ms_bfs += run.ms_bfs;
             st.ms_light += run.ms_light;

@@ -93,6 +93,55 @@ def test_graph_strata_and_rr_sets_bit_exact(hy, case):
         assert np.array_equal(mem, rmem)
 
 
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_bundled_mode_bit_exact(hy, case):
+    """Sets grown in bundles of 64, bit-parallel over the sets (forced here by
+    a members-per-set threshold of 1; the first 2048 sets of a graph run in
+    the per-set mode and teach the estimate) equal the oracle's."""
+    _flush(f"[gpu] bundled case={case}")
+    hg, model, p = CASES[case]()
+    g, o = _pair(hy, hg, model, p)
+    g.stratify()
+    o.stratify()
+    g.set_tuning(ms_min=1)
+    for pool_tag, (a, b) in [(0, (0, 2048 + 333)), (1, (100, 2048 + 100 + 130))]:
+        pool = hy.Pool(g)
+        hy.generate_rr(g, 7, 3, pool_tag, a, b, pool)
+        hy.generate_rr(g, 7, 3, pool_tag, b, b + 200, pool)
+        off, mem, roots = pool.read()
+        roff, rmem, rroots = o.generate(7, 3, pool_tag, a, b + 200)
+        assert np.array_equal(roots, rroots)
+        assert np.array_equal(off, roff)
+        assert np.array_equal(mem, rmem)
+
+
+def test_bundled_select_matches_oracle(hy):
+    _flush("[gpu] bundled select tiny / mid rr sets")
+    w = hypergen.workload("tiny")
+    hg = w.build()
+    g, o = _pair(hy, hg, w.model, w.p)
+    g.stratify()
+    o.stratify()
+    g.set_tuning(ms_min=1)
+    hy.select_seeds(g, w.k, w.eps, w.ell)        # learns the members per set
+    r = hy.select_seeds(g, w.k, w.eps, w.ell)
+    ro = o.select_seeds(w.k, w.eps, w.ell)
+    for key in ("rounds", "theta", "lambda1", "lambda2", "entries1", "entries2"):
+        assert r[key] == ro[key], key
+    assert np.array_equal(r["seeds"], ro["seeds"]) and np.array_equal(r["gains"], ro["gains"])
+    wm = hypergen.workload("mid")
+    hm = wm.build()
+    gm, om = _pair(hy, hm, wm.model, wm.p)
+    gm.stratify()
+    om.stratify()
+    gm.set_tuning(ms_min=1)
+    pool = hy.Pool(gm)
+    hy.generate_rr(gm, 0, 0, 0, 0, 2048 + 952, pool)
+    off, mem, roots = pool.read()
+    roff, rmem, rroots = om.generate(0, 0, 0, 0, 3000)
+    assert np.array_equal(off, roff) and np.array_equal(mem, rmem) and np.array_equal(roots, rroots)
+
+
 def test_append_across_ladder_blocks(hy):
     _flush("[gpu] append across ladder blocks")
     hg = hypergen.workload("tiny").build()
