@@ -793,6 +793,17 @@ __device__ __forceinline__ uint32_t nth_bit(unsigned long long m, uint32_t r) {
     return pos;
 }
 
+// Work of a frontier entry grows with its incidences times the sets in its
+// mask; a heavy entry is cut into chunks of about `chunk` (incidence, set)
+// pairs: chunk / (sets) incidences, at least 1, and at most kItemCap / 128
+// chunks per entry so that any batch of 64 entries fits an empty item buffer.
+// Returns the chunk length in incidences; the entry is heavy when its degree
+// exceeds it.
+__device__ __forceinline__ uint32_t ms_chunk(uint32_t deg, uint32_t sets, uint32_t chunk) {
+    const uint32_t c = max(1u, chunk / max(sets, 1u));
+    return max(c, (uint32_t)div_up(deg, kItemCap / 128));
+}
+
 __device__ __forceinline__ void ms_append_next(const MsArgs &m, uint32_t b, uint32_t u) {
     const unsigned long long pos = atomicAdd(&m.ctr[kMsNext], 1ull);
     if (pos < m.list_cap) {
@@ -880,16 +891,15 @@ __global__ __launch_bounds__(kWG) void k_ms_plan(MsArgs m) {
         if (uni(m.batch_epoch[bt]) == epoch) continue;
         const uint64_t f = bt * kWave + lane;
         const uint32_t nb = (uint32_t)min((uint64_t)kWave, ncur - bt * kWave);
-        uint32_t v = 0, e0 = 0, deg = 0, hv = 0, light = 0, cv = m.chunk;
+        uint32_t v = 0, e0 = 0, deg = 0, hv = 0, light = 0, cv = m.chunk, sets = 0;
         if (lane < nb) {
             v = m.cur_v[f];
+            sets = (uint32_t)__popcll(m.cur_m[f]);
             e0 = G.v_off[v];
             deg = G.v_off[v + 1] - e0;
-            // at most kItemCap / 128 items per vertex, so that any batch of 64
-            // entries fits an empty item buffer
-            cv = max(m.chunk, (uint32_t)div_up(deg, kItemCap / 128));
-            hv = deg > m.chunk ? (uint32_t)div_up(deg, cv) : 0u;
-            light = hv ? 0u : deg;
+            cv = ms_chunk(deg, sets, m.chunk);
+            hv = deg > cv ? (uint32_t)div_up(deg, cv) : 0u;
+            light = hv ? 0u : deg * sets;   // segment weight: (incidence, set) pairs
         }
         const uint32_t lscan = wave_incl_scan(light);
         const uint32_t seg = (lscan - light) / m.seg;
@@ -915,7 +925,7 @@ __global__ __launch_bounds__(kWG) void k_ms_plan(MsArgs m) {
             const uint32_t b0 = e0 + k * cv;
             m.items[base + nseg + hscan - hv + k] = make_uint4((uint32_t)f | 0x80000000u, b0, min(b0 + cv, e0 + deg), 0u);
         }
-        if (lane < nb) bytes += (unsigned long long)__popcll(m.cur_m[f]) * m.bytesw[v];
+        if (lane < nb) bytes += (unsigned long long)sets * m.bytesw[v];
         if (lane == 0) {
             m.batch_epoch[bt] = epoch;
             atomicSub(&m.ctr[kMsPending], 1ull);
@@ -1073,7 +1083,7 @@ __global__ __launch_bounds__(kWG) void k_ms_expand(MsArgs m) {
                 mask = m.cur_m[f];
                 e0 = G.v_off[v];
                 d = G.v_off[v + 1] - e0;
-                if (d > m.chunk) d = 0;   // expanded by its heavy items
+                if (d > ms_chunk(d, (uint32_t)__popcll(mask), m.chunk)) d = 0;   // expanded by its heavy items
             }
             ms_expand(m, G, L, b, v, mask, e0, d);
         } else {
