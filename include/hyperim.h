@@ -317,7 +317,9 @@ int hyperim_workspace_release(void);
  *                  average (learned from earlier launches) grow their sets
  *                  in bundles of 64, bit-parallel over the sets: each vertex
  *                  expansion serves every set that reached it in the same
- *                  level (4096; 0xFFFFFFFF = never). */
+ *                  level (0xFFFFFFFF = never, the default: it helps on some
+ *                  supercritical graphs and hurts on others, so the
+ *                  autotuner decides). */
 typedef struct {
     uint32_t heavy, budget, chunk, seg, prefilter_min, steps_per_sync;
     uint32_t stage_mib, blocks_a, blocks_b, ms_min;

@@ -6,7 +6,8 @@ multi-workgroup granularity), how many workgroups per compute unit each phase
 launches (blocks_a, blocks_b), how large the grid-wide work items are (chunk,
 seg), when visited marks are tested before coins (prefilter_min), how many
 supersteps run between host checks (steps_per_sync) and how much staging
-memory a launch group may use (stage_mib).  The tuner measures one round of
+memory a launch group may use (stage_mib) and when sets grow in bit-parallel
+bundles (ms_min).  The tuner measures one round of
 seed selection at a fixed theta for each candidate, by coordinate descent
 over a small grid per parameter, and keeps a candidate only if its seeds and
 gains equal the baseline's (they must: every schedule gives the same bytes).
@@ -38,6 +39,7 @@ SPACE = {
     "steps_per_sync": [2, 4, 8, 16, 32],
     "blocks_a": [2, 3, 4, 6, 8],
     "blocks_b": [3, 4, 6, 8],
+    "ms_min": [1024, 4096, 65536, 0xFFFFFFFF],
 }
 
 
@@ -112,6 +114,7 @@ def main():
     ap.add_argument("--sweeps", type=int, default=2)
     ap.add_argument("--theta", type=int, default=0, help="RR sets per pool of the measured round (0: the query's)")
     ap.add_argument("--out", default="")
+    ap.add_argument("--params", default="", help="comma-separated subset of the parameters to search")
     args = ap.parse_args()
     sys.path.insert(0, os.path.dirname(HERE))
     import torch  # noqa: F401
@@ -123,8 +126,12 @@ def main():
     g = hy.build_graph(hg.n, hg.he_off, hg.he_mem, w.model, w.p)
     g.stratify()
     t0 = time.time()
-    res = autotune(g, w.k, w.eps, w.ell, seed=w.philox_seed, theta=args.theta or None, reps=args.reps,
-                   sweeps=args.sweeps, log=lambda m: print(m, file=sys.stderr, flush=True))
+    space = {k: v for k, v in SPACE.items() if not args.params or k in args.params.split(",")}
+    stored = load(args.workload)
+    if stored:
+        g.set_tuning(**stored)   # refine the stored result
+    res = autotune(g, w.k, w.eps, w.ell, seed=w.philox_seed, theta=args.theta or None, space=space,
+                   reps=args.reps, sweeps=args.sweeps, log=lambda m: print(m, file=sys.stderr, flush=True))
     res["workload"] = args.workload
     res["seconds"] = time.time() - t0
     out = args.out or tuning_path(args.workload)

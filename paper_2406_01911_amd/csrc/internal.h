@@ -136,7 +136,7 @@ struct hyperim_graph_s {
     bool stratified = false;
     hyperim::DevBuf l, deg, top, stratum, P;
     hyperim_strata_info info{};
-    hyperim_tuning tune{1024, 262144, 256, 512, 0xFFFFFFFFu, 8, 16384, 4, 6, 4096};  // RR execution parameters
+    hyperim_tuning tune{1024, 262144, 256, 512, 0xFFFFFFFFu, 8, 16384, 4, 6, 0xFFFFFFFFu};  // RR execution parameters
     // learned from generated sets (launch-group and stage sizing, admission);
     // -1 = nothing generated yet
     double rr_members = -1.0, rr_defer = -1.0;
