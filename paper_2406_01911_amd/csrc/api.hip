@@ -141,6 +141,9 @@ void RRWorkspace::release() {
         x->release();
     for (hipEvent_t e : events) (void)hipEventDestroy(e);
     events.clear();
+    if (host) (void)hipHostFree(host);
+    host = nullptr;
+    host_words = 0;
     grid = waves = slots = grid_b = slot_n = slot_words = 0;
 }
 

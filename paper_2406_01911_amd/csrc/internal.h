@@ -72,6 +72,8 @@ struct RRWorkspace {
     DevBuf scan_tmp;             // scan block sums
     DevBuf big_ids;              // per-id indices of sets compacted by whole workgroups
     std::vector<hipEvent_t> events;  // start/stop pairs around RR-generation launches
+    unsigned long long *host = nullptr;  // pinned host staging: counter copies, descriptors, totals
+    size_t host_words = 0;
     size_t bytes() const;        // device memory held
     void release();
 };

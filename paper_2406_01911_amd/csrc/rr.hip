@@ -34,6 +34,7 @@
 //
 // Compaction turns the per-id sizes into CSR offsets (device scan) and moves
 // the staged members into the pools.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -305,12 +306,16 @@ __device__ __forceinline__ void test_octet(const GraphView &G, uint64_t j, uint3
 // (he, u -> v) of those incidences is tested with its coin and newly reached
 // members go to `app`.  Level 3 first tests the first 8 member positions of
 // each lane's own incidence, then spreads the remaining octets of the longer
-// hyperedges over the wave.  Returns the algorithmic bytes of the incidences
-// read (12 per incidence plus 4 per member position), wave-uniform.
+// hyperedges over the wave.  W waves (a power of two, wave w of them passing
+// w) may share one call: they split the batches of 64 incidences between
+// them, and when there are fewer batches than waves, each batch's octets too;
+// every octet is tested by exactly one of them.  Returns the algorithmic
+// bytes of the incidences read (12 per incidence plus 4 per member
+// position), each counted by one wave, wave-uniform.
 template <bool kLds, bool kUniform, class App>
 __device__ __forceinline__ uint64_t expand(const GraphView &G, WaveLds &L, uint64_t j, uint32_t pool, uint2 key,
                                            uint32_t *bm, bool prefilter, uint32_t v, uint32_t e0, uint32_t d,
-                                           App &app) {
+                                           App &app, uint32_t w = 0, uint32_t W = 1) {
     const uint32_t lane = lane_id();
     uint32_t D = d;
     uint32_t th_uniform = 0;
@@ -325,8 +330,18 @@ __device__ __forceinline__ uint64_t expand(const GraphView &G, WaveLds &L, uint6
         L.fr_e0[lane] = e0;
         wave_sync();
     }
+    // batch share: batches b = boff, boff + bstride, ...; within a batch,
+    // octets qb = sub_w * 64, (sub_w + sub) * 64, ...  (first octets: sub_w 0)
+    const uint32_t nbatch = (D + kWave - 1) / kWave;
+    uint32_t bstride = W, sub = 1;
+    if (nbatch < W) {
+        bstride = 1;
+        while (bstride < nbatch) bstride <<= 1;
+        sub = W / bstride;
+    }
+    const uint32_t boff = w & (bstride - 1), sub_w = w / bstride;
     uint64_t bytes = 0;
-    for (uint32_t base = 0; base < D; base += kWave) {
+    for (uint32_t base = boff * kWave; base < D; base += bstride * kWave) {
         // level 2: one incidence (v, he) per lane
         const uint32_t g = base + lane;
         uint32_t he = 0, hb = 0, hs = 0, vv = v, th = th_uniform, no = 0;
@@ -343,10 +358,11 @@ __device__ __forceinline__ uint64_t expand(const GraphView &G, WaveLds &L, uint6
             hb = G.he_off[he];
             hs = G.he_off[he + 1] - hb;
             no = th ? (hs + 7u) >> 3 : 0u;   // threshold 0: no channel into vv is live
-            bytes += 12u + 4u * hs;
+            if (sub_w == 0) bytes += 12u + 4u * hs;
         }
         // level 3, first pass: octet 0 of the lane's own incidence
-        test_octet<kLds>(G, j, pool, key, bm, prefilter, no > 0, he, hb, 0u, min(8u, hs), vv, th, app);
+        if (sub_w == 0)
+            test_octet<kLds>(G, j, pool, key, bm, prefilter, no > 0, he, hb, 0u, min(8u, hs), vv, th, app);
         // second pass: octets 1.. of the longer hyperedges, flattened over the wave
         const uint32_t rem = no > 1 ? no - 1u : 0u;
         if (__ballot(rem > 0) == 0) continue;
@@ -362,7 +378,7 @@ __device__ __forceinline__ uint64_t expand(const GraphView &G, WaveLds &L, uint6
             L.in_thr[lane] = th;
         }
         wave_sync();
-        for (uint32_t qb = 0; qb < R; qb += kWave) {
+        for (uint32_t qb = sub_w * kWave; qb < R; qb += sub * kWave) {
             const uint32_t qg = qb + lane;
             const bool active = qg < R;
             uint32_t hee = 0, hbk = 0, p0 = 0, cm = 0, ve = v, the = th_uniform;
@@ -542,10 +558,12 @@ __global__ __launch_bounds__(kWG) void k_rr_light(RRArgs a) {
 // abandoned: its slots below the cap are filled with skip markers (x = ~0)
 // by the reserving wave, so k_expand never reads an unwritten item.
 constexpr uint32_t kSkipItem = 0xFFFFFFFFu;
+constexpr uint32_t kShareMax = 16;   // waves that may share one item
 
-__global__ __launch_bounds__(kWG) void k_plan(RRArgs a, uint32_t ndef, uint32_t parity) {
+__global__ __launch_bounds__(kWG) void k_plan(RRArgs a, uint32_t parity) {
     const uint32_t lane = lane_id(), wv = uni(threadIdx.x / kWave);
     const uint32_t waves = gridDim.x * kWavesPerWG;
+    const uint32_t ndef = uni((uint32_t)a.ctr[kDefCount]);   // sets phase A deferred
     for (uint32_t d = blockIdx.x * kWavesPerWG + wv; d < ndef; d += waves) {
         uint32_t head = uni(a.def_head[d]);
         const uint32_t size = uni(a.def_size[d]);
@@ -615,10 +633,15 @@ __global__ __launch_bounds__(kWG) void k_expand(RRArgs a, uint32_t parity) {
     if (blockIdx.x == 0 && threadIdx.x == 0) a.ctr[kItems + (parity ^ 1u)] = 0ull;   // next superstep's counter
     uint64_t bytes_done = 0;
     // items have bounded cost (< seg + chunk incidences), so a static strided
-    // assignment balances well and needs no shared counter
+    // assignment balances well and needs no shared counter.  With fewer items
+    // than waves (the thin tail of a traversal), W waves share each item.
     const uint64_t waves = (uint64_t)gridDim.x * kWavesPerWG;
+    uint32_t W = 1;
+    while (W < kShareMax && 2ull * W * nitems <= waves) W <<= 1;
+    const uint64_t gw = (uint64_t)blockIdx.x * kWavesPerWG + wv, groups = waves / W;
+    const uint32_t w = (uint32_t)(gw & (W - 1));
     const uint32_t lane = lane_id();
-    for (uint64_t it = (uint64_t)blockIdx.x * kWavesPerWG + wv; it < nitems; it += waves) {
+    for (uint64_t it = gw / W; it < nitems && gw < groups * W; it += groups) {
         const uint4 ld = a.items[it];
         const uint4 item = make_uint4(uni(ld.x), uni(ld.y), uni(ld.z), uni(ld.w));
         if (item.x == kSkipItem) continue;
@@ -641,12 +664,12 @@ __global__ __launch_bounds__(kWG) void k_expand(RRArgs a, uint32_t parity) {
                 deg = G.v_off[v + 1] - e0;
                 if (deg > a.chunk) deg = 0;   // expanded by its heavy items
             }
-            bytes_done += 20ull * item.z;
-            bytes_done += expand<false, false>(G, L, S.j, S.pool, S.key, bm, prefilter, v, e0, deg, app);
+            if (w == 0) bytes_done += 20ull * item.z;
+            bytes_done += expand<false, false>(G, L, S.j, S.pool, S.key, bm, prefilter, v, e0, deg, app, w, W);
         } else {
             // one heavy vertex: incidences [item.z, item.w) of vertex item.y
             bytes_done += expand<false, true>(G, L, S.j, S.pool, S.key, bm, prefilter, item.y, item.z,
-                                              item.w - item.z, app);
+                                              item.w - item.z, app, w, W);
         }
     }
     if (lane == 0 && bytes_done) atomicAdd(&a.ctr[kBytesB], bytes_done);
@@ -1400,10 +1423,19 @@ int read_ctr(hipStream_t s, const unsigned long long *dev, int idx, uint64_t *ou
     return HYPERIM_OK;
 }
 
-// events[0..1] bracket a phase; events[2 + 2i], events[3 + 2i] bracket the
-// i-th k_expand launch of a superstep batch
+// Events of the RR workspace: [0], [1] start and end of phase A, [2], [3] of
+// the closing k_finish (bundled mode: of the whole group); superstep batch
+// slot b (two batches in flight) owns kBatchEv events from 4 + b * kBatchEv:
+// batch start, batch end (after its counter copy), then a start/end pair per
+// k_expand launch.  Events that time one kernel are stamped by its launch
+// (hipExtLaunchKernelGGL): stream markers between dependent kernels would
+// stall the device for several microseconds each.
+constexpr int kMaxBatch = 64;
+constexpr int kBatchEv = 2 + 2 * kMaxBatch;
+constexpr int kNumEv = 4 + 2 * kBatchEv;
+
 int event_pair(RRWorkspace &ws) {
-    while (ws.events.size() < 2 + 2 * 64) {
+    while (ws.events.size() < (size_t)kNumEv) {
         hipEvent_t e;
         HIM_HIP(hipEventCreate(&e));
         ws.events.push_back(e);
@@ -1411,90 +1443,162 @@ int event_pair(RRWorkspace &ws) {
     return HYPERIM_OK;
 }
 
+hipEvent_t *batch_events(RRWorkspace &ws, uint64_t k) { return &ws.events[4 + (size_t)(k & 1u) * kBatchEv]; }
+
+// Pinned host staging of the RR workspace, in 64-bit words: counter-block
+// copies (two superstep batches in flight, the end of a launch group), the
+// spare-slot cursor, then per-call regions (graph and task descriptors, the
+// pools' new totals).  Copies from and to it are asynchronous; the host
+// touches a region only after waiting for the copy that uses it.
+constexpr size_t kHostCtr = 16;
+constexpr size_t kHostBatch = 0;   // + (k & 1) * kHostCtr for batch k
+constexpr size_t kHostFinal = 2 * kHostCtr;
+constexpr size_t kHostFreeNext = 3 * kHostCtr;
+constexpr size_t kHostFixed = 4 * kHostCtr;
+static_assert(kNumCtr <= kHostCtr, "counter block");
+
+int ensure_host(RRWorkspace &ws, size_t words) {
+    if (ws.host_words >= words) return HYPERIM_OK;
+    if (ws.host) {
+        HIM_HIP(hipDeviceSynchronize());   // no copy may still use the old buffer
+        HIM_HIP(hipHostFree(ws.host));
+    }
+    ws.host = nullptr;
+    ws.host_words = 0;
+    const size_t w = std::max<size_t>(words, 2 * ws.host_words);
+    HIM_HIP(hipHostMalloc((void **)&ws.host, w * sizeof(unsigned long long), hipHostMallocDefault));
+    ws.host_words = w;
+    return HYPERIM_OK;
+}
+
 // One launch group: phase A over `a`'s tasks, then phase B over the sets it
-// deferred.  Per-id outputs land at a.out_base + launch index.
+// deferred, then the deferred sets' output.  Per-id outputs land at
+// a.out_base + launch index.  Supersteps go in batches of steps_per_sync, and
+// the next batch is queued before the host reads the frontier count at the end
+// of the last one, so the device never waits for the host between batches
+// (the batch queued after the frontier ran out finds no work).  The closing
+// counter block lands in ws.host + kHostFinal; `tail` may queue more work
+// behind it, and the call returns after the stream has drained.  With
+// `expect_defer` false the host first checks whether phase A deferred any set.
+template <class Tail>
 int run_launch(RRWorkspace &ws, RRStats &st, const hyperim_tuning &tune, RRArgs &a, const LaunchShape &shape,
-               uint32_t grid, uint32_t grid_b, bool trace, hipStream_t s) {
+               uint32_t grid, uint32_t grid_b, bool expect_defer, bool trace, hipStream_t s, Tail &&tail) {
     unsigned long long *ctr = a.ctr;
+    unsigned long long *h = ws.host;
     // fresh work counter, deferred list and spare-slot cursor (spare slots
     // follow the launched waves' own slots)
-    const unsigned long long first_free = (unsigned long long)grid * kWavesPerWG;
+    h[kHostFreeNext] = (unsigned long long)grid * kWavesPerWG;
     HIM_HIP(hipMemsetAsync(ctr + kWork, 0, sizeof(unsigned long long), s));
     HIM_HIP(hipMemsetAsync(ctr + kDefCount, 0, sizeof(unsigned long long), s));
-    HIM_HIP(hipMemcpyAsync(ctr + kFreeNext, &first_free, sizeof(unsigned long long), hipMemcpyHostToDevice, s));
+    HIM_HIP(hipMemcpyAsync(ctr + kFreeNext, h + kHostFreeNext, sizeof(unsigned long long), hipMemcpyHostToDevice, s));
     HIM_CHECK(event_pair(ws));
-    HIM_HIP(hipEventRecord(ws.events[0], s));
     if (shape.lds)
-        hipLaunchKernelGGL(k_rr_light<true>, dim3(grid), dim3(kWG), 0, s, a);
+        hipExtLaunchKernelGGL(k_rr_light<true>, dim3(grid), dim3(kWG), 0, s, ws.events[0], ws.events[1], 0u, a);
     else
-        hipLaunchKernelGGL(k_rr_light<false>, dim3(grid), dim3(kWG), 0, s, a);
+        hipExtLaunchKernelGGL(k_rr_light<false>, dim3(grid), dim3(kWG), 0, s, ws.events[0], ws.events[1], 0u, a);
     HIM_HIP(hipGetLastError());
-    HIM_HIP(hipEventRecord(ws.events[1], s));
+    st.launches += 1;
+
+    // phase B: supersteps over the deferred sets (LDS-bitmap launches defer none)
+    bool phase_b = !shape.lds;
     uint64_t ndef = 0;
-    HIM_CHECK(read_ctr(s, ctr, kDefCount, &ndef));
+    if (phase_b && !expect_defer) {
+        HIM_HIP(hipMemcpyAsync(h + kHostBatch, ctr, sizeof(unsigned long long) * kNumCtr, hipMemcpyDeviceToHost, s));
+        HIM_HIP(hipStreamSynchronize(s));
+        ndef = h[kHostBatch + kDefCount];
+        phase_b = ndef != 0;
+    }
+    const int batch = trace ? 1 : (int)std::min<uint32_t>(std::max<uint32_t>(tune.steps_per_sync, 1), kMaxBatch);
+    auto account = [&](uint64_t k) -> int {
+        hipEvent_t *E = batch_events(ws, k);
+        float ms = 0.f;
+        HIM_HIP(hipEventElapsedTime(&ms, E[0], E[3 + 2 * (batch - 1)]));   // first k_plan .. last k_expand
+        st.ms_bfs += ms;
+        st.ms_heavy += ms;
+        for (int i = 0; i < batch; ++i) {
+            float me = 0.f;
+            HIM_HIP(hipEventElapsedTime(&me, E[2 + 2 * i], E[3 + 2 * i]));
+            st.ms_expand += me;
+        }
+        st.expand_launches += batch;
+        st.launches += 2 * batch;
+        st.supersteps += batch;
+        return HYPERIM_OK;
+    };
+    bool queued = false;   // a batch is queued but not yet accounted
+    uint64_t k = 0;
+    if (phase_b) {
+        // planning waves: one per deferred set; until the count is known, the
+        // spare slots bound it
+        uint64_t plan_sets = ndef ? ndef : std::max<uint64_t>(shape.slots - (uint64_t)grid * kWavesPerWG, 1);
+        auto issue = [&](uint64_t kb) -> int {
+            hipEvent_t *E = batch_events(ws, kb);
+            const uint32_t plan_grid =
+                (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(div_up(plan_sets, kWavesPerWG), 4096));
+            for (int i = 0; i < batch; ++i) {
+                const uint32_t parity = (uint32_t)((kb * (uint64_t)batch + (uint64_t)i) & 1u);
+                hipExtLaunchKernelGGL(k_plan, dim3(plan_grid), dim3(kWG), 0, s, i == 0 ? E[0] : nullptr, nullptr,
+                                      0u, a, parity);
+                // the launch itself stamps its start and end events (no extra
+                // stream markers between the kernels)
+                hipExtLaunchKernelGGL(k_expand, dim3(grid_b), dim3(kWG), 0, s, E[2 + 2 * i], E[3 + 2 * i], 0u, a,
+                                      parity);
+            }
+            HIM_HIP(hipGetLastError());
+            HIM_HIP(hipMemcpyAsync(h + kHostBatch + (kb & 1u) * kHostCtr, ctr, sizeof(unsigned long long) * kNumCtr,
+                                   hipMemcpyDeviceToHost, s));
+            HIM_HIP(hipEventRecord(E[1], s));
+            return HYPERIM_OK;
+        };
+        HIM_HIP(hipMemsetAsync(ctr + kItems, 0, 2 * sizeof(unsigned long long), s));
+        HIM_CHECK(issue(0));
+        for (;;) {
+            HIM_CHECK(issue(k + 1));   // queued before batch k is read
+            HIM_HIP(hipEventSynchronize(batch_events(ws, k)[1]));
+            const unsigned long long *hb = h + kHostBatch + (k & 1u) * kHostCtr;
+            ndef = hb[kDefCount];
+            plan_sets = std::max<uint64_t>(ndef, 1);
+            const uint32_t last = (uint32_t)(((k + 1) * (uint64_t)batch - 1) & 1u);
+            const uint64_t items = hb[kItems + last];
+            HIM_CHECK(account(k));
+            if (trace)
+                fprintf(stderr, "[hyperim] superstep %llu: %llu items\n",
+                        (unsigned long long)((k + 1) * (uint64_t)batch), (unsigned long long)items);
+            if (items == 0) break;   // the last superstep found no frontier left
+            ++k;
+            // every superstep with items advances some queue head, and a set
+            // holds at most n members, so n supersteps per set bound the loop
+            if (k * (uint64_t)batch > (uint64_t)a.slot_n * std::max<uint64_t>(ndef, 1) + 2 * (uint64_t)batch) {
+                HIM_HIP(hipStreamSynchronize(s));
+                set_error_detail("phase B did not converge");
+                return HYPERIM_EHIP;
+            }
+        }
+        queued = true;   // batch k + 1, which finds no work
+    }
+    if (ndef) {
+        hipExtLaunchKernelGGL(k_finish, dim3((uint32_t)std::min<uint64_t>(ndef, 4096)), dim3(kWG), 0, s,
+                              ws.events[2], ws.events[3], 0u, a, (uint32_t)ndef);
+        HIM_HIP(hipGetLastError());
+        st.launches += 1;
+    }
+    HIM_HIP(hipMemcpyAsync(h + kHostFinal, ctr, sizeof(unsigned long long) * kNumCtr, hipMemcpyDeviceToHost, s));
+    const int rc = tail();
+    HIM_HIP(hipStreamSynchronize(s));
+    HIM_CHECK(rc);
     float ms = 0.f;
     HIM_HIP(hipEventElapsedTime(&ms, ws.events[0], ws.events[1]));
     st.ms_bfs += ms;
     st.ms_light += ms;
-    st.launches += 1;
-    if (ndef == 0) return HYPERIM_OK;
-    // phase B: supersteps over the deferred sets
-    const uint32_t plan_grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(div_up(ndef, kWavesPerWG), 4096));
-    // every superstep with items advances some queue head, and a set holds at
-    // most n members, so n supersteps per set bound the loop
-    const int per_sync = (int)std::max<uint32_t>(tune.steps_per_sync, 1);
-    const uint64_t max_steps = (uint64_t)a.slot_n * ndef + 2 * (uint64_t)per_sync;
-    uint64_t steps = 0;
-    HIM_HIP(hipMemsetAsync(ctr + kItems, 0, 2 * sizeof(unsigned long long), s));
-    for (;;) {
-        if (steps > max_steps) {
-            set_error_detail("phase B did not converge");
-            return HYPERIM_EHIP;
-        }
-        HIM_HIP(hipEventRecord(ws.events[0], s));
-        const int batch = trace ? 1 : per_sync;
-        uint32_t parity = 0;
-        for (int step = 0; step < batch; ++step) {
-            parity = (uint32_t)((steps + step) & 1u);
-            hipLaunchKernelGGL(k_plan, dim3(plan_grid), dim3(kWG), 0, s, a, (uint32_t)ndef, parity);
-            HIM_HIP(hipEventRecord(ws.events[2 + 2 * step], s));
-            hipLaunchKernelGGL(k_expand, dim3(grid_b), dim3(kWG), 0, s, a, parity);
-            HIM_HIP(hipEventRecord(ws.events[3 + 2 * step], s));
-        }
-        steps += batch;
-        HIM_HIP(hipGetLastError());
-        HIM_HIP(hipEventRecord(ws.events[1], s));
-        uint64_t items = 0;
-        HIM_CHECK(read_ctr(s, ctr, kItems + (int)parity, &items));
-        HIM_HIP(hipEventElapsedTime(&ms, ws.events[0], ws.events[1]));
-        for (int step = 0; step < batch; ++step) {
-            float me = 0.f;
-            HIM_HIP(hipEventElapsedTime(&me, ws.events[2 + 2 * step], ws.events[3 + 2 * step]));
-            st.ms_expand += me;
-        }
-        st.expand_launches += batch;
-        if (trace)
-            fprintf(stderr, "[hyperim] superstep %llu: %llu items, %.3f ms\n", (unsigned long long)steps,
-                    (unsigned long long)items, ms);
+    if (queued) HIM_CHECK(account(k + 1));
+    if (ndef) {
+        HIM_HIP(hipEventElapsedTime(&ms, ws.events[2], ws.events[3]));
         st.ms_bfs += ms;
         st.ms_heavy += ms;
-        st.launches += 2 * batch;
-        st.supersteps += batch;
-        if (items == 0) break;   // the last superstep found no frontier left
     }
-    HIM_HIP(hipEventRecord(ws.events[0], s));
-    hipLaunchKernelGGL(k_finish, dim3((uint32_t)std::min<uint64_t>(ndef, 4096)), dim3(kWG), 0, s, a, (uint32_t)ndef);
-    HIM_HIP(hipGetLastError());
-    HIM_HIP(hipEventRecord(ws.events[1], s));
-    HIM_HIP(hipEventSynchronize(ws.events[1]));
-    HIM_HIP(hipEventElapsedTime(&ms, ws.events[0], ws.events[1]));
-    st.ms_bfs += ms;
-    st.ms_heavy += ms;
-    st.launches += 1;
-    st.deferred += ndef;
+    st.deferred += h[kHostFinal + kDefCount];
     return HYPERIM_OK;
 }
-
 
 // Bytes of the bundled-mode state per bundle for a graph of n vertices:
 // seen and nxt masks, frontier and next-level lists, output counts, batch marks.
@@ -1505,9 +1609,11 @@ uint64_t ms_bytes_per_bundle(uint32_t n) {
 
 // One bundled launch group: ids [0, a.count) of one task (all on graph g),
 // bundles of 64 sets grown level by level, then written out in ascending
-// order per set.
+// order per set.  Ends like run_launch: closing counter block in
+// ws.host + kHostFinal, `tail` queued behind it, stream drained.
+template <class Tail>
 int run_ms_launch(RRWorkspace &ws, RRStats &st, const hyperim_tuning &tune, RRArgs &a, const LaunchShape &shape,
-                  hyperim_graph g, const TaskDesc &t, bool trace, hipStream_t s) {
+                  hyperim_graph g, const TaskDesc &t, bool trace, hipStream_t s, Tail &&tail) {
     const uint32_t n = g->n;
     const uint32_t nbundles = (uint32_t)div_up(a.count, kMsSets);
     const uint64_t stride = std::max<uint32_t>(n, 1);
@@ -1557,8 +1663,9 @@ int run_ms_launch(RRWorkspace &ws, RRStats &st, const hyperim_tuning &tune, RRAr
     HIM_HIP(hipMemsetAsync(m.nxt, 0, sizeof(unsigned long long) * nbundles * stride, s));
     HIM_HIP(hipMemsetAsync(m.batch_epoch, 0, sizeof(uint32_t) * div_up(list_cap, kWave), s));
     HIM_HIP(hipMemsetAsync(m.ctr, 0, sizeof(unsigned long long) * kMsNumCtr, s));
-    const unsigned long long one = 1;
-    HIM_HIP(hipMemcpyAsync(m.ctr + kMsLevelDone, &one, sizeof(one), hipMemcpyHostToDevice, s));
+    ws.host[kHostFreeNext + 1] = 1;
+    HIM_HIP(hipMemcpyAsync(m.ctr + kMsLevelDone, ws.host + kHostFreeNext + 1, sizeof(unsigned long long),
+                           hipMemcpyHostToDevice, s));
     HIM_CHECK(event_pair(ws));
     HIM_HIP(hipEventRecord(ws.events[0], s));
     const uint32_t grid_b = shape.grid_b;
@@ -1568,8 +1675,9 @@ int run_ms_launch(RRWorkspace &ws, RRStats &st, const hyperim_tuning &tune, RRAr
     HIM_HIP(hipGetLastError());
     // levels: plan, expand, bookkeeping, advance, bookkeeping; a level whose
     // items overflow the buffer takes several steps
-    const int per_sync = (int)std::max<uint32_t>(tune.steps_per_sync, 1);
+    const int per_sync = (int)std::min<uint32_t>(std::max<uint32_t>(tune.steps_per_sync, 1), kMaxBatch);
     const uint64_t max_steps = 4ull * stride + 64ull + 2ull * (uint64_t)per_sync;
+    hipEvent_t *E = batch_events(ws, 0);
     uint64_t steps = 0;
     float ms = 0.f;
     for (;;) {
@@ -1580,9 +1688,7 @@ int run_ms_launch(RRWorkspace &ws, RRStats &st, const hyperim_tuning &tune, RRAr
         const int batch = trace ? 1 : per_sync;
         for (int k = 0; k < batch; ++k) {
             hipLaunchKernelGGL(k_ms_plan, dim3(grid_b), dim3(kWG), 0, s, m);
-            HIM_HIP(hipEventRecord(ws.events[2 + 2 * k], s));
-            hipLaunchKernelGGL(k_ms_expand, dim3(grid_b), dim3(kWG), 0, s, m);
-            HIM_HIP(hipEventRecord(ws.events[3 + 2 * k], s));
+            hipExtLaunchKernelGGL(k_ms_expand, dim3(grid_b), dim3(kWG), 0, s, E[2 + 2 * k], E[3 + 2 * k], 0u, m);
             hipLaunchKernelGGL(k_ms_ctl_expanded, dim3(1), dim3(1), 0, s, m.ctr);
             hipLaunchKernelGGL(k_ms_advance, dim3(grid_b), dim3(kWG), 0, s, m);
             hipLaunchKernelGGL(k_ms_ctl_advanced, dim3(1), dim3(1), 0, s, m.ctr, list_cap);
@@ -1593,7 +1699,7 @@ int run_ms_launch(RRWorkspace &ws, RRStats &st, const hyperim_tuning &tune, RRAr
         HIM_CHECK(read_ctr(s, m.ctr, kMsDone, &done));
         for (int k = 0; k < batch; ++k) {
             float me = 0.f;
-            HIM_HIP(hipEventElapsedTime(&me, ws.events[2 + 2 * k], ws.events[3 + 2 * k]));
+            HIM_HIP(hipEventElapsedTime(&me, E[2 + 2 * k], E[3 + 2 * k]));
             st.ms_expand += me;
         }
         st.expand_launches += batch;
@@ -1619,9 +1725,13 @@ int run_ms_launch(RRWorkspace &ws, RRStats &st, const hyperim_tuning &tune, RRAr
     hipLaunchKernelGGL(k_ms_record, dim3((uint32_t)div_up(a.count, kWG)), dim3(kWG), 0, s, m, a);
     hipLaunchKernelGGL(k_ms_write, dim3(out_grid), dim3(kWG), 0, s, m, a);
     HIM_HIP(hipGetLastError());
-    HIM_HIP(hipEventRecord(ws.events[1], s));
-    HIM_HIP(hipEventSynchronize(ws.events[1]));
-    HIM_HIP(hipEventElapsedTime(&ms, ws.events[0], ws.events[1]));
+    HIM_HIP(hipMemcpyAsync(ws.host + kHostFinal, a.ctr, sizeof(unsigned long long) * kNumCtr, hipMemcpyDeviceToHost,
+                           s));
+    HIM_HIP(hipEventRecord(ws.events[3], s));
+    const int rc = tail();
+    HIM_HIP(hipStreamSynchronize(s));
+    HIM_CHECK(rc);
+    HIM_HIP(hipEventElapsedTime(&ms, ws.events[0], ws.events[3]));
     st.ms_bfs += ms;
     st.ms_heavy += ms;
     st.launches += 6;
@@ -1632,24 +1742,32 @@ int run_ms_launch(RRWorkspace &ws, RRStats &st, const hyperim_tuning &tune, RRAr
 
 namespace {
 
-// Append the staged sets with group-local indices [first, first + count) to
-// pool p (growing its storage; HYPERIM_ECAPACITY beyond max_entries or a
-// caller buffer).
-int compact_into(RRWorkspace &ws, hyperim_pool p, uint64_t first, uint64_t count, uint64_t max_entries,
+// Appending the staged sets with group-local indices [first, first + count)
+// to pool p takes two steps around a wait for the stream.  compact_scan
+// queues the offsets (an exclusive scan of the sizes from p's total) and the
+// copy of the new total into *total_host.
+int compact_scan(RRWorkspace &ws, hyperim_pool p, uint64_t first, uint64_t count, unsigned long long *total_host,
                  hipStream_t s) {
     if (count == 0) return HYPERIM_OK;
     HIM_CHECK(pool_reserve(p, count, 0, s));
     uint64_t *dst_off = p->off + p->count;
     HIM_CHECK(scan_u32_to_u64(ws.sizes.as<uint32_t>() + first, dst_off, count, p->total, ws.scan_tmp, s));
-    uint64_t new_total = 0;
-    HIM_HIP(hipMemcpyAsync(&new_total, dst_off + count, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
-    HIM_HIP(hipStreamSynchronize(s));
+    HIM_HIP(hipMemcpyAsync(total_host, dst_off + count, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    return HYPERIM_OK;
+}
+
+// compact_move, once the new total is on the host, grows p's storage and
+// moves the members and roots (HYPERIM_ECAPACITY beyond max_entries or a
+// caller buffer; the pool is then unchanged).
+int compact_move(RRWorkspace &ws, hyperim_pool p, uint64_t first, uint64_t count, uint64_t new_total,
+                 uint64_t max_entries, hipStream_t s) {
+    if (count == 0) return HYPERIM_OK;
     if (max_entries && new_total > max_entries) {
         set_error_detail("pool would exceed max_entries");
         return HYPERIM_ECAPACITY;
     }
     HIM_CHECK(pool_reserve(p, count, new_total - p->total, s));
-    dst_off = p->off + p->count;   // storage may have moved
+    uint64_t *dst_off = p->off + p->count;   // storage may have moved
     HIM_HIP(hipMemcpyAsync(p->roots + p->count, ws.roots.as<uint32_t>() + first, sizeof(uint32_t) * count,
                            hipMemcpyDeviceToDevice, s));
     const uint32_t grid = (uint32_t)std::min<uint64_t>(div_up(count, kWave * kWavesPerWG), 65535u);
@@ -1683,6 +1801,14 @@ int rr_generate_into(RRWorkspace &ws, RRStats &st, const std::vector<RRTask> &ta
     }();
     pool_status.assign(tasks.size(), HYPERIM_OK);
     if (tasks.empty()) return HYPERIM_OK;
+    // a launch group compacts its slices after one wait, so each task needs a
+    // pool of its own
+    std::vector<hyperim_pool> sorted(pools);
+    std::sort(sorted.begin(), sorted.end());
+    if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end()) {
+        set_error_detail("two tasks of one generation call share a pool");
+        return HYPERIM_EINVAL;
+    }
     // execution parameters of the first task's graph
     const hyperim_tuning &tune = tasks[0].g->tune;
     // graph descriptors (one per distinct graph)
@@ -1772,7 +1898,16 @@ int rr_generate_into(RRWorkspace &ws, RRStats &st, const std::vector<RRTask> &ta
     a.items = ws.items.as<uint4>();
     HIM_CHECK(ws.graph_desc.reserve(sizeof(GraphDesc) * gdesc.size(), s));
     HIM_CHECK(ws.task_desc.reserve(sizeof(TaskDesc) * tasks.size(), s));
-    HIM_HIP(hipMemcpyAsync(ws.graph_desc.ptr, gdesc.data(), sizeof(GraphDesc) * gdesc.size(), hipMemcpyHostToDevice, s));
+    // pinned staging: fixed words, then the pools' new totals (one per
+    // task), task descriptors, graph descriptors
+    auto words = [](size_t bytes) { return (bytes + sizeof(unsigned long long) - 1) / sizeof(unsigned long long); };
+    const size_t host_totals = kHostFixed;
+    const size_t host_tasks = host_totals + tasks.size();
+    const size_t host_graphs = host_tasks + words(sizeof(TaskDesc) * tasks.size());
+    HIM_CHECK(ensure_host(ws, host_graphs + words(sizeof(GraphDesc) * gdesc.size())));
+    GraphDesc *gstage = reinterpret_cast<GraphDesc *>(ws.host + host_graphs);
+    std::copy(gdesc.begin(), gdesc.end(), gstage);
+    HIM_HIP(hipMemcpyAsync(ws.graph_desc.ptr, gstage, sizeof(GraphDesc) * gdesc.size(), hipMemcpyHostToDevice, s));
     a.graphs = ws.graph_desc.as<GraphDesc>();
 
     struct Slice {
@@ -1842,9 +1977,10 @@ int rr_generate_into(RRWorkspace &ws, RRStats &st, const std::vector<RRTask> &ta
         const uint64_t predicted = (uint64_t)acc + 4 * n_ids + (1u << 20);
         if (ws.stage.bytes < sizeof(uint32_t) * predicted)
             HIM_CHECK(ws.stage.reserve(sizeof(uint32_t) * predicted, s, false));
-        HIM_HIP(hipMemcpyAsync(ws.task_desc.ptr, tdesc.data(), sizeof(TaskDesc) * tdesc.size(), hipMemcpyHostToDevice,
-                               s));
-        HIM_HIP(hipStreamSynchronize(s));   // host vectors are pageable and local
+        // descriptors go through the pinned staging (the previous group has drained)
+        TaskDesc *tstage = reinterpret_cast<TaskDesc *>(ws.host + host_tasks);
+        std::copy(tdesc.begin(), tdesc.end(), tstage);
+        HIM_HIP(hipMemcpyAsync(ws.task_desc.ptr, tstage, sizeof(TaskDesc) * tdesc.size(), hipMemcpyHostToDevice, s));
         a.tasks = ws.task_desc.as<TaskDesc>();
         a.ntasks = (uint32_t)tdesc.size();
         a.count = n_ids;
@@ -1854,6 +1990,23 @@ int rr_generate_into(RRWorkspace &ws, RRStats &st, const std::vector<RRTask> &ta
         a.big_ids = ws.big_ids.as<uint64_t>();
         const uint32_t grid =
             form == 0 ? grid_a : (uint32_t)std::min<uint64_t>(grid_a, div_up(a.count, kWavesPerWG));
+        // a graph whose sets were never deferred before is checked after phase A
+        bool expect_defer = false;
+        for (const Slice &sl : slices) expect_defer |= tasks[sl.task].g->rr_defer != 0.0;
+        // compaction offsets of every slice, queued behind the launch so that
+        // one wait covers both (a launch whose stage overflowed discards them)
+        std::vector<int> scan_rc(slices.size(), HYPERIM_OK);
+        auto scans = [&]() -> int {
+            for (size_t i = 0; i < slices.size(); ++i) {
+                const Slice &sl = slices[i];
+                scan_rc[i] = HYPERIM_OK;
+                if (pool_status[sl.task] != HYPERIM_OK) continue;
+                const int rc = compact_scan(ws, pools[sl.task], sl.lo - lo, sl.hi - sl.lo, ws.host + host_totals + i, s);
+                if (rc == HYPERIM_ECAPACITY) scan_rc[i] = rc;
+                else if (rc != HYPERIM_OK) return rc;
+            }
+            return HYPERIM_OK;
+        };
 
         // ---- run it ----------------------------------------------------
         bool staged = false;
@@ -1863,9 +2016,9 @@ int rr_generate_into(RRWorkspace &ws, RRStats &st, const std::vector<RRTask> &ta
             HIM_HIP(hipMemsetAsync(ctr, 0, sizeof(unsigned long long) * kNumCtr, s));
             RRStats run{};
             if (ms)
-                HIM_CHECK(run_ms_launch(ws, run, tune, a, shape, tasks[slices[0].task].g, tdesc[0], trace, s));
+                HIM_CHECK(run_ms_launch(ws, run, tune, a, shape, tasks[slices[0].task].g, tdesc[0], trace, s, scans));
             else
-                HIM_CHECK(run_launch(ws, run, tune, a, shape, grid, grid_b, trace, s));
+                HIM_CHECK(run_launch(ws, run, tune, a, shape, grid, grid_b, expect_defer, trace, s, scans));
             // time counts every attempt, work only the one that produced the output
             st.ms_bfs += run.ms_bfs;
             st.ms_light += run.ms_light;
@@ -1874,15 +2027,13 @@ int rr_generate_into(RRWorkspace &ws, RRStats &st, const std::vector<RRTask> &ta
             st.supersteps += run.supersteps;
             st.ms_expand += run.ms_expand;
             st.expand_launches += run.expand_launches;
-            uint64_t bump = 0, ba = 0, bb = 0;
-            HIM_CHECK(read_ctr(s, ctr, kBump, &bump));
-            HIM_CHECK(read_ctr(s, ctr, kBytesA, &ba));
-            HIM_CHECK(read_ctr(s, ctr, kBytesB, &bb));
+            const unsigned long long *hf = ws.host + kHostFinal;
+            const uint64_t bump = hf[kBump];
             for (const Slice &sl : slices) tasks[sl.task].g->rr_defer = (double)run.deferred / (double)a.count;
             if (bump <= a.stage_cap) {
                 st.deferred += run.deferred;
-                st.bytes_light += ba;
-                st.bytes_heavy += bb;
+                st.bytes_light += hf[kBytesA];
+                st.bytes_heavy += hf[kBytesB];
                 staged = true;
             } else {
                 HIM_CHECK(ws.stage.reserve(sizeof(uint32_t) * (size_t)(bump + bump / 4 + 1024), s, false));
@@ -1894,11 +2045,14 @@ int rr_generate_into(RRWorkspace &ws, RRStats &st, const std::vector<RRTask> &ta
         }
 
         // ---- compact it ------------------------------------------------
-        for (const Slice &sl : slices) {
+        for (size_t i = 0; i < slices.size(); ++i) {
+            const Slice &sl = slices[i];
             if (pool_status[sl.task] != HYPERIM_OK) continue;
             hyperim_pool p = pools[sl.task];
             const uint64_t before = p->total;
-            const int rc = compact_into(ws, p, sl.lo - lo, sl.hi - sl.lo, max_entries, s);
+            int rc = scan_rc[i];
+            if (rc == HYPERIM_OK)
+                rc = compact_move(ws, p, sl.lo - lo, sl.hi - sl.lo, ws.host[host_totals + i], max_entries, s);
             if (rc == HYPERIM_ECAPACITY) {
                 pool_status[sl.task] = rc;   // this pool is full; the others go on
             } else if (rc != HYPERIM_OK) {
