@@ -10,9 +10,9 @@
 // doubles as the BFS queue, plus a visited bitmap -- in LDS when every graph
 // of the launch is small).  Each frontier batch (up to 64 queued vertices) is
 // expanded in three load-balanced levels -- vertices -> incidences (v, he) ->
-// octets of 8 member positions -- so lanes stay busy under degree and size
-// skew and member ids are read contiguously; two Philox4x32-10 blocks give the
-// 8 coins of an octet; a live channel from an unvisited member sets its bit
+// runs of 4 member positions -- so lanes stay busy under degree and size skew
+// and member ids are read contiguously; one Philox4x32-10 block gives the 4
+// coins of a run; a live channel from an unvisited member sets its bit
 // (atomic OR) and the winner appends it with a ballot-ranked store.  A set
 // whose next batch holds a heavy vertex, or that has used up its incidence
 // budget, is handed over intact (slot, queue head, size) to phase B and the
@@ -23,8 +23,9 @@
 // deferred set's current frontier into work items of bounded cost --
 // segments of consecutive queue entries holding at most a few hundred
 // incidences, or one heavy vertex's incidences in chunks -- and k_expand
-// spreads the items over every wavefront of the GPU, so a single giant set
-// or hub expansion uses the whole chip.  Supersteps repeat until no frontier
+// spreads the items over every wavefront of the GPU (several wavefronts per
+// item when items are fewer than wavefronts), so a single giant set or hub
+// expansion uses the whole chip.  Supersteps repeat until no frontier
 // is left; k_finish sorts and stages each set.  No wave ever waits for
 // another: items only refer to finished supersteps.
 //
@@ -247,50 +248,68 @@ struct SharedAppend {
     }
 };
 
+// Member positions tested per lane and call: kQ Philox blocks of 4 coins.
+// One block per lane and pass keeps every lane's Philox work useful (most
+// hyperedges have few members, so the upper half of an 8-position run is
+// often empty while its block would still cost the whole wave).
+constexpr uint32_t kQ = 1;
+constexpr uint32_t kRun = 4 * kQ;
+
 // Test the channels (he, u -> ve) at member positions [p0, p0 + cm) of one
-// hyperedge (cm <= 8, p0 a multiple of 8) in this lane: the coins are the words
-// of the two Philox blocks of quads p0/4 and p0/4 + 1.  Newly reached members
-// go to `app`.  Every lane of the wave must call it (inactive lanes with
-// active = false).
+// hyperedge (cm <= kRun, p0 a multiple of 4) in this lane: the coins are the
+// words of the Philox blocks of quads p0/4, p0/4 + 1, ...  Newly reached
+// members go to `app`.  Every lane of the wave must call it (inactive lanes
+// with active = false).
 template <bool kLds, class App>
-__device__ __forceinline__ void test_octet(const GraphView &G, uint64_t j, uint32_t pool, uint2 key, uint32_t *bm,
-                                           bool prefilter, bool active, uint32_t he, uint32_t hb, uint32_t p0,
-                                           uint32_t cm, uint32_t ve, uint32_t the, App &app) {
+__device__ __forceinline__ void test_run(const GraphView &G, uint64_t j, uint32_t pool, uint2 key, uint32_t *bm,
+                                         bool prefilter, bool active, uint32_t he, uint32_t hb, uint32_t p0,
+                                         uint32_t cm, uint32_t ve, uint32_t the, App &app) {
     uint32_t u[8];
 #pragma unroll
-    for (uint32_t t = 0; t < 8; ++t) u[t] = (active && t < cm) ? G.he_mem[hb + p0 + t] : ve;
-    uint32_t seen[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
+    for (uint32_t t = 0; t < 8; ++t) u[t] = (t < kRun && active && t < cm) ? G.he_mem[hb + p0 + t] : ve;
+    uint32_t seen[kRun];
+#pragma unroll
+    for (uint32_t t = 0; t < kRun; ++t) seen[t] = 0u;
     if (prefilter) {
         // all mark words in flight together (u[t] is always a vertex id)
 #pragma unroll
-        for (uint32_t t = 0; t < 8; ++t) seen[t] = bm_load<kLds>(bm, u[t] >> 5);
+        for (uint32_t t = 0; t < kRun; ++t) seen[t] = bm_load<kLds>(bm, u[t] >> 5);
     }
-    bool cand[8];
-    bool lo = false, hi = false;
+    bool cand[kRun];
+    bool need[kQ];
 #pragma unroll
-    for (uint32_t t = 0; t < 8; ++t) {
+    for (uint32_t q = 0; q < kQ; ++q) need[q] = false;
+#pragma unroll
+    for (uint32_t t = 0; t < kRun; ++t) {
         cand[t] = u[t] != ve && !(seen[t] & (1u << (u[t] & 31)));
-        if (t < 4) lo |= cand[t];
-        else hi |= cand[t];
+        need[t / 4] |= cand[t];
     }
-    const uint64_t blo = __ballot(lo), bhi = __ballot(hi);
-    if ((blo | bhi) == 0) return;
-    uint4 c0 = make_uint4(0u, 0u, 0u, 0u), c1 = c0;
-    if (blo && lo) c0 = philox4x32_10(coin_counter(j, he, ve, pool, p0 >> 2), key);
-    if (bhi && hi) c1 = philox4x32_10(coin_counter(j, he, ve, pool, (p0 >> 2) + 1u), key);
-    const uint32_t w[8] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
-    bool live[8];
+    bool any = false;
+#pragma unroll
+    for (uint32_t q = 0; q < kQ; ++q) any |= need[q];
+    if (__ballot(any) == 0) return;
+    uint32_t w[kRun];
+#pragma unroll
+    for (uint32_t q = 0; q < kQ; ++q) {
+        uint4 c = make_uint4(0u, 0u, 0u, 0u);
+        if (__ballot(need[q]) != 0 && need[q]) c = philox4x32_10(coin_counter(j, he, ve, pool, (p0 >> 2) + q), key);
+        w[4 * q] = c.x;
+        w[4 * q + 1] = c.y;
+        w[4 * q + 2] = c.z;
+        w[4 * q + 3] = c.w;
+    }
+    bool live[kRun];
     bool any_live = false;
 #pragma unroll
-    for (uint32_t t = 0; t < 8; ++t) {
+    for (uint32_t t = 0; t < kRun; ++t) {
         live[t] = cand[t] && channel_live(w[t], the);
         any_live |= live[t];
     }
-    // with small probabilities most octets have no live channel at all
+    // with small probabilities most runs have no live channel at all
     if (__ballot(any_live) == 0) return;
     uint32_t fresh = 0;
 #pragma unroll
-    for (uint32_t t = 0; t < 8; ++t) {
+    for (uint32_t t = 0; t < kRun; ++t) {
         if (live[t]) {
             const uint32_t bit = 1u << (u[t] & 31);
             if ((atomicOr(&bm[u[t] >> 5], bit) & bit) == 0u) fresh |= 1u << t;
@@ -304,12 +323,12 @@ __device__ __forceinline__ void test_octet(const GraphView &G, uint64_t j, uint3
 // kUniform all lanes pass the same v and e0 and d is the wave's incidence
 // count (one heavy vertex), which needs no owner search.  Every channel
 // (he, u -> v) of those incidences is tested with its coin and newly reached
-// members go to `app`.  Level 3 first tests the first 8 member positions of
-// each lane's own incidence, then spreads the remaining octets of the longer
-// hyperedges over the wave.  W waves (a power of two, wave w of them passing
+// members go to `app`.  Level 3 first tests the first run of kRun member
+// positions of each lane's own incidence, then spreads the remaining runs of
+// the longer hyperedges over the wave.  W waves (a power of two, wave w of them passing
 // w) may share one call: they split the batches of 64 incidences between
-// them, and when there are fewer batches than waves, each batch's octets too;
-// every octet is tested by exactly one of them.  Returns the algorithmic
+// them, and when there are fewer batches than waves, each batch's runs too;
+// every run is tested by exactly one of them.  Returns the algorithmic
 // bytes of the incidences read (12 per incidence plus 4 per member
 // position), each counted by one wave, wave-uniform.
 template <bool kLds, bool kUniform, class App>
@@ -331,7 +350,7 @@ __device__ __forceinline__ uint64_t expand(const GraphView &G, WaveLds &L, uint6
         wave_sync();
     }
     // batch share: batches b = boff, boff + bstride, ...; within a batch,
-    // octets qb = sub_w * 64, (sub_w + sub) * 64, ...  (first octets: sub_w 0)
+    // runs qb = sub_w * 64, (sub_w + sub) * 64, ...  (first runs: sub_w 0)
     const uint32_t nbatch = (D + kWave - 1) / kWave;
     uint32_t bstride = W, sub = 1;
     if (nbatch < W) {
@@ -357,13 +376,13 @@ __device__ __forceinline__ uint64_t expand(const GraphView &G, WaveLds &L, uint6
             }
             hb = G.he_off[he];
             hs = G.he_off[he + 1] - hb;
-            no = th ? (hs + 7u) >> 3 : 0u;   // threshold 0: no channel into vv is live
+            no = th ? (hs + kRun - 1u) / kRun : 0u;   // threshold 0: no channel into vv is live
             if (sub_w == 0) bytes += 12u + 4u * hs;
         }
-        // level 3, first pass: octet 0 of the lane's own incidence
+        // level 3, first pass: run 0 of the lane's own incidence
         if (sub_w == 0)
-            test_octet<kLds>(G, j, pool, key, bm, prefilter, no > 0, he, hb, 0u, min(8u, hs), vv, th, app);
-        // second pass: octets 1.. of the longer hyperedges, flattened over the wave
+            test_run<kLds>(G, j, pool, key, bm, prefilter, no > 0, he, hb, 0u, min(kRun, hs), vv, th, app);
+        // second pass: runs 1.. of the longer hyperedges, flattened over the wave
         const uint32_t rem = no > 1 ? no - 1u : 0u;
         if (__ballot(rem > 0) == 0) continue;
         const uint32_t rscan = wave_incl_scan(rem);
@@ -385,16 +404,16 @@ __device__ __forceinline__ uint64_t expand(const GraphView &G, WaveLds &L, uint6
             if (active) {
                 const uint32_t k = search64(L.in_scan, qg);
                 const uint32_t start = k ? L.in_scan[k - 1] : 0u;
-                p0 = (qg - start + 1u) * 8u;
+                p0 = (qg - start + 1u) * kRun;
                 hee = L.in_he[k];
                 hbk = L.in_hb[k];
-                cm = min(8u, L.in_hs[k] - p0);
+                cm = min(kRun, L.in_hs[k] - p0);
                 if constexpr (!kUniform) {
                     ve = L.in_v[k];
                     the = L.in_thr[k];
                 }
             }
-            test_octet<kLds>(G, j, pool, key, bm, prefilter, active, hee, hbk, p0, cm, ve, the, app);
+            test_run<kLds>(G, j, pool, key, bm, prefilter, active, hee, hbk, p0, cm, ve, the, app);
         }
     }
     wave_sync();
