@@ -126,16 +126,32 @@ struct GreedyParams {
 
 // key = 0 for chosen vertices, else (cnt + 1) << 32 | (~v): the max is the
 // largest count, then the smallest id.
+__device__ __forceinline__ unsigned long long argmax_key(uint32_t c, uint8_t chosen, uint32_t v) {
+    return chosen ? 0ull : (((unsigned long long)c + 1ull) << 32) | (unsigned long long)(0xFFFFFFFFu - v);
+}
+
+// Each thread reads counts and chosen flags of 4 consecutive vertices at a
+// time (cnt and chosen are 256-byte aligned); one atomic max per workgroup.
 __global__ __launch_bounds__(kWG) void k_argmax(const GreedyParams *__restrict__ P, uint32_t round) {
     __shared__ unsigned long long part[kWavesPerWG];
     const uint32_t n = P->n;
-    const uint32_t *__restrict__ cnt = P->cnt;
-    const uint8_t *__restrict__ chosen = P->chosen;
+    const uint4 *__restrict__ cnt4 = reinterpret_cast<const uint4 *>(P->cnt);
+    const uchar4 *__restrict__ chosen4 = reinterpret_cast<const uchar4 *>(P->chosen);
+    const uint32_t n4 = n / 4, stride = gridDim.x * blockDim.x, t = blockIdx.x * blockDim.x + threadIdx.x;
     unsigned long long m = 0;
-    for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
-        const unsigned long long key =
-            chosen[v] ? 0ull : (((unsigned long long)cnt[v] + 1ull) << 32) | (unsigned long long)(0xFFFFFFFFu - v);
-        m = key > m ? key : m;
+    auto take = [&](unsigned long long key) { m = key > m ? key : m; };
+    for (uint32_t q = t; q < n4; q += stride) {
+        const uint4 c = cnt4[q];
+        const uchar4 ch = chosen4[q];
+        const uint32_t v = 4 * q;
+        take(argmax_key(c.x, ch.x, v));
+        take(argmax_key(c.y, ch.y, v + 1));
+        take(argmax_key(c.z, ch.z, v + 2));
+        take(argmax_key(c.w, ch.w, v + 3));
+    }
+    if (t < n - 4 * n4) {
+        const uint32_t v = 4 * n4 + t;
+        take(argmax_key(P->cnt[v], P->chosen[v], v));
     }
     m = wave_max(m);
     if (lane_id() == 0) part[threadIdx.x / kWave] = m;
@@ -304,7 +320,7 @@ int greedy_device(GreedyWorkspace &w, hyperim_graph g, hyperim_pool p, uint64_t 
     // this call's arguments in the device parameter block; the invalidation
     // grid is fixed (grid-stride over a seed's sets) so theta does not change
     // the graph
-    const uint32_t argmax_grid = grid_for(n, kWG, 1024);
+    const uint32_t argmax_grid = grid_for(n, 4 * 2 * kWG, 1024);   // two quads of vertices per thread
     const uint32_t inval_grid = 128;
     GreedyParams hp{p->off, p->mem, w.inv_off.as<uint64_t>(), w.inv.as<uint32_t>(), w.covered.as<uint8_t>(),
                     w.cnt.as<uint32_t>(), w.chosen.as<uint8_t>(), seeds, gains, w.round_big.as<uint64_t>(), best,
