@@ -84,7 +84,13 @@ typedef struct {
     uint64_t max_entries;   /* > 0: fail with HYPERIM_ECAPACITY rather than let
                                a pool exceed this many members                */
     uint32_t flags;         /* HYPERIM_FLAG_* bits                            */
-    uint32_t reserved;
+    uint32_t ahead;         /* a round whose RR generation would add fewer
+                               sets than this (both pools, all queries) also
+                               generates the ids of the following rounds, a
+                               doubling at a time (same sets, same results;
+                               unreached sets are spent work); 0 -> two per
+                               phase-A wavefront of the device, 1 -> off.
+                               Not with theta_fixed or form 1.              */
 } hyperim_options;
 
 #define HYPERIM_FLAG_INCIDENCES 1u  /* fill hyperim_result.incidences (one extra

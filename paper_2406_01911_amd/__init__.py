@@ -41,7 +41,7 @@ class _StrataInfo(C.Structure):
 
 class _Options(C.Structure):
     _fields_ = [("qlog", C.c_uint32), ("form", C.c_uint32), ("theta_fixed", C.c_uint64),
-                ("max_entries", C.c_uint64), ("flags", C.c_uint32), ("reserved", C.c_uint32)]
+                ("max_entries", C.c_uint64), ("flags", C.c_uint32), ("ahead", C.c_uint32)]
 
 
 class _Result(C.Structure):
@@ -297,11 +297,13 @@ def coverage(g: Graph, pool: Pool, theta: int, seeds, stream=None) -> int:
 
 
 def select_seeds(g: Graph, k: int, eps: float, ell: float, seed: int = 0, instance: int = 0, qlog: int = 0,
-                 form: int = 0, theta_fixed: int = 0, max_entries: int = 0, flags: int = 0, stream=None) -> dict:
-    """hyperim_select_seeds (HyperIM_BRR loop) -> dict with seeds, gains and the result fields."""
+                 form: int = 0, theta_fixed: int = 0, max_entries: int = 0, flags: int = 0, stream=None,
+                 ahead: int = 0) -> dict:
+    """hyperim_select_seeds (HyperIM_BRR loop) -> dict with seeds, gains and the result fields.
+    ahead: hyperim_options.ahead (0: device default, 1: off)."""
     seeds = np.zeros(k, np.uint32)
     gains = np.zeros(k, np.uint64)
-    opt = _Options(qlog, form, theta_fixed, max_entries, flags, 0)
+    opt = _Options(qlog, form, theta_fixed, max_entries, flags, ahead)
     res = _Result()
     _check(_lib.hyperim_select_seeds(g._h, k, eps, ell, seed, instance, C.byref(opt), _stream(stream),
                                      _ptr(seeds), _ptr(gains), C.byref(res)))
@@ -326,7 +328,8 @@ def _query(q) -> _Query:
 
 
 def select_seeds_batch(queries, qlog: int = 0, form: int = 0, theta_fixed: int = 0, max_entries: int = 0,
-                       flags: int = 0, stream=None, raise_on_error: bool = True, totals: dict | None = None) -> list:
+                       flags: int = 0, stream=None, raise_on_error: bool = True, totals: dict | None = None,
+                       ahead: int = 0) -> list:
     """hyperim_select_seeds_batch: queries answered together (shared RR launches).
 
     Each query is a dict {graph, k, eps, ell, seed, instance}; returns one dict
@@ -339,7 +342,7 @@ def select_seeds_batch(queries, qlog: int = 0, form: int = 0, theta_fixed: int =
     gains = np.zeros(max(sum(ks), 1), np.uint64)
     res = (_Result * max(len(qs), 1))()
     status = (C.c_int * max(len(qs), 1))()
-    opt = _Options(qlog, form, theta_fixed, max_entries, flags, 0)
+    opt = _Options(qlog, form, theta_fixed, max_entries, flags, ahead)
     tot = _Result()
     rc = _lib.hyperim_select_seeds_batch(arr, len(qs), C.byref(opt), _stream(stream), _ptr(seeds), _ptr(gains),
                                          res, status, C.byref(tot))
@@ -363,9 +366,9 @@ class Session:
     to advance every admitted query by one round, poll for results."""
 
     def __init__(self, hbm_budget: int = 0, qlog: int = 0, form: int = 0, theta_fixed: int = 0,
-                 max_entries: int = 0, flags: int = 0, stream=None):
+                 max_entries: int = 0, flags: int = 0, stream=None, ahead: int = 0):
         load_library()
-        opt = _Options(qlog, form, theta_fixed, max_entries, flags, 0)
+        opt = _Options(qlog, form, theta_fixed, max_entries, flags, ahead)
         h = C.c_void_p()
         _check(_lib.hyperim_session_create(int(hbm_budget), C.byref(opt), _stream(stream), C.byref(h)))
         self._h = h

@@ -351,6 +351,62 @@ struct Engine {
         return HYPERIM_OK;
     }
 
+    // Generate ahead.  A generation call pays the traversal depth of its
+    // deepest sets in supersteps however few sets it holds, and a call with
+    // fewer sets than the device has phase-A wavefronts leaves some idle.  A
+    // round whose call would add fewer than `ahead` sets (both pools, every
+    // pool pair) therefore also takes the ids of the following rounds, a
+    // doubling at a time, up to each pool pair's last admissible round; a
+    // later round then finds its prefix in the pools.  The ids and their sets
+    // are the same, so no result changes; sets a query never reaches are
+    // spent work, at most about one call's worth.  With a finite budget, a
+    // doubling is taken only while its estimated pool and stage bytes fit.
+    int generate_ahead(const std::vector<QueryRun *> &live, const std::vector<PoolPair *> &pps,
+                       std::vector<uint64_t> &target) {
+        if (pps.empty() || opt.ahead == 1) return HYPERIM_OK;
+        uint64_t want = opt.ahead;
+        if (want == 0) {
+            // two sets per phase-A wavefront of the device
+            int device = 0, cus = 0;
+            HIM_HIP(hipGetDevice(&device));
+            HIM_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device));
+            const uint32_t per_cu = pps[0]->g->tune.blocks_a ? pps[0]->g->tune.blocks_a : 4u;
+            want = 2ull * (uint64_t)cus * per_cu * 4u;
+        }
+        std::vector<uint64_t> cap(pps.size(), 0);
+        for (QueryRun *q : live) {
+            const size_t i = (size_t)(std::find(pps.begin(), pps.end(), q->pp) - pps.begin());
+            cap[i] = std::max(cap[i], q->sc.theta1 << (q->sc.i_max ? q->sc.i_max - 1u : 0u));
+        }
+        auto added = [&](const std::vector<uint64_t> &t) {
+            uint64_t a = 0;
+            for (size_t i = 0; i < pps.size(); ++i)
+                for (int x = 0; x < 2; ++x)
+                    if (t[i] > pps[i]->have[x]) a += t[i] - pps[i]->have[x];
+            return a;
+        };
+        size_t used = bounded() ? resident() : 0;
+        for (;;) {
+            const uint64_t now = added(target);
+            if (now == 0 || now >= want) break;
+            std::vector<uint64_t> next(target);
+            double extra = 0.0;
+            for (size_t i = 0; i < pps.size(); ++i) {
+                if (2 * target[i] > cap[i] || 2 * target[i] > kMaxIds) continue;
+                next[i] = 2 * target[i];
+                double m = members_per_id(pps[i]);
+                if (m < 0.0) m = (double)pps[i]->g->n;
+                // both pools' members and offsets, old storage kept while growing, stage
+                extra += 2.0 * (double)(next[i] - target[i]) * (4.0 * m * (2.0 + 1.3) + 36.0);
+            }
+            if (next == target) break;
+            if (bounded() && (double)used + extra > (double)budget) break;
+            used += (size_t)extra;
+            target.swap(next);
+        }
+        return HYPERIM_OK;
+    }
+
     // One round of every query in qs (none done): RR generation for all their
     // pools in one generation pass, then each query's greedy on R1[0, theta),
     // coverage of R2[0, theta) and bound test.  Per-query failures (a pool
@@ -381,6 +437,7 @@ struct Engine {
                 target[i] = std::max(target[i], theta);
             }
         }
+        if (!o.theta_fixed && o.form == 0) HIM_CHECK(generate_ahead(live, pps, target));
         std::vector<RRTask> tasks;
         std::vector<hyperim_pool> dst;
         std::vector<size_t> task_pp;

@@ -90,6 +90,24 @@ def test_batch_matches_alone_and_oracle(hy, small):
         _same(alone[i], ro, f"oracle instance {i}")
 
 
+def test_generate_ahead_keeps_results(hy, small):
+    """Rounds that also generate the ids of later rounds (options.ahead) return
+    the same bytes as rounds that generate exactly their own ids."""
+    _flush("[gpu] generate ahead")
+    for i, c in enumerate(small):
+        off = hy.select_seeds(c["g"], c["k"], c["eps"], c["ell"], seed=c["seed"], instance=c["instance"], ahead=1)
+        for ahead in (0, 1 << 16):
+            r = hy.select_seeds(c["g"], c["k"], c["eps"], c["ell"], seed=c["seed"], instance=c["instance"],
+                                ahead=ahead)
+            _same(off, r, f"instance {i} ahead {ahead}")
+    qs = [_q(c) for c in small]
+    for ahead in (1, 1 << 16):
+        batch = hy.select_seeds_batch(qs, ahead=ahead)
+        for i, (c, b) in enumerate(zip(small, batch)):
+            a = hy.select_seeds(c["g"], c["k"], c["eps"], c["ell"], seed=c["seed"], instance=c["instance"], ahead=1)
+            _same(a, b, f"batch instance {i} ahead {ahead}")
+
+
 def test_batch_shared_pools(hy, small):
     _flush("[gpu] batch shared pools")
     c = small[1]
