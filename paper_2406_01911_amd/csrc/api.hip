@@ -92,6 +92,7 @@ struct DevCtx {
     std::mutex mu;
     RRWorkspace rr;
     GreedyWorkspace gr;
+    PrepWorkspace prep;
 };
 constexpr int kMaxDevices = 256;
 std::mutex g_ctx_mu;
@@ -110,6 +111,7 @@ DeviceLock::DeviceLock(int device) {
     c->mu.lock();
     rr = &c->rr;
     gr = &c->gr;
+    prep = &c->prep;
     lock = c;
 }
 
@@ -147,6 +149,16 @@ void RRWorkspace::release() {
     grid = waves = slots = grid_b = slot_n = slot_words = 0;
 }
 
+size_t PrepWorkspace::bytes() const {
+    size_t b = 0;
+    for (const DevBuf *x : {&k1, &vals, &k2, &wmax, &pc, &tmp, &counts, &base, &isum, &lmax, &hist, &flag, &cnt, &off64, &lists, &bm}) b += x->bytes;
+    return b;
+}
+
+void PrepWorkspace::release() {
+    for (DevBuf *x : {&k1, &vals, &k2, &wmax, &pc, &tmp, &counts, &base, &isum, &lmax, &hist, &flag, &cnt, &off64, &lists, &bm}) x->release();
+}
+
 size_t GreedyWorkspace::bytes() const {
     size_t b = 0;
     for (const DevBuf *x : {&cnt, &inv_off, &cursor, &inv, &covered, &chosen, &best, &out, &big, &round_big, &flags,
@@ -156,14 +168,15 @@ size_t GreedyWorkspace::bytes() const {
 }
 
 SharedBytes shared_bytes() {
-    SharedBytes b{0, 0, 0, 0};
+    SharedBytes b{0, 0, 0, 0, 0};
     int device = 0;
     if (hipGetDevice(&device) != hipSuccess) return b;
     DeviceLock lk(device);
     b.slots = lk.rr->lists.bytes + lk.rr->bitmaps.bytes;
     b.stage = lk.rr->bytes() - b.slots;
     b.greedy = lk.gr->bytes();
-    b.total = b.slots + b.stage + b.greedy;
+    b.prep = lk.prep->bytes();
+    b.total = b.slots + b.stage + b.greedy + b.prep;
     return b;
 }
 
@@ -316,7 +329,8 @@ int hyperim_build_graph(uint32_t n, uint32_t m, const uint32_t *he_off, const ui
         HIM_CHECK(g->he_mem.reserve(sizeof(uint32_t) * std::max<uint64_t>(nnz, 1), s));
         HIM_HIP(hipMemcpyAsync(g->he_off.ptr, he_off, sizeof(uint32_t) * ((size_t)m + 1), kind, s));
         if (nnz) HIM_HIP(hipMemcpyAsync(g->he_mem.ptr, he_mem, sizeof(uint32_t) * (size_t)nnz, kind, s));
-        return graph_build_device(g, s);
+        DeviceLock lk(g->device);
+        return graph_build_device(g, *lk.prep, s);
     }();
     if (rc != HYPERIM_OK) {
         release_graph(g);
@@ -330,7 +344,10 @@ int hyperim_build_graph(uint32_t n, uint32_t m, const uint32_t *he_off, const ui
 int hyperim_stratify(hyperim_graph g, void *stream, hyperim_strata_info *out) {
     if (!g) return HYPERIM_EINVAL;
     g_detail.clear();
-    HIM_CHECK(stratify_device(g, as_stream(stream)));
+    {
+        DeviceLock lk(g->device);
+        HIM_CHECK(stratify_device(g, *lk.prep, as_stream(stream)));
+    }
     if (out) *out = g->info;
     return HYPERIM_OK;
 }
@@ -528,7 +545,7 @@ int hyperim_workspace_info(size_t *bytes) {
     int device = 0;
     HIM_HIP(hipGetDevice(&device));
     DeviceLock lk(device);
-    *bytes = lk.rr->bytes() + lk.gr->bytes();
+    *bytes = lk.rr->bytes() + lk.gr->bytes() + lk.prep->bytes();
     return HYPERIM_OK;
 }
 
@@ -539,6 +556,7 @@ int hyperim_workspace_release(void) {
     HIM_HIP(hipDeviceSynchronize());
     lk.rr->release();
     lk.gr->release();
+    lk.prep->release();
     return HYPERIM_OK;
 }
 

@@ -297,10 +297,10 @@ uint32_t grid_for(uint64_t items, uint32_t block = kBlock, uint32_t cap = 65535u
 
 }  // namespace
 
-int graph_build_device(hyperim_graph g, hipStream_t s) {
+int graph_build_device(hyperim_graph g, PrepWorkspace &w, hipStream_t s) {
     const uint32_t n = g->n, m = g->m;
     const uint64_t nnz = g->nnz;
-    DevBuf flag_b, cnt_b, off64_b, tmp_b;
+    DevBuf &flag_b = w.flag, &cnt_b = w.cnt, &off64_b = w.off64, &tmp_b = w.tmp;
     HIM_CHECK(flag_b.reserve(4 * sizeof(uint32_t), s));
     uint32_t *flag = flag_b.as<uint32_t>();
     HIM_HIP(hipMemsetAsync(flag, 0, 4 * sizeof(uint32_t), s));
@@ -336,7 +336,7 @@ int graph_build_device(hyperim_graph g, hipStream_t s) {
                            g->v_he.as<uint32_t>(), g->c.as<unsigned long long>());
 
     // order every segment by hyperedge id
-    DevBuf lists_b, bm_b;
+    DevBuf &lists_b = w.lists, &bm_b = w.bm;
     HIM_CHECK(lists_b.reserve(sizeof(uint32_t) * 2 * ((size_t)n + 1), s));
     uint32_t *mid_list = lists_b.as<uint32_t>();
     uint32_t *big_list = mid_list + n + 1;

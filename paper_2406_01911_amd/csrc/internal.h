@@ -113,11 +113,24 @@ struct GreedyWorkspace {
     void release();
 };
 
-// The device's shared workspaces (RR generation, greedy / coverage), locked
-// for the holder's lifetime.
+// Workspace of graph building and stratification: one per device, kept
+// between calls (the hash tables take up to 5 GB, and allocating and freeing
+// them per call cost more than a small graph's kernels).
+struct PrepWorkspace {
+    DevBuf k1, vals, k2;                   // (v,u) weight and (v,w) layer hash tables
+    DevBuf wmax, pc, tmp;                  // per-vertex maxima, pair prefix sums, scan blocks
+    DevBuf counts, base, isum, lmax, hist; // strata counts and statistics
+    DevBuf flag, cnt, off64, lists, bm;    // graph build: checks, degrees, offsets, sort lists and marks
+    size_t bytes() const;
+    void release();
+};
+
+// The device's shared workspaces (RR generation, greedy / coverage,
+// stratification), locked for the holder's lifetime.
 struct DeviceLock {
     RRWorkspace *rr;
     GreedyWorkspace *gr;
+    PrepWorkspace *prep;
     void *lock;
     explicit DeviceLock(int device);
     ~DeviceLock();
@@ -186,7 +199,7 @@ int pool_init_owned(hyperim_graph g, hyperim_pool p, hipStream_t s);
 // Current bytes of the device's shared workspaces: RR slots (lists and
 // bitmaps), RR stage and per-set arrays, greedy / coverage.
 struct SharedBytes {
-    size_t slots, stage, greedy, total;
+    size_t slots, stage, greedy, prep, total;
 };
 SharedBytes shared_bytes();
 void pool_clear(hyperim_pool p);                           // empty, keeps storage
@@ -202,10 +215,10 @@ int generate_into(const std::vector<RRTask> &tasks, const std::vector<hyperim_po
                   uint64_t max_entries, hipStream_t s, RRStats &st, std::vector<int> *pool_status);
 
 // ---- launchers (graph.hip) --------------------------------------------------
-int graph_build_device(hyperim_graph g, hipStream_t s);
+int graph_build_device(hyperim_graph g, PrepWorkspace &w, hipStream_t s);
 
 // ---- launchers (stratify.hip) -------------------------------------------------
-int stratify_device(hyperim_graph g, hipStream_t s);
+int stratify_device(hyperim_graph g, PrepWorkspace &w, hipStream_t s);
 
 // ---- launchers (scan.hip) -----------------------------------------------------
 // out[0..count] = exclusive prefix sums of in[0..count) plus init; out[count] = total.

@@ -555,7 +555,7 @@ struct Engine {
         if (bounded()) used = resident();
         std::vector<QueryRun *> run;
         Shared need;
-        const SharedBytes have = bounded() ? shared_bytes() : SharedBytes{0, 0, 0, 0};
+        const SharedBytes have = bounded() ? shared_bytes() : SharedBytes{0, 0, 0, 0, 0};
         size_t shared_so_far = 0;
         auto fits = [&](QueryRun *q) {
             if (!bounded()) return true;

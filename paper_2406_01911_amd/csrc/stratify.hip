@@ -276,7 +276,7 @@ uint32_t grid_for(uint64_t items) {
 
 }  // namespace
 
-int stratify_device(hyperim_graph g, hipStream_t s) {
+int stratify_device(hyperim_graph g, PrepWorkspace &w, hipStream_t s) {
     const uint32_t n = g->n;
     const size_t nn = std::max<uint32_t>(n, 1);
     HIM_CHECK(g->l.reserve(sizeof(uint32_t) * nn, s));
@@ -284,7 +284,7 @@ int stratify_device(hyperim_graph g, hipStream_t s) {
     HIM_CHECK(g->top.reserve(sizeof(uint32_t) * nn, s));
     HIM_CHECK(g->stratum.reserve(nn, s));
     HIM_CHECK(g->P.reserve(sizeof(uint32_t) * nn, s));
-    DevBuf wmax_b, pc_b, tmp_b;
+    DevBuf &wmax_b = w.wmax, &pc_b = w.pc, &tmp_b = w.tmp;
     HIM_CHECK(wmax_b.reserve(sizeof(uint32_t) * nn, s));
     for (DevBuf *b : {&g->l, &g->deg, &g->top, &wmax_b}) HIM_HIP(hipMemsetAsync(b->ptr, 0, sizeof(uint32_t) * nn, s));
 
@@ -308,7 +308,7 @@ int stratify_device(hyperim_graph g, hipStream_t s) {
     }
     if (max_pairs) {
         const uint64_t cap = next_pow2(std::max<uint64_t>(2 * max_pairs, 1024));
-        DevBuf k1, vals, k2;
+        DevBuf &k1 = w.k1, &vals = w.vals, &k2 = w.k2;
         HIM_CHECK(k1.reserve(sizeof(uint64_t) * cap, s));
         HIM_CHECK(vals.reserve(sizeof(uint32_t) * cap, s));
         HIM_CHECK(k2.reserve(sizeof(uint64_t) * cap, s));
@@ -333,7 +333,7 @@ int stratify_device(hyperim_graph g, hipStream_t s) {
 
     // strata, counts, statistics
     const uint32_t tiles = (uint32_t)std::max<uint64_t>(div_up(n, kBlock), 1);
-    DevBuf counts_b, base_b, isum_b, lmax_b, hist_b;
+    DevBuf &counts_b = w.counts, &base_b = w.base, &isum_b = w.isum, &lmax_b = w.lmax, &hist_b = w.hist;
     HIM_CHECK(counts_b.reserve(sizeof(uint32_t) * kNStrata * tiles, s));
     HIM_CHECK(base_b.reserve(sizeof(uint64_t) * (kNStrata * (size_t)tiles + 1), s));
     HIM_CHECK(isum_b.reserve(sizeof(uint64_t) * 3 * tiles, s));
