@@ -118,7 +118,7 @@ DeviceLock::DeviceLock(int device) {
 DeviceLock::~DeviceLock() { static_cast<DevCtx *>(lock)->mu.unlock(); }
 
 void GreedyWorkspace::release() {
-    for (DevBuf *x : {&cnt, &inv_off, &cursor, &inv, &covered, &chosen, &best, &out, &big, &round_big, &flags,
+    for (DevBuf *x : {&cnt, &inv_off, &cursor, &inv, &covered, &chosen, &best, &out, &big, &cursor_big, &flags,
                       &counters, &scan_tmp, &params})
         x->release();
     if (rounds_exec) (void)hipGraphExecDestroy(rounds_exec);
@@ -161,7 +161,7 @@ void PrepWorkspace::release() {
 
 size_t GreedyWorkspace::bytes() const {
     size_t b = 0;
-    for (const DevBuf *x : {&cnt, &inv_off, &cursor, &inv, &covered, &chosen, &best, &out, &big, &round_big, &flags,
+    for (const DevBuf *x : {&cnt, &inv_off, &cursor, &inv, &covered, &chosen, &best, &out, &big, &cursor_big, &flags,
                             &counters, &scan_tmp})
         b += x->bytes;
     return b;

@@ -9,8 +9,9 @@
 // 64-bit max, then invalidates: every not-yet-covered set of the seed is
 // marked covered and each of its members loses one count.  Every set is
 // invalidated at most once, so all rounds together touch each pool entry at
-// most once.  Small sets are processed by wavefronts flattened over 64 sets,
-// sets above kBigSet members by whole workgroups.
+// most once.  Each round is two kernels, the argmax and the invalidation; in
+// the latter small sets are processed by wavefronts flattened over 64 sets,
+// and sets above kBigSet members in chunks spread over the whole grid.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -95,13 +96,15 @@ __global__ __launch_bounds__(kWG) void k_inv_big(const uint64_t *__restrict__ of
                                                   const unsigned long long *__restrict__ count,
                                                   const uint64_t *__restrict__ inv_off, uint32_t *__restrict__ cursor,
                                                   uint32_t *__restrict__ inv) {
+    // big sets fill each vertex's list from its end, so the list is the small
+    // sets (the first cursor_small[u] entries) then the big ones
     const uint64_t nb = *count;
     for (uint64_t b = blockIdx.x; b < nb; b += gridDim.x) {
         const uint64_t j = list[b];
         for (uint64_t e = off[j] + threadIdx.x; e < off[j + 1]; e += blockDim.x) {
             const uint32_t u = mem[e];
             const uint32_t pos = atomicAdd(&cursor[u], 1u);
-            inv[inv_off[u] + pos] = (uint32_t)j;
+            inv[inv_off[u + 1] - 1u - pos] = (uint32_t)j;
         }
     }
 }
@@ -113,14 +116,13 @@ struct GreedyParams {
     const uint32_t *mem;
     const uint64_t *inv_off;
     const uint32_t *inv;
-    uint8_t *covered;
+    const uint32_t *nsmall;          // per vertex: small sets at the front of its list
+    uint32_t *covered;               // per set: 0, or the round that covered it, plus one
     uint32_t *cnt;
     uint8_t *chosen;
     uint32_t *seeds;
     unsigned long long *gains;
-    uint64_t *round_big;
     unsigned long long *best;        // k argmax keys
-    unsigned long long *nbig_round;  // k counters
     uint32_t n;
 };
 
@@ -163,8 +165,19 @@ __global__ __launch_bounds__(kWG) void k_argmax(const GreedyParams *__restrict__
     }
 }
 
+// Members of a big set per work chunk in the invalidation.
+constexpr uint32_t kBigChunk = 1024;
+
+// Round `round`: record the argmax seed s, then invalidate every set of s
+// not covered before this round.  Small sets (the front of s's list) go one
+// per lane, flattened over the wave; big sets are cut into chunks of
+// kBigChunk members spread over every wave of the grid.  A big set's chunks
+// agree that it is new in this round through its stamp: covered[j] is 0 or
+// round + 1 (set by the first chunk to look) for a set covered now, an older
+// round otherwise.
 __global__ __launch_bounds__(kWG) void k_invalidate(const GreedyParams *__restrict__ P, uint32_t round) {
     __shared__ FlatLds lds[kWavesPerWG];
+    __shared__ uint32_t csum[kWavesPerWG][kWave];
     const unsigned long long key = P->best[round];
     const uint32_t s = 0xFFFFFFFFu - (uint32_t)key;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -175,37 +188,60 @@ __global__ __launch_bounds__(kWG) void k_invalidate(const GreedyParams *__restri
     const uint64_t *__restrict__ off = P->off;
     const uint32_t *__restrict__ mem = P->mem;
     const uint32_t *__restrict__ inv = P->inv;
-    uint8_t *__restrict__ covered = P->covered;
+    uint32_t *__restrict__ covered = P->covered;
     uint32_t *__restrict__ cnt = P->cnt;
-    const uint64_t x0 = P->inv_off[s], x1 = P->inv_off[s + 1];
-    const uint32_t wv = threadIdx.x / kWave;
-    const uint64_t waves = (uint64_t)gridDim.x * kWavesPerWG;
-    for (uint64_t grp = (uint64_t)blockIdx.x * kWavesPerWG + wv; x0 + grp * kWave < x1; grp += waves) {
-        const uint64_t x = x0 + grp * kWave + lane_id();
+    const uint32_t stamp = round + 1u;
+    const uint64_t x0 = P->inv_off[s], xs = x0 + P->nsmall[s], x1 = P->inv_off[s + 1];
+    const uint32_t wv = threadIdx.x / kWave, lane = lane_id();
+    const uint64_t gw = (uint64_t)blockIdx.x * kWavesPerWG + wv, waves = (uint64_t)gridDim.x * kWavesPerWG;
+    // small sets: each appears once in s's list, so its lane owns it
+    for (uint64_t grp = gw; x0 + grp * kWave < xs; grp += waves) {
+        const uint64_t x = x0 + grp * kWave + lane;
         uint32_t len = 0;
         uint64_t beg = 0;
-        if (x < x1) {
+        if (x < xs) {
             const uint32_t j = inv[x];
-            if (!covered[j]) {
-                covered[j] = 1;
+            if (covered[j] == 0u) {
+                covered[j] = stamp;
                 beg = off[j];
-                const uint64_t sz = off[j + 1] - beg;
-                if (sz > kBigSet) P->round_big[atomicAdd(P->nbig_round + round, 1ull)] = j;
-                else len = (uint32_t)sz;
+                len = (uint32_t)(off[j + 1] - beg);
             }
         }
         wave_flat(lds[wv], len, beg, 0, [&](uint32_t, uint64_t e, uint64_t) { atomicSub(&cnt[mem[e]], 1u); });
     }
-}
-
-__global__ __launch_bounds__(kWG) void k_invalidate_big(const GreedyParams *__restrict__ P, uint32_t round) {
-    const uint64_t nb = P->nbig_round[round];
-    const uint64_t *__restrict__ off = P->off;
-    const uint32_t *__restrict__ mem = P->mem;
-    uint32_t *__restrict__ cnt = P->cnt;
-    for (uint64_t b = blockIdx.x; b < nb; b += gridDim.x) {
-        const uint64_t j = P->round_big[b];
-        for (uint64_t e = off[j] + threadIdx.x; e < off[j + 1]; e += blockDim.x) atomicSub(&cnt[mem[e]], 1u);
+    // big sets, 64 at a time: every wave numbers their chunks the same way
+    // and takes the chunks c with c = gw (mod waves)
+    uint64_t run = 0;   // chunks of earlier batches
+    for (uint64_t b0 = xs; b0 < x1; b0 += kWave) {
+        const uint64_t x = b0 + lane;
+        uint32_t nc = 0, j = 0;
+        if (x < x1) {
+            j = inv[x];
+            const uint32_t c = __hip_atomic_load(&covered[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (c == 0u || c == stamp) nc = (uint32_t)div_up(off[j + 1] - off[j], kBigChunk);
+        }
+        const uint32_t incl = wave_incl_scan(nc);
+        const uint32_t total = wave_bcast(incl, kWave - 1);
+        wave_sync();
+        csum[wv][lane] = incl;
+        wave_sync();
+        // first chunk index >= run owned by this wave
+        uint64_t c = run + ((gw + waves - run % waves) % waves);
+        for (; c < run + total; c += waves) {
+            const uint32_t r = (uint32_t)(c - run);
+            const uint32_t k = search64(csum[wv], r);
+            const uint32_t first = k ? csum[wv][k - 1] : 0u;
+            const uint32_t jk = (uint32_t)__shfl((int)j, (int)k, kWave);
+            if (lane == 0) {
+                const uint32_t old = atomicCAS(&covered[jk], 0u, stamp);
+                (void)old;   // 0 or stamp: this chunk's set is new in this round
+            }
+            const uint64_t b = off[jk] + (uint64_t)(r - first) * kBigChunk;
+            const uint64_t e1 = min(b + kBigChunk, off[jk + 1]);
+            for (uint64_t e = b + lane; e < e1; e += kWave) atomicSub(&cnt[mem[e]], 1u);
+        }
+        run += total;
+        wave_sync();
     }
 }
 
@@ -288,22 +324,22 @@ int greedy_device(GreedyWorkspace &w, hyperim_graph g, hyperim_pool p, uint64_t 
     HIM_CHECK(w.inv_off.reserve(sizeof(uint64_t) * ((size_t)n + 1), s));
     HIM_CHECK(w.cursor.reserve(sizeof(uint32_t) * n, s));
     HIM_CHECK(w.inv.reserve(sizeof(uint32_t) * std::max<uint64_t>(entries, 1), s));
-    HIM_CHECK(w.covered.reserve(std::max<uint64_t>(theta, 1), s));
+    HIM_CHECK(w.covered.reserve(sizeof(uint32_t) * std::max<uint64_t>(theta, 1), s));
     HIM_CHECK(w.chosen.reserve(n, s));
-    HIM_CHECK(w.best.reserve(sizeof(unsigned long long) * k + 2 * sizeof(unsigned long long) * (k + 1), s));
+    HIM_CHECK(w.best.reserve(sizeof(unsigned long long) * ((size_t)k + 1), s));
     HIM_CHECK(w.out.reserve(sizeof(uint32_t) * k + sizeof(uint64_t) * k, s));
     HIM_CHECK(w.big.reserve(sizeof(uint64_t) * std::max<uint64_t>(theta, 1), s));
-    HIM_CHECK(w.round_big.reserve(sizeof(uint64_t) * std::max<uint64_t>(theta, 1), s));
+    HIM_CHECK(w.cursor_big.reserve(sizeof(uint32_t) * n, s));
     unsigned long long *best = w.best.as<unsigned long long>();
-    unsigned long long *nbig_round = best + k;          // k counters
-    unsigned long long *nbig_all = best + 2 * k + 1;    // one counter
+    unsigned long long *nbig_all = best + k;   // big sets of the pool prefix
     uint32_t *seeds = w.out.as<uint32_t>();
     unsigned long long *gains = reinterpret_cast<unsigned long long *>(w.out.as<char>() + sizeof(uint32_t) * k);
     HIM_HIP(hipMemsetAsync(w.cnt.ptr, 0, sizeof(uint32_t) * n, s));
     HIM_HIP(hipMemsetAsync(w.cursor.ptr, 0, sizeof(uint32_t) * n, s));
-    HIM_HIP(hipMemsetAsync(w.covered.ptr, 0, std::max<uint64_t>(theta, 1), s));
+    HIM_HIP(hipMemsetAsync(w.covered.ptr, 0, sizeof(uint32_t) * std::max<uint64_t>(theta, 1), s));
+    HIM_HIP(hipMemsetAsync(w.cursor_big.ptr, 0, sizeof(uint32_t) * n, s));
     HIM_HIP(hipMemsetAsync(w.chosen.ptr, 0, n, s));
-    HIM_HIP(hipMemsetAsync(best, 0, sizeof(unsigned long long) * (3 * (size_t)k + 2), s));
+    HIM_HIP(hipMemsetAsync(best, 0, sizeof(unsigned long long) * ((size_t)k + 1), s));
 
     if (entries)
         hipLaunchKernelGGL(k_hist, dim3(grid_for(entries, kWG, 8192)), dim3(kWG), 0, s, p->mem, entries,
@@ -314,17 +350,16 @@ int greedy_device(GreedyWorkspace &w, hyperim_graph g, hyperim_pool p, uint64_t 
         hipLaunchKernelGGL(k_inv_small, dim3(grid_for(theta, kWG, 8192)), dim3(kWG), 0, s, p->off, p->mem, theta,
                            w.inv_off.as<uint64_t>(), w.cursor.as<uint32_t>(), w.inv.as<uint32_t>());
         hipLaunchKernelGGL(k_inv_big, dim3(1024), dim3(kWG), 0, s, p->off, p->mem, w.big.as<uint64_t>(), nbig_all,
-                           w.inv_off.as<uint64_t>(), w.cursor.as<uint32_t>(), w.inv.as<uint32_t>());
+                           w.inv_off.as<uint64_t>(), w.cursor_big.as<uint32_t>(), w.inv.as<uint32_t>());
     }
     // the k rounds: one captured graph per (k, argmax grid), replayed with
     // this call's arguments in the device parameter block; the invalidation
     // grid is fixed (grid-stride over a seed's sets) so theta does not change
     // the graph
     const uint32_t argmax_grid = grid_for(n, 4 * 2 * kWG, 1024);   // two quads of vertices per thread
-    const uint32_t inval_grid = 128;
-    GreedyParams hp{p->off, p->mem, w.inv_off.as<uint64_t>(), w.inv.as<uint32_t>(), w.covered.as<uint8_t>(),
-                    w.cnt.as<uint32_t>(), w.chosen.as<uint8_t>(), seeds, gains, w.round_big.as<uint64_t>(), best,
-                    nbig_round, n};
+    const uint32_t inval_grid = 256;
+    GreedyParams hp{p->off,   p->mem, w.inv_off.as<uint64_t>(), w.inv.as<uint32_t>(), w.cursor.as<uint32_t>(),
+                    w.covered.as<uint32_t>(), w.cnt.as<uint32_t>(), w.chosen.as<uint8_t>(), seeds, gains, best, n};
     HIM_CHECK(w.params.reserve(sizeof(GreedyParams), s));
     static_assert(sizeof(GreedyParams) <= sizeof(w.params_host), "parameter block");
     memcpy(w.params_host, &hp, sizeof(hp));
@@ -340,7 +375,6 @@ int greedy_device(GreedyWorkspace &w, hyperim_graph g, hyperim_pool p, uint64_t 
         for (uint32_t i = 0; i < k; ++i) {
             hipLaunchKernelGGL(k_argmax, dim3(argmax_grid), dim3(kWG), 0, w.capture, P, i);
             hipLaunchKernelGGL(k_invalidate, dim3(inval_grid), dim3(kWG), 0, w.capture, P, i);
-            hipLaunchKernelGGL(k_invalidate_big, dim3(256), dim3(kWG), 0, w.capture, P, i);
         }
         HIM_HIP(hipStreamEndCapture(w.capture, &graph));
         const hipError_t e = hipGraphInstantiate(&w.rounds_exec, graph, nullptr, nullptr, 0);

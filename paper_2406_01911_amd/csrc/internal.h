@@ -93,12 +93,12 @@ struct GreedyWorkspace {
     DevBuf inv_off;   // (n+1) uint64
     DevBuf cursor;    // n uint32
     DevBuf inv;       // entries uint32 (set ids)
-    DevBuf covered;   // theta uint8
+    DevBuf covered;   // theta uint32: 0 or covering round + 1
     DevBuf chosen;    // n uint8
     DevBuf best;      // k uint64 argmax keys + per-round counters
     DevBuf out;       // k seeds (uint32) then k gains (uint64)
     DevBuf big;       // sets above the big-set size (whole pool prefix)
-    DevBuf round_big; // big sets covered in one round
+    DevBuf cursor_big; // n uint32: big sets per vertex (inverted index)
     DevBuf flags;     // n uint8 seed marks (coverage)
     DevBuf counters;  // coverage counters
     DevBuf scan_tmp;
