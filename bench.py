@@ -179,13 +179,14 @@ def main():
         del src, dst
 
     def timed(steps, warmup, form):
+        # expansion launches timed by events they stamp, inside the timed region
         for _ in range(warmup):
-            step(form=form)
+            step(flags=hy.FLAG_KERNEL_TIMES, form=form)
         torch.cuda.synchronize()
         out = []
         t0 = time.perf_counter()
         for _ in range(steps):
-            out.append(step(form=form))
+            out.append(step(flags=hy.FLAG_KERNEL_TIMES, form=form))
         torch.cuda.synchronize()
         return out, time.perf_counter() - t0
 

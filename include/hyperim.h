@@ -93,6 +93,10 @@ typedef struct {
                                Not with theta_fixed or form 1.              */
 } hyperim_options;
 
+#define HYPERIM_FLAG_KERNEL_TIMES 2u /* time every expansion-kernel launch
+                                         with events its launch stamps
+                                         (fills ms_expand; costs a few
+                                         percent of a small query)       */
 #define HYPERIM_FLAG_INCIDENCES 1u  /* fill hyperim_result.incidences (one extra
                                        pass over the final pools)            */
 
@@ -125,8 +129,9 @@ typedef struct {
     uint64_t supersteps;    /* grid-wide supersteps launched                   */
     uint64_t bytes_light;   /* algorithmic bytes expanded by the per-set phase */
     uint64_t bytes_heavy;   /* algorithmic bytes expanded by the grid-wide one */
-    double ms_expand;       /* part of ms_heavy spent in the expansion kernel
-                               itself (HIP events around each launch)          */
+    double ms_expand;       /* with HYPERIM_FLAG_KERNEL_TIMES: part of ms_heavy
+                               spent in the expansion kernel
+                               itself (events each launch stamps)          */
     uint64_t expand_launches; /* its launches (one per superstep)              */
 } hyperim_result;
 

@@ -22,6 +22,7 @@ PENDING = 1
 MODEL_CONST, MODEL_WC = 0, 1
 NSTRATA = 8
 FLAG_INCIDENCES = 1
+FLAG_KERNEL_TIMES = 2
 
 
 class HyperIMError(RuntimeError):

@@ -235,7 +235,8 @@ size_t pool_bytes(const hyperim_pool_s &p) { return p.off_b.bytes + p.roots_b.by
 // Generate the tasks in one go and append each task's sets to its pool
 // (tasks with an empty id range are skipped).
 int generate_into(const std::vector<RRTask> &tasks, const std::vector<hyperim_pool> &pools, uint32_t qlog, int form,
-                  uint64_t max_entries, hipStream_t s, RRStats &st, std::vector<int> *pool_status) {
+                  uint64_t max_entries, hipStream_t s, RRStats &st, std::vector<int> *pool_status,
+                  bool time_kernels) {
     std::vector<RRTask> live;
     std::vector<hyperim_pool> dst;
     std::vector<size_t> which;
@@ -254,7 +255,8 @@ int generate_into(const std::vector<RRTask> &tasks, const std::vector<hyperim_po
     DeviceLock lk(device);
     std::vector<int> status;
     const uint64_t stage_budget = (uint64_t)std::max<uint32_t>(live[0].g->tune.stage_mib, 64) << 20;
-    HIM_CHECK(rr_generate_into(*lk.rr, st, live, dst, qlog, form, max_entries, stage_budget, s, status));
+    HIM_CHECK(rr_generate_into(*lk.rr, st, live, dst, qlog, form, max_entries, stage_budget, s, status,
+                               time_kernels));
     int first_fail = HYPERIM_OK;
     for (size_t i = 0; i < live.size(); ++i) {
         if (was_empty[i] && dst[i]->count) dst[i]->id_begin = live[i].id_begin;

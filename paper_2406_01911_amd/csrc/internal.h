@@ -211,8 +211,10 @@ struct RRTask;
 // ranges skipped).  With pool_status, a pool that would exceed max_entries
 // gets HYPERIM_ECAPACITY there and the others are still filled; without it
 // that status is returned.
+// time_kernels: time every expansion-kernel launch (RRStats::ms_expand).
 int generate_into(const std::vector<RRTask> &tasks, const std::vector<hyperim_pool> &pools, uint32_t qlog, int form,
-                  uint64_t max_entries, hipStream_t s, RRStats &st, std::vector<int> *pool_status);
+                  uint64_t max_entries, hipStream_t s, RRStats &st, std::vector<int> *pool_status,
+                  bool time_kernels = false);
 
 // ---- launchers (graph.hip) --------------------------------------------------
 int graph_build_device(hyperim_graph g, PrepWorkspace &w, hipStream_t s);
@@ -247,7 +249,7 @@ struct RRTask {
 size_t rr_slot_bytes(uint32_t n_max);
 int rr_generate_into(RRWorkspace &ws, RRStats &st, const std::vector<RRTask> &tasks,
                      const std::vector<hyperim_pool> &pools, uint32_t qlog, int form, uint64_t max_entries,
-                     uint64_t stage_budget, hipStream_t s, std::vector<int> &pool_status);
+                     uint64_t stage_budget, hipStream_t s, std::vector<int> &pool_status, bool time_kernels);
 // Make room in pool p for `ids` more ids and `entries` more members.
 int pool_reserve(hyperim_pool p, uint64_t ids, uint64_t entries, hipStream_t s);
 // Sums of weight[] (incidences) and bytesw[] (algorithmic bytes) over the

@@ -1446,7 +1446,8 @@ int read_ctr(hipStream_t s, const unsigned long long *dev, int idx, uint64_t *ou
 // the closing k_finish (bundled mode: of the whole group); superstep batch
 // slot b (two batches in flight) owns kBatchEv events from 4 + b * kBatchEv:
 // batch start, batch end (after its counter copy), then a start/end pair per
-// k_expand launch.  Events that time one kernel are stamped by its launch
+// k_expand launch when kernel times are asked for.  Events that time one
+// kernel are stamped by its launch
 // (hipExtLaunchKernelGGL): stream markers between dependent kernels would
 // stall the device for several microseconds each.
 constexpr int kMaxBatch = 64;
@@ -1501,7 +1502,8 @@ int ensure_host(RRWorkspace &ws, size_t words) {
 // `expect_defer` false the host first checks whether phase A deferred any set.
 template <class Tail>
 int run_launch(RRWorkspace &ws, RRStats &st, const hyperim_tuning &tune, RRArgs &a, const LaunchShape &shape,
-               uint32_t grid, uint32_t grid_b, bool expect_defer, bool trace, hipStream_t s, Tail &&tail) {
+               uint32_t grid, uint32_t grid_b, bool expect_defer, bool trace, bool time_kernels, hipStream_t s,
+               Tail &&tail) {
     unsigned long long *ctr = a.ctr;
     unsigned long long *h = ws.host;
     // fresh work counter, deferred list and spare-slot cursor (spare slots
@@ -1531,10 +1533,11 @@ int run_launch(RRWorkspace &ws, RRStats &st, const hyperim_tuning &tune, RRArgs 
     auto account = [&](uint64_t k) -> int {
         hipEvent_t *E = batch_events(ws, k);
         float ms = 0.f;
-        HIM_HIP(hipEventElapsedTime(&ms, E[0], E[3 + 2 * (batch - 1)]));   // first k_plan .. last k_expand
+        // first k_plan .. last k_expand (or the batch's counter copy)
+        HIM_HIP(hipEventElapsedTime(&ms, E[0], time_kernels ? E[3 + 2 * (batch - 1)] : E[1]));
         st.ms_bfs += ms;
         st.ms_heavy += ms;
-        for (int i = 0; i < batch; ++i) {
+        for (int i = 0; time_kernels && i < batch; ++i) {
             float me = 0.f;
             HIM_HIP(hipEventElapsedTime(&me, E[2 + 2 * i], E[3 + 2 * i]));
             st.ms_expand += me;
@@ -1558,10 +1561,13 @@ int run_launch(RRWorkspace &ws, RRStats &st, const hyperim_tuning &tune, RRArgs 
                 const uint32_t parity = (uint32_t)((kb * (uint64_t)batch + (uint64_t)i) & 1u);
                 hipExtLaunchKernelGGL(k_plan, dim3(plan_grid), dim3(kWG), 0, s, i == 0 ? E[0] : nullptr, nullptr,
                                       0u, a, parity);
-                // the launch itself stamps its start and end events (no extra
+                // timed: the launch itself stamps its start and end events (no
                 // stream markers between the kernels)
-                hipExtLaunchKernelGGL(k_expand, dim3(grid_b), dim3(kWG), 0, s, E[2 + 2 * i], E[3 + 2 * i], 0u, a,
-                                      parity);
+                if (time_kernels)
+                    hipExtLaunchKernelGGL(k_expand, dim3(grid_b), dim3(kWG), 0, s, E[2 + 2 * i], E[3 + 2 * i], 0u,
+                                          a, parity);
+                else
+                    hipLaunchKernelGGL(k_expand, dim3(grid_b), dim3(kWG), 0, s, a, parity);
             }
             HIM_HIP(hipGetLastError());
             HIM_HIP(hipMemcpyAsync(h + kHostBatch + (kb & 1u) * kHostCtr, ctr, sizeof(unsigned long long) * kNumCtr,
@@ -1632,7 +1638,7 @@ uint64_t ms_bytes_per_bundle(uint32_t n) {
 // ws.host + kHostFinal, `tail` queued behind it, stream drained.
 template <class Tail>
 int run_ms_launch(RRWorkspace &ws, RRStats &st, const hyperim_tuning &tune, RRArgs &a, const LaunchShape &shape,
-                  hyperim_graph g, const TaskDesc &t, bool trace, hipStream_t s, Tail &&tail) {
+                  hyperim_graph g, const TaskDesc &t, bool trace, bool time_kernels, hipStream_t s, Tail &&tail) {
     const uint32_t n = g->n;
     const uint32_t nbundles = (uint32_t)div_up(a.count, kMsSets);
     const uint64_t stride = std::max<uint32_t>(n, 1);
@@ -1707,7 +1713,10 @@ int run_ms_launch(RRWorkspace &ws, RRStats &st, const hyperim_tuning &tune, RRAr
         const int batch = trace ? 1 : per_sync;
         for (int k = 0; k < batch; ++k) {
             hipLaunchKernelGGL(k_ms_plan, dim3(grid_b), dim3(kWG), 0, s, m);
-            hipExtLaunchKernelGGL(k_ms_expand, dim3(grid_b), dim3(kWG), 0, s, E[2 + 2 * k], E[3 + 2 * k], 0u, m);
+            if (time_kernels)
+                hipExtLaunchKernelGGL(k_ms_expand, dim3(grid_b), dim3(kWG), 0, s, E[2 + 2 * k], E[3 + 2 * k], 0u, m);
+            else
+                hipLaunchKernelGGL(k_ms_expand, dim3(grid_b), dim3(kWG), 0, s, m);
             hipLaunchKernelGGL(k_ms_ctl_expanded, dim3(1), dim3(1), 0, s, m.ctr);
             hipLaunchKernelGGL(k_ms_advance, dim3(grid_b), dim3(kWG), 0, s, m);
             hipLaunchKernelGGL(k_ms_ctl_advanced, dim3(1), dim3(1), 0, s, m.ctr, list_cap);
@@ -1716,7 +1725,7 @@ int run_ms_launch(RRWorkspace &ws, RRStats &st, const hyperim_tuning &tune, RRAr
         steps += batch;
         uint64_t done = 0;
         HIM_CHECK(read_ctr(s, m.ctr, kMsDone, &done));
-        for (int k = 0; k < batch; ++k) {
+        for (int k = 0; time_kernels && k < batch; ++k) {
             float me = 0.f;
             HIM_HIP(hipEventElapsedTime(&me, E[2 + 2 * k], E[3 + 2 * k]));
             st.ms_expand += me;
@@ -1811,7 +1820,7 @@ size_t rr_slot_bytes(uint32_t n_max) {
 
 int rr_generate_into(RRWorkspace &ws, RRStats &st, const std::vector<RRTask> &tasks,
                      const std::vector<hyperim_pool> &pools, uint32_t qlog, int form, uint64_t max_entries,
-                     uint64_t stage_budget, hipStream_t s, std::vector<int> &pool_status) {
+                     uint64_t stage_budget, hipStream_t s, std::vector<int> &pool_status, bool time_kernels) {
     // HYPERIM_TRACE=1: synchronise after every grid-wide superstep and report
     // its item count and time on stderr (diagnostics; same results)
     static const bool trace = [] {
@@ -2035,9 +2044,11 @@ int rr_generate_into(RRWorkspace &ws, RRStats &st, const std::vector<RRTask> &ta
             HIM_HIP(hipMemsetAsync(ctr, 0, sizeof(unsigned long long) * kNumCtr, s));
             RRStats run{};
             if (ms)
-                HIM_CHECK(run_ms_launch(ws, run, tune, a, shape, tasks[slices[0].task].g, tdesc[0], trace, s, scans));
+                HIM_CHECK(run_ms_launch(ws, run, tune, a, shape, tasks[slices[0].task].g, tdesc[0], trace,
+                                        time_kernels, s, scans));
             else
-                HIM_CHECK(run_launch(ws, run, tune, a, shape, grid, grid_b, expect_defer, trace, s, scans));
+                HIM_CHECK(run_launch(ws, run, tune, a, shape, grid, grid_b, expect_defer, trace, time_kernels, s,
+                                     scans));
             // time counts every attempt, work only the one that produced the output
             st.ms_bfs += run.ms_bfs;
             st.ms_light += run.ms_light;
