@@ -25,7 +25,9 @@
 // incidences, or one heavy vertex's incidences in chunks -- and k_expand
 // spreads the items over every wavefront of the GPU (several wavefronts per
 // item when items are fewer than wavefronts), so a single giant set or hub
-// expansion uses the whole chip.  Supersteps repeat until no frontier
+// expansion uses the whole chip; a wavefront that found only a few light
+// members expands them itself right away (continuation) instead of leaving
+// one more thin level to the next superstep.  Supersteps repeat until no frontier
 // is left; k_finish sorts and stages each set.  No wave ever waits for
 // another: items only refer to finished supersteps.
 //
@@ -133,6 +135,7 @@ struct RRArgs {
 struct WaveLds {
     uint32_t fr_scan[kWave], fr_v[kWave], fr_e0[kWave];
     uint32_t in_scan[kWave], in_he[kWave], in_hb[kWave], in_hs[kWave], in_v[kWave], in_thr[kWave];
+    uint32_t cont_u[kWave], cont_pos[kWave];   // phase B: members this wave appended, and where
 };
 
 // The task of launch index idx (first task whose end exceeds idx); idx is
@@ -254,6 +257,42 @@ struct SharedAppend {
 // often empty while its block would still cost the whole wave).
 constexpr uint32_t kQ = 1;
 constexpr uint32_t kRun = 4 * kQ;
+
+// A queue entry of a deferred set with this bit set was expanded by the wave
+// that appended it (continuation, below); readers of the queue mask it.
+constexpr uint32_t kExpanded = 0x80000000u;
+
+// SharedAppend that also records the first 64 members this wave appends, and
+// their queue positions, in the wave's LDS.
+struct ContAppend {
+    uint32_t *list;
+    uint32_t *size;
+    uint32_t n;
+    uint32_t *cu, *cp;
+    uint32_t count;   // members appended so far (wave-uniform)
+    __device__ __forceinline__ void push8(uint32_t mask, const uint32_t (&u)[8]) {
+        const uint32_t cnt = (uint32_t)__popc(mask);
+        const uint32_t incl = wave_incl_scan(cnt);
+        const uint32_t total = uni(wave_bcast(incl, kWave - 1));
+        if (total == 0) return;
+        uint32_t base = 0;
+        if (lane_id() == kWave - 1) base = atomicAdd(size, total);
+        uint32_t at = uni(wave_bcast(base, kWave - 1)) + incl - cnt;
+        uint32_t c = count + incl - cnt;
+#pragma unroll
+        for (uint32_t t = 0; t < 8; ++t)
+            if ((mask >> t) & 1u) {
+                if (at < n) list[at] = u[t];
+                if (c < kWave) {
+                    cu[c] = u[t];
+                    cp[c] = at;
+                }
+                ++at;
+                ++c;
+            }
+        count += total;
+    }
+};
 
 // Test the channels (he, u -> ve) at member positions [p0, p0 + cm) of one
 // hyperedge (cm <= kRun, p0 a multiple of 4) in this lane: the coins are the
@@ -578,6 +617,7 @@ __global__ __launch_bounds__(kWG) void k_rr_light(RRArgs a) {
 // by the reserving wave, so k_expand never reads an unwritten item.
 constexpr uint32_t kSkipItem = 0xFFFFFFFFu;
 constexpr uint32_t kShareMax = 16;   // waves that may share one item
+constexpr uint32_t kContLevels = 8;  // levels a wave may expand past its item
 
 __global__ __launch_bounds__(kWG) void k_plan(RRArgs a, uint32_t parity) {
     const uint32_t lane = lane_id(), wv = uni(threadIdx.x / kWave);
@@ -591,8 +631,13 @@ __global__ __launch_bounds__(kWG) void k_plan(RRArgs a, uint32_t parity) {
         while (head < size) {
             uint32_t nb = min((uint32_t)kWave, size - head);
             uint32_t v = 0, e0 = 0, deg = 0, hv = 0, light = 0, cv = a.chunk;
-            if (lane < nb) {
-                v = list[head + lane];
+            const uint32_t raw = lane < nb ? list[head + lane] : kExpanded;
+            if (__ballot((raw & kExpanded) == 0u) == 0) {   // all expanded already
+                head += nb;
+                continue;
+            }
+            if ((raw & kExpanded) == 0u) {
+                v = raw;
                 e0 = G.v_off[v];
                 deg = G.v_off[v + 1] - e0;
                 // a heavy vertex is cut into chunks of cv incidences, cv grown
@@ -674,21 +719,46 @@ __global__ __launch_bounds__(kWG) void k_expand(RRArgs a, uint32_t parity) {
         uint32_t *size_p = &a.def_size[d];
         const bool prefilter =
             uni(__hip_atomic_load(size_p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) >= a.prefilter_min;
-        SharedAppend app{list, size_p, G.n};
+        ContAppend app{list, size_p, G.n, L.cont_u, L.cont_pos, 0u};
         if (!heavy) {
             uint32_t v = 0, e0 = 0, deg = 0;
-            if (lane < item.z) {
-                v = list[item.y + lane];
+            const uint32_t raw = lane < item.z ? list[item.y + lane] : kExpanded;
+            if ((raw & kExpanded) == 0u) {   // entries marked expanded are done
+                v = raw;
                 e0 = G.v_off[v];
                 deg = G.v_off[v + 1] - e0;
                 if (deg > a.chunk) deg = 0;   // expanded by its heavy items
             }
-            if (w == 0) bytes_done += 20ull * item.z;
+            if (w == 0) bytes_done += 20ull * (uint64_t)__popcll(__ballot((raw & kExpanded) == 0u));
             bytes_done += expand<false, false>(G, L, S.j, S.pool, S.key, bm, prefilter, v, e0, deg, app, w, W);
         } else {
             // one heavy vertex: incidences [item.z, item.w) of vertex item.y
             bytes_done += expand<false, true>(G, L, S.j, S.pool, S.key, bm, prefilter, item.y, item.z,
                                               item.w - item.z, app, w, W);
+        }
+        // Continuation: when this wave appended at most 64 members, all light
+        // and together under seg incidences, it expands them itself (up to
+        // kContLevels levels) and marks their queue entries expanded, so the
+        // thin tail of a traversal does not take one superstep per level.
+        // Nobody else reads those entries before the next superstep.
+        for (uint32_t lev = 0; G.n <= kExpanded && lev < kContLevels; ++lev) {
+            const uint32_t cn = app.count;
+            if (cn == 0 || cn > kWave) break;
+            wave_sync();
+            uint32_t v = 0, e0 = 0, deg = 0, pos = 0;
+            if (lane < cn) {
+                v = L.cont_u[lane];
+                pos = L.cont_pos[lane];
+                e0 = G.v_off[v];
+                deg = G.v_off[v + 1] - e0;
+            }
+            const uint32_t tot = wave_bcast(wave_incl_scan(deg), kWave - 1);
+            if (__ballot(lane < cn && deg > a.chunk) != 0 || tot > a.seg) break;   // left to k_plan
+            wave_sync();
+            if (lane < cn) list[pos] = v | kExpanded;
+            app.count = 0;
+            bytes_done += 20ull * cn;
+            bytes_done += expand<false, false>(G, L, S.j, S.pool, S.key, bm, prefilter, v, e0, deg, app, 0u, 1u);
         }
     }
     if (lane == 0 && bytes_done) atomicAdd(&a.ctr[kBytesB], bytes_done);
@@ -714,7 +784,7 @@ __global__ __launch_bounds__(kWG) void k_finish(RRArgs a, uint32_t ndef) {
             if (size <= kSortMaxWG) {
                 uint32_t P2 = kWG;
                 while (P2 < size) P2 <<= 1;
-                for (uint32_t i = threadIdx.x; i < P2; i += kWG) buf[i] = i < size ? list[i] : 0xFFFFFFFFu;
+                for (uint32_t i = threadIdx.x; i < P2; i += kWG) buf[i] = i < size ? (list[i] & ~kExpanded) : 0xFFFFFFFFu;
                 __syncthreads();
                 for (uint32_t k = 2; k <= P2; k <<= 1) {
                     for (uint32_t jj = k >> 1; jj > 0; jj >>= 1) {
@@ -762,7 +832,7 @@ __global__ __launch_bounds__(kWG) void k_finish(RRArgs a, uint32_t ndef) {
         if (size > words) {
             for (uint32_t i = threadIdx.x; i < words; i += kWG) bm[i] = 0u;
         } else {
-            for (uint32_t i = threadIdx.x; i < size; i += kWG) bm[list[i] >> 5] = 0u;
+            for (uint32_t i = threadIdx.x; i < size; i += kWG) bm[(list[i] & ~kExpanded) >> 5] = 0u;
         }
         __syncthreads();
     }
