@@ -68,23 +68,52 @@ __device__ __forceinline__ bool table_insert(unsigned long long *keys, uint64_t 
     }
 }
 
-// Every co-member occurrence (v, he, u != v) of the batch's vertices.
-__global__ void k_pairs(const uint32_t *__restrict__ he_off, const uint32_t *__restrict__ he_mem,
-                        const uint32_t *__restrict__ v_off, const uint32_t *__restrict__ v_he, uint32_t v0,
-                        uint32_t v1, unsigned long long *keys, uint32_t *vals, uint64_t mask) {
+// Every co-member occurrence (v, he, u != v) of the batch's vertices.  Each
+// wavefront takes 64 consecutive incidences (v, he) and spreads their member
+// positions over its lanes, so a large hyperedge is not one lane's serial
+// loop.
+__global__ __launch_bounds__(kBlock) void k_pairs(const uint32_t *__restrict__ he_off,
+                                                   const uint32_t *__restrict__ he_mem,
+                                                   const uint32_t *__restrict__ v_off,
+                                                   const uint32_t *__restrict__ v_he, uint32_t v0, uint32_t v1,
+                                                   unsigned long long *keys, uint32_t *vals, uint64_t mask) {
+    __shared__ uint32_t scan_s[kBlock / kWave][kWave], hb_s[kBlock / kWave][kWave], v_s[kBlock / kWave][kWave];
+    const uint32_t lane = lane_id(), wv = threadIdx.x / kWave;
     const uint32_t e_begin = v_off[v0], e_end = v_off[v1];
-    for (uint64_t e = (uint64_t)e_begin + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < e_end;
-         e += (uint64_t)gridDim.x * blockDim.x) {
-        uint32_t lo = v0, hi = v1;  // v_off[lo] <= e < v_off[hi]
-        while (hi - lo > 1) {
-            uint32_t mid = lo + (hi - lo) / 2;
-            if (v_off[mid] <= (uint32_t)e) lo = mid; else hi = mid;
+    const uint64_t waves = (uint64_t)gridDim.x * (kBlock / kWave);
+    for (uint64_t g0 = (uint64_t)e_begin + ((uint64_t)blockIdx.x * (kBlock / kWave) + wv) * kWave; g0 < e_end;
+         g0 += waves * kWave) {
+        const uint64_t e = g0 + lane;
+        uint32_t v = 0, hb = 0, hs = 0;
+        if (e < e_end) {
+            uint32_t lo = v0, hi = v1;  // v_off[lo] <= e < v_off[hi]
+            while (hi - lo > 1) {
+                const uint32_t mid = lo + (hi - lo) / 2;
+                if (v_off[mid] <= (uint32_t)e) lo = mid; else hi = mid;
+            }
+            v = lo;
+            const uint32_t he = v_he[e];
+            hb = he_off[he];
+            hs = he_off[he + 1] - hb;
         }
-        const uint32_t v = lo, he = v_he[e];
-        for (uint32_t i = he_off[he]; i < he_off[he + 1]; ++i) {
-            uint32_t u = he_mem[i];
-            if (u != v) table_count(keys, vals, mask, ((uint64_t)v << 32) | u);
+        const uint32_t incl = wave_incl_scan(hs);
+        const uint32_t total = wave_bcast(incl, kWave - 1);
+        wave_sync();
+        scan_s[wv][lane] = incl;
+        hb_s[wv][lane] = hb;
+        v_s[wv][lane] = v;
+        wave_sync();
+        for (uint32_t b = 0; b < total; b += kWave) {
+            const uint32_t q = b + lane;
+            if (q < total) {
+                const uint32_t k = search64(scan_s[wv], q);
+                const uint32_t first = k ? scan_s[wv][k - 1] : 0u;
+                const uint32_t vk = v_s[wv][k];
+                const uint32_t u = he_mem[hb_s[wv][k] + (q - first)];
+                if (u != vk) table_count(keys, vals, mask, ((uint64_t)vk << 32) | u);
+            }
         }
+        wave_sync();
     }
 }
 
@@ -319,7 +348,10 @@ int stratify_device(hyperim_graph g, PrepWorkspace &w, hipStream_t s) {
             HIM_HIP(hipMemsetAsync(k1.ptr, 0xFF, sizeof(uint64_t) * c, s));
             HIM_HIP(hipMemsetAsync(vals.ptr, 0, sizeof(uint32_t) * c, s));
             HIM_HIP(hipMemsetAsync(k2.ptr, 0xFF, sizeof(uint64_t) * c, s));
-            hipLaunchKernelGGL(k_pairs, dim3(grid_for(std::max<uint64_t>(pairs / 4, 1))), dim3(kBlock), 0, s,
+            // one wave per 64 incidences (grid-stride; pairs bound the incidences of
+            // hyperedges with two or more members)
+            hipLaunchKernelGGL(k_pairs, dim3(std::min<uint32_t>(grid_for(std::max<uint64_t>(pairs, 1)), 8192)),
+                               dim3(kBlock), 0, s,
                                g->he_off.as<uint32_t>(), g->he_mem.as<uint32_t>(), g->v_off.as<uint32_t>(),
                                g->v_he.as<uint32_t>(), v0, v1, k1.as<unsigned long long>(), vals.as<uint32_t>(),
                                c - 1);
