@@ -1549,13 +1549,13 @@ static_assert(kNumCtr <= kHostCtr, "counter block");
 
 int ensure_host(RRWorkspace &ws, size_t words) {
     if (ws.host_words >= words) return HYPERIM_OK;
+    const size_t w = std::max<size_t>(words, 2 * ws.host_words);
     if (ws.host) {
         HIM_HIP(hipDeviceSynchronize());   // no copy may still use the old buffer
         HIM_HIP(hipHostFree(ws.host));
     }
     ws.host = nullptr;
     ws.host_words = 0;
-    const size_t w = std::max<size_t>(words, 2 * ws.host_words);
     HIM_HIP(hipHostMalloc((void **)&ws.host, w * sizeof(unsigned long long), hipHostMallocDefault));
     ws.host_words = w;
     return HYPERIM_OK;
