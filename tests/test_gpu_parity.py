@@ -93,6 +93,42 @@ def test_graph_strata_and_rr_sets_bit_exact(hy, case):
         assert np.array_equal(mem, rmem)
 
 
+def _chain_with_hubs(n=40000, hubs=12, per_hub=40, seed=17):
+    """A path {i, i+1} over n vertices (long thin traversals) plus hubs that
+    sit in many 3-member hyperedges (heavy vertices for small chunk sizes)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    edges = [[i, i + 1] for i in range(n - 1)]
+    for h in rng.choice(n, size=hubs, replace=False):
+        for _ in range(per_hub):
+            a, b = rng.choice(n, size=2, replace=False)
+            if h not in (a, b):
+                edges.append([int(h), int(a), int(b)])
+    return hypergen.from_lists(n, edges)
+
+
+@pytest.mark.parametrize("prefilter", [1 << 30, 1])
+def test_grid_phase_chains_bit_exact(hy, prefilter):
+    """Sets deferred to the grid-wide phase almost at once (tiny budget and
+    heavy threshold, 16-incidence chunks): thin traversals many levels deep,
+    expanded by shared items, continuation and heavy chunks, must equal the
+    oracle's sets member for member."""
+    _flush(f"[gpu] grid-wide phase chains prefilter={prefilter}")
+    hg = _chain_with_hubs()
+    g, o = _pair(hy, hg, 0, 0.75)
+    g.stratify()
+    o.stratify()
+    g.set_tuning(budget=8, heavy=8, chunk=16, seg=16, prefilter_min=prefilter, steps_per_sync=3)
+    for pool_tag, (a, b) in [(0, (0, 600)), (1, (100, 400))]:
+        pool = hy.Pool(g)
+        hy.generate_rr(g, 5, 2, pool_tag, a, b, pool)
+        off, mem, roots = pool.read()
+        roff, rmem, rroots = o.generate(5, 2, pool_tag, a, b)
+        assert np.array_equal(roots, rroots)
+        assert np.array_equal(off, roff)
+        assert np.array_equal(mem, rmem)
+        assert off[-1] > 5 * (b - a)   # the sets are not trivial
+
+
 @pytest.mark.parametrize("case", sorted(CASES))
 def test_bundled_mode_bit_exact(hy, case):
     """Sets grown in bundles of 64, bit-parallel over the sets (forced here by
