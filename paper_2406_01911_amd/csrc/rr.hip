@@ -1943,8 +1943,9 @@ int rr_generate_into(RRWorkspace &ws, RRStats &st, const std::vector<RRTask> &ta
     // next group runs, so the stage holds one group.  A group takes indices
     // while its predicted members fit the stage budget -- 1.3 x the graph's
     // members per set seen so far, or n (an upper bound) for a graph not
-    // seen yet, whose first group then stops after kLearnIds of its sets --
-    // and (form 0) while the sets it defers fit the spare slots at the
+    // seen yet, whose first group then stops after kLearnIds of its sets
+    // unless that bound fits for all of them -- and (form 0) while the sets
+    // it defers fit the spare slots at the
     // deferral rate seen so far (a set that finds no spare slot stays with
     // its wave).  The plain form (1) also ends a group at every (task, ladder
     // block, stratum) boundary.
@@ -2043,8 +2044,10 @@ int rr_generate_into(RRWorkspace &ws, RRStats &st, const std::vector<RRTask> &ta
             const double m = per_set(t.g);
             const bool learn = t.g->rr_members < 0.0;
             const uint64_t rest = (form == 1 ? unit_end[unit] : tstart[ti + 1]) - pos;
-            const uint64_t limit = learn ? std::min(rest, kLearnIds) : rest;
             const double room = stage_words - acc;
+            // a graph not seen yet stops its first group after kLearnIds sets,
+            // unless the worst case of all its remaining sets fits already
+            const uint64_t limit = learn && (double)rest * m > room ? std::min(rest, kLearnIds) : rest;
             uint64_t take = std::min<uint64_t>(limit, room > 0.0 ? (uint64_t)(room / m) : 0);
             take = std::min<uint64_t>(take, def_chunk - (pos - lo));
             if (take == 0 && pos == lo) take = 1;   // one set always fits
