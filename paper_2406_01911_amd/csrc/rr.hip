@@ -616,6 +616,19 @@ __global__ __launch_bounds__(kWG) void k_rr_light(RRArgs a) {
 // abandoned: its slots below the cap are filled with skip markers (x = ~0)
 // by the reserving wave, so k_expand never reads an unwritten item.
 constexpr uint32_t kSkipItem = 0xFFFFFFFFu;
+
+// Lane l owns hv_l consecutive slots of a run of sum(hv) slots (hscan: the
+// inclusive scan of hv).  The owner of slot q, by binary search over the scan
+// read through lane shuffles; every lane of the wave calls it.
+__device__ __forceinline__ uint32_t owner_of(uint32_t hscan, uint32_t q) {
+    uint32_t k = 0;
+#pragma unroll
+    for (uint32_t s = 32; s > 0; s >>= 1) {
+        const uint32_t probe = (uint32_t)__shfl((int)hscan, (int)(k + s - 1), kWave);
+        if (probe <= q) k += s;
+    }
+    return k;
+}
 constexpr uint32_t kShareMax = 16;   // waves that may share one item
 constexpr uint32_t kContLevels = 8;  // levels a wave may expand past its item
 
@@ -679,9 +692,20 @@ __global__ __launch_bounds__(kWG) void k_plan(RRArgs a, uint32_t parity) {
                 const uint32_t next = above ? (uint32_t)__ffsll((unsigned long long)above) - 1u : nb;
                 a.items[base + lane_rank(firsts)] = make_uint4(d, head + lane, min(next, nb) - lane, 0u);
             }
-            for (uint32_t k = 0; k < hv; ++k) {
-                const uint32_t b0 = e0 + k * cv;
-                a.items[base + nseg + hscan - hv + k] = make_uint4(d | 0x80000000u, v, b0, min(b0 + cv, e0 + deg));
+            // heavy chunks, spread over the wave (a hub has hundreds)
+            const uint32_t H = wave_bcast(hscan, kWave - 1);
+            for (uint32_t q0 = 0; q0 < H; q0 += kWave) {
+                const uint32_t q = q0 + lane;
+                const uint32_t k = owner_of(hscan, min(q, H - 1u));
+                const uint32_t excl = (uint32_t)__shfl((int)(hscan - hv), (int)k, kWave);
+                const uint32_t vk = (uint32_t)__shfl((int)v, (int)k, kWave);
+                const uint32_t ek = (uint32_t)__shfl((int)e0, (int)k, kWave);
+                const uint32_t ck = (uint32_t)__shfl((int)cv, (int)k, kWave);
+                const uint32_t dk = (uint32_t)__shfl((int)deg, (int)k, kWave);
+                if (q < H) {
+                    const uint32_t b0 = ek + (q - excl) * ck;
+                    a.items[base + nseg + q] = make_uint4(d | 0x80000000u, vk, b0, min(b0 + ck, ek + dk));
+                }
             }
             head += nb;
         }
@@ -1033,9 +1057,20 @@ __global__ __launch_bounds__(kWG) void k_ms_plan(MsArgs m) {
             const uint32_t next = above ? (uint32_t)__ffsll((unsigned long long)above) - 1u : nb;
             m.items[base + lane_rank(firsts)] = make_uint4((uint32_t)f, min(next, nb) - lane, 0u, 0u);
         }
-        for (uint32_t k = 0; k < hv; ++k) {
-            const uint32_t b0 = e0 + k * cv;
-            m.items[base + nseg + hscan - hv + k] = make_uint4((uint32_t)f | 0x80000000u, b0, min(b0 + cv, e0 + deg), 0u);
+        // heavy chunks, spread over the wave
+        const uint32_t H = uni(wave_bcast(hscan, kWave - 1));
+        for (uint32_t q0 = 0; q0 < H; q0 += kWave) {
+            const uint32_t q = q0 + lane;
+            const uint32_t k = owner_of(hscan, min(q, H - 1u));
+            const uint32_t excl = (uint32_t)__shfl((int)(hscan - hv), (int)k, kWave);
+            const uint32_t fk = (uint32_t)__shfl((int)(uint32_t)f, (int)k, kWave);
+            const uint32_t ek = (uint32_t)__shfl((int)e0, (int)k, kWave);
+            const uint32_t ck = (uint32_t)__shfl((int)cv, (int)k, kWave);
+            const uint32_t dk = (uint32_t)__shfl((int)deg, (int)k, kWave);
+            if (q < H) {
+                const uint32_t b0 = ek + (q - excl) * ck;
+                m.items[base + nseg + q] = make_uint4(fk | 0x80000000u, b0, min(b0 + ck, ek + dk), 0u);
+            }
         }
         if (lane < nb) bytes += (unsigned long long)sets * m.bytesw[v];
         if (lane == 0) {
@@ -1944,7 +1979,8 @@ int rr_generate_into(RRWorkspace &ws, RRStats &st, const std::vector<RRTask> &ta
     // while its predicted members fit the stage budget -- 1.3 x the graph's
     // members per set seen so far, or n (an upper bound) for a graph not
     // seen yet, whose first group then stops after kLearnIds of its sets
-    // unless that bound fits for all of them -- and (form 0) while the sets
+    // unless that bound fits for all of them and the graph has no bundled
+    // mode to decide -- and (form 0) while the sets
     // it defers fit the spare slots at the
     // deferral rate seen so far (a set that finds no spare slot stays with
     // its wave).  The plain form (1) also ends a group at every (task, ladder
@@ -2046,8 +2082,10 @@ int rr_generate_into(RRWorkspace &ws, RRStats &st, const std::vector<RRTask> &ta
             const uint64_t rest = (form == 1 ? unit_end[unit] : tstart[ti + 1]) - pos;
             const double room = stage_words - acc;
             // a graph not seen yet stops its first group after kLearnIds sets,
-            // unless the worst case of all its remaining sets fits already
-            const uint64_t limit = learn && (double)rest * m > room ? std::min(rest, kLearnIds) : rest;
+            // unless the worst case of all its remaining sets fits already and
+            // no bundled mode waits for what the group would teach
+            const bool cap = learn && ((double)rest * m > room || t.g->tune.ms_min != 0xFFFFFFFFu);
+            const uint64_t limit = cap ? std::min(rest, kLearnIds) : rest;
             uint64_t take = std::min<uint64_t>(limit, room > 0.0 ? (uint64_t)(room / m) : 0);
             take = std::min<uint64_t>(take, def_chunk - (pos - lo));
             if (take == 0 && pos == lo) take = 1;   // one set always fits
