@@ -17,7 +17,8 @@
  *   - input arrays are borrowed for the duration of the call and never
  *     retained; handles own their device memory until *_free;
  *   - vertex ids are uint32 in [0, n); hyperedge ids uint32 in [0, m);
- *     n, m < 2^32 - 1 and the number of incidences nnz = he_off[m] < 2^32;
+ *     1 <= n <= 2^31, m < 2^32 - 1 and the number of incidences
+ *     nnz = he_off[m] < 2^32 (else HYPERIM_EINVAL);
  *   - distinct handles may be used from different threads; one handle must
  *     not be used by two threads at once (RR generation on one device is
  *     serialised internally: it shares that device's workspace).
@@ -184,6 +185,27 @@ int hyperim_pool_create(hyperim_graph g, void *dev_buf, size_t bytes, uint64_t i
  * u's index in he, is below v's threshold.  Members are stored ascending. */
 int hyperim_generate_rr(hyperim_graph g, uint64_t seed, uint32_t instance, uint32_t pool_tag,
                         uint64_t id_begin, uint64_t id_end, hyperim_pool pool, void *stream);
+
+/* One RR-generation task of a batched call: ids [id_begin, id_end) of pool
+ * `pool_tag` on `graph` for key (seed, instance), appended to `pool` (whose
+ * graph it must be), with the rules of hyperim_generate_rr. */
+typedef struct {
+    hyperim_graph graph;
+    hyperim_pool pool;
+    uint64_t seed;
+    uint32_t instance, pool_tag;
+    uint64_t id_begin, id_end;
+} hyperim_rr_task;
+
+/* hyperim_generate_rr for `count` tasks at once (Algorithm 3 for every id of
+ * every task): form 0 lays the tasks back to back into shared launch groups
+ * -- all strata, both pools and many IM instances in the same persistent
+ * launches -- and form 1 launches each (task, ladder block, stratum) range
+ * on its own.  The pools receive exactly the sets that one
+ * hyperim_generate_rr call per task would give them.  Two tasks must not name
+ * the same pool.  Stream-ordered; returns after the stream has drained.
+ * Errors as for hyperim_generate_rr, checked for every task before any work. */
+int hyperim_generate_rr_batch(const hyperim_rr_task *tasks, uint32_t count, uint32_t form, void *stream);
 
 /* Device pointers of the pool's CSR (rr_off[count+1] uint64 relative to the
  * pool, rr_mem, rr_root[count]) and its id range; valid until the next call

@@ -114,6 +114,18 @@ def philox_batch(ctr: np.ndarray, key: np.ndarray) -> np.ndarray:
     return out
 
 
+def block_of(j: int, qlog: int = 8):
+    """Ladder block of RR id j: (b, first id J, size T)."""
+    b, J, T = C.c_uint32(0), C.c_uint64(0), C.c_uint64(0)
+    lib().orc_block_of(j, qlog, C.byref(b), C.byref(J), C.byref(T))
+    return b.value, J.value, T.value
+
+
+def block_offset(n: int, seed: int, instance: int, pool: int, b: int) -> int:
+    """Random offset o_b of ladder block b of a pool."""
+    return int(lib().orc_block_offset(n, seed, instance, pool, b))
+
+
 def coin(seed, instance, pool, j, he, v, pos) -> int:
     return int(lib().orc_coin(seed, instance, pool, j, he, v, pos))
 

@@ -67,6 +67,11 @@ class _Query(C.Structure):
                 ("ell", C.c_double), ("seed", C.c_uint64)]
 
 
+class _RRTask(C.Structure):
+    _fields_ = [("graph", C.c_void_p), ("pool", C.c_void_p), ("seed", C.c_uint64), ("instance", C.c_uint32),
+                ("pool_tag", C.c_uint32), ("id_begin", C.c_uint64), ("id_end", C.c_uint64)]
+
+
 class _SessionStats(C.Structure):
     _fields_ = [("submitted", C.c_uint64), ("admitted", C.c_uint64), ("finished", C.c_uint64),
                 ("failed", C.c_uint64), ("active", C.c_uint32), ("waiting", C.c_uint32), ("steps", C.c_uint64),
@@ -77,7 +82,7 @@ TUNING_FIELDS = ["heavy", "budget", "chunk", "seg", "prefilter_min", "steps_per_
                  "blocks_b", "ms_min"]
 
 EXPORTS = ["hyperim_build_graph", "hyperim_stratify", "hyperim_graph_read", "hyperim_pool_create",
-           "hyperim_generate_rr", "hyperim_pool_view", "hyperim_pool_read", "hyperim_pool_required",
+           "hyperim_generate_rr", "hyperim_generate_rr_batch", "hyperim_pool_view", "hyperim_pool_read", "hyperim_pool_required",
            "hyperim_pool_reset", "hyperim_greedy", "hyperim_coverage", "hyperim_select_seeds",
            "hyperim_select_seeds_batch", "hyperim_session_create", "hyperim_session_submit",
            "hyperim_session_step", "hyperim_session_poll", "hyperim_session_drop", "hyperim_session_stats_get",
@@ -103,6 +108,7 @@ def load_library(path: str = LIB_PATH):
     L.hyperim_graph_read.argtypes = [vp] + [vp] * 9 + [i32, vp]
     L.hyperim_pool_create.argtypes = [vp, vp, C.c_size_t, u64, C.POINTER(vp)]
     L.hyperim_generate_rr.argtypes = [vp, u64, u32, u32, u64, u64, vp, vp]
+    L.hyperim_generate_rr_batch.argtypes = [C.POINTER(_RRTask), u32, u32, vp]
     L.hyperim_pool_view.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), C.POINTER(u64), C.POINTER(u64)]
     L.hyperim_pool_read.argtypes = [vp, vp, vp, vp, i32, vp]
     L.hyperim_pool_required.argtypes = [vp, C.POINTER(C.c_size_t)]
@@ -278,6 +284,17 @@ def generate_rr(g: Graph, seed: int, instance: int, pool_tag: int, id_begin: int
                 stream=None):
     """hyperim_generate_rr: append RR ids [id_begin, id_end) to pool."""
     _check(_lib.hyperim_generate_rr(g._h, seed, instance, pool_tag, id_begin, id_end, pool._h, _stream(stream)))
+
+
+def generate_rr_batch(tasks, form: int = 0, stream=None):
+    """hyperim_generate_rr_batch: tasks is a list of dicts with graph, pool,
+    seed, instance, pool_tag, id_begin, id_end; all generated in one call
+    (shared launch groups for form 0)."""
+    arr = (_RRTask * max(len(tasks), 1))()
+    for i, t in enumerate(tasks):
+        arr[i] = _RRTask(t["graph"]._h, t["pool"]._h, t.get("seed", 0), t.get("instance", 0), t.get("pool_tag", 0),
+                         t["id_begin"], t["id_end"])
+    _check(_lib.hyperim_generate_rr_batch(arr, len(tasks), form, _stream(stream)))
 
 
 def greedy(g: Graph, pool: Pool, theta: int, k: int, stream=None):

@@ -296,8 +296,10 @@ int hyperim_build_graph(uint32_t n, uint32_t m, const uint32_t *he_off, const ui
     if (!out) return HYPERIM_EINVAL;
     *out = nullptr;
     g_detail.clear();
-    if (n == 0 || n == 0xFFFFFFFFu || m == 0xFFFFFFFFu || !he_off || (!he_mem && m)) {
-        set_error_detail("n must be in [1, 2^32-2], m < 2^32-1, arrays non-null");
+    // vertex ids stay below 2^31: the grid-wide phase marks expanded queue
+    // entries with bit 31
+    if (n == 0 || n > kMaxVertices || m == 0xFFFFFFFFu || !he_off || (!he_mem && m)) {
+        set_error_detail("n must be in [1, 2^31], m < 2^32-1, arrays non-null");
         return HYPERIM_EINVAL;
     }
     if (prob.model > HYPERIM_MODEL_WC || (prob.model == HYPERIM_MODEL_CONST && (std::isnan(prob.p) || prob.p < 0.0f))) {
@@ -438,6 +440,44 @@ int hyperim_generate_rr(hyperim_graph g, uint64_t seed, uint32_t instance, uint3
     pool->seed = seed;
     pool->instance = instance;
     pool->tag = pool_tag;
+    HIM_HIP(hipStreamSynchronize(as_stream(stream)));
+    return HYPERIM_OK;
+}
+
+int hyperim_generate_rr_batch(const hyperim_rr_task *tasks, uint32_t count, uint32_t form, void *stream) {
+    g_detail.clear();
+    if ((!tasks && count) || form > 1) return HYPERIM_EINVAL;
+    if (count == 0) return HYPERIM_OK;
+    std::vector<RRTask> rt;
+    std::vector<hyperim_pool> pools;
+    for (uint32_t i = 0; i < count; ++i) {
+        const hyperim_rr_task &t = tasks[i];
+        if (!t.graph || !t.pool || t.pool->g != t.graph) return HYPERIM_EINVAL;
+        HIM_CHECK(check_device(t.graph));
+        if (!t.graph->stratified) return HYPERIM_ESTATE;
+        if (t.pool_tag > 1 || t.seed >> 32 || t.id_end < t.id_begin || t.id_end > kMaxIds) {
+            set_error_detail("pool_tag must be 0/1, seed < 2^32, id_begin <= id_end <= 2^39");
+            return HYPERIM_EINVAL;
+        }
+        const hyperim_pool p = t.pool;
+        if (p->count && (!p->has_key || p->seed != t.seed || p->instance != t.instance || p->tag != t.pool_tag ||
+                         t.id_begin != p->id_begin + p->count)) {
+            set_error_detail("a non-empty pool only grows at its end with its own key");
+            return HYPERIM_EINVAL;
+        }
+        rt.push_back(RRTask{t.graph, t.seed, t.instance, t.pool_tag, t.id_begin, t.id_end});
+        pools.push_back(p);
+    }
+    RRStats st;
+    HIM_CHECK(generate_into(rt, pools, kDefaultQlog, (int)form, 0, as_stream(stream), st, nullptr));
+    for (uint32_t i = 0; i < count; ++i) {
+        if (tasks[i].id_end == tasks[i].id_begin) continue;
+        hyperim_pool p = tasks[i].pool;
+        p->has_key = true;
+        p->seed = tasks[i].seed;
+        p->instance = tasks[i].instance;
+        p->tag = tasks[i].pool_tag;
+    }
     HIM_HIP(hipStreamSynchronize(as_stream(stream)));
     return HYPERIM_OK;
 }

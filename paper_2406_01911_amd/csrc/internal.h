@@ -178,6 +178,7 @@ struct hyperim_pool_s {
 namespace hyperim {
 
 constexpr uint64_t kMaxIds = 1ull << 39;   // RR ids use 39 bits of the coin counter
+constexpr uint32_t kMaxVertices = 1u << 31; // ids < 2^31: bit 31 of a queue entry marks it expanded
 constexpr uint32_t kDefaultQlog = 8;       // pool ladder base Q = 2^8
 
 inline hipStream_t as_stream(void *s) { return static_cast<hipStream_t>(s); }

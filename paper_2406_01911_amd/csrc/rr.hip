@@ -41,13 +41,17 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cstdio>
 #include <cstdlib>
 #include <map>
+#include <string>
+#include <thread>
 #include <vector>
 
 #include "dev_common.h"
 #include "internal.h"
+#include "plan_layout.h"
 
 namespace hyperim {
 namespace {
@@ -58,8 +62,7 @@ constexpr uint32_t kSortMax = 1024;          // phase A: sets up to this size ar
 constexpr uint32_t kSortMaxWG = 4096;        // phase B: one workgroup sorts up to this size in LDS
 constexpr uint32_t kLdsBitmapWords = 1024;   // visited bitmap in LDS when every |V| <= 32768
 constexpr uint32_t kBigSet = 4096;           // compaction: one workgroup per larger set
-constexpr uint32_t kItemCap = 1u << 22;      // phase B: work items per superstep
-constexpr uint32_t kMaxItemsPerVertex = 1u << 20;  // heavy chunks grow so one vertex fits a superstep
+constexpr uint32_t kItemCap = kPlanItemCap;      // phase B: work items per superstep
 constexpr uint64_t kSlotBudget = 48ull << 30; // bytes of slot lists + bitmaps
 // The remaining execution parameters (heavy-vertex threshold, per-set budget,
 // chunk and segment sizes, prefilter threshold, supersteps per sync) are
@@ -68,7 +71,9 @@ constexpr uint64_t kSlotBudget = 48ull << 30; // bytes of slot lists + bitmaps
 // Counters (uint64 each) in the workspace counter block.
 // kItems and kItems + 1 alternate between supersteps: superstep s plans into
 // counter s & 1 while its k_expand clears the other one for superstep s + 1.
-enum Ctr { kWork = 0, kBump, kBigCount, kFreeNext, kDefCount, kItems, kItemsOther, kBytesA, kBytesB, kNumCtr };
+// kPlanned counts the frontier entries k_plan has taken (summed queue heads),
+// the progress measure of the host loop.
+enum Ctr { kWork = 0, kBump, kBigCount, kFreeNext, kDefCount, kItems, kItemsOther, kBytesA, kBytesB, kPlanned, kNumCtr };
 
 // One graph of a launch group.
 struct GraphDesc {
@@ -617,17 +622,11 @@ __global__ __launch_bounds__(kWG) void k_rr_light(RRArgs a) {
 // by the reserving wave, so k_expand never reads an unwritten item.
 constexpr uint32_t kSkipItem = 0xFFFFFFFFu;
 
-// Lane l owns hv_l consecutive slots of a run of sum(hv) slots (hscan: the
-// inclusive scan of hv).  The owner of slot q, by binary search over the scan
-// read through lane shuffles; every lane of the wave calls it.
+// Owner lane of heavy-chunk slot q: binary search over the wave's inclusive
+// scan of per-lane chunk counts, read through lane shuffles (every lane of
+// the wave calls it).
 __device__ __forceinline__ uint32_t owner_of(uint32_t hscan, uint32_t q) {
-    uint32_t k = 0;
-#pragma unroll
-    for (uint32_t s = 32; s > 0; s >>= 1) {
-        const uint32_t probe = (uint32_t)__shfl((int)hscan, (int)(k + s - 1), kWave);
-        if (probe <= q) k += s;
-    }
-    return k;
+    return scan_owner([hscan](uint32_t k) { return (uint32_t)__shfl((int)hscan, (int)k, kWave); }, q);
 }
 constexpr uint32_t kShareMax = 16;   // waves that may share one item
 constexpr uint32_t kContLevels = 8;  // levels a wave may expand past its item
@@ -636,8 +635,10 @@ __global__ __launch_bounds__(kWG) void k_plan(RRArgs a, uint32_t parity) {
     const uint32_t lane = lane_id(), wv = uni(threadIdx.x / kWave);
     const uint32_t waves = gridDim.x * kWavesPerWG;
     const uint32_t ndef = uni((uint32_t)a.ctr[kDefCount]);   // sets phase A deferred
+    uint64_t taken = 0;   // frontier entries this wave planned (progress count)
     for (uint32_t d = blockIdx.x * kWavesPerWG + wv; d < ndef; d += waves) {
-        uint32_t head = uni(a.def_head[d]);
+        const uint32_t head0 = uni(a.def_head[d]);
+        uint32_t head = head0;
         const uint32_t size = uni(a.def_size[d]);
         const uint32_t *list = a.lists + (uint64_t)uni(a.def_slot[d]) * a.slot_n;
         const GraphView G = graph_view(a.graphs[uni(a.tasks[uni(a.def_task[d])].graph)]);
@@ -653,18 +654,15 @@ __global__ __launch_bounds__(kWG) void k_plan(RRArgs a, uint32_t parity) {
                 v = raw;
                 e0 = G.v_off[v];
                 deg = G.v_off[v + 1] - e0;
-                // a heavy vertex is cut into chunks of cv incidences, cv grown
-                // so that one vertex never needs more than kMaxItemsPerVertex
-                cv = max(a.chunk, (uint32_t)div_up(deg, kMaxItemsPerVertex));
-                hv = deg > a.chunk ? (uint32_t)div_up(deg, cv) : 0u;
+                // a heavy vertex is cut into chunks of cv incidences
+                const HeavySplit hs = heavy_split(deg, a.chunk);
+                cv = hs.len;
+                hv = hs.count;
                 light = hv ? 0u : deg;
             }
-            // light vertices form segments of consecutive queue entries: a lane
-            // belongs to segment floor(prefix of light incidences before it /
-            // seg); each light degree is <= chunk <= seg, so segments have no
-            // gaps and hold fewer than seg + chunk incidences
+            // light vertices form segments of consecutive queue entries
             const uint32_t lscan = wave_incl_scan(light);
-            const uint32_t seg = (lscan - light) / a.seg;
+            const uint32_t seg = segment_of(lscan, light, a.seg);
             const uint32_t prev_seg = __shfl_up(seg, 1, kWave);
             const bool first = lane < nb && (lane == 0 || seg != prev_seg);
             uint64_t firsts = __ballot(first);
@@ -703,14 +701,16 @@ __global__ __launch_bounds__(kWG) void k_plan(RRArgs a, uint32_t parity) {
                 const uint32_t ck = (uint32_t)__shfl((int)cv, (int)k, kWave);
                 const uint32_t dk = (uint32_t)__shfl((int)deg, (int)k, kWave);
                 if (q < H) {
-                    const uint32_t b0 = ek + (q - excl) * ck;
-                    a.items[base + nseg + q] = make_uint4(d | 0x80000000u, vk, b0, min(b0 + ck, ek + dk));
+                    const ChunkRange cr = chunk_range(ek, dk, ck, q - excl);
+                    a.items[base + nseg + q] = make_uint4(d | 0x80000000u, vk, cr.lo, cr.hi);
                 }
             }
             head += nb;
         }
         if (lane == 0) a.def_head[d] = head;
+        taken += head - head0;
     }
+    if (lane == 0 && taken) atomicAdd(&a.ctr[kPlanned], (unsigned long long)taken);
 }
 
 __global__ __launch_bounds__(kWG) void k_expand(RRArgs a, uint32_t parity) {
@@ -751,7 +751,7 @@ __global__ __launch_bounds__(kWG) void k_expand(RRArgs a, uint32_t parity) {
                 v = raw;
                 e0 = G.v_off[v];
                 deg = G.v_off[v + 1] - e0;
-                if (deg > a.chunk) deg = 0;   // expanded by its heavy items
+                if (heavy_split(deg, a.chunk).count) deg = 0;   // expanded by its heavy items
             }
             if (w == 0) bytes_done += 20ull * (uint64_t)__popcll(__ballot((raw & kExpanded) == 0u));
             bytes_done += expand<false, false>(G, L, S.j, S.pool, S.key, bm, prefilter, v, e0, deg, app, w, W);
@@ -929,17 +929,6 @@ __device__ __forceinline__ uint32_t nth_bit(unsigned long long m, uint32_t r) {
     return pos;
 }
 
-// Work of a frontier entry grows with its incidences times the sets in its
-// mask; a heavy entry is cut into chunks of about `chunk` (incidence, set)
-// pairs: chunk / (sets) incidences, at least 1, and at most kItemCap / 128
-// chunks per entry so that any batch of 64 entries fits an empty item buffer.
-// Returns the chunk length in incidences; the entry is heavy when its degree
-// exceeds it.
-__device__ __forceinline__ uint32_t ms_chunk(uint32_t deg, uint32_t sets, uint32_t chunk) {
-    const uint32_t c = max(1u, chunk / max(sets, 1u));
-    return max(c, (uint32_t)div_up(deg, kItemCap / 128));
-}
-
 __device__ __forceinline__ void ms_append_next(const MsArgs &m, uint32_t b, uint32_t u) {
     const unsigned long long pos = atomicAdd(&m.ctr[kMsNext], 1ull);
     if (pos < m.list_cap) {
@@ -1033,12 +1022,15 @@ __global__ __launch_bounds__(kWG) void k_ms_plan(MsArgs m) {
             sets = (uint32_t)__popcll(m.cur_m[f]);
             e0 = G.v_off[v];
             deg = G.v_off[v + 1] - e0;
-            cv = ms_chunk(deg, sets, m.chunk);
-            hv = deg > cv ? (uint32_t)div_up(deg, cv) : 0u;
+            // work grows with incidences times sets: heavy entries are cut
+            // into chunks of about `chunk` (incidence, set) pairs
+            const HeavySplit hs = ms_heavy_split(deg, sets, m.chunk);
+            cv = hs.len;
+            hv = hs.count;
             light = hv ? 0u : deg * sets;   // segment weight: (incidence, set) pairs
         }
         const uint32_t lscan = wave_incl_scan(light);
-        const uint32_t seg = (lscan - light) / m.seg;
+        const uint32_t seg = segment_of(lscan, light, m.seg);
         const uint32_t prev_seg = __shfl_up(seg, 1, kWave);
         const bool first = lane < nb && (lane == 0 || seg != prev_seg);
         const uint64_t firsts = __ballot(first);
@@ -1068,8 +1060,8 @@ __global__ __launch_bounds__(kWG) void k_ms_plan(MsArgs m) {
             const uint32_t ck = (uint32_t)__shfl((int)cv, (int)k, kWave);
             const uint32_t dk = (uint32_t)__shfl((int)deg, (int)k, kWave);
             if (q < H) {
-                const uint32_t b0 = ek + (q - excl) * ck;
-                m.items[base + nseg + q] = make_uint4(fk | 0x80000000u, b0, min(b0 + ck, ek + dk), 0u);
+                const ChunkRange cr = chunk_range(ek, dk, ck, q - excl);
+                m.items[base + nseg + q] = make_uint4(fk | 0x80000000u, cr.lo, cr.hi, 0u);
             }
         }
         if (lane < nb) bytes += (unsigned long long)sets * m.bytesw[v];
@@ -1230,7 +1222,7 @@ __global__ __launch_bounds__(kWG) void k_ms_expand(MsArgs m) {
                 mask = m.cur_m[f];
                 e0 = G.v_off[v];
                 d = G.v_off[v + 1] - e0;
-                if (d > ms_chunk(d, (uint32_t)__popcll(mask), m.chunk)) d = 0;   // expanded by its heavy items
+                if (ms_heavy_split(d, (uint32_t)__popcll(mask), m.chunk).count) d = 0;   // expanded by its heavy items
             }
             ms_expand(m, G, L, b, v, mask, e0, d);
         } else {
@@ -1433,7 +1425,7 @@ int slot_layout(uint32_t n_max, SlotLayout *out) {
     HIM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_glb, k_rr_light<false>, kWG, 0));
     HIM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_b, k_expand, kWG, 0));
     const bool lds = n_max <= kLdsBitmapWords * 32u;
-    const uint64_t words = (n_max + 31u) / 32u;
+    const uint64_t words = ((uint64_t)n_max + 31u) / 32u;
     const uint64_t per_slot = (uint64_t)n_max * 4u + (lds ? 0u : words * 4u);
     const uint64_t max_slots = std::max<uint64_t>(kSlotBudget / std::max<uint64_t>(per_slot, 1), 2 * kWavesPerWG);
     uint64_t grid = (uint64_t)cus * (uint64_t)std::max(lds ? per_cu_lds : per_cu_glb, 1);
@@ -1456,7 +1448,7 @@ int slot_layout(uint32_t n_max, SlotLayout *out) {
 // graph arrives).
 int ensure_workspace(RRWorkspace &ws, uint32_t n_max, hipStream_t s, LaunchShape *shape) {
     const bool lds = n_max <= kLdsBitmapWords * 32u;
-    const uint32_t words = (n_max + 31u) / 32u;
+    const uint32_t words = (uint32_t)(((uint64_t)n_max + 31u) / 32u);
     if (ws.grid != 0 && (ws.slot_n < n_max || ws.lds != lds)) {
         HIM_HIP(hipStreamSynchronize(s));
         ws.lists.release();
@@ -1545,6 +1537,34 @@ int read_ctr(hipStream_t s, const unsigned long long *dev, int idx, uint64_t *ou
     HIM_HIP(hipStreamSynchronize(s));
     *out = v;
     return HYPERIM_OK;
+}
+
+// Wait for an event of the superstep loops, but not forever: a batch that has
+// not finished after HYPERIM_WAIT_LIMIT_S seconds (default 600; a batch of
+// the largest workloads takes a few seconds) ends the call with HYPERIM_EHIP
+// naming the loop, instead of blocking the caller.
+int wait_event(hipEvent_t e, const char *what) {
+    static const double limit = [] {
+        const char *v = getenv("HYPERIM_WAIT_LIMIT_S");
+        const double x = v ? atof(v) : 0.0;
+        return x > 0.0 ? x : 600.0;
+    }();
+    const auto t0 = std::chrono::steady_clock::now();
+    for (;;) {
+        const hipError_t q = hipEventQuery(e);
+        if (q == hipSuccess) return HYPERIM_OK;
+        if (q != hipErrorNotReady) {
+            set_error_detail(std::string("waiting for ") + what + ": " + hipGetErrorString(q));
+            return HYPERIM_EHIP;
+        }
+        const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        if (el > limit) {
+            set_error_detail(std::string(what) + " did not finish within the wait limit");
+            return HYPERIM_EHIP;
+        }
+        if (el > 2e-3) std::this_thread::sleep_for(std::chrono::microseconds(20));
+        else std::this_thread::yield();
+    }
 }
 
 // Events of the RR workspace: [0], [1] start and end of phase A, [2], [3] of
@@ -1682,9 +1702,10 @@ int run_launch(RRWorkspace &ws, RRStats &st, const hyperim_tuning &tune, RRArgs 
         };
         HIM_HIP(hipMemsetAsync(ctr + kItems, 0, 2 * sizeof(unsigned long long), s));
         HIM_CHECK(issue(0));
+        uint64_t planned_before = 0;
         for (;;) {
             HIM_CHECK(issue(k + 1));   // queued before batch k is read
-            HIM_HIP(hipEventSynchronize(batch_events(ws, k)[1]));
+            HIM_CHECK(wait_event(batch_events(ws, k)[1], "a grid-wide superstep batch"));
             const unsigned long long *hb = h + kHostBatch + (k & 1u) * kHostCtr;
             ndef = hb[kDefCount];
             plan_sets = std::max<uint64_t>(ndef, 1);
@@ -1692,17 +1713,22 @@ int run_launch(RRWorkspace &ws, RRStats &st, const hyperim_tuning &tune, RRArgs 
             const uint64_t items = hb[kItems + last];
             HIM_CHECK(account(k));
             if (trace)
-                fprintf(stderr, "[hyperim] superstep %llu: %llu items\n",
-                        (unsigned long long)((k + 1) * (uint64_t)batch), (unsigned long long)items);
-            if (items == 0) break;   // the last superstep found no frontier left
-            ++k;
-            // every superstep with items advances some queue head, and a set
-            // holds at most n members, so n supersteps per set bound the loop
-            if (k * (uint64_t)batch > (uint64_t)a.slot_n * std::max<uint64_t>(ndef, 1) + 2 * (uint64_t)batch) {
+                fprintf(stderr, "[hyperim] superstep %llu: %llu items, %llu entries planned\n",
+                        (unsigned long long)((k + 1) * (uint64_t)batch), (unsigned long long)items,
+                        (unsigned long long)hb[kPlanned]);
+            // the deferred sets hold at most slot_n members each
+            const int chk = phase_b_check(planned_before, hb[kPlanned], items,
+                                          (uint64_t)a.slot_n * std::max<uint64_t>(ndef, 1));
+            if (chk == kLoopDone) break;   // the last superstep found no frontier left
+            if (chk != kLoopContinue) {
                 HIM_HIP(hipStreamSynchronize(s));
-                set_error_detail("phase B did not converge");
+                set_error_detail(chk == kLoopStalled
+                                     ? "grid-wide phase stalled: a batch of supersteps with work planned no entry"
+                                     : "grid-wide phase planned more entries than its sets can hold");
                 return HYPERIM_EHIP;
             }
+            planned_before = hb[kPlanned];
+            ++k;
         }
         queued = true;   // batch k + 1, which finds no work
     }
@@ -1762,7 +1788,8 @@ int run_ms_launch(RRWorkspace &ws, RRStats &st, const hyperim_tuning &tune, RRAr
     HIM_CHECK(ws.ms_ctr.reserve(sizeof(unsigned long long) * kMsNumCtr, s));
     MsArgs m{};
     m.graph = GraphDesc{g->he_off.as<uint32_t>(), g->he_mem.as<uint32_t>(), g->v_off.as<uint32_t>(),
-                        g->v_he.as<uint32_t>(), g->thr.as<uint32_t>(), g->P.as<uint32_t>(), n, (n + 31u) / 32u};
+                        g->v_he.as<uint32_t>(), g->thr.as<uint32_t>(), g->P.as<uint32_t>(), n,
+                        (uint32_t)(((uint64_t)n + 31u) / 32u)};
     m.bytesw = g->bytesw.as<unsigned long long>();
     m.first_id = t.first_id;
     m.pool = t.pool;
@@ -1806,15 +1833,14 @@ int run_ms_launch(RRWorkspace &ws, RRStats &st, const hyperim_tuning &tune, RRAr
     // levels: plan, expand, bookkeeping, advance, bookkeeping; a level whose
     // items overflow the buffer takes several steps
     const int per_sync = (int)std::min<uint32_t>(std::max<uint32_t>(tune.steps_per_sync, 1), kMaxBatch);
-    const uint64_t max_steps = 4ull * stride + 64ull + 2ull * (uint64_t)per_sync;
     hipEvent_t *E = batch_events(ws, 0);
     uint64_t steps = 0;
     float ms = 0.f;
+    // progress: (level epoch, pending frontier batches) before this batch
+    uint64_t epoch_before = 0, pending_before = ~0ull;
+    const unsigned long long *hm = ws.host + kHostBatch;
+    static_assert(kMsNumCtr <= kHostCtr, "bundled counter block");
     for (;;) {
-        if (steps > max_steps) {
-            set_error_detail("bundled generation did not converge");
-            return HYPERIM_EHIP;
-        }
         const int batch = trace ? 1 : per_sync;
         for (int k = 0; k < batch; ++k) {
             hipLaunchKernelGGL(k_ms_plan, dim3(grid_b), dim3(kWG), 0, s, m);
@@ -1828,8 +1854,22 @@ int run_ms_launch(RRWorkspace &ws, RRStats &st, const hyperim_tuning &tune, RRAr
         }
         HIM_HIP(hipGetLastError());
         steps += batch;
-        uint64_t done = 0;
-        HIM_CHECK(read_ctr(s, m.ctr, kMsDone, &done));
+        HIM_HIP(hipMemcpyAsync(ws.host + kHostBatch, m.ctr, sizeof(unsigned long long) * kMsNumCtr,
+                               hipMemcpyDeviceToHost, s));
+        HIM_HIP(hipEventRecord(E[1], s));
+        HIM_CHECK(wait_event(E[1], "a bundled superstep batch"));
+        const uint64_t done = hm[kMsDone];
+        // a level adds at least one new (set, member) pair, so levels are
+        // bounded by the members of the group's sets
+        const int chk = bundled_check(epoch_before, pending_before, hm[kMsEpoch], hm[kMsPending], done,
+                                      (uint64_t)nbundles * kMsSets * stride + 2);
+        if (chk == kLoopStalled || chk == kLoopOverBound) {
+            set_error_detail(chk == kLoopStalled ? "bundled generation stalled: a batch of steps changed no level"
+                                                 : "bundled generation ran more levels than its sets can have");
+            return HYPERIM_EHIP;
+        }
+        epoch_before = hm[kMsEpoch];
+        pending_before = hm[kMsPending];
         for (int k = 0; time_kernels && k < batch; ++k) {
             float me = 0.f;
             HIM_HIP(hipEventElapsedTime(&me, E[2 + 2 * k], E[3 + 2 * k]));
@@ -1954,7 +1994,7 @@ int rr_generate_into(RRWorkspace &ws, RRStats &st, const std::vector<RRTask> &ta
         hyperim_graph g = t.g;
         gdesc.push_back(GraphDesc{g->he_off.as<uint32_t>(), g->he_mem.as<uint32_t>(), g->v_off.as<uint32_t>(),
                                   g->v_he.as<uint32_t>(), g->thr.as<uint32_t>(), g->P.as<uint32_t>(), g->n,
-                                  (g->n + 31u) / 32u});
+                                  (uint32_t)(((uint64_t)g->n + 31u) / 32u)});
         n_max = std::max(n_max, g->n);
     }
     uint64_t count = 0;

@@ -81,6 +81,57 @@ def test_large_sampled_rr_sets_exact(large):
         assert np.array_equal(got, want), (tag, j, got.size, want.size)
 
 
+def test_large_bundled_mode_under_stored_tuning_exact(large):
+    """The launch configuration the benchmark times on this workload: the
+    stored tuning, whose bundled mode grows the sets of a graph that averages
+    at least ms_min members per set in bundles of 64.  Both pools' ids
+    [0, 6144) in one generation call on a fresh graph handle: R1's first 2048
+    ids form the learning group (per-set mode), every later id of R1 and all
+    of R2 run bundled.  Sampled ids of both modes, including the largest sets,
+    equal the oracle's sets and roots."""
+    hy, w, hg, g, o = large
+    from paper_2406_01911_amd import autotune
+    if not o.stratified:
+        o.stratify()
+    tuning = autotune.load("large")
+    assert tuning and tuning["ms_min"] < 0xFFFFFFFF
+    g2 = hy.build_graph(hg.n, hg.he_off, hg.he_mem, w.model, w.p)
+    g2.stratify()
+    g2.set_tuning(**tuning)
+    ids = 6144
+    pools = {tag: hy.Pool(g2) for tag in (0, 1)}
+    print(f"[gpu] large: both pools [0, {ids}) under the stored tuning", flush=True)
+    hy.generate_rr_batch([dict(graph=g2, pool=pools[tag], seed=w.philox_seed, instance=0, pool_tag=tag,
+                               id_begin=0, id_end=ids) for tag in (0, 1)])
+    data = {tag: pools[tag].read() for tag in (0, 1)}
+    off0 = data[0][0]
+    learned = off0[2048] / 2048.0
+    # the library switches a graph to bundled mode once its sets average at
+    # least ms_min members; the learning group's average is what it learns
+    assert learned >= tuning["ms_min"], learned
+    rng = np.random.default_rng(11)
+    checks = []
+    for tag in (0, 1):
+        off, mem, roots = data[tag]
+        sizes = np.diff(off)
+        lo = 2048 if tag == 0 else 0
+        bundled = np.arange(lo, ids)
+        big = list(bundled[np.argsort(sizes[lo:], kind="stable")[-4:]])
+        pick = big + [int(j) for j in rng.choice(bundled, size=4, replace=False) if j not in big]
+        if tag == 0:
+            pick += [int(j) for j in rng.choice(2048, size=2, replace=False)]
+        for j in pick:
+            checks.append((tag, int(j), mem[off[j]:off[j + 1]].copy(), int(roots[j])))
+    print(f"[gpu] large: {len(checks)} sampled ids on the CPU (learned {learned:.0f} members per set)", flush=True)
+    threads = max(1, min(len(checks), int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)))
+    with cf.ThreadPoolExecutor(max_workers=threads) as ex:
+        ref = list(ex.map(lambda c: (o.rr_set(w.philox_seed, 0, c[0], c[1]), o.root(w.philox_seed, 0, c[0], c[1])),
+                          checks))
+    for (tag, j, got, root), (want, wroot) in zip(checks, ref):
+        assert root == wroot, (tag, j)
+        assert np.array_equal(got, want), (tag, j, got.size, want.size)
+
+
 def test_large_forms_identical_on_a_round(large):
     """Plain per-stratum launches and the persistent launch give the same bytes."""
     hy, w, hg, g, o = large
