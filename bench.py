@@ -1,15 +1,19 @@
 """Benchmark of HyperIM's hot path on one MI355X.
 
-One step = one whole query on a device-resident synthetic hypergraph:
-build the incidence CSR and thresholds, stratify, then the HyperIM_BRR loop
-(RR-set generation for both pools, greedy max coverage, R2 check, doubling)
-until the seed set is returned.  Inputs (he_off, he_mem) are already in HBM
-when the timed region starts.
+One step = one whole query on a device-resident synthetic hypergraph: build
+the incidence CSR and thresholds, stratify, then the HyperIM_BRR loop (RR-set
+generation for both pools, greedy max coverage, R2 check, doubling) until the
+seed set is returned.  Inputs (he_off, he_mem) are already in HBM when the
+timed region starts.  The default workload is the large one (|V| = 1e6,
+|HE| = 2e6, IC p = 0.01, k = 100) under its stored tuning, with the plain
+per-stratum form timed beside it.
 
-Prints one JSON line: RR sets/s (value), incidences/s, time-to-seed-set, the
-roofline of the RR-generation kernel (algorithmic bytes per launch over its
-HIP-event-timed average duration, against 8 TB/s) and the CPU oracle timed on
-a bounded sample of the same workload.
+Prints one JSON line: RR sets/s (value), incidences/s, coins/s, Philox
+blocks/s, time-to-seed-set, the roofline of the dominant RR-generation kernel
+(its Philox work against the VALU peak and its algorithmic bytes against
+8 TB/s, both per HIP-event-timed launch; `bound` is what the committed
+hardware counters show) and the CPU oracle timed on a bounded sample of the
+same workload.
 """
 from __future__ import annotations
 
@@ -39,13 +43,13 @@ WORKLOAD_TEXT = {
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="mid", choices=sorted(WORKLOAD_TEXT))
+    ap.add_argument("--workload", default="large", choices=sorted(WORKLOAD_TEXT))
     ap.add_argument("--form", type=int, default=0, help="0 persistent launch per pool block, 1 plain per stratum")
     ap.add_argument("--plain-steps", type=int, default=-1,
-                    help="steps of the plain per-stratum form timed for comparison (-1: same as --steps on "
-                         "tiny/mid/multi, 0 on large)")
+                    help="steps of the plain per-stratum form timed for comparison (-1: 1 on large and multi, "
+                         "as many as --steps otherwise)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU-baseline sample time")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tuning", default="stored", choices=["stored", "default"],
@@ -56,6 +60,24 @@ def parse():
     return ap.parse_args()
 
 
+# The VALU peak of MI355X in 32-bit lane operations: 256 compute units x 4
+# SIMDs x 16 lanes per clock x 2.4 GHz (the 157.3 TFLOP/s fp32 vector figure
+# counts a packed FMA as 4 flops per lane).  One Philox4x32-10 block is 20
+# v_mad_u64_u32 and 40 v_xor_b32 in the generated code (key schedule in
+# scalar registers); a v_mad_u64_u32 takes PHILOX_MAD_PASSES issue passes.
+VALU_LANE_OPS_PER_S = 256 * 4 * 16 * 2.4e9
+PHILOX_XOR, PHILOX_MAD, PHILOX_MAD_PASSES = 40, 20, 4
+PHILOX_PEAK_BLOCKS_PER_S = VALU_LANE_OPS_PER_S / (PHILOX_XOR + PHILOX_MAD * PHILOX_MAD_PASSES)
+
+# expansion kernels the line can name as dominant: result fields of their
+# time, launches, algorithmic bytes and Philox blocks
+KERNELS = {
+    "k_rr_light": ("ms_light", None, "bytes_light", "philox_light"),
+    "k_expand": ("ms_expand", "expand_launches", "bytes_heavy", None),
+    "k_ms_expand": ("ms_bundled", "bundled_launches", "bytes_bundled", "philox_bundled"),
+}
+
+
 def rr_device_sha256() -> str:
     """sha256 of rr.hip's device code: the text before its host-side marker."""
     src = os.path.join(ROOT, "paper_2406_01911_amd", "csrc", "rr.hip")
@@ -64,24 +86,34 @@ def rr_device_sha256() -> str:
     return hashlib.sha256(text.split("// ---- host side", 1)[0].encode()).hexdigest()
 
 
-def expand_traffic(workload: str):
-    """HBM bytes per k_expand launch from the committed hardware-counter
+def kernel_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` from the committed hardware-counter
     summary of this workload (FETCH_SIZE + WRITE_SIZE per dispatch, scaled by
     the same counters on a copy of known size); None when there is none or
     when the device code of RR generation (rr.hip up to its host-side part)
     has changed since the counters were taken."""
-    path = os.path.join(ROOT, "profiles", f"k_expand_{workload}_counters.json")
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_counters.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
-    sha = rr_device_sha256()
-    if rec.get("rr_hip_sha256") != sha:
+    if rec.get("rr_hip_sha256") != rr_device_sha256():
         return None
     return rec["traffic_bytes_per_launch"]
 
 
-def cpu_baseline(hg, w, seconds: float):
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(hg, w, seconds: float, workload: str):
     """The oracle as it stands, on the host cores: RR sets of pool R1 from id 0
     in chunks until about `seconds` of CPU work (build + stratify untimed)."""
     import oracle
@@ -89,7 +121,7 @@ def cpu_baseline(hg, w, seconds: float):
     threads = max(1, min(threads, os.cpu_count() or 1))
     o = oracle.Graph(hg, w.model, w.p)
     o.stratify()
-    done, chunk, t0 = 0, 512, time.perf_counter()
+    done, chunk, t0 = 0, 2 * threads if workload == "large" else 512, time.perf_counter()
     while True:
         o.generate(w.philox_seed, 0, 0, done, done + chunk, nthreads=threads)
         done += chunk
@@ -98,9 +130,29 @@ def cpu_baseline(hg, w, seconds: float):
             break
         if el < seconds / 4:
             chunk *= 2
-    return {"value": done / el, "unit": "RR sets/s", "cores": threads, "kind": "oracle",
-            "sample": f"RR ids [0, {done}) of pool R1 of the same workload, {el:.1f} s wall, "
-                      f"{threads} threads over ids"}
+    what = (f"RR ids [0, {done}) of pool R1 of the same workload, {el:.1f} s wall, {threads} threads over ids")
+    if workload == "large":
+        what += ("; an extrapolation: the query needs tens of thousands of these sets, the sample covers the "
+                 "first ids of the ladder")
+    return {"value": done / el, "unit": "RR sets/s", "cores": threads, "kind": "oracle", "cpu": cpu_model(),
+            "sample": what}
+
+
+def philox_rate():
+    """Measured throughput of the library's Philox4x32-10 block function at
+    full occupancy (microbench/philox_rate.hip), blocks/s."""
+    import ctypes as C
+    path = os.path.join(ROOT, "paper_2406_01911_amd", "microbench", "libphilox_rate.so")
+    if not os.path.exists(path):
+        return None
+    L = C.CDLL(path)
+    L.philox_rate.argtypes = [C.c_uint32, C.c_uint32, C.c_uint32, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                              C.POINTER(C.c_double)]
+    bps, ms, blocks = C.c_double(), C.c_double(), C.c_double()
+    rc = L.philox_rate(2048, 16, 5, C.byref(bps), C.byref(ms), C.byref(blocks))
+    if rc != 0:
+        return None
+    return {"blocks_per_s": bps.value, "ms": ms.value, "blocks": blocks.value}
 
 
 def main():
@@ -118,35 +170,34 @@ def main():
     hy.load_library()
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
-    if args.workload != "multi":
-        w = hypergen.workload(args.workload)
-        hg = w.build()
-        dev_off = torch.from_numpy(hg.he_off.view(np.int32)).cuda()
-        dev_mem = torch.from_numpy(hg.he_mem.view(np.int32)).cuda()
-
+    t_gen = time.perf_counter()
     if args.workload == "multi":
         ws = hypergen.multi_instance_workloads(64)
-        t_gen = time.perf_counter()
         hgs = []
         for i, wl in enumerate(ws):
             hgs.append(wl.build())
             if i % 16 == 15:
                 print(f"[bench] generated {i + 1} of {len(ws)} instances "
                       f"({time.perf_counter() - t_gen:.1f} s)", file=sys.stderr, flush=True)
-        dev = [(torch.from_numpy(h.he_off.view(np.int32)).cuda(), torch.from_numpy(h.he_mem.view(np.int32)).cuda())
-               for h in hgs]
     else:
-        ws = [w]
-        hgs = [hg]
-        dev = [(dev_off, dev_mem)]
+        ws = [hypergen.workload(args.workload)]
+        hgs = [ws[0].build()]
+    w = ws[0]
+    dev = [(torch.from_numpy(h.he_off.view(np.int32)).cuda(), torch.from_numpy(h.he_mem.view(np.int32)).cuda())
+           for h in hgs]
     torch.cuda.synchronize()
+    print(f"[bench] {args.workload} input generated and resident ({time.perf_counter() - t_gen:.1f} s)",
+          file=sys.stderr, flush=True)
     from paper_2406_01911_amd import autotune
     tuning = autotune.load(args.workload) if args.tuning == "stored" else None
+    flags = hy.FLAG_KERNEL_TIMES | hy.FLAG_INCIDENCES
 
-    def step(flags=0, form=args.form):
+    def step(form):
         """One query step: build + stratify every graph, then seed selection
         (one query, or all instances batched; form 1 runs them one by one in
-        the plain per-stratum form)."""
+        the plain per-stratum form).  Every expansion launch is timed by
+        events it stamps, and the final pools' work (incidences, coins,
+        Philox blocks, algorithmic bytes) is summed in one extra pass."""
         gs = []
         for h, (o, m), wl in zip(hgs, dev, ws):
             g = hy.build_graph(h.n, o, m, wl.model, wl.p, stream=stream)
@@ -178,36 +229,43 @@ def main():
         print(json.dumps({"copy_calibration_bytes": nbytes}), file=sys.stderr, flush=True)
         del src, dst
 
-    def timed(steps, warmup, form):
-        # expansion launches timed by events they stamp, inside the timed region
-        for _ in range(warmup):
-            step(flags=hy.FLAG_KERNEL_TIMES, form=form)
+    px_rate = philox_rate()
+
+    def timed(steps, warmup, form, what):
+        for i in range(warmup):
+            step(form)
+            print(f"[bench] {what}: warm-up step {i + 1} of {warmup} done", file=sys.stderr, flush=True)
         torch.cuda.synchronize()
         out = []
         t0 = time.perf_counter()
-        for _ in range(steps):
-            out.append(step(flags=hy.FLAG_KERNEL_TIMES, form=form))
+        for i in range(steps):
+            out.append(step(form))
+            print(f"[bench] {what}: step {i + 1} of {steps} done ({time.perf_counter() - t0:.1f} s)",
+                  file=sys.stderr, flush=True)
         torch.cuda.synchronize()
         return out, time.perf_counter() - t0
 
-    steps_out, elapsed = timed(args.steps, args.warmup, args.form)
+    steps_out, elapsed = timed(args.steps, args.warmup, args.form, f"form {args.form}")
     results = [r for r, _ in steps_out]
     totals = [t for _, t in steps_out]
     print(f"[bench] {args.steps} steps of form {args.form}: {elapsed:.3f} s", file=sys.stderr, flush=True)
-    plain_steps = args.plain_steps if args.plain_steps >= 0 else (0 if args.workload == "large" else args.steps)
+    big = args.workload in ("large", "multi")
+    plain_steps = args.plain_steps if args.plain_steps >= 0 else (1 if big else args.steps)
     plain = None
     if plain_steps and args.form == 0:
-        pres, pel = timed(plain_steps, 1, 1)
+        # the workspace is warm from the steps above; small workloads still
+        # take one plain warm-up step
+        pres, pel = timed(plain_steps, 0 if big else 1, 1, "plain form")
         for a, b in zip(pres[-1][0], results[-1]):
             assert np.array_equal(a["seeds"], b["seeds"]) and a["theta"] == b["theta"]
         plain = {"form": "plain per-stratum launches, one query at a time", "steps": plain_steps,
                  "ms_per_step": 1000.0 * pel / plain_steps}
         print(f"[bench] {plain_steps} steps of the plain form: {pel:.3f} s", file=sys.stderr, flush=True)
-    # identical step with the incidence / byte counters switched on (untimed)
-    meas, mtot = step(flags=hy.FLAG_INCIDENCES)
     last = results[-1]
-    for a, b in zip(meas, last):
-        assert np.array_equal(a["seeds"], b["seeds"]) and a["theta"] == b["theta"]
+    mtot = totals[-1]
+    for r in results[:-1]:
+        for a, b in zip(r, last):
+            assert np.array_equal(a["seeds"], b["seeds"]) and a["theta"] == b["theta"]
 
     def mean_total(key):
         return float(np.mean([t[key] for t in totals]))
@@ -215,32 +273,58 @@ def main():
     ms_per_step = 1000.0 * elapsed / args.steps
     rr_sets_per_step = sum(2 * r["theta"] for r in last)
     value = rr_sets_per_step * args.steps / elapsed
-    incidences = mtot["incidences"]
-    inc_per_s = incidences * args.steps / elapsed
-    bfs_ms = mean_total("ms_bfs")
-    ms_light = mean_total("ms_light")
-    ms_heavy = mean_total("ms_heavy")
-    launches = totals[-1]["bfs_launches"]
+    per_s = args.steps / elapsed
     alg_bytes = mtot["alg_bytes"]
-    bytes_light, bytes_heavy = mtot["bytes_light"], mtot["bytes_heavy"]
-    # the kernels count the bytes of every expansion they perform; together
-    # they must equal the total recomputed from the output sets
-    assert bytes_light + bytes_heavy == alg_bytes, (bytes_light, bytes_heavy, alg_bytes)
-    achieved_all = alg_bytes / (bfs_ms * 1e-3) / 1e9 if bfs_ms > 0 else 0.0
-    # dominant kernel: k_expand (the grid-wide expansion); its own HIP-event
-    # time over the timed steps and the algorithmic bytes it expanded
-    ms_expand = mean_total("ms_expand")
-    expand_launches = totals[-1]["expand_launches"]
-    achieved = bytes_heavy / (ms_expand * 1e-3) / 1e9 if ms_expand > 0 else 0.0
-    traffic = expand_traffic(args.workload)
-    phases = {
-        "per_set_phase": {"kernel": "k_rr_light", "ms": ms_light, "alg_bytes": bytes_light,
-                          "GBps": bytes_light / (ms_light * 1e-3) / 1e9 if ms_light > 0 else 0.0},
-        "grid_wide_phase": {"kernels": "k_plan + k_expand + k_finish", "ms": ms_heavy,
-                            "alg_bytes": bytes_heavy, "deferred_sets": mtot["deferred"],
-                            "supersteps": mtot["supersteps"],
-                            "GBps": bytes_heavy / (ms_heavy * 1e-3) / 1e9 if ms_heavy > 0 else 0.0},
-    }
+    kernel_bytes = mtot["bytes_light"] + mtot["bytes_heavy"] + mtot["bytes_bundled"]
+    # the kernels count the bytes of every expansion they perform; the pools'
+    # final prefixes can only hold fewer (sets generated ahead of a round that
+    # was not reached are spent work)
+    assert kernel_bytes >= alg_bytes, (kernel_bytes, alg_bytes)
+    # dominant expansion kernel: the largest event-timed share
+    times = {k: mean_total(f[0]) for k, f in KERNELS.items()}
+    kern = max(times, key=times.get)
+    f_ms, f_launch, f_bytes, f_px = KERNELS[kern]
+    k_ms = times[kern]
+    k_launches = mtot[f_launch] if f_launch else 1
+    k_bytes = mtot[f_bytes]
+    if f_px is None:
+        k_px = mtot["philox_drawn"] - mtot["philox_light"] - mtot["philox_bundled"]
+    else:
+        k_px = mtot[f_px]
+    per_launch_s = k_ms * 1e-3 / max(k_launches, 1)
+    alg_per_launch = k_bytes / max(k_launches, 1)
+    px_per_launch = k_px / max(k_launches, 1)
+    hbm_achieved = alg_per_launch / per_launch_s / 1e9 if per_launch_s > 0 else 0.0
+    px_achieved = px_per_launch / per_launch_s if per_launch_s > 0 else 0.0
+    frac_hbm = hbm_achieved / HBM_PEAK_GBS
+    frac_valu = px_achieved / PHILOX_PEAK_BLOCKS_PER_S
+    traffic = kernel_traffic(kern, args.workload)
+    # bound: counters below the algorithmic bytes mean the bytes come from
+    # caches and the integer ALU binds; without counters, the larger fraction
+    if traffic is not None:
+        bound = "alu" if traffic < alg_per_launch else "hbm"
+    else:
+        bound = "alu" if frac_valu >= frac_hbm else "hbm"
+    if bound == "alu":
+        roof = {"bound": "alu", "achieved": px_achieved / 1e9, "peak": PHILOX_PEAK_BLOCKS_PER_S / 1e9,
+                "unit": "Gblocks/s (Philox4x32-10 on the VALU)", "frac": frac_valu}
+    else:
+        roof = {"bound": "hbm", "achieved": hbm_achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": frac_hbm}
+    roof.update({
+        "kernel": kern,
+        "traffic": traffic,
+        "frac_hbm": frac_hbm,
+        "frac_valu": frac_valu,
+        "alg_bytes_per_launch": alg_per_launch,
+        "philox_blocks_per_launch": px_per_launch,
+        "avg_launch_ms": per_launch_s * 1e3,
+        "launches_per_step": k_launches,
+        "philox_peak_derivation": f"{VALU_LANE_OPS_PER_S / 1e12:.1f}e12 VALU lane-ops/s / "
+                                  f"({PHILOX_XOR} + {PHILOX_MAD} x {PHILOX_MAD_PASSES}) per block",
+    })
+    if px_rate:
+        roof["philox_measured_peak_gblocks_s"] = px_rate["blocks_per_s"] / 1e9
+    bfs_ms = mean_total("ms_bfs")
     line = {
         "metric": "RR sets/s",
         "value": value,
@@ -258,39 +342,32 @@ def main():
                    "form": "persistent" if args.form == 0 else "plain-per-stratum",
                    "tuning": tuning if tuning else "default",
                    "parallelism": "single-gpu"},
-        "incidences_per_s": inc_per_s,
+        "incidences_per_s": mtot["incidences"] * per_s,
+        "coins_per_s": mtot["coins"] * per_s,
+        "philox_blocks_per_s": {"drawn": mtot["philox_drawn"] * per_s, "per_set_traversal": mtot["philox_alg"] * per_s},
         "time_to_seed_set_ms": ms_per_step,
         "theta": [r["theta"] for r in last] if len(last) > 1 else last[0]["theta"],
         "rounds": max(r["rounds"] for r in last),
         "spread": [r["spread"] for r in last] if len(last) > 1 else last[0]["spread"],
         "ms_rr": mean_total("ms_rr"),
         "ms_greedy": mean_total("ms_greedy"),
-        "rr_phases": phases,
-        "roofline": {
-            "kernel": "k_expand",
-            "bound": "hbm",
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": traffic,
-            "alg_bytes_per_launch": bytes_heavy / max(expand_launches, 1),
-            "avg_launch_ms": ms_expand / max(expand_launches, 1),
-            "launches_per_step": expand_launches,
-        },
+        "kernels_ms": {k: v for k, v in times.items()},
+        "roofline": roof,
         "rr_generation": {
-            "kernels": "k_rr_light, k_plan, k_expand, k_finish",
-            "achieved_GBps": achieved_all,
-            "frac": achieved_all / HBM_PEAK_GBS,
+            "kernels": "k_rr_light, k_plan, k_expand, k_finish, k_ms_*",
+            "achieved_GBps": kernel_bytes / (bfs_ms * 1e-3) / 1e9 if bfs_ms > 0 else 0.0,
+            "frac_hbm": kernel_bytes / (bfs_ms * 1e-3) / 1e9 / HBM_PEAK_GBS if bfs_ms > 0 else 0.0,
             "ms": bfs_ms,
-            "launches_per_step": launches,
+            "launches_per_step": totals[-1]["bfs_launches"],
+            "deferred_sets": mtot["deferred"],
+            "supersteps": mtot["supersteps"],
         },
     }
     if plain is not None:
         plain["batched_speedup"] = plain["ms_per_step"] / ms_per_step
         line["plain_form"] = plain
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(hgs[0], ws[0], args.cpu_seconds)
+        line["cpu_baseline"] = cpu_baseline(hgs[0], ws[0], args.cpu_seconds, args.workload)
     print(json.dumps(line), flush=True)
 
 

@@ -129,11 +129,29 @@ typedef struct {
     uint64_t deferred;      /* RR sets handed to the grid-wide phase           */
     uint64_t supersteps;    /* grid-wide supersteps launched                   */
     uint64_t bytes_light;   /* algorithmic bytes expanded by the per-set phase */
-    uint64_t bytes_heavy;   /* algorithmic bytes expanded by the grid-wide one */
+    uint64_t bytes_heavy;   /* ... by the grid-wide phase's per-set expansion  */
     double ms_expand;       /* with HYPERIM_FLAG_KERNEL_TIMES: part of ms_heavy
-                               spent in the expansion kernel
-                               itself (events each launch stamps)          */
+                               spent in the per-set expansion kernel of the
+                               grid-wide phase (events each launch stamps)  */
     uint64_t expand_launches; /* its launches (one per superstep)              */
+    uint64_t philox_drawn;  /* Philox4x32-10 blocks the RR-generation kernels
+                               drew (a block gives the coins of up to four
+                               channels; channels from members a set already
+                               holds need none)                               */
+    uint64_t coins;         /* with HYPERIM_FLAG_INCIDENCES: channels of the
+                               final pools' members, sum of c(v) = S(v) - d(v)
+                               over the members of R1[0, theta) and
+                               R2[0, theta)                                   */
+    uint64_t philox_alg;    /* with HYPERIM_FLAG_INCIDENCES: Philox blocks a
+                               per-set traversal of the same sets draws, sum
+                               over their members of sum over v's hyperedges
+                               of ceil(|he| / 4)                              */
+    uint64_t philox_bundled; /* part of philox_drawn drawn in bundled mode     */
+    uint64_t bytes_bundled; /* algorithmic bytes expanded in bundled mode      */
+    double ms_bundled;      /* with HYPERIM_FLAG_KERNEL_TIMES: device time of
+                               the bundled expansion kernel's launches        */
+    uint64_t bundled_launches; /* its launches                                */
+    uint64_t philox_light;  /* part of philox_drawn drawn by the per-set phase */
 } hyperim_result;
 
 /* Build the device-resident hypergraph (Section 2.1: G = (V, HE), V(he)).

@@ -53,7 +53,10 @@ class _Result(C.Structure):
                 ("ms_total", C.c_double), ("alg_bytes", C.c_uint64), ("ms_bfs", C.c_double),
                 ("bfs_launches", C.c_uint64), ("ms_light", C.c_double), ("ms_heavy", C.c_double),
                 ("deferred", C.c_uint64), ("supersteps", C.c_uint64), ("bytes_light", C.c_uint64),
-                ("bytes_heavy", C.c_uint64), ("ms_expand", C.c_double), ("expand_launches", C.c_uint64)]
+                ("bytes_heavy", C.c_uint64), ("ms_expand", C.c_double), ("expand_launches", C.c_uint64),
+                ("philox_drawn", C.c_uint64), ("coins", C.c_uint64), ("philox_alg", C.c_uint64),
+                ("philox_bundled", C.c_uint64), ("bytes_bundled", C.c_uint64), ("ms_bundled", C.c_double),
+                ("bundled_launches", C.c_uint64), ("philox_light", C.c_uint64)]
 
 
 class _Tuning(C.Structure):

@@ -2,7 +2,9 @@
 
 Every .hip source under csrc/ is compiled to an object (device code for
 gfx950, code-object v5) and the objects are linked into
-paper_2406_01911_amd/libhyperim.so next to this file.
+paper_2406_01911_amd/libhyperim.so next to this file.  The Philox throughput
+probe (microbench/philox_rate.hip) is built into its own small library,
+microbench/libphilox_rate.so, which the benchmark loads.
 """
 from __future__ import annotations
 
@@ -17,6 +19,8 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libhyperim.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
+MICRO = os.path.join(HERE, "microbench")
+MICRO_LIB = os.path.join(MICRO, "libphilox_rate.so")
 
 ARCH = os.environ.get("HYPERIM_ARCH", "gfx950")
 FLAGS = [
@@ -62,8 +66,14 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError("link failed:\n" + r.stdout)
     os.replace(tmp, LIB)
+    tmp = MICRO_LIB + ".tmp%d" % os.getpid()
+    cmd = [hipcc(), *FLAGS, "-shared", os.path.join(MICRO, "philox_rate.hip"), "-o", tmp]
+    r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("philox_rate build failed:\n" + r.stdout)
+    os.replace(tmp, MICRO_LIB)
     if verbose:
-        print("built", LIB)
+        print("built", LIB, "and", MICRO_LIB)
     return LIB
 
 

@@ -182,15 +182,15 @@ SharedBytes shared_bytes() {
 
 size_t graph_bytes(hyperim_graph g) {
     size_t b = 0;
-    for (const DevBuf *x : {&g->he_off, &g->he_mem, &g->v_off, &g->v_he, &g->thr, &g->c, &g->weight, &g->bytesw, &g->l,
-                            &g->deg, &g->top, &g->stratum, &g->P})
+    for (const DevBuf *x : {&g->he_off, &g->he_mem, &g->v_off, &g->v_he, &g->thr, &g->c, &g->weight, &g->bytesw,
+                            &g->phiw, &g->l, &g->deg, &g->top, &g->stratum, &g->P})
         b += x->bytes;
     return b;
 }
 
 void release_graph(hyperim_graph g) {
-    for (DevBuf *b : {&g->he_off, &g->he_mem, &g->v_off, &g->v_he, &g->thr, &g->c, &g->weight, &g->bytesw, &g->l,
-                      &g->deg, &g->top, &g->stratum, &g->P})
+    for (DevBuf *b : {&g->he_off, &g->he_mem, &g->v_off, &g->v_he, &g->thr, &g->c, &g->weight, &g->bytesw,
+                      &g->phiw, &g->l, &g->deg, &g->top, &g->stratum, &g->P})
         b->release();
 }
 

@@ -289,6 +289,25 @@ __global__ void k_thresholds(uint32_t n, uint32_t model, float p, const uint32_t
     bytesw[v] = 20ull + 16ull * d + 4ull * c[v];
 }
 
+// Philox blocks of a vertex's expansion: sum over its hyperedges of
+// ceil(|he| / 4).  One wavefront per vertex.
+__global__ __launch_bounds__(kBlock) void k_philox_weight(uint32_t n, const uint32_t *__restrict__ v_off,
+                                                          const uint32_t *__restrict__ v_he,
+                                                          const uint32_t *__restrict__ he_off,
+                                                          unsigned long long *__restrict__ phiw) {
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint64_t waves = (uint64_t)gridDim.x * (kBlock / kWave);
+    for (uint64_t v = (uint64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave; v < n; v += waves) {
+        unsigned long long acc = 0;
+        for (uint32_t e = v_off[v] + lane; e < v_off[v + 1]; e += kWave) {
+            const uint32_t he = v_he[e];
+            acc += (he_off[he + 1] - he_off[he] + 3u) / 4u;
+        }
+        acc = wave_sum(acc);
+        if (lane == 0) phiw[v] = acc;
+    }
+}
+
 uint32_t grid_for(uint64_t items, uint32_t block = kBlock, uint32_t cap = 65535u * 8u) {
     uint64_t g = div_up(items, block);
     if (g == 0) g = 1;
@@ -363,10 +382,15 @@ int graph_build_device(hyperim_graph g, PrepWorkspace &w, hipStream_t s) {
     HIM_CHECK(g->thr.reserve(sizeof(uint32_t) * std::max<uint32_t>(n, 1), s));
     HIM_CHECK(g->weight.reserve(sizeof(uint64_t) * std::max<uint32_t>(n, 1), s));
     HIM_CHECK(g->bytesw.reserve(sizeof(uint64_t) * std::max<uint32_t>(n, 1), s));
-    if (n)
+    HIM_CHECK(g->phiw.reserve(sizeof(uint64_t) * std::max<uint32_t>(n, 1), s));
+    if (n) {
         hipLaunchKernelGGL(k_thresholds, dim3(grid_for(n)), dim3(kBlock), 0, s, n, g->prob.model, g->prob.p,
                            g->v_off.as<uint32_t>(), g->c.as<unsigned long long>(), g->thr.as<uint32_t>(),
                            g->weight.as<unsigned long long>(), g->bytesw.as<unsigned long long>());
+        hipLaunchKernelGGL(k_philox_weight, dim3(grid_for((uint64_t)n * kWave, kBlock, 8192)), dim3(kBlock), 0, s, n,
+                           g->v_off.as<uint32_t>(), g->v_he.as<uint32_t>(), g->he_off.as<uint32_t>(),
+                           g->phiw.as<unsigned long long>());
+    }
     HIM_HIP(hipGetLastError());
     HIM_HIP(hipStreamSynchronize(s));
     return HYPERIM_OK;

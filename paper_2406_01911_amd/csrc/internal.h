@@ -85,6 +85,12 @@ struct RRStats {
     uint64_t bytes_light = 0, bytes_heavy = 0;   // algorithmic bytes expanded in each phase
     double ms_expand = 0.0;                      // k_expand launches alone
     uint64_t expand_launches = 0;
+    double ms_bundled = 0.0;                     // k_ms_expand launches alone
+    uint64_t bundled_launches = 0;
+    uint64_t bytes_bundled = 0;                  // algorithmic bytes expanded in bundled mode
+    uint64_t philox = 0;                         // Philox4x32-10 blocks drawn (all kernels)
+    uint64_t philox_light = 0;                   // ... of which in the per-set phase
+    uint64_t philox_bundled = 0;                 // ... of which in bundled mode
 };
 
 // Workspace of greedy / coverage: one per device, shared by every graph on it.
@@ -146,8 +152,9 @@ struct hyperim_graph_s {
     uint64_t nnz = 0;
     hyperim_prob prob{};
     // weight = d(v) + S(v) incidences read when v is expanded; bytesw = 20 + 12 d(v) + 4 S(v)
-    // algorithmic bytes of v as an RR-set member (d = hyperedges of v, S = their total size)
-    hyperim::DevBuf he_off, he_mem, v_off, v_he, thr, c, weight, bytesw;
+    // algorithmic bytes of v as an RR-set member (d = hyperedges of v, S = their total size);
+    // phiw = sum over v's hyperedges of ceil(|he| / 4), the Philox blocks of v's expansion
+    hyperim::DevBuf he_off, he_mem, v_off, v_he, thr, c, weight, bytesw, phiw;
     bool stratified = false;
     hyperim::DevBuf l, deg, top, stratum, P;
     hyperim_strata_info info{};
@@ -253,10 +260,13 @@ int rr_generate_into(RRWorkspace &ws, RRStats &st, const std::vector<RRTask> &ta
                      uint64_t stage_budget, hipStream_t s, std::vector<int> &pool_status, bool time_kernels);
 // Make room in pool p for `ids` more ids and `entries` more members.
 int pool_reserve(hyperim_pool p, uint64_t ids, uint64_t entries, hipStream_t s);
-// Sums of weight[] (incidences) and bytesw[] (algorithmic bytes) over the
-// members of the pool's first theta sets.
-int rr_incidences(hyperim_graph g, hyperim_pool p, uint64_t theta, hipStream_t s, uint64_t *incidences,
-                  uint64_t *alg_bytes);
+// Work of the pool's first theta sets, summed over their members v:
+// incidences d(v) + S(v), algorithmic bytes, coins S(v) - d(v) = c(v) and
+// Philox blocks sum over v's hyperedges of ceil(|he| / 4).
+struct RRWork {
+    uint64_t incidences = 0, alg_bytes = 0, coins = 0, philox = 0;
+};
+int rr_incidences(hyperim_graph g, hyperim_pool p, uint64_t theta, hipStream_t s, RRWork *out);
 
 // ---- launchers (greedy.hip) ---------------------------------------------------
 // Greedy max coverage of the pool's first theta sets; the seeds also stay in

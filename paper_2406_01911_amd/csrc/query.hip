@@ -194,6 +194,12 @@ void add_stats(hyperim_result &res, const RRStats &st, float ms_rr) {
     res.bytes_heavy += st.bytes_heavy;
     res.ms_expand += st.ms_expand;
     res.expand_launches += st.expand_launches;
+    res.philox_drawn += st.philox;
+    res.philox_bundled += st.philox_bundled;
+    res.philox_light += st.philox_light;
+    res.bytes_bundled += st.bytes_bundled;
+    res.ms_bundled += st.ms_bundled;
+    res.bundled_launches += st.bundled_launches;
 }
 
 size_t device_shared_bytes() {
@@ -529,17 +535,21 @@ struct Engine {
             res.entries1 = e[0];
             res.entries2 = e[1];
             if (o.flags & HYPERIM_FLAG_INCIDENCES) {
-                uint64_t i1 = 0, i2 = 0, b1 = 0, b2 = 0;
-                HIM_CHECK(rr_incidences(g, &q->pp->r[0], theta, s, &i1, &b1));
-                HIM_CHECK(rr_incidences(g, &q->pp->r[1], theta, s, &i2, &b2));
-                res.incidences = i1 + i2;
-                res.alg_bytes = b1 + b2;
+                RRWork w1, w2;
+                HIM_CHECK(rr_incidences(g, &q->pp->r[0], theta, s, &w1));
+                HIM_CHECK(rr_incidences(g, &q->pp->r[1], theta, s, &w2));
+                res.incidences = w1.incidences + w2.incidences;
+                res.alg_bytes = w1.alg_bytes + w2.alg_bytes;
+                res.coins = w1.coins + w2.coins;
+                res.philox_alg = w1.philox + w2.philox;
             }
             total.entries1 += res.entries1;
             total.entries2 += res.entries2;
             total.theta += theta;
             total.incidences += res.incidences;
             total.alg_bytes += res.alg_bytes;
+            total.coins += res.coins;
+            total.philox_alg += res.philox_alg;
             res.ms_total =
                 std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - q->t0).count();
             q->done = true;

@@ -73,7 +73,13 @@ constexpr uint64_t kSlotBudget = 48ull << 30; // bytes of slot lists + bitmaps
 // counter s & 1 while its k_expand clears the other one for superstep s + 1.
 // kPlanned counts the frontier entries k_plan has taken (summed queue heads),
 // the progress measure of the host loop.
-enum Ctr { kWork = 0, kBump, kBigCount, kFreeNext, kDefCount, kItems, kItemsOther, kBytesA, kBytesB, kPlanned, kNumCtr };
+// kPhiloxA and kPhilox count the Philox4x32-10 blocks k_rr_light and k_expand
+// drew (lane blocks whose coins were needed); kBytesMs and kPhiloxMs are
+// bundled mode's algorithmic bytes and blocks.
+enum Ctr {
+    kWork = 0, kBump, kBigCount, kFreeNext, kDefCount, kItems, kItemsOther, kBytesA, kBytesB, kPlanned, kPhilox,
+    kBytesMs, kPhiloxMs, kPhiloxA, kNumCtr
+};
 
 // One graph of a launch group.
 struct GraphDesc {
@@ -307,7 +313,7 @@ struct ContAppend {
 template <bool kLds, class App>
 __device__ __forceinline__ void test_run(const GraphView &G, uint64_t j, uint32_t pool, uint2 key, uint32_t *bm,
                                          bool prefilter, bool active, uint32_t he, uint32_t hb, uint32_t p0,
-                                         uint32_t cm, uint32_t ve, uint32_t the, App &app) {
+                                         uint32_t cm, uint32_t ve, uint32_t the, App &app, uint64_t &px) {
     uint32_t u[8];
 #pragma unroll
     for (uint32_t t = 0; t < 8; ++t) u[t] = (t < kRun && active && t < cm) ? G.he_mem[hb + p0 + t] : ve;
@@ -336,7 +342,10 @@ __device__ __forceinline__ void test_run(const GraphView &G, uint64_t j, uint32_
 #pragma unroll
     for (uint32_t q = 0; q < kQ; ++q) {
         uint4 c = make_uint4(0u, 0u, 0u, 0u);
-        if (__ballot(need[q]) != 0 && need[q]) c = philox4x32_10(coin_counter(j, he, ve, pool, (p0 >> 2) + q), key);
+        if (__ballot(need[q]) != 0 && need[q]) {
+            c = philox4x32_10(coin_counter(j, he, ve, pool, (p0 >> 2) + q), key);
+            ++px;
+        }
         w[4 * q] = c.x;
         w[4 * q + 1] = c.y;
         w[4 * q + 2] = c.z;
@@ -378,7 +387,7 @@ __device__ __forceinline__ void test_run(const GraphView &G, uint64_t j, uint32_
 template <bool kLds, bool kUniform, class App>
 __device__ __forceinline__ uint64_t expand(const GraphView &G, WaveLds &L, uint64_t j, uint32_t pool, uint2 key,
                                            uint32_t *bm, bool prefilter, uint32_t v, uint32_t e0, uint32_t d,
-                                           App &app, uint32_t w = 0, uint32_t W = 1) {
+                                           App &app, uint64_t &px, uint32_t w = 0, uint32_t W = 1) {
     const uint32_t lane = lane_id();
     uint32_t D = d;
     uint32_t th_uniform = 0;
@@ -425,7 +434,7 @@ __device__ __forceinline__ uint64_t expand(const GraphView &G, WaveLds &L, uint6
         }
         // level 3, first pass: run 0 of the lane's own incidence
         if (sub_w == 0)
-            test_run<kLds>(G, j, pool, key, bm, prefilter, no > 0, he, hb, 0u, min(kRun, hs), vv, th, app);
+            test_run<kLds>(G, j, pool, key, bm, prefilter, no > 0, he, hb, 0u, min(kRun, hs), vv, th, app, px);
         // second pass: runs 1.. of the longer hyperedges, flattened over the wave
         const uint32_t rem = no > 1 ? no - 1u : 0u;
         if (__ballot(rem > 0) == 0) continue;
@@ -457,7 +466,7 @@ __device__ __forceinline__ uint64_t expand(const GraphView &G, WaveLds &L, uint6
                     the = L.in_thr[k];
                 }
             }
-            test_run<kLds>(G, j, pool, key, bm, prefilter, active, hee, hbk, p0, cm, ve, the, app);
+            test_run<kLds>(G, j, pool, key, bm, prefilter, active, hee, hbk, p0, cm, ve, the, app, px);
         }
     }
     wave_sync();
@@ -493,7 +502,7 @@ __global__ __launch_bounds__(kWG) void k_rr_light(RRArgs a) {
     }
     wave_sync();
     bool can_defer = !kLdsBitmap;
-    uint64_t bytes_done = 0;
+    uint64_t bytes_done = 0, px = 0;
 
     for (;;) {
         unsigned long long idx = 0;
@@ -550,7 +559,7 @@ __global__ __launch_bounds__(kWG) void k_rr_light(RRArgs a) {
             head += nb;
             spent += wave_bcast(wave_incl_scan(d), kWave - 1);
             bytes_done += 20ull * nb;
-            bytes_done += expand<kLdsBitmap, false>(G, L, S.j, S.pool, S.key, bm, false, v, e0, d, app);
+            bytes_done += expand<kLdsBitmap, false>(G, L, S.j, S.pool, S.key, bm, false, v, e0, d, app, px);
         }
         if (deferred) continue;
         const uint32_t size = app.size;
@@ -612,6 +621,8 @@ __global__ __launch_bounds__(kWG) void k_rr_light(RRArgs a) {
         wave_sync();
     }
     if (lane == 0 && bytes_done) atomicAdd(&a.ctr[kBytesA], bytes_done);
+    px = wave_sum(px);
+    if (lane == 0 && px) atomicAdd(&a.ctr[kPhiloxA], (unsigned long long)px);
 }
 
 // ---- phase B ---------------------------------------------------------------
@@ -719,7 +730,7 @@ __global__ __launch_bounds__(kWG) void k_expand(RRArgs a, uint32_t parity) {
     WaveLds &L = lds[wv];
     const uint64_t nitems = min(a.ctr[kItems + parity], (unsigned long long)kItemCap);
     if (blockIdx.x == 0 && threadIdx.x == 0) a.ctr[kItems + (parity ^ 1u)] = 0ull;   // next superstep's counter
-    uint64_t bytes_done = 0;
+    uint64_t bytes_done = 0, px = 0;
     // items have bounded cost (< seg + chunk incidences), so a static strided
     // assignment balances well and needs no shared counter.  With fewer items
     // than waves (the thin tail of a traversal), W waves share each item.
@@ -754,11 +765,11 @@ __global__ __launch_bounds__(kWG) void k_expand(RRArgs a, uint32_t parity) {
                 if (heavy_split(deg, a.chunk).count) deg = 0;   // expanded by its heavy items
             }
             if (w == 0) bytes_done += 20ull * (uint64_t)__popcll(__ballot((raw & kExpanded) == 0u));
-            bytes_done += expand<false, false>(G, L, S.j, S.pool, S.key, bm, prefilter, v, e0, deg, app, w, W);
+            bytes_done += expand<false, false>(G, L, S.j, S.pool, S.key, bm, prefilter, v, e0, deg, app, px, w, W);
         } else {
             // one heavy vertex: incidences [item.z, item.w) of vertex item.y
             bytes_done += expand<false, true>(G, L, S.j, S.pool, S.key, bm, prefilter, item.y, item.z,
-                                              item.w - item.z, app, w, W);
+                                              item.w - item.z, app, px, w, W);
         }
         // Continuation: when this wave appended at most 64 members, all light
         // and together under seg incidences, it expands them itself (up to
@@ -782,10 +793,12 @@ __global__ __launch_bounds__(kWG) void k_expand(RRArgs a, uint32_t parity) {
             if (lane < cn) list[pos] = v | kExpanded;
             app.count = 0;
             bytes_done += 20ull * cn;
-            bytes_done += expand<false, false>(G, L, S.j, S.pool, S.key, bm, prefilter, v, e0, deg, app, 0u, 1u);
+            bytes_done += expand<false, false>(G, L, S.j, S.pool, S.key, bm, prefilter, v, e0, deg, app, px, 0u, 1u);
         }
     }
     if (lane == 0 && bytes_done) atomicAdd(&a.ctr[kBytesB], bytes_done);
+    px = wave_sum(px);
+    if (lane == 0 && px) atomicAdd(&a.ctr[kPhilox], (unsigned long long)px);
 }
 
 // One workgroup per deferred set: ascending members into the stage, per-id
@@ -893,6 +906,7 @@ struct MsArgs {
     uint64_t list_cap;                  // entries of each list
     unsigned long long *ctr;            // MsCtr
     unsigned long long *bytes;          // algorithmic bytes (RR counter block)
+    unsigned long long *philox;         // Philox blocks drawn (RR counter block)
     uint4 *items;
     uint32_t *vcnt;                     // output: per (bundle, vertex block, set) counts
     uint32_t nvb;                       // vertex blocks per bundle
@@ -1081,7 +1095,7 @@ __global__ __launch_bounds__(kWG) void k_ms_plan(MsArgs m) {
 // (quad, set) pairs whose coins are needed: the sets of the entry's mask
 // that do not hold the member yet.
 __device__ __forceinline__ void ms_expand(const MsArgs &m, const GraphView &G, MsLds &L, uint32_t b, uint32_t v,
-                                          unsigned long long mask, uint32_t e0, uint32_t d) {
+                                          unsigned long long mask, uint32_t e0, uint32_t d, uint64_t &px) {
     const uint32_t lane = lane_id();
     const uint32_t dscan = wave_incl_scan(d);
     const uint32_t D = uni(wave_bcast(dscan, kWave - 1));
@@ -1180,6 +1194,7 @@ __device__ __forceinline__ void ms_expand(const MsArgs &m, const GraphView &G, M
                     const uint64_t j = m.first_id + (uint64_t)bk * kMsSets + s;
                     const uint4 c = philox4x32_10(coin_counter(j, L.q_he[k], vk, m.pool, L.q_q[k]),
                                                   make_uint2(m.key0, m.key1));
+                    ++px;
                     const uint32_t w[4] = {c.x, c.y, c.z, c.w};
                     const unsigned long long bit = 1ull << s;
                     const uint64_t row = (uint64_t)bk * m.stride;
@@ -1207,6 +1222,7 @@ __global__ __launch_bounds__(kWG) void k_ms_expand(MsArgs m) {
     const uint64_t nitems = min(m.ctr[kMsItems], (unsigned long long)kItemCap);
     const uint64_t waves = (uint64_t)gridDim.x * kWavesPerWG;
     const uint32_t lane = lane_id();
+    uint64_t px = 0;
     for (uint64_t it = (uint64_t)blockIdx.x * kWavesPerWG + wv; it < nitems; it += waves) {
         const uint4 ld = m.items[it];
         const uint4 item = make_uint4(uni(ld.x), uni(ld.y), uni(ld.z), uni(ld.w));
@@ -1224,7 +1240,7 @@ __global__ __launch_bounds__(kWG) void k_ms_expand(MsArgs m) {
                 d = G.v_off[v + 1] - e0;
                 if (ms_heavy_split(d, (uint32_t)__popcll(mask), m.chunk).count) d = 0;   // expanded by its heavy items
             }
-            ms_expand(m, G, L, b, v, mask, e0, d);
+            ms_expand(m, G, L, b, v, mask, e0, d, px);
         } else {
             // one heavy vertex: incidences [item.y, item.z) of entry item.x
             const uint32_t f = item.x & 0x7FFFFFFFu;
@@ -1233,10 +1249,12 @@ __global__ __launch_bounds__(kWG) void k_ms_expand(MsArgs m) {
             // the chunk's incidences go to lanes in runs of up to 64 entries
             for (uint32_t e = item.y; e < item.z; e += kWave) {
                 const uint32_t mine = e + lane < item.z ? 1u : 0u;
-                ms_expand(m, G, L, b, v, mask, e + lane, mine);
+                ms_expand(m, G, L, b, v, mask, e + lane, mine, px);
             }
         }
     }
+    px = wave_sum(px);
+    if (lane == 0 && px) atomicAdd(m.philox, (unsigned long long)px);
 }
 
 // Output, pass 1: per (bundle, block of kMsOutVerts vertices) member counts
@@ -1379,22 +1397,31 @@ __global__ __launch_bounds__(kWG) void k_move_big(const uint64_t *__restrict__ b
     }
 }
 
+// Sums of four per-vertex weights over the members of a pool prefix.
 __global__ __launch_bounds__(kWG) void k_weight_sum(const uint32_t *__restrict__ mem, uint64_t entries,
                                                      const unsigned long long *__restrict__ w0,
                                                      const unsigned long long *__restrict__ w1,
+                                                     const unsigned long long *__restrict__ w2,
+                                                     const unsigned long long *__restrict__ w3,
                                                      unsigned long long *__restrict__ out) {
-    unsigned long long a0 = 0, a1 = 0;
+    unsigned long long a0 = 0, a1 = 0, a2 = 0, a3 = 0;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < entries;
          i += (uint64_t)gridDim.x * blockDim.x) {
         const uint32_t v = mem[i];
         a0 += w0[v];
         a1 += w1[v];
+        a2 += w2[v];
+        a3 += w3[v];
     }
     a0 = wave_sum(a0);
     a1 = wave_sum(a1);
+    a2 = wave_sum(a2);
+    a3 = wave_sum(a3);
     if (lane_id() == 0) {
         atomicAdd(out, a0);
         atomicAdd(out + 1, a1);
+        atomicAdd(out + 2, a2);
+        atomicAdd(out + 3, a3);
     }
 }
 
@@ -1811,7 +1838,8 @@ int run_ms_launch(RRWorkspace &ws, RRStats &st, const hyperim_tuning &tune, RRAr
     m.batch_epoch = ws.ms_batch.as<uint32_t>();
     m.list_cap = list_cap;
     m.ctr = ws.ms_ctr.as<unsigned long long>();
-    m.bytes = a.ctr + kBytesB;
+    m.bytes = a.ctr + kBytesMs;
+    m.philox = a.ctr + kPhiloxMs;
     m.items = a.items;
     m.vcnt = ws.ms_vcnt.as<uint32_t>();
     m.nvb = nvb;
@@ -1873,9 +1901,9 @@ int run_ms_launch(RRWorkspace &ws, RRStats &st, const hyperim_tuning &tune, RRAr
         for (int k = 0; time_kernels && k < batch; ++k) {
             float me = 0.f;
             HIM_HIP(hipEventElapsedTime(&me, E[2 + 2 * k], E[3 + 2 * k]));
-            st.ms_expand += me;
+            st.ms_bundled += me;
         }
-        st.expand_launches += batch;
+        st.bundled_launches += batch;
         st.supersteps += batch;
         st.launches += 5 * batch;
         if (trace) {
@@ -2208,6 +2236,8 @@ int rr_generate_into(RRWorkspace &ws, RRStats &st, const std::vector<RRTask> &ta
             st.supersteps += run.supersteps;
             st.ms_expand += run.ms_expand;
             st.expand_launches += run.expand_launches;
+            st.ms_bundled += run.ms_bundled;
+            st.bundled_launches += run.bundled_launches;
             const unsigned long long *hf = ws.host + kHostFinal;
             const uint64_t bump = hf[kBump];
             for (const Slice &sl : slices) tasks[sl.task].g->rr_defer = (double)run.deferred / (double)a.count;
@@ -2215,6 +2245,10 @@ int rr_generate_into(RRWorkspace &ws, RRStats &st, const std::vector<RRTask> &ta
                 st.deferred += run.deferred;
                 st.bytes_light += hf[kBytesA];
                 st.bytes_heavy += hf[kBytesB];
+                st.bytes_bundled += hf[kBytesMs];
+                st.philox += hf[kPhiloxA] + hf[kPhilox] + hf[kPhiloxMs];
+                st.philox_light += hf[kPhiloxA];
+                st.philox_bundled += hf[kPhiloxMs];
                 staged = true;
             } else {
                 HIM_CHECK(ws.stage.reserve(sizeof(uint32_t) * (size_t)(bump + bump / 4 + 1024), s, false));
@@ -2250,26 +2284,28 @@ int rr_generate_into(RRWorkspace &ws, RRStats &st, const std::vector<RRTask> &ta
     return HYPERIM_OK;
 }
 
-int rr_incidences(hyperim_graph g, hyperim_pool p, uint64_t theta, hipStream_t s, uint64_t *incidences,
-                  uint64_t *alg_bytes) {
+int rr_incidences(hyperim_graph g, hyperim_pool p, uint64_t theta, hipStream_t s, RRWork *out) {
     uint64_t entries = 0;
     HIM_HIP(hipMemcpyAsync(&entries, p->off + theta, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
     HIM_HIP(hipStreamSynchronize(s));
     DevBuf acc;
-    HIM_CHECK(acc.reserve(2 * sizeof(unsigned long long), s));
-    HIM_HIP(hipMemsetAsync(acc.ptr, 0, 2 * sizeof(unsigned long long), s));
+    HIM_CHECK(acc.reserve(4 * sizeof(unsigned long long), s));
+    HIM_HIP(hipMemsetAsync(acc.ptr, 0, 4 * sizeof(unsigned long long), s));
     if (entries) {
         const uint32_t grid = (uint32_t)std::min<uint64_t>(div_up(entries, kWG), 4096);
         hipLaunchKernelGGL(k_weight_sum, dim3(grid), dim3(kWG), 0, s, p->mem, entries,
                            g->weight.as<unsigned long long>(), g->bytesw.as<unsigned long long>(),
+                           g->c.as<unsigned long long>(), g->phiw.as<unsigned long long>(),
                            acc.as<unsigned long long>());
     }
-    unsigned long long v[2] = {0, 0};
+    unsigned long long v[4] = {0, 0, 0, 0};
     HIM_HIP(hipMemcpyAsync(v, acc.ptr, sizeof(v), hipMemcpyDeviceToHost, s));
     HIM_HIP(hipStreamSynchronize(s));
     acc.release();
-    *incidences = v[0];
-    *alg_bytes = v[1];
+    out->incidences = v[0];
+    out->alg_bytes = v[1];
+    out->coins = v[2];
+    out->philox = v[3];
     return HYPERIM_OK;
 }
 
