@@ -887,8 +887,13 @@ __global__ __launch_bounds__(kWG) void k_finish(RRArgs a, uint32_t ndef) {
 // per-set traversal.
 constexpr uint32_t kMsSets = 64;
 constexpr uint32_t kMsOutVerts = 4096;   // vertices per output block (16 per thread)
+constexpr uint32_t kMsFilterSets = 24;   // masks of at least this many sets test seen masks before coins
 
-enum MsCtr { kMsCur = 0, kMsNext, kMsItems, kMsPending, kMsLevelDone, kMsDone, kMsEpoch, kMsOverflow, kMsNumCtr };
+// kMsFetch: next work item of the running expansion (waves fetch items one at
+// a time; item costs vary with hyperedge sizes).
+enum MsCtr {
+    kMsCur = 0, kMsNext, kMsItems, kMsPending, kMsLevelDone, kMsDone, kMsEpoch, kMsOverflow, kMsFetch, kMsNumCtr
+};
 
 struct MsArgs {
     GraphDesc graph;
@@ -1002,6 +1007,7 @@ __global__ void k_ms_ctl_expanded(unsigned long long *ctr) {
         ctr[kMsLevelDone] = 0ull;
     }
     ctr[kMsItems] = 0ull;
+    ctr[kMsFetch] = 0ull;
 }
 
 // After advancing: the new level's batches are pending; no frontier, done.
@@ -1088,12 +1094,71 @@ __global__ __launch_bounds__(kWG) void k_ms_plan(MsArgs m) {
     if (lane_id() == 0 && bytes) atomicAdd(m.bytes, bytes);
 }
 
+// Appends (bundle, vertex) pairs that just got their first bit in nxt to the
+// next-level list: one counter reservation per wavefront.  Every lane of the
+// wave calls it; lanes with `fresh` set contribute (b, u).
+__device__ __forceinline__ void ms_append_wave(const MsArgs &m, bool fresh, uint32_t b, uint32_t u) {
+    const uint64_t who = __ballot(fresh);
+    if (who == 0) return;
+    unsigned long long base = 0;
+    if (lane_id() == (uint32_t)__ffsll((unsigned long long)who) - 1u)
+        base = atomicAdd(&m.ctr[kMsNext], (unsigned long long)__popcll(who));
+    base = wave_bcast64(base, (int)__ffsll((unsigned long long)who) - 1);
+    if (fresh) {
+        const unsigned long long pos = base + lane_rank(who);
+        if (pos < m.list_cap) {
+            m.nx_b[pos] = b;
+            m.nx_v[pos] = u;
+        } else {
+            atomicOr(&m.ctr[kMsOverflow], 1ull);
+        }
+    }
+}
+
+// Coins of one (quad, set) pair: channels (he, u[t] -> v) for the candidate
+// positions t of set s, live ones marked in nxt (sets already holding u are
+// removed when the level advances).  Lanes with act = false only join the
+// wave-wide appends.
+__device__ __forceinline__ void ms_pair(const MsArgs &m, bool act, uint32_t bnd, uint32_t s, uint32_t he, uint32_t q,
+                                        uint32_t v, uint32_t thr, uint32_t cand4, const uint32_t (&u)[4],
+                                        uint64_t &px) {
+    uint4 c = make_uint4(0u, 0u, 0u, 0u);
+    if (act) {
+        c = philox4x32_10(coin_counter(m.first_id + (uint64_t)bnd * kMsSets + s, he, v, m.pool, q),
+                          make_uint2(m.key0, m.key1));
+        ++px;
+    }
+    const uint32_t w[4] = {c.x, c.y, c.z, c.w};
+    bool live[4];
+    bool any = false;
+#pragma unroll
+    for (uint32_t t = 0; t < 4; ++t) {
+        live[t] = act && ((cand4 >> t) & 1u) && channel_live(w[t], thr);
+        any |= live[t];
+    }
+    if (__ballot(any) == 0) return;   // with small probabilities most pairs have no live channel
+    const unsigned long long bit = 1ull << s;
+    const uint64_t row = (uint64_t)bnd * m.stride;
+#pragma unroll
+    for (uint32_t t = 0; t < 4; ++t) {
+        bool fresh = false;
+        if (live[t]) fresh = atomicOr(&m.nxt[row + u[t]], bit) == 0ull;
+        ms_append_wave(m, fresh, bnd, u[t]);
+    }
+}
+
 // Levels 2-4 of a bundled expansion.  Each lane brings a frontier entry
 // (bundle b, vertex v, set mask) and the incidence range [e0, e0 + d) of v to
 // expand (d = 0 for none).  Level 2 spreads the incidences over the wave,
 // level 3 the quads of member positions of those hyperedges, level 4 the
-// (quad, set) pairs whose coins are needed: the sets of the entry's mask
-// that do not hold the member yet.
+// (quad, set) pairs whose coins are drawn.  A quad whose entry carries at
+// least kMsFilterSets sets first reads its members' seen masks and keeps
+// only the sets that do not hold them; for smaller masks those scattered
+// loads cost more than the coins they would save, so every set of the mask
+// draws its coins and the level's advance drops what a set already holds.
+// When the wave's pair counts are even (no lane has more than twice the
+// mean), every lane walks its own quad's sets in registers; otherwise the
+// pairs are spread over the wave through LDS.
 __device__ __forceinline__ void ms_expand(const MsArgs &m, const GraphView &G, MsLds &L, uint32_t b, uint32_t v,
                                           unsigned long long mask, uint32_t e0, uint32_t d, uint64_t &px) {
     const uint32_t lane = lane_id();
@@ -1142,7 +1207,7 @@ __device__ __forceinline__ void ms_expand(const MsArgs &m, const GraphView &G, M
             uint32_t pc = 0;
             uint32_t u[4] = {0u, 0u, 0u, 0u};
             unsigned long long cand[4] = {0ull, 0ull, 0ull, 0ull}, un = 0ull;
-            uint32_t qhe = 0, qq = 0, qv = 0, qth = 0, qbnd = 0;
+            uint32_t qhe = 0, qq = 0, qv = 0, qth = 0, qbnd = 0, valid = 0;
             if (qg < Q) {
                 const uint32_t k = search64(L.in_scan, qg);
                 const uint32_t start = k ? L.in_scan[k - 1] : 0u;
@@ -1153,22 +1218,45 @@ __device__ __forceinline__ void ms_expand(const MsArgs &m, const GraphView &G, M
                 qbnd = L.in_b[k];
                 const unsigned long long qm = L.in_m[k];
                 const uint32_t p0 = 4u * qq, cnt = min(4u, L.in_hs[k] - p0);
-                const uint64_t row = (uint64_t)qbnd * m.stride;
 #pragma unroll
                 for (uint32_t t = 0; t < 4; ++t) u[t] = t < cnt ? G.he_mem[L.in_hb[k] + p0 + t] : qv;
-                unsigned long long sm[4];
 #pragma unroll
-                for (uint32_t t = 0; t < 4; ++t) sm[t] = t < cnt && u[t] != qv ? m.seen[row + u[t]] : ~0ull;
+                for (uint32_t t = 0; t < 4; ++t) valid |= (t < cnt && u[t] != qv) ? 1u << t : 0u;
+                if ((uint32_t)__popcll(qm) >= kMsFilterSets) {
+                    const uint64_t row = (uint64_t)qbnd * m.stride;
+                    unsigned long long sm[4];
 #pragma unroll
-                for (uint32_t t = 0; t < 4; ++t) {
-                    cand[t] = qm & ~sm[t];
-                    un |= cand[t];
+                    for (uint32_t t = 0; t < 4; ++t) sm[t] = ((valid >> t) & 1u) ? m.seen[row + u[t]] : ~0ull;
+#pragma unroll
+                    for (uint32_t t = 0; t < 4; ++t) cand[t] = qm & ~sm[t];
+                } else {
+#pragma unroll
+                    for (uint32_t t = 0; t < 4; ++t) cand[t] = ((valid >> t) & 1u) ? qm : 0ull;
                 }
+#pragma unroll
+                for (uint32_t t = 0; t < 4; ++t) un |= cand[t];
                 pc = (uint32_t)__popcll(un);
             }
             const uint32_t pscan = wave_incl_scan(pc);
             const uint32_t PT = uni(wave_bcast(pscan, kWave - 1));
             if (PT == 0) continue;
+            const uint32_t pmax = uni(wave_max(pc));
+            if ((uint64_t)pmax * kWave <= 2ull * PT) {
+                // level 4 in registers: lane walks the sets of its own quad
+                unsigned long long rem = un;
+                for (uint32_t r = 0; r < pmax; ++r) {
+                    const bool act = rem != 0ull;
+                    uint32_t s = 0, c4 = 0;
+                    if (act) {
+                        s = (uint32_t)__ffsll(rem) - 1u;
+                        rem &= rem - 1ull;
+#pragma unroll
+                        for (uint32_t t = 0; t < 4; ++t) c4 |= (uint32_t)((cand[t] >> s) & 1ull) << t;
+                    }
+                    ms_pair(m, act, qbnd, s, qhe, qq, qv, qth, c4, u, px);
+                }
+                continue;
+            }
             wave_sync();
             L.q_scan[lane] = pscan;
             L.q_he[lane] = qhe;
@@ -1184,29 +1272,27 @@ __device__ __forceinline__ void ms_expand(const MsArgs &m, const GraphView &G, M
             }
             wave_sync();
             for (uint32_t pb = 0; pb < PT; pb += kWave) {
-                // level 4: one (quad, set) pair per lane
+                // level 4 over the wave: one (quad, set) pair per lane
                 const uint32_t pg = pb + lane;
-                if (pg < PT) {
+                const bool act = pg < PT;
+                uint32_t s = 0, bk = 0, vk = 0, thk = 0, hek = 0, qk = 0, c4 = 0;
+                uint32_t uk[4] = {0u, 0u, 0u, 0u};
+                if (act) {
                     const uint32_t k = search64(L.q_scan, pg);
                     const uint32_t r = pg - (k ? L.q_scan[k - 1] : 0u);
-                    const uint32_t s = nth_bit(L.q_union[k], r);
-                    const uint32_t bk = L.q_b[k], vk = L.q_v[k], thk = L.q_thr[k];
-                    const uint64_t j = m.first_id + (uint64_t)bk * kMsSets + s;
-                    const uint4 c = philox4x32_10(coin_counter(j, L.q_he[k], vk, m.pool, L.q_q[k]),
-                                                  make_uint2(m.key0, m.key1));
-                    ++px;
-                    const uint32_t w[4] = {c.x, c.y, c.z, c.w};
-                    const unsigned long long bit = 1ull << s;
-                    const uint64_t row = (uint64_t)bk * m.stride;
+                    s = nth_bit(L.q_union[k], r);
+                    bk = L.q_b[k];
+                    vk = L.q_v[k];
+                    thk = L.q_thr[k];
+                    hek = L.q_he[k];
+                    qk = L.q_q[k];
 #pragma unroll
                     for (uint32_t t = 0; t < 4; ++t) {
-                        if ((L.q_cand[k][t] & bit) && channel_live(w[t], thk)) {
-                            const uint32_t ut = L.q_u[k][t];
-                            const unsigned long long old = atomicOr(&m.nxt[row + ut], bit);
-                            if (old == 0ull) ms_append_next(m, bk, ut);
-                        }
+                        c4 |= (uint32_t)((L.q_cand[k][t] >> s) & 1ull) << t;
+                        uk[t] = L.q_u[k][t];
                     }
                 }
+                ms_pair(m, act, bk, s, hek, qk, vk, thk, c4, uk, px);
             }
             wave_sync();
         }
@@ -1220,10 +1306,15 @@ __global__ __launch_bounds__(kWG) void k_ms_expand(MsArgs m) {
     MsLds &L = lds[wv];
     const GraphView G = graph_view(m.graph);
     const uint64_t nitems = min(m.ctr[kMsItems], (unsigned long long)kItemCap);
-    const uint64_t waves = (uint64_t)gridDim.x * kWavesPerWG;
     const uint32_t lane = lane_id();
     uint64_t px = 0;
-    for (uint64_t it = (uint64_t)blockIdx.x * kWavesPerWG + wv; it < nitems; it += waves) {
+    for (;;) {
+        // items cost up to a few times each other (hyperedge sizes vary
+        // inside a chunk), so waves take them one at a time
+        unsigned long long it = 0;
+        if (lane == 0) it = atomicAdd(&m.ctr[kMsFetch], 1ull);
+        it = uni64(wave_bcast64(it, 0));
+        if (it >= nitems) break;
         const uint4 ld = m.items[it];
         const uint4 item = make_uint4(uni(ld.x), uni(ld.y), uni(ld.z), uni(ld.w));
         if (item.x == kSkipItem) continue;
