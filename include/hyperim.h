@@ -253,6 +253,20 @@ int hyperim_greedy(hyperim_graph g, hyperim_pool pool, uint64_t theta, uint32_t 
 int hyperim_coverage(hyperim_graph g, hyperim_pool pool, uint64_t theta, const uint32_t *seeds,
                      uint32_t k, void *stream, uint64_t *covered);
 
+/* hyperim_coverage for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the seeds (seeds_dev[k]) and the result (*covered_dev) are in
+ * device memory, the work is queued on `stream` and the call returns without
+ * waiting.  It allocates nothing: its scratch (hit counters, n bytes of seed
+ * flags, 8 bytes per set for the sets above 4096 members) lives in a 32 MiB
+ * static device array of the library, held by every device the library runs
+ * on until the process ends; n + 8 theta above about 32 MiB gives
+ * HYPERIM_ECAPACITY.  Seed ids >= n are ignored.  Calls on one device share
+ * that array, so calls that overlap on one device race (order them on one
+ * stream); each call clears what it uses with a fill kernel, no memset. */
+int hyperim_coverage_noalloc(hyperim_graph g, hyperim_pool pool, uint64_t theta, const uint32_t *seeds_dev,
+                             uint32_t k, void *stream, uint64_t *covered_dev);
+
 /* HyperIM_BRR (Algorithm 4) with delta = n^-ell: pools R1 and R2 grow over
  * the ladder theta_i = theta_1 2^(i-1) (theta_1 = theta_0 of Section 4.3
  * rounded up to the ladder); S* = greedy on R1[0, theta_i); Lambda2 =
@@ -364,6 +378,11 @@ int hyperim_workspace_release(void);
  *                  occupancy limit (4; 0 = the occupancy limit);
  *   blocks_b:      grid-wide expansion workgroups per compute unit (6; 0 =
  *                  the occupancy limit);
+ *   ms_filter:     bundled mode reads the members' seen masks before drawing
+ *                  coins only for frontier entries that carry at least this
+ *                  many sets (1 = always; 65 = never: every set of an entry
+ *                  draws its coins and the level's advance drops members a
+ *                  set already holds);
  *   ms_min:        graphs whose RR sets hold at least this many members on
  *                  average (learned from earlier launches) grow their sets
  *                  in bundles of 64, bit-parallel over the sets: each vertex
@@ -373,7 +392,7 @@ int hyperim_workspace_release(void);
  *                  autotuner decides). */
 typedef struct {
     uint32_t heavy, budget, chunk, seg, prefilter_min, steps_per_sync;
-    uint32_t stage_mib, blocks_a, blocks_b, ms_min;
+    uint32_t stage_mib, blocks_a, blocks_b, ms_min, ms_filter;
 } hyperim_tuning;
 
 /* Set / read the execution parameters of graph g (host-side values).  A

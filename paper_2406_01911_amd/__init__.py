@@ -62,7 +62,8 @@ class _Result(C.Structure):
 class _Tuning(C.Structure):
     _fields_ = [("heavy", C.c_uint32), ("budget", C.c_uint32), ("chunk", C.c_uint32), ("seg", C.c_uint32),
                 ("prefilter_min", C.c_uint32), ("steps_per_sync", C.c_uint32), ("stage_mib", C.c_uint32),
-                ("blocks_a", C.c_uint32), ("blocks_b", C.c_uint32), ("ms_min", C.c_uint32)]
+                ("blocks_a", C.c_uint32), ("blocks_b", C.c_uint32), ("ms_min", C.c_uint32),
+                ("ms_filter", C.c_uint32)]
 
 
 class _Query(C.Structure):
@@ -82,11 +83,12 @@ class _SessionStats(C.Structure):
 
 
 TUNING_FIELDS = ["heavy", "budget", "chunk", "seg", "prefilter_min", "steps_per_sync", "stage_mib", "blocks_a",
-                 "blocks_b", "ms_min"]
+                 "blocks_b", "ms_min", "ms_filter"]
 
 EXPORTS = ["hyperim_build_graph", "hyperim_stratify", "hyperim_graph_read", "hyperim_pool_create",
            "hyperim_generate_rr", "hyperim_generate_rr_batch", "hyperim_pool_view", "hyperim_pool_read", "hyperim_pool_required",
-           "hyperim_pool_reset", "hyperim_greedy", "hyperim_coverage", "hyperim_select_seeds",
+           "hyperim_pool_reset", "hyperim_greedy", "hyperim_coverage", "hyperim_coverage_noalloc",
+           "hyperim_select_seeds",
            "hyperim_select_seeds_batch", "hyperim_session_create", "hyperim_session_submit",
            "hyperim_session_step", "hyperim_session_poll", "hyperim_session_drop", "hyperim_session_stats_get",
            "hyperim_session_free", "hyperim_workspace_info", "hyperim_workspace_release",
@@ -118,6 +120,7 @@ def load_library(path: str = LIB_PATH):
     L.hyperim_pool_reset.argtypes = [vp]
     L.hyperim_greedy.argtypes = [vp, vp, u64, u32, vp, vp, vp]
     L.hyperim_coverage.argtypes = [vp, vp, u64, vp, u32, vp, C.POINTER(u64)]
+    L.hyperim_coverage_noalloc.argtypes = [vp, vp, u64, vp, u32, vp, vp]
     L.hyperim_select_seeds.argtypes = [vp, u32, C.c_double, C.c_double, u64, u32, C.POINTER(_Options), vp, vp, vp,
                                        C.POINTER(_Result)]
     L.hyperim_select_seeds_batch.argtypes = [C.POINTER(_Query), u32, C.POINTER(_Options), vp, vp, vp,
@@ -315,6 +318,20 @@ def coverage(g: Graph, pool: Pool, theta: int, seeds, stream=None) -> int:
     _check(_lib.hyperim_coverage(g._h, pool._h, theta, _ptr(seeds) if seeds.size else None, seeds.size,
                                  _stream(stream), C.byref(out)))
     return out.value
+
+
+def coverage_noalloc(g: Graph, pool: Pool, theta: int, seeds_dev: torch.Tensor, out_dev: torch.Tensor,
+                     stream=None) -> None:
+    """hyperim_coverage_noalloc: seeds_dev (int32/uint32 device tensor of k
+    ids) and out_dev (one 64-bit device word) stay on the device; the call is
+    stream-ordered and does not wait."""
+    if seeds_dev.dtype not in (torch.int32,) or not seeds_dev.is_cuda or not seeds_dev.is_contiguous():
+        raise ValueError("seeds_dev must be a contiguous int32 CUDA tensor")
+    if out_dev.dtype != torch.int64 or not out_dev.is_cuda or out_dev.numel() < 1:
+        raise ValueError("out_dev must be an int64 CUDA tensor")
+    k = seeds_dev.numel()
+    _check(_lib.hyperim_coverage_noalloc(g._h, pool._h, theta, C.c_void_p(seeds_dev.data_ptr()) if k else None, k,
+                                         _stream(stream), C.c_void_p(out_dev.data_ptr())))
 
 
 def select_seeds(g: Graph, k: int, eps: float, ell: float, seed: int = 0, instance: int = 0, qlog: int = 0,

@@ -40,6 +40,7 @@ SPACE = {
     "blocks_a": [2, 3, 4, 6, 8],
     "blocks_b": [3, 4, 6, 8],
     "ms_min": [1024, 4096, 65536, 0xFFFFFFFF],
+    "ms_filter": [1, 4, 8, 16, 24, 40, 65],
 }
 
 

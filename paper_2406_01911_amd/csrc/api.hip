@@ -183,14 +183,14 @@ SharedBytes shared_bytes() {
 size_t graph_bytes(hyperim_graph g) {
     size_t b = 0;
     for (const DevBuf *x : {&g->he_off, &g->he_mem, &g->v_off, &g->v_he, &g->thr, &g->c, &g->weight, &g->bytesw,
-                            &g->phiw, &g->l, &g->deg, &g->top, &g->stratum, &g->P})
+                            &g->phiw, &g->v_hbs, &g->l, &g->deg, &g->top, &g->stratum, &g->P})
         b += x->bytes;
     return b;
 }
 
 void release_graph(hyperim_graph g) {
     for (DevBuf *b : {&g->he_off, &g->he_mem, &g->v_off, &g->v_he, &g->thr, &g->c, &g->weight, &g->bytesw,
-                      &g->phiw, &g->l, &g->deg, &g->top, &g->stratum, &g->P})
+                      &g->phiw, &g->v_hbs, &g->l, &g->deg, &g->top, &g->stratum, &g->P})
         b->release();
 }
 
@@ -567,6 +567,7 @@ int hyperim_set_tuning(hyperim_graph g, const hyperim_tuning *t) {
     if (t->blocks_a) cur.blocks_a = t->blocks_a;
     if (t->blocks_b) cur.blocks_b = t->blocks_b;
     if (t->ms_min) cur.ms_min = t->ms_min;
+    if (t->ms_filter) cur.ms_filter = std::min<uint32_t>(t->ms_filter, 65);
     return HYPERIM_OK;
 }
 

@@ -308,6 +308,16 @@ __global__ __launch_bounds__(kBlock) void k_philox_weight(uint32_t n, const uint
     }
 }
 
+// Per incidence: first member position and size of its hyperedge.
+__global__ void k_incidence_spans(uint64_t nnz, const uint32_t *__restrict__ v_he, const uint32_t *__restrict__ he_off,
+                                  uint2 *__restrict__ v_hbs) {
+    for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t he = v_he[e];
+        const uint32_t b = he_off[he];
+        v_hbs[e] = make_uint2(b, he_off[he + 1] - b);
+    }
+}
+
 uint32_t grid_for(uint64_t items, uint32_t block = kBlock, uint32_t cap = 65535u * 8u) {
     uint64_t g = div_up(items, block);
     if (g == 0) g = 1;
@@ -383,6 +393,10 @@ int graph_build_device(hyperim_graph g, PrepWorkspace &w, hipStream_t s) {
     HIM_CHECK(g->weight.reserve(sizeof(uint64_t) * std::max<uint32_t>(n, 1), s));
     HIM_CHECK(g->bytesw.reserve(sizeof(uint64_t) * std::max<uint32_t>(n, 1), s));
     HIM_CHECK(g->phiw.reserve(sizeof(uint64_t) * std::max<uint32_t>(n, 1), s));
+    HIM_CHECK(g->v_hbs.reserve(sizeof(uint2) * std::max<uint64_t>(nnz, 1), s));
+    if (nnz)
+        hipLaunchKernelGGL(k_incidence_spans, dim3(grid_for(nnz, kBlock, 8192)), dim3(kBlock), 0, s, nnz,
+                           g->v_he.as<uint32_t>(), g->he_off.as<uint32_t>(), g->v_hbs.as<uint2>());
     if (n) {
         hipLaunchKernelGGL(k_thresholds, dim3(grid_for(n)), dim3(kBlock), 0, s, n, g->prob.model, g->prob.p,
                            g->v_off.as<uint32_t>(), g->c.as<unsigned long long>(), g->thr.as<uint32_t>(),

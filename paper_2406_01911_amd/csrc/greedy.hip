@@ -16,6 +16,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 
 #include "dev_common.h"
 #include "internal.h"
@@ -245,9 +246,10 @@ __global__ __launch_bounds__(kWG) void k_invalidate(const GreedyParams *__restri
     }
 }
 
-__global__ void k_mark(const uint32_t *__restrict__ seeds, uint32_t k, uint8_t *__restrict__ flags) {
+// Seed flags; ids >= n are ignored.
+__global__ void k_mark(const uint32_t *__restrict__ seeds, uint32_t k, uint32_t n, uint8_t *__restrict__ flags) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < k) flags[seeds[i]] = 1;
+    if (i < k && seeds[i] < n) flags[seeds[i]] = 1;
 }
 
 __global__ __launch_bounds__(kWG) void k_hits_small(const uint64_t *__restrict__ off, const uint32_t *__restrict__ mem,
@@ -402,7 +404,8 @@ int coverage_device(GreedyWorkspace &w, hyperim_graph g, hyperim_pool p, uint64_
     unsigned long long *ctr = w.counters.as<unsigned long long>();
     HIM_HIP(hipMemsetAsync(w.flags.ptr, 0, n, s));
     HIM_HIP(hipMemsetAsync(ctr, 0, 4 * sizeof(unsigned long long), s));
-    hipLaunchKernelGGL(k_mark, dim3(grid_for(k, kWG, 65535)), dim3(kWG), 0, s, seeds_dev, k, w.flags.as<uint8_t>());
+    hipLaunchKernelGGL(k_mark, dim3(grid_for(k, kWG, 65535)), dim3(kWG), 0, s, seeds_dev, k, n,
+                       w.flags.as<uint8_t>());
     HIM_CHECK(big_list(p, theta, w.big.as<uint64_t>(), ctr + 1, s));
     if (theta) {
         hipLaunchKernelGGL(k_hits_small, dim3(grid_for(theta, kWG, 8192)), dim3(kWG), 0, s, p->off, p->mem, theta,
@@ -418,4 +421,83 @@ int coverage_device(GreedyWorkspace &w, hyperim_graph g, hyperim_pool p, uint64_
     return HYPERIM_OK;
 }
 
+// ---- coverage without allocation ---------------------------------------------
+// Scratch of hyperim_coverage_noalloc: the hit counters, the seed flags (n
+// bytes) and the list of big sets (8 bytes per set), in one static device
+// array.  Each device holds its own copy; host code uses the address that
+// hipGetSymbolAddress returns on that device, never the array's name.
+constexpr size_t kScratchBytes = 32ull << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+unsigned char *g_scratch[kMaxDevices] = {};
+
+// The device address of `scratch` on `device` (the current device), looked
+// up once per device.
+int scratch_address(int device, unsigned char **out) {
+    if (device < 0 || device >= kMaxDevices) {
+        set_error_detail("device index beyond the scratch table");
+        return HYPERIM_EINVAL;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mutex);
+    if (!g_scratch[device]) {
+        void *p = nullptr;
+        HIM_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        g_scratch[device] = static_cast<unsigned char *>(p);
+    }
+    *out = g_scratch[device];
+    return HYPERIM_OK;
+}
+
+__global__ void k_zero_words(unsigned long long *__restrict__ p, uint64_t words) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = 0ull;
+}
+
+__global__ void k_store_count(const unsigned long long *__restrict__ src, uint64_t *__restrict__ dst) { *dst = *src; }
+
+inline size_t round256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+}  // namespace
+
 }  // namespace hyperim
+
+using namespace hyperim;
+
+extern "C" int hyperim_coverage_noalloc(hyperim_graph g, hyperim_pool pool, uint64_t theta, const uint32_t *seeds_dev,
+                                        uint32_t k, void *stream, uint64_t *covered_dev) {
+    if (!g || !pool || pool->g != g || !covered_dev || (k && !seeds_dev)) return HYPERIM_EINVAL;
+    HIM_CHECK(check_device(g));
+    if (theta > pool->count || k > g->n) {
+        set_error_detail("need theta <= pool size and k <= n");
+        return HYPERIM_EINVAL;
+    }
+    // layout: counters (256 B), flags (n bytes, 256-aligned), big-set list
+    const size_t flags_at = 256, list_at = flags_at + round256(g->n);
+    if (list_at + 8 * theta > kScratchBytes) {
+        set_error_detail("coverage without allocation needs n + 8 theta bytes within its 32 MiB scratch");
+        return HYPERIM_ECAPACITY;
+    }
+    unsigned char *base = nullptr;
+    HIM_CHECK(scratch_address(g->device, &base));
+    hipStream_t s = as_stream(stream);
+    unsigned long long *ctr = reinterpret_cast<unsigned long long *>(base);
+    uint8_t *flags = base + flags_at;
+    uint64_t *list = reinterpret_cast<uint64_t *>(base + list_at);
+    const uint64_t words = list_at / 8;   // counters and flags start at zero
+    hipLaunchKernelGGL(k_zero_words, dim3(grid_for(words, kWG, 4096)), dim3(kWG), 0, s, ctr, words);
+    if (k) hipLaunchKernelGGL(k_mark, dim3(grid_for(k, kWG, 65535)), dim3(kWG), 0, s, seeds_dev, k, g->n, flags);
+    if (theta) {
+        hipLaunchKernelGGL(k_big_list, dim3(grid_for(theta, kWG, 4096)), dim3(kWG), 0, s, pool->off, theta, list,
+                           ctr + 1);
+        hipLaunchKernelGGL(k_hits_small, dim3(grid_for(theta, kWG, 8192)), dim3(kWG), 0, s, pool->off, pool->mem,
+                           theta, flags, ctr);
+        hipLaunchKernelGGL(k_hits_big, dim3(1024), dim3(kWG), 0, s, list, ctr + 1, pool->off, pool->mem, flags, ctr);
+    }
+    hipLaunchKernelGGL(k_store_count, dim3(1), dim3(1), 0, s, ctr, covered_dev);
+    HIM_HIP(hipGetLastError());
+    return HYPERIM_OK;
+}

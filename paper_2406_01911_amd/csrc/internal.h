@@ -154,11 +154,12 @@ struct hyperim_graph_s {
     // weight = d(v) + S(v) incidences read when v is expanded; bytesw = 20 + 12 d(v) + 4 S(v)
     // algorithmic bytes of v as an RR-set member (d = hyperedges of v, S = their total size);
     // phiw = sum over v's hyperedges of ceil(|he| / 4), the Philox blocks of v's expansion
-    hyperim::DevBuf he_off, he_mem, v_off, v_he, thr, c, weight, bytesw, phiw;
+    // v_hbs[e] = (he_off[v_he[e]], size of that hyperedge), uint2 per incidence
+    hyperim::DevBuf he_off, he_mem, v_off, v_he, thr, c, weight, bytesw, phiw, v_hbs;
     bool stratified = false;
     hyperim::DevBuf l, deg, top, stratum, P;
     hyperim_strata_info info{};
-    hyperim_tuning tune{1024, 262144, 256, 512, 0xFFFFFFFFu, 8, 16384, 4, 6, 0xFFFFFFFFu};  // RR execution parameters
+    hyperim_tuning tune{1024, 262144, 256, 512, 0xFFFFFFFFu, 8, 16384, 4, 6, 0xFFFFFFFFu, 1};  // RR execution parameters
     // learned from generated sets (launch-group and stage sizing, admission);
     // -1 = nothing generated yet
     double rr_members = -1.0, rr_defer = -1.0;

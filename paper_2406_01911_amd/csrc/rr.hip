@@ -82,8 +82,11 @@ enum Ctr {
 };
 
 // One graph of a launch group.
+// v_hbs[e] = (first member position, size) of hyperedge v_he[e], beside the
+// incidence list so that an incidence's hyperedge needs no dependent load.
 struct GraphDesc {
     const uint32_t *he_off, *he_mem, *v_off, *v_he, *thr, *P;
+    const unsigned long long *v_hbs;   // low word: first position, high word: size
     uint32_t n, bm_words;
 };
 
@@ -93,6 +96,7 @@ struct GraphDesc {
 #define HIM_GLOBAL __attribute__((address_space(1)))
 struct GraphView {
     const HIM_GLOBAL uint32_t *he_off, *he_mem, *v_off, *v_he, *thr, *P;
+    const HIM_GLOBAL unsigned long long *v_hbs;
     uint32_t n, bm_words;
 };
 
@@ -106,6 +110,7 @@ __device__ __forceinline__ GraphView graph_view(const GraphDesc &d) {
     v.v_he = uni_ptr((const HIM_GLOBAL uint32_t *)d.v_he);
     v.thr = uni_ptr((const HIM_GLOBAL uint32_t *)d.thr);
     v.P = uni_ptr((const HIM_GLOBAL uint32_t *)d.P);
+    v.v_hbs = uni_ptr((const HIM_GLOBAL unsigned long long *)d.v_hbs);
     v.n = uni(d.n);
     v.bm_words = uni(d.bm_words);
     return v;
@@ -418,17 +423,18 @@ __device__ __forceinline__ uint64_t expand(const GraphView &G, WaveLds &L, uint6
         const uint32_t g = base + lane;
         uint32_t he = 0, hb = 0, hs = 0, vv = v, th = th_uniform, no = 0;
         if (g < D) {
-            if constexpr (kUniform) {
-                he = G.v_he[e0 + g];
-            } else {
+            uint32_t e = e0 + g;
+            if constexpr (!kUniform) {
                 const uint32_t k = search64(L.fr_scan, g);
                 const uint32_t start = k ? L.fr_scan[k - 1] : 0u;
                 vv = L.fr_v[k];
-                he = G.v_he[L.fr_e0[k] + (g - start)];
+                e = L.fr_e0[k] + (g - start);
                 th = G.thr[vv];
             }
-            hb = G.he_off[he];
-            hs = G.he_off[he + 1] - hb;
+            he = G.v_he[e];
+            const unsigned long long bs = G.v_hbs[e];
+            hb = (uint32_t)bs;
+            hs = (uint32_t)(bs >> 32);
             no = th ? (hs + kRun - 1u) / kRun : 0u;   // threshold 0: no channel into vv is live
             if (sub_w == 0) bytes += 12u + 4u * hs;
         }
@@ -887,7 +893,6 @@ __global__ __launch_bounds__(kWG) void k_finish(RRArgs a, uint32_t ndef) {
 // per-set traversal.
 constexpr uint32_t kMsSets = 64;
 constexpr uint32_t kMsOutVerts = 4096;   // vertices per output block (16 per thread)
-constexpr uint32_t kMsFilterSets = 24;   // masks of at least this many sets test seen masks before coins
 
 // kMsFetch: next work item of the running expansion (waves fetch items one at
 // a time; item costs vary with hyperedge sizes).
@@ -901,6 +906,7 @@ struct MsArgs {
     uint64_t first_id;                  // RR id of launch index 0
     uint32_t pool, key0, key1, qlog;
     uint32_t nbundles, chunk, seg;
+    uint32_t filter;                    // entries with this many sets read seen masks before coins
     uint64_t count;                     // sets: launch indices [0, count)
     uint64_t stride;                    // words per bundle in seen / nxt (>= n)
     unsigned long long *seen, *nxt;
@@ -919,15 +925,10 @@ struct MsArgs {
 
 struct MsLds {
     // level 2: frontier entries of the wave
-    uint32_t fr_scan[kWave], fr_v[kWave], fr_e0[kWave], fr_b[kWave];
+    uint32_t fr_scan[kWave], fr_v[kWave], fr_e0[kWave], fr_b[kWave], fr_thr[kWave];
     unsigned long long fr_m[kWave];
-    // level 3: one incidence per lane
-    uint32_t in_scan[kWave], in_he[kWave], in_hb[kWave], in_hs[kWave], in_v[kWave], in_thr[kWave], in_b[kWave];
-    unsigned long long in_m[kWave];
-    // level 4: one quad per lane
-    uint32_t q_scan[kWave], q_he[kWave], q_q[kWave], q_v[kWave], q_thr[kWave], q_b[kWave];
-    uint32_t q_u[kWave][4];
-    unsigned long long q_union[kWave], q_cand[kWave][4];
+    // level 3: one incidence per lane (in_k: its frontier entry's lane)
+    uint32_t in_scan[kWave], in_he[kWave], in_hb[kWave], in_hs[kWave], in_k[kWave];
 };
 
 // Position of the r-th set bit (r < popcount(m)) of m.
@@ -1152,7 +1153,7 @@ __device__ __forceinline__ void ms_pair(const MsArgs &m, bool act, uint32_t bnd,
 // expand (d = 0 for none).  Level 2 spreads the incidences over the wave,
 // level 3 the quads of member positions of those hyperedges, level 4 the
 // (quad, set) pairs whose coins are drawn.  A quad whose entry carries at
-// least kMsFilterSets sets first reads its members' seen masks and keeps
+// least m.filter sets first reads its members' seen masks and keeps
 // only the sets that do not hold them; for smaller masks those scattered
 // loads cost more than the coins they would save, so every set of the mask
 // draws its coins and the level's advance drops what a set already holds.
@@ -1164,29 +1165,28 @@ __device__ __forceinline__ void ms_expand(const MsArgs &m, const GraphView &G, M
     const uint32_t lane = lane_id();
     const uint32_t dscan = wave_incl_scan(d);
     const uint32_t D = uni(wave_bcast(dscan, kWave - 1));
+    const uint32_t th = d ? G.thr[v] : 0u;
     wave_sync();
     L.fr_scan[lane] = dscan;
     L.fr_v[lane] = v;
     L.fr_e0[lane] = e0;
     L.fr_b[lane] = b;
+    L.fr_thr[lane] = th;
     L.fr_m[lane] = mask;
     wave_sync();
     for (uint32_t base = 0; base < D; base += kWave) {
         // level 2: one incidence (v, he) per lane
         const uint32_t g = base + lane;
-        uint32_t he = 0, hb = 0, hs = 0, vv = 0, th = 0, bb = 0, nq = 0;
-        unsigned long long mm = 0;
+        uint32_t he = 0, hb = 0, hs = 0, nq = 0, fk = 0;
         if (g < D) {
-            const uint32_t k = search64(L.fr_scan, g);
-            const uint32_t start = k ? L.fr_scan[k - 1] : 0u;
-            vv = L.fr_v[k];
-            bb = L.fr_b[k];
-            mm = L.fr_m[k];
-            he = G.v_he[L.fr_e0[k] + (g - start)];
-            hb = G.he_off[he];
-            hs = G.he_off[he + 1] - hb;
-            th = G.thr[vv];
-            nq = th ? (hs + 3u) >> 2 : 0u;   // threshold 0: no channel into vv is live
+            fk = search64(L.fr_scan, g);
+            const uint32_t start = fk ? L.fr_scan[fk - 1] : 0u;
+            const uint32_t e = L.fr_e0[fk] + (g - start);
+            he = G.v_he[e];
+            const unsigned long long bs = G.v_hbs[e];
+            hb = (uint32_t)bs;
+            hs = (uint32_t)(bs >> 32);
+            nq = L.fr_thr[fk] ? (hs + 3u) >> 2 : 0u;   // threshold 0: no channel into the vertex is live
         }
         const uint32_t qscan = wave_incl_scan(nq);
         const uint32_t Q = uni(wave_bcast(qscan, kWave - 1));
@@ -1196,10 +1196,7 @@ __device__ __forceinline__ void ms_expand(const MsArgs &m, const GraphView &G, M
         L.in_he[lane] = he;
         L.in_hb[lane] = hb;
         L.in_hs[lane] = hs;
-        L.in_v[lane] = vv;
-        L.in_thr[lane] = th;
-        L.in_b[lane] = bb;
-        L.in_m[lane] = mm;
+        L.in_k[lane] = fk;
         wave_sync();
         for (uint32_t qb = 0; qb < Q; qb += kWave) {
             // level 3: one quad of member positions per lane
@@ -1207,22 +1204,25 @@ __device__ __forceinline__ void ms_expand(const MsArgs &m, const GraphView &G, M
             uint32_t pc = 0;
             uint32_t u[4] = {0u, 0u, 0u, 0u};
             unsigned long long cand[4] = {0ull, 0ull, 0ull, 0ull}, un = 0ull;
-            uint32_t qhe = 0, qq = 0, qv = 0, qth = 0, qbnd = 0, valid = 0;
+            uint32_t qhe = 0, qq = 0, qv = 0, qth = 0, qbnd = 0;
             if (qg < Q) {
                 const uint32_t k = search64(L.in_scan, qg);
                 const uint32_t start = k ? L.in_scan[k - 1] : 0u;
+                const uint32_t f = L.in_k[k];
                 qq = qg - start;
                 qhe = L.in_he[k];
-                qv = L.in_v[k];
-                qth = L.in_thr[k];
-                qbnd = L.in_b[k];
-                const unsigned long long qm = L.in_m[k];
+                qv = L.fr_v[f];
+                qth = L.fr_thr[f];
+                qbnd = L.fr_b[f];
+                const unsigned long long qm = L.fr_m[f];
                 const uint32_t p0 = 4u * qq, cnt = min(4u, L.in_hs[k] - p0);
+                const uint32_t hbk = L.in_hb[k];
 #pragma unroll
-                for (uint32_t t = 0; t < 4; ++t) u[t] = t < cnt ? G.he_mem[L.in_hb[k] + p0 + t] : qv;
+                for (uint32_t t = 0; t < 4; ++t) u[t] = t < cnt ? G.he_mem[hbk + p0 + t] : qv;
+                uint32_t valid = 0;
 #pragma unroll
                 for (uint32_t t = 0; t < 4; ++t) valid |= (t < cnt && u[t] != qv) ? 1u << t : 0u;
-                if ((uint32_t)__popcll(qm) >= kMsFilterSets) {
+                if ((uint32_t)__popcll(qm) >= m.filter) {
                     const uint64_t row = (uint64_t)qbnd * m.stride;
                     unsigned long long sm[4];
 #pragma unroll
@@ -1257,44 +1257,33 @@ __device__ __forceinline__ void ms_expand(const MsArgs &m, const GraphView &G, M
                 }
                 continue;
             }
-            wave_sync();
-            L.q_scan[lane] = pscan;
-            L.q_he[lane] = qhe;
-            L.q_q[lane] = qq;
-            L.q_v[lane] = qv;
-            L.q_thr[lane] = qth;
-            L.q_b[lane] = qbnd;
-            L.q_union[lane] = un;
-#pragma unroll
-            for (uint32_t t = 0; t < 4; ++t) {
-                L.q_u[lane][t] = u[t];
-                L.q_cand[lane][t] = cand[t];
-            }
-            wave_sync();
+            // level 4 over the wave: one (quad, set) pair per lane, the
+            // quad's data read from its lane by shuffles
             for (uint32_t pb = 0; pb < PT; pb += kWave) {
-                // level 4 over the wave: one (quad, set) pair per lane
                 const uint32_t pg = pb + lane;
                 const bool act = pg < PT;
-                uint32_t s = 0, bk = 0, vk = 0, thk = 0, hek = 0, qk = 0, c4 = 0;
-                uint32_t uk[4] = {0u, 0u, 0u, 0u};
-                if (act) {
-                    const uint32_t k = search64(L.q_scan, pg);
-                    const uint32_t r = pg - (k ? L.q_scan[k - 1] : 0u);
-                    s = nth_bit(L.q_union[k], r);
-                    bk = L.q_b[k];
-                    vk = L.q_v[k];
-                    thk = L.q_thr[k];
-                    hek = L.q_he[k];
-                    qk = L.q_q[k];
+                const uint32_t k = owner_of(pscan, act ? pg : PT - 1u);
+                const uint32_t before = (uint32_t)__shfl((int)(pscan - pc), (int)k, kWave);
+                const unsigned long long unk =
+                    ((unsigned long long)(uint32_t)__shfl((int)(uint32_t)(un >> 32), (int)k, kWave) << 32) |
+                    (uint32_t)__shfl((int)(uint32_t)un, (int)k, kWave);
+                const uint32_t s = nth_bit(unk, act ? pg - before : 0u);
+                const uint32_t bk = (uint32_t)__shfl((int)qbnd, (int)k, kWave);
+                const uint32_t vk = (uint32_t)__shfl((int)qv, (int)k, kWave);
+                const uint32_t thk = (uint32_t)__shfl((int)qth, (int)k, kWave);
+                const uint32_t hek = (uint32_t)__shfl((int)qhe, (int)k, kWave);
+                const uint32_t qk = (uint32_t)__shfl((int)qq, (int)k, kWave);
+                uint32_t uk[4], c4 = 0;
 #pragma unroll
-                    for (uint32_t t = 0; t < 4; ++t) {
-                        c4 |= (uint32_t)((L.q_cand[k][t] >> s) & 1ull) << t;
-                        uk[t] = L.q_u[k][t];
-                    }
+                for (uint32_t t = 0; t < 4; ++t) {
+                    uk[t] = (uint32_t)__shfl((int)u[t], (int)k, kWave);
+                    // the set's bit of cand[t]: from the half that holds bit s
+                    const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)cand[t], (int)k, kWave);
+                    const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(cand[t] >> 32), (int)k, kWave);
+                    c4 |= (((s < 32 ? lo >> s : hi >> (s - 32)) & 1u)) << t;
                 }
                 ms_pair(m, act, bk, s, hek, qk, vk, thk, c4, uk, px);
             }
-            wave_sync();
         }
     }
     wave_sync();
@@ -1906,7 +1895,7 @@ int run_ms_launch(RRWorkspace &ws, RRStats &st, const hyperim_tuning &tune, RRAr
     HIM_CHECK(ws.ms_ctr.reserve(sizeof(unsigned long long) * kMsNumCtr, s));
     MsArgs m{};
     m.graph = GraphDesc{g->he_off.as<uint32_t>(), g->he_mem.as<uint32_t>(), g->v_off.as<uint32_t>(),
-                        g->v_he.as<uint32_t>(), g->thr.as<uint32_t>(), g->P.as<uint32_t>(), n,
+                        g->v_he.as<uint32_t>(), g->thr.as<uint32_t>(), g->P.as<uint32_t>(), g->v_hbs.as<unsigned long long>(), n,
                         (uint32_t)(((uint64_t)n + 31u) / 32u)};
     m.bytesw = g->bytesw.as<unsigned long long>();
     m.first_id = t.first_id;
@@ -1917,6 +1906,7 @@ int run_ms_launch(RRWorkspace &ws, RRStats &st, const hyperim_tuning &tune, RRAr
     m.nbundles = nbundles;
     m.chunk = a.chunk;
     m.seg = a.seg;
+    m.filter = std::max<uint32_t>(tune.ms_filter, 1);
     m.count = a.count;
     m.stride = stride;
     m.seen = ws.ms_seen.as<unsigned long long>();
@@ -2112,7 +2102,8 @@ int rr_generate_into(RRWorkspace &ws, RRStats &st, const std::vector<RRTask> &ta
         gid[t.g] = (uint32_t)gdesc.size();
         hyperim_graph g = t.g;
         gdesc.push_back(GraphDesc{g->he_off.as<uint32_t>(), g->he_mem.as<uint32_t>(), g->v_off.as<uint32_t>(),
-                                  g->v_he.as<uint32_t>(), g->thr.as<uint32_t>(), g->P.as<uint32_t>(), g->n,
+                                  g->v_he.as<uint32_t>(), g->thr.as<uint32_t>(), g->P.as<uint32_t>(),
+                                  g->v_hbs.as<unsigned long long>(), g->n,
                                   (uint32_t)(((uint64_t)g->n + 31u) / 32u)});
         n_max = std::max(n_max, g->n);
     }
