@@ -64,9 +64,11 @@ def parse():
 # SIMDs x 16 lanes per clock x 2.4 GHz (the 157.3 TFLOP/s fp32 vector figure
 # counts a packed FMA as 4 flops per lane).  One Philox4x32-10 block is 20
 # v_mad_u64_u32 and 40 v_xor_b32 in the generated code (key schedule in
-# scalar registers); a v_mad_u64_u32 takes PHILOX_MAD_PASSES issue passes.
+# scalar registers); a v_mad_u64_u32 issues in one pass on gfx950 (the
+# throughput probe measures 661-684 Gblocks/s, against 655 for one pass and
+# 328 for four).
 VALU_LANE_OPS_PER_S = 256 * 4 * 16 * 2.4e9
-PHILOX_XOR, PHILOX_MAD, PHILOX_MAD_PASSES = 40, 20, 4
+PHILOX_XOR, PHILOX_MAD, PHILOX_MAD_PASSES = 40, 20, 1
 PHILOX_PEAK_BLOCKS_PER_S = VALU_LANE_OPS_PER_S / (PHILOX_XOR + PHILOX_MAD * PHILOX_MAD_PASSES)
 
 # expansion kernels the line can name as dominant: result fields of their

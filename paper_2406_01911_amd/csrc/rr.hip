@@ -47,6 +47,7 @@
 #include <map>
 #include <string>
 #include <thread>
+#include <type_traits>
 #include <vector>
 
 #include "dev_common.h"
@@ -148,10 +149,16 @@ struct RRArgs {
     uint4 *items;
 };
 
-struct WaveLds {
+constexpr uint32_t kLiveCap = 256;   // live channels a wave holds before marking them (global marks)
+
+struct WaveLdsCore {
     uint32_t fr_scan[kWave], fr_v[kWave], fr_e0[kWave];
     uint32_t in_scan[kWave], in_he[kWave], in_hb[kWave], in_hs[kWave], in_v[kWave], in_thr[kWave];
     uint32_t cont_u[kWave], cont_pos[kWave];   // phase B: members this wave appended, and where
+};
+// With visited bitmaps in global memory a wave also buffers live channels.
+struct WaveLds : WaveLdsCore {
+    uint32_t live[kLiveCap];                   // sources of live channels waiting to be marked
 };
 
 // The task of launch index idx (first task whose end exceeds idx); idx is
@@ -310,15 +317,49 @@ struct ContAppend {
     }
 };
 
+// Marks the wave's buffered live-channel sources in the set's visited
+// bitmap (global memory) and appends the ones not marked before.  Each lane
+// issues up to four atomics before waiting for any, so a wave pays one
+// memory round trip per 256 live channels rather than one per coin batch.
+// Every lane of the wave calls it.
+template <class App>
+__device__ __forceinline__ void flush_live(uint32_t *bm, WaveLds &L, uint32_t &nlive, App &app) {
+    wave_sync();
+    const uint32_t lane = lane_id();
+    for (uint32_t i0 = 0; i0 < nlive; i0 += 4 * kWave) {
+        uint32_t uu[8], old[4];
+#pragma unroll
+        for (uint32_t r = 0; r < 8; ++r) uu[r] = 0u;
+#pragma unroll
+        for (uint32_t r = 0; r < 4; ++r) {
+            const uint32_t i = i0 + r * kWave + lane;
+            old[r] = ~0u;
+            if (i < nlive) {
+                uu[r] = L.live[i];
+                old[r] = atomicOr(&bm[uu[r] >> 5], 1u << (uu[r] & 31));
+            }
+        }
+        uint32_t fresh = 0;
+#pragma unroll
+        for (uint32_t r = 0; r < 4; ++r) fresh |= ((old[r] >> (uu[r] & 31)) & 1u) ? 0u : 1u << r;
+        app.push8(fresh, uu);
+    }
+    nlive = 0;
+    wave_sync();
+}
+
 // Test the channels (he, u -> ve) at member positions [p0, p0 + cm) of one
 // hyperedge (cm <= kRun, p0 a multiple of 4) in this lane: the coins are the
 // words of the Philox blocks of quads p0/4, p0/4 + 1, ...  Newly reached
-// members go to `app`.  Every lane of the wave must call it (inactive lanes
-// with active = false).
-template <bool kLds, class App>
+// members go to `app`: at once when the visited bitmap is in LDS, else
+// through the wave's buffer of live channels (L.live, nlive entries), marked
+// in batches.  Every lane of the wave must call it (inactive lanes with
+// active = false).
+template <bool kLds, class App, class Lds>
 __device__ __forceinline__ void test_run(const GraphView &G, uint64_t j, uint32_t pool, uint2 key, uint32_t *bm,
                                          bool prefilter, bool active, uint32_t he, uint32_t hb, uint32_t p0,
-                                         uint32_t cm, uint32_t ve, uint32_t the, App &app, uint64_t &px) {
+                                         uint32_t cm, uint32_t ve, uint32_t the, App &app, uint64_t &px,
+                                         Lds &L, uint32_t &nlive) {
     uint32_t u[8];
 #pragma unroll
     for (uint32_t t = 0; t < 8; ++t) u[t] = (t < kRun && active && t < cm) ? G.he_mem[hb + p0 + t] : ve;
@@ -365,15 +406,29 @@ __device__ __forceinline__ void test_run(const GraphView &G, uint64_t j, uint32_
     }
     // with small probabilities most runs have no live channel at all
     if (__ballot(any_live) == 0) return;
-    uint32_t fresh = 0;
+    if constexpr (kLds) {
+        uint32_t fresh = 0;
 #pragma unroll
-    for (uint32_t t = 0; t < kRun; ++t) {
-        if (live[t]) {
-            const uint32_t bit = 1u << (u[t] & 31);
-            if ((atomicOr(&bm[u[t] >> 5], bit) & bit) == 0u) fresh |= 1u << t;
+        for (uint32_t t = 0; t < kRun; ++t) {
+            if (live[t]) {
+                const uint32_t bit = 1u << (u[t] & 31);
+                if ((atomicOr(&bm[u[t] >> 5], bit) & bit) == 0u) fresh |= 1u << t;
+            }
         }
+        app.push8(fresh, u);
+    } else {
+        uint32_t cnt = 0;
+#pragma unroll
+        for (uint32_t t = 0; t < kRun; ++t) cnt += live[t] ? 1u : 0u;
+        const uint32_t incl = wave_incl_scan(cnt);
+        const uint32_t tot = uni(wave_bcast(incl, kWave - 1));
+        if (nlive + tot > kLiveCap) flush_live(bm, L, nlive, app);
+        uint32_t at = nlive + incl - cnt;
+#pragma unroll
+        for (uint32_t t = 0; t < kRun; ++t)
+            if (live[t]) L.live[at++] = u[t];
+        nlive += tot;
     }
-    app.push8(fresh, u);
 }
 
 // Levels 2 and 3 of a frontier expansion.  Each lane brings one vertex v with
@@ -389,11 +444,12 @@ __device__ __forceinline__ void test_run(const GraphView &G, uint64_t j, uint32_
 // every run is tested by exactly one of them.  Returns the algorithmic
 // bytes of the incidences read (12 per incidence plus 4 per member
 // position), each counted by one wave, wave-uniform.
-template <bool kLds, bool kUniform, class App>
-__device__ __forceinline__ uint64_t expand(const GraphView &G, WaveLds &L, uint64_t j, uint32_t pool, uint2 key,
+template <bool kLds, bool kUniform, class App, class Lds>
+__device__ __forceinline__ uint64_t expand(const GraphView &G, Lds &L, uint64_t j, uint32_t pool, uint2 key,
                                            uint32_t *bm, bool prefilter, uint32_t v, uint32_t e0, uint32_t d,
                                            App &app, uint64_t &px, uint32_t w = 0, uint32_t W = 1) {
     const uint32_t lane = lane_id();
+    uint32_t nlive = 0;   // live channels buffered in L.live (wave-uniform)
     uint32_t D = d;
     uint32_t th_uniform = 0;
     if constexpr (kUniform) {
@@ -440,7 +496,8 @@ __device__ __forceinline__ uint64_t expand(const GraphView &G, WaveLds &L, uint6
         }
         // level 3, first pass: run 0 of the lane's own incidence
         if (sub_w == 0)
-            test_run<kLds>(G, j, pool, key, bm, prefilter, no > 0, he, hb, 0u, min(kRun, hs), vv, th, app, px);
+            test_run<kLds>(G, j, pool, key, bm, prefilter, no > 0, he, hb, 0u, min(kRun, hs), vv, th, app, px, L,
+                           nlive);
         // second pass: runs 1.. of the longer hyperedges, flattened over the wave
         const uint32_t rem = no > 1 ? no - 1u : 0u;
         if (__ballot(rem > 0) == 0) continue;
@@ -472,9 +529,10 @@ __device__ __forceinline__ uint64_t expand(const GraphView &G, WaveLds &L, uint6
                     the = L.in_thr[k];
                 }
             }
-            test_run<kLds>(G, j, pool, key, bm, prefilter, active, hee, hbk, p0, cm, ve, the, app, px);
+            test_run<kLds>(G, j, pool, key, bm, prefilter, active, hee, hbk, p0, cm, ve, the, app, px, L, nlive);
         }
     }
+    if constexpr (!kLds) flush_live(bm, L, nlive, app);
     wave_sync();
     return wave_sum(bytes);
 }
@@ -491,12 +549,13 @@ __device__ __forceinline__ void record_set(const RRArgs &a, uint64_t idx, uint64
 // ---- phase A ---------------------------------------------------------------
 template <bool kLdsBitmap>
 __global__ __launch_bounds__(kWG) void k_rr_light(RRArgs a) {
-    __shared__ WaveLds lds[kWavesPerWG];
+    using Lds = typename std::conditional<kLdsBitmap, WaveLdsCore, WaveLds>::type;
+    __shared__ Lds lds[kWavesPerWG];
     __shared__ uint32_t sort_s[kWavesPerWG][kSortMax];
     __shared__ uint32_t lbm[kLdsBitmap ? kWavesPerWG : 1][kLdsBitmap ? kLdsBitmapWords : 1];
     const uint32_t lane = lane_id(), wv = uni(threadIdx.x / kWave);
     uint32_t slot = blockIdx.x * kWavesPerWG + wv;
-    WaveLds &L = lds[wv];
+    Lds &L = lds[wv];
     uint32_t *sortb = sort_s[wv];
     uint32_t *list = a.lists + (uint64_t)slot * a.slot_n;
     uint32_t *bm;
@@ -923,12 +982,16 @@ struct MsArgs {
     uint32_t nvb;                       // vertex blocks per bundle
 };
 
+constexpr uint32_t kMsLiveCap = 512;   // live channels a wave holds before marking them
+
 struct MsLds {
     // level 2: frontier entries of the wave
     uint32_t fr_scan[kWave], fr_v[kWave], fr_e0[kWave], fr_b[kWave], fr_thr[kWave];
     unsigned long long fr_m[kWave];
     // level 3: one incidence per lane (in_k: its frontier entry's lane)
     uint32_t in_scan[kWave], in_he[kWave], in_hb[kWave], in_hs[kWave], in_k[kWave];
+    // live channels waiting to be marked: (member, bundle << 6 | set)
+    uint2 live[kMsLiveCap];
 };
 
 // Position of the r-th set bit (r < popcount(m)) of m.
@@ -1116,13 +1179,45 @@ __device__ __forceinline__ void ms_append_wave(const MsArgs &m, bool fresh, uint
     }
 }
 
+// Marks the wave's buffered live channels in nxt and appends the (bundle,
+// member) pairs that got their first bit to the next-level list.  A marking
+// needs the old mask back, so each lane first issues up to four atomics and
+// only then waits: one memory round trip per 256 channels instead of one per
+// coin batch.  Every lane of the wave calls it.
+__device__ __forceinline__ void ms_flush(const MsArgs &m, MsLds &L, uint32_t &nlive) {
+    wave_sync();
+    const uint32_t lane = lane_id();
+    for (uint32_t i0 = 0; i0 < nlive; i0 += 4 * kWave) {
+        unsigned long long old[4];
+        uint32_t bb[4], uu[4];
+        bool act[4];
+#pragma unroll
+        for (uint32_t r = 0; r < 4; ++r) {
+            const uint32_t i = i0 + r * kWave + lane;
+            act[r] = i < nlive;
+            bb[r] = uu[r] = 0;
+            old[r] = ~0ull;
+            if (act[r]) {
+                const uint2 e = L.live[i];
+                uu[r] = e.x;
+                bb[r] = e.y >> 6;
+                old[r] = atomicOr(&m.nxt[(uint64_t)bb[r] * m.stride + uu[r]], 1ull << (e.y & 63u));
+            }
+        }
+#pragma unroll
+        for (uint32_t r = 0; r < 4; ++r) ms_append_wave(m, act[r] && old[r] == 0ull, bb[r], uu[r]);
+    }
+    nlive = 0;
+    wave_sync();
+}
+
 // Coins of one (quad, set) pair: channels (he, u[t] -> v) for the candidate
-// positions t of set s, live ones marked in nxt (sets already holding u are
-// removed when the level advances).  Lanes with act = false only join the
-// wave-wide appends.
-__device__ __forceinline__ void ms_pair(const MsArgs &m, bool act, uint32_t bnd, uint32_t s, uint32_t he, uint32_t q,
-                                        uint32_t v, uint32_t thr, uint32_t cand4, const uint32_t (&u)[4],
-                                        uint64_t &px) {
+// positions t of set s; live ones wait in the wave's buffer to be marked in
+// nxt (sets already holding u are removed when the level advances).  Lanes
+// with act = false only join the wave-wide steps.
+__device__ __forceinline__ void ms_pair(const MsArgs &m, MsLds &L, uint32_t &nlive, bool act, uint32_t bnd,
+                                        uint32_t s, uint32_t he, uint32_t q, uint32_t v, uint32_t thr,
+                                        uint32_t cand4, const uint32_t (&u)[4], uint64_t &px) {
     uint4 c = make_uint4(0u, 0u, 0u, 0u);
     if (act) {
         c = philox4x32_10(coin_counter(m.first_id + (uint64_t)bnd * kMsSets + s, he, v, m.pool, q),
@@ -1130,22 +1225,20 @@ __device__ __forceinline__ void ms_pair(const MsArgs &m, bool act, uint32_t bnd,
         ++px;
     }
     const uint32_t w[4] = {c.x, c.y, c.z, c.w};
-    bool live[4];
-    bool any = false;
+    uint32_t lv = 0;
 #pragma unroll
-    for (uint32_t t = 0; t < 4; ++t) {
-        live[t] = act && ((cand4 >> t) & 1u) && channel_live(w[t], thr);
-        any |= live[t];
-    }
-    if (__ballot(any) == 0) return;   // with small probabilities most pairs have no live channel
-    const unsigned long long bit = 1ull << s;
-    const uint64_t row = (uint64_t)bnd * m.stride;
+    for (uint32_t t = 0; t < 4; ++t)
+        lv |= (act && ((cand4 >> t) & 1u) && channel_live(w[t], thr)) ? 1u << t : 0u;
+    if (__ballot(lv != 0u) == 0) return;   // with small probabilities most pairs have no live channel
+    const uint32_t cnt = (uint32_t)__popc(lv);
+    const uint32_t incl = wave_incl_scan(cnt);
+    const uint32_t tot = uni(wave_bcast(incl, kWave - 1));
+    if (nlive + tot > kMsLiveCap) ms_flush(m, L, nlive);
+    uint32_t at = nlive + incl - cnt;
 #pragma unroll
-    for (uint32_t t = 0; t < 4; ++t) {
-        bool fresh = false;
-        if (live[t]) fresh = atomicOr(&m.nxt[row + u[t]], bit) == 0ull;
-        ms_append_wave(m, fresh, bnd, u[t]);
-    }
+    for (uint32_t t = 0; t < 4; ++t)
+        if ((lv >> t) & 1u) L.live[at++] = make_uint2(u[t], (bnd << 6) | s);
+    nlive += tot;
 }
 
 // Levels 2-4 of a bundled expansion.  Each lane brings a frontier entry
@@ -1160,8 +1253,8 @@ __device__ __forceinline__ void ms_pair(const MsArgs &m, bool act, uint32_t bnd,
 // When the wave's pair counts are even (no lane has more than twice the
 // mean), every lane walks its own quad's sets in registers; otherwise the
 // pairs are spread over the wave through LDS.
-__device__ __forceinline__ void ms_expand(const MsArgs &m, const GraphView &G, MsLds &L, uint32_t b, uint32_t v,
-                                          unsigned long long mask, uint32_t e0, uint32_t d, uint64_t &px) {
+__device__ __forceinline__ void ms_expand(const MsArgs &m, const GraphView &G, MsLds &L, uint32_t &nlive, uint32_t b,
+                                          uint32_t v, unsigned long long mask, uint32_t e0, uint32_t d, uint64_t &px) {
     const uint32_t lane = lane_id();
     const uint32_t dscan = wave_incl_scan(d);
     const uint32_t D = uni(wave_bcast(dscan, kWave - 1));
@@ -1253,7 +1346,7 @@ __device__ __forceinline__ void ms_expand(const MsArgs &m, const GraphView &G, M
 #pragma unroll
                         for (uint32_t t = 0; t < 4; ++t) c4 |= (uint32_t)((cand[t] >> s) & 1ull) << t;
                     }
-                    ms_pair(m, act, qbnd, s, qhe, qq, qv, qth, c4, u, px);
+                    ms_pair(m, L, nlive, act, qbnd, s, qhe, qq, qv, qth, c4, u, px);
                 }
                 continue;
             }
@@ -1282,7 +1375,7 @@ __device__ __forceinline__ void ms_expand(const MsArgs &m, const GraphView &G, M
                     const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(cand[t] >> 32), (int)k, kWave);
                     c4 |= (((s < 32 ? lo >> s : hi >> (s - 32)) & 1u)) << t;
                 }
-                ms_pair(m, act, bk, s, hek, qk, vk, thk, c4, uk, px);
+                ms_pair(m, L, nlive, act, bk, s, hek, qk, vk, thk, c4, uk, px);
             }
         }
     }
@@ -1297,6 +1390,7 @@ __global__ __launch_bounds__(kWG) void k_ms_expand(MsArgs m) {
     const uint64_t nitems = min(m.ctr[kMsItems], (unsigned long long)kItemCap);
     const uint32_t lane = lane_id();
     uint64_t px = 0;
+    uint32_t nlive = 0;   // live channels buffered in L.live (wave-uniform)
     for (;;) {
         // items cost up to a few times each other (hyperedge sizes vary
         // inside a chunk), so waves take them one at a time
@@ -1320,7 +1414,7 @@ __global__ __launch_bounds__(kWG) void k_ms_expand(MsArgs m) {
                 d = G.v_off[v + 1] - e0;
                 if (ms_heavy_split(d, (uint32_t)__popcll(mask), m.chunk).count) d = 0;   // expanded by its heavy items
             }
-            ms_expand(m, G, L, b, v, mask, e0, d, px);
+            ms_expand(m, G, L, nlive, b, v, mask, e0, d, px);
         } else {
             // one heavy vertex: incidences [item.y, item.z) of entry item.x
             const uint32_t f = item.x & 0x7FFFFFFFu;
@@ -1329,10 +1423,11 @@ __global__ __launch_bounds__(kWG) void k_ms_expand(MsArgs m) {
             // the chunk's incidences go to lanes in runs of up to 64 entries
             for (uint32_t e = item.y; e < item.z; e += kWave) {
                 const uint32_t mine = e + lane < item.z ? 1u : 0u;
-                ms_expand(m, G, L, b, v, mask, e + lane, mine, px);
+                ms_expand(m, G, L, nlive, b, v, mask, e + lane, mine, px);
             }
         }
     }
+    ms_flush(m, L, nlive);
     px = wave_sum(px);
     if (lane == 0 && px) atomicAdd(m.philox, (unsigned long long)px);
 }
