@@ -100,6 +100,9 @@ typedef struct {
                                          percent of a small query)       */
 #define HYPERIM_FLAG_INCIDENCES 1u  /* fill hyperim_result.incidences (one extra
                                        pass over the final pools)            */
+#define HYPERIM_FLAG_NO_GRAPHS 4u   /* launch every superstep kernel directly
+                                       instead of replaying captured batches
+                                       (HIP graphs); same results           */
 
 /* Outcome of hyperim_select_seeds. */
 typedef struct {

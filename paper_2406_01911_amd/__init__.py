@@ -23,6 +23,7 @@ MODEL_CONST, MODEL_WC = 0, 1
 NSTRATA = 8
 FLAG_INCIDENCES = 1
 FLAG_KERNEL_TIMES = 2
+FLAG_NO_GRAPHS = 4
 
 
 class HyperIMError(RuntimeError):

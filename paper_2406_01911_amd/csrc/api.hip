@@ -131,15 +131,23 @@ size_t RRWorkspace::bytes() const {
     size_t b = 0;
     for (const DevBuf *x : {&lists, &bitmaps, &def_idx, &def_u32, &graph_desc, &task_desc, &items, &counters, &stage,
                             &stage_off, &sizes, &roots, &scan_tmp, &big_ids, &ms_seen, &ms_nxt, &ms_cur, &ms_next,
-                            &ms_batch, &ms_vcnt, &ms_ctr})
+                            &ms_batch, &ms_vcnt, &ms_ctr, &args_dev})
         b += x->bytes;
     return b;
 }
 
+void RRWorkspace::drop_graphs() {
+    for (BatchGraph &b : batch_graphs) (void)hipGraphExecDestroy(b.exec);
+    batch_graphs.clear();
+}
+
 void RRWorkspace::release() {
+    drop_graphs();
+    if (capture) (void)hipStreamDestroy(capture);
+    capture = nullptr;
     for (DevBuf *x : {&lists, &bitmaps, &def_idx, &def_u32, &graph_desc, &task_desc, &items, &counters, &stage,
                       &stage_off, &sizes, &roots, &scan_tmp, &big_ids, &ms_seen, &ms_nxt, &ms_cur, &ms_next,
-                      &ms_batch, &ms_vcnt, &ms_ctr})
+                      &ms_batch, &ms_vcnt, &ms_ctr, &args_dev})
         x->release();
     for (hipEvent_t e : events) (void)hipEventDestroy(e);
     events.clear();
@@ -236,7 +244,7 @@ size_t pool_bytes(const hyperim_pool_s &p) { return p.off_b.bytes + p.roots_b.by
 // (tasks with an empty id range are skipped).
 int generate_into(const std::vector<RRTask> &tasks, const std::vector<hyperim_pool> &pools, uint32_t qlog, int form,
                   uint64_t max_entries, hipStream_t s, RRStats &st, std::vector<int> *pool_status,
-                  bool time_kernels) {
+                  bool time_kernels, bool graphs) {
     std::vector<RRTask> live;
     std::vector<hyperim_pool> dst;
     std::vector<size_t> which;
@@ -256,7 +264,7 @@ int generate_into(const std::vector<RRTask> &tasks, const std::vector<hyperim_po
     std::vector<int> status;
     const uint64_t stage_budget = (uint64_t)std::max<uint32_t>(live[0].g->tune.stage_mib, 64) << 20;
     HIM_CHECK(rr_generate_into(*lk.rr, st, live, dst, qlog, form, max_entries, stage_budget, s, status,
-                               time_kernels));
+                               time_kernels, graphs));
     int first_fail = HYPERIM_OK;
     for (size_t i = 0; i < live.size(); ++i) {
         if (was_empty[i] && dst[i]->count) dst[i]->id_begin = live[i].id_begin;

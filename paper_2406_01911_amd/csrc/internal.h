@@ -72,6 +72,17 @@ struct RRWorkspace {
     DevBuf scan_tmp;             // scan block sums
     DevBuf big_ids;              // per-id indices of sets compacted by whole workgroups
     std::vector<hipEvent_t> events;  // start/stop pairs around RR-generation launches
+    DevBuf args_dev;             // arguments of the grid-wide phase kernels (device copy)
+    // superstep batches captured as HIP graphs, replayed while a traversal
+    // lasts; keyed by everything a capture bakes in
+    struct BatchGraph {
+        uint64_t key[8];
+        hipGraphExec_t exec;
+    };
+    std::vector<BatchGraph> batch_graphs;
+    hipStream_t capture = nullptr;   // stream the batches are captured on
+    bool graphs_off = false;         // capture failed on this device: launch kernels directly
+    void drop_graphs();
     unsigned long long *host = nullptr;  // pinned host staging: counter copies, descriptors, totals
     size_t host_words = 0;
     size_t bytes() const;        // device memory held
@@ -221,9 +232,10 @@ struct RRTask;
 // gets HYPERIM_ECAPACITY there and the others are still filled; without it
 // that status is returned.
 // time_kernels: time every expansion-kernel launch (RRStats::ms_expand).
+// graphs: replay captured superstep batches (HIP graphs) where the device allows.
 int generate_into(const std::vector<RRTask> &tasks, const std::vector<hyperim_pool> &pools, uint32_t qlog, int form,
                   uint64_t max_entries, hipStream_t s, RRStats &st, std::vector<int> *pool_status,
-                  bool time_kernels = false);
+                  bool time_kernels = false, bool graphs = true);
 
 // ---- launchers (graph.hip) --------------------------------------------------
 int graph_build_device(hyperim_graph g, PrepWorkspace &w, hipStream_t s);
@@ -258,7 +270,8 @@ struct RRTask {
 size_t rr_slot_bytes(uint32_t n_max);
 int rr_generate_into(RRWorkspace &ws, RRStats &st, const std::vector<RRTask> &tasks,
                      const std::vector<hyperim_pool> &pools, uint32_t qlog, int form, uint64_t max_entries,
-                     uint64_t stage_budget, hipStream_t s, std::vector<int> &pool_status, bool time_kernels);
+                     uint64_t stage_budget, hipStream_t s, std::vector<int> &pool_status, bool time_kernels,
+                     bool graphs);
 // Make room in pool p for `ids` more ids and `entries` more members.
 int pool_reserve(hyperim_pool p, uint64_t ids, uint64_t entries, hipStream_t s);
 // Work of the pool's first theta sets, summed over their members v:

@@ -341,7 +341,7 @@ struct Engine {
         float ms = 0.f;
         HIM_HIP(hipEventRecord(ev.a, stream));
         HIM_CHECK(generate_into(tasks, dst, opt.qlog, (int)opt.form, opt.max_entries, stream, st, &status,
-                                (opt.flags & HYPERIM_FLAG_KERNEL_TIMES) != 0));
+                                (opt.flags & HYPERIM_FLAG_KERNEL_TIMES) != 0, (opt.flags & HYPERIM_FLAG_NO_GRAPHS) == 0));
         HIM_HIP(hipEventRecord(ev.b, stream));
         HIM_HIP(hipEventSynchronize(ev.b));
         HIM_HIP(hipEventElapsedTime(&ms, ev.a, ev.b));
@@ -466,7 +466,7 @@ struct Engine {
             HIM_HIP(hipEventRecord(ev.a, s));
             std::vector<int> pool_status;
             HIM_CHECK(generate_into(tasks, dst, o.qlog, (int)o.form, o.max_entries, s, st, &pool_status,
-                                    (o.flags & HYPERIM_FLAG_KERNEL_TIMES) != 0));
+                                    (o.flags & HYPERIM_FLAG_KERNEL_TIMES) != 0, (o.flags & HYPERIM_FLAG_NO_GRAPHS) == 0));
             HIM_HIP(hipEventRecord(ev.b, s));
             HIM_HIP(hipEventSynchronize(ev.b));
             HIM_HIP(hipEventElapsedTime(&ms_rr, ev.a, ev.b));

@@ -707,7 +707,10 @@ __device__ __forceinline__ uint32_t owner_of(uint32_t hscan, uint32_t q) {
 constexpr uint32_t kShareMax = 16;   // waves that may share one item
 constexpr uint32_t kContLevels = 8;  // levels a wave may expand past its item
 
-__global__ __launch_bounds__(kWG) void k_plan(RRArgs a, uint32_t parity) {
+// k_plan and k_expand read their arguments from device memory, so that a
+// captured batch of supersteps serves every launch group.
+__global__ __launch_bounds__(kWG) void k_plan(const RRArgs *__restrict__ ap, uint32_t parity) {
+    const RRArgs a = *ap;
     const uint32_t lane = lane_id(), wv = uni(threadIdx.x / kWave);
     const uint32_t waves = gridDim.x * kWavesPerWG;
     const uint32_t ndef = uni((uint32_t)a.ctr[kDefCount]);   // sets phase A deferred
@@ -789,7 +792,8 @@ __global__ __launch_bounds__(kWG) void k_plan(RRArgs a, uint32_t parity) {
     if (lane == 0 && taken) atomicAdd(&a.ctr[kPlanned], (unsigned long long)taken);
 }
 
-__global__ __launch_bounds__(kWG) void k_expand(RRArgs a, uint32_t parity) {
+__global__ __launch_bounds__(kWG) void k_expand(const RRArgs *__restrict__ ap, uint32_t parity) {
+    const RRArgs a = *ap;
     __shared__ WaveLds lds[kWavesPerWG];
     const uint32_t wv = uni(threadIdx.x / kWave);
     WaveLds &L = lds[wv];
@@ -1681,6 +1685,7 @@ int ensure_workspace(RRWorkspace &ws, uint32_t n_max, hipStream_t s, LaunchShape
         HIM_CHECK(ws.def_idx.reserve(sizeof(uint64_t) * ndef, s));
         HIM_CHECK(ws.def_u32.reserve(sizeof(uint32_t) * 5 * ndef, s));
         HIM_CHECK(ws.items.reserve(sizeof(uint4) * (size_t)kItemCap, s));
+        HIM_CHECK(ws.args_dev.reserve(sizeof(RRArgs), s));
     }
     shape->grid = ws.grid;
     shape->slots = ws.slots;
@@ -1801,7 +1806,8 @@ constexpr size_t kHostCtr = 16;
 constexpr size_t kHostBatch = 0;   // + (k & 1) * kHostCtr for batch k
 constexpr size_t kHostFinal = 2 * kHostCtr;
 constexpr size_t kHostFreeNext = 3 * kHostCtr;
-constexpr size_t kHostFixed = 4 * kHostCtr;
+constexpr size_t kHostArgs = 4 * kHostCtr;   // the grid-wide phase's RRArgs on their way to the device
+constexpr size_t kHostFixed = kHostArgs + (sizeof(RRArgs) + 7) / 8;
 static_assert(kNumCtr <= kHostCtr, "counter block");
 
 int ensure_host(RRWorkspace &ws, size_t words) {
@@ -1815,6 +1821,59 @@ int ensure_host(RRWorkspace &ws, size_t words) {
     ws.host_words = 0;
     HIM_HIP(hipHostMalloc((void **)&ws.host, w * sizeof(unsigned long long), hipHostMallocDefault));
     ws.host_words = w;
+    ws.drop_graphs();   // captured batches copy into the old buffer
+    return HYPERIM_OK;
+}
+
+// Captures the work `record` issues on the capture stream as one executable
+// graph (record returns false when something it calls fails).  A device that
+// cannot capture is remembered (graphs_off); *out is null then and the
+// caller launches the kernels itself.
+template <class Record>
+int capture_graph(RRWorkspace &ws, Record &&record, hipGraphExec_t *out) {
+    *out = nullptr;
+    if (ws.graphs_off) return HYPERIM_OK;
+    if (!ws.capture && hipStreamCreateWithFlags(&ws.capture, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipGetLastError();
+        ws.graphs_off = true;
+        return HYPERIM_OK;
+    }
+    hipGraph_t g = nullptr;
+    bool ok = hipStreamBeginCapture(ws.capture, hipStreamCaptureModeThreadLocal) == hipSuccess;
+    if (ok) {
+        ok = record(ws.capture) && hipGetLastError() == hipSuccess;
+        ok = hipStreamEndCapture(ws.capture, &g) == hipSuccess && ok && g;
+    }
+    hipGraphExec_t ex = nullptr;
+    if (ok) ok = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) == hipSuccess;
+    if (g) (void)hipGraphDestroy(g);
+    if (!ok) {
+        (void)hipGetLastError();
+        ws.graphs_off = true;
+        return HYPERIM_OK;
+    }
+    *out = ex;
+    return HYPERIM_OK;
+}
+
+// The captured superstep batch for `key` (everything the capture bakes in),
+// captured on first use and kept in the workspace.
+template <class Record>
+int captured_batch(RRWorkspace &ws, const uint64_t (&key)[8], Record &&record, hipGraphExec_t *out) {
+    *out = nullptr;
+    for (const RRWorkspace::BatchGraph &b : ws.batch_graphs)
+        if (std::equal(std::begin(key), std::end(key), std::begin(b.key))) {
+            *out = b.exec;
+            return HYPERIM_OK;
+        }
+    hipGraphExec_t ex = nullptr;
+    HIM_CHECK(capture_graph(ws, record, &ex));
+    if (!ex) return HYPERIM_OK;
+    RRWorkspace::BatchGraph b;
+    std::copy(std::begin(key), std::end(key), std::begin(b.key));
+    b.exec = ex;
+    ws.batch_graphs.push_back(b);
+    *out = ex;
     return HYPERIM_OK;
 }
 
@@ -1829,10 +1888,14 @@ int ensure_host(RRWorkspace &ws, size_t words) {
 // `expect_defer` false the host first checks whether phase A deferred any set.
 template <class Tail>
 int run_launch(RRWorkspace &ws, RRStats &st, const hyperim_tuning &tune, RRArgs &a, const LaunchShape &shape,
-               uint32_t grid, uint32_t grid_b, bool expect_defer, bool trace, bool time_kernels, hipStream_t s,
-               Tail &&tail) {
+               uint32_t grid, uint32_t grid_b, bool expect_defer, bool trace, bool time_kernels, bool graphs,
+               hipStream_t s, Tail &&tail) {
     unsigned long long *ctr = a.ctr;
     unsigned long long *h = ws.host;
+    // the grid-wide phase reads its arguments from the device
+    *reinterpret_cast<RRArgs *>(h + kHostArgs) = a;
+    HIM_HIP(hipMemcpyAsync(ws.args_dev.ptr, h + kHostArgs, sizeof(RRArgs), hipMemcpyHostToDevice, s));
+    const RRArgs *ap = ws.args_dev.as<RRArgs>();
     // fresh work counter, deferred list and spare-slot cursor (spare slots
     // follow the launched waves' own slots)
     h[kHostFreeNext] = (unsigned long long)grid * kWavesPerWG;
@@ -1856,7 +1919,11 @@ int run_launch(RRWorkspace &ws, RRStats &st, const hyperim_tuning &tune, RRArgs 
         ndef = h[kHostBatch + kDefCount];
         phase_b = ndef != 0;
     }
-    const int batch = trace ? 1 : (int)std::min<uint32_t>(std::max<uint32_t>(tune.steps_per_sync, 1), kMaxBatch);
+    int batch = trace ? 1 : (int)std::min<uint32_t>(std::max<uint32_t>(tune.steps_per_sync, 1), kMaxBatch);
+    // captured batches replay the same parities every time: an even batch
+    // starts every replay on counter parity 0
+    const bool use_graphs = graphs && !trace && !ws.graphs_off;
+    if (use_graphs && (batch & 1)) batch = std::min(batch + 1, kMaxBatch);
     auto account = [&](uint64_t k) -> int {
         hipEvent_t *E = batch_events(ws, k);
         float ms = 0.f;
@@ -1880,25 +1947,59 @@ int run_launch(RRWorkspace &ws, RRStats &st, const hyperim_tuning &tune, RRArgs 
         // planning waves: one per deferred set; until the count is known, the
         // spare slots bound it
         uint64_t plan_sets = ndef ? ndef : std::max<uint64_t>(shape.slots - (uint64_t)grid * kWavesPerWG, 1);
+        // captured batches plan with one grid wide enough for any count of
+        // deferred sets (planning waves stride over the sets)
+        const uint32_t plan_grid_all = (uint32_t)std::max<uint64_t>(
+            1, std::min<uint64_t>(div_up(std::max<uint64_t>(shape.slots - (uint64_t)grid * kWavesPerWG, 1),
+                                         kWavesPerWG),
+                                  4096));
         auto issue = [&](uint64_t kb) -> int {
             hipEvent_t *E = batch_events(ws, kb);
+            unsigned long long *dst = h + kHostBatch + (kb & 1u) * kHostCtr;
+            if (use_graphs) {
+                // one replay: batch x (k_plan, k_expand) and the counter copy
+                const uint64_t key[8] = {1u, (uint64_t)(kb & 1u), (uint64_t)batch, plan_grid_all,
+                                         (uint64_t)grid_b, (uint64_t)time_kernels, (uint64_t)(uintptr_t)ap,
+                                         (uint64_t)(uintptr_t)h ^ ((uint64_t)(uintptr_t)ctr << 1)};
+                hipGraphExec_t ex = nullptr;
+                HIM_CHECK(captured_batch(
+                    ws, key,
+                    [&](hipStream_t c) {
+                        for (int i = 0; i < batch; ++i) {
+                            const uint32_t parity = (uint32_t)(i & 1);
+                            hipLaunchKernelGGL(k_plan, dim3(plan_grid_all), dim3(kWG), 0, c, ap, parity);
+                            if (time_kernels && hipEventRecord(E[2 + 2 * i], c) != hipSuccess) return false;
+                            hipLaunchKernelGGL(k_expand, dim3(grid_b), dim3(kWG), 0, c, ap, parity);
+                            if (time_kernels && hipEventRecord(E[3 + 2 * i], c) != hipSuccess) return false;
+                        }
+                        return hipMemcpyAsync(dst, ctr, sizeof(unsigned long long) * kNumCtr, hipMemcpyDeviceToHost,
+                                              c) == hipSuccess;
+                    },
+                    &ex));
+                if (ex) {
+                    HIM_HIP(hipEventRecord(E[0], s));
+                    HIM_HIP(hipGraphLaunch(ex, s));
+                    HIM_HIP(hipEventRecord(E[1], s));
+                    return HYPERIM_OK;
+                }
+                // no capture on this device: launch directly (same parities)
+            }
             const uint32_t plan_grid =
                 (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(div_up(plan_sets, kWavesPerWG), 4096));
             for (int i = 0; i < batch; ++i) {
                 const uint32_t parity = (uint32_t)((kb * (uint64_t)batch + (uint64_t)i) & 1u);
                 hipExtLaunchKernelGGL(k_plan, dim3(plan_grid), dim3(kWG), 0, s, i == 0 ? E[0] : nullptr, nullptr,
-                                      0u, a, parity);
+                                      0u, ap, parity);
                 // timed: the launch itself stamps its start and end events (no
                 // stream markers between the kernels)
                 if (time_kernels)
                     hipExtLaunchKernelGGL(k_expand, dim3(grid_b), dim3(kWG), 0, s, E[2 + 2 * i], E[3 + 2 * i], 0u,
-                                          a, parity);
+                                          ap, parity);
                 else
-                    hipLaunchKernelGGL(k_expand, dim3(grid_b), dim3(kWG), 0, s, a, parity);
+                    hipLaunchKernelGGL(k_expand, dim3(grid_b), dim3(kWG), 0, s, ap, parity);
             }
             HIM_HIP(hipGetLastError());
-            HIM_HIP(hipMemcpyAsync(h + kHostBatch + (kb & 1u) * kHostCtr, ctr, sizeof(unsigned long long) * kNumCtr,
-                                   hipMemcpyDeviceToHost, s));
+            HIM_HIP(hipMemcpyAsync(dst, ctr, sizeof(unsigned long long) * kNumCtr, hipMemcpyDeviceToHost, s));
             HIM_HIP(hipEventRecord(E[1], s));
             return HYPERIM_OK;
         };
@@ -1971,7 +2072,8 @@ uint64_t ms_bytes_per_bundle(uint32_t n) {
 // ws.host + kHostFinal, `tail` queued behind it, stream drained.
 template <class Tail>
 int run_ms_launch(RRWorkspace &ws, RRStats &st, const hyperim_tuning &tune, RRArgs &a, const LaunchShape &shape,
-                  hyperim_graph g, const TaskDesc &t, bool trace, bool time_kernels, hipStream_t s, Tail &&tail) {
+                  hyperim_graph g, const TaskDesc &t, bool trace, bool time_kernels, bool graphs, hipStream_t s,
+                  Tail &&tail) {
     const uint32_t n = g->n;
     const uint32_t nbundles = (uint32_t)div_up(a.count, kMsSets);
     const uint64_t stride = std::max<uint32_t>(n, 1);
@@ -2044,22 +2146,46 @@ int run_ms_launch(RRWorkspace &ws, RRStats &st, const hyperim_tuning &tune, RRAr
     uint64_t epoch_before = 0, pending_before = ~0ull;
     const unsigned long long *hm = ws.host + kHostBatch;
     static_assert(kMsNumCtr <= kHostCtr, "bundled counter block");
+    // a batch of steps and the counter copy, captured once for the group
+    // (the arguments are the group's) and replayed until the sets are done
+    struct ExecGuard {
+        hipGraphExec_t ex = nullptr;
+        ~ExecGuard() {
+            if (ex) (void)hipGraphExecDestroy(ex);
+        }
+    } batch_exec;
+    auto record_batch = [&](hipStream_t c, int batch, bool in_capture) {
+        for (int k = 0; k < batch; ++k) {
+            hipLaunchKernelGGL(k_ms_plan, dim3(grid_b), dim3(kWG), 0, c, m);
+            if (time_kernels && in_capture) {
+                if (hipEventRecord(E[2 + 2 * k], c) != hipSuccess) return false;
+                hipLaunchKernelGGL(k_ms_expand, dim3(grid_b), dim3(kWG), 0, c, m);
+                if (hipEventRecord(E[3 + 2 * k], c) != hipSuccess) return false;
+            } else if (time_kernels) {
+                hipExtLaunchKernelGGL(k_ms_expand, dim3(grid_b), dim3(kWG), 0, c, E[2 + 2 * k], E[3 + 2 * k], 0u, m);
+            } else {
+                hipLaunchKernelGGL(k_ms_expand, dim3(grid_b), dim3(kWG), 0, c, m);
+            }
+            hipLaunchKernelGGL(k_ms_ctl_expanded, dim3(1), dim3(1), 0, c, m.ctr);
+            hipLaunchKernelGGL(k_ms_advance, dim3(grid_b), dim3(kWG), 0, c, m);
+            hipLaunchKernelGGL(k_ms_ctl_advanced, dim3(1), dim3(1), 0, c, m.ctr, list_cap);
+        }
+        return hipMemcpyAsync(ws.host + kHostBatch, m.ctr, sizeof(unsigned long long) * kMsNumCtr,
+                              hipMemcpyDeviceToHost, c) == hipSuccess;
+    };
+    if (graphs && !trace)
+        HIM_CHECK(capture_graph(ws, [&](hipStream_t c) { return record_batch(c, per_sync, true); }, &batch_exec.ex));
     for (;;) {
         const int batch = trace ? 1 : per_sync;
-        for (int k = 0; k < batch; ++k) {
-            hipLaunchKernelGGL(k_ms_plan, dim3(grid_b), dim3(kWG), 0, s, m);
-            if (time_kernels)
-                hipExtLaunchKernelGGL(k_ms_expand, dim3(grid_b), dim3(kWG), 0, s, E[2 + 2 * k], E[3 + 2 * k], 0u, m);
-            else
-                hipLaunchKernelGGL(k_ms_expand, dim3(grid_b), dim3(kWG), 0, s, m);
-            hipLaunchKernelGGL(k_ms_ctl_expanded, dim3(1), dim3(1), 0, s, m.ctr);
-            hipLaunchKernelGGL(k_ms_advance, dim3(grid_b), dim3(kWG), 0, s, m);
-            hipLaunchKernelGGL(k_ms_ctl_advanced, dim3(1), dim3(1), 0, s, m.ctr, list_cap);
+        if (batch_exec.ex) {
+            HIM_HIP(hipGraphLaunch(batch_exec.ex, s));
+        } else if (!record_batch(s, batch, false)) {
+            HIM_HIP(hipGetLastError());
+            set_error_detail("bundled superstep batch: a launch or copy failed");
+            return HYPERIM_EHIP;
         }
         HIM_HIP(hipGetLastError());
         steps += batch;
-        HIM_HIP(hipMemcpyAsync(ws.host + kHostBatch, m.ctr, sizeof(unsigned long long) * kMsNumCtr,
-                               hipMemcpyDeviceToHost, s));
         HIM_HIP(hipEventRecord(E[1], s));
         HIM_CHECK(wait_event(E[1], "a bundled superstep batch"));
         const uint64_t done = hm[kMsDone];
@@ -2169,7 +2295,8 @@ size_t rr_slot_bytes(uint32_t n_max) {
 
 int rr_generate_into(RRWorkspace &ws, RRStats &st, const std::vector<RRTask> &tasks,
                      const std::vector<hyperim_pool> &pools, uint32_t qlog, int form, uint64_t max_entries,
-                     uint64_t stage_budget, hipStream_t s, std::vector<int> &pool_status, bool time_kernels) {
+                     uint64_t stage_budget, hipStream_t s, std::vector<int> &pool_status, bool time_kernels,
+                     bool graphs) {
     // HYPERIM_TRACE=1: synchronise after every grid-wide superstep and report
     // its item count and time on stderr (diagnostics; same results)
     static const bool trace = [] {
@@ -2401,10 +2528,10 @@ int rr_generate_into(RRWorkspace &ws, RRStats &st, const std::vector<RRTask> &ta
             RRStats run{};
             if (ms)
                 HIM_CHECK(run_ms_launch(ws, run, tune, a, shape, tasks[slices[0].task].g, tdesc[0], trace,
-                                        time_kernels, s, scans));
+                                        time_kernels, graphs, s, scans));
             else
-                HIM_CHECK(run_launch(ws, run, tune, a, shape, grid, grid_b, expect_defer, trace, time_kernels, s,
-                                     scans));
+                HIM_CHECK(run_launch(ws, run, tune, a, shape, grid, grid_b, expect_defer, trace, time_kernels,
+                                     graphs, s, scans));
             // time counts every attempt, work only the one that produced the output
             st.ms_bfs += run.ms_bfs;
             st.ms_light += run.ms_light;
