@@ -88,7 +88,11 @@ def lib():
         L.orc_sigma_upper.argtypes = [C.c_double, C.c_uint32, C.c_double, C.c_double, C.c_double]
         L.orc_sigma_upper.restype = C.c_double
         L.orc_select_seeds.argtypes = [vp, C.c_uint32, C.c_double, C.c_double, C.c_uint64, C.c_uint32,
-                                       C.c_uint32, C.c_uint64, C.c_uint32, vp, vp, vp]
+                                       C.c_uint32, C.c_uint64, C.c_uint32, C.c_uint32, vp, vp, vp]
+        L.orc_upper_eq8.argtypes = [C.c_uint32, C.c_uint64, vp, vp, C.c_uint32, vp]
+        L.orc_upper_eq8.restype = C.c_uint64
+        L.orc_sigma_upper_cov.argtypes = [C.c_double] * 4
+        L.orc_sigma_upper_cov.restype = C.c_double
         _lib = L
     return _lib
 
@@ -140,7 +144,7 @@ class _Result(C.Structure):
     _fields_ = [("rounds", C.c_uint32), ("i_max", C.c_uint32), ("theta", C.c_uint64),
                 ("lambda1", C.c_uint64), ("lambda2", C.c_uint64), ("sigma_l", C.c_double),
                 ("sigma_u", C.c_double), ("spread", C.c_double), ("theta_max", C.c_double),
-                ("entries1", C.c_uint64), ("entries2", C.c_uint64)]
+                ("entries1", C.c_uint64), ("entries2", C.c_uint64), ("lambda_u", C.c_uint64)]
 
 
 def schedule(n, k, eps, ell, qlog=8) -> dict:
@@ -157,6 +161,20 @@ def sigma_lower(lambda2, a, n, theta) -> float:
 
 def sigma_upper(lambda1, k, a, n, theta) -> float:
     return float(lib().orc_sigma_upper(lambda1, k, a, n, theta))
+
+
+def sigma_upper_cov(cov_upper, a, n, theta) -> float:
+    return float(lib().orc_sigma_upper_cov(cov_upper, a, n, theta))
+
+
+def upper_eq8(n, off, mem, seeds, theta=None) -> int:
+    """Equation (8) (p_max = 1) for greedy seeds in selection order."""
+    off = np.ascontiguousarray(off, dtype=np.uint64)
+    mem = np.ascontiguousarray(mem, dtype=np.uint32)
+    seeds = np.ascontiguousarray(seeds, dtype=np.uint32)
+    theta = len(off) - 1 if theta is None else theta
+    return int(lib().orc_upper_eq8(n, theta, _p(off), _p(mem if mem.size else np.zeros(1, np.uint32)),
+                                   len(seeds), _p(seeds)))
 
 
 def greedy(n, off: np.ndarray, mem: np.ndarray, k: int, theta: int | None = None):
@@ -271,13 +289,14 @@ class Graph:
             lib().orc_free(ptr)
         return off, mem, rts
 
-    def select_seeds(self, k, eps, ell, seed=0, instance=0, qlog=8, theta_fixed=0, nthreads=None):
+    def select_seeds(self, k, eps, ell, seed=0, instance=0, qlog=8, theta_fixed=0, nthreads=None, bound=0):
+        """Algorithm 4; bound 0 = Equation (8)'s upper bound, 1 = Lemma 5's closed form."""
         if nthreads is None:
             nthreads = os.cpu_count() or 1
         seeds = np.zeros(k, np.uint32)
         gains = np.zeros(k, np.uint64)
         res = _Result()
-        rc = lib().orc_select_seeds(self._h, k, eps, ell, seed, instance, qlog, theta_fixed, nthreads,
+        rc = lib().orc_select_seeds(self._h, k, eps, ell, seed, instance, qlog, theta_fixed, nthreads, bound,
                                     _p(seeds), _p(gains), C.byref(res))
         if rc:
             raise OracleError("orc_select_seeds: %d" % rc)

@@ -611,6 +611,45 @@ uint64_t orc_coverage(uint32_t n, uint64_t theta, const uint64_t *off, const uin
     return hit;
 }
 
+/* Equation (8) with p_max = 1: the smallest, over the greedy prefixes
+ * S_0* = {}, S_1*, ..., S_k* (seeds[] in selection order), of
+ * Lambda_R1(S_i*) plus the sum of the k largest marginal coverages
+ * Lambda_R1(u | S_i*) over all vertices u -- Lemma 4's bound on the coverage
+ * of an optimal k-set, from each prefix.  Marginal coverages are recounted
+ * from the sets S_i* leaves uncovered, one prefix at a time. */
+static int cmp_u64_desc(const void *a, const void *b)
+{
+    uint64_t x = *(const uint64_t *)a, y = *(const uint64_t *)b;
+    return (x < y) - (x > y);
+}
+
+uint64_t orc_upper_eq8(uint32_t n, uint64_t theta, const uint64_t *off, const uint32_t *mem,
+                       uint32_t k, const uint32_t *seeds)
+{
+    uint8_t *covered = (uint8_t *)calloc(theta ? theta : 1, 1);
+    uint64_t *marg = (uint64_t *)malloc(sizeof(uint64_t) * (n ? n : 1));
+    uint64_t best = UINT64_MAX, cov = 0;
+    for (uint32_t i = 0; i <= k; ++i) {
+        memset(marg, 0, sizeof(uint64_t) * (n ? n : 1));
+        for (uint64_t j = 0; j < theta; ++j)
+            if (!covered[j])
+                for (uint64_t e = off[j]; e < off[j + 1]; ++e) marg[mem[e]] += 1;
+        qsort(marg, n, sizeof(uint64_t), cmp_u64_desc);
+        uint64_t top = 0;
+        for (uint32_t x = 0; x < k && x < n; ++x) top += marg[x];
+        if (cov + top < best) best = cov + top;
+        if (i == k) break;
+        for (uint64_t j = 0; j < theta; ++j) {
+            if (covered[j]) continue;
+            for (uint64_t e = off[j]; e < off[j + 1]; ++e)
+                if (mem[e] == seeds[i]) { covered[j] = 1; cov += 1; break; }
+        }
+    }
+    free(covered);
+    free(marg);
+    return best;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Sample-size control (Section 4, Algorithm 4)                              */
 /* ------------------------------------------------------------------------ */
@@ -664,6 +703,14 @@ double orc_sigma_lower(double lambda2, double a, double n, double theta)
 /* Lemma 5 with p_max = 1: the optimum's coverage in R1 is at most
  * Lambda1 / (1 - (1 - 1/k)^k); lifted to spread by the same concentration
  * term as the lower bound. */
+/* The concentration lift of a coverage upper bound on R1 to an upper bound
+ * on the optimal spread, as in orc_sigma_upper. */
+double orc_sigma_upper_cov(double cov_upper, double a, double n, double theta)
+{
+    double r = sqrt(cov_upper + a / 2.0) + sqrt(a / 2.0);
+    return r * r * n / theta;
+}
+
 double orc_sigma_upper(double lambda1, uint32_t k, double a, double n, double theta)
 {
     double up = lambda1 / (1.0 - pow(1.0 - 1.0 / (double)k, (double)k));
@@ -678,6 +725,7 @@ typedef struct {
     uint64_t lambda1, lambda2;
     double sigma_l, sigma_u, spread, theta_max;
     uint64_t entries1, entries2;
+    uint64_t lambda_u;   /* Equation (8) coverage bound of the last round (bound 0) */
 } orc_result;
 
 /* HyperIM_BRR (Algorithm 4): two independent pools R1 (tag 0) and R2 (tag 1)
@@ -687,7 +735,7 @@ typedef struct {
  * size with no bound test. */
 int orc_select_seeds(const orc_graph *g, uint32_t k, double eps, double ell, uint64_t seed,
                      uint32_t instance, uint32_t qlog, uint64_t theta_fixed, uint32_t nthreads,
-                     uint32_t *seeds, uint64_t *gains, orc_result *res)
+                     uint32_t bound, uint32_t *seeds, uint64_t *gains, orc_result *res)
 {
     if (!g->stratified) return ORC_EINVAL;
     orc_schedule s;
@@ -727,7 +775,14 @@ int orc_select_seeds(const orc_graph *g, uint32_t k, double eps, double ell, uin
         for (uint32_t x = 0; x < k; ++x) lambda1 += gains[x];
         uint64_t lambda2 = orc_coverage(g->n, theta, off2, mem2, k, seeds);
         double sl = orc_sigma_lower((double)lambda2, s.a, (double)g->n, (double)theta);
-        double su = orc_sigma_upper((double)lambda1, k, s.a, (double)g->n, (double)theta);
+        /* upper bound: Equation (8) (bound 0) or Lemma 5's closed form (1) */
+        double su;
+        if (bound == 0) {
+            res->lambda_u = orc_upper_eq8(g->n, theta, off1, mem1, k, seeds);
+            su = orc_sigma_upper_cov((double)res->lambda_u, s.a, (double)g->n, (double)theta);
+        } else {
+            su = orc_sigma_upper((double)lambda1, k, s.a, (double)g->n, (double)theta);
+        }
         res->rounds = i;
         res->theta = theta;
         res->lambda1 = lambda1;

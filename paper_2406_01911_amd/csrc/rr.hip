@@ -1921,8 +1921,10 @@ int run_launch(RRWorkspace &ws, RRStats &st, const hyperim_tuning &tune, RRArgs 
     }
     int batch = trace ? 1 : (int)std::min<uint32_t>(std::max<uint32_t>(tune.steps_per_sync, 1), kMaxBatch);
     // captured batches replay the same parities every time: an even batch
-    // starts every replay on counter parity 0
-    const bool use_graphs = graphs && !trace && !ws.graphs_off;
+    // starts every replay on counter parity 0.  Launches timed one by one
+    // (events stamped by the launch itself) are not captured: an event
+    // recorded inside a graph does not time against one recorded outside.
+    const bool use_graphs = graphs && !trace && !time_kernels && !ws.graphs_off;
     if (use_graphs && (batch & 1)) batch = std::min(batch + 1, kMaxBatch);
     auto account = [&](uint64_t k) -> int {
         hipEvent_t *E = batch_events(ws, k);
@@ -1959,7 +1961,7 @@ int run_launch(RRWorkspace &ws, RRStats &st, const hyperim_tuning &tune, RRArgs 
             if (use_graphs) {
                 // one replay: batch x (k_plan, k_expand) and the counter copy
                 const uint64_t key[8] = {1u, (uint64_t)(kb & 1u), (uint64_t)batch, plan_grid_all,
-                                         (uint64_t)grid_b, (uint64_t)time_kernels, (uint64_t)(uintptr_t)ap,
+                                         (uint64_t)grid_b, 0u, (uint64_t)(uintptr_t)ap,
                                          (uint64_t)(uintptr_t)h ^ ((uint64_t)(uintptr_t)ctr << 1)};
                 hipGraphExec_t ex = nullptr;
                 HIM_CHECK(captured_batch(
@@ -1968,9 +1970,7 @@ int run_launch(RRWorkspace &ws, RRStats &st, const hyperim_tuning &tune, RRArgs 
                         for (int i = 0; i < batch; ++i) {
                             const uint32_t parity = (uint32_t)(i & 1);
                             hipLaunchKernelGGL(k_plan, dim3(plan_grid_all), dim3(kWG), 0, c, ap, parity);
-                            if (time_kernels && hipEventRecord(E[2 + 2 * i], c) != hipSuccess) return false;
                             hipLaunchKernelGGL(k_expand, dim3(grid_b), dim3(kWG), 0, c, ap, parity);
-                            if (time_kernels && hipEventRecord(E[3 + 2 * i], c) != hipSuccess) return false;
                         }
                         return hipMemcpyAsync(dst, ctr, sizeof(unsigned long long) * kNumCtr, hipMemcpyDeviceToHost,
                                               c) == hipSuccess;
@@ -2154,14 +2154,10 @@ int run_ms_launch(RRWorkspace &ws, RRStats &st, const hyperim_tuning &tune, RRAr
             if (ex) (void)hipGraphExecDestroy(ex);
         }
     } batch_exec;
-    auto record_batch = [&](hipStream_t c, int batch, bool in_capture) {
+    auto record_batch = [&](hipStream_t c, int batch) {
         for (int k = 0; k < batch; ++k) {
             hipLaunchKernelGGL(k_ms_plan, dim3(grid_b), dim3(kWG), 0, c, m);
-            if (time_kernels && in_capture) {
-                if (hipEventRecord(E[2 + 2 * k], c) != hipSuccess) return false;
-                hipLaunchKernelGGL(k_ms_expand, dim3(grid_b), dim3(kWG), 0, c, m);
-                if (hipEventRecord(E[3 + 2 * k], c) != hipSuccess) return false;
-            } else if (time_kernels) {
+            if (time_kernels) {
                 hipExtLaunchKernelGGL(k_ms_expand, dim3(grid_b), dim3(kWG), 0, c, E[2 + 2 * k], E[3 + 2 * k], 0u, m);
             } else {
                 hipLaunchKernelGGL(k_ms_expand, dim3(grid_b), dim3(kWG), 0, c, m);
@@ -2173,13 +2169,14 @@ int run_ms_launch(RRWorkspace &ws, RRStats &st, const hyperim_tuning &tune, RRAr
         return hipMemcpyAsync(ws.host + kHostBatch, m.ctr, sizeof(unsigned long long) * kMsNumCtr,
                               hipMemcpyDeviceToHost, c) == hipSuccess;
     };
-    if (graphs && !trace)
-        HIM_CHECK(capture_graph(ws, [&](hipStream_t c) { return record_batch(c, per_sync, true); }, &batch_exec.ex));
+    // (launches timed one by one are not captured, as in run_launch)
+    if (graphs && !trace && !time_kernels)
+        HIM_CHECK(capture_graph(ws, [&](hipStream_t c) { return record_batch(c, per_sync); }, &batch_exec.ex));
     for (;;) {
         const int batch = trace ? 1 : per_sync;
         if (batch_exec.ex) {
             HIM_HIP(hipGraphLaunch(batch_exec.ex, s));
-        } else if (!record_batch(s, batch, false)) {
+        } else if (!record_batch(s, batch)) {
             HIM_HIP(hipGetLastError());
             set_error_detail("bundled superstep batch: a launch or copy failed");
             return HYPERIM_EHIP;

@@ -17,6 +17,7 @@ typedef struct {
     uint64_t theta, lambda1, lambda2;
     double sigma_l, sigma_u, spread, theta_max;
     uint64_t entries1, entries2;
+    uint64_t lambda_u;
 } orc_result;
 
 int orc_graph_new(uint32_t n, uint32_t m, const uint32_t *he_off, const uint32_t *he_mem, uint32_t model, float p,
@@ -35,8 +36,10 @@ int orc_greedy(uint32_t n, uint64_t theta, const uint64_t *off, const uint32_t *
 uint64_t orc_coverage(uint32_t n, uint64_t theta, const uint64_t *off, const uint32_t *mem, uint32_t k,
                       const uint32_t *seeds);
 int orc_select_seeds(const orc_graph *g, uint32_t k, double eps, double ell, uint64_t seed, uint32_t instance,
-                     uint32_t qlog, uint64_t theta_fixed, uint32_t nthreads, uint32_t *seeds, uint64_t *gains,
-                     orc_result *res);
+                     uint32_t qlog, uint64_t theta_fixed, uint32_t nthreads, uint32_t bound, uint32_t *seeds,
+                     uint64_t *gains, orc_result *res);
+uint64_t orc_upper_eq8(uint32_t n, uint64_t theta, const uint64_t *off, const uint32_t *mem, uint32_t k,
+                       const uint32_t *seeds);
 
 static void *read_all(FILE *f, size_t bytes)
 {
@@ -90,13 +93,16 @@ int main(int argc, char **argv)
     if (orc_greedy(n, 2048, off, mem, k, seeds, gains) != 0) return 7;
     sum += orc_coverage(n, 2048, off, mem, k, seeds);
     if (orc_greedy(n, 2048, off, mem, 0, seeds, gains) == 0) return 7;
+    sum += orc_upper_eq8(n, 2048, off, mem, k, seeds);
     orc_free(off);
     orc_free(mem);
     orc_free(roots);
     orc_result r;
-    if (orc_select_seeds(g, k, eps, 1.0, 0, 0, 8, 0, 4, seeds, gains, &r) != 0) return 8;
-    for (uint32_t i = 0; i < k; ++i) sum += seeds[i] + gains[i];
-    if (orc_select_seeds(g, k, eps, 1.0, 0, 0, 8, 4096, 2, seeds, gains, &r) != 0) return 8;
+    for (uint32_t bound = 0; bound < 2; ++bound) {
+        if (orc_select_seeds(g, k, eps, 1.0, 0, 0, 8, 0, 4, bound, seeds, gains, &r) != 0) return 8;
+        for (uint32_t i = 0; i < k; ++i) sum += seeds[i] + gains[i];
+    }
+    if (orc_select_seeds(g, k, eps, 1.0, 0, 0, 8, 4096, 2, 0, seeds, gains, &r) != 0) return 8;
     printf("ok %llu theta %llu\n", (unsigned long long)sum, (unsigned long long)r.theta);
     free(set);
     free(seeds);
