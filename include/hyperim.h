@@ -92,6 +92,12 @@ typedef struct {
                                unreached sets are spent work); 0 -> two per
                                phase-A wavefront of the device, 1 -> off.
                                Not with theta_fixed or form 1.              */
+    uint32_t bound;         /* upper bound of the stop test: 0 = Equation (8),
+                               the smallest over the greedy prefixes S_i*
+                               (i = 0..k) of Lambda_R1(S_i*) plus the k
+                               largest marginal coverages given S_i*
+                               (Lemma 4, p_max = 1); 1 = Lemma 5's closed
+                               form Lambda_R1(S_k*) / (1 - (1 - 1/k)^k)      */
 } hyperim_options;
 
 #define HYPERIM_FLAG_KERNEL_TIMES 2u /* time every expansion-kernel launch
@@ -155,6 +161,8 @@ typedef struct {
                                the bundled expansion kernel's launches        */
     uint64_t bundled_launches; /* its launches                                */
     uint64_t philox_light;  /* part of philox_drawn drawn by the per-set phase */
+    uint64_t lambda_u;      /* upper bound on the optimal coverage of R1 that
+                               sigma_u lifts (Equation (8) or Lemma 5)       */
 } hyperim_result;
 
 /* Build the device-resident hypergraph (Section 2.1: G = (V, HE), V(he)).

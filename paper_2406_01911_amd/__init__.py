@@ -43,7 +43,7 @@ class _StrataInfo(C.Structure):
 
 class _Options(C.Structure):
     _fields_ = [("qlog", C.c_uint32), ("form", C.c_uint32), ("theta_fixed", C.c_uint64),
-                ("max_entries", C.c_uint64), ("flags", C.c_uint32), ("ahead", C.c_uint32)]
+                ("max_entries", C.c_uint64), ("flags", C.c_uint32), ("ahead", C.c_uint32), ("bound", C.c_uint32)]
 
 
 class _Result(C.Structure):
@@ -57,7 +57,7 @@ class _Result(C.Structure):
                 ("bytes_heavy", C.c_uint64), ("ms_expand", C.c_double), ("expand_launches", C.c_uint64),
                 ("philox_drawn", C.c_uint64), ("coins", C.c_uint64), ("philox_alg", C.c_uint64),
                 ("philox_bundled", C.c_uint64), ("bytes_bundled", C.c_uint64), ("ms_bundled", C.c_double),
-                ("bundled_launches", C.c_uint64), ("philox_light", C.c_uint64)]
+                ("bundled_launches", C.c_uint64), ("philox_light", C.c_uint64), ("lambda_u", C.c_uint64)]
 
 
 class _Tuning(C.Structure):
@@ -337,12 +337,12 @@ def coverage_noalloc(g: Graph, pool: Pool, theta: int, seeds_dev: torch.Tensor, 
 
 def select_seeds(g: Graph, k: int, eps: float, ell: float, seed: int = 0, instance: int = 0, qlog: int = 0,
                  form: int = 0, theta_fixed: int = 0, max_entries: int = 0, flags: int = 0, stream=None,
-                 ahead: int = 0) -> dict:
+                 ahead: int = 0, bound: int = 0) -> dict:
     """hyperim_select_seeds (HyperIM_BRR loop) -> dict with seeds, gains and the result fields.
     ahead: hyperim_options.ahead (0: device default, 1: off)."""
     seeds = np.zeros(k, np.uint32)
     gains = np.zeros(k, np.uint64)
-    opt = _Options(qlog, form, theta_fixed, max_entries, flags, ahead)
+    opt = _Options(qlog, form, theta_fixed, max_entries, flags, ahead, bound)
     res = _Result()
     _check(_lib.hyperim_select_seeds(g._h, k, eps, ell, seed, instance, C.byref(opt), _stream(stream),
                                      _ptr(seeds), _ptr(gains), C.byref(res)))
@@ -368,7 +368,7 @@ def _query(q) -> _Query:
 
 def select_seeds_batch(queries, qlog: int = 0, form: int = 0, theta_fixed: int = 0, max_entries: int = 0,
                        flags: int = 0, stream=None, raise_on_error: bool = True, totals: dict | None = None,
-                       ahead: int = 0) -> list:
+                       ahead: int = 0, bound: int = 0) -> list:
     """hyperim_select_seeds_batch: queries answered together (shared RR launches).
 
     Each query is a dict {graph, k, eps, ell, seed, instance}; returns one dict
@@ -381,7 +381,7 @@ def select_seeds_batch(queries, qlog: int = 0, form: int = 0, theta_fixed: int =
     gains = np.zeros(max(sum(ks), 1), np.uint64)
     res = (_Result * max(len(qs), 1))()
     status = (C.c_int * max(len(qs), 1))()
-    opt = _Options(qlog, form, theta_fixed, max_entries, flags, ahead)
+    opt = _Options(qlog, form, theta_fixed, max_entries, flags, ahead, bound)
     tot = _Result()
     rc = _lib.hyperim_select_seeds_batch(arr, len(qs), C.byref(opt), _stream(stream), _ptr(seeds), _ptr(gains),
                                          res, status, C.byref(tot))
@@ -405,9 +405,9 @@ class Session:
     to advance every admitted query by one round, poll for results."""
 
     def __init__(self, hbm_budget: int = 0, qlog: int = 0, form: int = 0, theta_fixed: int = 0,
-                 max_entries: int = 0, flags: int = 0, stream=None, ahead: int = 0):
+                 max_entries: int = 0, flags: int = 0, stream=None, ahead: int = 0, bound: int = 0):
         load_library()
-        opt = _Options(qlog, form, theta_fixed, max_entries, flags, ahead)
+        opt = _Options(qlog, form, theta_fixed, max_entries, flags, ahead, bound)
         h = C.c_void_p()
         _check(_lib.hyperim_session_create(int(hbm_budget), C.byref(opt), _stream(stream), C.byref(h)))
         self._h = h

@@ -119,7 +119,7 @@ DeviceLock::~DeviceLock() { static_cast<DevCtx *>(lock)->mu.unlock(); }
 
 void GreedyWorkspace::release() {
     for (DevBuf *x : {&cnt, &inv_off, &cursor, &inv, &covered, &chosen, &best, &out, &big, &cursor_big, &flags,
-                      &counters, &scan_tmp, &params})
+                      &counters, &scan_tmp, &params, &topk})
         x->release();
     if (rounds_exec) (void)hipGraphExecDestroy(rounds_exec);
     rounds_exec = nullptr;
@@ -170,7 +170,7 @@ void PrepWorkspace::release() {
 size_t GreedyWorkspace::bytes() const {
     size_t b = 0;
     for (const DevBuf *x : {&cnt, &inv_off, &cursor, &inv, &covered, &chosen, &best, &out, &big, &cursor_big, &flags,
-                            &counters, &scan_tmp})
+                            &counters, &scan_tmp, &topk})
         b += x->bytes;
     return b;
 }

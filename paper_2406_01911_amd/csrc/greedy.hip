@@ -125,7 +125,121 @@ struct GreedyParams {
     unsigned long long *gains;
     unsigned long long *best;        // k argmax keys
     uint32_t n;
+    // Equation (8): before each round (and after the last) the sum of the k
+    // largest counts, exact, selected by value-range histograms of kTkBins
+    // bins over up to three levels of the counts' bits
+    uint32_t *tk_cnt;                // kTkBins bin counts
+    unsigned long long *tk_sum;      // kTkBins bin sums
+    unsigned long long *tk_state;    // selected prefix, remaining count, sum so far
+    unsigned long long *ub;          // k + 1 top-k sums, one per greedy prefix
+    uint32_t k, tk_levels, tk_shift[3];
 };
+
+constexpr uint32_t kTkBins = 2048;
+
+// Histogram, for the current prefix's top-k selection at `level`, of the
+// counts whose higher bits equal the prefix selected so far: bin
+// (cnt >> tk_shift[level]) & (kTkBins - 1), counts and sums.  Most counts
+// fall into bin 0, which each wavefront adds up before one LDS update.
+__global__ __launch_bounds__(kWG) void k_topk_hist(const GreedyParams *__restrict__ P, uint32_t level) {
+    __shared__ uint32_t hc[kTkBins];
+    __shared__ unsigned long long hs[kTkBins];
+    for (uint32_t i = threadIdx.x; i < kTkBins; i += kWG) {
+        hc[i] = 0u;
+        hs[i] = 0ull;
+    }
+    __syncthreads();
+    const uint32_t n = P->n, shift = P->tk_shift[level];
+    const bool filt = level > 0;
+    const uint32_t pshift = filt ? P->tk_shift[level - 1] : 0u;
+    const unsigned long long prefix = filt ? P->tk_state[0] : 0ull;
+    const uint32_t lane = lane_id();
+    for (uint64_t base = (uint64_t)blockIdx.x * kWG; base < n; base += (uint64_t)gridDim.x * kWG) {
+        const uint64_t v = base + threadIdx.x;
+        uint32_t x = 0;
+        bool in = false;
+        if (v < n) {
+            x = P->cnt[v];
+            in = !filt || (unsigned long long)(x >> pshift) == prefix;
+        }
+        const uint32_t bin = (x >> shift) & (kTkBins - 1u);
+        const bool zero = in && bin == 0u;
+        const uint64_t zb = __ballot(zero);
+        const unsigned long long zs = wave_sum(zero ? (unsigned long long)x : 0ull);
+        if (lane == 0 && zb) {
+            atomicAdd(&hc[0], (uint32_t)__popcll(zb));
+            atomicAdd(&hs[0], zs);
+        }
+        if (in && bin != 0u) {
+            atomicAdd(&hc[bin], 1u);
+            atomicAdd(&hs[bin], (unsigned long long)x);
+        }
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < kTkBins; i += kWG)
+        if (hc[i]) {
+            atomicAdd(&P->tk_cnt[i], hc[i]);
+            atomicAdd(&P->tk_sum[i], hs[i]);
+        }
+}
+
+// One wavefront: the bin that holds the k-th largest count among those the
+// histogram took; the bins above it are added to the sum.  At the last
+// level the bin is one exact value and ub[round] is complete; otherwise the
+// prefix, the remaining count and the sum go to tk_state for the next level.
+// The histogram is cleared for the next pass.
+__global__ __launch_bounds__(kWave) void k_topk_select(const GreedyParams *__restrict__ P, uint32_t level,
+                                                       uint32_t round) {
+    const uint32_t lane = lane_id();
+    unsigned long long need = level ? P->tk_state[1] : (unsigned long long)P->k;
+    unsigned long long acc = level ? P->tk_state[2] : 0ull;
+    const unsigned long long prefix = level ? P->tk_state[0] : 0ull;
+    unsigned long long above = 0, above_sum = 0;
+    uint32_t found = 0;
+    for (int c = (int)(kTkBins / kWave) - 1; c >= 0; --c) {
+        const uint32_t b = (uint32_t)c * kWave + lane;
+        const unsigned long long cb = P->tk_cnt[b], sb = P->tk_sum[b];
+        // from the top: counts and sums of this chunk's bins b' >= b
+        unsigned long long cs = cb, ss = sb;
+#pragma unroll
+        for (uint32_t d = 1; d < kWave; d <<= 1) {
+            const unsigned long long y = __shfl_down(cs, d, kWave), z = __shfl_down(ss, d, kWave);
+            if (lane + d < kWave) {
+                cs += y;
+                ss += z;
+            }
+        }
+        const bool hit = above + cs >= need && above + cs - cb < need;
+        const uint64_t hb = __ballot(hit);
+        if (hb) {
+            const int hl = __ffsll((unsigned long long)hb) - 1;
+            const unsigned long long cab = above + __shfl(cs, hl, kWave) - __shfl(cb, hl, kWave);
+            const unsigned long long sab = above_sum + __shfl(ss, hl, kWave) - __shfl(sb, hl, kWave);
+            need -= cab;
+            acc += sab;
+            found = (uint32_t)c * kWave + (uint32_t)hl;
+            break;
+        }
+        above += __shfl(cs, 0, kWave);
+        above_sum += __shfl(ss, 0, kWave);
+    }
+    const uint32_t shift = P->tk_shift[level];
+    const uint32_t pshift = level ? P->tk_shift[level - 1] : shift;
+    const unsigned long long sel = level ? (prefix << (pshift - shift)) | found : (unsigned long long)found;
+    if (lane == 0) {
+        if (level + 1 == P->tk_levels) {
+            P->ub[round] = acc + need * sel;   // shift 0: the bin is the value itself
+        } else {
+            P->tk_state[0] = sel;
+            P->tk_state[1] = need;
+            P->tk_state[2] = acc;
+        }
+    }
+    for (uint32_t i = lane; i < kTkBins; i += kWave) {
+        P->tk_cnt[i] = 0u;
+        P->tk_sum[i] = 0ull;
+    }
+}
 
 // key = 0 for chosen vertices, else (cnt + 1) << 32 | (~v): the max is the
 // largest count, then the smallest id.
@@ -318,7 +432,7 @@ int big_list(hyperim_pool p, uint64_t theta, uint64_t *list, unsigned long long 
 }  // namespace
 
 int greedy_device(GreedyWorkspace &w, hyperim_graph g, hyperim_pool p, uint64_t theta, uint32_t k, hipStream_t s,
-                  uint32_t *seeds_host, uint64_t *gains_host) {
+                  uint32_t *seeds_host, uint64_t *gains_host, uint64_t *ub_host) {
     const uint32_t n = g->n;
     uint64_t entries = 0;
     HIM_CHECK(read_entries(p, theta, s, &entries));
@@ -362,19 +476,46 @@ int greedy_device(GreedyWorkspace &w, hyperim_graph g, hyperim_pool p, uint64_t 
     const uint32_t inval_grid = 256;
     GreedyParams hp{p->off,   p->mem, w.inv_off.as<uint64_t>(), w.inv.as<uint32_t>(), w.cursor.as<uint32_t>(),
                     w.covered.as<uint32_t>(), w.cnt.as<uint32_t>(), w.chosen.as<uint8_t>(), seeds, gains, best, n};
+    // Equation (8): levels of kTkBins-bin histograms over the counts' bits
+    // (every count is at most theta)
+    uint32_t levels = 0;
+    if (ub_host) {
+        const uint32_t bits = theta ? 64u - (uint32_t)__builtin_clzll(theta) : 1u;
+        levels = bits <= 11 ? 1u : bits <= 22 ? 2u : 3u;
+        hp.tk_shift[0] = levels == 1 ? 0u : bits - 11u;
+        hp.tk_shift[1] = levels == 2 ? 0u : bits - 22u;
+        hp.tk_shift[2] = 0u;
+        const size_t tk_bytes = kTkBins * (sizeof(uint32_t) + sizeof(unsigned long long)) +
+                                3 * sizeof(unsigned long long) + sizeof(unsigned long long) * ((size_t)k + 1);
+        HIM_CHECK(w.topk.reserve(tk_bytes, s));
+        hp.tk_sum = w.topk.as<unsigned long long>();
+        hp.tk_state = hp.tk_sum + kTkBins;
+        hp.ub = hp.tk_state + 3;
+        hp.tk_cnt = reinterpret_cast<uint32_t *>(hp.ub + k + 1);
+        HIM_HIP(hipMemsetAsync(w.topk.ptr, 0, tk_bytes, s));
+    }
+    hp.k = k;
+    hp.tk_levels = levels;
     HIM_CHECK(w.params.reserve(sizeof(GreedyParams), s));
     static_assert(sizeof(GreedyParams) <= sizeof(w.params_host), "parameter block");
     memcpy(w.params_host, &hp, sizeof(hp));
     HIM_HIP(hipMemcpyAsync(w.params.ptr, w.params_host, sizeof(GreedyParams), hipMemcpyHostToDevice, s));
     const GreedyParams *P = w.params.as<GreedyParams>();
+    const uint32_t hist_grid = grid_for(n, 4 * kWG, 1024);
     if (!w.rounds_exec || w.graph_k != k || w.graph_grid[0] != argmax_grid || w.graph_grid[1] != inval_grid ||
-        w.graph_params != w.params.ptr) {
+        w.graph_params != w.params.ptr || w.graph_levels != levels) {
         if (w.rounds_exec) HIM_HIP(hipGraphExecDestroy(w.rounds_exec));
         w.rounds_exec = nullptr;
         if (!w.capture) HIM_HIP(hipStreamCreateWithFlags(&w.capture, hipStreamNonBlocking));
         hipGraph_t graph = nullptr;
         HIM_HIP(hipStreamBeginCapture(w.capture, hipStreamCaptureModeThreadLocal));
-        for (uint32_t i = 0; i < k; ++i) {
+        for (uint32_t i = 0; i <= k; ++i) {
+            // Equation (8)'s term for the first i seeds, then round i
+            for (uint32_t l = 0; l < levels; ++l) {
+                hipLaunchKernelGGL(k_topk_hist, dim3(hist_grid), dim3(kWG), 0, w.capture, P, l);
+                hipLaunchKernelGGL(k_topk_select, dim3(1), dim3(kWave), 0, w.capture, P, l, i);
+            }
+            if (i == k) break;
             hipLaunchKernelGGL(k_argmax, dim3(argmax_grid), dim3(kWG), 0, w.capture, P, i);
             hipLaunchKernelGGL(k_invalidate, dim3(inval_grid), dim3(kWG), 0, w.capture, P, i);
         }
@@ -386,11 +527,14 @@ int greedy_device(GreedyWorkspace &w, hyperim_graph g, hyperim_pool p, uint64_t 
         w.graph_grid[0] = argmax_grid;
         w.graph_grid[1] = inval_grid;
         w.graph_params = w.params.ptr;
+        w.graph_levels = levels;
     }
     HIM_HIP(hipGraphLaunch(w.rounds_exec, s));
     HIM_HIP(hipGetLastError());
     if (seeds_host) HIM_HIP(hipMemcpyAsync(seeds_host, seeds, sizeof(uint32_t) * k, hipMemcpyDeviceToHost, s));
     if (gains_host) HIM_HIP(hipMemcpyAsync(gains_host, gains, sizeof(uint64_t) * k, hipMemcpyDeviceToHost, s));
+    if (ub_host)
+        HIM_HIP(hipMemcpyAsync(ub_host, hp.ub, sizeof(uint64_t) * ((size_t)k + 1), hipMemcpyDeviceToHost, s));
     HIM_HIP(hipStreamSynchronize(s));
     return HYPERIM_OK;
 }

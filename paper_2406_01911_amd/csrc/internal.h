@@ -119,12 +119,13 @@ struct GreedyWorkspace {
     DevBuf flags;     // n uint8 seed marks (coverage)
     DevBuf counters;  // coverage counters
     DevBuf scan_tmp;
+    DevBuf topk;      // Equation (8): bin counts and sums, selection state, k + 1 top-k sums
     DevBuf params;    // argument block of the per-round kernels
     alignas(16) unsigned char params_host[256];
     // captured graph of the k greedy rounds and what it was captured for
     hipStream_t capture = nullptr;
     hipGraphExec_t rounds_exec = nullptr;
-    uint32_t graph_k = 0, graph_grid[2] = {0, 0};
+    uint32_t graph_k = 0, graph_grid[2] = {0, 0}, graph_levels = 0;
     void *graph_params = nullptr;
     size_t bytes() const;
     void release();
@@ -285,8 +286,10 @@ int rr_incidences(hyperim_graph g, hyperim_pool p, uint64_t theta, hipStream_t s
 // ---- launchers (greedy.hip) ---------------------------------------------------
 // Greedy max coverage of the pool's first theta sets; the seeds also stay in
 // w.out (device) for coverage_device.
+// ub_host (k + 1 entries, may be null): for i = 0..k the sum of the k largest
+// marginal coverages given the first i seeds (Equation (8)'s terms).
 int greedy_device(GreedyWorkspace &w, hyperim_graph g, hyperim_pool p, uint64_t theta, uint32_t k, hipStream_t s,
-                  uint32_t *seeds_host, uint64_t *gains_host);
+                  uint32_t *seeds_host, uint64_t *gains_host, uint64_t *ub_host = nullptr);
 int coverage_device(GreedyWorkspace &w, hyperim_graph g, hyperim_pool p, uint64_t theta, const uint32_t *seeds_dev,
                     uint32_t k, hipStream_t s, uint64_t *covered_host);
 

@@ -59,11 +59,27 @@ double lower_bound(double lambda2, double a, double n, double theta) {
     return v * n / theta;
 }
 
-// Lemma 5 with p_max = 1, lifted by the OPIM-C concentration term.
-double upper_bound(double lambda1, uint32_t k, double a, double n, double theta) {
-    const double cov = lambda1 / (1.0 - std::pow(1.0 - 1.0 / (double)k, (double)k));
+// An upper bound on the optimal coverage of R1, lifted to the optimal spread
+// by the OPIM-C concentration term.
+double upper_bound_cov(double cov, double a, double n, double theta) {
     const double r = std::sqrt(cov + a / 2.0) + std::sqrt(a / 2.0);
     return r * r * n / theta;
+}
+
+// Lemma 5 with p_max = 1: Lambda1 / (1 - (1 - 1/k)^k), lifted.
+double upper_bound(double lambda1, uint32_t k, double a, double n, double theta) {
+    return upper_bound_cov(lambda1 / (1.0 - std::pow(1.0 - 1.0 / (double)k, (double)k)), a, n, theta);
+}
+
+// Equation (8) with p_max = 1 from greedy's gains and the top-k sums of the
+// marginal coverages before each round and after the last (ub[0..k]).
+uint64_t eq8_coverage(const std::vector<uint64_t> &gains, const std::vector<uint64_t> &ub) {
+    uint64_t best = ~0ull, cov = 0;
+    for (size_t i = 0; i < ub.size(); ++i) {
+        best = std::min(best, cov + ub[i]);
+        if (i < gains.size()) cov += gains[i];
+    }
+    return best;
 }
 
 struct EventPair {
@@ -164,8 +180,8 @@ int validate(const hyperim_query &q, const hyperim_options &o) {
         return HYPERIM_ESTATE;
     }
     if (q.k == 0 || q.k > q.graph->n || !(q.eps > 0.0 && q.eps < 1.0) || !(q.ell > 0.0) || q.seed >> 32 ||
-        o.qlog > 24 || o.form > 1) {
-        set_error_detail("need 1 <= k <= n, 0 < eps < 1, ell > 0, seed < 2^32, qlog <= 24, form 0/1");
+        o.qlog > 24 || o.form > 1 || o.bound > 1) {
+        set_error_detail("need 1 <= k <= n, 0 < eps < 1, ell > 0, seed < 2^32, qlog <= 24, form 0/1, bound 0/1");
         return HYPERIM_EINVAL;
     }
     return HYPERIM_OK;
@@ -499,10 +515,12 @@ struct Engine {
             const uint32_t k = q->q.k;
             float ms = 0.f;
             uint64_t lambda2 = 0;
+            std::vector<uint64_t> ub(o.bound == 0 ? (size_t)k + 1 : 0, 0ull);
             {
                 DeviceLock lk(device);
                 HIM_HIP(hipEventRecord(ev.a, s));
-                HIM_CHECK(greedy_device(*lk.gr, g, &q->pp->r[0], theta, k, s, q->seeds.data(), q->gains.data()));
+                HIM_CHECK(greedy_device(*lk.gr, g, &q->pp->r[0], theta, k, s, q->seeds.data(), q->gains.data(),
+                                        o.bound == 0 ? ub.data() : nullptr));
                 HIM_CHECK(coverage_device(*lk.gr, g, &q->pp->r[1], theta, lk.gr->out.as<uint32_t>(), k, s,
                                           &lambda2));
                 HIM_HIP(hipEventRecord(ev.b, s));
@@ -515,7 +533,10 @@ struct Engine {
             for (uint32_t x = 0; x < k; ++x) lambda1 += q->gains[x];
             const double n = (double)g->n;
             const double sl = lower_bound((double)lambda2, q->sc.a, n, (double)theta);
-            const double su = upper_bound((double)lambda1, k, q->sc.a, n, (double)theta);
+            // the stop test's upper bound: Equation (8), or Lemma 5's closed form
+            const uint64_t lam_u = o.bound == 0 ? eq8_coverage(q->gains, ub) : 0ull;
+            const double su = o.bound == 0 ? upper_bound_cov((double)lam_u, q->sc.a, n, (double)theta)
+                                           : upper_bound((double)lambda1, k, q->sc.a, n, (double)theta);
             q->round += 1;
             res.rounds = q->round;
             res.theta = theta;
@@ -523,6 +544,7 @@ struct Engine {
             res.lambda2 = lambda2;
             res.sigma_l = sl;
             res.sigma_u = su;
+            res.lambda_u = lam_u;
             res.spread = n * (double)lambda2 / (double)theta;
             const bool stop =
                 o.theta_fixed || (su > 0.0 && sl / su >= tconst - q->q.eps) || q->round >= q->sc.i_max;
