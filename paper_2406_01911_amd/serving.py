@@ -98,7 +98,9 @@ def serve(graphs: list, queries: list, arrivals: np.ndarray, hbm_budget: int = 0
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--qps", type=float, default=5.0)
+    ap.add_argument("--qps", type=str, default="5.0",
+                    help="arrival rate, or a comma-separated list of rates run one after another "
+                         "(a fresh session each, the graphs built once)")
     ap.add_argument("--queries", type=int, default=200)
     ap.add_argument("--graphs", type=int, default=16)
     ap.add_argument("--n-max", type=float, default=5e6)
@@ -124,25 +126,28 @@ def main():
         graphs.append(g)
         log(f"[serving] graph {i}: n={w.n} nnz={int(hg.he_off[-1])} ({time.time() - t0:.1f} s)")
     queries = draw_queries(args.queries, len(graphs), seed=args.seed)
-    arrivals = poisson_arrivals(args.queries, args.qps, seed=args.seed)
-    run = serve(graphs, queries, arrivals, int(args.budget_gb * 1e9), log=log)
-    # a sample re-run alone must give the same bytes
-    rng = np.random.Generator(np.random.PCG64(args.seed + 7))
-    checked = 0
-    for i in rng.choice(len(queries), size=min(args.verify, len(queries)), replace=False):
-        q, r = queries[i], run["results"][i]
-        a = hy.select_seeds(graphs[q["graph"]], q["k"], q["eps"], q["ell"], seed=q["seed"], instance=q["instance"])
-        assert np.array_equal(a["seeds"], r["seeds"]) and np.array_equal(a["gains"], r["gains"]), i
-        assert a["theta"] == r["theta"] and a["lambda2"] == r["lambda2"], i
-        checked += 1
-    line = {"metric": "queries/s", "value": run["summary"]["qps_served"], "unit": "queries/s",
-            "latency": {k: run["summary"][k] for k in ("p50_ms", "p99_ms", "mean_ms", "max_ms")},
-            "workload": f"{args.graphs} graphs, |V| log-spaced {int(args.n_min)}..{int(args.n_max)}, |HE|=2|V|, "
-                        f"sizes power-law(2.1) on [2,1000], uniform members, WC; k in {{10,50,200}}, eps=0.1; "
-                        f"Poisson arrivals at {args.qps} qps, {args.queries} queries",
-            "verified_alone": checked}
-    line.update({k: v for k, v in run["summary"].items() if k not in line["latency"]})
-    print(json.dumps(line), flush=True)
+    for qps in [float(x) for x in args.qps.split(",") if x.strip()]:
+        log(f"[serving] rate {qps} qps, {args.queries} queries")
+        arrivals = poisson_arrivals(args.queries, qps, seed=args.seed)
+        run = serve(graphs, queries, arrivals, int(args.budget_gb * 1e9), log=log)
+        # a sample re-run alone must give the same bytes
+        rng = np.random.Generator(np.random.PCG64(args.seed + 7))
+        checked = 0
+        for i in rng.choice(len(queries), size=min(args.verify, len(queries)), replace=False):
+            q, r = queries[i], run["results"][i]
+            a = hy.select_seeds(graphs[q["graph"]], q["k"], q["eps"], q["ell"], seed=q["seed"],
+                                instance=q["instance"])
+            assert np.array_equal(a["seeds"], r["seeds"]) and np.array_equal(a["gains"], r["gains"]), i
+            assert a["theta"] == r["theta"] and a["lambda2"] == r["lambda2"], i
+            checked += 1
+        line = {"metric": "queries/s", "value": run["summary"]["qps_served"], "unit": "queries/s",
+                "latency": {k: run["summary"][k] for k in ("p50_ms", "p99_ms", "mean_ms", "max_ms")},
+                "workload": f"{args.graphs} graphs, |V| log-spaced {int(args.n_min)}..{int(args.n_max)}, "
+                            f"|HE|=2|V|, sizes power-law(2.1) on [2,1000], uniform members, WC; "
+                            f"k in {{10,50,200}}, eps=0.1; Poisson arrivals at {qps} qps, {args.queries} queries",
+                "qps_rate": qps, "verified_alone": checked}
+        line.update({k: v for k, v in run["summary"].items() if k not in line["latency"]})
+        print(json.dumps(line), flush=True)
 
 
 if __name__ == "__main__":
