@@ -11,7 +11,9 @@
 // invalidated at most once, so all rounds together touch each pool entry at
 // most once.  Each round is two kernels, the argmax and the invalidation; in
 // the latter small sets are processed by wavefronts flattened over 64 sets,
-// and sets above kBigSet members in chunks spread over the whole grid.
+// and sets above kBigSet members in chunks spread over the whole grid.  With
+// Equation (8)'s bound the argmax pass also builds the first level of the
+// prefix's top-k histogram (one more pass per further level).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -132,113 +134,149 @@ struct GreedyParams {
     unsigned long long *tk_sum;      // kTkBins bin sums
     unsigned long long *tk_state;    // selected prefix, remaining count, sum so far
     unsigned long long *ub;          // k + 1 top-k sums, one per greedy prefix
+    uint32_t *tk_done;               // workgroups that added their histogram (zero between passes)
     uint32_t k, tk_levels, tk_shift[3];
 };
 
 constexpr uint32_t kTkBins = 2048;
 
-// Histogram, for the current prefix's top-k selection at `level`, of the
-// counts whose higher bits equal the prefix selected so far: bin
-// (cnt >> tk_shift[level]) & (kTkBins - 1), counts and sums.  Most counts
-// fall into bin 0, which each wavefront adds up before one LDS update.
-__global__ __launch_bounds__(kWG) void k_topk_hist(const GreedyParams *__restrict__ P, uint32_t level) {
-    __shared__ uint32_t hc[kTkBins];
-    __shared__ unsigned long long hs[kTkBins];
-    for (uint32_t i = threadIdx.x; i < kTkBins; i += kWG) {
-        hc[i] = 0u;
-        hs[i] = 0ull;
+// Equation (8)'s term for one greedy prefix: the sum of the k largest
+// counts, by value-range histograms over the counts' bits.  At `level` a
+// count x whose higher bits equal the prefix selected so far goes to bin
+// (x >> tk_shift[level]) & (kTkBins - 1) (counts and sums).  Each workgroup
+// builds its histogram in LDS and adds it to the global one; the workgroup
+// that finishes last selects the bin holding the k-th largest count.
+
+// Adds x (when `in`) to the LDS histogram; every lane of the wave calls it.
+// Most counts fall into bin 0, which the wave adds up before one update.
+__device__ __forceinline__ void tk_add(uint32_t *hc, unsigned long long *hs, uint32_t x, bool in, uint32_t shift) {
+    const uint32_t bin = (x >> shift) & (kTkBins - 1u);
+    const bool zero = in && bin == 0u;
+    const uint64_t zb = __ballot(zero);
+    const unsigned long long zs = wave_sum(zero ? (unsigned long long)x : 0ull);
+    if (lane_id() == 0 && zb) {
+        atomicAdd(&hc[0], (uint32_t)__popcll(zb));
+        atomicAdd(&hs[0], zs);
     }
+    if (in && bin != 0u) {
+        atomicAdd(&hc[bin], 1u);
+        atomicAdd(&hs[bin], (unsigned long long)x);
+    }
+}
+
+// The whole (last) workgroup, after every workgroup's histogram is in: the
+// bin that holds the k-th largest count among those the histogram took; the
+// bins above it are added to the sum.  Each thread loads kTkBins / kWG
+// consecutive bins at once; a suffix scan of the per-thread totals over the
+// workgroup finds the thread whose range holds the boundary, which walks
+// its bins from the top.  At the last level the bin is one exact value and
+// ub[round] is complete; otherwise the prefix, the remaining count and the
+// sum go to tk_state for the next level.  The histogram and the workgroup
+// counter are cleared for the next pass.
+constexpr uint32_t kTkPerThread = kTkBins / kWG;
+static_assert(kTkBins % kWG == 0, "bins per thread");
+__device__ void tk_select(const GreedyParams *__restrict__ P, uint32_t level, uint32_t round) {
+    __shared__ unsigned long long sc[kWG], ss[kWG];
+    const uint32_t t = threadIdx.x, b0 = t * kTkPerThread;
+    unsigned long long c[kTkPerThread], v[kTkPerThread];
+    unsigned long long tc = 0, ts = 0;
+#pragma unroll
+    for (uint32_t j = 0; j < kTkPerThread; ++j) {
+        c[j] = __hip_atomic_load(&P->tk_cnt[b0 + j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        v[j] = __hip_atomic_load(&P->tk_sum[b0 + j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        tc += c[j];
+        ts += v[j];
+    }
+    sc[t] = tc;
+    ss[t] = ts;
     __syncthreads();
-    const uint32_t n = P->n, shift = P->tk_shift[level];
-    const bool filt = level > 0;
-    const uint32_t pshift = filt ? P->tk_shift[level - 1] : 0u;
-    const unsigned long long prefix = filt ? P->tk_state[0] : 0ull;
-    const uint32_t lane = lane_id();
-    for (uint64_t base = (uint64_t)blockIdx.x * kWG; base < n; base += (uint64_t)gridDim.x * kWG) {
-        const uint64_t v = base + threadIdx.x;
-        uint32_t x = 0;
-        bool in = false;
-        if (v < n) {
-            x = P->cnt[v];
-            in = !filt || (unsigned long long)(x >> pshift) == prefix;
+    // suffix sums: sc[t] = counts of bins >= b0
+    for (uint32_t d = 1; d < (uint32_t)kWG; d <<= 1) {
+        const unsigned long long yc = t + d < (uint32_t)kWG ? sc[t + d] : 0ull;
+        const unsigned long long ys = t + d < (uint32_t)kWG ? ss[t + d] : 0ull;
+        __syncthreads();
+        sc[t] += yc;
+        ss[t] += ys;
+        __syncthreads();
+    }
+    const unsigned long long need = level ? P->tk_state[1] : (unsigned long long)P->k;
+    unsigned long long above = sc[t] - tc, above_sum = ss[t] - ts;
+    if (above < need && sc[t] >= need) {   // exactly one thread: the boundary is in its range
+        const unsigned long long acc0 = level ? P->tk_state[2] : 0ull;
+        const unsigned long long prefix = level ? P->tk_state[0] : 0ull;
+        uint32_t found = b0;
+        for (int j = (int)kTkPerThread - 1; j >= 0; --j) {
+            if (above + c[j] >= need) {
+                found = b0 + (uint32_t)j;
+                break;
+            }
+            above += c[j];
+            above_sum += v[j];
         }
-        const uint32_t bin = (x >> shift) & (kTkBins - 1u);
-        const bool zero = in && bin == 0u;
-        const uint64_t zb = __ballot(zero);
-        const unsigned long long zs = wave_sum(zero ? (unsigned long long)x : 0ull);
-        if (lane == 0 && zb) {
-            atomicAdd(&hc[0], (uint32_t)__popcll(zb));
-            atomicAdd(&hs[0], zs);
-        }
-        if (in && bin != 0u) {
-            atomicAdd(&hc[bin], 1u);
-            atomicAdd(&hs[bin], (unsigned long long)x);
+        const unsigned long long rest = need - above, acc = acc0 + above_sum;
+        const uint32_t shift = P->tk_shift[level];
+        const uint32_t pshift = level ? P->tk_shift[level - 1] : shift;
+        const unsigned long long sel = level ? (prefix << (pshift - shift)) | found : (unsigned long long)found;
+        if (level + 1 == P->tk_levels) {
+            P->ub[round] = acc + rest * sel;   // shift 0: the bin is the value itself
+        } else {
+            P->tk_state[0] = sel;
+            P->tk_state[1] = rest;
+            P->tk_state[2] = acc;
         }
     }
+#pragma unroll
+    for (uint32_t j = 0; j < kTkPerThread; ++j) {
+        P->tk_cnt[b0 + j] = 0u;
+        P->tk_sum[b0 + j] = 0ull;
+    }
+    if (t == 0) *P->tk_done = 0u;
+}
+
+// Adds the workgroup's LDS histogram to the global one; the workgroup that
+// adds last (a device-scope counter, each workgroup's atomics fenced before
+// its increment) runs tk_select.
+__device__ void tk_flush(const GreedyParams *__restrict__ P, const uint32_t *hc, const unsigned long long *hs,
+                         uint32_t level, uint32_t round) {
+    __shared__ uint32_t last;
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < kTkBins; i += kWG)
         if (hc[i]) {
             atomicAdd(&P->tk_cnt[i], hc[i]);
             atomicAdd(&P->tk_sum[i], hs[i]);
         }
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) last = atomicAdd(P->tk_done, 1u) == gridDim.x - 1u ? 1u : 0u;
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    tk_select(P, level, round);
 }
 
-// One wavefront: the bin that holds the k-th largest count among those the
-// histogram took; the bins above it are added to the sum.  At the last
-// level the bin is one exact value and ub[round] is complete; otherwise the
-// prefix, the remaining count and the sum go to tk_state for the next level.
-// The histogram is cleared for the next pass.
-__global__ __launch_bounds__(kWave) void k_topk_select(const GreedyParams *__restrict__ P, uint32_t level,
-                                                       uint32_t round) {
-    const uint32_t lane = lane_id();
-    unsigned long long need = level ? P->tk_state[1] : (unsigned long long)P->k;
-    unsigned long long acc = level ? P->tk_state[2] : 0ull;
-    const unsigned long long prefix = level ? P->tk_state[0] : 0ull;
-    unsigned long long above = 0, above_sum = 0;
-    uint32_t found = 0;
-    for (int c = (int)(kTkBins / kWave) - 1; c >= 0; --c) {
-        const uint32_t b = (uint32_t)c * kWave + lane;
-        const unsigned long long cb = P->tk_cnt[b], sb = P->tk_sum[b];
-        // from the top: counts and sums of this chunk's bins b' >= b
-        unsigned long long cs = cb, ss = sb;
-#pragma unroll
-        for (uint32_t d = 1; d < kWave; d <<= 1) {
-            const unsigned long long y = __shfl_down(cs, d, kWave), z = __shfl_down(ss, d, kWave);
-            if (lane + d < kWave) {
-                cs += y;
-                ss += z;
-            }
-        }
-        const bool hit = above + cs >= need && above + cs - cb < need;
-        const uint64_t hb = __ballot(hit);
-        if (hb) {
-            const int hl = __ffsll((unsigned long long)hb) - 1;
-            const unsigned long long cab = above + __shfl(cs, hl, kWave) - __shfl(cb, hl, kWave);
-            const unsigned long long sab = above_sum + __shfl(ss, hl, kWave) - __shfl(sb, hl, kWave);
-            need -= cab;
-            acc += sab;
-            found = (uint32_t)c * kWave + (uint32_t)hl;
-            break;
-        }
-        above += __shfl(cs, 0, kWave);
-        above_sum += __shfl(ss, 0, kWave);
+__device__ __forceinline__ void tk_clear(uint32_t *hc, unsigned long long *hs) {
+    for (uint32_t i = threadIdx.x; i < kTkBins; i += kWG) {
+        hc[i] = 0u;
+        hs[i] = 0ull;
     }
-    const uint32_t shift = P->tk_shift[level];
-    const uint32_t pshift = level ? P->tk_shift[level - 1] : shift;
-    const unsigned long long sel = level ? (prefix << (pshift - shift)) | found : (unsigned long long)found;
-    if (lane == 0) {
-        if (level + 1 == P->tk_levels) {
-            P->ub[round] = acc + need * sel;   // shift 0: the bin is the value itself
-        } else {
-            P->tk_state[0] = sel;
-            P->tk_state[1] = need;
-            P->tk_state[2] = acc;
-        }
+    __syncthreads();
+}
+
+// Level `level` > 0 of a prefix's top-k selection (level 0 runs inside
+// k_argmax): the counts whose higher bits equal the prefix selected so far.
+__global__ __launch_bounds__(kWG) void k_topk_hist(const GreedyParams *__restrict__ P, uint32_t level,
+                                                   uint32_t round) {
+    __shared__ uint32_t hc[kTkBins];
+    __shared__ unsigned long long hs[kTkBins];
+    tk_clear(hc, hs);
+    const uint32_t n = P->n, shift = P->tk_shift[level], pshift = P->tk_shift[level - 1];
+    const unsigned long long prefix = P->tk_state[0];
+    for (uint64_t base = (uint64_t)blockIdx.x * kWG; base < n; base += (uint64_t)gridDim.x * kWG) {
+        const uint64_t v = base + threadIdx.x;
+        const uint32_t x = v < n ? P->cnt[v] : 0u;
+        tk_add(hc, hs, x, v < n && (unsigned long long)(x >> pshift) == prefix, shift);
     }
-    for (uint32_t i = lane; i < kTkBins; i += kWave) {
-        P->tk_cnt[i] = 0u;
-        P->tk_sum[i] = 0ull;
-    }
+    tk_flush(P, hc, hs, level, round);
 }
 
 // key = 0 for chosen vertices, else (cnt + 1) << 32 | (~v): the max is the
@@ -247,37 +285,65 @@ __device__ __forceinline__ unsigned long long argmax_key(uint32_t c, uint8_t cho
     return chosen ? 0ull : (((unsigned long long)c + 1ull) << 32) | (unsigned long long)(0xFFFFFFFFu - v);
 }
 
-// Each thread reads counts and chosen flags of 4 consecutive vertices at a
-// time (cnt and chosen are 256-byte aligned); one atomic max per workgroup.
-__global__ __launch_bounds__(kWG) void k_argmax(const GreedyParams *__restrict__ P, uint32_t round) {
+// Round `round`'s argmax (when `argmax` is set; the pass after the last
+// round only takes the histogram) and, with kHist, level 0 of the prefix's
+// top-k histogram over the same counts.  Each thread reads the counts and
+// chosen flags of 4 consecutive vertices at a time (cnt and chosen are
+// 256-byte aligned; the last quad may be partial); one atomic max per
+// workgroup.
+template <bool kHist>
+__global__ __launch_bounds__(kWG) void k_argmax(const GreedyParams *__restrict__ P, uint32_t round,
+                                                uint32_t argmax) {
     __shared__ unsigned long long part[kWavesPerWG];
+    __shared__ uint32_t hc[kHist ? kTkBins : 1];
+    __shared__ unsigned long long hs[kHist ? kTkBins : 1];
+    if (kHist) tk_clear(hc, hs);
     const uint32_t n = P->n;
+    const uint32_t shift = kHist ? P->tk_shift[0] : 0u;
     const uint4 *__restrict__ cnt4 = reinterpret_cast<const uint4 *>(P->cnt);
     const uchar4 *__restrict__ chosen4 = reinterpret_cast<const uchar4 *>(P->chosen);
-    const uint32_t n4 = n / 4, stride = gridDim.x * blockDim.x, t = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t n4 = n / 4, nq = (n + 3u) / 4u, stride = gridDim.x * kWG;
     unsigned long long m = 0;
-    auto take = [&](unsigned long long key) { m = key > m ? key : m; };
-    for (uint32_t q = t; q < n4; q += stride) {
-        const uint4 c = cnt4[q];
-        const uchar4 ch = chosen4[q];
-        const uint32_t v = 4 * q;
-        take(argmax_key(c.x, ch.x, v));
-        take(argmax_key(c.y, ch.y, v + 1));
-        take(argmax_key(c.z, ch.z, v + 2));
-        take(argmax_key(c.w, ch.w, v + 3));
+    // block-uniform trip count: every lane reaches the wave operations of tk_add
+    for (uint32_t q0 = blockIdx.x * kWG; q0 < nq; q0 += stride) {
+        const uint32_t q = q0 + threadIdx.x, v = 4 * q;
+        uint32_t c[4] = {0u, 0u, 0u, 0u};
+        uint8_t ch[4] = {1, 1, 1, 1};
+        bool in[4] = {false, false, false, false};
+        if (q < n4) {
+            const uint4 cq = cnt4[q];
+            const uchar4 hq = chosen4[q];
+            c[0] = cq.x; c[1] = cq.y; c[2] = cq.z; c[3] = cq.w;
+            ch[0] = hq.x; ch[1] = hq.y; ch[2] = hq.z; ch[3] = hq.w;
+            in[0] = in[1] = in[2] = in[3] = true;
+        } else if (q < nq) {
+            for (uint32_t i = 0; i < 4; ++i)
+                if (v + i < n) {
+                    c[i] = P->cnt[v + i];
+                    ch[i] = P->chosen[v + i];
+                    in[i] = true;
+                }
+        }
+#pragma unroll
+        for (uint32_t i = 0; i < 4; ++i) {
+            if (in[i]) {
+                const unsigned long long key = argmax_key(c[i], ch[i], v + i);
+                m = key > m ? key : m;
+            }
+            if (kHist) tk_add(hc, hs, c[i], in[i], shift);
+        }
     }
-    if (t < n - 4 * n4) {
-        const uint32_t v = 4 * n4 + t;
-        take(argmax_key(P->cnt[v], P->chosen[v], v));
+    if (argmax) {
+        m = wave_max(m);
+        if (lane_id() == 0) part[threadIdx.x / kWave] = m;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            for (int w = 1; w < kWavesPerWG; ++w) m = part[w] > m ? part[w] : m;
+            m = part[0] > m ? part[0] : m;
+            atomicMax(P->best + round, m);
+        }
     }
-    m = wave_max(m);
-    if (lane_id() == 0) part[threadIdx.x / kWave] = m;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int w = 1; w < kWavesPerWG; ++w) m = part[w] > m ? part[w] : m;
-        m = part[0] > m ? part[0] : m;
-        atomicMax(P->best + round, m);
-    }
+    if (kHist) tk_flush(P, hc, hs, 0u, round);
 }
 
 // Members of a big set per work chunk in the invalidation.
@@ -486,12 +552,14 @@ int greedy_device(GreedyWorkspace &w, hyperim_graph g, hyperim_pool p, uint64_t 
         hp.tk_shift[1] = levels == 2 ? 0u : bits - 22u;
         hp.tk_shift[2] = 0u;
         const size_t tk_bytes = kTkBins * (sizeof(uint32_t) + sizeof(unsigned long long)) +
-                                3 * sizeof(unsigned long long) + sizeof(unsigned long long) * ((size_t)k + 1);
+                                3 * sizeof(unsigned long long) + sizeof(unsigned long long) * ((size_t)k + 1) +
+                                sizeof(uint32_t);
         HIM_CHECK(w.topk.reserve(tk_bytes, s));
         hp.tk_sum = w.topk.as<unsigned long long>();
         hp.tk_state = hp.tk_sum + kTkBins;
         hp.ub = hp.tk_state + 3;
         hp.tk_cnt = reinterpret_cast<uint32_t *>(hp.ub + k + 1);
+        hp.tk_done = hp.tk_cnt + kTkBins;
         HIM_HIP(hipMemsetAsync(w.topk.ptr, 0, tk_bytes, s));
     }
     hp.k = k;
@@ -510,13 +578,17 @@ int greedy_device(GreedyWorkspace &w, hyperim_graph g, hyperim_pool p, uint64_t 
         hipGraph_t graph = nullptr;
         HIM_HIP(hipStreamBeginCapture(w.capture, hipStreamCaptureModeThreadLocal));
         for (uint32_t i = 0; i <= k; ++i) {
-            // Equation (8)'s term for the first i seeds, then round i
-            for (uint32_t l = 0; l < levels; ++l) {
-                hipLaunchKernelGGL(k_topk_hist, dim3(hist_grid), dim3(kWG), 0, w.capture, P, l);
-                hipLaunchKernelGGL(k_topk_select, dim3(1), dim3(kWave), 0, w.capture, P, l, i);
+            // round i's argmax with level 0 of Equation (8)'s term for the
+            // first i seeds, the term's further levels, then the invalidation
+            // (after the last round, the term alone)
+            if (levels) {
+                hipLaunchKernelGGL(k_argmax<true>, dim3(argmax_grid), dim3(kWG), 0, w.capture, P, i, i < k ? 1u : 0u);
+                for (uint32_t l = 1; l < levels; ++l)
+                    hipLaunchKernelGGL(k_topk_hist, dim3(hist_grid), dim3(kWG), 0, w.capture, P, l, i);
+            } else if (i < k) {
+                hipLaunchKernelGGL(k_argmax<false>, dim3(argmax_grid), dim3(kWG), 0, w.capture, P, i, 1u);
             }
             if (i == k) break;
-            hipLaunchKernelGGL(k_argmax, dim3(argmax_grid), dim3(kWG), 0, w.capture, P, i);
             hipLaunchKernelGGL(k_invalidate, dim3(inval_grid), dim3(kWG), 0, w.capture, P, i);
         }
         HIM_HIP(hipStreamEndCapture(w.capture, &graph));
