@@ -9,9 +9,13 @@ Functions (each cites the passage of the paper it follows in the C source):
   philox(ctr, key)            Philox4x32-10 block (SC'11 definition)
   coin(...)                   the keyed coin of one channel (IC, Section 2.1)
   Graph(hg, model, p)         validated hypergraph + incidence lists + thresholds
+                              (model 0/1: IC with constant p / weighted cascade;
+                              2/3: the linear-threshold model, live-edge form,
+                              with the same thresholds)
   Graph.stratify()            sample-set layers (Section 3.1.1), strata, P
   Graph.root(...)             stratified root of an RR id
-  Graph.rr_set(...)           one RR set (Algorithm 3 skeleton), ascending
+  Graph.rr_set(...)           one RR set (Algorithm 3 skeleton; under LT the
+                              reverse walk of the live-edge form), ascending
   Graph.generate(...)         many RR sets as a CSR (threads over ids)
   greedy(...)                 Algorithm 1
   coverage(...)               Lambda_R(S), Equation (1)

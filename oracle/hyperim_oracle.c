@@ -13,6 +13,11 @@
  *   - independent-cascade channels (Section 2.1, "Cascade models", IC):
  *     every hyperedge he and every ordered pair of distinct members u->v of he
  *     is one channel, live with probability p_v;
+ *   - the linear-threshold model (Section 2.1, "Cascade models", LT) in its
+ *     live-edge form: every vertex v keeps at most one of its channels, each
+ *     with weight W_v (the per-channel probability, capped so that the
+ *     weights into v sum to at most 1), and an RR set is the reverse walk
+ *     along kept channels until it meets a vertex already in the set;
  *   - the sample-set layers of each vertex by co-membership weight w(v,u)
  *     (Section 3.1.1, "Sample set division"), the layer count l_v, and the
  *     statistics alpha, beta of Section 4.1 and theta(l*) of Theorem 2;
@@ -30,7 +35,10 @@
  * from float32 p; layers by descending w; stratum = min(7, 1+floor(log2 l_v))
  * (0 for l_v = 0); roots by systematic sampling over the stratum-sorted vertex
  * list with one 64-bit random offset per ladder block; theta_max in the
- * OPIM-C form; the stop test sigma_l/sigma_u >= 1-1/e-eps.
+ * OPIM-C form; the stop test sigma_l/sigma_u >= 1-1/e-eps.  Under LT each
+ * channel into v weighs min(thr[v], floor(2^32 / c(v))) / 2^32 and one Philox
+ * word per (RR id, v), the coin at hyperedge slot 0xFFFFFFFE and position 0,
+ * picks the kept channel.
  *
  * Build: gcc -O2 -shared -fPIC -pthread -o liboracle.so hyperim_oracle.c -lm
  */
@@ -111,6 +119,7 @@ typedef struct orc_graph {
     uint32_t *v_off, *v_he;        /* vertex -> hyperedges (ascending ids)  */
     uint32_t *thr;                 /* coin threshold of channels into v     */
     uint64_t *c;                   /* sum over he containing v of |he|-1    */
+    int lt;                        /* linear-threshold model (else IC)      */
     int stratified;
     uint32_t *l, *deg, *top, *P;   /* layers, G_w degree, |L_1|, ordering   */
     uint8_t *stratum;
@@ -139,14 +148,15 @@ static uint32_t orc_threshold(float pv)
 
 /* Section 2.1: G = (V, HE) with V(he) given as member lists.  Validates the
  * input, builds the vertex -> hyperedge incidence lists and the per-target
- * thresholds (model 0: constant p; model 1: weighted cascade, p_v = 1/c(v)
- * with c(v) the weighted in-degree of v in G_w). */
+ * thresholds (model 0: IC, constant p; model 1: IC, weighted cascade,
+ * p_v = 1/c(v) with c(v) the weighted in-degree of v in G_w; models 2 and 3:
+ * the linear-threshold model with the thresholds of models 0 and 1). */
 int orc_graph_new(uint32_t n, uint32_t m, const uint32_t *he_off, const uint32_t *he_mem,
                   uint32_t model, float p, orc_graph **out)
 {
     *out = NULL;
-    if (model > 1u) return ORC_EINVAL;
-    if (model == 0u && (isnan(p) || p < 0.0f)) return ORC_EINVAL;
+    if (model > 3u) return ORC_EINVAL;
+    if ((model & 1u) == 0u && (isnan(p) || p < 0.0f)) return ORC_EINVAL;
     if (he_off[0] != 0u) return ORC_EINVAL;
     for (uint32_t e = 0; e < m; ++e)
         if (he_off[e + 1] < he_off[e]) return ORC_EINVAL;
@@ -167,6 +177,7 @@ int orc_graph_new(uint32_t n, uint32_t m, const uint32_t *he_off, const uint32_t
     orc_graph *g = (orc_graph *)calloc(1, sizeof(orc_graph));
     if (!g) return ORC_ENOMEM;
     g->n = n; g->m = m; g->nnz = nnz;
+    g->lt = model >= 2u;
     g->he_off = (uint32_t *)malloc(sizeof(uint32_t) * (m + 1));
     g->he_mem = (uint32_t *)malloc(sizeof(uint32_t) * (nnz ? nnz : 1));
     g->v_off = (uint32_t *)calloc(n + 1, sizeof(uint32_t));
@@ -195,7 +206,7 @@ int orc_graph_new(uint32_t n, uint32_t m, const uint32_t *he_off, const uint32_t
 
     for (uint32_t v = 0; v < n; ++v) {
         float pv;
-        if (model == 0u) pv = p;
+        if ((model & 1u) == 0u) pv = p;
         else pv = g->c[v] ? (float)(1.0 / (double)g->c[v]) : 0.0f;
         g->thr[v] = orc_threshold(pv);
     }
@@ -420,6 +431,74 @@ static uint32_t orc_rr_into(const orc_graph *g, uint64_t seed, uint32_t instance
     return tail;
 }
 
+/* Linear-threshold model, live-edge form (Section 2.1, LT bullet; the
+ * threshold process and this form give every vertex the same activation
+ * probability).  The channels into v are its (hyperedge, member) pairs in
+ * ascending hyperedge order and the hyperedge's stored member order, v
+ * itself skipped: c(v) of them.  Each has weight W / 2^32 with
+ * W = min(thr[v], floor(2^32 / c(v))) (thr = ALWAYS counting as 2^32), so
+ * the weights into v sum to at most 1.  One Philox word per (RR id, v) -- the
+ * coin at hyperedge slot 0xFFFFFFFE, position 0 -- picks channel
+ * floor(x / W) when x < W c(v), and none otherwise.  Returns 1 and the
+ * picked member in *u, or 0. */
+static int orc_lt_pick(const orc_graph *g, uint64_t seed, uint32_t instance, uint32_t pool, uint64_t j,
+                       uint32_t v, uint32_t *u)
+{
+    uint64_t C = g->c[v];
+    if (C == 0) return 0;
+    uint64_t W = g->thr[v] == ORC_ALWAYS ? (1ull << 32) : (uint64_t)g->thr[v];
+    uint64_t cap = (1ull << 32) / C;
+    if (W > cap) W = cap;
+    uint64_t x = orc_coin(seed, instance, pool, j, 0xFFFFFFFEu, v, 0u);
+    if (x >= W * C) return 0;
+    uint64_t k = x / W;
+    for (uint32_t e = g->v_off[v]; e < g->v_off[v + 1]; ++e) {
+        uint32_t he = g->v_he[e];
+        uint32_t base = g->he_off[he];
+        uint32_t size = g->he_off[he + 1] - base;
+        if (k >= (uint64_t)(size - 1u)) {
+            k -= size - 1u;
+            continue;
+        }
+        for (uint32_t pos = 0; pos < size; ++pos) {
+            uint32_t w = g->he_mem[base + pos];
+            if (w == v) continue;
+            if (k == 0) { *u = w; return 1; }
+            --k;
+        }
+    }
+    return 0;   /* not reached: k < c(v) */
+}
+
+/* The LT RR set of root r: r, the member r's kept channel comes from, that
+ * member's, and so on, until no channel is kept or the walk meets a vertex
+ * already in the set; written ascending. */
+static uint32_t orc_lt_into(const orc_graph *g, uint64_t seed, uint32_t instance, uint32_t pool,
+                            uint64_t j, uint32_t root, orc_scratch *s, uint32_t *out)
+{
+    uint32_t len = 0, cur = root, u = 0;
+    s->queue[len++] = root;
+    s->inR[root] = 1;
+    while (orc_lt_pick(g, seed, instance, pool, j, cur, &u) && !s->inR[u]) {
+        s->inR[u] = 1;
+        s->queue[len++] = u;
+        cur = u;
+    }
+    for (uint32_t i = 0; i < len; ++i) {
+        out[i] = s->queue[i];
+        s->inR[s->queue[i]] = 0;
+    }
+    qsort(out, len, sizeof(uint32_t), cmp_u32);
+    return len;
+}
+
+static uint32_t orc_set_into(const orc_graph *g, uint64_t seed, uint32_t instance, uint32_t pool,
+                             uint64_t j, uint32_t root, orc_scratch *s, uint32_t *out)
+{
+    return g->lt ? orc_lt_into(g, seed, instance, pool, j, root, s, out)
+                 : orc_rr_into(g, seed, instance, pool, j, root, s, out);
+}
+
 /* RR set j of pool `pool` into out[] (room for n ids); returns its size. */
 uint32_t orc_rr_set(const orc_graph *g, uint64_t seed, uint32_t instance, uint32_t pool,
                     uint64_t j, uint32_t qlog, uint32_t *out)
@@ -428,7 +507,7 @@ uint32_t orc_rr_set(const orc_graph *g, uint64_t seed, uint32_t instance, uint32
     s.inR = (uint8_t *)calloc(g->n, 1);
     s.queue = (uint32_t *)malloc(sizeof(uint32_t) * g->n);
     uint32_t root = orc_root(g, seed, instance, pool, j, qlog);
-    uint32_t size = orc_rr_into(g, seed, instance, pool, j, root, &s, out);
+    uint32_t size = orc_set_into(g, seed, instance, pool, j, root, &s, out);
     free(s.inR);
     free(s.queue);
     return size;
@@ -441,7 +520,7 @@ uint32_t orc_rr_set_rooted(const orc_graph *g, uint64_t seed, uint32_t instance,
     orc_scratch s;
     s.inR = (uint8_t *)calloc(g->n, 1);
     s.queue = (uint32_t *)malloc(sizeof(uint32_t) * g->n);
-    uint32_t size = orc_rr_into(g, seed, instance, pool, j, root, &s, out);
+    uint32_t size = orc_set_into(g, seed, instance, pool, j, root, &s, out);
     free(s.inR);
     free(s.queue);
     return size;
@@ -473,7 +552,7 @@ static void *orc_gen_worker(void *arg)
         uint64_t k = j - job->id_begin;
         uint32_t root = job->roots ? job->roots[k]
                                    : orc_root(g, job->seed, job->instance, job->pool, j, job->qlog);
-        uint32_t sz = orc_rr_into(g, job->seed, job->instance, job->pool, j, root, &s, tmp);
+        uint32_t sz = orc_set_into(g, job->seed, job->instance, job->pool, j, root, &s, tmp);
         job->buf[k] = (uint32_t *)malloc(sizeof(uint32_t) * (sz ? sz : 1));
         if (!job->buf[k]) { job->err = ORC_ENOMEM; goto done; }
         memcpy(job->buf[k], tmp, sizeof(uint32_t) * sz);
