@@ -29,6 +29,8 @@ __all__ = [
 
 MODEL_CONST = 0   # constant channel probability p
 MODEL_WC = 1      # weighted cascade: p_v = 1 / (weighted clique in-degree of v)
+MODEL_LT_CONST = 2   # linear threshold, channel weight p
+MODEL_LT_WC = 3      # linear threshold, channel weight 1 / (weighted clique in-degree of v)
 
 
 @dataclasses.dataclass
@@ -58,7 +60,7 @@ class Workload:
     m: int
     sizes: tuple            # ("uniform", lo, hi) or ("powerlaw", gamma, lo, hi)
     members: tuple          # ("uniform",) or ("zipf", s)
-    model: int              # MODEL_CONST or MODEL_WC
+    model: int              # MODEL_CONST, MODEL_WC, MODEL_LT_CONST or MODEL_LT_WC
     p: float                # used when model == MODEL_CONST
     k: int
     eps: float
@@ -80,6 +82,14 @@ WORKLOADS = {
                     MODEL_WC, 0.0, 50, 0.1, 1.0, gen_seed=1),
     "large": Workload("large", 1_000_000, 2_000_000, ("powerlaw", 2.2, 2, 200), ("zipf", 1.1),
                       MODEL_CONST, 0.01, 100, 0.1, 1.0, gen_seed=2),
+    # the same hypergraphs under the linear-threshold model (weighted cascade
+    # weights, the standard LT setting)
+    "tiny_lt": Workload("tiny_lt", 1_000, 2_000, ("uniform", 2, 6), ("uniform",),
+                        MODEL_LT_WC, 0.0, 10, 0.5, 1.0, gen_seed=0),
+    "mid_lt": Workload("mid_lt", 100_000, 200_000, ("powerlaw", 2.5, 2, 50), ("zipf", 1.0),
+                       MODEL_LT_WC, 0.0, 50, 0.1, 1.0, gen_seed=1),
+    "large_lt": Workload("large_lt", 1_000_000, 2_000_000, ("powerlaw", 2.2, 2, 200), ("zipf", 1.1),
+                         MODEL_LT_WC, 0.0, 100, 0.1, 1.0, gen_seed=2),
 }
 
 

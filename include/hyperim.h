@@ -43,6 +43,8 @@ extern "C" {
 
 #define HYPERIM_MODEL_CONST 0u  /* every channel into v live with probability p */
 #define HYPERIM_MODEL_WC 1u     /* weighted cascade: p_v = 1 / c(v)             */
+#define HYPERIM_MODEL_LT_CONST 2u /* linear threshold, channel weight p         */
+#define HYPERIM_MODEL_LT_WC 3u  /* linear threshold, channel weight 1 / c(v)    */
 #define HYPERIM_NSTRATA 8u
 
 typedef struct hyperim_graph_s *hyperim_graph;
@@ -57,7 +59,18 @@ typedef struct hyperim_session_s *hyperim_session;
  *   HYPERIM_MODEL_WC:    p_v = (float)(1.0 / c(v)), c(v) = sum over
  *                        hyperedges he containing v of (|he| - 1), the
  *                        weighted in-degree of v in G_w; p is ignored.
- * A channel is live when its coin is below floor(p_v * 2^32). */
+ * A channel is live when its coin is below floor(p_v * 2^32).
+ *
+ * Linear-threshold model (Section 2.1, "Cascade models", LT), in its
+ * live-edge form: HYPERIM_MODEL_LT_CONST and HYPERIM_MODEL_LT_WC take p_v as
+ * the two IC models do; every vertex v keeps at most one of its c(v) channels
+ * (hyperedges of v in ascending order, members in the caller's order, v
+ * skipped), each with weight W_v / 2^32, W_v = min(floor(p_v * 2^32),
+ * floor(2^32 / c(v))) (p_v >= 1 counting as 2^32), so that the weights into v
+ * sum to at most 1.  The Philox word of (RR id, v) at hyperedge slot
+ * 0xFFFFFFFE, position 0, picks channel floor(x / W_v) when x < W_v c(v),
+ * none otherwise; an RR set is the reverse walk from its root along kept
+ * channels until none is kept or the walk meets a vertex already in it. */
 typedef struct {
     uint32_t model;
     float p;

@@ -270,7 +270,7 @@ __global__ void k_thresholds(uint32_t n, uint32_t model, float p, const uint32_t
     uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= n) return;
     float pv;
-    if (model == HYPERIM_MODEL_CONST) {
+    if ((model & 1u) == 0u) {   // constant p (IC or LT)
         pv = p;
     } else {
         unsigned long long cv = c[v];

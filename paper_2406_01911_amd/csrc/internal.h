@@ -163,6 +163,7 @@ struct hyperim_graph_s {
     uint32_t n = 0, m = 0;
     uint64_t nnz = 0;
     hyperim_prob prob{};
+    bool lt() const { return prob.model >= HYPERIM_MODEL_LT_CONST; }   // linear-threshold RR sets
     // weight = d(v) + S(v) incidences read when v is expanded; bytesw = 20 + 12 d(v) + 4 S(v)
     // algorithmic bytes of v as an RR-set member (d = hyperedges of v, S = their total size);
     // phiw = sum over v's hyperedges of ceil(|he| / 4), the Philox blocks of v's expansion

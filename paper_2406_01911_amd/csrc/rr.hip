@@ -690,6 +690,172 @@ __global__ __launch_bounds__(kWG) void k_rr_light(RRArgs a) {
     if (lane == 0 && px) atomicAdd(&a.ctr[kPhiloxA], (unsigned long long)px);
 }
 
+// ---- linear-threshold model ------------------------------------------------
+// RR sets of the live-edge form of LT (Section 2.1, LT bullet): every vertex v
+// keeps at most one of its c(v) channels -- (hyperedge, member) pairs in
+// ascending hyperedge order and stored member order, v skipped -- each with
+// weight W / 2^32, W = min(thr[v], floor(2^32 / c(v))) (thr = always-live
+// counting as 2^32), so the weights into v sum to at most 1.  The Philox word
+// at hyperedge slot kLtSlot, position 0, of (RR id, v) picks channel
+// floor(x / W) when x < W c(v), none otherwise.  An RR set is the reverse
+// walk from its root along kept channels until no channel is kept or the
+// walk meets a vertex already in the set.
+//
+// One wave per set (persistent over the launch group's ids, like phase A):
+// the lanes sum c(v) and locate the picked channel over v's incidences 64 at
+// a time and find v's position in the hyperedge; lane 0 keeps the walk's
+// list and visited bitmap (a slot of the phase-A workspace), so the
+// membership test reads what the same lane wrote.  The set leaves ascending
+// through the phase-A output path.
+constexpr uint32_t kLtSlot = 0xFFFFFFFEu;
+
+template <bool kLdsBitmap>
+__global__ __launch_bounds__(kWG) void k_lt_walk(RRArgs a) {
+    __shared__ uint32_t sort_s[kWavesPerWG][kSortMax];
+    __shared__ uint32_t lbm[kLdsBitmap ? kWavesPerWG : 1][kLdsBitmap ? kLdsBitmapWords : 1];
+    const uint32_t lane = lane_id(), wv = uni(threadIdx.x / kWave);
+    const uint32_t slot = blockIdx.x * kWavesPerWG + wv;
+    uint32_t *sortb = sort_s[wv];
+    uint32_t *list = a.lists + (uint64_t)slot * a.slot_n;
+    uint32_t *bm;
+    if constexpr (kLdsBitmap) {
+        bm = lbm[wv];
+        for (uint32_t i = lane; i < kLdsBitmapWords; i += kWave) bm[i] = 0u;
+    } else {
+        bm = a.bitmaps + (uint64_t)slot * a.slot_words;
+    }
+    wave_sync();
+    uint64_t bytes_done = 0, px = 0;
+    for (;;) {
+        unsigned long long idx = 0;
+        if (lane == 0) idx = atomicAdd(&a.ctr[kWork], 1ull);
+        idx = uni64(wave_bcast64(idx, 0));
+        if (idx >= a.count) break;
+        const uint32_t task = task_of(a, idx);
+        const SetRef S = set_ref(a, task, idx);
+        const GraphView &G = S.G;
+        const uint32_t root = rr_root(G, a.qlog, S.j, S.pool, S.key);
+        if (lane == 0) {
+            list[0] = root;
+            bm[root >> 5] |= 1u << (root & 31);
+        }
+        uint32_t size = 1, cur = root;
+        for (;;) {
+            const uint32_t e0 = uni(G.v_off[cur]), e1 = uni(G.v_off[cur + 1]);
+            uint64_t c = 0;
+            for (uint32_t e = e0 + lane; e < e1; e += kWave) c += (uint32_t)(G.v_hbs[e] >> 32) - 1u;
+            const uint64_t C = uni64(wave_sum(c));
+            bytes_done += 20ull + 8ull * (e1 - e0);
+            if (C == 0) break;
+            const uint32_t thr = uni(G.thr[cur]);
+            const uint64_t cap = (1ull << 32) / C;
+            const uint64_t W = min(thr == kAlways ? (1ull << 32) : (uint64_t)thr, cap);
+            const uint32_t x = uni(philox4x32_10(coin_counter(S.j, kLtSlot, cur, S.pool, 0u), S.key).x);
+            ++px;
+            if ((uint64_t)x >= W * C) break;   // W = 0 included: no channel is kept
+            uint64_t k = (uint64_t)x / W;
+            // the incidence holding channel k, and k's rank among its channels
+            uint32_t hb = 0, hs = 0;
+            for (uint32_t e = e0; e < e1; e += kWave) {
+                const uint32_t ei = e + lane;
+                unsigned long long bs = 0;
+                uint64_t cnt = 0;
+                if (ei < e1) {
+                    bs = G.v_hbs[ei];
+                    cnt = (uint32_t)(bs >> 32) - 1u;
+                }
+                const uint64_t incl = wave_incl_scan(cnt);
+                const uint64_t tot = uni64(wave_bcast64(incl, kWave - 1));
+                if (k < tot) {
+                    const int l = __ffsll((unsigned long long)__ballot(incl > k)) - 1;
+                    const unsigned long long bl = uni64(wave_bcast64(bs, l));
+                    k -= uni64(wave_bcast64(incl - cnt, l));
+                    hb = (uint32_t)bl;
+                    hs = (uint32_t)(bl >> 32);
+                    break;
+                }
+                k -= tot;
+            }
+            // member k of the hyperedge with cur skipped
+            uint32_t pc = hs;
+            for (uint32_t p0 = 0; p0 < hs; p0 += kWave) {
+                const uint64_t hit = __ballot(p0 + lane < hs && G.he_mem[hb + p0 + lane] == cur);
+                if (hit) {
+                    pc = p0 + (uint32_t)__ffsll((unsigned long long)hit) - 1u;
+                    break;
+                }
+            }
+            const uint32_t u = uni(G.he_mem[hb + ((uint32_t)k < pc ? (uint32_t)k : (uint32_t)k + 1u)]);
+            bytes_done += 4ull * hs + 8ull;
+            uint32_t seen = 0;
+            if (lane == 0) {
+                const uint32_t bit = 1u << (u & 31);
+                seen = (bm_load<kLdsBitmap>(bm, u >> 5) & bit) != 0u;
+                if (!seen) {
+                    bm[u >> 5] |= bit;
+                    list[size] = u;
+                }
+            }
+            if (wave_bcast(seen, 0)) break;
+            ++size;
+            cur = u;
+        }
+
+        // ---- output: ascending members into the stage, as in phase A -----
+        unsigned long long off = 0;
+        if (lane == 0) off = atomicAdd(&a.ctr[kBump], (unsigned long long)size);
+        off = wave_bcast64(off, 0);
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // lane 0's list and bitmap stores
+        if (off + size <= a.stage_cap) {
+            if (size <= kSortMax) {
+                uint32_t P2 = kWave;
+                while (P2 < size) P2 <<= 1;
+                for (uint32_t i = lane; i < P2; i += kWave) sortb[i] = i < size ? list[i] : 0xFFFFFFFFu;
+                wave_sync();
+                for (uint32_t kk = 2; kk <= P2; kk <<= 1) {
+                    for (uint32_t jj = kk >> 1; jj > 0; jj >>= 1) {
+                        for (uint32_t i = lane; i < P2; i += kWave) {
+                            const uint32_t xx = i ^ jj;
+                            if (xx > i) {
+                                const uint32_t pv = sortb[i], qv = sortb[xx];
+                                if ((pv > qv) == ((i & kk) == 0)) {
+                                    sortb[i] = qv;
+                                    sortb[xx] = pv;
+                                }
+                            }
+                        }
+                        wave_sync();
+                    }
+                }
+                for (uint32_t i = lane; i < size; i += kWave) a.stage[off + i] = sortb[i];
+                wave_sync();
+            } else {
+                uint32_t written = 0;
+                for (uint32_t w0 = 0; w0 < G.bm_words; w0 += kWave) {
+                    const uint32_t wi = w0 + lane;
+                    uint32_t word = wi < G.bm_words ? bm_load<kLdsBitmap>(bm, wi) : 0u;
+                    const uint32_t cnt = (uint32_t)__popc(word);
+                    const uint32_t incl = wave_incl_scan(cnt);
+                    uint64_t pos = off + written + incl - cnt;
+                    while (word) {
+                        const uint32_t bit = (uint32_t)__ffs(word) - 1u;
+                        word &= word - 1u;
+                        if (pos < off + size) a.stage[pos] = wi * 32u + bit;
+                        ++pos;
+                    }
+                    written += wave_bcast(incl, kWave - 1);
+                }
+            }
+        }
+        if (lane == 0) record_set(a, idx, off, size, root);
+        for (uint32_t i = lane; i < size; i += kWave) bm[list[i] >> 5] = 0u;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        wave_sync();
+    }
+    if (lane == 0 && bytes_done) atomicAdd(&a.ctr[kBytesA], bytes_done);
+    if (lane == 0 && px) atomicAdd(&a.ctr[kPhiloxA], (unsigned long long)px);
+}
+
 // ---- phase B ---------------------------------------------------------------
 // Item: x = deferred set d | heavy << 31; light: y = first queue index,
 // z = count (<= 64); heavy: y = vertex, z = first incidence, w = end.
@@ -2059,6 +2225,31 @@ int run_launch(RRWorkspace &ws, RRStats &st, const hyperim_tuning &tune, RRArgs 
     return HYPERIM_OK;
 }
 
+// One launch group of linear-threshold sets: one walk per set (k_lt_walk).
+// Ends like run_launch: closing counter block in ws.host + kHostFinal,
+// `tail` queued behind it, stream drained.
+template <class Tail>
+int run_lt_launch(RRWorkspace &ws, RRStats &st, const RRArgs &a, const LaunchShape &shape, uint32_t grid,
+                  hipStream_t s, Tail &&tail) {
+    unsigned long long *h = ws.host;
+    HIM_CHECK(event_pair(ws));
+    if (shape.lds)
+        hipExtLaunchKernelGGL(k_lt_walk<true>, dim3(grid), dim3(kWG), 0, s, ws.events[0], ws.events[1], 0u, a);
+    else
+        hipExtLaunchKernelGGL(k_lt_walk<false>, dim3(grid), dim3(kWG), 0, s, ws.events[0], ws.events[1], 0u, a);
+    HIM_HIP(hipGetLastError());
+    st.launches += 1;
+    HIM_HIP(hipMemcpyAsync(h + kHostFinal, a.ctr, sizeof(unsigned long long) * kNumCtr, hipMemcpyDeviceToHost, s));
+    const int rc = tail();
+    HIM_HIP(hipStreamSynchronize(s));
+    HIM_CHECK(rc);
+    float ms = 0.f;
+    HIM_HIP(hipEventElapsedTime(&ms, ws.events[0], ws.events[1]));
+    st.ms_bfs += ms;
+    st.ms_light += ms;
+    return HYPERIM_OK;
+}
+
 // Bytes of the bundled-mode state per bundle for a graph of n vertices:
 // seen and nxt masks, frontier and next-level lists, output counts, batch marks.
 uint64_t ms_bytes_per_bundle(uint32_t n) {
@@ -2359,7 +2550,7 @@ int rr_generate_into(RRWorkspace &ws, RRStats &st, const std::vector<RRTask> &ta
     // bundled mode for graphs whose sets are large on average (form 0 only;
     // the plain form keeps one traversal per set)
     auto bundled = [&](const RRTask &t) {
-        return form == 0 && t.g->rr_members >= 0.0 && t.g->rr_members >= (double)tune.ms_min;
+        return form == 0 && !t.g->lt() && t.g->rr_members >= 0.0 && t.g->rr_members >= (double)tune.ms_min;
     };
     const double stage_words = (double)stage_budget / 4.0;
     auto per_set = [](hyperim_graph g) { return g->rr_members >= 0.0 ? 1.3 * g->rr_members + 1.0 : (double)g->n; };
@@ -2462,7 +2653,8 @@ int rr_generate_into(RRWorkspace &ws, RRStats &st, const std::vector<RRTask> &ta
             pos += take;
             if (take < rest || pos == count || form == 1 || pos - lo >= def_chunk) break;
             ++ti;   // form 0: the group continues with the next task ...
-            if (bundled(tasks[ti])) break;   // ... unless that one runs bundled
+            // ... unless that one runs bundled or has the other cascade model
+            if (bundled(tasks[ti]) || tasks[ti].g->lt() != tasks[ti - 1].g->lt()) break;
         }
         const uint64_t hi = pos;
         // descriptors of the group's task slices
@@ -2526,6 +2718,8 @@ int rr_generate_into(RRWorkspace &ws, RRStats &st, const std::vector<RRTask> &ta
             if (ms)
                 HIM_CHECK(run_ms_launch(ws, run, tune, a, shape, tasks[slices[0].task].g, tdesc[0], trace,
                                         time_kernels, graphs, s, scans));
+            else if (tasks[slices[0].task].g->lt())
+                HIM_CHECK(run_lt_launch(ws, run, a, shape, grid, s, scans));
             else
                 HIM_CHECK(run_launch(ws, run, tune, a, shape, grid, grid_b, expect_defer, trace, time_kernels,
                                      graphs, s, scans));

@@ -1,0 +1,146 @@
+"""GPU parity of the linear-threshold model (Section 2.1, LT bullet, in its
+live-edge form): the walk kernel through the C ABI against the oracle, bit
+for bit -- roots, RR sets (ascending members), and the whole HyperIM_BRR
+query (seeds, gains, theta, rounds, Lambda1, Lambda2, Lambda_u).  Cases cover
+the LDS and global visited bitmaps (|V| above 32768), capped weights, p = 0
+and p = 1, isolated vertices, high RR ids, the plain form, and a generation
+call that mixes LT and IC graphs."""
+import sys
+
+import numpy as np
+import pytest
+
+import hypergen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+LT_CONST, LT_WC = 2, 3
+
+
+def _flush(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def hy():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2406_01911_amd as hy
+    hy.load_library()
+    return hy
+
+
+def _path(n):
+    return hypergen.from_lists(n, [[i, i + 1] for i in range(n - 1)])
+
+
+CASES = {
+    "tiny_lt": lambda: (hypergen.workload("tiny_lt").build(), LT_WC, 0.0),
+    "small_const_015": lambda: (hypergen.tiny_hypergraph(31, 60, 80, 2, 6), LT_CONST, 0.15),
+    "small_const_capped": lambda: (hypergen.tiny_hypergraph(32, 60, 80, 2, 6), LT_CONST, 0.6),
+    "singletons_wc": lambda: (hypergen.tiny_hypergraph(5, 300, 500, 1, 8, allow_singletons=True), LT_WC, 0.0),
+    "p_one_star": lambda: (hypergen.from_lists(7, [[0, i] for i in range(1, 6)] + [[6]]), LT_CONST, 1.0),
+    "p_zero": lambda: (hypergen.tiny_hypergraph(4, 50, 40), LT_CONST, 0.0),
+    "path_40000": lambda: (_path(40000), LT_WC, 0.0),
+}
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_lt_rr_sets_bit_exact(hy, case):
+    _flush(f"[gpu] LT rr sets case={case}")
+    hg, model, p = CASES[case]()
+    g = hy.build_graph(hg.n, hg.he_off, hg.he_mem, model, p)
+    o = oracle.Graph(hg, model, p)
+    a, b = g.read(strata=False), o.arrays()
+    for k in ("v_off", "v_he", "thr", "c"):
+        assert np.array_equal(a[k], b[k]), k
+    g.stratify()
+    o.stratify()
+    for pool_tag, (lo, hi) in [(0, (0, 1500)), (1, (200, 700)), (0, ((1 << 33) - 100, (1 << 33) + 100))]:
+        pool = hy.Pool(g)
+        hy.generate_rr(g, 7, 3, pool_tag, lo, hi, pool)
+        off, mem, roots = pool.read()
+        roff, rmem, rroots = o.generate(7, 3, pool_tag, lo, hi)
+        assert np.array_equal(roots, rroots)
+        assert np.array_equal(off, roff)
+        assert np.array_equal(mem, rmem)
+    if case == "path_40000":
+        assert np.diff(off).max() > 2   # walks go on past their first step (global bitmaps: |V| > 32768)
+
+
+def test_lt_mid_sets_sampled_and_select_seeds_match_oracle(hy):
+    """mid_lt (|V| = 1e5, global visited bitmaps): a generation call's sets
+    and the whole query, in the persistent and the plain form, for both upper
+    bounds."""
+    _flush("[gpu] LT mid")
+    w = hypergen.workload("mid_lt")
+    hg = w.build()
+    g = hy.build_graph(hg.n, hg.he_off, hg.he_mem, w.model, w.p)
+    o = oracle.Graph(hg, w.model, w.p)
+    g.stratify()
+    o.stratify()
+    pool = hy.Pool(g)
+    hy.generate_rr(g, w.philox_seed, 0, 0, 0, 4096, pool)
+    off, mem, roots = pool.read()
+    roff, rmem, rroots = o.generate(w.philox_seed, 0, 0, 0, 4096)
+    assert np.array_equal(roots, rroots) and np.array_equal(off, roff) and np.array_equal(mem, rmem)
+    for bound in (0, 1):
+        ro = o.select_seeds(w.k, w.eps, w.ell, seed=w.philox_seed, bound=bound)
+        for form in (0, 1):
+            r = hy.select_seeds(g, w.k, w.eps, w.ell, seed=w.philox_seed, form=form, bound=bound)
+            for key in ("rounds", "theta", "lambda1", "lambda2", "entries1", "entries2", "i_max", "lambda_u"):
+                assert r[key] == ro[key], (bound, form, key, r[key], ro[key])
+            assert np.array_equal(r["seeds"], ro["seeds"]) and np.array_equal(r["gains"], ro["gains"])
+            assert r["sigma_l"] == pytest.approx(ro["sigma_l"], rel=1e-12)
+            assert r["sigma_u"] == pytest.approx(ro["sigma_u"], rel=1e-12)
+
+
+def test_lt_tiny_select_seeds_matches_oracle(hy):
+    _flush("[gpu] LT tiny select")
+    w = hypergen.workload("tiny_lt")
+    hg = w.build()
+    g = hy.build_graph(hg.n, hg.he_off, hg.he_mem, w.model, w.p)
+    o = oracle.Graph(hg, w.model, w.p)
+    g.stratify()
+    o.stratify()
+    r = hy.select_seeds(g, w.k, w.eps, w.ell)
+    ro = o.select_seeds(w.k, w.eps, w.ell)
+    for key in ("rounds", "theta", "lambda1", "lambda2", "entries1", "entries2", "lambda_u"):
+        assert r[key] == ro[key], key
+    assert np.array_equal(r["seeds"], ro["seeds"]) and np.array_equal(r["gains"], ro["gains"])
+
+
+def test_lt_and_ic_graphs_in_one_generation_call(hy):
+    """Tasks of an LT graph and an IC graph in one call run in separate launch
+    groups; every pool equals the oracle's."""
+    _flush("[gpu] LT + IC in one call")
+    hg = hypergen.tiny_hypergraph(41, 2000, 3000, 2, 6)
+    graphs = []
+    for model, p in ((LT_WC, 0.0), (0, 0.1), (LT_CONST, 0.05)):
+        g = hy.build_graph(hg.n, hg.he_off, hg.he_mem, model, p)
+        g.stratify()
+        o = oracle.Graph(hg, model, p)
+        o.stratify()
+        graphs.append((g, o))
+    tasks, pools = [], []
+    for i, (g, o) in enumerate(graphs):
+        for tag in (0, 1):
+            pl = hy.Pool(g)
+            pools.append((pl, o, tag, i))
+            tasks.append(dict(graph=g, pool=pl, seed=3, instance=i, pool_tag=tag, id_begin=0, id_end=1000))
+    hy.generate_rr_batch(tasks)
+    for pl, o, tag, i in pools:
+        off, mem, roots = pl.read()
+        roff, rmem, rroots = o.generate(3, i, tag, 0, 1000)
+        assert np.array_equal(roots, rroots) and np.array_equal(off, roff) and np.array_equal(mem, rmem), (i, tag)
+
+
+def test_lt_graph_rejects_unknown_model(hy):
+    hg = hypergen.from_lists(3, [[0, 1]])
+    with pytest.raises(hy.HyperIMError):
+        hy.build_graph(hg.n, hg.he_off, hg.he_mem, 4, 0.1)
+    with pytest.raises(hy.HyperIMError):
+        hy.build_graph(hg.n, hg.he_off, hg.he_mem, LT_CONST, float("nan"))
