@@ -191,14 +191,14 @@ SharedBytes shared_bytes() {
 size_t graph_bytes(hyperim_graph g) {
     size_t b = 0;
     for (const DevBuf *x : {&g->he_off, &g->he_mem, &g->v_off, &g->v_he, &g->thr, &g->c, &g->weight, &g->bytesw,
-                            &g->phiw, &g->v_hbs, &g->l, &g->deg, &g->top, &g->stratum, &g->P})
+                            &g->phiw, &g->v_hbs, &g->chan, &g->l, &g->deg, &g->top, &g->stratum, &g->P})
         b += x->bytes;
     return b;
 }
 
 void release_graph(hyperim_graph g) {
     for (DevBuf *b : {&g->he_off, &g->he_mem, &g->v_off, &g->v_he, &g->thr, &g->c, &g->weight, &g->bytesw,
-                      &g->phiw, &g->v_hbs, &g->l, &g->deg, &g->top, &g->stratum, &g->P})
+                      &g->phiw, &g->v_hbs, &g->chan, &g->l, &g->deg, &g->top, &g->stratum, &g->P})
         b->release();
 }
 

@@ -318,6 +318,13 @@ __global__ void k_incidence_spans(uint64_t nnz, const uint32_t *__restrict__ v_h
     }
 }
 
+// Channels of each incidence (v, he) under the linear-threshold model:
+// |he| - 1 (the members of he other than v).
+__global__ void k_channel_counts(uint64_t nnz, const uint2 *__restrict__ v_hbs, uint32_t *__restrict__ cnt) {
+    for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += (uint64_t)gridDim.x * blockDim.x)
+        cnt[e] = v_hbs[e].y - 1u;
+}
+
 uint32_t grid_for(uint64_t items, uint32_t block = kBlock, uint32_t cap = 65535u * 8u) {
     uint64_t g = div_up(items, block);
     if (g == 0) g = 1;
@@ -329,6 +336,7 @@ uint32_t grid_for(uint64_t items, uint32_t block = kBlock, uint32_t cap = 65535u
 int graph_build_device(hyperim_graph g, PrepWorkspace &w, hipStream_t s) {
     const uint32_t n = g->n, m = g->m;
     const uint64_t nnz = g->nnz;
+    DevBuf chan_cnt, chan_tmp;   // linear-threshold channel prefix (freed after the final wait)
     DevBuf &flag_b = w.flag, &cnt_b = w.cnt, &off64_b = w.off64, &tmp_b = w.tmp;
     HIM_CHECK(flag_b.reserve(4 * sizeof(uint32_t), s));
     uint32_t *flag = flag_b.as<uint32_t>();
@@ -397,6 +405,16 @@ int graph_build_device(hyperim_graph g, PrepWorkspace &w, hipStream_t s) {
     if (nnz)
         hipLaunchKernelGGL(k_incidence_spans, dim3(grid_for(nnz, kBlock, 8192)), dim3(kBlock), 0, s, nnz,
                            g->v_he.as<uint32_t>(), g->he_off.as<uint32_t>(), g->v_hbs.as<uint2>());
+    if (g->lt()) {
+        // exclusive prefix over all incidences of their channel counts: the
+        // channels into v are chan[v_off[v]] .. chan[v_off[v + 1]]
+        HIM_CHECK(g->chan.reserve(sizeof(uint64_t) * (nnz + 1), s));
+        HIM_CHECK(chan_cnt.reserve(sizeof(uint32_t) * std::max<uint64_t>(nnz, 1), s));
+        if (nnz)
+            hipLaunchKernelGGL(k_channel_counts, dim3(grid_for(nnz, kBlock, 8192)), dim3(kBlock), 0, s, nnz,
+                               g->v_hbs.as<uint2>(), chan_cnt.as<uint32_t>());
+        HIM_CHECK(scan_u32_to_u64(chan_cnt.as<uint32_t>(), g->chan.as<uint64_t>(), nnz, 0, chan_tmp, s));
+    }
     if (n) {
         hipLaunchKernelGGL(k_thresholds, dim3(grid_for(n)), dim3(kBlock), 0, s, n, g->prob.model, g->prob.p,
                            g->v_off.as<uint32_t>(), g->c.as<unsigned long long>(), g->thr.as<uint32_t>(),

@@ -168,7 +168,9 @@ struct hyperim_graph_s {
     // algorithmic bytes of v as an RR-set member (d = hyperedges of v, S = their total size);
     // phiw = sum over v's hyperedges of ceil(|he| / 4), the Philox blocks of v's expansion
     // v_hbs[e] = (he_off[v_he[e]], size of that hyperedge), uint2 per incidence
-    hyperim::DevBuf he_off, he_mem, v_off, v_he, thr, c, weight, bytesw, phiw, v_hbs;
+    // chan (linear-threshold graphs only): exclusive prefix over v_he of the
+    // incidences' channel counts |he| - 1, nnz + 1 entries
+    hyperim::DevBuf he_off, he_mem, v_off, v_he, thr, c, weight, bytesw, phiw, v_hbs, chan;
     bool stratified = false;
     hyperim::DevBuf l, deg, top, stratum, P;
     hyperim_strata_info info{};

@@ -89,6 +89,9 @@ struct GraphDesc {
     const uint32_t *he_off, *he_mem, *v_off, *v_he, *thr, *P;
     const unsigned long long *v_hbs;   // low word: first position, high word: size
     uint32_t n, bm_words;
+    // linear-threshold graphs: channels of the incidences before each one
+    // (exclusive prefix of |he| - 1 over v_he, nnz + 1 entries); else null
+    const unsigned long long *chan;
 };
 
 // The same arrays as global-memory pointers: descriptors are read from device
@@ -701,12 +704,14 @@ __global__ __launch_bounds__(kWG) void k_rr_light(RRArgs a) {
 // walk from its root along kept channels until no channel is kept or the
 // walk meets a vertex already in the set.
 //
-// One wave per set (persistent over the launch group's ids, like phase A):
-// the lanes sum c(v) and locate the picked channel over v's incidences 64 at
-// a time and find v's position in the hyperedge; lane 0 keeps the walk's
-// list and visited bitmap (a slot of the phase-A workspace), so the
-// membership test reads what the same lane wrote.  The set leaves ascending
-// through the phase-A output path.
+// One wave per set (persistent over the launch group's ids, like phase A).
+// c(v) and the incidence holding the picked channel come from the graph's
+// channel prefix over v's incidences (a 64-way search: each round the lanes
+// probe 64 evenly spaced incidences of the remaining range); the lanes then
+// find v's position in that hyperedge.  Lane 0 keeps the walk's list and
+// visited bitmap (a slot of the phase-A workspace), so the membership test
+// reads what the same lane wrote.  The set leaves ascending through the
+// phase-A output path.
 constexpr uint32_t kLtSlot = 0xFFFFFFFEu;
 
 template <bool kLdsBitmap>
@@ -735,6 +740,8 @@ __global__ __launch_bounds__(kWG) void k_lt_walk(RRArgs a) {
         const SetRef S = set_ref(a, task, idx);
         const GraphView &G = S.G;
         const uint32_t root = rr_root(G, a.qlog, S.j, S.pool, S.key);
+        const HIM_GLOBAL unsigned long long *chan =
+            uni_ptr((const HIM_GLOBAL unsigned long long *)a.graphs[uni(a.tasks[task].graph)].chan);
         if (lane == 0) {
             list[0] = root;
             bm[root >> 5] |= 1u << (root & 31);
@@ -742,10 +749,9 @@ __global__ __launch_bounds__(kWG) void k_lt_walk(RRArgs a) {
         uint32_t size = 1, cur = root;
         for (;;) {
             const uint32_t e0 = uni(G.v_off[cur]), e1 = uni(G.v_off[cur + 1]);
-            uint64_t c = 0;
-            for (uint32_t e = e0 + lane; e < e1; e += kWave) c += (uint32_t)(G.v_hbs[e] >> 32) - 1u;
-            const uint64_t C = uni64(wave_sum(c));
-            bytes_done += 20ull + 8ull * (e1 - e0);
+            const uint64_t base = uni64(chan[e0]);
+            const uint64_t C = uni64(chan[e1]) - base;   // c(v)
+            bytes_done += 36ull;
             if (C == 0) break;
             const uint32_t thr = uni(G.thr[cur]);
             const uint64_t cap = (1ull << 32) / C;
@@ -753,29 +759,25 @@ __global__ __launch_bounds__(kWG) void k_lt_walk(RRArgs a) {
             const uint32_t x = uni(philox4x32_10(coin_counter(S.j, kLtSlot, cur, S.pool, 0u), S.key).x);
             ++px;
             if ((uint64_t)x >= W * C) break;   // W = 0 included: no channel is kept
-            uint64_t k = (uint64_t)x / W;
-            // the incidence holding channel k, and k's rank among its channels
-            uint32_t hb = 0, hs = 0;
-            for (uint32_t e = e0; e < e1; e += kWave) {
-                const uint32_t ei = e + lane;
-                unsigned long long bs = 0;
-                uint64_t cnt = 0;
-                if (ei < e1) {
-                    bs = G.v_hbs[ei];
-                    cnt = (uint32_t)(bs >> 32) - 1u;
-                }
-                const uint64_t incl = wave_incl_scan(cnt);
-                const uint64_t tot = uni64(wave_bcast64(incl, kWave - 1));
-                if (k < tot) {
-                    const int l = __ffsll((unsigned long long)__ballot(incl > k)) - 1;
-                    const unsigned long long bl = uni64(wave_bcast64(bs, l));
-                    k -= uni64(wave_bcast64(incl - cnt, l));
-                    hb = (uint32_t)bl;
-                    hs = (uint32_t)(bl >> 32);
-                    break;
-                }
-                k -= tot;
+            // the incidence e holding channel k: the last one in [e0, e1)
+            // with chan[e] <= base + k (chan[e0] = base qualifies; the next
+            // prefix exceeds it, so e has at least one channel)
+            const uint64_t t = base + (uint64_t)x / W;
+            uint32_t lo = e0, hi = e1;   // the answer lies in [lo, hi)
+            while (hi - lo > (uint32_t)kWave) {
+                const uint32_t step = (hi - lo + kWave - 1) / kWave;
+                const uint32_t probe = lo + lane * step;
+                const uint64_t ok = __ballot(probe < hi && chan[probe] <= t);
+                const uint32_t l = 63u - (uint32_t)__clzll((long long)ok);   // lane 0 always qualifies
+                lo += l * step;
+                hi = min(hi, lo + step);
+                bytes_done += 8ull;
             }
+            const uint64_t ok = __ballot(lo + lane < hi && chan[lo + lane] <= t);
+            const uint32_t e = lo + 63u - (uint32_t)__clzll((long long)ok);
+            const unsigned long long bl = uni64(G.v_hbs[e]);
+            const uint64_t k = t - uni64(chan[e]);   // rank among e's channels
+            const uint32_t hb = (uint32_t)bl, hs = (uint32_t)(bl >> 32);
             // member k of the hyperedge with cur skipped
             uint32_t pc = hs;
             for (uint32_t p0 = 0; p0 < hs; p0 += kWave) {
@@ -786,7 +788,7 @@ __global__ __launch_bounds__(kWG) void k_lt_walk(RRArgs a) {
                 }
             }
             const uint32_t u = uni(G.he_mem[hb + ((uint32_t)k < pc ? (uint32_t)k : (uint32_t)k + 1u)]);
-            bytes_done += 4ull * hs + 8ull;
+            bytes_done += 4ull * hs + 24ull;
             uint32_t seen = 0;
             if (lane == 0) {
                 const uint32_t bit = 1u << (u & 31);
@@ -2514,7 +2516,8 @@ int rr_generate_into(RRWorkspace &ws, RRStats &st, const std::vector<RRTask> &ta
         gdesc.push_back(GraphDesc{g->he_off.as<uint32_t>(), g->he_mem.as<uint32_t>(), g->v_off.as<uint32_t>(),
                                   g->v_he.as<uint32_t>(), g->thr.as<uint32_t>(), g->P.as<uint32_t>(),
                                   g->v_hbs.as<unsigned long long>(), g->n,
-                                  (uint32_t)(((uint64_t)g->n + 31u) / 32u)});
+                                  (uint32_t)(((uint64_t)g->n + 31u) / 32u),
+                                  g->lt() ? g->chan.as<unsigned long long>() : nullptr});
         n_max = std::max(n_max, g->n);
     }
     uint64_t count = 0;
@@ -2549,8 +2552,12 @@ int rr_generate_into(RRWorkspace &ws, RRStats &st, const std::vector<RRTask> &ta
     constexpr uint64_t kMsBudget = 8ull << 30;   // bytes of bundled-mode state per launch group
     // bundled mode for graphs whose sets are large on average (form 0 only;
     // the plain form keeps one traversal per set)
+    // (a graph not seen yet starts bundled when its tuning enables the mode:
+    // the first group's sets teach the estimate either way, and a graph tuned
+    // for bundled mode has large sets, which the per-set mode grows slowly)
     auto bundled = [&](const RRTask &t) {
-        return form == 0 && !t.g->lt() && t.g->rr_members >= 0.0 && t.g->rr_members >= (double)tune.ms_min;
+        return form == 0 && !t.g->lt() && tune.ms_min != 0xFFFFFFFFu &&
+               (t.g->rr_members < 0.0 || t.g->rr_members >= (double)tune.ms_min);
     };
     const double stage_words = (double)stage_budget / 4.0;
     auto per_set = [](hyperim_graph g) { return g->rr_members >= 0.0 ? 1.3 * g->rr_members + 1.0 : (double)g->n; };

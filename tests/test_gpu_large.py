@@ -84,11 +84,11 @@ def test_large_sampled_rr_sets_exact(large):
 def test_large_bundled_mode_under_stored_tuning_exact(large):
     """The launch configuration the benchmark times on this workload: the
     stored tuning, whose bundled mode grows the sets of a graph that averages
-    at least ms_min members per set in bundles of 64.  Both pools' ids
-    [0, 6144) in one generation call on a fresh graph handle: R1's first 2048
-    ids form the learning group (per-set mode), every later id of R1 and all
-    of R2 run bundled.  Sampled ids of both modes, including the largest sets,
-    equal the oracle's sets and roots."""
+    at least ms_min members per set in bundles of 64 (a graph not seen yet
+    starts bundled and learns its members per set from that first group).
+    Both pools' ids [0, 6144) in one generation call on a fresh graph handle.
+    Sampled ids, including the largest sets, equal the oracle's sets and
+    roots."""
     hy, w, hg, g, o = large
     from paper_2406_01911_amd import autotune
     if not o.stratified:
@@ -106,8 +106,7 @@ def test_large_bundled_mode_under_stored_tuning_exact(large):
     data = {tag: pools[tag].read() for tag in (0, 1)}
     off0 = data[0][0]
     learned = off0[2048] / 2048.0
-    # the library switches a graph to bundled mode once its sets average at
-    # least ms_min members; the learning group's average is what it learns
+    # the sets are large: bundled mode stays on after the first group
     assert learned >= tuning["ms_min"], learned
     rng = np.random.default_rng(11)
     checks = []

@@ -132,8 +132,8 @@ def test_grid_phase_chains_bit_exact(hy, prefilter):
 @pytest.mark.parametrize("case", sorted(CASES))
 def test_bundled_mode_bit_exact(hy, case):
     """Sets grown in bundles of 64, bit-parallel over the sets (forced here by
-    a members-per-set threshold of 1; the first 2048 sets of a graph run in
-    the per-set mode and teach the estimate) equal the oracle's."""
+    a members-per-set threshold of 1, which also starts a graph not seen yet
+    in bundled mode), appended over two calls, equal the oracle's."""
     _flush(f"[gpu] bundled case={case}")
     hg, model, p = CASES[case]()
     g, o = _pair(hy, hg, model, p)
