@@ -146,3 +146,27 @@ def test_lt_graph_rejects_unknown_model(hy):
         hy.build_graph(hg.n, hg.he_off, hg.he_mem, 4, 0.1)
     with pytest.raises(hy.HyperIMError):
         hy.build_graph(hg.n, hg.he_off, hg.he_mem, LT_CONST, float("nan"))
+
+
+def test_lt_query_batched_with_ic_query_matches_alone_and_oracle(hy):
+    """A batch (shared launch groups per round) holding an LT query and an IC
+    query on the same hypergraph: each result equals the query alone, and
+    the LT one the oracle's."""
+    _flush("[gpu] LT + IC batch")
+    w = hypergen.workload("tiny_lt")
+    hg = w.build()
+    g_lt = hy.build_graph(hg.n, hg.he_off, hg.he_mem, LT_WC, 0.0)
+    g_ic = hy.build_graph(hg.n, hg.he_off, hg.he_mem, 0, 0.05)
+    for g in (g_lt, g_ic):
+        g.stratify()
+    qs = [dict(graph=g_lt, k=w.k, eps=w.eps, ell=w.ell, seed=0, instance=0),
+          dict(graph=g_ic, k=w.k, eps=w.eps, ell=w.ell, seed=0, instance=1)]
+    rs = hy.select_seeds_batch(qs)
+    for q, r in zip(qs, rs):
+        a = hy.select_seeds(q["graph"], q["k"], q["eps"], q["ell"], seed=q["seed"], instance=q["instance"])
+        assert np.array_equal(a["seeds"], r["seeds"]) and np.array_equal(a["gains"], r["gains"])
+        assert a["theta"] == r["theta"] and a["lambda2"] == r["lambda2"]
+    o = oracle.Graph(hg, LT_WC, 0.0)
+    o.stratify()
+    ro = o.select_seeds(w.k, w.eps, w.ell, seed=0, instance=0)
+    assert np.array_equal(rs[0]["seeds"], ro["seeds"]) and rs[0]["theta"] == ro["theta"]
