@@ -11,7 +11,9 @@ Functions (each cites the passage of the paper it follows in the C source):
   Graph(hg, model, p)         validated hypergraph + incidence lists + thresholds
                               (model 0/1: IC with constant p / weighted cascade;
                               2/3: the linear-threshold model, live-edge form,
-                              with the same thresholds)
+                              with the same thresholds; 4: the stratified
+                              setting of Section 3.1.1)
+  Graph.layers()              stratified setting: A(v) by layers
   Graph.stratify()            sample-set layers (Section 3.1.1), strata, P
   Graph.root(...)             stratified root of an RR id
   Graph.rr_set(...)           one RR set (Algorithm 3 skeleton; under LT the
@@ -97,6 +99,7 @@ def lib():
         L.orc_upper_eq8.restype = C.c_uint64
         L.orc_sigma_upper_cov.argtypes = [C.c_double] * 4
         L.orc_sigma_upper_cov.restype = C.c_double
+        L.orc_layers_export.argtypes = [vp, vp, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -258,6 +261,22 @@ class Graph:
         out["B"] = B
         out["alpha"], out["beta"], out["theta_l"] = (float(x) for x in stats)
         return out
+
+    def layers(self):
+        """Stratified-setting model only: per vertex the members of A(v) layer by
+        layer (layer 1 = largest w(v,u)), ascending ids within a layer, as
+        (nb_off, nb, ly_off, ly_end): layer i of v is nb[nb_off[v] + ly_end[ly_off[v] + i - 2]
+        .. nb_off[v] + ly_end[ly_off[v] + i - 1]) (the first layer starts at nb_off[v])."""
+        st = self.strata()
+        n = self.n
+        nb_off = np.zeros(n + 1, np.uint64)
+        ly_off = np.zeros(n + 1, np.uint64)
+        nb = np.zeros(max(int(st["deg"].sum()), 1), np.uint32)
+        ly_end = np.zeros(max(int(st["l"].sum()), 1), np.uint32)
+        rc = lib().orc_layers_export(self._h, _p(nb_off), _p(nb), _p(ly_off), _p(ly_end))
+        if rc:
+            raise OracleError("orc_layers_export: %d" % rc)
+        return nb_off, nb[:int(st["deg"].sum())], ly_off, ly_end[:int(st["l"].sum())]
 
     def root(self, seed, instance, pool, j, qlog=8) -> int:
         return int(lib().orc_root(self._h, seed, instance, pool, j, qlog))

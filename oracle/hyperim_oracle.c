@@ -13,6 +13,12 @@
  *   - independent-cascade channels (Section 2.1, "Cascade models", IC):
  *     every hyperedge he and every ordered pair of distinct members u->v of he
  *     is one channel, live with probability p_v;
+ *   - the stratified setting (Section 3.1.1, "Activation probability" and
+ *     "Sampling strategy"; Algorithm 3's per-layer draws): a member of layer
+ *     i of A(v) activates v with probability P(L_i) / n(L_i),
+ *     P(L_i) = 1 / (i ln(l_v + 1)); an RR set draws per popped vertex and
+ *     layer a count (Binomial for layers of at most 20 members, Poisson
+ *     above) and selects that many members without replacement;
  *   - the linear-threshold model (Section 2.1, "Cascade models", LT) in its
  *     live-edge form: every vertex v keeps at most one of its channels, each
  *     with weight W_v (the per-channel probability, capped so that the
@@ -120,6 +126,13 @@ typedef struct orc_graph {
     uint32_t *thr;                 /* coin threshold of channels into v     */
     uint64_t *c;                   /* sum over he containing v of |he|-1    */
     int lt;                        /* linear-threshold model (else IC)      */
+    int layered;                   /* stratified-setting model (model 4)    */
+    /* stratified setting: per vertex v the members of A(v), layer by layer
+     * (layer 1 = largest w(v,u)), ascending ids within a layer:
+     * nb[nb_off[v] .. nb_off[v+1]); layer i (1-based) of v ends at
+     * nb_off[v] + ly_end[ly_off[v] + i - 1] */
+    uint64_t *nb_off, *ly_off;
+    uint32_t *nb, *ly_end;
     int stratified;
     uint32_t *l, *deg, *top, *P;   /* layers, G_w degree, |L_1|, ordering   */
     uint8_t *stratum;
@@ -133,6 +146,7 @@ void orc_graph_free(orc_graph *g)
     free(g->he_off); free(g->he_mem); free(g->v_off); free(g->v_he);
     free(g->thr); free(g->c); free(g->l); free(g->deg); free(g->top);
     free(g->P); free(g->stratum);
+    free(g->nb_off); free(g->ly_off); free(g->nb); free(g->ly_end);
     free(g);
 }
 
@@ -155,8 +169,8 @@ int orc_graph_new(uint32_t n, uint32_t m, const uint32_t *he_off, const uint32_t
                   uint32_t model, float p, orc_graph **out)
 {
     *out = NULL;
-    if (model > 3u) return ORC_EINVAL;
-    if ((model & 1u) == 0u && (isnan(p) || p < 0.0f)) return ORC_EINVAL;
+    if (model > 4u) return ORC_EINVAL;
+    if ((model == 0u || model == 2u) && (isnan(p) || p < 0.0f)) return ORC_EINVAL;
     if (he_off[0] != 0u) return ORC_EINVAL;
     for (uint32_t e = 0; e < m; ++e)
         if (he_off[e + 1] < he_off[e]) return ORC_EINVAL;
@@ -177,7 +191,8 @@ int orc_graph_new(uint32_t n, uint32_t m, const uint32_t *he_off, const uint32_t
     orc_graph *g = (orc_graph *)calloc(1, sizeof(orc_graph));
     if (!g) return ORC_ENOMEM;
     g->n = n; g->m = m; g->nnz = nnz;
-    g->lt = model >= 2u;
+    g->lt = model == 2u || model == 3u;
+    g->layered = model == 4u;
     g->he_off = (uint32_t *)malloc(sizeof(uint32_t) * (m + 1));
     g->he_mem = (uint32_t *)malloc(sizeof(uint32_t) * (nnz ? nnz : 1));
     g->v_off = (uint32_t *)calloc(n + 1, sizeof(uint32_t));
@@ -206,8 +221,8 @@ int orc_graph_new(uint32_t n, uint32_t m, const uint32_t *he_off, const uint32_t
 
     for (uint32_t v = 0; v < n; ++v) {
         float pv;
-        if ((model & 1u) == 0u) pv = p;
-        else pv = g->c[v] ? (float)(1.0 / (double)g->c[v]) : 0.0f;
+        if (model == 0u || model == 2u) pv = p;
+        else pv = g->c[v] ? (float)(1.0 / (double)g->c[v]) : 0.0f;   /* model 4 keeps these unused */
         g->thr[v] = orc_threshold(pv);
     }
     *out = g;
@@ -249,6 +264,86 @@ static uint32_t orc_stratum_of(uint32_t l)
  * stratum h.  Section 4.1 statistics: alpha = F_cnt / T_cnt (first-layer
  * vertices over all layered vertices), beta = L_cnt / |V|, and Theorem 2's
  * theta(l*) = (1/|V|) sum_v l_v / ln(l_v + 1). */
+/* (w, u) pairs: w descending, then u ascending */
+static int cmp_wu_desc(const void *a, const void *b)
+{
+    const uint32_t *x = (const uint32_t *)a, *y = (const uint32_t *)b;
+    if (x[0] != y[0]) return x[0] > y[0] ? -1 : 1;
+    return (x[1] > y[1]) - (x[1] < y[1]);
+}
+
+/* Sample-set division (Section 3.1.1) written out for the stratified
+ * setting: A(v) = the co-members of v, in layers by w(v,u) (layer 1 the
+ * largest), ascending ids within a layer.  Uses l and deg from orc_stratify. */
+static int orc_build_layers(orc_graph *g)
+{
+    uint32_t n = g->n;
+    free(g->nb_off); free(g->ly_off); free(g->nb); free(g->ly_end);
+    g->nb_off = (uint64_t *)calloc((size_t)n + 1, sizeof(uint64_t));
+    g->ly_off = (uint64_t *)calloc((size_t)n + 1, sizeof(uint64_t));
+    if (!g->nb_off || !g->ly_off) return ORC_ENOMEM;
+    for (uint32_t v = 0; v < n; ++v) {
+        g->nb_off[v + 1] = g->nb_off[v] + g->deg[v];
+        g->ly_off[v + 1] = g->ly_off[v] + g->l[v];
+    }
+    g->nb = (uint32_t *)malloc(sizeof(uint32_t) * (g->nb_off[n] ? g->nb_off[n] : 1));
+    g->ly_end = (uint32_t *)malloc(sizeof(uint32_t) * (g->ly_off[n] ? g->ly_off[n] : 1));
+    if (!g->nb || !g->ly_end) return ORC_ENOMEM;
+    uint64_t cap = 16;
+    uint32_t *buf = (uint32_t *)malloc(sizeof(uint32_t) * cap);
+    uint32_t *wu = (uint32_t *)malloc(sizeof(uint32_t) * 2 * cap);
+    if (!buf || !wu) { free(buf); free(wu); return ORC_ENOMEM; }
+    for (uint32_t v = 0; v < n; ++v) {
+        uint64_t cnt = 0;
+        for (uint32_t e = g->v_off[v]; e < g->v_off[v + 1]; ++e) {
+            uint32_t he = g->v_he[e];
+            for (uint32_t i = g->he_off[he]; i < g->he_off[he + 1]; ++i) {
+                uint32_t u = g->he_mem[i];
+                if (u == v) continue;
+                if (cnt == cap) {
+                    cap *= 2;
+                    uint32_t *nb = (uint32_t *)realloc(buf, sizeof(uint32_t) * cap);
+                    uint32_t *nw = (uint32_t *)realloc(wu, sizeof(uint32_t) * 2 * cap);
+                    if (!nb || !nw) { free(nb ? nb : buf); free(nw ? nw : wu); return ORC_ENOMEM; }
+                    buf = nb; wu = nw;
+                }
+                buf[cnt++] = u;
+            }
+        }
+        qsort(buf, cnt, sizeof(uint32_t), cmp_u32);
+        uint64_t d = 0;
+        for (uint64_t i = 0; i < cnt;) {
+            uint64_t r = i;
+            while (r < cnt && buf[r] == buf[i]) ++r;
+            wu[2 * d] = (uint32_t)(r - i);
+            wu[2 * d + 1] = buf[i];
+            ++d;
+            i = r;
+        }
+        qsort(wu, d, 2 * sizeof(uint32_t), cmp_wu_desc);
+        uint64_t base = g->nb_off[v], lb = g->ly_off[v];
+        uint32_t layer = 0;
+        for (uint64_t i = 0; i < d; ++i) {
+            g->nb[base + i] = wu[2 * i + 1];
+            if (i + 1 == d || wu[2 * (i + 1)] != wu[2 * i]) g->ly_end[lb + layer++] = (uint32_t)(i + 1);
+        }
+    }
+    free(buf);
+    free(wu);
+    return ORC_OK;
+}
+
+int orc_layers_export(const orc_graph *g, uint64_t *nb_off, uint32_t *nb, uint64_t *ly_off, uint32_t *ly_end)
+{
+    if (!g->layered || !g->stratified) return ORC_EINVAL;
+    uint32_t n = g->n;
+    memcpy(nb_off, g->nb_off, sizeof(uint64_t) * ((size_t)n + 1));
+    memcpy(ly_off, g->ly_off, sizeof(uint64_t) * ((size_t)n + 1));
+    if (g->nb_off[n]) memcpy(nb, g->nb, sizeof(uint32_t) * g->nb_off[n]);
+    if (g->ly_off[n]) memcpy(ly_end, g->ly_end, sizeof(uint32_t) * g->ly_off[n]);
+    return ORC_OK;
+}
+
 int orc_stratify(orc_graph *g)
 {
     uint32_t n = g->n;
@@ -325,6 +420,7 @@ int orc_stratify(orc_graph *g)
     g->beta = n ? (double)sum_l / (double)n : 0.0;
     g->theta_l = n ? theta_l / (double)n : 0.0;
     g->stratified = 1;
+    if (g->layered) return orc_build_layers(g);
     return ORC_OK;
 }
 
@@ -492,9 +588,124 @@ static uint32_t orc_lt_into(const orc_graph *g, uint64_t seed, uint32_t instance
     return len;
 }
 
+/* Stratified setting.  Random numbers of (RR id j, vertex v, layer i): the
+ * Philox blocks at counter (j_lo, i, v, pool<<31 | j_hi<<24 | r), r = 0, 1, ...
+ * Block 0's words 0 and 1 give U = (w0 >> 11 | w1 << 21) / 2^53 in [0, 1);
+ * block 0's words 2, 3 and every word of the blocks r >= 1, in order, are the
+ * selection draws. */
+static void orc_layer_block(uint64_t seed, uint32_t instance, uint32_t pool, uint64_t j, uint32_t i, uint32_t v,
+                            uint32_t r, uint32_t out[4])
+{
+    uint32_t ctr[4], key[2];
+    ctr[0] = (uint32_t)j;
+    ctr[1] = i;
+    ctr[2] = v;
+    ctr[3] = (pool << 31) | ((uint32_t)(j >> 32) << 24) | r;
+    key[0] = (uint32_t)seed;
+    key[1] = instance;
+    orc_philox4x32_10(ctr, key, out);
+}
+
+/* Count h of layer i of v (n members, l layers): the layer's probability is
+ * P = 1 / (i ln(l + 1)) (Section 3.1.1), each member's p = P / n, at most 1
+ * (the P of the top layers exceed 1 / n when l is small).  n <= 20: Binomial
+ * (n, p) by inversion of U, probabilities q^n, then
+ * prob_{h+1} = ((prob_h (n - h)) / (h + 1)) (p / q); n > 20: Poisson with
+ * lambda = n p = P, prob_0 = e^-lambda, prob_{h+1} = (prob_h lambda) / (h + 1),
+ * truncated at min(n, 64) (lambda < 1.5, so a count above 64 has probability
+ * below 1e-70).  h is the first count whose cumulative probability exceeds
+ * U. */
+#define ORC_MAX_PICK 64u
+static uint32_t orc_layer_count(uint32_t n, uint32_t i, uint32_t l, double U)
+{
+    double P = 1.0 / ((double)i * log((double)l + 1.0));
+    double p = P / (double)n;
+    if (n <= 20u) {
+        if (p >= 1.0) return n;
+        double q = 1.0 - p;
+        double prob = 1.0;
+        for (uint32_t t = 0; t < n; ++t) prob = prob * q;
+        double ratio = p / q, cdf = prob;
+        uint32_t h = 0;
+        while (U >= cdf && h < n) {
+            prob = ((prob * (double)(n - h)) / (double)(h + 1)) * ratio;
+            ++h;
+            cdf = cdf + prob;
+        }
+        return h;
+    }
+    double lambda = P;
+    double prob = exp(-lambda), cdf = prob;
+    uint32_t h = 0, hmax = n < ORC_MAX_PICK ? n : ORC_MAX_PICK;
+    while (U >= cdf && h < hmax) {
+        prob = (prob * lambda) / (double)(h + 1);
+        ++h;
+        cdf = cdf + prob;
+    }
+    return h;
+}
+
+/* R = {root}; pop v; for each layer i of A(v): draw the count h, then h
+ * members without replacement -- draw r picks index floor(x (n - r) / 2^32)
+ * among the layer's members not picked yet, in ascending order -- and every
+ * picked member outside R joins R and the queue (Algorithm 3's loop). */
+static uint32_t orc_layered_into(const orc_graph *g, uint64_t seed, uint32_t instance, uint32_t pool,
+                                 uint64_t j, uint32_t root, orc_scratch *s, uint32_t *out)
+{
+    uint32_t head = 0, tail = 0;
+    uint32_t picked[ORC_MAX_PICK];
+    s->queue[tail++] = root;
+    s->inR[root] = 1;
+    while (head < tail) {
+        uint32_t v = s->queue[head++];
+        uint32_t l = g->l[v];
+        uint64_t base = g->nb_off[v];
+        for (uint32_t i = 1; i <= l; ++i) {
+            uint32_t lo = i == 1 ? 0u : g->ly_end[g->ly_off[v] + i - 2];
+            uint32_t hi = g->ly_end[g->ly_off[v] + i - 1];
+            uint32_t n = hi - lo;
+            uint32_t w[4];
+            orc_layer_block(seed, instance, pool, j, i, v, 0u, w);
+            double U = (double)(((uint64_t)(w[0] >> 11)) | ((uint64_t)w[1] << 21)) * 0x1.0p-53;
+            uint32_t h = orc_layer_count(n, i, l, U);
+            uint32_t r_blk = 0, word = 2, np = 0;
+            for (uint32_t r = 0; r < h; ++r) {
+                if (word == 4) {
+                    orc_layer_block(seed, instance, pool, j, i, v, ++r_blk, w);
+                    word = 0;
+                }
+                uint32_t x = w[word++];
+                uint32_t a = (uint32_t)(((uint64_t)x * (uint64_t)(n - r)) >> 32);
+                /* the a-th index not picked yet: walk the picked ones ascending */
+                uint32_t idx = a;
+                for (uint32_t t = 0; t < np; ++t) {     /* picked[] kept ascending */
+                    if (picked[t] <= idx) ++idx;
+                    else break;
+                }
+                uint32_t t = np;
+                while (t > 0 && picked[t - 1] > idx) { picked[t] = picked[t - 1]; --t; }
+                picked[t] = idx;
+                ++np;
+                uint32_t u = g->nb[base + lo + idx];
+                if (!s->inR[u]) {
+                    s->inR[u] = 1;
+                    s->queue[tail++] = u;
+                }
+            }
+        }
+    }
+    for (uint32_t i = 0; i < tail; ++i) {
+        out[i] = s->queue[i];
+        s->inR[s->queue[i]] = 0;
+    }
+    qsort(out, tail, sizeof(uint32_t), cmp_u32);
+    return tail;
+}
+
 static uint32_t orc_set_into(const orc_graph *g, uint64_t seed, uint32_t instance, uint32_t pool,
                              uint64_t j, uint32_t root, orc_scratch *s, uint32_t *out)
 {
+    if (g->layered) return orc_layered_into(g, seed, instance, pool, j, root, s, out);
     return g->lt ? orc_lt_into(g, seed, instance, pool, j, root, s, out)
                  : orc_rr_into(g, seed, instance, pool, j, root, s, out);
 }
