@@ -42,8 +42,17 @@ WORKLOAD_TEXT = {
               "the linear-threshold model, channel weights 1/c(v), k=50 eps=0.1 ell=1",
     "large_lt": "the large hypergraph (|V|=1e6 |HE|=2e6 sizes power-law(2.2) on [2,200], Zipf(1.1) members) "
                 "under the linear-threshold model, channel weights 1/c(v), k=100 eps=0.1 ell=1",
+    "tiny_layered": "the tiny hypergraph under the stratified setting (per-layer probabilities 1/(i ln(l+1)) "
+                    "split over the layer), k=10 eps=0.5 ell=1",
+    "mid_layered": "the mid hypergraph (|V|=1e5 |HE|=2e5 sizes power-law(2.5) on [2,50], Zipf(1.0) members) under "
+                   "the stratified setting (per-layer probabilities 1/(i ln(l+1)) split over the layer), "
+                   "k=50 eps=0.1 ell=1",
+    "large_layered": "the large hypergraph (|V|=1e6 |HE|=2e6 sizes power-law(2.2) on [2,200], Zipf(1.1) members) "
+                     "under the stratified setting (per-layer probabilities 1/(i ln(l+1)) split over the layer), "
+                     "k=100 eps=0.1 ell=1",
 }
 LT_WORKLOADS = ("tiny_lt", "mid_lt", "large_lt")
+LAYERED_WORKLOADS = ("tiny_layered", "mid_layered", "large_layered")
 
 
 def parse():
@@ -295,18 +304,19 @@ def main():
     value = rr_sets_per_step * args.steps / elapsed
     per_s = args.steps / elapsed
     lt = args.workload in LT_WORKLOADS
+    layered = args.workload in LAYERED_WORKLOADS
     kernel_bytes = mtot["bytes_light"] + mtot["bytes_heavy"] + mtot["bytes_bundled"]
     # the kernels count the bytes of every expansion they perform; the pools'
     # final prefixes can only hold fewer (sets generated ahead of a round that
     # was not reached are spent work).  A linear-threshold walk reads one
     # channel per step: its algorithmic bytes are the walk kernel's own count.
-    alg_bytes = kernel_bytes if lt else mtot["alg_bytes"]
+    alg_bytes = kernel_bytes if (lt or layered) else mtot["alg_bytes"]
     assert kernel_bytes >= alg_bytes, (kernel_bytes, alg_bytes)
     # dominant expansion kernel: the largest event-timed share in the
     # instrumented step
     kernels = dict(KERNELS)
-    if lt:   # the walk kernel reports through the per-set phase's fields
-        kernels = {"k_lt_walk": kernels.pop("k_rr_light")}
+    if lt or layered:   # these kernels report through the per-set phase's fields
+        kernels = {"k_lt_walk" if lt else "k_layered": kernels.pop("k_rr_light")}
     times = {k: float(itot[f[0]]) for k, f in kernels.items()}
     kern = max(times, key=times.get)
     f_ms, f_launch, f_bytes, f_px = kernels[kern]
@@ -371,9 +381,9 @@ def main():
                    "form": "persistent" if args.form == 0 else "plain-per-stratum",
                    "tuning": tuning if tuning else "default",
                    "parallelism": "single-gpu"},
-        # channel-model figures (IC); a linear-threshold walk draws one word per step
-        "incidences_per_s": None if lt else mtot["incidences"] * per_s,
-        "coins_per_s": mtot["philox_drawn"] * per_s if lt else mtot["coins"] * per_s,
+        # channel-model figures (IC); the other models draw per step or per layer
+        "incidences_per_s": None if (lt or layered) else mtot["incidences"] * per_s,
+        "coins_per_s": mtot["philox_drawn"] * per_s if (lt or layered) else mtot["coins"] * per_s,
         "philox_blocks_per_s": {"drawn": mtot["philox_drawn"] * per_s, "per_set_traversal": mtot["philox_alg"] * per_s},
         "time_to_seed_set_ms": ms_per_step,
         "theta": [r["theta"] for r in last] if len(last) > 1 else last[0]["theta"],
@@ -384,7 +394,8 @@ def main():
         "kernels_ms": {k: v for k, v in times.items()},
         "roofline": roof,
         "rr_generation": {
-            "kernels": "k_lt_walk" if lt else "k_rr_light, k_plan, k_expand, k_finish, k_ms_*",
+            "kernels": "k_lt_walk" if lt else "k_layered" if layered else
+                       "k_rr_light, k_plan, k_expand, k_finish, k_ms_*",
             "achieved_GBps": kernel_bytes / (bfs_ms * 1e-3) / 1e9 if bfs_ms > 0 else 0.0,
             "frac_hbm": kernel_bytes / (bfs_ms * 1e-3) / 1e9 / HBM_PEAK_GBS if bfs_ms > 0 else 0.0,
             "ms": bfs_ms,

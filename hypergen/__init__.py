@@ -31,6 +31,7 @@ MODEL_CONST = 0   # constant channel probability p
 MODEL_WC = 1      # weighted cascade: p_v = 1 / (weighted clique in-degree of v)
 MODEL_LT_CONST = 2   # linear threshold, channel weight p
 MODEL_LT_WC = 3      # linear threshold, channel weight 1 / (weighted clique in-degree of v)
+MODEL_LAYERED = 4    # stratified setting: per-layer probabilities of the sample sets
 
 
 @dataclasses.dataclass
@@ -60,7 +61,7 @@ class Workload:
     m: int
     sizes: tuple            # ("uniform", lo, hi) or ("powerlaw", gamma, lo, hi)
     members: tuple          # ("uniform",) or ("zipf", s)
-    model: int              # MODEL_CONST, MODEL_WC, MODEL_LT_CONST or MODEL_LT_WC
+    model: int              # MODEL_CONST, MODEL_WC, MODEL_LT_CONST, MODEL_LT_WC or MODEL_LAYERED
     p: float                # used when model == MODEL_CONST
     k: int
     eps: float
@@ -90,6 +91,13 @@ WORKLOADS = {
                        MODEL_LT_WC, 0.0, 50, 0.1, 1.0, gen_seed=1),
     "large_lt": Workload("large_lt", 1_000_000, 2_000_000, ("powerlaw", 2.2, 2, 200), ("zipf", 1.1),
                          MODEL_LT_WC, 0.0, 100, 0.1, 1.0, gen_seed=2),
+    # ... and under the stratified setting of the sample-set layers
+    "tiny_layered": Workload("tiny_layered", 1_000, 2_000, ("uniform", 2, 6), ("uniform",),
+                             MODEL_LAYERED, 0.0, 10, 0.5, 1.0, gen_seed=0),
+    "mid_layered": Workload("mid_layered", 100_000, 200_000, ("powerlaw", 2.5, 2, 50), ("zipf", 1.0),
+                            MODEL_LAYERED, 0.0, 50, 0.1, 1.0, gen_seed=1),
+    "large_layered": Workload("large_layered", 1_000_000, 2_000_000, ("powerlaw", 2.2, 2, 200), ("zipf", 1.1),
+                              MODEL_LAYERED, 0.0, 100, 0.1, 1.0, gen_seed=2),
 }
 
 

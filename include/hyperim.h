@@ -45,6 +45,7 @@ extern "C" {
 #define HYPERIM_MODEL_WC 1u     /* weighted cascade: p_v = 1 / c(v)             */
 #define HYPERIM_MODEL_LT_CONST 2u /* linear threshold, channel weight p         */
 #define HYPERIM_MODEL_LT_WC 3u  /* linear threshold, channel weight 1 / c(v)    */
+#define HYPERIM_MODEL_LAYERED 4u /* stratified setting of Section 3.1.1         */
 #define HYPERIM_NSTRATA 8u
 
 typedef struct hyperim_graph_s *hyperim_graph;
@@ -70,7 +71,22 @@ typedef struct hyperim_session_s *hyperim_session;
  * sum to at most 1.  The Philox word of (RR id, v) at hyperedge slot
  * 0xFFFFFFFE, position 0, picks channel floor(x / W_v) when x < W_v c(v),
  * none otherwise; an RR set is the reverse walk from its root along kept
- * channels until none is kept or the walk meets a vertex already in it. */
+ * channels until none is kept or the walk meets a vertex already in it.
+ *
+ * Stratified setting (Section 3.1.1, "Activation probability" and
+ * "Sampling strategy"; Algorithm 3's per-layer draws), HYPERIM_MODEL_LAYERED,
+ * p ignored: A(v), the co-members of v, in layers by w(v,u) (layer 1 the
+ * largest, ascending ids within a layer); a member of layer i (n members, l
+ * layers) activates v with p = min(1, P / n), P = 1 / (i ln(l + 1)).  RR
+ * sets: per popped vertex v and layer i, the Philox blocks at counter
+ * (j_lo, i, v, pool << 31 | j_hi << 24 | r), r = 0, 1, ...; block 0's words 0
+ * and 1 give U = (w0 >> 11 | w1 << 21) / 2^53 and the count h inverts U --
+ * Binomial(n, p) for n <= 20 (p = 1: h = n), else Poisson(P) truncated at
+ * min(n, 64) -- with the recursions prob_{h+1} = ((prob_h (n - h)) / (h + 1))
+ * (p / q) from q^n, and prob_{h+1} = (prob_h P) / (h + 1) from e^-P; the
+ * following words x pick, h times, index floor(x (n - r) / 2^32) among the
+ * layer's members not picked yet (ascending).  Picked members outside the
+ * set join it.  ln and exp come from the host's C library. */
 typedef struct {
     uint32_t model;
     float p;

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libhyperim.so")
 
 OK, EINVAL, ENOMEM, ECAPACITY, ESTATE, EHIP = 0, -1, -2, -3, -4, -5
 PENDING = 1
-MODEL_CONST, MODEL_WC, MODEL_LT_CONST, MODEL_LT_WC = 0, 1, 2, 3
+MODEL_CONST, MODEL_WC, MODEL_LT_CONST, MODEL_LT_WC, MODEL_LAYERED = 0, 1, 2, 3, 4
 NSTRATA = 8
 FLAG_INCIDENCES = 1
 FLAG_KERNEL_TIMES = 2

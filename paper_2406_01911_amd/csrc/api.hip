@@ -131,7 +131,7 @@ size_t RRWorkspace::bytes() const {
     size_t b = 0;
     for (const DevBuf *x : {&lists, &bitmaps, &def_idx, &def_u32, &graph_desc, &task_desc, &items, &counters, &stage,
                             &stage_off, &sizes, &roots, &scan_tmp, &big_ids, &ms_seen, &ms_nxt, &ms_cur, &ms_next,
-                            &ms_batch, &ms_vcnt, &ms_ctr, &args_dev})
+                            &ms_batch, &ms_vcnt, &ms_ctr, &args_dev, &picks})
         b += x->bytes;
     return b;
 }
@@ -147,7 +147,7 @@ void RRWorkspace::release() {
     capture = nullptr;
     for (DevBuf *x : {&lists, &bitmaps, &def_idx, &def_u32, &graph_desc, &task_desc, &items, &counters, &stage,
                       &stage_off, &sizes, &roots, &scan_tmp, &big_ids, &ms_seen, &ms_nxt, &ms_cur, &ms_next,
-                      &ms_batch, &ms_vcnt, &ms_ctr, &args_dev})
+                      &ms_batch, &ms_vcnt, &ms_ctr, &args_dev, &picks})
         x->release();
     for (hipEvent_t e : events) (void)hipEventDestroy(e);
     events.clear();
@@ -191,14 +191,16 @@ SharedBytes shared_bytes() {
 size_t graph_bytes(hyperim_graph g) {
     size_t b = 0;
     for (const DevBuf *x : {&g->he_off, &g->he_mem, &g->v_off, &g->v_he, &g->thr, &g->c, &g->weight, &g->bytesw,
-                            &g->phiw, &g->v_hbs, &g->chan, &g->l, &g->deg, &g->top, &g->stratum, &g->P})
+                            &g->phiw, &g->v_hbs, &g->chan, &g->l, &g->deg, &g->top, &g->stratum, &g->P,
+                            &g->lay_nb_off, &g->lay_nb, &g->lay_ly_off, &g->lay_ly_end, &g->lay_ln, &g->lay_expm})
         b += x->bytes;
     return b;
 }
 
 void release_graph(hyperim_graph g) {
     for (DevBuf *b : {&g->he_off, &g->he_mem, &g->v_off, &g->v_he, &g->thr, &g->c, &g->weight, &g->bytesw,
-                      &g->phiw, &g->v_hbs, &g->chan, &g->l, &g->deg, &g->top, &g->stratum, &g->P})
+                      &g->phiw, &g->v_hbs, &g->chan, &g->l, &g->deg, &g->top, &g->stratum, &g->P,
+                            &g->lay_nb_off, &g->lay_nb, &g->lay_ly_off, &g->lay_ly_end, &g->lay_ln, &g->lay_expm})
         b->release();
 }
 
@@ -310,8 +312,9 @@ int hyperim_build_graph(uint32_t n, uint32_t m, const uint32_t *he_off, const ui
         set_error_detail("n must be in [1, 2^31], m < 2^32-1, arrays non-null");
         return HYPERIM_EINVAL;
     }
-    if (prob.model > HYPERIM_MODEL_LT_WC ||
-        ((prob.model & 1u) == 0u && (std::isnan(prob.p) || prob.p < 0.0f))) {
+    if (prob.model > HYPERIM_MODEL_LAYERED ||
+        ((prob.model == HYPERIM_MODEL_CONST || prob.model == HYPERIM_MODEL_LT_CONST) &&
+         (std::isnan(prob.p) || prob.p < 0.0f))) {
         set_error_detail("probability model unknown or p NaN / negative");
         return HYPERIM_EINVAL;
     }

@@ -270,7 +270,7 @@ __global__ void k_thresholds(uint32_t n, uint32_t model, float p, const uint32_t
     uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= n) return;
     float pv;
-    if ((model & 1u) == 0u) {   // constant p (IC or LT)
+    if (model == HYPERIM_MODEL_CONST || model == HYPERIM_MODEL_LT_CONST) {   // constant p
         pv = p;
     } else {
         unsigned long long cv = c[v];
@@ -405,7 +405,7 @@ int graph_build_device(hyperim_graph g, PrepWorkspace &w, hipStream_t s) {
     if (nnz)
         hipLaunchKernelGGL(k_incidence_spans, dim3(grid_for(nnz, kBlock, 8192)), dim3(kBlock), 0, s, nnz,
                            g->v_he.as<uint32_t>(), g->he_off.as<uint32_t>(), g->v_hbs.as<uint2>());
-    if (g->lt()) {
+    if (g->lt() || g->layered()) {
         // exclusive prefix over all incidences of their channel counts: the
         // channels into v are chan[v_off[v]] .. chan[v_off[v + 1]]
         HIM_CHECK(g->chan.reserve(sizeof(uint64_t) * (nnz + 1), s));

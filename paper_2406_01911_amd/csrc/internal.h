@@ -64,6 +64,7 @@ struct RRWorkspace {
     // bundled mode: per-bundle seen / found masks, frontier and next-level
     // lists, batch marks, output counts, counters
     DevBuf ms_seen, ms_nxt, ms_cur, ms_next, ms_batch, ms_vcnt, ms_ctr;
+    DevBuf picks;                // stratified setting: per-lane pick lists
     DevBuf counters;             // work counter, stage bump, misc
     DevBuf stage;                // unsorted->sorted members before compaction
     DevBuf stage_off;            // per id (uint64)
@@ -163,7 +164,10 @@ struct hyperim_graph_s {
     uint32_t n = 0, m = 0;
     uint64_t nnz = 0;
     hyperim_prob prob{};
-    bool lt() const { return prob.model >= HYPERIM_MODEL_LT_CONST; }   // linear-threshold RR sets
+    bool lt() const { return prob.model == HYPERIM_MODEL_LT_CONST || prob.model == HYPERIM_MODEL_LT_WC; }
+    bool layered() const { return prob.model == HYPERIM_MODEL_LAYERED; }   // stratified setting
+    // RR-set kernel family: 0 independent cascade, 1 linear threshold, 2 stratified setting
+    int kind() const { return layered() ? 2 : lt() ? 1 : 0; }
     // weight = d(v) + S(v) incidences read when v is expanded; bytesw = 20 + 12 d(v) + 4 S(v)
     // algorithmic bytes of v as an RR-set member (d = hyperedges of v, S = their total size);
     // phiw = sum over v's hyperedges of ceil(|he| / 4), the Philox blocks of v's expansion
@@ -171,6 +175,12 @@ struct hyperim_graph_s {
     // chan (linear-threshold graphs only): exclusive prefix over v_he of the
     // incidences' channel counts |he| - 1, nnz + 1 entries
     hyperim::DevBuf he_off, he_mem, v_off, v_he, thr, c, weight, bytesw, phiw, v_hbs, chan;
+    // stratified setting (built by stratify): A(v) by layers -- members
+    // lay_nb[lay_nb_off[v] ..], layer i ending at lay_nb_off[v] +
+    // lay_ly_end[lay_ly_off[v] + i - 1] -- and the host-evaluated tables
+    // lay_ln[l] = ln(l + 1), lay_expm[l (l - 1) / 2 + i - 1] = e^-P(L_i)
+    hyperim::DevBuf lay_nb_off, lay_nb, lay_ly_off, lay_ly_end, lay_ln, lay_expm;
+    uint32_t lay_lmax = 0;
     bool stratified = false;
     hyperim::DevBuf l, deg, top, stratum, P;
     hyperim_strata_info info{};
@@ -246,6 +256,8 @@ int graph_build_device(hyperim_graph g, PrepWorkspace &w, hipStream_t s);
 
 // ---- launchers (stratify.hip) -------------------------------------------------
 int stratify_device(hyperim_graph g, PrepWorkspace &w, hipStream_t s);
+// Stratified-setting tables of a stratified graph (layers.hip); lmax = largest l_v.
+int layers_build_device(hyperim_graph g, uint32_t lmax, hipStream_t s);
 
 // ---- launchers (scan.hip) -----------------------------------------------------
 // out[0..count] = exclusive prefix sums of in[0..count) plus init; out[count] = total.

@@ -92,6 +92,10 @@ struct GraphDesc {
     // linear-threshold graphs: channels of the incidences before each one
     // (exclusive prefix of |he| - 1 over v_he, nnz + 1 entries); else null
     const unsigned long long *chan;
+    // stratified-setting graphs: A(v) by layers and the count tables; else null
+    const unsigned long long *lay_nb_off, *lay_ly_off;
+    const uint32_t *lay_nb, *lay_ly_end, *l;
+    const double *lay_ln, *lay_expm;
 };
 
 // The same arrays as global-memory pointers: descriptors are read from device
@@ -854,6 +858,233 @@ __global__ __launch_bounds__(kWG) void k_lt_walk(RRArgs a) {
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         wave_sync();
     }
+    if (lane == 0 && bytes_done) atomicAdd(&a.ctr[kBytesA], bytes_done);
+    if (lane == 0 && px) atomicAdd(&a.ctr[kPhiloxA], (unsigned long long)px);
+}
+
+// ---- stratified setting -------------------------------------------------------
+// RR sets of the stratified setting (Section 3.1.1, "Activation probability"
+// and "Sampling strategy"; Algorithm 3's per-layer draws).  For a popped
+// vertex v with l layers and layer i of n members: the layer probability is
+// P = 1 / (i ln(l + 1)), a member's p = min(1, P / n); the Philox blocks at
+// counter (j_lo, i, v, pool << 31 | j_hi << 24 | r) give U from block 0's
+// first two words and the selection draws from its last two and every word
+// of the later blocks.  The count h inverts U: Binomial(n, p) for n <= 20,
+// else Poisson(P) truncated at min(n, kMaxPick); then h members are picked
+// one at a time, draw x picking index floor(x (n - r) / 2^32) among those not
+// picked yet (ascending).  ln(l + 1) and e^-P come from the graph's
+// host-evaluated tables; the count arithmetic is IEEE double with no fused
+// multiply-adds, in the order the recursions state.
+//
+// One wave per set (persistent, phase A's slots, bitmaps and output path):
+// the lanes take the set's queued vertices 64 at a time and each walks its
+// vertex's layers; picked members go through the visited bitmap (atomic or:
+// the lane that sets the bit appends the member at a wave counter in LDS).
+// Picks of a layer of at most 32 members live in a bit mask; larger layers
+// keep their picked indices, ascending, in a per-lane scratch list.
+constexpr uint32_t kMaxPick = 64;
+
+__device__ __forceinline__ uint32_t layer_count(uint32_t n, uint32_t i, uint32_t l, double U,
+                                                const HIM_GLOBAL double *ln, const HIM_GLOBAL double *expm) {
+#pragma clang fp contract(off)
+    const double P = 1.0 / ((double)i * ln[l]);
+    const double p = P / (double)n;
+    if (n <= 20u) {
+        if (p >= 1.0) return n;
+        const double q = 1.0 - p;
+        double prob = 1.0;
+        for (uint32_t t = 0; t < n; ++t) prob = prob * q;
+        const double ratio = p / q;
+        double cdf = prob;
+        uint32_t h = 0;
+        while (U >= cdf && h < n) {
+            prob = ((prob * (double)(n - h)) / (double)(h + 1)) * ratio;
+            ++h;
+            cdf = cdf + prob;
+        }
+        return h;
+    }
+    double prob = expm[(size_t)l * (l - 1) / 2 + i - 1];
+    double cdf = prob;
+    const uint32_t hmax = min(n, kMaxPick);
+    uint32_t h = 0;
+    while (U >= cdf && h < hmax) {
+        prob = (prob * P) / (double)(h + 1);
+        ++h;
+        cdf = cdf + prob;
+    }
+    return h;
+}
+
+template <bool kLdsBitmap>
+__global__ __launch_bounds__(kWG) void k_layered(RRArgs a, uint32_t *__restrict__ pick_scratch) {
+    __shared__ uint32_t sort_s[kWavesPerWG][kSortMax];
+    __shared__ uint32_t lbm[kLdsBitmap ? kWavesPerWG : 1][kLdsBitmap ? kLdsBitmapWords : 1];
+    __shared__ uint32_t tail_s[kWavesPerWG];
+    const uint32_t lane = lane_id(), wv = uni(threadIdx.x / kWave);
+    const uint32_t slot = blockIdx.x * kWavesPerWG + wv;
+    uint32_t *sortb = sort_s[wv];
+    uint32_t *list = a.lists + (uint64_t)slot * a.slot_n;
+    uint32_t *picks = pick_scratch + ((uint64_t)slot * kWave + lane) * kMaxPick;
+    uint32_t *bm;
+    if constexpr (kLdsBitmap) {
+        bm = lbm[wv];
+        for (uint32_t i = lane; i < kLdsBitmapWords; i += kWave) bm[i] = 0u;
+    } else {
+        bm = a.bitmaps + (uint64_t)slot * a.slot_words;
+    }
+    wave_sync();
+    uint64_t bytes_done = 0, px = 0;
+    for (;;) {
+        unsigned long long idx = 0;
+        if (lane == 0) idx = atomicAdd(&a.ctr[kWork], 1ull);
+        idx = uni64(wave_bcast64(idx, 0));
+        if (idx >= a.count) break;
+        const uint32_t task = task_of(a, idx);
+        const SetRef S = set_ref(a, task, idx);
+        const GraphView &G = S.G;
+        const GraphDesc &D = a.graphs[uni(a.tasks[task].graph)];
+        const HIM_GLOBAL unsigned long long *nb_off = uni_ptr((const HIM_GLOBAL unsigned long long *)D.lay_nb_off);
+        const HIM_GLOBAL unsigned long long *ly_off = uni_ptr((const HIM_GLOBAL unsigned long long *)D.lay_ly_off);
+        const HIM_GLOBAL uint32_t *nb = uni_ptr((const HIM_GLOBAL uint32_t *)D.lay_nb);
+        const HIM_GLOBAL uint32_t *ly_end = uni_ptr((const HIM_GLOBAL uint32_t *)D.lay_ly_end);
+        const HIM_GLOBAL uint32_t *lv_of = uni_ptr((const HIM_GLOBAL uint32_t *)D.l);
+        const HIM_GLOBAL double *ln = uni_ptr((const HIM_GLOBAL double *)D.lay_ln);
+        const HIM_GLOBAL double *expm = uni_ptr((const HIM_GLOBAL double *)D.lay_expm);
+        const uint32_t root = rr_root(G, a.qlog, S.j, S.pool, S.key);
+        if (lane == 0) {
+            list[0] = root;
+            if constexpr (kLdsBitmap) bm[root >> 5] |= 1u << (root & 31);
+            else atomicOr(&bm[root >> 5], 1u << (root & 31));
+            tail_s[wv] = 1u;
+        }
+        wave_sync();
+        uint32_t head = 0, size = 1;
+        while (head < size) {
+            // queue entries were stored by other lanes of this wave
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            const uint32_t nbq = min((uint32_t)kWave, size - head);
+            if (lane < nbq) {
+                const uint32_t v = list[head + lane];
+                const uint32_t l = lv_of[v];
+                const uint64_t base = nb_off[v], lb = ly_off[v];
+                uint32_t lo = 0;
+                bytes_done += 20ull + 4ull * l;
+                for (uint32_t i = 1; i <= l; ++i) {
+                    const uint32_t hi = ly_end[lb + i - 1], n = hi - lo;
+                    uint4 w = philox4x32_10(make_uint4((uint32_t)S.j, i, v,
+                                                       (S.pool << 31) | ((uint32_t)(S.j >> 32) << 24)),
+                                            S.key);
+                    ++px;
+                    const double U = (double)((uint64_t)(w.x >> 11) | ((uint64_t)w.y << 21)) * 0x1.0p-53;
+                    const uint32_t h = layer_count(n, i, l, U, ln, expm);
+                    uint32_t mask = 0, np = 0, word = 2, blk = 0;
+                    for (uint32_t r = 0; r < h; ++r) {
+                        if (word == 4) {
+                            w = philox4x32_10(make_uint4((uint32_t)S.j, i, v,
+                                                         (S.pool << 31) | ((uint32_t)(S.j >> 32) << 24) | ++blk),
+                                              S.key);
+                            ++px;
+                            word = 0;
+                        }
+                        const uint32_t x = word == 0 ? w.x : word == 1 ? w.y : word == 2 ? w.z : w.w;
+                        ++word;
+                        const uint32_t aidx = (uint32_t)(((uint64_t)x * (uint64_t)(n - r)) >> 32);
+                        uint32_t pi;
+                        if (n <= 32u) {
+                            // the aidx-th clear bit of the mask
+                            uint32_t c = aidx;
+                            pi = 0;
+                            for (uint32_t t = 0; t < n; ++t) {
+                                if ((mask >> t) & 1u) continue;
+                                if (c == 0) {
+                                    pi = t;
+                                    break;
+                                }
+                                --c;
+                            }
+                            mask |= 1u << pi;
+                        } else {
+                            pi = aidx;
+                            uint32_t t = 0;
+                            for (; t < np; ++t) {
+                                const uint32_t q = picks[t];
+                                if (q <= pi) ++pi;
+                                else break;
+                            }
+                            for (uint32_t z = np; z > t; --z) picks[z] = picks[z - 1];
+                            picks[t] = pi;
+                            ++np;
+                        }
+                        const uint32_t u = nb[base + lo + pi];
+                        const uint32_t bit = 1u << (u & 31);
+                        if ((atomicOr(&bm[u >> 5], bit) & bit) == 0u) {
+                            const uint32_t pos = atomicAdd(&tail_s[wv], 1u);
+                            list[pos] = u;
+                        }
+                    }
+                    bytes_done += 8ull + 4ull * h;
+                    lo = hi;
+                }
+            }
+            wave_sync();
+            head += nbq;
+            size = uni(tail_s[wv]);
+        }
+
+        // ---- output: ascending members into the stage, as in phase A -----
+        unsigned long long off = 0;
+        if (lane == 0) off = atomicAdd(&a.ctr[kBump], (unsigned long long)size);
+        off = wave_bcast64(off, 0);
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        if (off + size <= a.stage_cap) {
+            if (size <= kSortMax) {
+                uint32_t P2 = kWave;
+                while (P2 < size) P2 <<= 1;
+                for (uint32_t i = lane; i < P2; i += kWave) sortb[i] = i < size ? list[i] : 0xFFFFFFFFu;
+                wave_sync();
+                for (uint32_t kk = 2; kk <= P2; kk <<= 1) {
+                    for (uint32_t jj = kk >> 1; jj > 0; jj >>= 1) {
+                        for (uint32_t i = lane; i < P2; i += kWave) {
+                            const uint32_t xx = i ^ jj;
+                            if (xx > i) {
+                                const uint32_t pv = sortb[i], qv = sortb[xx];
+                                if ((pv > qv) == ((i & kk) == 0)) {
+                                    sortb[i] = qv;
+                                    sortb[xx] = pv;
+                                }
+                            }
+                        }
+                        wave_sync();
+                    }
+                }
+                for (uint32_t i = lane; i < size; i += kWave) a.stage[off + i] = sortb[i];
+                wave_sync();
+            } else {
+                uint32_t written = 0;
+                for (uint32_t w0 = 0; w0 < G.bm_words; w0 += kWave) {
+                    const uint32_t wi = w0 + lane;
+                    uint32_t wd = wi < G.bm_words ? bm_load<kLdsBitmap>(bm, wi) : 0u;
+                    const uint32_t cnt = (uint32_t)__popc(wd);
+                    const uint32_t incl = wave_incl_scan(cnt);
+                    uint64_t pos = off + written + incl - cnt;
+                    while (wd) {
+                        const uint32_t bit = (uint32_t)__ffs(wd) - 1u;
+                        wd &= wd - 1u;
+                        if (pos < off + size) a.stage[pos] = wi * 32u + bit;
+                        ++pos;
+                    }
+                    written += wave_bcast(incl, kWave - 1);
+                }
+            }
+        }
+        if (lane == 0) record_set(a, idx, off, size, root);
+        for (uint32_t i = lane; i < size; i += kWave) bm[list[i] >> 5] = 0u;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        wave_sync();
+    }
+    bytes_done = wave_sum(bytes_done);
+    px = wave_sum(px);
     if (lane == 0 && bytes_done) atomicAdd(&a.ctr[kBytesA], bytes_done);
     if (lane == 0 && px) atomicAdd(&a.ctr[kPhiloxA], (unsigned long long)px);
 }
@@ -2252,6 +2483,33 @@ int run_lt_launch(RRWorkspace &ws, RRStats &st, const RRArgs &a, const LaunchSha
     return HYPERIM_OK;
 }
 
+// One launch group of stratified-setting sets (k_layered), with the per-lane
+// pick lists in the workspace.  Ends like run_launch.
+template <class Tail>
+int run_layered_launch(RRWorkspace &ws, RRStats &st, const RRArgs &a, const LaunchShape &shape, uint32_t grid,
+                       hipStream_t s, Tail &&tail) {
+    unsigned long long *h = ws.host;
+    HIM_CHECK(ws.picks.reserve(sizeof(uint32_t) * (size_t)grid * kWavesPerWG * kWave * kMaxPick, s));
+    HIM_CHECK(event_pair(ws));
+    if (shape.lds)
+        hipExtLaunchKernelGGL(k_layered<true>, dim3(grid), dim3(kWG), 0, s, ws.events[0], ws.events[1], 0u, a,
+                              ws.picks.as<uint32_t>());
+    else
+        hipExtLaunchKernelGGL(k_layered<false>, dim3(grid), dim3(kWG), 0, s, ws.events[0], ws.events[1], 0u, a,
+                              ws.picks.as<uint32_t>());
+    HIM_HIP(hipGetLastError());
+    st.launches += 1;
+    HIM_HIP(hipMemcpyAsync(h + kHostFinal, a.ctr, sizeof(unsigned long long) * kNumCtr, hipMemcpyDeviceToHost, s));
+    const int rc = tail();
+    HIM_HIP(hipStreamSynchronize(s));
+    HIM_CHECK(rc);
+    float ms = 0.f;
+    HIM_HIP(hipEventElapsedTime(&ms, ws.events[0], ws.events[1]));
+    st.ms_bfs += ms;
+    st.ms_light += ms;
+    return HYPERIM_OK;
+}
+
 // Bytes of the bundled-mode state per bundle for a graph of n vertices:
 // seen and nxt masks, frontier and next-level lists, output counts, batch marks.
 uint64_t ms_bytes_per_bundle(uint32_t n) {
@@ -2513,11 +2771,20 @@ int rr_generate_into(RRWorkspace &ws, RRStats &st, const std::vector<RRTask> &ta
         if (gid.count(t.g)) continue;
         gid[t.g] = (uint32_t)gdesc.size();
         hyperim_graph g = t.g;
-        gdesc.push_back(GraphDesc{g->he_off.as<uint32_t>(), g->he_mem.as<uint32_t>(), g->v_off.as<uint32_t>(),
-                                  g->v_he.as<uint32_t>(), g->thr.as<uint32_t>(), g->P.as<uint32_t>(),
-                                  g->v_hbs.as<unsigned long long>(), g->n,
-                                  (uint32_t)(((uint64_t)g->n + 31u) / 32u),
-                                  g->lt() ? g->chan.as<unsigned long long>() : nullptr});
+        GraphDesc d{g->he_off.as<uint32_t>(), g->he_mem.as<uint32_t>(), g->v_off.as<uint32_t>(),
+                    g->v_he.as<uint32_t>(), g->thr.as<uint32_t>(), g->P.as<uint32_t>(),
+                    g->v_hbs.as<unsigned long long>(), g->n, (uint32_t)(((uint64_t)g->n + 31u) / 32u),
+                    g->lt() ? g->chan.as<unsigned long long>() : nullptr};
+        if (g->layered()) {
+            d.lay_nb_off = g->lay_nb_off.as<unsigned long long>();
+            d.lay_ly_off = g->lay_ly_off.as<unsigned long long>();
+            d.lay_nb = g->lay_nb.as<uint32_t>();
+            d.lay_ly_end = g->lay_ly_end.as<uint32_t>();
+            d.l = g->l.as<uint32_t>();
+            d.lay_ln = g->lay_ln.as<double>();
+            d.lay_expm = g->lay_expm.as<double>();
+        }
+        gdesc.push_back(d);
         n_max = std::max(n_max, g->n);
     }
     uint64_t count = 0;
@@ -2556,7 +2823,7 @@ int rr_generate_into(RRWorkspace &ws, RRStats &st, const std::vector<RRTask> &ta
     // the first group's sets teach the estimate either way, and a graph tuned
     // for bundled mode has large sets, which the per-set mode grows slowly)
     auto bundled = [&](const RRTask &t) {
-        return form == 0 && !t.g->lt() && tune.ms_min != 0xFFFFFFFFu &&
+        return form == 0 && t.g->kind() == 0 && tune.ms_min != 0xFFFFFFFFu &&
                (t.g->rr_members < 0.0 || t.g->rr_members >= (double)tune.ms_min);
     };
     const double stage_words = (double)stage_budget / 4.0;
@@ -2661,7 +2928,7 @@ int rr_generate_into(RRWorkspace &ws, RRStats &st, const std::vector<RRTask> &ta
             if (take < rest || pos == count || form == 1 || pos - lo >= def_chunk) break;
             ++ti;   // form 0: the group continues with the next task ...
             // ... unless that one runs bundled or has the other cascade model
-            if (bundled(tasks[ti]) || tasks[ti].g->lt() != tasks[ti - 1].g->lt()) break;
+            if (bundled(tasks[ti]) || tasks[ti].g->kind() != tasks[ti - 1].g->kind()) break;
         }
         const uint64_t hi = pos;
         // descriptors of the group's task slices
@@ -2727,6 +2994,8 @@ int rr_generate_into(RRWorkspace &ws, RRStats &st, const std::vector<RRTask> &ta
                                         time_kernels, graphs, s, scans));
             else if (tasks[slices[0].task].g->lt())
                 HIM_CHECK(run_lt_launch(ws, run, a, shape, grid, s, scans));
+            else if (tasks[slices[0].task].g->layered())
+                HIM_CHECK(run_layered_launch(ws, run, a, shape, grid, s, scans));
             else
                 HIM_CHECK(run_launch(ws, run, tune, a, shape, grid, grid_b, expect_defer, trace, time_kernels,
                                      graphs, s, scans));

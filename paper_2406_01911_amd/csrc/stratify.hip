@@ -414,6 +414,7 @@ int stratify_device(hyperim_graph g, PrepWorkspace &w, hipStream_t s) {
     info.alpha = info.sum_deg ? (double)info.sum_top / (double)info.sum_deg : 0.0;
     info.beta = n ? (double)info.sum_l / (double)n : 0.0;
     info.theta_l = n ? tl / (double)n : 0.0;
+    if (g->layered()) HIM_CHECK(layers_build_device(g, lmax, s));
     g->stratified = true;
     return HYPERIM_OK;
 }

@@ -1,0 +1,132 @@
+"""GPU parity of the stratified-setting model (Section 3.1.1; Algorithm 3's
+per-layer draws): the device layer tables built at stratify time and the
+RR kernel, through the C ABI, against the oracle bit for bit -- roots, RR
+sets (ascending members), and whole HyperIM_BRR queries.  Cases cover the
+LDS and global visited bitmaps (|V| above 32768), Binomial layers (at most
+20 members), Poisson layers picked through the bit mask (21-32 members) and
+through the per-lane pick lists (above 32), single-member top layers
+(probability clamped at 1), isolated vertices and empty hyperedges, high RR
+ids, the plain form, and generation calls mixing models."""
+import sys
+
+import numpy as np
+import pytest
+
+import hypergen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+LAYERED = 4
+
+
+def _flush(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def hy():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2406_01911_amd as hy
+    hy.load_library()
+    return hy
+
+
+def _star_layers(sizes, extra=0):
+    """Centre 0 whose layer t has sizes[t] members (each in len(sizes) - t
+    copies of {0, member}), plus `extra` isolated vertices."""
+    edges, nxt, L = [], 1, len(sizes)
+    for t, size in enumerate(sizes):
+        for u in range(nxt, nxt + size):
+            edges.extend([[0, u]] * (L - t))
+        nxt += size
+    return hypergen.from_lists(nxt + extra, edges + [[]])
+
+
+def _chain_of_cliques(n=40000, k=5):
+    """Overlapping cliques along a path (|V| > 32768: global bitmaps)."""
+    return hypergen.from_lists(n, [list(range(i, min(n, i + k))) for i in range(0, n - 1, k - 1)])
+
+
+CASES = {
+    "tiny_layered": lambda: hypergen.workload("tiny_layered").build(),
+    "small_random": lambda: hypergen.tiny_hypergraph(51, 300, 400, 2, 9, allow_singletons=True),
+    "star_all_strategies": lambda: _star_layers([1, 3, 20, 25, 40, 200], extra=3),
+    "pair": lambda: hypergen.from_lists(3, [[0, 1]]),
+    "chain_40000": lambda: _chain_of_cliques(),
+}
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_layered_rr_sets_bit_exact(hy, case):
+    _flush(f"[gpu] stratified setting rr sets case={case}")
+    hg = CASES[case]()
+    g = hy.build_graph(hg.n, hg.he_off, hg.he_mem, LAYERED, 0.0)
+    o = oracle.Graph(hg, LAYERED, 0.0)
+    info = g.stratify()
+    st = o.stratify()
+    a = g.read()
+    for k in ("l", "deg", "top", "stratum", "P"):
+        assert np.array_equal(a[k], st[k]), k
+    centre = 0
+    for pool_tag, (lo, hi) in [(0, (0, 1500)), (1, (300, 800)), (0, ((1 << 33) - 64, (1 << 33) + 64))]:
+        pool = hy.Pool(g)
+        hy.generate_rr(g, 9, 2, pool_tag, lo, hi, pool)
+        off, mem, roots = pool.read()
+        roff, rmem, rroots = o.generate(9, 2, pool_tag, lo, hi)
+        assert np.array_equal(roots, rroots)
+        assert np.array_equal(off, roff)
+        assert np.array_equal(mem, rmem)
+        centre += int((roots == 0).sum())
+    assert info["B"][-1] == hg.n
+    if case == "star_all_strategies":
+        assert centre > 0   # sets rooted at the centre draw from every layer kind
+
+
+def test_layered_queries_match_oracle(hy):
+    for name in ("tiny_layered", "mid_layered"):
+        _flush(f"[gpu] stratified setting query {name}")
+        w = hypergen.workload(name)
+        hg = w.build()
+        g = hy.build_graph(hg.n, hg.he_off, hg.he_mem, w.model, w.p)
+        o = oracle.Graph(hg, w.model, w.p)
+        g.stratify()
+        o.stratify()
+        pool = hy.Pool(g)
+        hy.generate_rr(g, w.philox_seed, 0, 1, 0, 4096, pool)
+        off, mem, roots = pool.read()
+        roff, rmem, rroots = o.generate(w.philox_seed, 0, 1, 0, 4096)
+        assert np.array_equal(roots, rroots) and np.array_equal(off, roff) and np.array_equal(mem, rmem)
+        for bound in (0, 1):
+            ro = o.select_seeds(w.k, w.eps, w.ell, seed=w.philox_seed, bound=bound)
+            for form in (0, 1):
+                r = hy.select_seeds(g, w.k, w.eps, w.ell, seed=w.philox_seed, form=form, bound=bound)
+                for key in ("rounds", "theta", "lambda1", "lambda2", "entries1", "entries2", "lambda_u"):
+                    assert r[key] == ro[key], (name, bound, form, key, r[key], ro[key])
+                assert np.array_equal(r["seeds"], ro["seeds"]) and np.array_equal(r["gains"], ro["gains"])
+
+
+def test_layered_lt_and_ic_in_one_generation_call(hy):
+    _flush("[gpu] stratified setting + LT + IC in one call")
+    hg = hypergen.tiny_hypergraph(61, 3000, 4000, 2, 6)
+    graphs = []
+    for model, p in ((LAYERED, 0.0), (0, 0.1), (3, 0.0)):
+        g = hy.build_graph(hg.n, hg.he_off, hg.he_mem, model, p)
+        g.stratify()
+        o = oracle.Graph(hg, model, p)
+        o.stratify()
+        graphs.append((g, o))
+    tasks, pools = [], []
+    for i, (g, o) in enumerate(graphs):
+        for tag in (0, 1):
+            pl = hy.Pool(g)
+            pools.append((pl, o, tag, i))
+            tasks.append(dict(graph=g, pool=pl, seed=4, instance=i, pool_tag=tag, id_begin=0, id_end=1200))
+    hy.generate_rr_batch(tasks)
+    for pl, o, tag, i in pools:
+        off, mem, roots = pl.read()
+        roff, rmem, rroots = o.generate(4, i, tag, 0, 1200)
+        assert np.array_equal(roots, rroots) and np.array_equal(off, roff) and np.array_equal(mem, rmem), (i, tag)
