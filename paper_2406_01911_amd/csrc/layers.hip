@@ -4,21 +4,22 @@
 // tables of ln(l + 1) and e^-P(L_i) that the RR kernel's count draws use.
 //
 // Built once per graph at stratify time, on the device:
-//   1. every co-member occurrence (v, u) of incidence e is written at the
-//      incidence's channel prefix chan[e] (the graph's exclusive prefix of
-//      |he| - 1 over v_he), so v's occurrences form one segment;
-//   2. a segmented radix sort orders each segment by u (rocPRIM);
-//   3. run heads give the distinct co-members and their run lengths w(v,u);
-//   4. a second, stable segmented sort by descending w puts them in layers
-//      (equal w keep ascending u);
-//   5. positions where w changes inside a segment are the layer ends.
+//   1. every co-member occurrence (v, u) of incidence e is written, as the
+//      key v << b | u (b = bits of a vertex id), at the incidence's channel
+//      prefix chan[e] (the graph's exclusive prefix of |he| - 1 over v_he);
+//   2. a device-wide radix sort orders the keys (rocPRIM), so each vertex's
+//      occurrences are contiguous and ascending in u;
+//   3. run heads give the distinct pairs (v, u) and their run lengths w(v,u);
+//   4. a second, stable radix sort by the key v << 32 | ~w puts each vertex's
+//      co-members in layers (descending w; equal w keep ascending u);
+//   5. positions where the key changes are the layer ends.
 // ln and e^-P are evaluated on the host with the C library's log and exp, so
 // the device uses the same doubles as any host code that calls them.
 #include <hip/hip_runtime.h>
 
 #include <cstring>
 
-#include <rocprim/device/device_segmented_radix_sort.hpp>
+#include <rocprim/device/device_radix_sort.hpp>
 
 #include <algorithm>
 #include <cmath>
@@ -47,80 +48,69 @@ __device__ __forceinline__ uint32_t owner(const uint32_t *__restrict__ v_off, ui
     return lo;
 }
 
-// 1. Occurrences: incidence e = (v, he) writes the members of he other than v
-// at chan[e] ...
-__global__ void k_occ_emit(uint32_t n, uint64_t nnz, const uint32_t *__restrict__ v_off,
+// 1. Occurrences: incidence e = (v, he) writes v << b | u for the members u
+// of he other than v at chan[e] ...
+__global__ void k_occ_emit(uint32_t n, uint64_t nnz, uint32_t b, const uint32_t *__restrict__ v_off,
                            const uint32_t *__restrict__ v_he, const uint32_t *__restrict__ he_off,
                            const uint32_t *__restrict__ he_mem, const unsigned long long *__restrict__ chan,
-                           uint32_t *__restrict__ occ) {
+                           unsigned long long *__restrict__ occ) {
     for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += (uint64_t)gridDim.x * blockDim.x) {
         const uint32_t v = owner(v_off, n, e), he = v_he[e];
         uint64_t at = chan[e];
         for (uint32_t i = he_off[he]; i < he_off[he + 1]; ++i) {
             const uint32_t u = he_mem[i];
-            if (u != v) occ[at++] = u;
+            if (u != v) occ[at++] = ((unsigned long long)v << b) | u;
         }
     }
 }
 
-// Segment begins of the occurrence lists: seg[v] = chan[v_off[v]], v <= n.
-__global__ void k_seg_begin(uint32_t n, const uint32_t *__restrict__ v_off, const unsigned long long *__restrict__ chan,
-                            uint32_t *__restrict__ seg) {
-    for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v <= n; v += (uint64_t)gridDim.x * blockDim.x)
-        seg[v] = (uint32_t)chan[v_off[v]];
+// 3. Run heads of the sorted keys.
+__global__ void k_heads(uint64_t total, const unsigned long long *__restrict__ key, uint32_t *__restrict__ head) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (uint64_t)gridDim.x * blockDim.x)
+        head[i] = (i == 0 || key[i] != key[i - 1]) ? 1u : 0u;
 }
 
-// 3. Run heads of the sorted occurrences (a new segment always starts a run).
-__global__ void k_heads(uint32_t n, uint64_t total, const uint32_t *__restrict__ seg, const uint32_t *__restrict__ occ,
-                        uint32_t *__restrict__ head) {
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (uint64_t)gridDim.x * blockDim.x) {
-        bool h = i == 0 || occ[i] != occ[i - 1];
-        if (!h) {
-            const uint32_t v = owner(seg, n, i);
-            h = seg[v] == (uint32_t)i;
-        }
-        head[i] = h ? 1u : 0u;
-    }
-}
-
-// Distinct co-member k (at run head i): u, and its run's start for the
-// lengths.
-__global__ void k_runs(uint64_t total, const uint32_t *__restrict__ occ, const uint32_t *__restrict__ head,
-                       const unsigned long long *__restrict__ hscan, uint32_t *__restrict__ uniq_u,
+// Distinct pair k (at run head i): its key and its run's start.
+__global__ void k_runs(uint64_t total, const unsigned long long *__restrict__ key, const uint32_t *__restrict__ head,
+                       const unsigned long long *__restrict__ hscan, unsigned long long *__restrict__ ukey,
                        uint32_t *__restrict__ run_start) {
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (uint64_t)gridDim.x * blockDim.x)
         if (head[i]) {
             const uint64_t k = hscan[i];
-            uniq_u[k] = occ[i];
+            ukey[k] = key[i];
             run_start[k] = (uint32_t)i;
         }
 }
 
-// Sort key of distinct co-member k: ~w, so ascending keys are descending w.
-__global__ void k_wkeys(uint64_t uniq, uint64_t total, const uint32_t *__restrict__ run_start,
-                        uint32_t *__restrict__ key) {
+// Layer sort key of distinct pair k: v << 32 | ~w (ascending keys: v, then
+// descending w); the value is u.
+__global__ void k_wkeys(uint64_t uniq, uint64_t total, uint32_t b, const unsigned long long *__restrict__ ukey,
+                        const uint32_t *__restrict__ run_start, unsigned long long *__restrict__ key2,
+                        uint32_t *__restrict__ val) {
+    const unsigned long long umask = (1ull << b) - 1ull;
     for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < uniq; k += (uint64_t)gridDim.x * blockDim.x) {
         const uint32_t end = k + 1 < uniq ? run_start[k + 1] : (uint32_t)total;
-        key[k] = ~(end - run_start[k]);
+        const uint32_t w = end - run_start[k];
+        const unsigned long long v = ukey[k] >> b;
+        key2[k] = (v << 32) | (unsigned long long)(~w);
+        val[k] = (uint32_t)(ukey[k] & umask);
     }
 }
 
-// 5. Layer ends: entry k of vertex v's range [nb_off[v], nb_off[v+1]) ends a
-// layer when the next entry has another weight or the range ends.
-__global__ void k_layer_flags(uint32_t n, uint64_t uniq, const uint32_t *__restrict__ nbo, const uint32_t *__restrict__ key,
-                              uint32_t *__restrict__ flag) {
-    for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < uniq; k += (uint64_t)gridDim.x * blockDim.x) {
-        const uint32_t v = owner(nbo, n, k);
-        flag[k] = (k + 1 == nbo[v + 1] || key[k + 1] != key[k]) ? 1u : 0u;
-    }
+// 5. Layer ends: entry k ends a layer when the next key differs (another
+// weight or another vertex) or k is the last entry.
+__global__ void k_layer_flags(uint64_t uniq, const unsigned long long *__restrict__ key2, uint32_t *__restrict__ flag) {
+    for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < uniq; k += (uint64_t)gridDim.x * blockDim.x)
+        flag[k] = (k + 1 == uniq || key2[k + 1] != key2[k]) ? 1u : 0u;
 }
 
-__global__ void k_layer_ends(uint32_t n, uint64_t uniq, const uint32_t *__restrict__ nbo, const uint32_t *__restrict__ flag,
-                             const unsigned long long *__restrict__ fscan, uint32_t *__restrict__ ly_end) {
+__global__ void k_layer_ends(uint64_t uniq, const unsigned long long *__restrict__ key2, const uint32_t *__restrict__ flag,
+                             const unsigned long long *__restrict__ fscan, const unsigned long long *__restrict__ nb_off,
+                             uint32_t *__restrict__ ly_end) {
     for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < uniq; k += (uint64_t)gridDim.x * blockDim.x)
         if (flag[k]) {
-            const uint32_t v = owner(nbo, n, k);
-            ly_end[fscan[k]] = (uint32_t)(k + 1 - nbo[v]);
+            const uint32_t v = (uint32_t)(key2[k] >> 32);
+            ly_end[fscan[k]] = (uint32_t)(k + 1 - nb_off[v]);
         }
 }
 
@@ -138,45 +128,38 @@ int layers_build_device(hyperim_graph g, uint32_t lmax, hipStream_t s) {
         set_error_detail("stratified-setting tables: more than 2^32 co-member occurrences or 16384 layers");
         return HYPERIM_EINVAL;
     }
-    DevBuf occ, occ2, seg, tmp, head, hscan, run_start, key, key2, nbo, flag, fscan, scan_tmp;
-    HIM_CHECK(occ.reserve(sizeof(uint32_t) * std::max<uint64_t>(total, 1), s));
-    HIM_CHECK(occ2.reserve(sizeof(uint32_t) * std::max<uint64_t>(total, 1), s));
-    HIM_CHECK(seg.reserve(sizeof(uint32_t) * ((size_t)n + 1), s));
+    const uint32_t b = n > 1 ? 32u - (uint32_t)__builtin_clz(n - 1u) : 1u;   // bits of a vertex id
+    DevBuf occ, occ2, tmp, head, hscan, run_start, key2, key2s, val, flag, fscan, scan_tmp;
+    HIM_CHECK(occ.reserve(sizeof(uint64_t) * std::max<uint64_t>(total, 1), s));
+    HIM_CHECK(occ2.reserve(sizeof(uint64_t) * std::max<uint64_t>(total, 1), s));
     if (nnz)
-        hipLaunchKernelGGL(k_occ_emit, dim3(grid_for(nnz)), dim3(kBlock), 0, s, n, nnz, g->v_off.as<uint32_t>(),
+        hipLaunchKernelGGL(k_occ_emit, dim3(grid_for(nnz)), dim3(kBlock), 0, s, n, nnz, b, g->v_off.as<uint32_t>(),
                            g->v_he.as<uint32_t>(), g->he_off.as<uint32_t>(), g->he_mem.as<uint32_t>(),
-                           g->chan.as<unsigned long long>(), occ.as<uint32_t>());
-    hipLaunchKernelGGL(k_seg_begin, dim3(grid_for((uint64_t)n + 1)), dim3(kBlock), 0, s, n, g->v_off.as<uint32_t>(),
-                       g->chan.as<unsigned long long>(), seg.as<uint32_t>());
+                           g->chan.as<unsigned long long>(), occ.as<unsigned long long>());
     HIM_HIP(hipGetLastError());
-    const uint32_t id_bits = n > 1 ? 32u - (uint32_t)__builtin_clz(n - 1u) : 1u;
-    // 2. each vertex's occurrences by u
+    // 2. all occurrences by (v, u)
     size_t tbytes = 0;
-    HIM_HIP(rocprim::segmented_radix_sort_keys(nullptr, tbytes, occ.as<uint32_t>(), occ2.as<uint32_t>(),
-                                               (unsigned int)total, n, seg.as<uint32_t>(), seg.as<uint32_t>() + 1, 0u,
-                                               id_bits, s));
+    HIM_HIP(rocprim::radix_sort_keys(nullptr, tbytes, occ.as<unsigned long long>(), occ2.as<unsigned long long>(),
+                                     (size_t)total, 0u, 2u * b, s));
     HIM_CHECK(tmp.reserve(std::max<size_t>(tbytes, 1), s));
     if (total)
-        HIM_HIP(rocprim::segmented_radix_sort_keys(tmp.ptr, tbytes, occ.as<uint32_t>(), occ2.as<uint32_t>(),
-                                                   (unsigned int)total, n, seg.as<uint32_t>(), seg.as<uint32_t>() + 1,
-                                                   0u, id_bits, s));
-    // 3. distinct co-members and their weights
+        HIM_HIP(rocprim::radix_sort_keys(tmp.ptr, tbytes, occ.as<unsigned long long>(), occ2.as<unsigned long long>(),
+                                         (size_t)total, 0u, 2u * b, s));
+    // 3. distinct pairs and their weights (occ is free again: it takes the
+    // distinct keys)
     HIM_CHECK(head.reserve(sizeof(uint32_t) * std::max<uint64_t>(total, 1), s));
     HIM_CHECK(hscan.reserve(sizeof(uint64_t) * (total + 1), s));
     HIM_CHECK(run_start.reserve(sizeof(uint32_t) * std::max<uint64_t>(uniq, 1), s));
+    HIM_CHECK(key2.reserve(sizeof(uint64_t) * std::max<uint64_t>(uniq, 1), s));
+    HIM_CHECK(key2s.reserve(sizeof(uint64_t) * std::max<uint64_t>(uniq, 1), s));
+    HIM_CHECK(val.reserve(sizeof(uint32_t) * std::max<uint64_t>(uniq, 1), s));
     HIM_CHECK(g->lay_nb.reserve(sizeof(uint32_t) * std::max<uint64_t>(uniq, 1), s));
-    HIM_CHECK(key.reserve(sizeof(uint32_t) * std::max<uint64_t>(uniq, 1), s));
-    HIM_CHECK(key2.reserve(sizeof(uint32_t) * std::max<uint64_t>(uniq, 1), s));
     if (total) {
-        hipLaunchKernelGGL(k_heads, dim3(grid_for(total)), dim3(kBlock), 0, s, n, total, seg.as<uint32_t>(),
-                           occ2.as<uint32_t>(), head.as<uint32_t>());
+        hipLaunchKernelGGL(k_heads, dim3(grid_for(total)), dim3(kBlock), 0, s, total, occ2.as<unsigned long long>(),
+                           head.as<uint32_t>());
         HIM_CHECK(scan_u32_to_u64(head.as<uint32_t>(), hscan.as<uint64_t>(), total, 0, scan_tmp, s));
-        // the sorted occurrences are no longer needed: occ holds the distinct u
-        hipLaunchKernelGGL(k_runs, dim3(grid_for(total)), dim3(kBlock), 0, s, total, occ2.as<uint32_t>(),
-                           head.as<uint32_t>(), hscan.as<unsigned long long>(), occ.as<uint32_t>(),
-                           run_start.as<uint32_t>());
-        hipLaunchKernelGGL(k_wkeys, dim3(grid_for(uniq)), dim3(kBlock), 0, s, uniq, total, run_start.as<uint32_t>(),
-                           key.as<uint32_t>());
+    } else {
+        HIM_HIP(hipMemsetAsync(hscan.ptr, 0, sizeof(uint64_t), s));
     }
     uint64_t uniq_dev = 0;
     HIM_HIP(hipMemcpyAsync(&uniq_dev, hscan.as<uint64_t>() + total, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
@@ -185,40 +168,40 @@ int layers_build_device(hyperim_graph g, uint32_t lmax, hipStream_t s) {
         set_error_detail("stratified-setting tables: distinct co-members disagree with deg");
         return HYPERIM_EHIP;
     }
+    if (total) {
+        hipLaunchKernelGGL(k_runs, dim3(grid_for(total)), dim3(kBlock), 0, s, total, occ2.as<unsigned long long>(),
+                           head.as<uint32_t>(), hscan.as<unsigned long long>(), occ.as<unsigned long long>(),
+                           run_start.as<uint32_t>());
+        hipLaunchKernelGGL(k_wkeys, dim3(grid_for(uniq)), dim3(kBlock), 0, s, uniq, total, b,
+                           occ.as<unsigned long long>(), run_start.as<uint32_t>(), key2.as<unsigned long long>(),
+                           val.as<uint32_t>());
+    }
     // per-vertex ranges of the distinct co-members (deg prefix) and of the
     // layers (l prefix)
     HIM_CHECK(g->lay_nb_off.reserve(sizeof(uint64_t) * ((size_t)n + 1), s));
     HIM_CHECK(g->lay_ly_off.reserve(sizeof(uint64_t) * ((size_t)n + 1), s));
     HIM_CHECK(scan_u32_to_u64(g->deg.as<uint32_t>(), g->lay_nb_off.as<uint64_t>(), n, 0, scan_tmp, s));
     HIM_CHECK(scan_u32_to_u64(g->l.as<uint32_t>(), g->lay_ly_off.as<uint64_t>(), n, 0, scan_tmp, s));
-    // 32-bit copy of the co-member ranges for the segment sort
-    HIM_CHECK(nbo.reserve(sizeof(uint32_t) * ((size_t)n + 1), s));
-    std::vector<uint64_t> h64((size_t)n + 1);
-    std::vector<uint32_t> h32((size_t)n + 1);
-    HIM_HIP(hipMemcpyAsync(h64.data(), g->lay_nb_off.ptr, sizeof(uint64_t) * h64.size(), hipMemcpyDeviceToHost, s));
-    HIM_HIP(hipStreamSynchronize(s));
-    for (size_t v = 0; v <= n; ++v) h32[v] = (uint32_t)h64[v];
-    HIM_HIP(hipMemcpyAsync(nbo.ptr, h32.data(), sizeof(uint32_t) * h32.size(), hipMemcpyHostToDevice, s));
-    // 4. layers: stable sort of each vertex's distinct co-members by ~w
+    // 4. layers: stable sort of the distinct pairs by v << 32 | ~w, values u
     tbytes = 0;
-    HIM_HIP(rocprim::segmented_radix_sort_pairs(nullptr, tbytes, key.as<uint32_t>(), key2.as<uint32_t>(),
-                                                occ.as<uint32_t>(), g->lay_nb.as<uint32_t>(), (unsigned int)uniq, n,
-                                                nbo.as<uint32_t>(), nbo.as<uint32_t>() + 1, 0u, 32u, s));
+    HIM_HIP(rocprim::radix_sort_pairs(nullptr, tbytes, key2.as<unsigned long long>(), key2s.as<unsigned long long>(),
+                                      val.as<uint32_t>(), g->lay_nb.as<uint32_t>(), (size_t)uniq, 0u, 32u + b, s));
     HIM_CHECK(tmp.reserve(std::max<size_t>(tbytes, 1), s));
     if (uniq)
-        HIM_HIP(rocprim::segmented_radix_sort_pairs(tmp.ptr, tbytes, key.as<uint32_t>(), key2.as<uint32_t>(),
-                                                    occ.as<uint32_t>(), g->lay_nb.as<uint32_t>(), (unsigned int)uniq,
-                                                    n, nbo.as<uint32_t>(), nbo.as<uint32_t>() + 1, 0u, 32u, s));
+        HIM_HIP(rocprim::radix_sort_pairs(tmp.ptr, tbytes, key2.as<unsigned long long>(),
+                                          key2s.as<unsigned long long>(), val.as<uint32_t>(),
+                                          g->lay_nb.as<uint32_t>(), (size_t)uniq, 0u, 32u + b, s));
     // 5. layer ends
     HIM_CHECK(flag.reserve(sizeof(uint32_t) * std::max<uint64_t>(uniq, 1), s));
     HIM_CHECK(fscan.reserve(sizeof(uint64_t) * (uniq + 1), s));
     HIM_CHECK(g->lay_ly_end.reserve(sizeof(uint32_t) * std::max<uint64_t>(nlay, 1), s));
     if (uniq) {
-        hipLaunchKernelGGL(k_layer_flags, dim3(grid_for(uniq)), dim3(kBlock), 0, s, n, uniq, nbo.as<uint32_t>(),
-                           key2.as<uint32_t>(), flag.as<uint32_t>());
+        hipLaunchKernelGGL(k_layer_flags, dim3(grid_for(uniq)), dim3(kBlock), 0, s, uniq,
+                           key2s.as<unsigned long long>(), flag.as<uint32_t>());
         HIM_CHECK(scan_u32_to_u64(flag.as<uint32_t>(), fscan.as<uint64_t>(), uniq, 0, scan_tmp, s));
-        hipLaunchKernelGGL(k_layer_ends, dim3(grid_for(uniq)), dim3(kBlock), 0, s, n, uniq, nbo.as<uint32_t>(),
-                           flag.as<uint32_t>(), fscan.as<unsigned long long>(), g->lay_ly_end.as<uint32_t>());
+        hipLaunchKernelGGL(k_layer_ends, dim3(grid_for(uniq)), dim3(kBlock), 0, s, uniq,
+                           key2s.as<unsigned long long>(), flag.as<uint32_t>(), fscan.as<unsigned long long>(),
+                           g->lay_nb_off.as<unsigned long long>(), g->lay_ly_end.as<uint32_t>());
     }
     HIM_HIP(hipGetLastError());
     // host tables: ln(l + 1) for l <= lmax, and e^-P(L_i) with
