@@ -138,7 +138,9 @@ struct GreedyParams {
     uint32_t k, tk_levels, tk_shift[3];
 };
 
-constexpr uint32_t kTkBins = 2048;
+constexpr uint32_t kTkBins = 4096;
+constexpr uint32_t kTkBits = 12;   // log2 kTkBins
+static_assert(kTkBins == 1u << kTkBits, "bins");
 
 // Equation (8)'s term for one greedy prefix: the sum of the k largest
 // counts, by value-range histograms over the counts' bits.  At `level` a
@@ -547,9 +549,9 @@ int greedy_device(GreedyWorkspace &w, hyperim_graph g, hyperim_pool p, uint64_t 
     uint32_t levels = 0;
     if (ub_host) {
         const uint32_t bits = theta ? 64u - (uint32_t)__builtin_clzll(theta) : 1u;
-        levels = bits <= 11 ? 1u : bits <= 22 ? 2u : 3u;
-        hp.tk_shift[0] = levels == 1 ? 0u : bits - 11u;
-        hp.tk_shift[1] = levels == 2 ? 0u : bits - 22u;
+        levels = bits <= kTkBits ? 1u : bits <= 2 * kTkBits ? 2u : 3u;
+        hp.tk_shift[0] = levels == 1 ? 0u : bits - kTkBits;
+        hp.tk_shift[1] = levels == 2 ? 0u : bits - 2 * kTkBits;
         hp.tk_shift[2] = 0u;
         const size_t tk_bytes = kTkBins * (sizeof(uint32_t) + sizeof(unsigned long long)) +
                                 3 * sizeof(unsigned long long) + sizeof(unsigned long long) * ((size_t)k + 1) +

@@ -56,6 +56,7 @@ CASES = {
     "small_random": lambda: hypergen.tiny_hypergraph(51, 300, 400, 2, 9, allow_singletons=True),
     "star_all_strategies": lambda: _star_layers([1, 3, 20, 25, 40, 200], extra=3),
     "pair": lambda: hypergen.from_lists(3, [[0, 1]]),
+    "one_vertex": lambda: hypergen.from_lists(1, [[0], []]),
     "chain_40000": lambda: _chain_of_cliques(),
 }
 

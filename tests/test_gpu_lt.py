@@ -44,6 +44,7 @@ CASES = {
     "singletons_wc": lambda: (hypergen.tiny_hypergraph(5, 300, 500, 1, 8, allow_singletons=True), LT_WC, 0.0),
     "p_one_star": lambda: (hypergen.from_lists(7, [[0, i] for i in range(1, 6)] + [[6]]), LT_CONST, 1.0),
     "p_zero": lambda: (hypergen.tiny_hypergraph(4, 50, 40), LT_CONST, 0.0),
+    "one_vertex": lambda: (hypergen.from_lists(1, [[0], []]), LT_WC, 0.0),
     "path_40000": lambda: (_path(40000), LT_WC, 0.0),
     # a hub in 9999 hyperedges: the channel search takes several 64-way rounds
     "hub_lt": lambda: (hypergen.from_lists(10001, [[0, i, i + 1] for i in range(1, 10000)]), LT_WC, 0.0),
