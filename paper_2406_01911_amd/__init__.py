@@ -220,7 +220,9 @@ class Graph:
 
 
 def build_graph(n: int, he_off, he_mem, model: int, p: float = 0.0, stream=None) -> Graph:
-    """hyperim_build_graph: he_off/he_mem as numpy (host) or torch cuda tensors (device)."""
+    """hyperim_build_graph: he_off/he_mem as numpy (host) or torch cuda tensors (device).
+    model: MODEL_CONST / MODEL_WC (independent cascade), MODEL_LT_CONST / MODEL_LT_WC
+    (linear threshold), MODEL_LAYERED (stratified setting; p ignored)."""
     load_library()
     on_dev = isinstance(he_off, torch.Tensor) and he_off.is_cuda
     if not on_dev:
