@@ -12,7 +12,8 @@ Functions (each cites the passage of the paper it follows in the C source):
                               (model 0/1: IC with constant p / weighted cascade;
                               2/3: the linear-threshold model, live-edge form,
                               with the same thresholds; 4: the stratified
-                              setting of Section 3.1.1)
+                              setting of Section 3.1.1; 5/6: IC with constant
+                              p / weighted cascade drawn by geometric gaps)
   Graph.layers()              stratified setting: A(v) by layers
   Graph.stratify()            sample-set layers (Section 3.1.1), strata, P
   Graph.root(...)             stratified root of an RR id
@@ -100,6 +101,8 @@ def lib():
         L.orc_sigma_upper_cov.argtypes = [C.c_double] * 4
         L.orc_sigma_upper_cov.restype = C.c_double
         L.orc_layers_export.argtypes = [vp, vp, vp, vp, vp]
+        L.orc_gap_draw.argtypes = [C.c_double, C.c_uint32, C.c_uint32]
+        L.orc_gap_draw.restype = C.c_uint32
         _lib = L
     return _lib
 
@@ -182,6 +185,12 @@ def upper_eq8(n, off, mem, seeds, theta=None) -> int:
     theta = len(off) - 1 if theta is None else theta
     return int(lib().orc_upper_eq8(n, theta, _p(off), _p(mem if mem.size else np.zeros(1, np.uint32)),
                                    len(seeds), _p(seeds)))
+
+
+def gap_draw(q: float, x: int, G: int) -> int:
+    """Geometric-gap sampler: the gap drawn from word x with G positions left
+    (q = 1 - p)."""
+    return int(lib().orc_gap_draw(q, x, G))
 
 
 def greedy(n, off: np.ndarray, mem: np.ndarray, k: int, theta: int | None = None):

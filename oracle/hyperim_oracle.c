@@ -19,6 +19,10 @@
  *     P(L_i) = 1 / (i ln(l_v + 1)); an RR set draws per popped vertex and
  *     layer a count (Binomial for layers of at most 20 members, Poisson
  *     above) and selects that many members without replacement;
+ *   - independent cascade drawn by geometric gaps (models 5 and 6): the same
+ *     channels and probabilities as models 0 and 1, but the live positions
+ *     of each stream (RR id, hyperedge, target) are drawn as gaps of dead
+ *     positions instead of one coin per position;
  *   - the linear-threshold model (Section 2.1, "Cascade models", LT) in its
  *     live-edge form: every vertex v keeps at most one of its channels, each
  *     with weight W_v (the per-channel probability, capped so that the
@@ -127,6 +131,7 @@ typedef struct orc_graph {
     uint64_t *c;                   /* sum over he containing v of |he|-1    */
     int lt;                        /* linear-threshold model (else IC)      */
     int layered;                   /* stratified-setting model (model 4)    */
+    int gaps;                      /* IC drawn by geometric gaps (5, 6)     */
     /* stratified setting: per vertex v the members of A(v), layer by layer
      * (layer 1 = largest w(v,u)), ascending ids within a layer:
      * nb[nb_off[v] .. nb_off[v+1]); layer i (1-based) of v ends at
@@ -169,8 +174,8 @@ int orc_graph_new(uint32_t n, uint32_t m, const uint32_t *he_off, const uint32_t
                   uint32_t model, float p, orc_graph **out)
 {
     *out = NULL;
-    if (model > 4u) return ORC_EINVAL;
-    if ((model == 0u || model == 2u) && (isnan(p) || p < 0.0f)) return ORC_EINVAL;
+    if (model > 6u) return ORC_EINVAL;
+    if ((model == 0u || model == 2u || model == 5u) && (isnan(p) || p < 0.0f)) return ORC_EINVAL;
     if (he_off[0] != 0u) return ORC_EINVAL;
     for (uint32_t e = 0; e < m; ++e)
         if (he_off[e + 1] < he_off[e]) return ORC_EINVAL;
@@ -193,6 +198,7 @@ int orc_graph_new(uint32_t n, uint32_t m, const uint32_t *he_off, const uint32_t
     g->n = n; g->m = m; g->nnz = nnz;
     g->lt = model == 2u || model == 3u;
     g->layered = model == 4u;
+    g->gaps = model == 5u || model == 6u;
     g->he_off = (uint32_t *)malloc(sizeof(uint32_t) * (m + 1));
     g->he_mem = (uint32_t *)malloc(sizeof(uint32_t) * (nnz ? nnz : 1));
     g->v_off = (uint32_t *)calloc(n + 1, sizeof(uint32_t));
@@ -221,7 +227,7 @@ int orc_graph_new(uint32_t n, uint32_t m, const uint32_t *he_off, const uint32_t
 
     for (uint32_t v = 0; v < n; ++v) {
         float pv;
-        if (model == 0u || model == 2u) pv = p;
+        if (model == 0u || model == 2u || model == 5u) pv = p;
         else pv = g->c[v] ? (float)(1.0 / (double)g->c[v]) : 0.0f;   /* model 4 keeps these unused */
         g->thr[v] = orc_threshold(pv);
     }
@@ -702,9 +708,95 @@ static uint32_t orc_layered_into(const orc_graph *g, uint64_t seed, uint32_t ins
     return tail;
 }
 
+/* Independent cascade by geometric gaps.  The stream of (RR id j, hyperedge
+ * he, target v) is he's positions 0 .. |he|-1 in stored order, each live with
+ * p_v = thr[v] / 2^32 (2^32 for thr = ALWAYS); a live position holding v
+ * itself is no channel and is dropped, so every channel u -> v is live with
+ * p_v independently, as under coins.  The gaps -- dead positions before the
+ * next live one, Geometric(p_v) -- come from the words of the Philox blocks
+ * at counter (j_lo, he, v, pool<<31 | j_hi<<24 | r/4), word r mod 4 for gap r.
+ *
+ * Gap from word x with G positions left: t = (2^32 - x) / 2^32 in (0, 1]; the
+ * gap is the largest g <= G with Q(g) >= t, found by descending over the bits
+ * i = b-1 .. 0 of G (b bits): take bit i when g + 2^i <= G and
+ * acc * S_i >= t, then acc = acc * S_i, where S_0 = q = 1 - p_v and
+ * S_{i+1} = S_i * S_i (Q(g) is q^g up to rounding).  g = G means no live
+ * position is left. */
+static uint32_t orc_gap(double q, uint32_t x, uint32_t G)
+{
+    double t = (double)((1ull << 32) - (uint64_t)x) * 0x1.0p-32;
+    uint32_t b = 0;
+    while (b < 32u && (G >> b) != 0u) ++b;
+    uint32_t g = 0;
+    double acc = 1.0;
+    for (int i = (int)b - 1; i >= 0; --i) {
+        double S = q;
+        for (int k = 0; k < i; ++k) S = S * S;
+        if ((uint64_t)g + (1ull << i) <= (uint64_t)G && acc * S >= t) {
+            acc = acc * S;
+            g += 1u << i;
+        }
+    }
+    return g;
+}
+
+uint32_t orc_gap_draw(double q, uint32_t x, uint32_t G) { return orc_gap(q, x, G); }
+
+static uint32_t orc_gaps_into(const orc_graph *g, uint64_t seed, uint32_t instance, uint32_t pool,
+                              uint64_t j, uint32_t root, orc_scratch *s, uint32_t *out)
+{
+    uint32_t head = 0, tail = 0;
+    s->queue[tail++] = root;
+    s->inR[root] = 1;
+    while (head < tail) {
+        uint32_t v = s->queue[head++];
+        uint32_t thr = g->thr[v];
+        if (thr == 0u) continue;
+        double p = thr == ORC_ALWAYS ? 1.0 : (double)thr * 0x1.0p-32;
+        double q = 1.0 - p;
+        for (uint32_t e = g->v_off[v]; e < g->v_off[v + 1]; ++e) {
+            uint32_t he = g->v_he[e];
+            uint32_t base = g->he_off[he];
+            uint32_t size = g->he_off[he + 1] - base;
+            uint32_t cur = 0, r = 0, w[4] = {0, 0, 0, 0};
+            while (cur < size) {
+                if ((r & 3u) == 0u) {
+                    uint32_t ctr[4], key[2];
+                    ctr[0] = (uint32_t)j;
+                    ctr[1] = he;
+                    ctr[2] = v;
+                    ctr[3] = (pool << 31) | ((uint32_t)(j >> 32) << 24) | (r >> 2);
+                    key[0] = (uint32_t)seed;
+                    key[1] = instance;
+                    orc_philox4x32_10(ctr, key, w);
+                }
+                uint32_t x = w[r & 3u];
+                ++r;
+                uint32_t G = size - cur;
+                uint32_t gap = orc_gap(q, x, G);
+                if (gap == G) break;
+                uint32_t pos = cur + gap;
+                uint32_t u = g->he_mem[base + pos];
+                if (u != v && !s->inR[u]) {
+                    s->inR[u] = 1;
+                    s->queue[tail++] = u;
+                }
+                cur = pos + 1;
+            }
+        }
+    }
+    for (uint32_t i = 0; i < tail; ++i) {
+        out[i] = s->queue[i];
+        s->inR[s->queue[i]] = 0;
+    }
+    qsort(out, tail, sizeof(uint32_t), cmp_u32);
+    return tail;
+}
+
 static uint32_t orc_set_into(const orc_graph *g, uint64_t seed, uint32_t instance, uint32_t pool,
                              uint64_t j, uint32_t root, orc_scratch *s, uint32_t *out)
 {
+    if (g->gaps) return orc_gaps_into(g, seed, instance, pool, j, root, s, out);
     if (g->layered) return orc_layered_into(g, seed, instance, pool, j, root, s, out);
     return g->lt ? orc_lt_into(g, seed, instance, pool, j, root, s, out)
                  : orc_rr_into(g, seed, instance, pool, j, root, s, out);

@@ -78,7 +78,7 @@ def test_weighted_cascade_threshold_exact_rational():
     ([[0, 1, 0]], 3, 0, 0.1),           # duplicate member
     ([[0, 1]], 3, 0, float("nan")),     # NaN p
     ([[0, 1]], 3, 0, -0.5),             # negative p
-    ([[0, 1]], 3, 5, 0.1),              # unknown model
+    ([[0, 1]], 3, 7, 0.1),              # unknown model
     ([[0, 1]], 3, 2, float("nan")),     # NaN p under LT
 ])
 def test_invalid_inputs_rejected(edges, n, model, p):
