@@ -50,9 +50,15 @@ WORKLOAD_TEXT = {
     "large_layered": "the large hypergraph (|V|=1e6 |HE|=2e6 sizes power-law(2.2) on [2,200], Zipf(1.1) members) "
                      "under the stratified setting (per-layer probabilities 1/(i ln(l+1)) split over the layer), "
                      "k=100 eps=0.1 ell=1",
+    "tiny_gaps": "the tiny workload (IC p=0.05) with live channels drawn by geometric gaps, k=10 eps=0.5 ell=1",
+    "mid_gaps": "the mid hypergraph (|V|=1e5 |HE|=2e5 sizes power-law(2.5) on [2,50], Zipf(1.0) members), "
+                "weighted cascade with live channels drawn by geometric gaps, k=50 eps=0.1 ell=1",
+    "large_gaps": "the large hypergraph (|V|=1e6 |HE|=2e6 sizes power-law(2.2) on [2,200], Zipf(1.1) members), "
+                  "IC p=0.01 with live channels drawn by geometric gaps, k=100 eps=0.1 ell=1",
 }
 LT_WORKLOADS = ("tiny_lt", "mid_lt", "large_lt")
 LAYERED_WORKLOADS = ("tiny_layered", "mid_layered", "large_layered")
+GAPS_WORKLOADS = ("tiny_gaps", "mid_gaps", "large_gaps")
 
 
 def parse():
@@ -140,7 +146,8 @@ def cpu_baseline(hg, w, seconds: float, workload: str, sets_needed: int = 0):
     threads = max(1, min(threads, os.cpu_count() or 1))
     o = oracle.Graph(hg, w.model, w.p)
     o.stratify()
-    done, chunk, t0 = 0, 2 * threads if workload == "large" else 512, time.perf_counter()
+    supercritical = workload in ("large", "large_gaps")   # sets of ~1e5 members
+    done, chunk, t0 = 0, 2 * threads if supercritical else 512, time.perf_counter()
     while True:
         o.generate(w.philox_seed, 0, 0, done, done + chunk, nthreads=threads)
         done += chunk
@@ -150,7 +157,7 @@ def cpu_baseline(hg, w, seconds: float, workload: str, sets_needed: int = 0):
         if el < seconds / 4:
             chunk *= 2
     what = (f"RR ids [0, {done}) of pool R1 of the same workload, {el:.1f} s wall, {threads} threads over ids")
-    if workload == "large":
+    if supercritical:
         what += (f"; an extrapolation: the query draws {sets_needed} sets (both pools), the sample covers "
                  f"the first ids of pool R1")
     return {"value": done / el, "unit": "RR sets/s", "cores": threads, "kind": "oracle", "cpu": cpu_model(),
@@ -305,12 +312,14 @@ def main():
     per_s = args.steps / elapsed
     lt = args.workload in LT_WORKLOADS
     layered = args.workload in LAYERED_WORKLOADS
+    gaps = args.workload in GAPS_WORKLOADS
     kernel_bytes = mtot["bytes_light"] + mtot["bytes_heavy"] + mtot["bytes_bundled"]
     # the kernels count the bytes of every expansion they perform; the pools'
     # final prefixes can only hold fewer (sets generated ahead of a round that
     # was not reached are spent work).  A linear-threshold walk reads one
-    # channel per step: its algorithmic bytes are the walk kernel's own count.
-    alg_bytes = kernel_bytes if (lt or layered) else mtot["alg_bytes"]
+    # channel per step, and the gap sampler reads only the live positions of a
+    # hyperedge: their algorithmic bytes are the kernels' own count.
+    alg_bytes = kernel_bytes if (lt or layered or gaps) else mtot["alg_bytes"]
     assert kernel_bytes >= alg_bytes, (kernel_bytes, alg_bytes)
     # dominant expansion kernel: the largest event-timed share in the
     # instrumented step
@@ -383,7 +392,7 @@ def main():
                    "parallelism": "single-gpu"},
         # channel-model figures (IC); the other models draw per step or per layer
         "incidences_per_s": None if (lt or layered) else mtot["incidences"] * per_s,
-        "coins_per_s": mtot["philox_drawn"] * per_s if (lt or layered) else mtot["coins"] * per_s,
+        "coins_per_s": mtot["philox_drawn"] * per_s if (lt or layered or gaps) else mtot["coins"] * per_s,
         "philox_blocks_per_s": {"drawn": mtot["philox_drawn"] * per_s, "per_set_traversal": mtot["philox_alg"] * per_s},
         "time_to_seed_set_ms": ms_per_step,
         "theta": [r["theta"] for r in last] if len(last) > 1 else last[0]["theta"],

@@ -32,6 +32,8 @@ MODEL_WC = 1      # weighted cascade: p_v = 1 / (weighted clique in-degree of v)
 MODEL_LT_CONST = 2   # linear threshold, channel weight p
 MODEL_LT_WC = 3      # linear threshold, channel weight 1 / (weighted clique in-degree of v)
 MODEL_LAYERED = 4    # stratified setting: per-layer probabilities of the sample sets
+MODEL_GAPS_CONST = 5   # MODEL_CONST's cascade, live channels found by geometric gaps
+MODEL_GAPS_WC = 6      # MODEL_WC's cascade, live channels found by geometric gaps
 
 
 @dataclasses.dataclass
@@ -61,7 +63,7 @@ class Workload:
     m: int
     sizes: tuple            # ("uniform", lo, hi) or ("powerlaw", gamma, lo, hi)
     members: tuple          # ("uniform",) or ("zipf", s)
-    model: int              # MODEL_CONST, MODEL_WC, MODEL_LT_CONST, MODEL_LT_WC or MODEL_LAYERED
+    model: int              # MODEL_CONST .. MODEL_GAPS_WC
     p: float                # used when model == MODEL_CONST
     k: int
     eps: float
@@ -98,6 +100,14 @@ WORKLOADS = {
                             MODEL_LAYERED, 0.0, 50, 0.1, 1.0, gen_seed=1),
     "large_layered": Workload("large_layered", 1_000_000, 2_000_000, ("powerlaw", 2.2, 2, 200), ("zipf", 1.1),
                               MODEL_LAYERED, 0.0, 100, 0.1, 1.0, gen_seed=2),
+    # ... and the independent cascade of tiny / mid / large with its live
+    # channels drawn by geometric gaps instead of one coin per channel
+    "tiny_gaps": Workload("tiny_gaps", 1_000, 2_000, ("uniform", 2, 6), ("uniform",),
+                          MODEL_GAPS_CONST, 0.05, 10, 0.5, 1.0, gen_seed=0),
+    "mid_gaps": Workload("mid_gaps", 100_000, 200_000, ("powerlaw", 2.5, 2, 50), ("zipf", 1.0),
+                         MODEL_GAPS_WC, 0.0, 50, 0.1, 1.0, gen_seed=1),
+    "large_gaps": Workload("large_gaps", 1_000_000, 2_000_000, ("powerlaw", 2.2, 2, 200), ("zipf", 1.1),
+                           MODEL_GAPS_CONST, 0.01, 100, 0.1, 1.0, gen_seed=2),
 }
 
 

@@ -46,6 +46,8 @@ extern "C" {
 #define HYPERIM_MODEL_LT_CONST 2u /* linear threshold, channel weight p         */
 #define HYPERIM_MODEL_LT_WC 3u  /* linear threshold, channel weight 1 / c(v)    */
 #define HYPERIM_MODEL_LAYERED 4u /* stratified setting of Section 3.1.1         */
+#define HYPERIM_MODEL_GAPS_CONST 5u /* IC with constant p, by geometric gaps    */
+#define HYPERIM_MODEL_GAPS_WC 6u /* weighted-cascade IC, by geometric gaps      */
 #define HYPERIM_NSTRATA 8u
 
 typedef struct hyperim_graph_s *hyperim_graph;
@@ -86,7 +88,21 @@ typedef struct hyperim_session_s *hyperim_session;
  * (p / q) from q^n, and prob_{h+1} = (prob_h P) / (h + 1) from e^-P; the
  * following words x pick, h times, index floor(x (n - r) / 2^32) among the
  * layer's members not picked yet (ascending).  Picked members outside the
- * set join it.  ln and exp come from the host's C library. */
+ * set join it.  ln and exp come from the host's C library.
+ *
+ * Independent cascade drawn by geometric gaps, HYPERIM_MODEL_GAPS_CONST and
+ * HYPERIM_MODEL_GAPS_WC (p_v as for the two IC models): the same cascade, with
+ * the live positions of each stream (RR id j, hyperedge he, target v) -- he's
+ * member positions in the caller's order, each live with p_v, a live
+ * position holding v itself ignored -- found by skipping over the dead ones.
+ * Gap r of the stream (the dead positions before the next live one, G
+ * positions left) comes from word r mod 4 of the Philox block at counter
+ * (j_lo, he, v, pool << 31 | j_hi << 24 | r / 4): with t = (2^32 - x) / 2^32
+ * for word x, q = 1 - p_v and S_0 = q, S_{i+1} = S_i * S_i, the gap is built
+ * bit by bit from the top bit of G, taking bit i when the gap stays <= G and
+ * acc * S_i >= t (then acc *= S_i; acc starts at 1), in IEEE double; a gap of
+ * G ends the stream.  Sets are not equal to the coin models' sets for the
+ * same seed (different random numbers), but have the same distribution. */
 typedef struct {
     uint32_t model;
     float p;

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libhyperim.so")
 OK, EINVAL, ENOMEM, ECAPACITY, ESTATE, EHIP = 0, -1, -2, -3, -4, -5
 PENDING = 1
 MODEL_CONST, MODEL_WC, MODEL_LT_CONST, MODEL_LT_WC, MODEL_LAYERED = 0, 1, 2, 3, 4
+MODEL_GAPS_CONST, MODEL_GAPS_WC = 5, 6
 NSTRATA = 8
 FLAG_INCIDENCES = 1
 FLAG_KERNEL_TIMES = 2
@@ -222,7 +223,9 @@ class Graph:
 def build_graph(n: int, he_off, he_mem, model: int, p: float = 0.0, stream=None) -> Graph:
     """hyperim_build_graph: he_off/he_mem as numpy (host) or torch cuda tensors (device).
     model: MODEL_CONST / MODEL_WC (independent cascade), MODEL_LT_CONST / MODEL_LT_WC
-    (linear threshold), MODEL_LAYERED (stratified setting; p ignored)."""
+    (linear threshold), MODEL_LAYERED (stratified setting; p ignored),
+    MODEL_GAPS_CONST / MODEL_GAPS_WC (independent cascade with live channels
+    drawn by geometric gaps)."""
     load_library()
     on_dev = isinstance(he_off, torch.Tensor) and he_off.is_cuda
     if not on_dev:

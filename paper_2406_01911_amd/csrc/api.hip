@@ -312,8 +312,9 @@ int hyperim_build_graph(uint32_t n, uint32_t m, const uint32_t *he_off, const ui
         set_error_detail("n must be in [1, 2^31], m < 2^32-1, arrays non-null");
         return HYPERIM_EINVAL;
     }
-    if (prob.model > HYPERIM_MODEL_LAYERED ||
-        ((prob.model == HYPERIM_MODEL_CONST || prob.model == HYPERIM_MODEL_LT_CONST) &&
+    if (prob.model > HYPERIM_MODEL_GAPS_WC ||
+        ((prob.model == HYPERIM_MODEL_CONST || prob.model == HYPERIM_MODEL_LT_CONST ||
+          prob.model == HYPERIM_MODEL_GAPS_CONST) &&
          (std::isnan(prob.p) || prob.p < 0.0f))) {
         set_error_detail("probability model unknown or p NaN / negative");
         return HYPERIM_EINVAL;

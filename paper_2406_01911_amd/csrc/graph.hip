@@ -270,7 +270,7 @@ __global__ void k_thresholds(uint32_t n, uint32_t model, float p, const uint32_t
     uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= n) return;
     float pv;
-    if (model == HYPERIM_MODEL_CONST || model == HYPERIM_MODEL_LT_CONST) {   // constant p
+    if (model == HYPERIM_MODEL_CONST || model == HYPERIM_MODEL_LT_CONST || model == HYPERIM_MODEL_GAPS_CONST) {
         pv = p;
     } else {
         unsigned long long cv = c[v];

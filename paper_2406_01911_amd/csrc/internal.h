@@ -166,8 +166,11 @@ struct hyperim_graph_s {
     hyperim_prob prob{};
     bool lt() const { return prob.model == HYPERIM_MODEL_LT_CONST || prob.model == HYPERIM_MODEL_LT_WC; }
     bool layered() const { return prob.model == HYPERIM_MODEL_LAYERED; }   // stratified setting
-    // RR-set kernel family: 0 independent cascade, 1 linear threshold, 2 stratified setting
-    int kind() const { return layered() ? 2 : lt() ? 1 : 0; }
+    // independent cascade drawn by geometric gaps
+    bool gaps() const { return prob.model == HYPERIM_MODEL_GAPS_CONST || prob.model == HYPERIM_MODEL_GAPS_WC; }
+    // RR-set kernel family: 0 independent cascade by coins, 1 linear
+    // threshold, 2 stratified setting, 3 independent cascade by gaps
+    int kind() const { return gaps() ? 3 : layered() ? 2 : lt() ? 1 : 0; }
     // weight = d(v) + S(v) incidences read when v is expanded; bytesw = 20 + 12 d(v) + 4 S(v)
     // algorithmic bytes of v as an RR-set member (d = hyperedges of v, S = their total size);
     // phiw = sum over v's hyperedges of ceil(|he| / 4), the Philox blocks of v's expansion

@@ -438,6 +438,58 @@ __device__ __forceinline__ void test_run(const GraphView &G, uint64_t j, uint32_
     }
 }
 
+// Independent cascade drawn by geometric gaps (models HYPERIM_MODEL_GAPS_*):
+// the stream of (RR id j, hyperedge he, target v) is he's positions in
+// stored order, each live with p_v (a live position holding v itself is no
+// channel and is dropped); the gaps of dead positions before the next live
+// one, Geometric(p_v), come from word r mod 4 of the Philox block at
+// counter (j_lo, he, v, pool << 31 | j_hi << 24 | r / 4) for gap r.  A gap
+// drawn from word x with G positions left is the largest g <= G with
+// Q(g) >= t, t = (2^32 - x) / 2^32: a descent over the bits of G, from the
+// top, taking bit i when acc * S_i >= t (then acc = acc * S_i), with
+// S_0 = q = 1 - p_v and S_{i+1} = S_i^2 -- IEEE double products in a fixed
+// order, no logarithm, so any implementation of the same steps draws the
+// same gaps.  g = G: no live position is left in the stream.
+__device__ __forceinline__ uint32_t gap_draw(double q, uint32_t x, uint32_t G) {
+#pragma clang fp contract(off)
+    const double t = (double)((1ull << 32) - (uint64_t)x) * 0x1.0p-32;
+    const uint32_t b = G ? 32u - (uint32_t)__clz(G) : 0u;
+    uint32_t g = 0;
+    double acc = 1.0;
+    for (int i = (int)b - 1; i >= 0; --i) {
+        double S = q;
+        for (int k = 0; k < i; ++k) S = S * S;
+        if ((uint64_t)g + (1ull << i) <= (uint64_t)G && acc * S >= t) {
+            acc = acc * S;
+            g += 1u << i;
+        }
+    }
+    return g;
+}
+
+// One candidate per lane (`live` with member u): marked and appended as in
+// test_run.  Every lane of the wave calls it.
+template <bool kLds, class App, class Lds>
+__device__ __forceinline__ void push_live(uint32_t *bm, Lds &L, uint32_t &nlive, App &app, bool live, uint32_t u) {
+    if (__ballot(live) == 0) return;
+    if constexpr (kLds) {
+        uint32_t fresh = 0;
+        if (live) {
+            const uint32_t bit = 1u << (u & 31);
+            if ((atomicOr(&bm[u >> 5], bit) & bit) == 0u) fresh = 1u;
+        }
+        const uint32_t uu[8] = {u, u, u, u, u, u, u, u};
+        app.push8(fresh, uu);
+    } else {
+        const uint32_t cnt = live ? 1u : 0u;
+        const uint32_t incl = wave_incl_scan(cnt);
+        const uint32_t tot = uni(wave_bcast(incl, kWave - 1));
+        if (nlive + tot > kLiveCap) flush_live(bm, L, nlive, app);
+        if (live) L.live[nlive + incl - cnt] = u;
+        nlive += tot;
+    }
+}
+
 // Levels 2 and 3 of a frontier expansion.  Each lane brings one vertex v with
 // the incidence range [e0, e0 + d) of v_he to expand (d = 0 for none); with
 // kUniform all lanes pass the same v and e0 and d is the wave's incidence
@@ -451,7 +503,7 @@ __device__ __forceinline__ void test_run(const GraphView &G, uint64_t j, uint32_
 // every run is tested by exactly one of them.  Returns the algorithmic
 // bytes of the incidences read (12 per incidence plus 4 per member
 // position), each counted by one wave, wave-uniform.
-template <bool kLds, bool kUniform, class App, class Lds>
+template <bool kLds, bool kUniform, bool kGaps, class App, class Lds>
 __device__ __forceinline__ uint64_t expand(const GraphView &G, Lds &L, uint64_t j, uint32_t pool, uint2 key,
                                            uint32_t *bm, bool prefilter, uint32_t v, uint32_t e0, uint32_t d,
                                            App &app, uint64_t &px, uint32_t w = 0, uint32_t W = 1) {
@@ -499,7 +551,42 @@ __device__ __forceinline__ uint64_t expand(const GraphView &G, Lds &L, uint64_t 
             hb = (uint32_t)bs;
             hs = (uint32_t)(bs >> 32);
             no = th ? (hs + kRun - 1u) / kRun : 0u;   // threshold 0: no channel into vv is live
-            if (sub_w == 0) bytes += 12u + 4u * hs;
+            if (sub_w == 0) bytes += kGaps ? 12u : 12u + 4u * hs;
+        }
+        if constexpr (kGaps) {
+            // level 3 by gaps: each lane walks its own incidence's stream
+            // (only the waves of the first share: every stream once)
+            if (sub_w != 0) continue;
+            bool more = g < D && th != 0u;
+            const double q = 1.0 - (th == kAlways ? 1.0 : (double)th * 0x1.0p-32);
+            uint32_t cur = 0, r = 0;
+            uint4 blk = make_uint4(0u, 0u, 0u, 0u);
+            while (__ballot(more) != 0) {
+                uint32_t u = vv;
+                bool live = false;
+                if (more) {
+                    if ((r & 3u) == 0u) {
+                        blk = philox4x32_10(coin_counter(j, he, vv, pool, r >> 2), key);
+                        ++px;
+                    }
+                    const uint32_t x = (r & 3u) == 0u ? blk.x : (r & 3u) == 1u ? blk.y : (r & 3u) == 2u ? blk.z : blk.w;
+                    ++r;
+                    const uint32_t left = hs - cur;
+                    const uint32_t gap = gap_draw(q, x, left);
+                    if (gap >= left) {
+                        more = false;
+                    } else {
+                        const uint32_t pos = cur + gap;
+                        u = G.he_mem[hb + pos];
+                        bytes += 4u;
+                        live = u != vv;
+                        cur = pos + 1u;
+                        more = cur < hs;
+                    }
+                }
+                push_live<kLds>(bm, L, nlive, app, live, u);
+            }
+            continue;
         }
         // level 3, first pass: run 0 of the lane's own incidence
         if (sub_w == 0)
@@ -554,7 +641,7 @@ __device__ __forceinline__ void record_set(const RRArgs &a, uint64_t idx, uint64
 }
 
 // ---- phase A ---------------------------------------------------------------
-template <bool kLdsBitmap>
+template <bool kLdsBitmap, bool kGaps>
 __global__ __launch_bounds__(kWG) void k_rr_light(RRArgs a) {
     using Lds = typename std::conditional<kLdsBitmap, WaveLdsCore, WaveLds>::type;
     __shared__ Lds lds[kWavesPerWG];
@@ -631,7 +718,7 @@ __global__ __launch_bounds__(kWG) void k_rr_light(RRArgs a) {
             head += nb;
             spent += wave_bcast(wave_incl_scan(d), kWave - 1);
             bytes_done += 20ull * nb;
-            bytes_done += expand<kLdsBitmap, false>(G, L, S.j, S.pool, S.key, bm, false, v, e0, d, app, px);
+            bytes_done += expand<kLdsBitmap, false, kGaps>(G, L, S.j, S.pool, S.key, bm, false, v, e0, d, app, px);
         }
         if (deferred) continue;
         const uint32_t size = app.size;
@@ -1191,6 +1278,7 @@ __global__ __launch_bounds__(kWG) void k_plan(const RRArgs *__restrict__ ap, uin
     if (lane == 0 && taken) atomicAdd(&a.ctr[kPlanned], (unsigned long long)taken);
 }
 
+template <bool kGaps>
 __global__ __launch_bounds__(kWG) void k_expand(const RRArgs *__restrict__ ap, uint32_t parity) {
     const RRArgs a = *ap;
     __shared__ WaveLds lds[kWavesPerWG];
@@ -1233,10 +1321,10 @@ __global__ __launch_bounds__(kWG) void k_expand(const RRArgs *__restrict__ ap, u
                 if (heavy_split(deg, a.chunk).count) deg = 0;   // expanded by its heavy items
             }
             if (w == 0) bytes_done += 20ull * (uint64_t)__popcll(__ballot((raw & kExpanded) == 0u));
-            bytes_done += expand<false, false>(G, L, S.j, S.pool, S.key, bm, prefilter, v, e0, deg, app, px, w, W);
+            bytes_done += expand<false, false, kGaps>(G, L, S.j, S.pool, S.key, bm, prefilter, v, e0, deg, app, px, w, W);
         } else {
             // one heavy vertex: incidences [item.z, item.w) of vertex item.y
-            bytes_done += expand<false, true>(G, L, S.j, S.pool, S.key, bm, prefilter, item.y, item.z,
+            bytes_done += expand<false, true, kGaps>(G, L, S.j, S.pool, S.key, bm, prefilter, item.y, item.z,
                                               item.w - item.z, app, px, w, W);
         }
         // Continuation: when this wave appended at most 64 members, all light
@@ -1261,7 +1349,7 @@ __global__ __launch_bounds__(kWG) void k_expand(const RRArgs *__restrict__ ap, u
             if (lane < cn) list[pos] = v | kExpanded;
             app.count = 0;
             bytes_done += 20ull * cn;
-            bytes_done += expand<false, false>(G, L, S.j, S.pool, S.key, bm, prefilter, v, e0, deg, app, px, 0u, 1u);
+            bytes_done += expand<false, false, kGaps>(G, L, S.j, S.pool, S.key, bm, prefilter, v, e0, deg, app, px, 0u, 1u);
         }
     }
     if (lane == 0 && bytes_done) atomicAdd(&a.ctr[kBytesB], bytes_done);
@@ -2026,9 +2114,9 @@ int slot_layout(uint32_t n_max, SlotLayout *out) {
     int per_cu_lds = 0, per_cu_glb = 0, per_cu_b = 0, cus = 0, dev = 0;
     HIM_HIP(hipGetDevice(&dev));
     HIM_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    HIM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_lds, k_rr_light<true>, kWG, 0));
-    HIM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_glb, k_rr_light<false>, kWG, 0));
-    HIM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_b, k_expand, kWG, 0));
+    HIM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_lds, k_rr_light<true, false>, kWG, 0));
+    HIM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_glb, k_rr_light<false, false>, kWG, 0));
+    HIM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_b, k_expand<false>, kWG, 0));
     const bool lds = n_max <= kLdsBitmapWords * 32u;
     const uint64_t words = ((uint64_t)n_max + 31u) / 32u;
     const uint64_t per_slot = (uint64_t)n_max * 4u + (lds ? 0u : words * 4u);
@@ -2288,7 +2376,7 @@ int captured_batch(RRWorkspace &ws, const uint64_t (&key)[8], Record &&record, h
 template <class Tail>
 int run_launch(RRWorkspace &ws, RRStats &st, const hyperim_tuning &tune, RRArgs &a, const LaunchShape &shape,
                uint32_t grid, uint32_t grid_b, bool expect_defer, bool trace, bool time_kernels, bool graphs,
-               hipStream_t s, Tail &&tail) {
+               bool gaps, hipStream_t s, Tail &&tail) {
     unsigned long long *ctr = a.ctr;
     unsigned long long *h = ws.host;
     // the grid-wide phase reads its arguments from the device
@@ -2302,10 +2390,10 @@ int run_launch(RRWorkspace &ws, RRStats &st, const hyperim_tuning &tune, RRArgs 
     HIM_HIP(hipMemsetAsync(ctr + kDefCount, 0, sizeof(unsigned long long), s));
     HIM_HIP(hipMemcpyAsync(ctr + kFreeNext, h + kHostFreeNext, sizeof(unsigned long long), hipMemcpyHostToDevice, s));
     HIM_CHECK(event_pair(ws));
-    if (shape.lds)
-        hipExtLaunchKernelGGL(k_rr_light<true>, dim3(grid), dim3(kWG), 0, s, ws.events[0], ws.events[1], 0u, a);
-    else
-        hipExtLaunchKernelGGL(k_rr_light<false>, dim3(grid), dim3(kWG), 0, s, ws.events[0], ws.events[1], 0u, a);
+    auto light = shape.lds ? (gaps ? k_rr_light<true, true> : k_rr_light<true, false>)
+                           : (gaps ? k_rr_light<false, true> : k_rr_light<false, false>);
+    auto expand_k = gaps ? k_expand<true> : k_expand<false>;
+    hipExtLaunchKernelGGL(light, dim3(grid), dim3(kWG), 0, s, ws.events[0], ws.events[1], 0u, a);
     HIM_HIP(hipGetLastError());
     st.launches += 1;
 
@@ -2360,7 +2448,7 @@ int run_launch(RRWorkspace &ws, RRStats &st, const hyperim_tuning &tune, RRArgs 
             if (use_graphs) {
                 // one replay: batch x (k_plan, k_expand) and the counter copy
                 const uint64_t key[8] = {1u, (uint64_t)(kb & 1u), (uint64_t)batch, plan_grid_all,
-                                         (uint64_t)grid_b, 0u, (uint64_t)(uintptr_t)ap,
+                                         (uint64_t)grid_b, gaps ? 1u : 0u, (uint64_t)(uintptr_t)ap,
                                          (uint64_t)(uintptr_t)h ^ ((uint64_t)(uintptr_t)ctr << 1)};
                 hipGraphExec_t ex = nullptr;
                 HIM_CHECK(captured_batch(
@@ -2369,7 +2457,7 @@ int run_launch(RRWorkspace &ws, RRStats &st, const hyperim_tuning &tune, RRArgs 
                         for (int i = 0; i < batch; ++i) {
                             const uint32_t parity = (uint32_t)(i & 1);
                             hipLaunchKernelGGL(k_plan, dim3(plan_grid_all), dim3(kWG), 0, c, ap, parity);
-                            hipLaunchKernelGGL(k_expand, dim3(grid_b), dim3(kWG), 0, c, ap, parity);
+                            hipLaunchKernelGGL(expand_k, dim3(grid_b), dim3(kWG), 0, c, ap, parity);
                         }
                         return hipMemcpyAsync(dst, ctr, sizeof(unsigned long long) * kNumCtr, hipMemcpyDeviceToHost,
                                               c) == hipSuccess;
@@ -2392,10 +2480,10 @@ int run_launch(RRWorkspace &ws, RRStats &st, const hyperim_tuning &tune, RRArgs 
                 // timed: the launch itself stamps its start and end events (no
                 // stream markers between the kernels)
                 if (time_kernels)
-                    hipExtLaunchKernelGGL(k_expand, dim3(grid_b), dim3(kWG), 0, s, E[2 + 2 * i], E[3 + 2 * i], 0u,
+                    hipExtLaunchKernelGGL(expand_k, dim3(grid_b), dim3(kWG), 0, s, E[2 + 2 * i], E[3 + 2 * i], 0u,
                                           ap, parity);
                 else
-                    hipLaunchKernelGGL(k_expand, dim3(grid_b), dim3(kWG), 0, s, ap, parity);
+                    hipLaunchKernelGGL(expand_k, dim3(grid_b), dim3(kWG), 0, s, ap, parity);
             }
             HIM_HIP(hipGetLastError());
             HIM_HIP(hipMemcpyAsync(dst, ctr, sizeof(unsigned long long) * kNumCtr, hipMemcpyDeviceToHost, s));
@@ -2998,7 +3086,7 @@ int rr_generate_into(RRWorkspace &ws, RRStats &st, const std::vector<RRTask> &ta
                 HIM_CHECK(run_layered_launch(ws, run, a, shape, grid, s, scans));
             else
                 HIM_CHECK(run_launch(ws, run, tune, a, shape, grid, grid_b, expect_defer, trace, time_kernels,
-                                     graphs, s, scans));
+                                     graphs, tasks[slices[0].task].g->gaps(), s, scans));
             // time counts every attempt, work only the one that produced the output
             st.ms_bfs += run.ms_bfs;
             st.ms_light += run.ms_light;

@@ -144,7 +144,7 @@ def test_lt_and_ic_graphs_in_one_generation_call(hy):
 def test_lt_graph_rejects_unknown_model(hy):
     hg = hypergen.from_lists(3, [[0, 1]])
     with pytest.raises(hy.HyperIMError):
-        hy.build_graph(hg.n, hg.he_off, hg.he_mem, 5, 0.1)
+        hy.build_graph(hg.n, hg.he_off, hg.he_mem, 7, 0.1)
     with pytest.raises(hy.HyperIMError):
         hy.build_graph(hg.n, hg.he_off, hg.he_mem, LT_CONST, float("nan"))
 
