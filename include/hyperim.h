@@ -90,8 +90,9 @@ typedef struct hyperim_session_s *hyperim_session;
  * layer's members not picked yet (ascending).  Picked members outside the
  * set join it.  ln and exp come from the host's C library.
  *
- * Independent cascade drawn by geometric gaps, HYPERIM_MODEL_GAPS_CONST and
- * HYPERIM_MODEL_GAPS_WC (p_v as for the two IC models): the same cascade, with
+ * Independent cascade drawn by geometric gaps (the subset sampling of Section
+ * 2.2.1, Algorithm 2), HYPERIM_MODEL_GAPS_CONST and HYPERIM_MODEL_GAPS_WC (p_v
+ * as for the two IC models): the same cascade, with
  * the live positions of each stream (RR id j, hyperedge he, target v) -- he's
  * member positions in the caller's order, each live with p_v, a live
  * position holding v itself ignored -- found by skipping over the dead ones.

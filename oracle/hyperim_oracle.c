@@ -19,7 +19,8 @@
  *     P(L_i) = 1 / (i ln(l_v + 1)); an RR set draws per popped vertex and
  *     layer a count (Binomial for layers of at most 20 members, Poisson
  *     above) and selects that many members without replacement;
- *   - independent cascade drawn by geometric gaps (models 5 and 6): the same
+ *   - independent cascade drawn by geometric gaps (models 5 and 6; the
+ *     subset sampling of Section 2.2.1, Algorithm 2, on IC channels): the same
  *     channels and probabilities as models 0 and 1, but the live positions
  *     of each stream (RR id, hyperedge, target) are drawn as gaps of dead
  *     positions instead of one coin per position;

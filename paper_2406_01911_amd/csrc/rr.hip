@@ -438,7 +438,8 @@ __device__ __forceinline__ void test_run(const GraphView &G, uint64_t j, uint32_
     }
 }
 
-// Independent cascade drawn by geometric gaps (models HYPERIM_MODEL_GAPS_*):
+// Independent cascade drawn by geometric gaps (models HYPERIM_MODEL_GAPS_*;
+// the subset sampling of Section 2.2.1, Algorithm 2, on the IC channels):
 // the stream of (RR id j, hyperedge he, target v) is he's positions in
 // stored order, each live with p_v (a live position holding v itself is no
 // channel and is dropped); the gaps of dead positions before the next live
