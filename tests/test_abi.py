@@ -77,3 +77,19 @@ def test_invalid_arguments_rejected_before_any_device_work():
     with pytest.raises(hy.HyperIMError) as e:
         hy.build_graph(3, np.array([0, 2], np.uint32), np.array([0, 1], np.uint32), 7, 0.1)
     assert e.value.status == hy.EINVAL
+    for model in (hy.MODEL_LT_CONST, hy.MODEL_GAPS_CONST):
+        with pytest.raises(hy.HyperIMError) as e:
+            hy.build_graph(3, np.array([0, 2], np.uint32), np.array([0, 1], np.uint32), model, -0.25)
+        assert e.value.status == hy.EINVAL
+
+
+def test_model_constants_match_the_header():
+    """The binding's and the input generator's model numbers are the header's."""
+    import hypergen
+    import paper_2406_01911_amd as hy
+    text = open(HEADER).read()
+    header = {k: int(v) for k, v in re.findall(r"#define HYPERIM_(MODEL_\w+) (\d+)u", text)}
+    assert sorted(header.values()) == list(range(7))
+    for name, value in header.items():
+        assert getattr(hy, name) == value, name
+        assert getattr(hypergen, name) == value, name
