@@ -491,6 +491,85 @@ __device__ __forceinline__ void push_live(uint32_t *bm, Lds &L, uint32_t &nlive,
     }
 }
 
+// Levels 2 and 3 under the gap models: the call's incidences g in [0, D)
+// (wave w of W takes g = w, w + W, ...) go to lanes as a queue -- a lane whose
+// stream has ended takes the next incidence -- so lanes stay busy while
+// streams of different lengths run (a stream is sequential: gap r + 1 starts
+// where gap r ended).  Each step draws one gap per busy lane; a live position
+// yields its member (the target itself excepted), which is marked and
+// appended as in test_run.  Returns the algorithmic bytes (12 per incidence,
+// 4 per member read), wave-uniform after the caller's sum.
+template <bool kLds, bool kUniform, class App, class Lds>
+__device__ __forceinline__ uint64_t expand_gaps(const GraphView &G, Lds &L, uint64_t j, uint32_t pool, uint2 key,
+                                                uint32_t *bm, uint32_t v, uint32_t e0, uint32_t D,
+                                                uint32_t th_uniform, App &app, uint64_t &px, uint32_t &nlive,
+                                                uint32_t w, uint32_t W) {
+#pragma clang fp contract(off)
+    const uint32_t lane = lane_id();
+    const uint64_t below = (1ull << lane) - 1ull;
+    uint64_t next = w;   // next incidence of this wave (wave-uniform)
+    uint64_t bytes = 0;
+    bool more = false;
+    uint32_t he = 0, hb = 0, hs = 0, vv = v, cur = 0, r = 0;
+    double q = 1.0;
+    uint4 blk = make_uint4(0u, 0u, 0u, 0u);
+    for (;;) {
+        const uint64_t idle = __ballot(!more);
+        if (idle != 0ull && next < D) {
+            // refill: the idle lanes take the next incidences in lane order
+            const uint64_t g = next + (uint64_t)__popcll(idle & below) * W;
+            if (!more && g < D) {
+                uint32_t e = e0 + (uint32_t)g, th = th_uniform;
+                if constexpr (!kUniform) {
+                    const uint32_t k = search64(L.fr_scan, (uint32_t)g);
+                    const uint32_t start = k ? L.fr_scan[k - 1] : 0u;
+                    vv = L.fr_v[k];
+                    e = L.fr_e0[k] + ((uint32_t)g - start);
+                    th = G.thr[vv];
+                }
+                he = G.v_he[e];
+                const unsigned long long bs = G.v_hbs[e];
+                hb = (uint32_t)bs;
+                hs = (uint32_t)(bs >> 32);
+                bytes += 12u;
+                more = th != 0u && hs != 0u;   // threshold 0: no channel into vv is live
+                cur = 0u;
+                r = 0u;
+                q = 1.0 - (th == kAlways ? 1.0 : (double)th * 0x1.0p-32);
+            }
+            next += (uint64_t)__popcll(idle) * W;
+        }
+        if (__ballot(more) == 0ull) {
+            if (next >= D) break;
+            continue;
+        }
+        uint32_t u = vv;
+        bool live = false;
+        if (more) {
+            if ((r & 3u) == 0u) {
+                blk = philox4x32_10(coin_counter(j, he, vv, pool, r >> 2), key);
+                ++px;
+            }
+            const uint32_t x = (r & 3u) == 0u ? blk.x : (r & 3u) == 1u ? blk.y : (r & 3u) == 2u ? blk.z : blk.w;
+            ++r;
+            const uint32_t left = hs - cur;
+            const uint32_t gap = gap_draw(q, x, left);
+            if (gap >= left) {
+                more = false;
+            } else {
+                const uint32_t pos = cur + gap;
+                u = G.he_mem[hb + pos];
+                bytes += 4u;
+                live = u != vv;
+                cur = pos + 1u;
+                more = cur < hs;
+            }
+        }
+        push_live<kLds>(bm, L, nlive, app, live, u);
+    }
+    return bytes;
+}
+
 // Levels 2 and 3 of a frontier expansion.  Each lane brings one vertex v with
 // the incidence range [e0, e0 + d) of v_he to expand (d = 0 for none); with
 // kUniform all lanes pass the same v and e0 and d is the wave's incidence
@@ -523,6 +602,13 @@ __device__ __forceinline__ uint64_t expand(const GraphView &G, Lds &L, uint64_t 
         L.fr_e0[lane] = e0;
         wave_sync();
     }
+    if constexpr (kGaps) {
+        const uint64_t bytes = expand_gaps<kLds, kUniform>(G, L, j, pool, key, bm, v, e0, D, th_uniform, app, px,
+                                                           nlive, w, W);
+        if constexpr (!kLds) flush_live(bm, L, nlive, app);
+        wave_sync();
+        return wave_sum(bytes);
+    }
     // batch share: batches b = boff, boff + bstride, ...; within a batch,
     // runs qb = sub_w * 64, (sub_w + sub) * 64, ...  (first runs: sub_w 0)
     const uint32_t nbatch = (D + kWave - 1) / kWave;
@@ -552,42 +638,7 @@ __device__ __forceinline__ uint64_t expand(const GraphView &G, Lds &L, uint64_t 
             hb = (uint32_t)bs;
             hs = (uint32_t)(bs >> 32);
             no = th ? (hs + kRun - 1u) / kRun : 0u;   // threshold 0: no channel into vv is live
-            if (sub_w == 0) bytes += kGaps ? 12u : 12u + 4u * hs;
-        }
-        if constexpr (kGaps) {
-            // level 3 by gaps: each lane walks its own incidence's stream
-            // (only the waves of the first share: every stream once)
-            if (sub_w != 0) continue;
-            bool more = g < D && th != 0u;
-            const double q = 1.0 - (th == kAlways ? 1.0 : (double)th * 0x1.0p-32);
-            uint32_t cur = 0, r = 0;
-            uint4 blk = make_uint4(0u, 0u, 0u, 0u);
-            while (__ballot(more) != 0) {
-                uint32_t u = vv;
-                bool live = false;
-                if (more) {
-                    if ((r & 3u) == 0u) {
-                        blk = philox4x32_10(coin_counter(j, he, vv, pool, r >> 2), key);
-                        ++px;
-                    }
-                    const uint32_t x = (r & 3u) == 0u ? blk.x : (r & 3u) == 1u ? blk.y : (r & 3u) == 2u ? blk.z : blk.w;
-                    ++r;
-                    const uint32_t left = hs - cur;
-                    const uint32_t gap = gap_draw(q, x, left);
-                    if (gap >= left) {
-                        more = false;
-                    } else {
-                        const uint32_t pos = cur + gap;
-                        u = G.he_mem[hb + pos];
-                        bytes += 4u;
-                        live = u != vv;
-                        cur = pos + 1u;
-                        more = cur < hs;
-                    }
-                }
-                push_live<kLds>(bm, L, nlive, app, live, u);
-            }
-            continue;
+            if (sub_w == 0) bytes += 12u + 4u * hs;
         }
         // level 3, first pass: run 0 of the lane's own incidence
         if (sub_w == 0)
