@@ -468,6 +468,26 @@ __device__ __forceinline__ uint32_t gap_draw(double q, uint32_t x, uint32_t G) {
     return g;
 }
 
+// The same draw from the stream's powers S_i = q^(2^i), i < kGapTab, kept in
+// registers (each S_i is q squared i times in sequence, so the values and the
+// descent's products are those of gap_draw); for G < 2^kGapTab.
+constexpr uint32_t kGapTab = 8;
+__device__ __forceinline__ uint32_t gap_draw_tab(const double (&S)[kGapTab], uint32_t x, uint32_t G) {
+#pragma clang fp contract(off)
+    const double t = (double)((1ull << 32) - (uint64_t)x) * 0x1.0p-32;
+    uint32_t g = 0;
+    double acc = 1.0;
+#pragma unroll
+    for (int i = (int)kGapTab - 1; i >= 0; --i) {
+        const double a = acc * S[i];
+        if (g + (1u << i) <= G && a >= t) {
+            acc = a;
+            g += 1u << i;
+        }
+    }
+    return g;
+}
+
 // One candidate per lane (`live` with member u): marked and appended as in
 // test_run.  Every lane of the wave calls it.
 template <bool kLds, class App, class Lds>
@@ -512,6 +532,9 @@ __device__ __forceinline__ uint64_t expand_gaps(const GraphView &G, Lds &L, uint
     bool more = false;
     uint32_t he = 0, hb = 0, hs = 0, vv = v, cur = 0, r = 0;
     double q = 1.0;
+    double S[kGapTab];   // q^(2^i) of the lane's stream, when hs < 2^kGapTab
+#pragma unroll
+    for (uint32_t i = 0; i < kGapTab; ++i) S[i] = 1.0;
     uint4 blk = make_uint4(0u, 0u, 0u, 0u);
     for (;;) {
         const uint64_t idle = __ballot(!more);
@@ -536,6 +559,11 @@ __device__ __forceinline__ uint64_t expand_gaps(const GraphView &G, Lds &L, uint
                 cur = 0u;
                 r = 0u;
                 q = 1.0 - (th == kAlways ? 1.0 : (double)th * 0x1.0p-32);
+                if (hs < (1u << kGapTab)) {
+                    S[0] = q;
+#pragma unroll
+                    for (uint32_t i = 1; i < kGapTab; ++i) S[i] = S[i - 1] * S[i - 1];
+                }
             }
             next += (uint64_t)__popcll(idle) * W;
         }
@@ -553,7 +581,7 @@ __device__ __forceinline__ uint64_t expand_gaps(const GraphView &G, Lds &L, uint
             const uint32_t x = (r & 3u) == 0u ? blk.x : (r & 3u) == 1u ? blk.y : (r & 3u) == 2u ? blk.z : blk.w;
             ++r;
             const uint32_t left = hs - cur;
-            const uint32_t gap = gap_draw(q, x, left);
+            const uint32_t gap = hs < (1u << kGapTab) ? gap_draw_tab(S, x, left) : gap_draw(q, x, left);
             if (gap >= left) {
                 more = false;
             } else {
