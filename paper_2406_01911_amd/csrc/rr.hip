@@ -257,6 +257,16 @@ struct LocalAppend {
             }
         size = min(size + total, n);
     }
+    // One member per lane at most (`fresh`): places from the wave's ballot.
+    __device__ __forceinline__ void push1(bool fresh, uint32_t u) {
+        const uint64_t bal = __ballot(fresh);
+        if (bal == 0ull) return;
+        if (fresh) {
+            const uint32_t at = size + (uint32_t)__popcll(bal & ((1ull << lane_id()) - 1ull));
+            if (at < n) list[at] = u;
+        }
+        size = min(size + (uint32_t)__popcll(bal), n);
+    }
 };
 
 // Same with the size in global memory (phase B: many waves grow one set).
@@ -492,21 +502,19 @@ __device__ __forceinline__ uint32_t gap_draw_tab(const double (&S)[kGapTab], uin
 // test_run.  Every lane of the wave calls it.
 template <bool kLds, class App, class Lds>
 __device__ __forceinline__ void push_live(uint32_t *bm, Lds &L, uint32_t &nlive, App &app, bool live, uint32_t u) {
-    if (__ballot(live) == 0) return;
+    const uint64_t bal = __ballot(live);
+    if (bal == 0ull) return;
     if constexpr (kLds) {
-        uint32_t fresh = 0;
+        bool fresh = false;
         if (live) {
             const uint32_t bit = 1u << (u & 31);
-            if ((atomicOr(&bm[u >> 5], bit) & bit) == 0u) fresh = 1u;
+            fresh = (atomicOr(&bm[u >> 5], bit) & bit) == 0u;
         }
-        const uint32_t uu[8] = {u, u, u, u, u, u, u, u};
-        app.push8(fresh, uu);
+        app.push1(fresh, u);
     } else {
-        const uint32_t cnt = live ? 1u : 0u;
-        const uint32_t incl = wave_incl_scan(cnt);
-        const uint32_t tot = uni(wave_bcast(incl, kWave - 1));
+        const uint32_t tot = (uint32_t)__popcll(bal);
         if (nlive + tot > kLiveCap) flush_live(bm, L, nlive, app);
-        if (live) L.live[nlive + incl - cnt] = u;
+        if (live) L.live[nlive + (uint32_t)__popcll(bal & ((1ull << lane_id()) - 1ull))] = u;
         nlive += tot;
     }
 }
