@@ -35,6 +35,12 @@
 // to back, described in device memory: both pools of a doubling round, or
 // many IM instances on different graphs, share phase A and the supersteps.
 //
+// The other cascade models reuse this frame: under the gap models the same
+// two phases run with level 3 replaced by one geometric-gap stream per
+// incidence (expand_gaps); the linear-threshold walk (k_lt_walk) and the
+// stratified setting's per-layer draws (k_layered) are one wave per set in
+// phase A's slots.  A launch group holds graphs of one kind only.
+//
 // Compaction turns the per-id sizes into CSR offsets (device scan) and moves
 // the staged members into the pools.
 #include <hip/hip_ext.h>

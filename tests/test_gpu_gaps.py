@@ -155,3 +155,48 @@ def test_gap_graph_rejects_nan_and_unknown_model(hy):
         hy.build_graph(hg.n, hg.he_off, hg.he_mem, GAPS_CONST, float("nan"))
     with pytest.raises(hy.HyperIMError):
         hy.build_graph(hg.n, hg.he_off, hg.he_mem, GAPS_CONST, -0.5)
+
+
+def test_large_gaps_sampled_sets_under_stored_tuning_exact(hy):
+    """The launch configuration the benchmark times on large_gaps (|V| = 1e6,
+    |HE| = 2e6, giant sets of ~1e5 members): its stored tuning, both pools'
+    ids [0, 4096) in one generation call.  Sampled ids, including the largest
+    sets, regenerated one by one by the oracle (each id depends only on its
+    key), equal the library's sets and roots."""
+    import concurrent.futures as cf
+    import os
+    from paper_2406_01911_amd import autotune
+    _flush("[gpu] large_gaps: generating the hypergraph")
+    w = hypergen.workload("large_gaps")
+    hg = w.build()
+    g = hy.build_graph(hg.n, hg.he_off, hg.he_mem, w.model, w.p)
+    g.stratify()
+    tuning = autotune.load("large_gaps")
+    assert tuning is not None
+    g.set_tuning(**tuning)
+    ids = 4096
+    pools = {tag: hy.Pool(g) for tag in (0, 1)}
+    _flush(f"[gpu] large_gaps: both pools [0, {ids}) under the stored tuning")
+    hy.generate_rr_batch([dict(graph=g, pool=pools[tag], seed=w.philox_seed, instance=0, pool_tag=tag,
+                               id_begin=0, id_end=ids) for tag in (0, 1)])
+    _flush("[gpu] large_gaps: oracle graph and strata (about a minute)")
+    o = oracle.Graph(hg, w.model, w.p)
+    o.stratify()
+    rng = np.random.default_rng(13)
+    checks = []
+    for tag in (0, 1):
+        off, mem, roots = pools[tag].read()
+        sizes = np.diff(off)
+        assert sizes.max() > 50_000   # giant sets are generated and checked
+        big = [int(j) for j in np.argsort(sizes, kind="stable")[-3:]]
+        pick = big + [int(j) for j in rng.choice(ids, size=5, replace=False) if int(j) not in big]
+        for j in pick:
+            checks.append((tag, j, mem[off[j]:off[j + 1]].copy(), int(roots[j])))
+    _flush(f"[gpu] large_gaps: {len(checks)} sampled ids on the CPU")
+    threads = max(1, min(len(checks), int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)))
+    with cf.ThreadPoolExecutor(max_workers=threads) as ex:
+        ref = list(ex.map(lambda c: (o.rr_set(w.philox_seed, 0, c[0], c[1]), o.root(w.philox_seed, 0, c[0], c[1])),
+                          checks))
+    for (tag, j, got, root), (want, wroot) in zip(checks, ref):
+        assert root == wroot, (tag, j)
+        assert np.array_equal(got, want), (tag, j, got.size, want.size)
