@@ -101,6 +101,8 @@ def lib():
         L.orc_sigma_upper_cov.argtypes = [C.c_double] * 4
         L.orc_sigma_upper_cov.restype = C.c_double
         L.orc_layers_export.argtypes = [vp, vp, vp, vp, vp]
+        L.orc_route.argtypes = [vp, C.c_int, u32p]
+        L.orc_route_export.argtypes = [vp, vp, vp, vp]
         L.orc_gap_draw.argtypes = [C.c_double, C.c_uint32, C.c_uint32]
         L.orc_gap_draw.restype = C.c_uint32
         _lib = L
@@ -272,7 +274,7 @@ class Graph:
         return out
 
     def layers(self):
-        """Stratified-setting model only: per vertex the members of A(v) layer by
+        """Stratified-setting model (or a graph divided by route()): per vertex the members of A(v) layer by
         layer (layer 1 = largest w(v,u)), ascending ids within a layer, as
         (nb_off, nb, ly_off, ly_end): layer i of v is nb[nb_off[v] + ly_end[ly_off[v] + i - 2]
         .. nb_off[v] + ly_end[ly_off[v] + i - 1]) (the first layer starts at nb_off[v])."""
@@ -286,6 +288,32 @@ class Graph:
         if rc:
             raise OracleError("orc_layers_export: %d" % rc)
         return nb_off, nb[:int(st["deg"].sum())], ly_off, ly_end[:int(st["l"].sum())]
+
+    def route(self, on: bool = True) -> int:
+        """Division of the RR sets into R1 / R2 (Section 4.1), after stratify():
+        pool 0 then draws its roots from the vertices with a small layer
+        (|L_i| < alpha |A(v)| for some i <= floor(beta)) and its sets start from
+        the root and those layers' members; pool 1 draws from the other
+        vertices.  Returns the number of R1 vertices (the division is inert
+        when that is 0 or n)."""
+        n1 = C.c_uint32()
+        rc = lib().orc_route(self._h, 1 if on else 0, C.byref(n1))
+        if rc:
+            raise OracleError("orc_route: %d" % rc)
+        return int(n1.value)
+
+    def route_tables(self):
+        """(rP, f_off, f_mem) of a divided graph: R1 roots rP[:n1], R2 roots
+        rP[n1:], and the forced members of each vertex."""
+        n = self.n
+        rP = np.zeros(max(n, 1), np.uint32)
+        f_off = np.zeros(n + 1, np.uint64)
+        nb_total = int(self.strata()["deg"].sum())
+        f_mem = np.zeros(max(nb_total, 1), np.uint32)
+        rc = lib().orc_route_export(self._h, _p(rP), _p(f_off), _p(f_mem))
+        if rc:
+            raise OracleError("orc_route_export: %d" % rc)
+        return rP[:n], f_off, f_mem[:int(f_off[-1])]
 
     def root(self, seed, instance, pool, j, qlog=8) -> int:
         return int(lib().orc_root(self._h, seed, instance, pool, j, qlog))

@@ -34,6 +34,10 @@
  *     statistics alpha, beta of Section 4.1 and theta(l*) of Theorem 2;
  *   - RR sets: a root, then the reverse breadth-first closure over live
  *     channels (Algorithm 3's skeleton: root, queue, activated marks);
+ *   - optionally, the division of the RR sets into R1 and R2 of Section 4.1
+ *     (roots with a small layer among the first beta go to R1, whose sets
+ *     contain those layers' members; the others to R2), which biases the
+ *     estimates and is off unless switched on;
  *   - greedy max coverage (Algorithm 1, Equations (1)-(2));
  *   - the sample-size loop of HyperIM_BRR (Algorithm 4): theta_max
  *     (Lemma 6 / Equation (13)), theta_0, the lower bound of Equation (12)
@@ -144,6 +148,14 @@ typedef struct orc_graph {
     uint8_t *stratum;
     uint32_t B[ORC_NSTRATA + 1];
     double alpha, beta, theta_l;
+    /* division of the RR sets (Section 4.1), when switched on: R1 (pool 0)
+     * draws its roots from rP[0 .. n1), the vertices with a small layer,
+     * R2 (pool 1) from rP[n1 .. n); an R1 set of root v starts from v and
+     * f_mem[f_off[v] .. f_off[v+1]) */
+    int routed;
+    uint32_t n1;
+    uint32_t *rP, *f_mem;
+    uint64_t *f_off;
 } orc_graph;
 
 void orc_graph_free(orc_graph *g)
@@ -153,6 +165,7 @@ void orc_graph_free(orc_graph *g)
     free(g->thr); free(g->c); free(g->l); free(g->deg); free(g->top);
     free(g->P); free(g->stratum);
     free(g->nb_off); free(g->ly_off); free(g->nb); free(g->ly_end);
+    free(g->rP); free(g->f_off); free(g->f_mem);
     free(g);
 }
 
@@ -342,7 +355,7 @@ static int orc_build_layers(orc_graph *g)
 
 int orc_layers_export(const orc_graph *g, uint64_t *nb_off, uint32_t *nb, uint64_t *ly_off, uint32_t *ly_end)
 {
-    if (!g->layered || !g->stratified) return ORC_EINVAL;
+    if (!g->stratified || !g->nb_off) return ORC_EINVAL;
     uint32_t n = g->n;
     memcpy(nb_off, g->nb_off, sizeof(uint64_t) * ((size_t)n + 1));
     memcpy(ly_off, g->ly_off, sizeof(uint64_t) * ((size_t)n + 1));
@@ -354,6 +367,12 @@ int orc_layers_export(const orc_graph *g, uint64_t *nb_off, uint32_t *nb, uint64
 int orc_stratify(orc_graph *g)
 {
     uint32_t n = g->n;
+    /* new strata: any division of the RR sets is stale */
+    free(g->rP); free(g->f_off); free(g->f_mem);
+    g->rP = NULL; g->f_off = NULL; g->f_mem = NULL;
+    g->routed = 0; g->n1 = 0;
+    free(g->nb_off); free(g->ly_off); free(g->nb); free(g->ly_end);
+    g->nb_off = NULL; g->ly_off = NULL; g->nb = NULL; g->ly_end = NULL;
     free(g->l); free(g->deg); free(g->top); free(g->P); free(g->stratum);
     g->l = (uint32_t *)calloc(n ? n : 1, sizeof(uint32_t));
     g->deg = (uint32_t *)calloc(n ? n : 1, sizeof(uint32_t));
@@ -448,6 +467,99 @@ int orc_strata_export(const orc_graph *g, uint32_t *l, uint32_t *deg, uint32_t *
 }
 
 /* ------------------------------------------------------------------------ */
+/* Division of the RR sets into R1 and R2 (Section 4.1), opt-in              */
+/* ------------------------------------------------------------------------ */
+/* alpha = F_cnt / T_cnt (the share of first-layer vertices among all layer
+ * vertices) and beta = L_cnt / |V| (the mean number of layers).  For a
+ * vertex v and each layer i of A(v) with 1 <= i <= beta (i <= floor(beta)),
+ * the layer is small when |L_i| < alpha |A(v)|, compared exactly as
+ * |L_i| T_cnt < F_cnt |A(v)| in 128-bit integers.  v's RR sets go to R1 when
+ * some layer is small, and then contain every member of the small layers;
+ * otherwise to R2.  Here R1 (pool 0) draws its roots, stratified as usual,
+ * from the R1 vertices only (the stratum order of P kept), R2 (pool 1) from
+ * the others; an R1 set starts its reverse traversal from the root and the
+ * members of its small layers together (their channels into the root count
+ * as live).  When either side is empty the division is inert (both pools
+ * over V, no forced members).  Not for the linear-threshold or stratified-
+ * setting models.  *n1 = the number of R1 vertices. */
+int orc_route(orc_graph *g, int on, uint32_t *n1)
+{
+    uint32_t n = g->n;
+    *n1 = 0;
+    if (!g->stratified || g->lt || g->layered) return ORC_EINVAL;
+    free(g->rP); free(g->f_off); free(g->f_mem);
+    g->rP = NULL; g->f_off = NULL; g->f_mem = NULL;
+    g->routed = 0; g->n1 = 0;
+    if (!on) return ORC_OK;
+    if (!g->nb_off) {
+        int rc = orc_build_layers(g);
+        if (rc) return rc;
+    }
+    uint64_t Fc = 0, Tc = 0, Lc = 0;
+    for (uint32_t v = 0; v < n; ++v) {
+        Fc += g->top[v];
+        Tc += g->deg[v];
+        Lc += g->l[v];
+    }
+    uint64_t ilim = n ? Lc / n : 0;   /* layers 1 .. floor(beta) */
+    g->f_off = (uint64_t *)calloc((size_t)n + 1, sizeof(uint64_t));
+    if (!g->f_off) return ORC_ENOMEM;
+    for (int pass = 0; pass < 2; ++pass) {
+        for (uint32_t v = 0; v < n; ++v) {
+            uint64_t at = pass ? g->f_off[v] : 0;   /* pass 0 counts, pass 1 writes */
+            uint32_t prev = 0;
+            for (uint64_t i = 0; i < g->l[v] && i < ilim; ++i) {
+                uint32_t end = g->ly_end[g->ly_off[v] + i];
+                uint32_t size = end - prev;
+                if ((unsigned __int128)size * Tc < (unsigned __int128)Fc * g->deg[v]) {
+                    if (pass == 0) {
+                        at += size;
+                    } else {
+                        for (uint32_t k = prev; k < end; ++k) g->f_mem[at++] = g->nb[g->nb_off[v] + k];
+                    }
+                }
+                prev = end;
+            }
+            if (pass == 0) g->f_off[v + 1] = at;   /* count, summed below */
+        }
+        if (pass == 0) {
+            for (uint32_t v = 0; v < n; ++v) g->f_off[v + 1] += g->f_off[v];
+            g->f_mem = (uint32_t *)malloc(sizeof(uint32_t) * (g->f_off[n] ? g->f_off[n] : 1));
+            if (!g->f_mem) return ORC_ENOMEM;
+        }
+    }
+    uint32_t c1 = 0;
+    for (uint32_t v = 0; v < n; ++v) c1 += g->f_off[v + 1] > g->f_off[v];
+    *n1 = c1;
+    if (c1 == 0 || c1 == n) {
+        free(g->f_off); free(g->f_mem);
+        g->f_off = NULL; g->f_mem = NULL;
+        return ORC_OK;
+    }
+    g->rP = (uint32_t *)malloc(sizeof(uint32_t) * n);
+    if (!g->rP) return ORC_ENOMEM;
+    uint32_t a = 0, b = c1;
+    for (uint32_t i = 0; i < n; ++i) {
+        uint32_t v = g->P[i];
+        if (g->f_off[v + 1] > g->f_off[v]) g->rP[a++] = v;
+        else g->rP[b++] = v;
+    }
+    g->n1 = c1;
+    g->routed = 1;
+    return ORC_OK;
+}
+
+/* The division's tables: rP (n), f_off (n + 1), f_mem (f_off[n]). */
+int orc_route_export(const orc_graph *g, uint32_t *rP, uint64_t *f_off, uint32_t *f_mem)
+{
+    if (!g->routed) return ORC_EINVAL;
+    memcpy(rP, g->rP, sizeof(uint32_t) * g->n);
+    memcpy(f_off, g->f_off, sizeof(uint64_t) * ((size_t)g->n + 1));
+    if (g->f_off[g->n]) memcpy(f_mem, g->f_mem, sizeof(uint32_t) * g->f_off[g->n]);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Roots: stratified (systematic, proportional) root sampling                */
 /* ------------------------------------------------------------------------ */
 /* The pool's ids are cut into a ladder of blocks: block 0 = [0, Q), block
@@ -486,9 +598,17 @@ uint32_t orc_root(const orc_graph *g, uint64_t seed, uint32_t instance, uint32_t
     uint32_t b;
     uint64_t J, T;
     orc_block_of(j, qlog, &b, &J, &T);
-    uint64_t o = orc_block_offset(g->n, seed, instance, pool, b);
-    unsigned __int128 pos = ((unsigned __int128)(j - J) * g->n + o) / T;
-    return g->P[(uint64_t)pos];
+    /* with the RR sets divided (Section 4.1), each pool samples its own
+     * vertices, in the same way */
+    const uint32_t *P = g->P;
+    uint32_t n = g->n;
+    if (g->routed) {
+        P = pool == 0u ? g->rP : g->rP + g->n1;
+        n = pool == 0u ? g->n1 : g->n - g->n1;
+    }
+    uint64_t o = orc_block_offset(n, seed, instance, pool, b);
+    unsigned __int128 pos = ((unsigned __int128)(j - J) * n + o) / T;
+    return P[(uint64_t)pos];
 }
 
 /* ------------------------------------------------------------------------ */
@@ -498,6 +618,19 @@ typedef struct {
     uint8_t *inR;
     uint32_t *queue;
 } orc_scratch;
+
+/* An R1 set of a divided graph (Section 4.1) starts with the members of its
+ * root's small layers beside the root. */
+static void orc_seed_forced(const orc_graph *g, uint32_t pool, uint32_t root, orc_scratch *s, uint32_t *tail)
+{
+    if (!g->routed || pool != 0u) return;
+    for (uint64_t f = g->f_off[root]; f < g->f_off[root + 1]; ++f) {
+        uint32_t u = g->f_mem[f];
+        if (s->inR[u]) continue;
+        s->inR[u] = 1;
+        s->queue[(*tail)++] = u;
+    }
+}
 
 /* R = {root}; pop v; for every hyperedge he containing v and every member u
  * of he other than v, the channel u -> v is tested with its own coin; a live
@@ -509,6 +642,7 @@ static uint32_t orc_rr_into(const orc_graph *g, uint64_t seed, uint32_t instance
     uint32_t head = 0, tail = 0;
     s->queue[tail++] = root;
     s->inR[root] = 1;
+    orc_seed_forced(g, pool, root, s, &tail);
     while (head < tail) {
         uint32_t v = s->queue[head++];
         uint32_t thr = g->thr[v];
@@ -749,6 +883,7 @@ static uint32_t orc_gaps_into(const orc_graph *g, uint64_t seed, uint32_t instan
     uint32_t head = 0, tail = 0;
     s->queue[tail++] = root;
     s->inR[root] = 1;
+    orc_seed_forced(g, pool, root, s, &tail);
     while (head < tail) {
         uint32_t v = s->queue[head++];
         uint32_t thr = g->thr[v];
