@@ -152,7 +152,7 @@ typedef struct orc_graph {
      * draws its roots from rP[0 .. n1), the vertices with a small layer,
      * R2 (pool 1) from rP[n1 .. n); an R1 set of root v starts from v and
      * f_mem[f_off[v] .. f_off[v+1]) */
-    int routed;
+    int route_on, routed;          /* asked for; in effect (both sides)     */
     uint32_t n1;
     uint32_t *rP, *f_mem;
     uint64_t *f_off;
@@ -364,10 +364,12 @@ int orc_layers_export(const orc_graph *g, uint64_t *nb_off, uint32_t *nb, uint64
     return ORC_OK;
 }
 
+int orc_route(orc_graph *g, int on, uint32_t *n1);
+
 int orc_stratify(orc_graph *g)
 {
     uint32_t n = g->n;
-    /* new strata: any division of the RR sets is stale */
+    /* new strata: the division of the RR sets is rebuilt at the end */
     free(g->rP); free(g->f_off); free(g->f_mem);
     g->rP = NULL; g->f_off = NULL; g->f_mem = NULL;
     g->routed = 0; g->n1 = 0;
@@ -446,7 +448,14 @@ int orc_stratify(orc_graph *g)
     g->beta = n ? (double)sum_l / (double)n : 0.0;
     g->theta_l = n ? theta_l / (double)n : 0.0;
     g->stratified = 1;
-    if (g->layered) return orc_build_layers(g);
+    if (g->layered) {
+        int rc = orc_build_layers(g);
+        if (rc) return rc;
+    }
+    if (g->route_on) {
+        uint32_t n1;
+        return orc_route(g, 1, &n1);
+    }
     return ORC_OK;
 }
 
@@ -490,6 +499,7 @@ int orc_route(orc_graph *g, int on, uint32_t *n1)
     free(g->rP); free(g->f_off); free(g->f_mem);
     g->rP = NULL; g->f_off = NULL; g->f_mem = NULL;
     g->routed = 0; g->n1 = 0;
+    g->route_on = on != 0;
     if (!on) return ORC_OK;
     if (!g->nb_off) {
         int rc = orc_build_layers(g);

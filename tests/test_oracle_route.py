@@ -12,7 +12,8 @@
 * Bias (documented, reading R25): the R2 estimate n Lambda_R2({s}) / theta
   converges to n times the mean, over the R2 vertices only, of
   Pr[s in RR(v)] (exact enumeration), which differs from the spread.
-* Inert and rejected cases, switching off, and re-stratifying.
+* Inert and rejected cases, switching off, and re-stratifying (which keeps
+  the division).
 """
 import numpy as np
 import pytest
@@ -173,5 +174,6 @@ def test_inert_rejected_off_and_restratify():
     assert [g2.root(1, 0, 0, j) for j in range(200)] == base
     assert all(np.array_equal(a, g2.rr_set(1, 0, 0, j)) for j, a in enumerate(sets))
     g2.route()
-    g2.stratify()   # new strata: the division is dropped
-    assert [g2.root(1, 0, 0, j) for j in range(200)] == base
+    routed = [g2.root(1, 0, 0, j) for j in range(200)]
+    g2.stratify()   # new strata: the division is rebuilt (the same strata give the same one)
+    assert [g2.root(1, 0, 0, j) for j in range(200)] == routed
