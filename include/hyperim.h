@@ -230,6 +230,26 @@ int hyperim_build_graph(uint32_t n, uint32_t m, const uint32_t *he_off, const ui
  * before hyperim_generate_rr / hyperim_select_seeds.  `out` may be NULL. */
 int hyperim_stratify(hyperim_graph g, void *stream, hyperim_strata_info *out);
 
+/* Division of the RR sets into R1 and R2 (Section 4.1, "Division of the RR
+ * sets"), opt-in and biased.  With alpha = F_cnt / T_cnt and beta =
+ * L_cnt / |V| of the graph's strata, layer i (1 <= i <= floor(beta)) of A(v)
+ * is small when n(L_i) < alpha |A(v)| (compared exactly as
+ * n(L_i) T_cnt < F_cnt |A(v)|).  on = 1: pool 0 (R1) draws its roots, with the
+ * usual stratified sampling, only from the vertices that have a small layer
+ * (in the order of P), and each of its RR sets starts from the root and all
+ * members of the root's small layers together (their channels into the root
+ * count as live); pool 1 (R2) draws its roots from the other vertices.  The
+ * estimators keep their factor n / theta, so R2's lower bound estimates n
+ * times the mean over the R2 vertices only, not the spread.  on = 0 undoes it.
+ * When every vertex or none has a small layer the division is inert.
+ * Independent-cascade models only (HYPERIM_EINVAL otherwise); needs
+ * hyperim_stratify first (HYPERIM_ESTATE), and must come before the first RR
+ * set is generated on the graph (HYPERIM_ESTATE after); a later
+ * hyperim_stratify keeps it.  Builds the layer tables of A(v) on the device
+ * when the graph has none (HYPERIM_EINVAL beyond 2^32 co-member occurrences
+ * or 16384 layers).  *n_r1 (may be NULL) receives the number of R1 vertices. */
+int hyperim_route(hyperim_graph g, uint32_t on, void *stream, uint32_t *n_r1);
+
 /* Copy the graph's derived arrays to caller buffers (host pointers unless
  * dst_on_device != 0); any pointer may be NULL.  Sizes: v_off n+1, v_he nnz,
  * thr n, c n (uint64), l/deg/top/P n, stratum n (uint8).  The strata arrays

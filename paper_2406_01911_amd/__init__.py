@@ -87,7 +87,7 @@ class _SessionStats(C.Structure):
 TUNING_FIELDS = ["heavy", "budget", "chunk", "seg", "prefilter_min", "steps_per_sync", "stage_mib", "blocks_a",
                  "blocks_b", "ms_min", "ms_filter"]
 
-EXPORTS = ["hyperim_build_graph", "hyperim_stratify", "hyperim_graph_read", "hyperim_pool_create",
+EXPORTS = ["hyperim_build_graph", "hyperim_stratify", "hyperim_route", "hyperim_graph_read", "hyperim_pool_create",
            "hyperim_generate_rr", "hyperim_generate_rr_batch", "hyperim_pool_view", "hyperim_pool_read", "hyperim_pool_required",
            "hyperim_pool_reset", "hyperim_greedy", "hyperim_coverage", "hyperim_coverage_noalloc",
            "hyperim_select_seeds",
@@ -112,6 +112,7 @@ def load_library(path: str = LIB_PATH):
     vp, u32, u64, i32 = C.c_void_p, C.c_uint32, C.c_uint64, C.c_int
     L.hyperim_build_graph.argtypes = [u32, u32, vp, vp, i32, _Prob, vp, C.POINTER(vp)]
     L.hyperim_stratify.argtypes = [vp, vp, C.POINTER(_StrataInfo)]
+    L.hyperim_route.argtypes = [vp, u32, vp, C.POINTER(u32)]
     L.hyperim_graph_read.argtypes = [vp] + [vp] * 9 + [i32, vp]
     L.hyperim_pool_create.argtypes = [vp, vp, C.c_size_t, u64, C.POINTER(vp)]
     L.hyperim_generate_rr.argtypes = [vp, u64, u32, u32, u64, u64, vp, vp]
@@ -190,6 +191,15 @@ class Graph:
         self.info = {"B": np.array(list(info.B), np.uint32), "sum_top": info.sum_top, "sum_deg": info.sum_deg,
                      "sum_l": info.sum_l, "alpha": info.alpha, "beta": info.beta, "theta_l": info.theta_l}
         return self.info
+
+    # hyperim_route
+    def route(self, on: bool = True, stream=None) -> int:
+        """Division of the RR sets into R1 (pool 0) and R2 (pool 1) of
+        Section 4.1 (biased; see hyperim_route); returns the number of R1
+        vertices."""
+        n1 = C.c_uint32()
+        _check(_lib.hyperim_route(self._h, 1 if on else 0, _stream(stream), C.byref(n1)))
+        return int(n1.value)
 
     # hyperim_set_tuning / hyperim_get_tuning
     def set_tuning(self, **kw):

@@ -192,7 +192,8 @@ size_t graph_bytes(hyperim_graph g) {
     size_t b = 0;
     for (const DevBuf *x : {&g->he_off, &g->he_mem, &g->v_off, &g->v_he, &g->thr, &g->c, &g->weight, &g->bytesw,
                             &g->phiw, &g->v_hbs, &g->chan, &g->l, &g->deg, &g->top, &g->stratum, &g->P,
-                            &g->lay_nb_off, &g->lay_nb, &g->lay_ly_off, &g->lay_ly_end, &g->lay_ln, &g->lay_expm})
+                            &g->lay_nb_off, &g->lay_nb, &g->lay_ly_off, &g->lay_ly_end, &g->lay_ln, &g->lay_expm,
+                            &g->route_P, &g->force_off, &g->force})
         b += x->bytes;
     return b;
 }
@@ -200,7 +201,8 @@ size_t graph_bytes(hyperim_graph g) {
 void release_graph(hyperim_graph g) {
     for (DevBuf *b : {&g->he_off, &g->he_mem, &g->v_off, &g->v_he, &g->thr, &g->c, &g->weight, &g->bytesw,
                       &g->phiw, &g->v_hbs, &g->chan, &g->l, &g->deg, &g->top, &g->stratum, &g->P,
-                            &g->lay_nb_off, &g->lay_nb, &g->lay_ly_off, &g->lay_ly_end, &g->lay_ln, &g->lay_expm})
+                            &g->lay_nb_off, &g->lay_nb, &g->lay_ly_off, &g->lay_ly_end, &g->lay_ln, &g->lay_expm,
+                            &g->route_P, &g->force_off, &g->force})
         b->release();
 }
 
@@ -253,6 +255,7 @@ int generate_into(const std::vector<RRTask> &tasks, const std::vector<hyperim_po
     std::vector<bool> was_empty;
     for (size_t i = 0; i < tasks.size(); ++i)
         if (tasks[i].id_end > tasks[i].id_begin) {
+            tasks[i].g->rr_used = true;
             live.push_back(tasks[i]);
             dst.push_back(pools[i]);
             which.push_back(i);
@@ -366,6 +369,31 @@ int hyperim_stratify(hyperim_graph g, void *stream, hyperim_strata_info *out) {
         HIM_CHECK(stratify_device(g, *lk.prep, as_stream(stream)));
     }
     if (out) *out = g->info;
+    return HYPERIM_OK;
+}
+
+int hyperim_route(hyperim_graph g, uint32_t on, void *stream, uint32_t *n_r1) {
+    if (!g || on > 1) return HYPERIM_EINVAL;
+    g_detail.clear();
+    if (n_r1) *n_r1 = 0;
+    if (g->lt() || g->layered()) {
+        set_error_detail("the division of the RR sets applies to the independent-cascade models only");
+        return HYPERIM_EINVAL;
+    }
+    if (!g->stratified) return HYPERIM_ESTATE;
+    if (g->rr_used && (on != 0) != g->route_on) {
+        set_error_detail("RR sets were generated on this graph already: divide (or undo) before the first");
+        return HYPERIM_ESTATE;
+    }
+    HIM_CHECK(check_device(g));
+    g->route_on = on != 0;
+    g->routed = false;
+    uint32_t n1 = 0;
+    if (on) {
+        DeviceLock lk(g->device);
+        HIM_CHECK(route_build(g, as_stream(stream), &n1));
+    }
+    if (n_r1) *n_r1 = n1;
     return HYPERIM_OK;
 }
 

@@ -333,6 +333,20 @@ uint32_t grid_for(uint64_t items, uint32_t block = kBlock, uint32_t cap = 65535u
 
 }  // namespace
 
+// Exclusive prefix over all incidences of their channel counts |he| - 1: the
+// channels into v are chan[v_off[v]] .. chan[v_off[v + 1]] (needs v_hbs).
+// cnt and tmp are scratch the caller keeps alive until the stream has run.
+int channel_prefix(hyperim_graph g, DevBuf &cnt, DevBuf &tmp, hipStream_t s) {
+    const uint64_t nnz = g->nnz;
+    HIM_CHECK(g->chan.reserve(sizeof(uint64_t) * (nnz + 1), s));
+    HIM_CHECK(cnt.reserve(sizeof(uint32_t) * std::max<uint64_t>(nnz, 1), s));
+    if (nnz)
+        hipLaunchKernelGGL(k_channel_counts, dim3(grid_for(nnz, kBlock, 8192)), dim3(kBlock), 0, s, nnz,
+                           g->v_hbs.as<uint2>(), cnt.as<uint32_t>());
+    HIM_HIP(hipGetLastError());
+    return scan_u32_to_u64(cnt.as<uint32_t>(), g->chan.as<uint64_t>(), nnz, 0, tmp, s);
+}
+
 int graph_build_device(hyperim_graph g, PrepWorkspace &w, hipStream_t s) {
     const uint32_t n = g->n, m = g->m;
     const uint64_t nnz = g->nnz;
@@ -405,16 +419,7 @@ int graph_build_device(hyperim_graph g, PrepWorkspace &w, hipStream_t s) {
     if (nnz)
         hipLaunchKernelGGL(k_incidence_spans, dim3(grid_for(nnz, kBlock, 8192)), dim3(kBlock), 0, s, nnz,
                            g->v_he.as<uint32_t>(), g->he_off.as<uint32_t>(), g->v_hbs.as<uint2>());
-    if (g->lt() || g->layered()) {
-        // exclusive prefix over all incidences of their channel counts: the
-        // channels into v are chan[v_off[v]] .. chan[v_off[v + 1]]
-        HIM_CHECK(g->chan.reserve(sizeof(uint64_t) * (nnz + 1), s));
-        HIM_CHECK(chan_cnt.reserve(sizeof(uint32_t) * std::max<uint64_t>(nnz, 1), s));
-        if (nnz)
-            hipLaunchKernelGGL(k_channel_counts, dim3(grid_for(nnz, kBlock, 8192)), dim3(kBlock), 0, s, nnz,
-                               g->v_hbs.as<uint2>(), chan_cnt.as<uint32_t>());
-        HIM_CHECK(scan_u32_to_u64(chan_cnt.as<uint32_t>(), g->chan.as<uint64_t>(), nnz, 0, chan_tmp, s));
-    }
+    if (g->lt() || g->layered()) HIM_CHECK(channel_prefix(g, chan_cnt, chan_tmp, s));
     if (n) {
         hipLaunchKernelGGL(k_thresholds, dim3(grid_for(n)), dim3(kBlock), 0, s, n, g->prob.model, g->prob.p,
                            g->v_off.as<uint32_t>(), g->c.as<unsigned long long>(), g->thr.as<uint32_t>(),

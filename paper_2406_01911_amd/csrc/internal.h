@@ -185,11 +185,22 @@ struct hyperim_graph_s {
     hyperim::DevBuf lay_nb_off, lay_nb, lay_ly_off, lay_ly_end, lay_ln, lay_expm;
     uint32_t lay_lmax = 0;
     bool stratified = false;
+    uint32_t strat_lmax = 0;   // largest l_v (set by stratify)
+    // division of the RR sets into R1 / R2 (Section 4.1; hyperim_route):
+    // route_on = asked for (kept across stratify), routed = in effect (both
+    // sides non-empty); pool 0 roots route_P[0 .. route_n1), pool 1 the rest,
+    // each side's strata ending at route_B[side][h]; a pool-0 set of root v
+    // starts with force[force_off[v] .. force_off[v + 1])
+    bool route_on = false, routed = false;
+    uint32_t route_n1 = 0;
+    uint32_t route_B[2][HYPERIM_NSTRATA + 1] = {};
+    hyperim::DevBuf route_P, force_off, force;
     hyperim::DevBuf l, deg, top, stratum, P;
     hyperim_strata_info info{};
     hyperim_tuning tune{1024, 262144, 256, 512, 0xFFFFFFFFu, 8, 16384, 4, 6, 0xFFFFFFFFu, 1};  // RR execution parameters
     // learned from generated sets (launch-group and stage sizing, admission);
     // -1 = nothing generated yet
+    bool rr_used = false;   // RR sets have been generated on this graph
     double rr_members = -1.0, rr_defer = -1.0;
     uint64_t rr_seen_sets = 0, rr_seen_members = 0;
 };
@@ -256,6 +267,14 @@ int generate_into(const std::vector<RRTask> &tasks, const std::vector<hyperim_po
 
 // ---- launchers (graph.hip) --------------------------------------------------
 int graph_build_device(hyperim_graph g, PrepWorkspace &w, hipStream_t s);
+// chan of g (the channel prefix over its incidences); cnt / tmp: scratch
+int channel_prefix(hyperim_graph g, DevBuf &cnt, DevBuf &tmp, hipStream_t s);
+
+// ---- launchers (route.hip) ------------------------------------------------------
+// Division of g's RR sets into R1 / R2 (Section 4.1) from its strata and
+// layer tables (built here when missing); sets route_P, force_off, force,
+// route_n1, route_B and routed.  *n1 = the number of R1 vertices.
+int route_build(hyperim_graph g, hipStream_t s, uint32_t *n1);
 
 // ---- launchers (stratify.hip) -------------------------------------------------
 int stratify_device(hyperim_graph g, PrepWorkspace &w, hipStream_t s);

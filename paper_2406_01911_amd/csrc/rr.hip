@@ -102,6 +102,12 @@ struct GraphDesc {
     const unsigned long long *lay_nb_off, *lay_ly_off;
     const uint32_t *lay_nb, *lay_ly_end, *l;
     const double *lay_ln, *lay_expm;
+    // RR sets divided into R1 / R2 (Section 4.1): pool 0 draws its roots from
+    // rP[0 .. rn1), pool 1 from rP[rn1 .. n), and a pool-0 set starts with
+    // force[force_off[root] .. force_off[root + 1]) beside its root; else null
+    const uint32_t *rP, *force;
+    const unsigned long long *force_off;
+    uint32_t rn1;
 };
 
 // The same arrays as global-memory pointers: descriptors are read from device
@@ -109,9 +115,9 @@ struct GraphDesc {
 // flat loads.
 #define HIM_GLOBAL __attribute__((address_space(1)))
 struct GraphView {
-    const HIM_GLOBAL uint32_t *he_off, *he_mem, *v_off, *v_he, *thr, *P;
+    const HIM_GLOBAL uint32_t *he_off, *he_mem, *v_off, *v_he, *thr, *P, *rP;
     const HIM_GLOBAL unsigned long long *v_hbs;
-    uint32_t n, bm_words;
+    uint32_t n, bm_words, rn1;
 };
 
 // Descriptors are read at wave-uniform indices; their fields go to scalar
@@ -125,8 +131,10 @@ __device__ __forceinline__ GraphView graph_view(const GraphDesc &d) {
     v.thr = uni_ptr((const HIM_GLOBAL uint32_t *)d.thr);
     v.P = uni_ptr((const HIM_GLOBAL uint32_t *)d.P);
     v.v_hbs = uni_ptr((const HIM_GLOBAL unsigned long long *)d.v_hbs);
+    v.rP = uni_ptr((const HIM_GLOBAL uint32_t *)d.rP);
     v.n = uni(d.n);
     v.bm_words = uni(d.bm_words);
+    v.rn1 = uni(d.rn1);
     return v;
 }
 
@@ -208,7 +216,8 @@ __device__ __forceinline__ SetRef set_ref(const RRArgs &a, uint32_t t, uint64_t 
 // Stratified root of RR id j: block b of the ladder (Q = 2^qlog ids in block
 // 0, Q 2^(b-1) in block b >= 1, so block sizes are powers of two), offset
 // o_b = floor(x n / 2^64) from the block's Philox draw, root =
-// P[floor((t n + o_b) / T_b)] computed in 128-bit arithmetic.
+// P[floor((t n + o_b) / T_b)] computed in 128-bit arithmetic.  With the RR
+// sets divided, P and n are the pool's own root list and its length.
 __device__ __forceinline__ uint32_t rr_root(const GraphView &G, uint32_t qlog, uint64_t j, uint32_t pool, uint2 key) {
     const uint64_t Q = 1ull << qlog;
     uint32_t b, s;
@@ -223,16 +232,22 @@ __device__ __forceinline__ uint32_t rr_root(const GraphView &G, uint32_t qlog, u
         J = 1ull << hb;
         s = hb;
     }
+    const HIM_GLOBAL uint32_t *P = G.P;
+    uint64_t n = G.n;
+    if (G.rP != nullptr) {
+        P = pool == 0u ? G.rP : G.rP + G.rn1;
+        n = pool == 0u ? G.rn1 : G.n - G.rn1;
+    }
     const uint4 r = philox4x32_10(root_counter(b, pool), key);
     const uint64_t x = (uint64_t)r.x | ((uint64_t)r.y << 32);
-    const uint64_t o = __umul64hi(x, (uint64_t)G.n);
+    const uint64_t o = __umul64hi(x, n);
     const uint64_t t = j - J;
-    const uint64_t lo = t * (uint64_t)G.n;
-    uint64_t hi = __umul64hi(t, (uint64_t)G.n);
+    const uint64_t lo = t * n;
+    uint64_t hi = __umul64hi(t, n);
     const uint64_t lo2 = lo + o;
     hi += lo2 < lo ? 1ull : 0ull;
     const uint64_t pos = s == 0 ? lo2 : ((lo2 >> s) | (hi << (64u - s)));
-    return G.P[pos];
+    return P[pos];
 }
 
 template <bool kLds>
@@ -735,6 +750,27 @@ __device__ __forceinline__ void record_set(const RRArgs &a, uint64_t idx, uint64
 }
 
 // ---- phase A ---------------------------------------------------------------
+// A pool-0 set of a graph whose RR sets are divided (Section 4.1) starts
+// with the members of its root's small layers beside the root: they are
+// marked and appended before the traversal (every lane of the wave calls it).
+__device__ __forceinline__ void seed_forced(const GraphDesc &D, uint32_t root, uint32_t *bm, LocalAppend &app) {
+    const HIM_GLOBAL unsigned long long *fo = uni_ptr((const HIM_GLOBAL unsigned long long *)D.force_off);
+    if (fo == nullptr) return;
+    const HIM_GLOBAL uint32_t *fm = uni_ptr((const HIM_GLOBAL uint32_t *)D.force);
+    const uint64_t f0 = uni64(fo[root]), f1 = uni64(fo[root + 1]);
+    const uint32_t lane = lane_id();
+    for (uint64_t f = f0; f < f1; f += kWave) {
+        uint32_t u = 0;
+        bool fresh = false;
+        if (f + lane < f1) {
+            u = fm[f + lane];
+            const uint32_t bit = 1u << (u & 31);
+            fresh = (atomicOr(&bm[u >> 5], bit) & bit) == 0u;
+        }
+        app.push1(fresh, u);
+    }
+}
+
 template <bool kLdsBitmap, bool kGaps>
 __global__ __launch_bounds__(kWG) void k_rr_light(RRArgs a) {
     using Lds = typename std::conditional<kLdsBitmap, WaveLdsCore, WaveLds>::type;
@@ -771,6 +807,7 @@ __global__ __launch_bounds__(kWG) void k_rr_light(RRArgs a) {
             atomicOr(&bm[root >> 5], 1u << (root & 31));
         }
         LocalAppend app{list, 1u, G.n};
+        if (S.pool == 0u) seed_forced(a.graphs[uni(a.tasks[task].graph)], root, bm, app);
         uint32_t head = 0;
         uint64_t spent = 0;
         bool deferred = false;
@@ -1617,6 +1654,15 @@ __global__ __launch_bounds__(kWG) void k_ms_roots(MsArgs m, RRArgs a) {
     const uint32_t b = (uint32_t)(i / kMsSets), s = (uint32_t)(i % kMsSets);
     const unsigned long long old = atomicOr(&m.nxt[(uint64_t)b * m.stride + root], 1ull << s);
     if (old == 0ull) ms_append_next(m, b, root);
+    // divided RR sets (Section 4.1): a pool-0 set also starts from the
+    // members of its root's small layers
+    if (m.pool == 0u && m.graph.force_off != nullptr) {
+        for (unsigned long long f = m.graph.force_off[root]; f < m.graph.force_off[root + 1]; ++f) {
+            const uint32_t u = m.graph.force[f];
+            const unsigned long long o2 = atomicOr(&m.nxt[(uint64_t)b * m.stride + u], 1ull << s);
+            if (o2 == 0ull) ms_append_next(m, b, u);
+        }
+    }
 }
 
 // New level: the vertices reached in the last one, with the sets that did not
@@ -2186,6 +2232,30 @@ __global__ __launch_bounds__(kWG) void k_weight_sum(const uint32_t *__restrict__
 }
 
 // ---- host side -------------------------------------------------------------
+
+// The descriptor of one graph in a launch group.
+GraphDesc graph_desc(hyperim_graph g) {
+    GraphDesc d{g->he_off.as<uint32_t>(), g->he_mem.as<uint32_t>(), g->v_off.as<uint32_t>(),
+                g->v_he.as<uint32_t>(), g->thr.as<uint32_t>(), g->P.as<uint32_t>(),
+                g->v_hbs.as<unsigned long long>(), g->n, (uint32_t)(((uint64_t)g->n + 31u) / 32u),
+                g->lt() ? g->chan.as<unsigned long long>() : nullptr};
+    if (g->layered()) {
+        d.lay_nb_off = g->lay_nb_off.as<unsigned long long>();
+        d.lay_ly_off = g->lay_ly_off.as<unsigned long long>();
+        d.lay_nb = g->lay_nb.as<uint32_t>();
+        d.lay_ly_end = g->lay_ly_end.as<uint32_t>();
+        d.l = g->l.as<uint32_t>();
+        d.lay_ln = g->lay_ln.as<double>();
+        d.lay_expm = g->lay_expm.as<double>();
+    }
+    if (g->routed) {
+        d.rP = g->route_P.as<uint32_t>();
+        d.force = g->force.as<uint32_t>();
+        d.force_off = g->force_off.as<unsigned long long>();
+        d.rn1 = g->route_n1;
+    }
+    return d;
+}
 struct LaunchShape {
     uint32_t grid;        // phase A workgroups at full occupancy (one slot per wave)
     uint32_t slots;       // total slots (phase A waves + spare slots for deferred sets)
@@ -2282,7 +2352,9 @@ int ensure_workspace(RRWorkspace &ws, uint32_t n_max, hipStream_t s, LaunchShape
 void stratum_ranges(hyperim_graph g, uint64_t seed, uint32_t instance, uint32_t qlog, uint32_t pool,
                     uint64_t id_begin, uint64_t id_end, std::vector<std::pair<uint64_t, uint64_t>> *out) {
     const uint64_t Q = 1ull << qlog;
-    const uint32_t n = g->n;
+    // with the RR sets divided, the pool's own root list and its strata
+    const uint32_t n = g->routed ? (pool == 0 ? g->route_n1 : g->n - g->route_n1) : g->n;
+    const uint32_t *B = g->routed ? g->route_B[pool ? 1 : 0] : g->info.B;
     uint64_t j = id_begin;
     while (j < id_end) {
         uint32_t b;
@@ -2307,7 +2379,7 @@ void stratum_ranges(hyperim_graph g, uint64_t seed, uint32_t instance, uint32_t 
                 th = T;
             } else {
                 // first t with floor((t n + o) / T) >= B_h
-                unsigned __int128 need = (unsigned __int128)g->info.B[h] * T;
+                unsigned __int128 need = (unsigned __int128)B[h] * T;
                 th = need <= o ? 0 : (uint64_t)((need - o + n - 1) / n);
                 th = std::min<uint64_t>(th, T);
             }
@@ -2724,9 +2796,7 @@ int run_ms_launch(RRWorkspace &ws, RRStats &st, const hyperim_tuning &tune, RRAr
     HIM_CHECK(ws.ms_vcnt.reserve(sizeof(uint32_t) * (uint64_t)nbundles * nvb * kMsSets, s));
     HIM_CHECK(ws.ms_ctr.reserve(sizeof(unsigned long long) * kMsNumCtr, s));
     MsArgs m{};
-    m.graph = GraphDesc{g->he_off.as<uint32_t>(), g->he_mem.as<uint32_t>(), g->v_off.as<uint32_t>(),
-                        g->v_he.as<uint32_t>(), g->thr.as<uint32_t>(), g->P.as<uint32_t>(), g->v_hbs.as<unsigned long long>(), n,
-                        (uint32_t)(((uint64_t)n + 31u) / 32u)};
+    m.graph = graph_desc(g);
     m.bytesw = g->bytesw.as<unsigned long long>();
     m.first_id = t.first_id;
     m.pool = t.pool;
@@ -2953,20 +3023,7 @@ int rr_generate_into(RRWorkspace &ws, RRStats &st, const std::vector<RRTask> &ta
         if (gid.count(t.g)) continue;
         gid[t.g] = (uint32_t)gdesc.size();
         hyperim_graph g = t.g;
-        GraphDesc d{g->he_off.as<uint32_t>(), g->he_mem.as<uint32_t>(), g->v_off.as<uint32_t>(),
-                    g->v_he.as<uint32_t>(), g->thr.as<uint32_t>(), g->P.as<uint32_t>(),
-                    g->v_hbs.as<unsigned long long>(), g->n, (uint32_t)(((uint64_t)g->n + 31u) / 32u),
-                    g->lt() ? g->chan.as<unsigned long long>() : nullptr};
-        if (g->layered()) {
-            d.lay_nb_off = g->lay_nb_off.as<unsigned long long>();
-            d.lay_ly_off = g->lay_ly_off.as<unsigned long long>();
-            d.lay_nb = g->lay_nb.as<uint32_t>();
-            d.lay_ly_end = g->lay_ly_end.as<uint32_t>();
-            d.l = g->l.as<uint32_t>();
-            d.lay_ln = g->lay_ln.as<double>();
-            d.lay_expm = g->lay_expm.as<double>();
-        }
-        gdesc.push_back(d);
+        gdesc.push_back(graph_desc(g));
         n_max = std::max(n_max, g->n);
     }
     uint64_t count = 0;

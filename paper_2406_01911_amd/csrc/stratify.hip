@@ -414,8 +414,15 @@ int stratify_device(hyperim_graph g, PrepWorkspace &w, hipStream_t s) {
     info.alpha = info.sum_deg ? (double)info.sum_top / (double)info.sum_deg : 0.0;
     info.beta = n ? (double)info.sum_l / (double)n : 0.0;
     info.theta_l = n ? tl / (double)n : 0.0;
+    g->strat_lmax = lmax;
     if (g->layered()) HIM_CHECK(layers_build_device(g, lmax, s));
     g->stratified = true;
+    // a divided graph keeps its division (the same strata give the same one)
+    g->routed = false;
+    if (g->route_on) {
+        uint32_t n1 = 0;
+        HIM_CHECK(route_build(g, s, &n1));
+    }
     return HYPERIM_OK;
 }
 
