@@ -15,7 +15,9 @@ gains equal the baseline's (they must: every schedule gives the same bytes).
     python -m paper_2406_01911_amd.autotune --workload mid
 
 writes tuning/<workload>.json beside this file; Graph.apply_tuning / the
-bench's --tuning flag read it back.
+bench's --tuning flag read it back.  `--workload multi` tunes the
+64-instance workload: one tuning applied to every graph, each candidate
+timed on one batched round of all instances.
 """
 from __future__ import annotations
 
@@ -95,6 +97,66 @@ def autotune(g, k: int, eps: float, ell: float = 1.0, seed: int = 0, theta: int 
     return {"tuning": cur, "ms_rr": cur_ms, "baseline_ms_rr": base_ms, "theta": theta, "trials": trials}
 
 
+def _measure_batch(hy, gs, ws, theta, reps, stream):
+    """Best RR time of one batched round (all instances, shared launch
+    groups) over `reps` runs, and that run's per-query results."""
+    best, out = None, None
+    qs = [dict(graph=g, k=w.k, eps=w.eps, ell=w.ell, seed=w.philox_seed, instance=i)
+          for i, (g, w) in enumerate(zip(gs, ws))]
+    for _ in range(reps):
+        tot = {}
+        rs = hy.select_seeds_batch(qs, theta_fixed=theta, stream=stream, totals=tot)
+        t = tot["ms_rr"]
+        if best is None or t < best:
+            best, out = t, rs
+    return best, out
+
+
+def autotune_batch(gs, ws, theta: int, space: dict | None = None, reps: int = 2, sweeps: int = 1, stream=None,
+                   log=None) -> dict:
+    """Coordinate descent as `autotune`, for many instances answered in one
+    batch: a candidate is applied to every graph and timed on one batched
+    round at `theta` sets per pool; it is kept only if every query's seeds
+    and gains equal the baseline's."""
+    import paper_2406_01911_amd as hy
+    space = space or SPACE
+    start = gs[0].tuning()
+    for g in gs:
+        g.set_tuning(**start)
+    _measure_batch(hy, gs, ws, theta, 1, stream)   # warm-up
+    base_ms, base = _measure_batch(hy, gs, ws, theta, reps, stream)
+    cur, cur_ms = dict(start), base_ms
+    trials = [{"tuning": dict(cur), "ms_rr": base_ms}]
+    for sweep in range(sweeps):
+        improved = False
+        for name, values in space.items():
+            for v in values:
+                if v == cur[name]:
+                    continue
+                cand = dict(cur)
+                cand[name] = v
+                if cand["seg"] < cand["chunk"]:
+                    continue
+                for g in gs:
+                    g.set_tuning(**cand)
+                ms, rs = _measure_batch(hy, gs, ws, theta, reps, stream)
+                for a, b in zip(rs, base):
+                    if not (np.array_equal(a["seeds"], b["seeds"]) and np.array_equal(a["gains"], b["gains"])):
+                        raise RuntimeError(f"tuning {cand} changed a result")
+                trials.append({"tuning": dict(cand), "ms_rr": ms})
+                if log:
+                    log(f"[autotune] sweep {sweep} {name}={v}: {ms:.1f} ms (best {cur_ms:.1f})")
+                if ms < cur_ms * 0.98:
+                    cur, cur_ms, improved = cand, ms, True
+            for g in gs:
+                g.set_tuning(**cur)
+        if not improved:
+            break
+    for g in gs:
+        g.set_tuning(**cur)
+    return {"tuning": cur, "ms_rr": cur_ms, "baseline_ms_rr": base_ms, "theta": theta, "trials": trials}
+
+
 def tuning_path(workload: str) -> str:
     return os.path.join(TUNING_DIR, f"{workload}.json")
 
@@ -122,17 +184,33 @@ def main():
     import hypergen
     import paper_2406_01911_amd as hy
     hy.load_library()
-    w = hypergen.workload(args.workload)
-    hg = w.build()
-    g = hy.build_graph(hg.n, hg.he_off, hg.he_mem, w.model, w.p)
-    g.stratify()
     t0 = time.time()
     space = {k: v for k, v in SPACE.items() if not args.params or k in args.params.split(",")}
     stored = load(args.workload)
-    if stored:
-        g.set_tuning(**stored)   # refine the stored result
-    res = autotune(g, w.k, w.eps, w.ell, seed=w.philox_seed, theta=args.theta or None, space=space,
-                   reps=args.reps, sweeps=args.sweeps, log=lambda m: print(m, file=sys.stderr, flush=True))
+    log = lambda m: print(m, file=sys.stderr, flush=True)   # noqa: E731
+    if args.workload == "multi":
+        # the 64-instance workload: one tuning for every graph, timed on one
+        # batched round
+        ws = hypergen.multi_instance_workloads(64)
+        gs = []
+        for wl in ws:
+            hg = wl.build()
+            g = hy.build_graph(hg.n, hg.he_off, hg.he_mem, wl.model, wl.p)
+            g.stratify()
+            if stored:
+                g.set_tuning(**stored)
+            gs.append(g)
+        log(f"[autotune] multi: {len(gs)} graphs built ({time.time() - t0:.1f} s)")
+        res = autotune_batch(gs, ws, args.theta or 1024, space=space, reps=args.reps, sweeps=args.sweeps, log=log)
+    else:
+        w = hypergen.workload(args.workload)
+        hg = w.build()
+        g = hy.build_graph(hg.n, hg.he_off, hg.he_mem, w.model, w.p)
+        g.stratify()
+        if stored:
+            g.set_tuning(**stored)   # refine the stored result
+        res = autotune(g, w.k, w.eps, w.ell, seed=w.philox_seed, theta=args.theta or None, space=space,
+                       reps=args.reps, sweeps=args.sweeps, log=log)
     res["workload"] = args.workload
     res["seconds"] = time.time() - t0
     out = args.out or tuning_path(args.workload)
