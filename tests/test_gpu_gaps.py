@@ -174,6 +174,7 @@ def test_large_gaps_sampled_sets_under_stored_tuning_exact(hy):
     tuning = autotune.load("large_gaps")
     assert tuning is not None
     g.set_tuning(**tuning)
+    _flush(f"[gpu] large_gaps: tuning {tuning}")
     ids = 4096
     pools = {tag: hy.Pool(g) for tag in (0, 1)}
     _flush(f"[gpu] large_gaps: both pools [0, {ids}) under the stored tuning")
