@@ -35,14 +35,14 @@ TUNING_DIR = os.path.join(HERE, "tuning")
 SPACE = {
     "heavy": [256, 512, 1024, 2048, 4096],
     "budget": [4096, 8192, 16384, 32768, 65536],
-    "chunk": [128, 256, 512, 1024],
-    "seg": [256, 512, 1024, 2048],
+    "chunk": [128, 256, 512, 1024, 2048, 4096],
+    "seg": [256, 512, 1024, 2048, 4096, 8192],
     "prefilter_min": [256, 1024, 4096, 16384, 1 << 30],
     "steps_per_sync": [2, 4, 8, 16, 32],
     "blocks_a": [2, 3, 4, 6, 8],
     "blocks_b": [3, 4, 6, 8],
     "ms_min": [1024, 4096, 65536, 0xFFFFFFFF],
-    "ms_filter": [1, 4, 8, 16, 24, 40, 65],
+    "ms_filter": [1, 4, 6, 8, 12, 16, 24, 40, 65],
 }
 
 
