@@ -243,9 +243,10 @@ int hyperim_stratify(hyperim_graph g, void *stream, hyperim_strata_info *out);
  * times the mean over the R2 vertices only, not the spread.  on = 0 undoes it.
  * When every vertex or none has a small layer the division is inert.
  * Independent-cascade models only (HYPERIM_EINVAL otherwise); needs
- * hyperim_stratify first (HYPERIM_ESTATE), and must come before the first RR
- * set is generated on the graph (HYPERIM_ESTATE after); a later
- * hyperim_stratify keeps it.  Builds the layer tables of A(v) on the device
+ * hyperim_stratify first (HYPERIM_ESTATE); switching the division on or off
+ * after the graph's first RR set gives HYPERIM_ESTATE (pools would mix both
+ * kinds of sets); a later hyperim_stratify keeps it; a failed call leaves
+ * the graph undivided.  Builds the layer tables of A(v) on the device
  * when the graph has none (HYPERIM_EINVAL beyond 2^32 co-member occurrences
  * or 16384 layers).  *n_r1 (may be NULL) receives the number of R1 vertices. */
 int hyperim_route(hyperim_graph g, uint32_t on, void *stream, uint32_t *n_r1);

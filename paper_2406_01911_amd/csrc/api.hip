@@ -386,12 +386,13 @@ int hyperim_route(hyperim_graph g, uint32_t on, void *stream, uint32_t *n_r1) {
         return HYPERIM_ESTATE;
     }
     HIM_CHECK(check_device(g));
-    g->route_on = on != 0;
     g->routed = false;
+    g->route_on = false;   // set once the tables are built (a failed build leaves the graph undivided)
     uint32_t n1 = 0;
     if (on) {
         DeviceLock lk(g->device);
         HIM_CHECK(route_build(g, as_stream(stream), &n1));
+        g->route_on = true;
     }
     if (n_r1) *n_r1 = n1;
     return HYPERIM_OK;
