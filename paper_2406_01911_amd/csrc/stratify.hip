@@ -421,7 +421,11 @@ int stratify_device(hyperim_graph g, PrepWorkspace &w, hipStream_t s) {
     g->routed = false;
     if (g->route_on) {
         uint32_t n1 = 0;
-        HIM_CHECK(route_build(g, s, &n1));
+        const int rc = route_build(g, s, &n1);
+        if (rc != HYPERIM_OK) {
+            g->route_on = false;   // left undivided, as after a failed hyperim_route
+            return rc;
+        }
     }
     return HYPERIM_OK;
 }
