@@ -455,16 +455,17 @@ __device__ __forceinline__ void test_run(const GraphView &G, uint64_t j, uint32_
         }
         app.push8(fresh, u);
     } else {
-        uint32_t cnt = 0;
-#pragma unroll
-        for (uint32_t t = 0; t < kRun; ++t) cnt += live[t] ? 1u : 0u;
-        const uint32_t incl = wave_incl_scan(cnt);
-        const uint32_t tot = uni(wave_bcast(incl, kWave - 1));
+        // placement from one ballot per position (as in ms_pair)
+        static_assert(kRun == 4, "one ballot per run position");
+        const uint64_t b0 = __ballot(live[0]), b1 = __ballot(live[1]), b2 = __ballot(live[2]), b3 = __ballot(live[3]);
+        const uint32_t c0 = (uint32_t)__popcll(b0), c1 = (uint32_t)__popcll(b1), c2 = (uint32_t)__popcll(b2);
+        const uint32_t tot = c0 + c1 + c2 + (uint32_t)__popcll(b3);
         if (nlive + tot > kLiveCap) flush_live(bm, L, nlive, app);
-        uint32_t at = nlive + incl - cnt;
-#pragma unroll
-        for (uint32_t t = 0; t < kRun; ++t)
-            if (live[t]) L.live[at++] = u[t];
+        const uint64_t below = (1ull << lane_id()) - 1ull;
+        if (live[0]) L.live[nlive + (uint32_t)__popcll(b0 & below)] = u[0];
+        if (live[1]) L.live[nlive + c0 + (uint32_t)__popcll(b1 & below)] = u[1];
+        if (live[2]) L.live[nlive + c0 + c1 + (uint32_t)__popcll(b2 & below)] = u[2];
+        if (live[3]) L.live[nlive + c0 + c1 + c2 + (uint32_t)__popcll(b3 & below)] = u[3];
         nlive += tot;
     }
 }
@@ -1860,15 +1861,19 @@ __device__ __forceinline__ void ms_pair(const MsArgs &m, MsLds &L, uint32_t &nli
 #pragma unroll
     for (uint32_t t = 0; t < 4; ++t)
         lv |= (act && ((cand4 >> t) & 1u) && channel_live(w[t], thr)) ? 1u << t : 0u;
-    if (__ballot(lv != 0u) == 0) return;   // with small probabilities most pairs have no live channel
-    const uint32_t cnt = (uint32_t)__popc(lv);
-    const uint32_t incl = wave_incl_scan(cnt);
-    const uint32_t tot = uni(wave_bcast(incl, kWave - 1));
+    // placement from one ballot per position: the live channels of position
+    // t follow those of positions < t, in lane order
+    const uint64_t b0 = __ballot(lv & 1u), b1 = __ballot(lv & 2u), b2 = __ballot(lv & 4u), b3 = __ballot(lv & 8u);
+    if ((b0 | b1 | b2 | b3) == 0ull) return;   // with small probabilities most pairs have no live channel
+    const uint32_t c0 = (uint32_t)__popcll(b0), c1 = (uint32_t)__popcll(b1), c2 = (uint32_t)__popcll(b2);
+    const uint32_t tot = c0 + c1 + c2 + (uint32_t)__popcll(b3);
     if (nlive + tot > kMsLiveCap) ms_flush(m, L, nlive);
-    uint32_t at = nlive + incl - cnt;
-#pragma unroll
-    for (uint32_t t = 0; t < 4; ++t)
-        if ((lv >> t) & 1u) L.live[at++] = make_uint2(u[t], (bnd << 6) | s);
+    const uint64_t below = (1ull << lane_id()) - 1ull;
+    const uint32_t tag = (bnd << 6) | s;
+    if (lv & 1u) L.live[nlive + (uint32_t)__popcll(b0 & below)] = make_uint2(u[0], tag);
+    if (lv & 2u) L.live[nlive + c0 + (uint32_t)__popcll(b1 & below)] = make_uint2(u[1], tag);
+    if (lv & 4u) L.live[nlive + c0 + c1 + (uint32_t)__popcll(b2 & below)] = make_uint2(u[2], tag);
+    if (lv & 8u) L.live[nlive + c0 + c1 + c2 + (uint32_t)__popcll(b3 & below)] = make_uint2(u[3], tag);
     nlive += tot;
 }
 
