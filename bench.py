@@ -217,12 +217,13 @@ def main():
     from paper_2406_01911_amd import autotune
     tuning = autotune.load(args.workload) if args.tuning == "stored" else None
     # timed steps: the production path (superstep batches replayed as captured
-    # graphs) plus one extra pass that sums the final pools' work
-    # (incidences, coins, Philox blocks, algorithmic bytes)
-    flags_prod = hy.FLAG_INCIDENCES | (hy.FLAG_NO_GRAPHS if args.no_graphs else 0)
-    # one instrumented step: every expansion launch timed by events its
-    # launch stamps (direct launches: events recorded inside a captured graph
-    # do not time against the stream)
+    # graphs), nothing else
+    flags_prod = hy.FLAG_NO_GRAPHS if args.no_graphs else 0
+    # one instrumented step after them: every expansion launch timed by events
+    # its launch stamps (direct launches: events recorded inside a captured
+    # graph do not time against the stream), plus the extra pass that sums the
+    # final pools' work (incidences, coins, Philox blocks, algorithmic bytes);
+    # the ids, and so the work, are those of every timed step
     flags_inst = hy.FLAG_INCIDENCES | hy.FLAG_KERNEL_TIMES
 
     def step(form, flags=flags_prod):
@@ -313,13 +314,13 @@ def main():
     lt = args.workload in LT_WORKLOADS
     layered = args.workload in LAYERED_WORKLOADS
     gaps = args.workload in GAPS_WORKLOADS
-    kernel_bytes = mtot["bytes_light"] + mtot["bytes_heavy"] + mtot["bytes_bundled"]
+    kernel_bytes = itot["bytes_light"] + itot["bytes_heavy"] + itot["bytes_bundled"]
     # the kernels count the bytes of every expansion they perform; the pools'
     # final prefixes can only hold fewer (sets generated ahead of a round that
     # was not reached are spent work).  A linear-threshold walk reads one
     # channel per step, and the gap sampler reads only the live positions of a
     # hyperedge: their algorithmic bytes are the kernels' own count.
-    alg_bytes = kernel_bytes if (lt or layered or gaps) else mtot["alg_bytes"]
+    alg_bytes = kernel_bytes if (lt or layered or gaps) else itot["alg_bytes"]
     assert kernel_bytes >= alg_bytes, (kernel_bytes, alg_bytes)
     # dominant expansion kernel: the largest event-timed share in the
     # instrumented step
@@ -391,9 +392,9 @@ def main():
                    "tuning": tuning if tuning else "default",
                    "parallelism": "single-gpu"},
         # channel-model figures (IC); the other models draw per step or per layer
-        "incidences_per_s": None if (lt or layered) else mtot["incidences"] * per_s,
-        "coins_per_s": mtot["philox_drawn"] * per_s if (lt or layered or gaps) else mtot["coins"] * per_s,
-        "philox_blocks_per_s": {"drawn": mtot["philox_drawn"] * per_s, "per_set_traversal": mtot["philox_alg"] * per_s},
+        "incidences_per_s": None if (lt or layered) else itot["incidences"] * per_s,
+        "coins_per_s": mtot["philox_drawn"] * per_s if (lt or layered or gaps) else itot["coins"] * per_s,
+        "philox_blocks_per_s": {"drawn": mtot["philox_drawn"] * per_s, "per_set_traversal": itot["philox_alg"] * per_s},
         "time_to_seed_set_ms": ms_per_step,
         "theta": [r["theta"] for r in last] if len(last) > 1 else last[0]["theta"],
         "rounds": max(r["rounds"] for r in last),
