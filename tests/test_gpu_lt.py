@@ -171,3 +171,40 @@ def test_lt_query_batched_with_ic_query_matches_alone_and_oracle(hy):
     o.stratify()
     ro = o.select_seeds(w.k, w.eps, w.ell, seed=0, instance=0)
     assert np.array_equal(rs[0]["seeds"], ro["seeds"]) and rs[0]["theta"] == ro["theta"]
+
+
+def test_large_lt_sampled_sets_exact(hy):
+    """large_lt (|V| = 1e6, |HE| = 2e6) as the benchmark runs it: both pools'
+    ids [0, 4096) in one generation call; sampled ids, including the longest
+    walks, regenerated one by one by the oracle, equal the library's sets and
+    roots."""
+    import concurrent.futures as cf
+    import os
+    _flush("[gpu] large_lt: generating the hypergraph")
+    w = hypergen.workload("large_lt")
+    hg = w.build()
+    g = hy.build_graph(hg.n, hg.he_off, hg.he_mem, w.model, w.p)
+    g.stratify()
+    ids = 4096
+    pools = {tag: hy.Pool(g) for tag in (0, 1)}
+    hy.generate_rr_batch([dict(graph=g, pool=pools[tag], seed=w.philox_seed, instance=0, pool_tag=tag,
+                               id_begin=0, id_end=ids) for tag in (0, 1)])
+    _flush("[gpu] large_lt: oracle graph and strata (about a minute)")
+    o = oracle.Graph(hg, w.model, w.p)
+    o.stratify()
+    rng = np.random.default_rng(17)
+    checks = []
+    for tag in (0, 1):
+        off, mem, roots = pools[tag].read()
+        sizes = np.diff(off)
+        big = [int(j) for j in np.argsort(sizes, kind="stable")[-4:]]
+        pick = big + [int(j) for j in rng.choice(ids, size=12, replace=False) if int(j) not in big]
+        for j in pick:
+            checks.append((tag, j, mem[off[j]:off[j + 1]].copy(), int(roots[j])))
+    threads = max(1, min(len(checks), int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)))
+    with cf.ThreadPoolExecutor(max_workers=threads) as ex:
+        ref = list(ex.map(lambda c: (o.rr_set(w.philox_seed, 0, c[0], c[1]), o.root(w.philox_seed, 0, c[0], c[1])),
+                          checks))
+    for (tag, j, got, root), (want, wroot) in zip(checks, ref):
+        assert root == wroot, (tag, j)
+        assert np.array_equal(got, want), (tag, j, got.size, want.size)
