@@ -131,3 +131,40 @@ def test_layered_lt_and_ic_in_one_generation_call(hy):
         off, mem, roots = pl.read()
         roff, rmem, rroots = o.generate(4, i, tag, 0, 1200)
         assert np.array_equal(roots, rroots) and np.array_equal(off, roff) and np.array_equal(mem, rmem), (i, tag)
+
+
+def test_large_layered_sampled_sets_exact(hy):
+    """large_layered (|V| = 1e6, |HE| = 2e6; 3.4e8 co-member occurrences in
+    the layer tables) as the benchmark runs it: both pools' ids [0, 4096) in
+    one generation call; sampled ids, including the largest sets, equal the
+    oracle's sets and roots."""
+    import concurrent.futures as cf
+    import os
+    _flush("[gpu] large_layered: generating the hypergraph")
+    w = hypergen.workload("large_layered")
+    hg = w.build()
+    g = hy.build_graph(hg.n, hg.he_off, hg.he_mem, w.model, w.p)
+    g.stratify()
+    ids = 4096
+    pools = {tag: hy.Pool(g) for tag in (0, 1)}
+    hy.generate_rr_batch([dict(graph=g, pool=pools[tag], seed=w.philox_seed, instance=0, pool_tag=tag,
+                               id_begin=0, id_end=ids) for tag in (0, 1)])
+    _flush("[gpu] large_layered: oracle graph, strata and layer tables (one to two minutes)")
+    o = oracle.Graph(hg, w.model, w.p)
+    o.stratify()
+    rng = np.random.default_rng(19)
+    checks = []
+    for tag in (0, 1):
+        off, mem, roots = pools[tag].read()
+        sizes = np.diff(off)
+        big = [int(j) for j in np.argsort(sizes, kind="stable")[-4:]]
+        pick = big + [int(j) for j in rng.choice(ids, size=12, replace=False) if int(j) not in big]
+        for j in pick:
+            checks.append((tag, j, mem[off[j]:off[j + 1]].copy(), int(roots[j])))
+    threads = max(1, min(len(checks), int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)))
+    with cf.ThreadPoolExecutor(max_workers=threads) as ex:
+        ref = list(ex.map(lambda c: (o.rr_set(w.philox_seed, 0, c[0], c[1]), o.root(w.philox_seed, 0, c[0], c[1])),
+                          checks))
+    for (tag, j, got, root), (want, wroot) in zip(checks, ref):
+        assert root == wroot, (tag, j)
+        assert np.array_equal(got, want), (tag, j, got.size, want.size)
