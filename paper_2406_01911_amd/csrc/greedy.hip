@@ -542,8 +542,19 @@ int greedy_device(GreedyWorkspace &w, hyperim_graph g, hyperim_pool p, uint64_t 
     // the graph
     const uint32_t argmax_grid = grid_for(n, 4 * 2 * kWG, 1024);   // two quads of vertices per thread
     const uint32_t inval_grid = 256;
-    GreedyParams hp{p->off,   p->mem, w.inv_off.as<uint64_t>(), w.inv.as<uint32_t>(), w.cursor.as<uint32_t>(),
-                    w.covered.as<uint32_t>(), w.cnt.as<uint32_t>(), w.chosen.as<uint8_t>(), seeds, gains, best, n};
+    GreedyParams hp{};   // the top-k fields are set below
+    hp.off = p->off;
+    hp.mem = p->mem;
+    hp.inv_off = w.inv_off.as<uint64_t>();
+    hp.inv = w.inv.as<uint32_t>();
+    hp.nsmall = w.cursor.as<uint32_t>();
+    hp.covered = w.covered.as<uint32_t>();
+    hp.cnt = w.cnt.as<uint32_t>();
+    hp.chosen = w.chosen.as<uint8_t>();
+    hp.seeds = seeds;
+    hp.gains = gains;
+    hp.best = best;
+    hp.n = n;
     // Equation (8): levels of kTkBins-bin histograms over the counts' bits
     // (every count is at most theta)
     uint32_t levels = 0;

@@ -2240,10 +2240,17 @@ __global__ __launch_bounds__(kWG) void k_weight_sum(const uint32_t *__restrict__
 
 // The descriptor of one graph in a launch group.
 GraphDesc graph_desc(hyperim_graph g) {
-    GraphDesc d{g->he_off.as<uint32_t>(), g->he_mem.as<uint32_t>(), g->v_off.as<uint32_t>(),
-                g->v_he.as<uint32_t>(), g->thr.as<uint32_t>(), g->P.as<uint32_t>(),
-                g->v_hbs.as<unsigned long long>(), g->n, (uint32_t)(((uint64_t)g->n + 31u) / 32u),
-                g->lt() ? g->chan.as<unsigned long long>() : nullptr};
+    GraphDesc d{};   // fields of other models stay null
+    d.he_off = g->he_off.as<uint32_t>();
+    d.he_mem = g->he_mem.as<uint32_t>();
+    d.v_off = g->v_off.as<uint32_t>();
+    d.v_he = g->v_he.as<uint32_t>();
+    d.thr = g->thr.as<uint32_t>();
+    d.P = g->P.as<uint32_t>();
+    d.v_hbs = g->v_hbs.as<unsigned long long>();
+    d.n = g->n;
+    d.bm_words = (uint32_t)(((uint64_t)g->n + 31u) / 32u);
+    if (g->lt()) d.chan = g->chan.as<unsigned long long>();
     if (g->layered()) {
         d.lay_nb_off = g->lay_nb_off.as<unsigned long long>();
         d.lay_ly_off = g->lay_ly_off.as<unsigned long long>();
