@@ -117,3 +117,24 @@ def test_p_one_components_and_p_zero_root():
     g0.stratify()
     for j in range(30):
         assert np.array_equal(g0.rr_set(0, 0, 0, j), [g0.root(0, 0, 0, j)])
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_gap_draw_bounds_and_special_words(seed):
+    """Over random (p, G): the gap lies in [0, G]; the largest word gives the
+    longest gap and word 0 the shortest (t = 1 needs q^g >= 1); p = 1 (q = 0)
+    makes every position live (gap 0) and p = 0 none (gap G); and the gap
+    never decreases as the word grows."""
+    rng = np.random.default_rng(100 + seed)
+    for _ in range(300):
+        p = float(rng.choice([rng.uniform(1e-6, 1e-3), rng.uniform(1e-3, 0.5), rng.uniform(0.5, 1.0)]))
+        q = 1.0 - p
+        G = int(rng.integers(1, 1 << int(rng.integers(1, 27))))
+        xs = np.sort(rng.integers(0, 1 << 32, size=6))
+        gs = [oracle.gap_draw(q, int(x), G) for x in xs]
+        assert all(0 <= g <= G for g in gs)
+        assert all(a <= b for a, b in zip(gs, gs[1:]))
+        assert oracle.gap_draw(q, 0, G) == 0
+        assert oracle.gap_draw(q, (1 << 32) - 1, G) >= gs[-1]
+        assert oracle.gap_draw(0.0, int(xs[0]), G) == 0
+        assert oracle.gap_draw(1.0, int(xs[0]), G) == G
