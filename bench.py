@@ -226,12 +226,13 @@ def main():
     # the ids, and so the work, are those of every timed step
     flags_inst = hy.FLAG_INCIDENCES | hy.FLAG_KERNEL_TIMES
 
-    def step(form, flags=flags_prod):
+    def step(form, flags=flags_prod, inputs=dev):
         """One query step: build + stratify every graph, then seed selection
         (one query, or all instances batched; form 1 runs them one by one in
-        the plain per-stratum form)."""
+        the plain per-stratum form).  `inputs` holds each graph's (he_off,
+        he_mem): device tensors, or host arrays that build_graph copies over."""
         gs = []
-        for h, (o, m), wl in zip(hgs, dev, ws):
+        for h, (o, m), wl in zip(hgs, inputs, ws):
             g = hy.build_graph(h.n, o, m, wl.model, wl.p, stream=stream)
             g.stratify(stream=stream)
             if tuning:
@@ -303,6 +304,20 @@ def main():
     for a, b in zip(inst_res, last):
         assert np.array_equal(a["seeds"], b["seeds"]) and a["theta"] == b["theta"]
     print("[bench] instrumented step done", file=sys.stderr, flush=True)
+    # the same step with the input handed over in host memory: build_graph
+    # copies it across PCIe inside the step (reported beside the line; the
+    # line's value keeps the input resident in HBM)
+    host_in = [(h.he_off, h.he_mem) for h in hgs]
+    host_steps = 1 if big else min(args.steps, 5)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(host_steps):
+        hres, _ = step(args.form, inputs=host_in)
+    torch.cuda.synchronize()
+    host_el = time.perf_counter() - t0
+    for a, b in zip(hres, last):
+        assert np.array_equal(a["seeds"], b["seeds"]) and a["theta"] == b["theta"]
+    print(f"[bench] {host_steps} steps from host input: {host_el:.3f} s", file=sys.stderr, flush=True)
 
     def mean_total(key):
         return float(np.mean([t[key] for t in totals]))
@@ -414,6 +429,14 @@ def main():
             "deferred_sets": mtot["deferred"],
             "supersteps": mtot["supersteps"],
         },
+    }
+    line["host_input"] = {
+        "what": "the same step with he_off / he_mem handed to build_graph in host memory "
+                "(pageable), so the input crosses PCIe inside each step",
+        "steps": host_steps,
+        "input_bytes": int(sum(h.he_off.nbytes + h.he_mem.nbytes for h in hgs)),
+        "ms_per_step": 1000.0 * host_el / host_steps,
+        "value": rr_sets_per_step * host_steps / host_el,
     }
     if plain is not None:
         plain["batched_speedup"] = plain["ms_per_step"] / ms_per_step
